@@ -1,0 +1,343 @@
+"""FP64 CPU oracle for the pixel-level splatting path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__``'s
+smoke check and by the CPU-baseline leg of ``bench.py``.  The product library
+never imports, links or calls anything in this directory.
+
+The heavy lifting is in ``splat_oracle.cpp`` (double precision, OpenMP over
+pixels/Gaussians); this module marshals numpy arrays through ctypes and adds
+the pieces that are plain enough to state in numpy (L1 loss, Adam).
+
+Paper anchors (the paper's own numbering of equations):
+  * Eq. 1  alpha_i = o_i exp(-1/2 d^T (Sigma2D)^-1 d)
+  * Eq. 2  C_p = sum_i c_i alpha_i T_i,  T_i = prod_{j<i} (1 - alpha_j)
+  * Eq. 3-4 per-cell partial colour C^m, transmittance T^m, depth D^m
+  * Eq. 5  C_p = sum_m C^m prod_{k<m} T^k   (cells in ray order)
+  * Eq. 6-7 gradients of C_p with respect to alpha_i and c_i through Eq. 5
+  * saturation redundancy: cells behind prod T^k < eps are inactive for the
+    next render of the same view.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "splat_oracle.cpp")
+_LIB = os.path.join(_HERE, "libsplat_oracle.so")
+
+FLAG_ALPHA_BAND = 1
+FLAG_TERMINATE = 2
+FLAG_DEPTH_ROUND = 4
+FLAG_ORDER = 8
+FLAG_CLAMP = 16
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or (
+            os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Cam(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("znear", ctypes.c_double), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("sh_degree", ctypes.c_int32),
+                ("same_frame_cull", ctypes.c_int32),
+                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("t_min", ctypes.c_double), ("eps2d", ctypes.c_double),
+                ("bg", ctypes.c_double * 3), ("delta_q", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = ctypes.CDLL(_LIB)
+        _lib.or_sort_keys.restype = ctypes.c_int64
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _cam(cam) -> _Cam:
+    c = _Cam()
+    R = np.asarray(cam.R, np.float64).reshape(9)
+    t = np.asarray(cam.t, np.float64).reshape(3)
+    for i in range(9):
+        c.R[i] = float(np.float32(R[i]))
+    for i in range(3):
+        c.t[i] = float(np.float32(t[i]))
+    c.fx, c.fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
+    c.cx, c.cy = float(np.float32(cam.cx)), float(np.float32(cam.cy))
+    c.znear = float(np.float32(cam.znear))
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _params(settings, sh_degree: int, same_frame_cull: bool = False,
+            delta_q: float = 0.0) -> _Params:
+    p = _Params()
+    p.tile_w, p.tile_h = int(settings.tile_w), int(settings.tile_h)
+    p.sh_degree = int(sh_degree)
+    p.same_frame_cull = int(bool(same_frame_cull))
+    # the FP32 path receives these as float32; the oracle uses the same values
+    p.alpha_min = float(np.float32(settings.alpha_min))
+    p.alpha_max = float(np.float32(settings.alpha_max))
+    p.t_min = float(np.float32(settings.t_min))
+    p.eps2d = float(np.float32(settings.eps2d))
+    for i in range(3):
+        p.bg[i] = float(np.float32(settings.bg[i]))
+    p.delta_q = float(delta_q)
+    return p
+
+
+def _scene64(scene):
+    return [np.ascontiguousarray(np.asarray(a, np.float64))
+            for a in (scene.means, scene.log_scales, scene.quats,
+                      scene.opacity_logits, scene.sh)]
+
+
+def _sh_degree(scene) -> int:
+    k = scene.sh.shape[1]
+    d = int(round(k ** 0.5)) - 1
+    assert (d + 1) ** 2 == k
+    return d
+
+
+# --------------------------------------------------------------------------
+def preprocess(scene, cam, settings) -> dict:
+    """Per-Gaussian projection (double).  Keys: valid, depth, tcam, mean2d,
+    cov2d, conic, opacity, rgb, rgb_pos, tau, pix_rect, tile_rect, n_tiles."""
+    n = scene.n
+    s = _scene64(scene)
+    out = dict(valid=np.zeros(n, np.uint8), depth=np.zeros(n),
+               tcam=np.zeros((n, 3)), mean2d=np.zeros((n, 2)),
+               cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)),
+               opacity=np.zeros(n), rgb=np.zeros((n, 3)),
+               rgb_pos=np.zeros((n, 3), np.uint8), tau=np.zeros(n),
+               pix_rect=np.zeros((n, 4), np.int32),
+               tile_rect=np.zeros((n, 4), np.int32),
+               n_tiles=np.zeros(n, np.int64))
+    c, p = _cam(cam), _params(settings, _sh_degree(scene))
+    lib().or_preprocess(
+        ctypes.c_int64(n), *[_p(a) for a in s], ctypes.byref(c),
+        ctypes.byref(p), *[_p(out[k]) for k in (
+            "valid", "depth", "tcam", "mean2d", "cov2d", "conic", "opacity",
+            "rgb", "rgb_pos", "tau", "pix_rect", "tile_rect", "n_tiles")])
+    return out
+
+
+def sh_eval(degree: int, dirs: np.ndarray):
+    """Real SH basis values [n,(D+1)^2] and gradients [n,(D+1)^2,3]."""
+    dirs = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(-1, 3))
+    n = dirs.shape[0]
+    nc = (degree + 1) ** 2
+    Y = np.zeros((n, nc))
+    G = np.zeros((n, nc, 3))
+    lib().or_sh_eval(ctypes.c_int(degree), ctypes.c_int64(n), _p(dirs), _p(Y),
+                     _p(G))
+    return Y, G
+
+
+def sort_keys(scene, cam, settings):
+    """Sorted instance keys (tile<<32 | float32 depth bits), values (Gaussian
+    index) and per-tile [start, end) ranges."""
+    s = _scene64(scene)
+    c, p = _cam(cam), _params(settings, _sh_degree(scene))
+    n_inst = lib().or_sort_keys(ctypes.c_int64(scene.n), *[_p(a) for a in s],
+                                ctypes.byref(c), ctypes.byref(p), None, None,
+                                None)
+    tiles = (((cam.width + settings.tile_w - 1) // settings.tile_w) *
+             ((cam.height + settings.tile_h - 1) // settings.tile_h))
+    keys = np.zeros(n_inst, np.uint64)
+    vals = np.zeros(n_inst, np.uint32)
+    ranges = np.zeros((tiles, 2), np.uint32)
+    lib().or_sort_keys(ctypes.c_int64(scene.n), *[_p(a) for a in s],
+                       ctypes.byref(c), ctypes.byref(p), _p(keys), _p(vals),
+                       _p(ranges))
+    return keys, vals, ranges
+
+
+def render(scene, cam, settings, mode: str = "binned",
+           mask: Optional[np.ndarray] = None, delta_q: float = 0.0) -> dict:
+    """Partial render of one cell (Eq. 3-4).  Returns C [H,W,3], T [H,W],
+    D [H,W], nblend [H,W] (blended pairs) and flags [H,W]."""
+    H, W = cam.height, cam.width
+    s = _scene64(scene)
+    c = _cam(cam)
+    p = _params(settings, _sh_degree(scene), delta_q=delta_q)
+    out = dict(C=np.zeros((H, W, 3)), T=np.zeros((H, W)), D=np.zeros((H, W)),
+               nblend=np.zeros((H, W), np.int32),
+               flags=np.zeros((H, W), np.uint8))
+    m = None if mask is None else np.ascontiguousarray(mask.astype(np.uint8))
+    lib().or_render(ctypes.c_int64(scene.n), *[_p(a) for a in s],
+                    ctypes.byref(c), ctypes.byref(p),
+                    ctypes.c_int(0 if mode == "brute" else 1), _p(m),
+                    _p(out["C"]), _p(out["T"]), _p(out["D"]),
+                    _p(out["nblend"]), _p(out["flags"]))
+    return out
+
+
+def _cells_lohi(cells):
+    lo = np.ascontiguousarray(np.array([c.lo for c in cells], np.float64))
+    hi = np.ascontiguousarray(np.array([c.hi for c in cells], np.float64))
+    return lo, hi
+
+
+def composite(Cparts: np.ndarray, Tparts: np.ndarray, cells, cam, settings,
+              same_frame_cull: bool = False) -> dict:
+    """Eq. 5 over K partial buffers Cparts [K,H,W,3], Tparts [K,H,W].
+    Returns rgb [H,W,3], T [H,W], order [H,W,K], mask [K,H,W] (1 = cell
+    still active for the next render of this view), flags [H,W]."""
+    K = len(cells)
+    H, W = cam.height, cam.width
+    Cp = np.ascontiguousarray(np.asarray(Cparts, np.float64))
+    Tp = np.ascontiguousarray(np.asarray(Tparts, np.float64))
+    lo, hi = _cells_lohi(cells)
+    out = dict(rgb=np.zeros((H, W, 3)), T=np.zeros((H, W)),
+               order=np.zeros((H, W, K), np.int32),
+               mask=np.zeros((K, H, W), np.uint8),
+               flags=np.zeros((H, W), np.uint8))
+    lib().or_composite(ctypes.c_int(K), _p(Cp), _p(Tp), _p(lo), _p(hi),
+                       ctypes.byref(_cam(cam)),
+                       ctypes.byref(_params(settings, 0, same_frame_cull)),
+                       _p(out["rgb"]), _p(out["T"]), _p(out["order"]),
+                       _p(out["mask"]), _p(out["flags"]))
+    return out
+
+
+def composite_backward(Cparts, Tparts, order, cam, settings, drgb,
+                       dT=None, active=None, same_frame_cull=False):
+    K = Cparts.shape[0]
+    H, W = cam.height, cam.width
+    Cp = np.ascontiguousarray(np.asarray(Cparts, np.float64))
+    Tp = np.ascontiguousarray(np.asarray(Tparts, np.float64))
+    dC = np.zeros((K, H, W, 3))
+    dTo = np.zeros((K, H, W))
+    g = np.ascontiguousarray(np.asarray(drgb, np.float64))
+    gT = None if dT is None else np.ascontiguousarray(np.asarray(dT, np.float64))
+    act = None if active is None else np.ascontiguousarray(active.astype(np.uint8))
+    lib().or_composite_backward(
+        ctypes.c_int(K), _p(Cp), _p(Tp), _p(np.ascontiguousarray(order)),
+        _p(act), ctypes.byref(_cam(cam)),
+        ctypes.byref(_params(settings, 0, same_frame_cull)), _p(g), _p(gT),
+        _p(dC), _p(dTo))
+    return dC, dTo
+
+
+def render_backward(scene, cam, settings, dC=None, dT=None, dD=None,
+                    mask=None) -> dict:
+    """Gradients of one cell's partial render with respect to the screen
+    quantities (g2d [n,10]: mean2d x/y, conic a/b/c, opacity, rgb, depth) and
+    the raw parameters (means, log_scales, quats, opacity_logits, sh)."""
+    n = scene.n
+    nc = scene.sh.shape[1]
+    s = _scene64(scene)
+    out = dict(g2d=np.zeros((n, 10)), means=np.zeros((n, 3)),
+               log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+               opacity_logits=np.zeros(n), sh=np.zeros((n, nc, 3)))
+
+    def arr(a):
+        return None if a is None else np.ascontiguousarray(np.asarray(a, np.float64))
+    m = None if mask is None else np.ascontiguousarray(mask.astype(np.uint8))
+    lib().or_render_backward(
+        ctypes.c_int64(n), *[_p(a) for a in s], ctypes.byref(_cam(cam)),
+        ctypes.byref(_params(settings, _sh_degree(scene))), _p(m),
+        _p(arr(dC)), _p(arr(dT)), _p(arr(dD)), _p(out["g2d"]),
+        _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]),
+        _p(out["opacity_logits"]), _p(out["sh"]))
+    return out
+
+
+# --------------------------------------------------------------------------
+# whole-frame drivers over K cells
+
+
+@dataclass
+class Frame:
+    parts: List[dict]  # per-cell render outputs
+    comp: dict         # composite outputs
+    Cparts: np.ndarray
+    Tparts: np.ndarray
+
+
+def forward(cell_scenes: Sequence, cells, cam, settings,
+            masks: Optional[np.ndarray] = None, same_frame_cull=False,
+            delta_q: float = 0.0) -> Frame:
+    """Render every cell (Eq. 3-4) and compose them (Eq. 5).  ``masks``
+    [K,H,W] (1 = active) restricts each cell's render."""
+    parts = [render(sc, cam, settings, "binned",
+                    None if masks is None else masks[k], delta_q)
+             for k, sc in enumerate(cell_scenes)]
+    Cp = np.stack([p["C"] for p in parts])
+    Tp = np.stack([p["T"] for p in parts])
+    comp = composite(Cp, Tp, cells, cam, settings, same_frame_cull)
+    return Frame(parts, comp, Cp, Tp)
+
+
+def backward(cell_scenes, cells, cam, settings, frame: Frame, drgb, dT=None,
+             masks=None, same_frame_cull=False) -> List[dict]:
+    """Gradients for every cell's Gaussians through the composition (Eq. 6-7)
+    and each cell's local render."""
+    dC, dTp = composite_backward(frame.Cparts, frame.Tparts,
+                                 frame.comp["order"], cam, settings, drgb, dT,
+                                 frame.comp["mask"], same_frame_cull)
+    return [render_backward(sc, cam, settings, dC[k], dTp[k], None,
+                            None if masks is None else masks[k])
+            for k, sc in enumerate(cell_scenes)]
+
+
+def l1_loss(rgb: np.ndarray, target: np.ndarray):
+    """Mean absolute error over H*W*3 and its gradient sign(C - target)/(3HW)
+    with sign(0) = 0 (the RGB term of the paper's training loss)."""
+    d = np.asarray(rgb, np.float64) - np.asarray(target, np.float64)
+    n = d.size
+    return float(np.abs(d).sum() / n), np.sign(d) / n
+
+
+def adam_step(param, grad, m, v, step: int, lr: float, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8):
+    """Textbook Adam (Kingma & Ba, Algorithm 1) with bias correction; updates
+    the arrays in place and returns them."""
+    m *= beta1
+    m += (1 - beta1) * grad
+    v *= beta2
+    v += (1 - beta2) * grad * grad
+    mhat = m / (1 - beta1 ** step)
+    vhat = v / (1 - beta2 ** step)
+    param -= lr * mhat / (np.sqrt(vhat) + eps)
+    return param, m, v
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(ctypes.c_int(n))

@@ -1,0 +1,504 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by
+mathematics (closed forms, invariants, library routines, brute force), so
+that the oracle is trusted before any kernel is compared with it.
+
+Each test names the passage it pins: the paper's Eq. 1 (alpha), Eq. 2
+(blending), Eq. 3-4 (partials), Eq. 5 and the claim that it equals Eq. 2
+(composition), Eq. 6-7 (gradients), the saturation rule of the redundancy
+reduction section, and the projection step of the background section.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+ST = synth.RenderSettings()
+
+
+def _sigmoid(x):
+    return 1.0 / (1.0 + math.exp(-x))
+
+
+def _one(mean, log_scale, quat, logit, rgb):
+    """A Scene holding the given Gaussians (SH degree 0 colour = rgb)."""
+    mean = np.atleast_2d(np.asarray(mean, np.float64))
+    n = mean.shape[0]
+    rgb = np.broadcast_to(np.asarray(rgb, np.float64), (n, 3))
+    sh = ((rgb - 0.5) * 2.0 * math.sqrt(math.pi))[:, None, :]
+    return synth.Scene(
+        mean.astype(np.float32),
+        np.broadcast_to(np.asarray(log_scale, np.float64), (n, 3)).astype(np.float32).copy(),
+        np.broadcast_to(np.asarray(quat, np.float64), (n, 4)).astype(np.float32).copy(),
+        np.broadcast_to(np.asarray(logit, np.float64), (n,)).astype(np.float32).copy(),
+        sh.astype(np.float32))
+
+
+def _col(sc, i=0):
+    """Colour that degree-0 SH coefficients stored in FP32 evaluate to:
+    k0 / (2 sqrt(pi)) + 0.5 (the DC real harmonic is 1/(2 sqrt(pi)))."""
+    return sc.sh[i, 0].astype(np.float64) / (2.0 * math.sqrt(math.pi)) + 0.5
+
+
+def _axis_cam(size=64, f=50.0, centre=32.5):
+    # camera at (0,0,-3) looking +z; the optical axis hits pixel `centre`
+    return synth.camera_from_rows(np.eye(3), (0.0, 0.0, -3.0), size, size, f,
+                                  cx=centre, cy=centre)
+
+
+# ----------------------------------------------------------------- Eq. 1-2
+def test_single_gaussian_centre_alpha_equals_opacity(orc):
+    """A Gaussian projected exactly onto a pixel centre has alpha = o there
+    (Eq. 1 with d = 0), so C = c min(o, 0.99) and T = 1 - min(o, 0.99)."""
+    cam = _axis_cam()
+    for logit in (-1.3, 0.5, 6.0):
+        rgb = (0.25, 0.5, 0.75)
+        sc = _one([0, 0, 0], (-3.0, -3.2, -2.9), (1, 0, 0, 0), logit, rgb)
+        r = orc.render(sc, cam, ST)
+        o = _sigmoid(float(np.float32(logit)))
+        a = min(o, float(np.float32(0.99)))
+        c = r["C"][32, 32]
+        np.testing.assert_allclose(c, _col(sc) * a, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(c, np.array(rgb) * a, rtol=0, atol=1e-7)
+        assert abs(r["T"][32, 32] - (1 - a)) < 1e-12
+        assert r["nblend"][32, 32] == 1
+
+
+def test_on_axis_ewa_closed_form(orc):
+    """Projection step: on the optical axis with R = I, J W Sigma W^T J^T is
+    diag((f s_x / z)^2, (f s_y / z)^2); alpha off-centre follows Eq. 1."""
+    cam = _axis_cam()
+    ls = np.array([-3.0, -2.6, -2.2], np.float32)
+    sc = _one([0, 0, 0.5], ls, (1, 0, 0, 0), 0.7, (0.3, 0.3, 0.3))
+    pr = orc.preprocess(sc, cam, ST)
+    z = 3.5
+    s = np.exp(ls.astype(np.float64))
+    eps = float(np.float32(ST.eps2d))
+    vx, vy = (50.0 * s[0] / z) ** 2 + eps, (50.0 * s[1] / z) ** 2 + eps
+    np.testing.assert_allclose(pr["cov2d"][0], [vx, 0.0, vy], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(pr["conic"][0], [1 / vx, 0.0, 1 / vy], rtol=1e-12)
+    assert pr["depth"][0] == z
+    r = orc.render(sc, cam, ST)
+    o = _sigmoid(float(np.float32(0.7)))
+    for (px, py) in [(33, 32), (34, 33), (31, 30)]:
+        dx, dy = px + 0.5 - 32.5, py + 0.5 - 32.5
+        a = o * math.exp(-0.5 * (dx * dx / vx + dy * dy / vy))
+        if a < 1 / 255:
+            continue
+        assert abs(r["C"][py, px, 0] - _col(sc)[0] * a) < 1e-15
+
+
+def test_rotation_matches_library(orc):
+    """Sigma = R S S^T R^T with R from the unit quaternion (w,x,y,z): checked
+    against scipy's rotation for a Gaussian on the optical axis, where the
+    projected covariance is (f/z)^2 times the upper-left 2x2 block."""
+    from scipy.spatial.transform import Rotation
+    cam = _axis_cam()
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        q = rng.normal(size=4).astype(np.float32)
+        ls = rng.normal(-2.5, 0.4, size=3).astype(np.float32)
+        sc = _one([0, 0, 0], ls, q * np.float32(1.7), 0.0, (0.5, 0.5, 0.5))
+        pr = orc.preprocess(sc, cam, ST)
+        q64 = sc.quats[0].astype(np.float64)
+        Rm = Rotation.from_quat([q64[1], q64[2], q64[3], q64[0]]).as_matrix()
+        Sig = Rm @ np.diag(np.exp(2 * ls.astype(np.float64))) @ Rm.T
+        k = (50.0 / 3.0) ** 2
+        eps = float(np.float32(ST.eps2d))
+        np.testing.assert_allclose(
+            pr["cov2d"][0], [k * Sig[0, 0] + eps, k * Sig[0, 1], k * Sig[1, 1] + eps],
+            rtol=1e-10)
+
+
+def test_ewa_matches_numerical_jacobian(orc):
+    """Off-axis: Sigma2D equals Jn (W Sigma W^T) Jn^T + eps I where Jn is a
+    central-difference Jacobian of the pinhole projection (x,y,z) ->
+    (fx x/z + cx, fy y/z + cy) at the camera-space mean."""
+    cam = synth.g2_camera(320, 180)
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        mu = np.array([rng.uniform(-30, 30), rng.uniform(120, 200), rng.uniform(0, 20)])
+        ls = rng.normal(0.0, 0.5, 3).astype(np.float32)
+        q = rng.normal(size=4).astype(np.float32)
+        sc = _one(mu, ls, q, 2.0, (0.5, 0.5, 0.5))
+        pr = orc.preprocess(sc, cam, ST)
+        assert pr["valid"][0]
+        R = cam.R.astype(np.float64)
+        t = R @ sc.means[0].astype(np.float64) + cam.t.astype(np.float64)
+
+        fx, fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
+        cx, cy = float(np.float32(cam.cx)), float(np.float32(cam.cy))
+
+        def proj(v):
+            return np.array([fx * v[0] / v[2] + cx, fy * v[1] / v[2] + cy])
+        Jn = np.zeros((2, 3))
+        for k in range(3):
+            h = 1e-4 * max(1.0, abs(t[k]))
+            e = np.zeros(3)
+            e[k] = h
+            Jn[:, k] = (proj(t + e) - proj(t - e)) / (2 * h)
+        qd = q.astype(np.float64) / np.linalg.norm(q.astype(np.float64))
+        w, x, y, z = qd
+        Rq = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                       [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                       [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+        Sig = Rq @ np.diag(np.exp(2 * ls.astype(np.float64))) @ Rq.T
+        S2 = Jn @ (R @ Sig @ R.T) @ Jn.T
+        eps = float(np.float32(ST.eps2d))
+        np.testing.assert_allclose(pr["cov2d"][0],
+                                   [S2[0, 0] + eps, S2[0, 1], S2[1, 1] + eps], rtol=2e-6)
+        np.testing.assert_allclose(pr["mean2d"][0], proj(t), rtol=1e-13)
+
+
+def test_two_gaussians_worked_example(orc):
+    """Eq. 2 on two coincident on-axis Gaussians: the nearer one is blended
+    first whatever its index: C = c1 a1 + c2 a2 (1 - a1), T = (1-a1)(1-a2)."""
+    cam = _axis_cam()
+    far = ([0, 0, 1.0], -1.0, (0.9, 0.1, 0.2))
+    near = ([0, 0, -0.5], 0.4, (0.1, 0.8, 0.3))
+    sc = _one([far[0], near[0]], (-3.0, -3.0, -3.0), (1, 0, 0, 0),
+              np.array([far[1], near[1]]), np.array([far[2], near[2]]))
+    r = orc.render(sc, cam, ST)
+    a1 = _sigmoid(float(np.float32(near[1])))
+    a2 = _sigmoid(float(np.float32(far[1])))
+    c1, c2 = _col(sc, 1), _col(sc, 0)
+    np.testing.assert_allclose(r["C"][32, 32], c1 * a1 + c2 * a2 * (1 - a1), atol=1e-15)
+    assert abs(r["T"][32, 32] - (1 - a1) * (1 - a2)) < 1e-12
+    assert abs(r["D"][32, 32] - (2.5 * a1 + 4.0 * a2 * (1 - a1))) < 1e-12
+
+
+def test_termination_blend_then_stop(orc):
+    """Transmittance stop: the walk ends right after the blend that takes T
+    below t_min (1e-4); later Gaussians get no weight."""
+    cam = _axis_cam()
+    a = 0.95
+    logit = math.log(a / (1 - a))
+    zs = [[0, 0, -1.0 + 0.3 * k] for k in range(6)]
+    cols = np.array([[0.1 * (k + 1)] * 3 for k in range(6)])
+    sc = _one(zs, (-3.0, -3.0, -3.0), (1, 0, 0, 0), logit, cols)
+    r = orc.render(sc, cam, ST)
+    o = _sigmoid(float(np.float32(logit)))
+    T, C, n = 1.0, 0.0, 0
+    for k in range(6):
+        C += _col(sc, k)[0] * o * T
+        T *= 1 - o
+        n += 1
+        if T < float(np.float32(ST.t_min)):
+            break
+    assert n == 4 and r["nblend"][32, 32] == 4
+    assert abs(r["C"][32, 32, 0] - C) < 1e-12 and abs(r["T"][32, 32] - T) < 1e-15
+
+
+def test_alpha_skip_threshold(orc):
+    """A pair with alpha < 1/255 is skipped (no blend, no transmittance)."""
+    cam = _axis_cam()
+    logit = math.log(0.003 / 0.997)  # o < alpha_min: culled entirely
+    sc = _one([0, 0, 0], (-3.0, -3.0, -3.0), (1, 0, 0, 0), logit, (1, 1, 1))
+    r = orc.render(sc, cam, ST)
+    assert r["nblend"].sum() == 0 and np.all(r["T"] == 1.0)
+
+
+def test_transmittance_is_product_and_constant_colour(orc):
+    """Telescoping of Eq. 2: with every colour equal to c0, C = c0 (1 - T)
+    exactly, for every pixel of the tiny workload."""
+    sc = synth.tiny_scene()
+    c0 = 0.37
+    sc.sh[:] = np.float32((c0 - 0.5) * 2.0 * math.sqrt(math.pi))
+    r = orc.render(sc, synth.tiny_camera(), ST)
+    pr = orc.preprocess(sc, synth.tiny_camera(), ST)
+    cval = pr["rgb"][pr["valid"] == 1]
+    assert np.ptp(cval) < 1e-15
+    np.testing.assert_allclose(r["C"], cval[0][None, None, :] * (1 - r["T"])[..., None], atol=1e-13)
+
+
+def test_brute_equals_binned(orc):
+    """Exact-extent bins drop only pairs with alpha < alpha_min: binned and
+    brute-force renders agree bit for bit."""
+    sc = synth.tiny_scene()
+    cam = synth.tiny_camera()
+    a = orc.render(sc, cam, ST, "brute")
+    b = orc.render(sc, cam, ST, "binned")
+    for k in ("C", "T", "D", "nblend"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_keys_sorted_complete_and_ranges(orc):
+    """Sort step: keys are sorted by (tile, float32 depth, index); every pair
+    with alpha >= alpha_min (checked by brute force over pixels) appears in
+    its tile's list; ranges partition the instance list."""
+    sc = synth.make_cube_scene(7, 300, log_scale=(-3.0, 0.5))
+    cam = synth.tiny_camera(64, 48)
+    keys, vals, ranges = orc.sort_keys(sc, cam, ST)
+    pr = orc.preprocess(sc, cam, ST)
+    order = np.lexsort((vals, keys))
+    assert np.array_equal(order, np.arange(len(keys)))
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    tx = (cam.width + 15) // 16
+    assert ranges[0, 0] == 0 and ranges[-1, 1] == len(keys)
+    assert np.array_equal(ranges[1:, 0], ranges[:-1, 1])
+    for t in range(len(ranges)):
+        assert np.all(tiles[ranges[t, 0]:ranges[t, 1]] == t)
+    zbits = (keys & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    assert np.array_equal(zbits, pr["depth"][vals].astype(np.float32).view(np.uint32))
+    members = {(int(t), int(v)) for t, v in zip(tiles, vals)}
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    for g in np.nonzero(pr["valid"])[0]:
+        dx = xs + 0.5 - pr["mean2d"][g, 0]
+        dy = ys + 0.5 - pr["mean2d"][g, 1]
+        a, b, c = pr["conic"][g]
+        alpha = pr["opacity"][g] * np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+        hit = np.nonzero(alpha >= ST.alpha_min * (1 + 1e-9))
+        for y, x in zip(*hit):
+            assert ((y // 16) * tx + x // 16, g) in members
+
+
+# ------------------------------------------------------------------ SH ----
+def _unit_dirs(n, seed=0):
+    d = np.random.default_rng(seed).normal(size=(n, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def test_sh_y00_and_addition_theorem(orc):
+    d = _unit_dirs(200)
+    Y, _ = orc.sh_eval(3, d)
+    assert np.allclose(Y[:, 0], 1 / (2 * math.sqrt(math.pi)), atol=1e-15)
+    for l in range(4):
+        s = (Y[:, l * l:(l + 1) * (l + 1)] ** 2).sum(1)
+        np.testing.assert_allclose(s, (2 * l + 1) / (4 * math.pi), rtol=1e-12)
+
+
+def test_sh_orthonormal_by_quadrature(orc):
+    """Gauss-Legendre in cos(theta) times the trapezoid rule in phi integrates
+    products of degree <= 6 exactly."""
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    nphi = 16
+    phi = 2 * math.pi * np.arange(nphi) / nphi
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    d = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    w = (wg[:, None] * np.full(nphi, 2 * math.pi / nphi)[None, :]).reshape(-1)
+    Y, _ = orc.sh_eval(3, d)
+    G = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_matches_scipy_convention(orc):
+    """Real basis from scipy's complex harmonics (Condon-Shortley phase):
+    Y_l0 = Re Y_l^0, Y_lm = sqrt2 Re Y_l^m, Y_l,-m = sqrt2 Im Y_l^m."""
+    import scipy.special as sp
+    d = _unit_dirs(50, 1)
+    theta = np.arccos(np.clip(d[:, 2], -1, 1))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    Y, _ = orc.sh_eval(3, d)
+    for l in range(4):
+        for m in range(0, l + 1):
+            if hasattr(sp, "sph_harm_y"):
+                c = sp.sph_harm_y(l, m, theta, phi)
+            else:
+                c = sp.sph_harm(m, l, phi, theta)
+            if m == 0:
+                np.testing.assert_allclose(Y[:, l * l + l], c.real, atol=1e-12)
+            else:
+                np.testing.assert_allclose(Y[:, l * l + l + m], math.sqrt(2) * c.real, atol=1e-12)
+                np.testing.assert_allclose(Y[:, l * l + l - m], math.sqrt(2) * c.imag, atol=1e-12)
+
+
+def test_sh_gradient_tangential_part(orc):
+    """The tangential gradient of each basis function matches a central
+    difference along the sphere (the radial part is irrelevant because the
+    direction is normalised)."""
+    d = _unit_dirs(20, 2)
+    _, G = orc.sh_eval(3, d)
+    h = 1e-6
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        dp = d + e
+        dm = d - e
+        dp /= np.linalg.norm(dp, axis=1, keepdims=True)
+        dm /= np.linalg.norm(dm, axis=1, keepdims=True)
+        Yp, _ = orc.sh_eval(3, dp)
+        Ym, _ = orc.sh_eval(3, dm)
+        fd = (Yp - Ym) / (2 * h)
+        proj = G - (G * d[:, None, :]).sum(-1, keepdims=True) * d[:, None, :]
+        np.testing.assert_allclose(proj[:, :, k], fd, atol=1e-7)
+
+
+# ---------------------------------------------------------- composition ---
+def _zslab_cells(edges):
+    return [synth.Cell((-math.inf, -math.inf, float(edges[i])),
+                       (math.inf, math.inf, float(edges[i + 1])))
+            for i in range(len(edges) - 1)]
+
+
+def test_composite_associative_identity_k1(orc):
+    """over((C1,T1),(C2,T2)) = (C1 + T1 C2, T1 T2) is associative, (0,1) is
+    its identity, and a single cell composes to C + T bg (Eq. 5)."""
+    cam = synth.tiny_camera(16, 16)
+    rng = np.random.default_rng(9)
+    K = 3
+    Tp = rng.uniform(0.0, 1.0, size=(K, 16, 16))
+    Cp = rng.uniform(0, 1, size=(K, 16, 16, 3)) * (1 - Tp[..., None])
+    cells = _zslab_cells([-2.0, -1.0, 0.0, 1.0])
+    st0 = synth.RenderSettings(t_min=0.0)
+    full = orc.composite(Cp, Tp, cells, cam, st0)
+    ab = orc.composite(Cp[:2], Tp[:2], cells[:2], cam, st0)
+    left = orc.composite(np.stack([ab["rgb"], Cp[2]]), np.stack([ab["T"], Tp[2]]),
+                         [cells[0], cells[2]], cam, st0)
+    bc = orc.composite(Cp[1:], Tp[1:], cells[1:], cam, st0)
+    right = orc.composite(np.stack([Cp[0], bc["rgb"]]), np.stack([Tp[0], bc["T"]]),
+                          [cells[0], cells[1]], cam, st0)
+    for o in (left, right):
+        np.testing.assert_allclose(o["rgb"], full["rgb"], atol=1e-14)
+        np.testing.assert_allclose(o["T"], full["T"], atol=1e-15)
+    Cid = Cp.copy()
+    Tid = Tp.copy()
+    Cid[1] = 0.0
+    Tid[1] = 1.0
+    ident = orc.composite(Cid, Tid, cells, cam, st0)
+    two = orc.composite(Cp[[0, 2]], Tp[[0, 2]], [cells[0], cells[2]], cam, st0)
+    np.testing.assert_allclose(ident["rgb"], two["rgb"], atol=1e-15)
+    bg = synth.RenderSettings(t_min=0.0, bg=(0.2, 0.4, 0.6))
+    one = orc.composite(Cp[:1], Tp[:1], cells[:1], cam, bg)
+    np.testing.assert_allclose(one["rgb"], Cp[0] + Tp[0][..., None] * np.array(bg.bg, np.float32),
+                               atol=1e-15)
+    assert np.all(full["order"] == np.arange(K))
+
+
+def test_eq5_equals_eq2_on_depth_separated_slabs(orc):
+    """The paper's claim that Eq. 5 equals Eq. 2: with no early stop, the
+    composite of depth-separated slab partials equals the single-pass render
+    (to rounding)."""
+    sc = synth.tiny_scene()
+    cam = synth.tiny_camera()
+    st0 = synth.RenderSettings(t_min=0.0)
+    edges = synth.quantile_edges(sc.means[:, 2], 4)
+    part = synth.axis_slab_partition(sc, 2, edges)
+    cells = part.cells
+    fr = orc.forward(part.cell_scenes(sc), cells, cam, st0)
+    single = orc.render(sc, cam, st0)
+    np.testing.assert_allclose(fr.comp["rgb"], single["C"], atol=1e-12)
+    np.testing.assert_allclose(fr.comp["T"], single["T"], atol=1e-12)
+    assert np.all(fr.comp["order"] == np.arange(4))
+
+
+def test_saturation_culling_bound(orc):
+    """Saturation redundancy: a cell behind prod T < eps is marked inactive;
+    skipping it changes a pixel by at most eps * max colour."""
+    sc = synth.make_cube_scene(11, 6000, log_scale=(-3.2, 0.4), logit_sigma=2.0)
+    cam = synth.tiny_camera(64, 64)
+    edges = synth.quantile_edges(sc.means[:, 2], 4)
+    part = synth.axis_slab_partition(sc, 2, edges)
+    scenes = part.cell_scenes(sc)
+    full = orc.forward(scenes, part.cells, cam, ST)
+    culled = orc.forward(scenes, part.cells, cam, ST, same_frame_cull=True)
+    inactive = full.comp["mask"] == 0
+    assert inactive.sum() > 0
+    cmax = max(orc.preprocess(s, cam, ST)["rgb"].max() for s in scenes)
+    assert np.abs(culled.comp["rgb"] - full.comp["rgb"]).max() <= ST.t_min * cmax + 1e-15
+    # the next render of the view with the masks: inactive pairs produce the
+    # identity partial, and composing gives the same-frame-culled image
+    nxt = orc.forward(scenes, part.cells, cam, ST, masks=full.comp["mask"])
+    np.testing.assert_allclose(nxt.comp["rgb"], culled.comp["rgb"], atol=1e-15)
+    assert np.all(nxt.Tparts[inactive] == 1.0)
+
+
+# ------------------------------------------------------------ Eq. 6-7 -----
+def _flag_free_fd_scene(orc, seed0, cam, cells_fn):
+    for seed in range(seed0, seed0 + 40):
+        sc = synth.fd_scene(seed).astype(np.float64)
+        part = cells_fn(sc)
+        fr = orc.forward(part.cell_scenes(sc), part.cells, cam, ST, delta_q=1e-3)
+        fl = np.bitwise_or.reduce([p["flags"] for p in fr.parts])
+        if not np.any(fl) and not np.any(fr.comp["flags"]):
+            return sc, part
+    raise AssertionError("no flag-free FD scene")
+
+
+def _fd_check(orc, sc, part, cam, seed):
+    rng = np.random.default_rng(seed)
+    H, W = cam.height, cam.width
+    wr = rng.normal(size=(H, W, 3))
+    wt = rng.normal(size=(H, W))
+    scenes = part.cell_scenes(sc)
+    fr = orc.forward(scenes, part.cells, cam, ST)
+    grads = orc.backward(scenes, part.cells, cam, ST, fr, wr, wt)
+
+    def loss(scs):
+        f = orc.forward(scs, part.cells, cam, ST)
+        return float((f.comp["rgb"] * wr).sum() + (f.comp["T"] * wt).sum())
+
+    names = ("means", "log_scales", "quats", "opacity_logits", "sh")
+    for k, cs in enumerate(scenes):
+        for name in names:
+            arr = getattr(cs, name)
+            g = grads[k][name]
+            flat = arr.reshape(-1)
+            gflat = g.reshape(-1)
+            idx = np.arange(flat.size)
+            if flat.size > 120:
+                idx = np.sort(rng.choice(flat.size, 120, replace=False))
+            fd = np.zeros(len(idx))
+            for j, i in enumerate(idx):
+                h = 1e-6 * max(1.0, abs(flat[i]))
+                old = flat[i]
+                flat[i] = old + h
+                lp = loss(scenes)
+                flat[i] = old - h
+                lm = loss(scenes)
+                flat[i] = old
+                fd[j] = (lp - lm) / (2 * h)
+            ga = gflat[idx]
+            scale = max(np.abs(fd).max(), 1e-12)
+            err = np.abs(ga - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
+            assert err.max() <= 1e-3, (k, name, err.max())
+
+
+def test_backward_matches_finite_differences_k1(orc):
+    """Eq. 6-7 with one cell, every parameter family, FP64 central
+    differences on a 64-Gaussian scene (seed re-drawn if any pair sits within
+    reach of a discrete threshold)."""
+    cam = synth.fd_camera()
+
+    def one_cell(s):
+        return synth.axis_slab_partition(s, 2, [-10.0, 10.0])
+    sc, part = _flag_free_fd_scene(orc, 100, cam, one_cell)
+    _fd_check(orc, sc, part, cam, 1)
+
+
+def test_backward_matches_finite_differences_k2(orc):
+    """Eq. 6-7 through a two-cell composition (depth-separated slabs): the
+    transmittance gradient term of Eq. 6 reaches the front cell."""
+    cam = synth.fd_camera()
+
+    def two_cells(s):
+        return synth.axis_slab_partition(s, 2, [-10.0, 0.0, 10.0])
+    sc, part = _flag_free_fd_scene(orc, 200, cam, two_cells)
+    _fd_check(orc, sc, part, cam, 2)
+
+
+# ------------------------------------------------------------- harness ----
+def test_l1_and_adam_match_torch(orc):
+    import torch
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(8, 6, 3))
+    tgt = rng.normal(size=(8, 6, 3))
+    tgt[0, 0, 0] = x[0, 0, 0]
+    L, g = orc.l1_loss(x, tgt)
+    xt = torch.tensor(x, requires_grad=True)
+    lt = torch.nn.functional.l1_loss(xt, torch.tensor(tgt))
+    lt.backward()
+    assert abs(L - lt.item()) < 1e-14
+    np.testing.assert_allclose(g, xt.grad.numpy(), atol=1e-17)
+    p = rng.normal(size=50)
+    pt = torch.tensor(p.copy(), requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    for step in range(1, 6):
+        gr = rng.normal(size=50)
+        pt.grad = torch.tensor(gr)
+        opt.step()
+        orc.adam_step(p, gr, m, v, step, 1e-2)
+    np.testing.assert_allclose(p, pt.detach().numpy(), rtol=1e-12, atol=1e-14)
