@@ -1,0 +1,288 @@
+/*
+ * splaxel.h -- C ABI of libsplaxel.so, the MI355X (gfx950) hot path of
+ * pixel-level distributed 3D Gaussian splatting (Splaxel, arXiv 2606.18588).
+ *
+ * One GPU renders the Gaussians of each convex cell (one GPU's partition in
+ * the paper) into a *partial pixel* buffer (premultiplied colour C^m and
+ * residual transmittance T^m, Eq. 3-4), composes the K partial buffers front
+ * to back per pixel (Eq. 5) and back-propagates through the composition and
+ * each local render (Eq. 6-7).  The paper's cross-GPU pixel exchange is
+ * replaced by K buffers resident in HBM.
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers owned by the caller unless a
+ *     comment says "host".  The library never allocates device memory; the
+ *     caller provides workspaces sized by the *_workspace_size queries.
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *     stream) and is asynchronous unless a comment says the call
+ *     synchronises.
+ *   - Return value: SX_OK (0) or a negative sx_status.  Argument errors are
+ *     detected on the host before anything is enqueued (SX_EINVAL);
+ *     launch/runtime failures map to SX_EDEVICE.  No C++ exception or abort
+ *     crosses the ABI; sx_last_error_string() describes the last failure of
+ *     the calling thread.
+ *   - Layouts are row-major; pixel (x, y) has index y*W + x and its centre
+ *     at (x + 0.5, y + 0.5).  FP32 throughout unless stated.
+ *   - Calls on distinct streams with distinct buffers are independent; the
+ *     library holds no mutable global state.
+ */
+#ifndef SPLAXEL_H
+#define SPLAXEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sx_status;
+#define SX_OK 0
+#define SX_EINVAL (-1)      /* null/inconsistent argument, unsupported size */
+#define SX_ECAPACITY (-2)   /* instance count exceeds the caller's capacity */
+#define SX_EDEVICE (-3)     /* HIP launch or runtime error                  */
+#define SX_EUNSUPPORTED (-4)
+
+typedef void* sx_stream; /* hipStream_t */
+
+/* Pinhole camera: x_cam = R x_world + t, OpenCV axes (x right, y down,
+ * z forward); R row-major. */
+typedef struct sx_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float znear; /* Gaussians whose mean has camera z <= znear are culled */
+} sx_camera;
+
+/* Rendering constants.  tile_w*tile_h pixels form one work item; supported
+ * shapes: 16x16, 32x8, 8x32, 32x16, 16x32, 8x8. */
+typedef struct sx_params {
+  int32_t tile_w, tile_h;
+  int32_t sh_degree; /* 0..3 */
+  int32_t flags;     /* SX_FLAG_* */
+  float alpha_min;   /* pairs with alpha < alpha_min are skipped (1/255)  */
+  float alpha_max;   /* alpha = min(alpha_max, o exp(-q/2)) (0.99)        */
+  float t_min;       /* stop after the blend that takes T below it (1e-4);
+                        also the saturation threshold of the composition  */
+  float eps2d;       /* added to the diagonal of the 2D covariance (0.3)  */
+  float bg[3];       /* background colour composed behind the last cell   */
+} sx_params;
+
+/* treat (cell, pixel) pairs behind a saturated prefix as the identity in
+ * the same frame (otherwise they are only marked inactive for the next
+ * render of the view) */
+#define SX_FLAG_SAME_FRAME_CULL 1
+
+/* Gaussian parameters of one cell, SoA FP32, device pointers:
+ *   means[n*3], log_scales[n*3], quats[n*4] (w,x,y,z, need not be unit),
+ *   opacity_logits[n], sh[n*(D+1)^2*3] (coefficient l*l+l+m, channel
+ *   fastest).  The parametrisation is the paper's background section:
+ *   Sigma = R(q) S S^T R(q)^T, S = diag(exp(log_scales)),
+ *   o = sigmoid(logit), colour = max(0, sum_lm k_lm Y_lm(dir) + 0.5). */
+typedef struct sx_gaussians {
+  int64_t n;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh;
+} sx_gaussians;
+
+/* Per-Gaussian projection written by sx_preprocess (caller-allocated):
+ *   rec[n*12]   float record: mean2d - (cx, cy) (2), conic a, b, c of the
+ *               inverse 2D covariance (3), opacity, rgb (3), camera depth,
+ *               2 unused.  Valid only where n_tiles > 0.
+ *   rect[n*4]   uint16 tile rectangle [x0, y0, x1, y1) of the exact
+ *               alpha >= alpha_min footprint.
+ *   n_tiles[n]  tiles touched; 0 = culled.
+ *   block_sums[sx_preprocess_blocks(n)*2]  per-block (visible, instances)
+ *               partial sums consumed by sx_sort. */
+typedef struct sx_projected {
+  float* rec;
+  uint16_t* rect;
+  uint32_t* n_tiles;
+  uint32_t* block_sums;
+} sx_projected;
+
+/* Axis-aligned convex cell (one GPU's partition); bounds may be +-inf. */
+typedef struct sx_cell {
+  float lo[3];
+  float hi[3];
+} sx_cell;
+
+/* Parameter gradients of one cell, same layouts as sx_gaussians. */
+typedef struct sx_grads {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+} sx_grads;
+
+const char* sx_last_error_string(void);
+const char* sx_version(void);
+
+/* ------------------------------------------------------------------ a1 --
+ * Projection of one cell's Gaussians for one camera (paper, background:
+ * projection step; Eq. 1 footprint).  Per Gaussian: cull by mean depth,
+ * Sigma2D = J W Sigma W^T J^T + eps2d I (EWA), conic = Sigma2D^-1, mean2d,
+ * depth, SH colour, opacity, exact alpha >= alpha_min footprint, tiles
+ * touched.  Computed in FP64, stored in FP32.
+ * Errors: SX_EINVAL for null pointers, n < 0, n >= 2^31, sh_degree > 3,
+ * unsupported tile shape, or width/height outside 1..16384. */
+int64_t sx_preprocess_blocks(int64_t n);
+sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
+                        const sx_params* p, sx_projected* out,
+                        sx_stream stream);
+
+/* ------------------------------------------------------------- a2-a4 --
+ * Depth sort (paper, background: sorting step) as a radix sort of 64-bit
+ * keys  key = tile_id << 32 | bits(float32 depth)  with ties by Gaussian
+ * index, done as two LSD phases: the low (depth) digits on the visible
+ * Gaussians before duplication, then the tile digits on the duplicated
+ * instances.  Produces vals[i] = Gaussian index of the i-th instance,
+ * optionally keys[i], and tile_ranges[t] = [start, end) per tile
+ * (tile_id = ty * tiles_x + tx; an empty tile has start == end).
+ *   capacity   instances the caller allocated in keys/vals.
+ *   ws         workspace of sx_sort_workspace_size(n, capacity, tiles).
+ *   h_counts   HOST uint64[2] or NULL.  If non-NULL the call synchronises
+ *              the stream once after counting, writes {visible,
+ *              instances} and returns SX_ECAPACITY (with nothing sorted)
+ *              when instances > capacity.  If NULL the call is fully
+ *              asynchronous; an overflow sorts only the first `capacity`
+ *              instances and raises a flag read by sx_sort_counts().
+ * keys may be NULL. */
+sx_status sx_sort_workspace_size(int64_t n, int64_t capacity,
+                                 int64_t tiles_total, size_t* bytes);
+sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
+                  const sx_params* p, int64_t capacity, uint64_t* keys,
+                  uint32_t* vals, uint32_t* tile_ranges, void* ws,
+                  size_t ws_bytes, uint64_t* h_counts, sx_stream stream);
+/* Reads {visible, instances, overflow} from a sort workspace (device ->
+ * HOST uint64[3]); synchronises the stream. */
+sx_status sx_sort_counts(const void* ws, int64_t n, uint64_t* h_out,
+                         sx_stream stream);
+
+/* ------------------------------------------------------------------ a5 --
+ * Partial render of one cell (Eq. 1-4): per pixel, front to back over its
+ * tile's list, alpha = min(alpha_max, o exp(-q/2)); skip alpha < alpha_min;
+ * C += c alpha T, D += z alpha T, T *= 1 - alpha; stop after T < t_min.
+ *   mask       active bits, bit (y*W+x) of uint32 words, NULL = all.
+ *              Inactive pixels output the identity (C=0, T=1).
+ *   partial    [H*W*4] out: (C_r, C_g, C_b, T) per pixel.
+ *   depth      [H*W] out or NULL: D = sum z alpha T.
+ *   last       [H*W] out: 1 + position (within the tile list) of the last
+ *              blended pair, 0 if none; needed by the backward.
+ *   nblend     [H*W] out or NULL: number of blended pairs. */
+sx_status sx_render_partial(const sx_projected* proj, const uint32_t* vals,
+                            const uint32_t* tile_ranges, const sx_camera* cam,
+                            const sx_params* p, const uint32_t* mask,
+                            float* partial, float* depth, uint32_t* last,
+                            uint32_t* nblend, sx_stream stream);
+
+/* ------------------------------------------------------------------ a6 --
+ * Composition of K partial buffers (Eq. 5).  Per pixel the cells are
+ * ordered by the ray's entry parameter into their box, max(0, t_near)
+ * (ties by cell index); C = sum_j P_j C_j, P_{j+1} = P_j T_j; output
+ * (C + P_{K+1} bg, P_{K+1}).  Saturation (redundancy reduction): when
+ * P_j < t_min the bit of (cell m_j, pixel) is cleared in masks for the
+ * next render of the view (and, with SX_FLAG_SAME_FRAME_CULL, the cell is
+ * skipped now).
+ *   partials  HOST array of K device pointers to [H*W*4] buffers.
+ *   cells     HOST array of K boxes.
+ *   out       [H*W*4] (rgb, T).
+ *   masks     [K * ceil(H*W/32)] uint32 words, cell-major, or NULL; bits
+ *             are only cleared, so the caller initialises them (all ones
+ *             = every pair active).
+ * K in 1..16. */
+sx_status sx_composite(int32_t K, const float* const* partials,
+                       const sx_cell* cells, const sx_camera* cam,
+                       const sx_params* p, float* out, uint32_t* masks,
+                       sx_stream stream);
+
+/* L1 loss of the composed image (the RGB term of the paper's loss):
+ * dout[H*W*4] = (sign(rgb - target) / (3HW), 0); loss_sum (device float,
+ * may be NULL) receives += the mean absolute error.  target [H*W*3]. */
+sx_status sx_l1_loss(const float* out, const float* target, int32_t width,
+                     int32_t height, float* dout, float* loss_sum,
+                     sx_stream stream);
+
+/* ------------------------------------------------------------- a7-a9 --
+ * Backward through the composition and every cell's render and
+ * projection (Eq. 6-7).  For cell m at pixel p with order position j:
+ * dC^m = P_j G, dT^m = P_j (G . B_{j+1} + g_T U_j) with B the colour behind
+ * the cell (background included) and U_j the transmittance behind it; then
+ * a reverse walk of the cell's blended pairs gives per-Gaussian gradients of
+ * mean2d, conic, opacity, colour and depth, chained to the parameters.
+ * Per cell (sx_cell_state, device pointers):
+ *   g, proj, vals, ranges           the cell's inputs and sort outputs
+ *   partial, last, mask             its forward outputs / mask (mask NULL =
+ *                                   all active)
+ *   grads                           parameter gradients: rows of Gaussians
+ *                                   visible in this view are written
+ *                                   (or accumulated with SX_BWD_ACCUMULATE);
+ *                                   other rows are untouched
+ *   g2d_ws                          [n*12] scratch (screen-space grads)
+ *   dpartial_ws                     [H*W*4] scratch (dL/d(C^m, T^m))
+ * dout [H*W*4]: dL/d(rgb, T) of the composed image.
+ * cells: HOST array of K boxes (same order as the forward). */
+#define SX_BWD_ACCUMULATE 1
+typedef struct sx_cell_state {
+  const sx_gaussians* g;
+  const sx_projected* proj;
+  const uint32_t* vals;
+  const uint32_t* ranges;
+  const float* partial;
+  const uint32_t* last;
+  const uint32_t* mask;
+  const sx_grads* grads;
+  float* g2d_ws;
+  float* dpartial_ws;
+} sx_cell_state;
+
+sx_status sx_backward(int32_t K, const sx_cell_state* cells,
+                      const sx_cell* boxes, const sx_camera* cam,
+                      const sx_params* p, const float* dout, int32_t flags,
+                      sx_stream stream);
+
+/* Stages of sx_backward, exposed for testing and for callers that
+ * schedule them themselves. */
+sx_status sx_composite_backward(int32_t K, const float* const* partials,
+                                const sx_cell* cells, const sx_camera* cam,
+                                const sx_params* p, const uint32_t* masks,
+                                const float* dout, float* const* dpartials,
+                                sx_stream stream);
+/* zeroes g2d rows of visible Gaussians, then accumulates screen-space
+ * gradients: g2d[i*12 + 0..9] = d(mean2d x, y, conic a, b, c, opacity,
+ * r, g, b, depth) */
+sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
+                             const uint32_t* tile_ranges, int64_t n,
+                             const sx_camera* cam,
+                             const sx_params* p, const uint32_t* mask,
+                             const float* partial, const uint32_t* last,
+                             const float* dpartial, const float* ddepth,
+                             float* g2d, sx_stream stream);
+sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,
+                                 const sx_params* p, const sx_projected* proj,
+                                 const float* g2d,
+                                 const sx_grads* grads, int32_t flags,
+                                 sx_stream stream);
+
+/* ----------------------------------------------------------------- a10 --
+ * Adam (the paper's optimiser is unnamed; textbook Adam with bias
+ * correction) over n FP32 elements: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, param -= lr (m / (1-b1^t)) / (sqrt(v/(1-b2^t)) +
+ * eps). */
+sx_status sx_adam(int64_t n, float* param, const float* grad, float* m,
+                  float* v, int32_t step, float lr, float beta1, float beta2,
+                  float eps, sx_stream stream);
+
+/* Fill n uint32 words with a value (kernel, safe inside graph capture). */
+sx_status sx_fill_u32(uint32_t* ptr, int64_t n, uint32_t value,
+                      sx_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPLAXEL_H */

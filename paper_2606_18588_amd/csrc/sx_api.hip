@@ -1,0 +1,308 @@
+// Host side of the C ABI declared in include/splaxel.h: argument
+// validation, conversion of the camera/parameters to kernel form, and
+// mapping of HIP errors to sx_status.  Nothing here allocates device memory.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "sx_internal.h"
+
+namespace {
+thread_local std::string g_err;
+
+sx_status fail(sx_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+sx_status fail(sx_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+sx_status dev(hipError_t e, const char* where) {
+  if (e == hipSuccess) return SX_OK;
+  return fail(SX_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+sx_status check_cam(const sx_camera* c) {
+  if (!c) return fail(SX_EINVAL, "camera is NULL");
+  if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384)
+    return fail(SX_EINVAL, "image size %dx%d outside 1..16384", c->width, c->height);
+  if (!(c->fx > 0.f) || !(c->fy > 0.f)) return fail(SX_EINVAL, "focal lengths must be > 0");
+  if (!(c->znear > 0.f)) return fail(SX_EINVAL, "znear must be > 0");
+  return SX_OK;
+}
+
+sx_status check_params(const sx_params* p) {
+  if (!p) return fail(SX_EINVAL, "params is NULL");
+  if (!sx::tile_shape_supported(p->tile_w, p->tile_h))
+    return fail(SX_EINVAL, "unsupported tile shape %dx%d", p->tile_w, p->tile_h);
+  if (p->sh_degree < 0 || p->sh_degree > 3)
+    return fail(SX_EINVAL, "sh_degree %d outside 0..3", p->sh_degree);
+  if (!(p->alpha_min > 0.f) || !(p->alpha_max > p->alpha_min) || !(p->alpha_max < 1.f))
+    return fail(SX_EINVAL, "need 0 < alpha_min < alpha_max < 1");
+  if (!(p->t_min >= 0.f) || !(p->eps2d >= 0.f)) return fail(SX_EINVAL, "t_min, eps2d must be >= 0");
+  return SX_OK;
+}
+
+sx_status check_gauss(const sx_gaussians* g) {
+  if (!g) return fail(SX_EINVAL, "gaussians is NULL");
+  if (g->n < 0 || g->n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "n=%lld out of range", (long long)g->n);
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+    return fail(SX_EINVAL, "null Gaussian parameter array");
+  return SX_OK;
+}
+
+int64_t tiles_of(const sx_camera* c, const sx_params* p) {
+  return (int64_t)((c->width + p->tile_w - 1) / p->tile_w) * ((c->height + p->tile_h - 1) / p->tile_h);
+}
+
+#define SX_TRY(expr)                 \
+  do {                               \
+    sx_status _s = (expr);           \
+    if (_s != SX_OK) return _s;      \
+  } while (0)
+}  // namespace
+
+namespace sx {
+DCam make_dcam(const sx_camera& c) {
+  DCam d;
+  for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = c.t[i];
+  d.fx = c.fx, d.fy = c.fy, d.cx = c.cx, d.cy = c.cy, d.znear = c.znear;
+  for (int j = 0; j < 3; ++j)
+    d.C[j] = -(d.R[0 * 3 + j] * d.t[0] + d.R[1 * 3 + j] * d.t[1] + d.R[2 * 3 + j] * d.t[2]);
+  d.W = c.width, d.H = c.height;
+  return d;
+}
+
+KParams make_kparams(const sx_params& p, const sx_camera& c) {
+  KParams k;
+  k.tile_w = p.tile_w, k.tile_h = p.tile_h;
+  k.tiles_x = (c.width + p.tile_w - 1) / p.tile_w;
+  k.tiles_y = (c.height + p.tile_h - 1) / p.tile_h;
+  k.sh_degree = p.sh_degree, k.flags = p.flags;
+  k.alpha_min = p.alpha_min, k.alpha_max = p.alpha_max, k.t_min = p.t_min;
+  k.eps2d = p.eps2d, k.alpha_min_d = p.alpha_min;
+  for (int i = 0; i < 3; ++i) k.bg[i] = p.bg[i];
+  return k;
+}
+}  // namespace sx
+
+extern "C" {
+
+const char* sx_last_error_string(void) { return g_err.c_str(); }
+const char* sx_version(void) { return "splaxel-mi355x 0.1 (gfx950)"; }
+
+int64_t sx_preprocess_blocks(int64_t n) { return n <= 0 ? 1 : (n + sx::kPreBlock - 1) / sx::kPreBlock; }
+
+sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
+                        const sx_params* p, sx_projected* out,
+                        sx_stream stream) {
+  SX_TRY(check_gauss(g));
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  if (!out || (g->n > 0 && (!out->rec || !out->rect || !out->n_tiles || !out->block_sums)))
+    return fail(SX_EINVAL, "null projected output array");
+  const int64_t tiles_x = (cam->width + p->tile_w - 1) / p->tile_w;
+  const int64_t tiles_y = (cam->height + p->tile_h - 1) / p->tile_h;
+  if (tiles_x > 65535 || tiles_y > 65535) return fail(SX_EINVAL, "tile grid too large for uint16 rects");
+  return dev(sx::launch_preprocess(*g, sx::make_dcam(*cam), sx::make_kparams(*p, *cam), *out,
+                                   (hipStream_t)stream),
+             "sx_preprocess");
+}
+
+sx_status sx_sort_workspace_size(int64_t n, int64_t capacity, int64_t tiles_total,
+                                 size_t* bytes) {
+  if (!bytes) return fail(SX_EINVAL, "bytes is NULL");
+  if (n < 0 || capacity < 0 || tiles_total < 1) return fail(SX_EINVAL, "negative size");
+  if (capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "capacity must be < 2^30");
+  *bytes = sx::sort_layout(n, capacity).total;
+  return SX_OK;
+}
+
+sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
+                  const sx_params* p, int64_t capacity, uint64_t* keys,
+                  uint32_t* vals, uint32_t* tile_ranges, void* ws,
+                  size_t ws_bytes, uint64_t* h_counts, sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  if (!proj || (n > 0 && (!proj->rec || !proj->rect || !proj->n_tiles || !proj->block_sums)))
+    return fail(SX_EINVAL, "null projected array");
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "n out of range");
+  if (capacity < 0 || capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "capacity must be in [0, 2^30)");
+  if (!vals && capacity > 0) return fail(SX_EINVAL, "vals is NULL");
+  if (!tile_ranges || !ws) return fail(SX_EINVAL, "tile_ranges/ws is NULL");
+  const int64_t tiles = tiles_of(cam, p);
+  const size_t need = sx::sort_layout(n, capacity).total;
+  if (ws_bytes < need) return fail(SX_EINVAL, "workspace %zu bytes < required %zu", ws_bytes, need);
+  bool over = false;
+  hipError_t e = sx::launch_sort(*proj, n, sx::make_kparams(*p, *cam), capacity, tiles, keys, vals,
+                                 tile_ranges, static_cast<char*>(ws), h_counts, &over,
+                                 (hipStream_t)stream);
+  SX_TRY(dev(e, "sx_sort"));
+  if (over)
+    return fail(SX_ECAPACITY, "instances %llu exceed capacity %lld",
+                (unsigned long long)h_counts[1], (long long)capacity);
+  return SX_OK;
+}
+
+sx_status sx_sort_counts(const void* ws, int64_t n, uint64_t* h_out, sx_stream stream) {
+  (void)n;
+  if (!ws || !h_out) return fail(SX_EINVAL, "null argument");
+  const size_t off = sx::sort_layout(0, 0).counts;
+  hipError_t e = hipMemcpyAsync(h_out, static_cast<const char*>(ws) + off, 4 * sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  return dev(e, "sx_sort_counts");
+}
+
+sx_status sx_render_partial(const sx_projected* proj, const uint32_t* vals,
+                            const uint32_t* tile_ranges, const sx_camera* cam,
+                            const sx_params* p, const uint32_t* mask,
+                            float* partial, float* depth, uint32_t* last,
+                            uint32_t* nblend, sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  if (!proj || !proj->rec || !tile_ranges || !partial || !last)
+    return fail(SX_EINVAL, "null argument");
+  return dev(sx::launch_render(*proj, vals, tile_ranges, sx::make_dcam(*cam),
+                               sx::make_kparams(*p, *cam), mask, partial, depth, last, nblend,
+                               (hipStream_t)stream),
+             "sx_render_partial");
+}
+
+static sx_status check_cells(int32_t K, const void* partials, const sx_cell* cells) {
+  if (K < 1 || K > sx::kMaxCells) return fail(SX_EINVAL, "K=%d outside 1..%d", K, sx::kMaxCells);
+  if (!partials || !cells) return fail(SX_EINVAL, "null partials/cells");
+  for (int m = 0; m < K; ++m)
+    for (int j = 0; j < 3; ++j)
+      if (std::isnan(cells[m].lo[j]) || std::isnan(cells[m].hi[j]) || cells[m].lo[j] > cells[m].hi[j])
+        return fail(SX_EINVAL, "cell %d has an empty or NaN box", m);
+  return SX_OK;
+}
+
+sx_status sx_composite(int32_t K, const float* const* partials,
+                       const sx_cell* cells, const sx_camera* cam,
+                       const sx_params* p, float* out, uint32_t* masks,
+                       sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  SX_TRY(check_cells(K, partials, cells));
+  if (!out) return fail(SX_EINVAL, "out is NULL");
+  for (int m = 0; m < K; ++m)
+    if (!partials[m]) return fail(SX_EINVAL, "partial %d is NULL", m);
+  return dev(sx::launch_composite(K, partials, cells, sx::make_dcam(*cam), sx::make_kparams(*p, *cam),
+                                  out, masks, (hipStream_t)stream),
+             "sx_composite");
+}
+
+sx_status sx_l1_loss(const float* out, const float* target, int32_t width,
+                     int32_t height, float* dout, float* loss_sum, sx_stream stream) {
+  if (!out || !target || !dout) return fail(SX_EINVAL, "null argument");
+  if (width < 1 || height < 1) return fail(SX_EINVAL, "bad image size");
+  return dev(sx::launch_l1(out, target, width, height, dout, loss_sum, (hipStream_t)stream),
+             "sx_l1_loss");
+}
+
+sx_status sx_composite_backward(int32_t K, const float* const* partials,
+                                const sx_cell* cells, const sx_camera* cam,
+                                const sx_params* p, const uint32_t* masks,
+                                const float* dout, float* const* dpartials,
+                                sx_stream stream) {
+  (void)masks;
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  SX_TRY(check_cells(K, partials, cells));
+  if (!dout || !dpartials) return fail(SX_EINVAL, "null argument");
+  for (int m = 0; m < K; ++m)
+    if (!partials[m] || !dpartials[m]) return fail(SX_EINVAL, "null buffer for cell %d", m);
+  return dev(sx::launch_composite_backward(K, partials, cells, sx::make_dcam(*cam),
+                                           sx::make_kparams(*p, *cam), dout, dpartials,
+                                           (hipStream_t)stream),
+             "sx_composite_backward");
+}
+
+sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
+                             const uint32_t* tile_ranges, int64_t n,
+                             const sx_camera* cam, const sx_params* p,
+                             const uint32_t* mask, const float* partial,
+                             const uint32_t* last, const float* dpartial,
+                             const float* ddepth, float* g2d, sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  if (!proj || !proj->rec || !proj->n_tiles || !tile_ranges || !partial || !last || !dpartial || !g2d)
+    return fail(SX_EINVAL, "null argument");
+  if (n < 0) return fail(SX_EINVAL, "n < 0");
+  return dev(sx::launch_render_backward(*proj, vals, tile_ranges, n, sx::make_dcam(*cam),
+                                        sx::make_kparams(*p, *cam), mask, partial, last, dpartial,
+                                        ddepth, g2d, (hipStream_t)stream),
+             "sx_render_backward");
+}
+
+sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,
+                                 const sx_params* p, const sx_projected* proj,
+                                 const float* g2d, const sx_grads* grads,
+                                 int32_t flags, sx_stream stream) {
+  SX_TRY(check_gauss(g));
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  if (!proj || !proj->n_tiles || !g2d || !grads) return fail(SX_EINVAL, "null argument");
+  if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
+    return fail(SX_EINVAL, "null gradient array");
+  return dev(sx::launch_preprocess_backward(*g, sx::make_dcam(*cam), sx::make_kparams(*p, *cam), *proj,
+                                            g2d, *grads, (flags & SX_BWD_ACCUMULATE) != 0,
+                                            (hipStream_t)stream),
+             "sx_preprocess_backward");
+}
+
+sx_status sx_backward(int32_t K, const sx_cell_state* cells, const sx_cell* boxes,
+                      const sx_camera* cam, const sx_params* p, const float* dout,
+                      int32_t flags, sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  if (K < 1 || K > sx::kMaxCells) return fail(SX_EINVAL, "K=%d outside 1..%d", K, sx::kMaxCells);
+  if (!cells || !boxes || !dout) return fail(SX_EINVAL, "null argument");
+  const float* parts[sx::kMaxCells];
+  float* dparts[sx::kMaxCells];
+  for (int m = 0; m < K; ++m) {
+    const sx_cell_state& c = cells[m];
+    if (!c.g || !c.proj || !c.ranges || !c.partial || !c.last || !c.grads || !c.g2d_ws || !c.dpartial_ws)
+      return fail(SX_EINVAL, "cell %d has a null member", m);
+    SX_TRY(check_gauss(c.g));
+    parts[m] = c.partial;
+    dparts[m] = c.dpartial_ws;
+  }
+  SX_TRY(sx_composite_backward(K, parts, boxes, cam, p, nullptr, dout, dparts, stream));
+  for (int m = 0; m < K; ++m) {
+    const sx_cell_state& c = cells[m];
+    SX_TRY(sx_render_backward(c.proj, c.vals, c.ranges, c.g->n, cam, p, c.mask, c.partial, c.last,
+                              c.dpartial_ws, nullptr, c.g2d_ws, stream));
+    SX_TRY(sx_preprocess_backward(c.g, cam, p, c.proj, c.g2d_ws, c.grads, flags, stream));
+  }
+  return SX_OK;
+}
+
+sx_status sx_adam(int64_t n, float* param, const float* grad, float* m, float* v,
+                  int32_t step, float lr, float beta1, float beta2, float eps,
+                  sx_stream stream) {
+  if (n < 0) return fail(SX_EINVAL, "n < 0");
+  if (n > 0 && (!param || !grad || !m || !v)) return fail(SX_EINVAL, "null argument");
+  if (step < 1) return fail(SX_EINVAL, "step must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f)) return fail(SX_EINVAL, "betas in [0,1)");
+  const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  return dev(sx::launch_adam(n, param, grad, m, v, lr, beta1, beta2, eps, bc1, bc2, (hipStream_t)stream),
+             "sx_adam");
+}
+
+sx_status sx_fill_u32(uint32_t* ptr, int64_t n, uint32_t value, sx_stream stream) {
+  if (n < 0 || (n > 0 && !ptr)) return fail(SX_EINVAL, "bad fill arguments");
+  return dev(sx::launch_fill(ptr, n, value, (hipStream_t)stream), "sx_fill_u32");
+}
+
+}  // extern "C"

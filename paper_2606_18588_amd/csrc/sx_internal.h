@@ -1,0 +1,257 @@
+// Internal declarations shared by the HIP translation units of libsplaxel.
+// Device helpers live here; the public C ABI is include/splaxel.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "splaxel.h"
+
+namespace sx {
+
+constexpr int kRecFloats = 12;   // per-Gaussian render record (48 B)
+constexpr int kG2dFloats = 12;   // per-Gaussian screen-space gradient row
+constexpr int kPreBlock = 256;   // Gaussians per preprocess block
+constexpr int kSortBlock = 256;  // threads per radix-sort block
+constexpr int kSortItems = 16;   // keys per thread
+constexpr int kSortTile = kSortBlock * kSortItems;  // keys per partition
+constexpr int kRadixBins = 256;
+constexpr int kMaxCells = 16;
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Camera in double (exact widening of the caller's float values) plus the
+// camera centre -R^T t, used by the FP64 projection kernels.
+struct DCam {
+  double R[9];
+  double t[3];
+  double fx, fy, cx, cy, znear;
+  double C[3];
+  int32_t W, H;
+};
+
+struct KParams {
+  int32_t tile_w, tile_h, tiles_x, tiles_y, sh_degree, flags;
+  float alpha_min, alpha_max, t_min;
+  double eps2d, alpha_min_d;
+  float bg[3];
+};
+
+DCam make_dcam(const sx_camera& c);
+KParams make_kparams(const sx_params& p, const sx_camera& c);
+
+// ---------------------------------------------------------------------------
+// sort workspace layout (byte offsets), shared by the size query and sx_sort
+struct SortLayout {
+  size_t counts;       // uint64[4]: visible, instances, overflow, error
+  size_t vis_off;      // uint32[nb]   exclusive visible offsets per block
+  size_t dkey[2];      // uint32[n]    depth keys (ping-pong)
+  size_t didx[2];      // uint32[n]    Gaussian indices (ping-pong)
+  size_t zero_begin;   // start of the region cleared on every call
+  size_t dhist;        // uint32[4][256] depth digit histograms
+  size_t thist;        // uint32[3][256] tile digit histograms
+  size_t counters;     // uint32[16] partition counters
+  size_t dstatus;      // uint32[4][dparts][256]
+  size_t tstatus;      // uint32[3][tparts][256]
+  size_t estatus;      // uint64[eparts] emit look-back
+  size_t zero_end;
+  size_t tkey[2];      // uint32[cap] tile ids (ping-pong)
+  size_t tval[2];      // uint32[cap] Gaussian indices (ping-pong)
+  size_t tsorted;      // uint32[cap] sorted tile ids (for ranges)
+  size_t total;
+  int64_t nb, dparts, tparts, eparts;
+};
+SortLayout sort_layout(int64_t n, int64_t capacity);
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Sum over a 64-lane wavefront with DPP row rotations and row broadcasts;
+// the total ends up in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  int x = __float_as_int(v);
+  // quad_perm [1,0,3,2] and [2,3,0,1]
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false));
+  x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false));
+  x = __float_as_int(v);
+  // row_ror:4, row_ror:8 -> every lane holds its 16-lane row sum
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x124, 0xF, 0xF, false));
+  x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false));
+  x = __float_as_int(v);
+  // row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false));
+  x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    uint32_t w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// Real orthonormal SH (Condon-Shortley phase) as homogeneous polynomials of
+// the unit direction (x, y, z); the constants are the normalisations
+// sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) times sqrt2 for m != 0, folded with the
+// polynomial coefficients of P_l^m.
+struct SHC {
+  static constexpr double c0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+  static constexpr double c1 = 0.48860251190291992;   // sqrt(3/(4 pi))
+  static constexpr double c2a = 1.0925484305920792;   // sqrt(15/(4 pi))
+  static constexpr double c2b = 0.31539156525252005;  // sqrt(5/(16 pi))
+  static constexpr double c2c = 0.54627421529603959;  // sqrt(15/(16 pi))
+  static constexpr double c3a = 0.59004358992664352;  // sqrt(35/(32 pi))
+  static constexpr double c3b = 2.8906114426405538;   // sqrt(105/(4 pi))
+  static constexpr double c3c = 0.45704579946446572;  // sqrt(21/(32 pi))
+  static constexpr double c3d = 0.37317633259011546;  // sqrt(7/(16 pi))
+  static constexpr double c3e = 1.4453057213202769;   // sqrt(105/(16 pi))
+};
+
+__device__ __forceinline__ void sh_basis(int deg, double x, double y, double z,
+                                         double* Y) {
+  Y[0] = SHC::c0;
+  if (deg < 1) return;
+  Y[1] = -SHC::c1 * y;
+  Y[2] = SHC::c1 * z;
+  Y[3] = -SHC::c1 * x;
+  if (deg < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = SHC::c2a * x * y;
+  Y[5] = -SHC::c2a * y * z;
+  Y[6] = SHC::c2b * (2.0 * zz - xx - yy);
+  Y[7] = -SHC::c2a * x * z;
+  Y[8] = SHC::c2c * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = -SHC::c3a * y * (3.0 * xx - yy);
+  Y[10] = SHC::c3b * x * y * z;
+  Y[11] = -SHC::c3c * y * (4.0 * zz - xx - yy);
+  Y[12] = SHC::c3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -SHC::c3c * x * (4.0 * zz - xx - yy);
+  Y[14] = SHC::c3e * z * (xx - yy);
+  Y[15] = -SHC::c3a * x * (xx - 3.0 * yy);
+}
+
+// gradient of each polynomial above with respect to (x, y, z): dY[k*3+c]
+__device__ __forceinline__ void sh_basis_grad(int deg, double x, double y,
+                                              double z, double* dY) {
+  for (int k = 0; k < 3; ++k) dY[k] = 0.0;
+  if (deg < 1) return;
+  dY[3 + 0] = 0.0, dY[3 + 1] = -SHC::c1, dY[3 + 2] = 0.0;
+  dY[6 + 0] = 0.0, dY[6 + 1] = 0.0, dY[6 + 2] = SHC::c1;
+  dY[9 + 0] = -SHC::c1, dY[9 + 1] = 0.0, dY[9 + 2] = 0.0;
+  if (deg < 2) return;
+  const double a = SHC::c2a, b = SHC::c2b, c = SHC::c2c;
+  dY[12 + 0] = a * y, dY[12 + 1] = a * x, dY[12 + 2] = 0.0;
+  dY[15 + 0] = 0.0, dY[15 + 1] = -a * z, dY[15 + 2] = -a * y;
+  dY[18 + 0] = -2.0 * b * x, dY[18 + 1] = -2.0 * b * y, dY[18 + 2] = 4.0 * b * z;
+  dY[21 + 0] = -a * z, dY[21 + 1] = 0.0, dY[21 + 2] = -a * x;
+  dY[24 + 0] = 2.0 * c * x, dY[24 + 1] = -2.0 * c * y, dY[24 + 2] = 0.0;
+  if (deg < 3) return;
+  const double e = -SHC::c3a, f = SHC::c3b, g = -SHC::c3c, h = SHC::c3d,
+               k = SHC::c3e;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  // e (3 x^2 y - y^3)
+  dY[27 + 0] = 6.0 * e * x * y, dY[27 + 1] = e * (3.0 * xx - 3.0 * yy), dY[27 + 2] = 0.0;
+  // f x y z
+  dY[30 + 0] = f * y * z, dY[30 + 1] = f * x * z, dY[30 + 2] = f * x * y;
+  // g (4 y z^2 - x^2 y - y^3)
+  dY[33 + 0] = -2.0 * g * x * y, dY[33 + 1] = g * (4.0 * zz - xx - 3.0 * yy),
+          dY[33 + 2] = 8.0 * g * y * z;
+  // h (2 z^3 - 3 x^2 z - 3 y^2 z)
+  dY[36 + 0] = -6.0 * h * x * z, dY[36 + 1] = -6.0 * h * y * z,
+          dY[36 + 2] = h * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+  // g (4 x z^2 - x^3 - x y^2)
+  dY[39 + 0] = g * (4.0 * zz - 3.0 * xx - yy), dY[39 + 1] = -2.0 * g * x * y,
+          dY[39 + 2] = 8.0 * g * x * z;
+  // k (x^2 z - y^2 z)
+  dY[42 + 0] = 2.0 * k * x * z, dY[42 + 1] = -2.0 * k * y * z, dY[42 + 2] = k * (xx - yy);
+  // e (x^3 - 3 x y^2)
+  dY[45 + 0] = e * (3.0 * xx - 3.0 * yy), dY[45 + 1] = -6.0 * e * x * y, dY[45 + 2] = 0.0;
+}
+
+// Rotation matrix of a unit quaternion (w, x, y, z), row-major.
+__device__ __forceinline__ void quat_rot(double w, double x, double y,
+                                         double z, double* R) {
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Per-pixel alpha of one Gaussian (Eq. 1 with the clamp): the forward and
+// the backward kernels call this same function so their decisions agree
+// bit for bit.
+struct AlphaEval {
+  float G;      // exp(-q/2)
+  float alpha;  // min(alpha_max, o G)
+  bool clamped;
+};
+__device__ __forceinline__ AlphaEval eval_alpha(float dx, float dy, float a,
+                                                float b, float c, float o,
+                                                float alpha_max) {
+  const float t = fmaf(b + b, dy, a * dx);     // a dx + 2 b dy
+  const float q = fmaf(t, dx, (c * dy) * dy);  // a dx^2 + 2 b dx dy + c dy^2
+  AlphaEval r;
+  r.G = __builtin_amdgcn_exp2f(q * (-0.5f * kLog2e));
+  const float araw = o * r.G;
+  r.clamped = araw > alpha_max;
+  r.alpha = r.clamped ? alpha_max : araw;
+  return r;
+}
+
+}  // namespace sx
+
+// host-side launchers (defined in the .hip files)
+namespace sx {
+hipError_t launch_preprocess(const sx_gaussians& g, const DCam& cam,
+                             const KParams& p, const sx_projected& out,
+                             hipStream_t st);
+hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
+                                      const KParams& p,
+                                      const sx_projected& proj,
+                                      const float* g2d, const sx_grads& gr,
+                                      bool accumulate, hipStream_t st);
+hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
+                       int64_t capacity, int64_t tiles_total, uint64_t* keys,
+                       uint32_t* vals, uint32_t* ranges, char* ws,
+                       uint64_t* h_counts, bool* over_capacity,
+                       hipStream_t st);
+hipError_t launch_render(const sx_projected& proj, const uint32_t* vals,
+                         const uint32_t* ranges, const DCam& cam,
+                         const KParams& p, const uint32_t* mask,
+                         float* partial, float* depth, uint32_t* last,
+                         uint32_t* nblend, hipStream_t st);
+hipError_t launch_render_backward(const sx_projected& proj,
+                                  const uint32_t* vals, const uint32_t* ranges,
+                                  int64_t n, const DCam& cam, const KParams& p,
+                                  const uint32_t* mask, const float* partial,
+                                  const uint32_t* last, const float* dpartial,
+                                  const float* ddepth, float* g2d,
+                                  hipStream_t st);
+hipError_t launch_composite(int K, const float* const* partials,
+                            const sx_cell* cells, const DCam& cam,
+                            const KParams& p, float* out, uint32_t* masks,
+                            hipStream_t st);
+hipError_t launch_composite_backward(int K, const float* const* partials,
+                                     const sx_cell* cells, const DCam& cam,
+                                     const KParams& p, const float* dout,
+                                     float* const* dpartials, hipStream_t st);
+hipError_t launch_l1(const float* out, const float* target, int W, int H,
+                     float* dout, float* loss, hipStream_t st);
+hipError_t launch_adam(int64_t n, float* param, const float* grad, float* m,
+                       float* v, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, hipStream_t st);
+hipError_t launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+bool tile_shape_supported(int tw, int th);
+}  // namespace sx

@@ -1,0 +1,383 @@
+// Projection of Gaussians to screen space and its backward (paper,
+// background: projection step; Eq. 1 footprint; chain of the
+// parametrisation Sigma = R S S^T R^T).
+//
+// One thread per Gaussian.  The arithmetic is FP64 (cheap on CDNA4: the
+// kernel is bound by HBM reads of the parameters), rounded once to FP32 for
+// the render record, so depths, footprints and tile counts are reproducible
+// to the last bit.  A Gaussian culled by its mean depth costs one 12-byte
+// read and a 4-byte write; only visible ones read rotation, scale, opacity
+// and SH coefficients.
+#include "sx_internal.h"
+
+namespace sx {
+
+struct PreArgs {
+  int64_t n;
+  const float* __restrict__ means;
+  const float* __restrict__ log_scales;
+  const float* __restrict__ quats;
+  const float* __restrict__ logits;
+  const float* __restrict__ sh;
+  DCam cam;
+  KParams p;
+  float* __restrict__ rec;
+  uint16_t* __restrict__ rect;
+  uint32_t* __restrict__ n_tiles;
+  uint32_t* __restrict__ block_sums;
+};
+
+// Screen-space quantities of one Gaussian, double precision.
+struct Proj64 {
+  double t[3];       // camera-space mean
+  double Rq[9];      // rotation of the normalised quaternion
+  double qh[4], qn;  // normalised quaternion and the input norm
+  double s[3];       // scales
+  double M[9];       // W Sigma W^T
+  double J[6];
+  double cov[3];     // dilated 2D covariance xx, xy, yy
+  double conic[3];
+  double o;
+  double dir[3], dist;
+};
+
+// Camera transform, culling and the EWA covariance.  Returns false when the
+// Gaussian is culled (mean behind znear, zero quaternion, singular 2D
+// covariance).
+__device__ __forceinline__ bool project_geometry(const float* __restrict__ means,
+                                                 const float* __restrict__ log_scales,
+                                                 const float* __restrict__ quats,
+                                                 int64_t i, const DCam& cam,
+                                                 double eps2d, Proj64& g) {
+  const double mx = means[i * 3 + 0], my = means[i * 3 + 1], mz = means[i * 3 + 2];
+  for (int r = 0; r < 3; ++r)
+    g.t[r] = cam.R[r * 3 + 0] * mx + cam.R[r * 3 + 1] * my + cam.R[r * 3 + 2] * mz + cam.t[r];
+  if (!(g.t[2] > cam.znear)) return false;
+  const double qw = quats[i * 4 + 0], qx = quats[i * 4 + 1], qy = quats[i * 4 + 2],
+               qz = quats[i * 4 + 3];
+  g.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  if (g.qn < 1e-12) return false;
+  g.qh[0] = qw / g.qn, g.qh[1] = qx / g.qn, g.qh[2] = qy / g.qn, g.qh[3] = qz / g.qn;
+  quat_rot(g.qh[0], g.qh[1], g.qh[2], g.qh[3], g.Rq);
+  double s2[3];
+  for (int k = 0; k < 3; ++k) {
+    g.s[k] = exp((double)log_scales[i * 3 + k]);
+    s2[k] = g.s[k] * g.s[k];
+  }
+  double Sig[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += g.Rq[r * 3 + k] * s2[k] * g.Rq[c * 3 + k];
+      Sig[r * 3 + c] = v;
+    }
+  double WS[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += cam.R[r * 3 + k] * Sig[k * 3 + c];
+      WS[r * 3 + c] = v;
+    }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += WS[r * 3 + k] * cam.R[c * 3 + k];
+      g.M[r * 3 + c] = v;
+    }
+  const double z = g.t[2];
+  g.J[0] = cam.fx / z, g.J[1] = 0.0, g.J[2] = -cam.fx * g.t[0] / (z * z);
+  g.J[3] = 0.0, g.J[4] = cam.fy / z, g.J[5] = -cam.fy * g.t[1] / (z * z);
+  double JM[6];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += g.J[r * 3 + k] * g.M[k * 3 + c];
+      JM[r * 3 + c] = v;
+    }
+  double S2[4];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += JM[r * 3 + k] * g.J[c * 3 + k];
+      S2[r * 2 + c] = v;
+    }
+  g.cov[0] = S2[0] + eps2d;
+  g.cov[1] = 0.5 * (S2[1] + S2[2]);
+  g.cov[2] = S2[3] + eps2d;
+  const double det = g.cov[0] * g.cov[2] - g.cov[1] * g.cov[1];
+  if (!(det > 0.0)) return false;
+  g.conic[0] = g.cov[2] / det;
+  g.conic[1] = -g.cov[1] / det;
+  g.conic[2] = g.cov[0] / det;
+  const double dv[3] = {mx - cam.C[0], my - cam.C[1], mz - cam.C[2]};
+  g.dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  for (int k = 0; k < 3; ++k) g.dir[k] = dv[k] / g.dist;
+  return true;
+}
+
+__device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
+  Proj64 g;
+  if (!project_geometry(a.means, a.log_scales, a.quats, i, a.cam, a.p.eps2d, g)) return 0;
+  const double z = g.t[2];
+  const double mx2 = a.cam.fx * g.t[0] / z, my2 = a.cam.fy * g.t[1] / z;
+  const double mux = mx2 + a.cam.cx, muy = my2 + a.cam.cy;
+  const double o = 1.0 / (1.0 + exp(-(double)a.logits[i]));
+  if (o < a.p.alpha_min_d) return 0;
+  // exact footprint of alpha >= alpha_min: q <= tau with tau = 2 ln(o/alpha_min)
+  const double tau = 2.0 * log(o / a.p.alpha_min_d);
+  const double ex = sqrt(tau * g.cov[0]), ey = sqrt(tau * g.cov[2]);
+  double x0 = ceil(mux - ex - 0.5), x1 = floor(mux + ex - 0.5);
+  double y0 = ceil(muy - ey - 0.5), y1 = floor(muy + ey - 0.5);
+  x0 = fmin(fmax(x0, 0.0), (double)a.cam.W);
+  y0 = fmin(fmax(y0, 0.0), (double)a.cam.H);
+  x1 = fmin(fmax(x1, -1.0), (double)a.cam.W - 1);
+  y1 = fmin(fmax(y1, -1.0), (double)a.cam.H - 1);
+  if (!(x0 <= x1 && y0 <= y1)) return 0;
+  const int tx0 = (int)x0 / a.p.tile_w, tx1 = (int)x1 / a.p.tile_w;
+  const int ty0 = (int)y0 / a.p.tile_h, ty1 = (int)y1 / a.p.tile_h;
+  // colour: max(0, sum_lm k_lm Y_lm(dir) + 0.5)
+  const int deg = a.p.sh_degree;
+  const int nc = (deg + 1) * (deg + 1);
+  double Y[16];
+  sh_basis(deg, g.dir[0], g.dir[1], g.dir[2], Y);
+  const float* __restrict__ shp = a.sh + (size_t)i * nc * 3;
+  double col[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < nc; ++k) {
+    col[0] += (double)shp[k * 3 + 0] * Y[k];
+    col[1] += (double)shp[k * 3 + 1] * Y[k];
+    col[2] += (double)shp[k * 3 + 2] * Y[k];
+  }
+  float* r = a.rec + (size_t)i * kRecFloats;
+  float4 r0, r1, r2;
+  r0.x = (float)mx2, r0.y = (float)my2, r0.z = (float)g.conic[0], r0.w = (float)g.conic[1];
+  r1.x = (float)g.conic[2], r1.y = (float)o;
+  r1.z = (float)fmax(col[0] + 0.5, 0.0), r1.w = (float)fmax(col[1] + 0.5, 0.0);
+  r2.x = (float)fmax(col[2] + 0.5, 0.0), r2.y = (float)z, r2.z = 0.f, r2.w = 0.f;
+  reinterpret_cast<float4*>(r)[0] = r0;
+  reinterpret_cast<float4*>(r)[1] = r1;
+  reinterpret_cast<float4*>(r)[2] = r2;
+  ushort4 rc;
+  rc.x = (uint16_t)tx0, rc.y = (uint16_t)ty0, rc.z = (uint16_t)(tx1 + 1), rc.w = (uint16_t)(ty1 + 1);
+  reinterpret_cast<ushort4*>(a.rect)[i] = rc;
+  return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+}
+
+__global__ __launch_bounds__(kPreBlock) void k_preprocess(PreArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  uint32_t cnt = 0;
+  if (i < a.n) {
+    cnt = project_one(a, i);
+    a.n_tiles[i] = cnt;
+  }
+  uint32_t vis = cnt > 0 ? 1u : 0u;
+  for (int o = 32; o >= 1; o >>= 1) {
+    vis += __shfl_xor(vis, o, 64);
+    cnt += __shfl_xor(cnt, o, 64);
+  }
+  __shared__ uint32_t sv[kPreBlock / 64], sc[kPreBlock / 64];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sv[w] = vis, sc[w] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a0 = 0, a1 = 0;
+    for (int k = 0; k < kPreBlock / 64; ++k) a0 += sv[k], a1 += sc[k];
+    a.block_sums[2 * (size_t)blockIdx.x + 0] = a0;
+    a.block_sums[2 * (size_t)blockIdx.x + 1] = a1;
+  }
+}
+
+hipError_t launch_preprocess(const sx_gaussians& g, const DCam& cam,
+                             const KParams& p, const sx_projected& out,
+                             hipStream_t st) {
+  if (g.n == 0) return hipSuccess;
+  PreArgs a;
+  a.n = g.n;
+  a.means = g.means, a.log_scales = g.log_scales, a.quats = g.quats;
+  a.logits = g.opacity_logits, a.sh = g.sh;
+  a.cam = cam, a.p = p;
+  a.rec = out.rec, a.rect = out.rect, a.n_tiles = out.n_tiles;
+  a.block_sums = out.block_sums;
+  const int64_t blocks = (g.n + kPreBlock - 1) / kPreBlock;
+  hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(kPreBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- backward
+struct PreBwdArgs {
+  int64_t n;
+  const float* __restrict__ means;
+  const float* __restrict__ log_scales;
+  const float* __restrict__ quats;
+  const float* __restrict__ logits;
+  const float* __restrict__ sh;
+  const uint32_t* __restrict__ n_tiles;
+  const float* __restrict__ g2d;
+  DCam cam;
+  KParams p;
+  float* gmeans;
+  float* glog_scales;
+  float* gquats;
+  float* glogits;
+  float* gsh;
+  int accumulate;
+};
+
+__device__ __forceinline__ void put(float* p, double v, bool acc) {
+  if (acc)
+    *p += (float)v;
+  else
+    *p = (float)v;
+}
+
+// Chain of screen-space gradients (mean2d, conic, opacity, colour, depth)
+// to the parameters: conic -> 2D covariance (G_S = -A Gc A), -> (J, M)
+// (dM = J^T G_S J, dJ = 2 G_S J M), M -> Sigma (W^T dM W), Sigma = L L^T
+// with L = R(q) S (dL = 2 dSigma L) -> log-scales and the quaternion; the
+// mean through mean2d, J(t), depth and the SH view direction.
+__global__ __launch_bounds__(128) void k_preprocess_backward(PreBwdArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (i >= a.n || a.n_tiles[i] == 0) return;
+  const bool acc = a.accumulate != 0;
+  Proj64 g;
+  if (!project_geometry(a.means, a.log_scales, a.quats, i, a.cam, a.p.eps2d, g)) return;
+  const float* gr = a.g2d + (size_t)i * kG2dFloats;
+  const float4 g0 = reinterpret_cast<const float4*>(gr)[0];
+  const float4 g1 = reinterpret_cast<const float4*>(gr)[1];
+  const float2 g2 = reinterpret_cast<const float2*>(gr)[4];
+  const double gmx = g0.x, gmy = g0.y, ga = g0.z, gb = g0.w, gc = g1.x, gop = g1.y;
+  const double gcol[3] = {g1.z, g1.w, g2.x};
+  const double gz = g2.y;
+  const int deg = a.p.sh_degree;
+  const int nc = (deg + 1) * (deg + 1);
+  // colour -> SH coefficients and direction
+  double Y[16], dY[48];
+  sh_basis(deg, g.dir[0], g.dir[1], g.dir[2], Y);
+  sh_basis_grad(deg, g.dir[0], g.dir[1], g.dir[2], dY);
+  const float* __restrict__ shp = a.sh + (size_t)i * nc * 3;
+  float* gshp = a.gsh + (size_t)i * nc * 3;
+  double gdir[3] = {0.0, 0.0, 0.0};
+  for (int ch = 0; ch < 3; ++ch) {
+    double v = 0.0;
+    for (int k = 0; k < nc; ++k) v += (double)shp[k * 3 + ch] * Y[k];
+    const bool pos = v + 0.5 > 0.0;
+    const double gcv = pos ? gcol[ch] : 0.0;
+    for (int k = 0; k < nc; ++k) {
+      put(&gshp[k * 3 + ch], gcv * Y[k], acc);
+      const double w = gcv * (double)shp[k * 3 + ch];
+      gdir[0] += w * dY[k * 3 + 0];
+      gdir[1] += w * dY[k * 3 + 1];
+      gdir[2] += w * dY[k * 3 + 2];
+    }
+  }
+  double gmu[3];
+  {
+    const double dd = gdir[0] * g.dir[0] + gdir[1] * g.dir[1] + gdir[2] * g.dir[2];
+    for (int k = 0; k < 3; ++k) gmu[k] = (gdir[k] - dd * g.dir[k]) / g.dist;
+  }
+  // opacity through the sigmoid
+  const double o = 1.0 / (1.0 + exp(-(double)a.logits[i]));
+  put(&a.glogits[i], gop * o * (1.0 - o), acc);
+  // conic -> covariance
+  const double A[4] = {g.conic[0], g.conic[1], g.conic[1], g.conic[2]};
+  const double Gc[4] = {ga, 0.5 * gb, 0.5 * gb, gc};
+  double T1[4], GS[4];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) T1[r * 2 + c] = A[r * 2 + 0] * Gc[0 * 2 + c] + A[r * 2 + 1] * Gc[1 * 2 + c];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) GS[r * 2 + c] = -(T1[r * 2 + 0] * A[0 * 2 + c] + T1[r * 2 + 1] * A[1 * 2 + c]);
+  double dM[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int u = 0; u < 2; ++u)
+        for (int w = 0; w < 2; ++w) v += g.J[u * 3 + r] * GS[u * 2 + w] * g.J[w * 3 + c];
+      dM[r * 3 + c] = v;
+    }
+  double GJ[6], dJ[6];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c) GJ[r * 3 + c] = GS[r * 2 + 0] * g.J[0 * 3 + c] + GS[r * 2 + 1] * g.J[1 * 3 + c];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += GJ[r * 3 + k] * g.M[k * 3 + c];
+      dJ[r * 3 + c] = 2.0 * v;
+    }
+  const double* W = a.cam.R;
+  double Tm[9], dS[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += W[k * 3 + r] * dM[k * 3 + c];
+      Tm[r * 3 + c] = v;
+    }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += Tm[r * 3 + k] * W[k * 3 + c];
+      dS[r * 3 + c] = v;
+    }
+  // dL = 2 dSigma L, L = Rq diag(s)
+  double dLm[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += dS[r * 3 + k] * g.Rq[k * 3 + c] * g.s[c];
+      dLm[r * 3 + c] = 2.0 * v;
+    }
+  for (int k = 0; k < 3; ++k) {
+    double v = 0;
+    for (int r = 0; r < 3; ++r) v += dLm[r * 3 + k] * g.Rq[r * 3 + k];
+    put(&a.glog_scales[i * 3 + k], v * g.s[k], acc);
+  }
+  double dR[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dLm[r * 3 + c] * g.s[c];
+  const double w = g.qh[0], x = g.qh[1], y = g.qh[2], zq = g.qh[3];
+  double dq[4];
+  dq[0] = 2.0 * (-zq * dR[1] + y * dR[2] + zq * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  dq[1] = 2.0 * (y * dR[1] + zq * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + zq * dR[6] +
+                 w * dR[7] - 2.0 * x * dR[8]);
+  dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + zq * dR[5] - w * dR[6] +
+                 zq * dR[7] - 2.0 * y * dR[8]);
+  dq[3] = 2.0 * (-2.0 * zq * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * zq * dR[4] +
+                 y * dR[5] + x * dR[6] + y * dR[7]);
+  {
+    const double dd = dq[0] * g.qh[0] + dq[1] * g.qh[1] + dq[2] * g.qh[2] + dq[3] * g.qh[3];
+    for (int k = 0; k < 4; ++k) put(&a.gquats[i * 4 + k], (dq[k] - dd * g.qh[k]) / g.qn, acc);
+  }
+  // mean: mean2d, J(t), depth; then world = W^T dt (+ SH direction term)
+  const double z = g.t[2], fx = a.cam.fx, fy = a.cam.fy;
+  const double tx = g.t[0], ty = g.t[1];
+  double dt[3];
+  dt[0] = gmx * fx / z + dJ[2] * (-fx / (z * z));
+  dt[1] = gmy * fy / z + dJ[5] * (-fy / (z * z));
+  dt[2] = gmx * (-fx * tx / (z * z)) + gmy * (-fy * ty / (z * z)) + dJ[0] * (-fx / (z * z)) +
+          dJ[2] * (2.0 * fx * tx / (z * z * z)) + dJ[4] * (-fy / (z * z)) +
+          dJ[5] * (2.0 * fy * ty / (z * z * z)) + gz;
+  for (int k = 0; k < 3; ++k)
+    put(&a.gmeans[i * 3 + k], W[0 * 3 + k] * dt[0] + W[1 * 3 + k] * dt[1] + W[2 * 3 + k] * dt[2] + gmu[k],
+        acc);
+}
+
+hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
+                                      const KParams& p,
+                                      const sx_projected& proj,
+                                      const float* g2d, const sx_grads& gr,
+                                      bool accumulate, hipStream_t st) {
+  if (g.n == 0) return hipSuccess;
+  PreBwdArgs a;
+  a.n = g.n;
+  a.means = g.means, a.log_scales = g.log_scales, a.quats = g.quats;
+  a.logits = g.opacity_logits, a.sh = g.sh;
+  a.n_tiles = proj.n_tiles;
+  a.g2d = g2d;
+  a.cam = cam, a.p = p;
+  a.gmeans = gr.means, a.glog_scales = gr.log_scales, a.gquats = gr.quats;
+  a.glogits = gr.opacity_logits, a.gsh = gr.sh;
+  a.accumulate = accumulate ? 1 : 0;
+  const int64_t blocks = (g.n + 127) / 128;
+  hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)blocks), dim3(128), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace sx

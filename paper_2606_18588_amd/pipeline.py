@@ -1,0 +1,239 @@
+"""One view over K cells on one GPU: per cell preprocess -> sort -> partial
+render (Eq. 1-4), then composition (Eq. 5) and the backward (Eq. 6-7).
+
+The paper gives every GPU one convex cell and exchanges partial pixels
+between GPUs; here the K cells' partial buffers stay resident in HBM and the
+composition reads them directly.  Buffers are torch tensors (device memory
+and streams only); every step runs in libsplaxel's HIP kernels.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+@dataclass
+class GaussianParams:
+    """One cell's Gaussian parameters on the GPU (FP32, SoA)."""
+
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacity_logits: torch.Tensor
+    sh: torch.Tensor
+
+    @classmethod
+    def from_arrays(cls, means, log_scales, quats, opacity_logits, sh,
+                    device="cuda") -> "GaussianParams":
+        def t(a):
+            return torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(device)
+        return cls(t(means), t(log_scales), t(quats), t(opacity_logits), t(sh))
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda") -> "GaussianParams":
+        return cls.from_arrays(scene.means, scene.log_scales, scene.quats,
+                               scene.opacity_logits, scene.sh, device)
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def sh_degree(self) -> int:
+        return int(round(math.sqrt(self.sh.shape[1]))) - 1
+
+    def tensors(self) -> List[torch.Tensor]:
+        return [self.means, self.log_scales, self.quats, self.opacity_logits, self.sh]
+
+    def zeros_like(self) -> "GaussianParams":
+        return GaussianParams(*[torch.zeros_like(t) for t in self.tensors()])
+
+    def struct(self) -> B.SxGaussians:
+        return B.gaussians(*self.tensors())
+
+    def grad_struct(self) -> B.SxGrads:
+        return B.grads(*self.tensors())
+
+
+def tiles_of(cam, settings):
+    tx = (cam.width + settings.tile_w - 1) // settings.tile_w
+    ty = (cam.height + settings.tile_h - 1) // settings.tile_h
+    return tx, ty
+
+
+class CellView:
+    """Buffers and steps for one (cell, view) pair."""
+
+    def __init__(self, params: GaussianParams, cam, settings, capacity=None,
+                 keep_keys=False, flags=0, device="cuda"):
+        self.params = params
+        self.cam = cam
+        self.settings = settings
+        self.flags = flags
+        self.device = device
+        n = params.n
+        self.tiles_x, self.tiles_y = tiles_of(cam, settings)
+        self.tiles = self.tiles_x * self.tiles_y
+        self.H, self.W = cam.height, cam.width
+        self.c_cam = B.camera(cam)
+        self.c_par = B.params(settings, params.sh_degree, flags)
+        self.c_g = params.struct()
+        self.rec = torch.empty((max(n, 1), 12), dtype=torch.float32, device=device)
+        self.rect = torch.empty((max(n, 1), 4), dtype=torch.int16, device=device)
+        self.n_tiles = torch.empty((max(n, 1),), dtype=torch.int32, device=device)
+        self.block_sums = torch.empty((B.sx_preprocess_blocks(n) * 2,), dtype=torch.int32,
+                                      device=device)
+        self.c_proj = B.projected(self.rec, self.rect, self.n_tiles, self.block_sums)
+        self.ranges = torch.empty((self.tiles, 2), dtype=torch.int32, device=device)
+        self.keep_keys = keep_keys
+        self.counts = None
+        self._alloc_sort(capacity if capacity is not None else max(1024, 4 * n))
+        hw = self.H * self.W
+        self.partial = torch.empty((self.H, self.W, 4), dtype=torch.float32, device=device)
+        self.last = torch.empty((self.H, self.W), dtype=torch.int32, device=device)
+        self.nblend = torch.empty((self.H, self.W), dtype=torch.int32, device=device)
+        self.depth = None
+        self.g2d = None
+        self.dpartial = None
+        self.mask = None
+        self._hw = hw
+
+    def _alloc_sort(self, capacity: int):
+        self.capacity = int(capacity)
+        self.vals = torch.empty((max(self.capacity, 1),), dtype=torch.int32, device=self.device)
+        self.keys = (torch.empty((max(self.capacity, 1),), dtype=torch.int64, device=self.device)
+                     if self.keep_keys else None)
+        nbytes = B.sx_sort_workspace_size(self.params.n, self.capacity, self.tiles)
+        self.ws = torch.empty((nbytes,), dtype=torch.uint8, device=self.device)
+
+    # ---------------------------------------------------------------- steps
+    def preprocess(self):
+        B.sx_preprocess(self.c_g, self.c_cam, self.c_par, self.c_proj)
+
+    def sort(self, sync=True):
+        """With sync, reads the instance count back once and grows the
+        buffers when they are too small; without, sorts asynchronously into
+        the current capacity."""
+        if not sync:
+            B.sx_sort(self.c_proj, self.params.n, self.c_cam, self.c_par, self.capacity,
+                      self.keys, self.vals, self.ranges, self.ws, sync_counts=False)
+            return None
+        try:
+            self.counts = B.sx_sort(self.c_proj, self.params.n, self.c_cam, self.c_par,
+                                    self.capacity, self.keys, self.vals, self.ranges, self.ws,
+                                    sync_counts=True)
+        except B.SplaxelError as e:
+            if e.code != B.SX_ECAPACITY:
+                raise
+            need = B.sx_sort_counts(self.ws, self.params.n)[1]
+            self._alloc_sort(int(need * 1.25) + 1024)
+            self.counts = B.sx_sort(self.c_proj, self.params.n, self.c_cam, self.c_par,
+                                    self.capacity, self.keys, self.vals, self.ranges, self.ws,
+                                    sync_counts=True)
+        return self.counts
+
+    def render(self, mask=None, want_depth=False, want_nblend=True):
+        self.mask = mask
+        if want_depth and self.depth is None:
+            self.depth = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
+        B.sx_render_partial(self.c_proj, self.vals, self.ranges, self.c_cam, self.c_par, mask,
+                            self.partial, self.depth if want_depth else None, self.last,
+                            self.nblend if want_nblend else None)
+        return self.partial
+
+    def ensure_backward_buffers(self):
+        if self.g2d is None:
+            self.g2d = torch.empty((max(self.params.n, 1), 12), dtype=torch.float32,
+                                   device=self.device)
+            self.dpartial = torch.empty((self.H, self.W, 4), dtype=torch.float32,
+                                        device=self.device)
+
+    def render_backward(self, dpartial, ddepth=None):
+        self.ensure_backward_buffers()
+        B.sx_render_backward(self.c_proj, self.vals, self.ranges, self.params.n, self.c_cam,
+                             self.c_par, self.mask, self.partial, self.last, dpartial, ddepth,
+                             self.g2d)
+        return self.g2d
+
+    def preprocess_backward(self, grads: GaussianParams, accumulate=False):
+        B.sx_preprocess_backward(self.c_g, self.c_cam, self.c_par, self.c_proj, self.g2d,
+                                 grads.grad_struct(),
+                                 B.SX_BWD_ACCUMULATE if accumulate else 0)
+
+    def state(self, grads: GaussianParams) -> B.SxCellState:
+        """C struct for sx_backward; keeps the referenced structs alive."""
+        self.ensure_backward_buffers()
+        self._gs = grads.grad_struct()
+        s = B.SxCellState()
+        s.g = ctypes_pointer(self.c_g)
+        s.proj = ctypes_pointer(self.c_proj)
+        s.vals = B.ptr(self.vals)
+        s.ranges = B.ptr(self.ranges)
+        s.partial = B.ptr(self.partial)
+        s.last = B.ptr(self.last)
+        s.mask = B.ptr(self.mask) if self.mask is not None else None
+        s.grads = ctypes_pointer(self._gs)
+        s.g2d_ws = B.ptr(self.g2d)
+        s.dpartial_ws = B.ptr(self.dpartial)
+        return s
+
+
+def ctypes_pointer(obj):
+    import ctypes
+    return ctypes.pointer(obj)
+
+
+class Frame:
+    """One view of a scene split into K cells: forward and backward."""
+
+    def __init__(self, cells: Sequence[GaussianParams], boxes, cam, settings,
+                 flags=0, capacities=None, keep_keys=False, device="cuda"):
+        self.cells = list(cells)
+        self.boxes = list(boxes)
+        assert len(self.cells) == len(self.boxes)
+        self.cam = cam
+        self.settings = settings
+        self.flags = flags
+        sh_deg = self.cells[0].sh_degree
+        self.views = [CellView(c, cam, settings,
+                               None if capacities is None else capacities[k],
+                               keep_keys, flags, device)
+                      for k, c in enumerate(self.cells)]
+        self.c_cam = B.camera(cam)
+        self.c_par = B.params(settings, sh_deg, flags)
+        self.out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=device)
+        self.masks = None
+
+    @property
+    def K(self):
+        return len(self.cells)
+
+    def init_masks(self):
+        words = (self.cam.width * self.cam.height + 31) // 32
+        self.masks = torch.empty((self.K, words), dtype=torch.int32, device=self.out.device)
+        B.sx_fill_u32(self.masks, 0xFFFFFFFF)
+        return self.masks
+
+    def forward(self, use_masks=False, update_masks=False, sync=True):
+        """Render every cell (optionally restricted to the active mask bits
+        from the previous render of this view) and compose them; with
+        update_masks the composition clears the bits of saturated pairs."""
+        for k, v in enumerate(self.views):
+            v.preprocess()
+            v.sort(sync=sync)
+            m = self.masks[k] if (use_masks and self.masks is not None) else None
+            v.render(m)
+        B.sx_composite([v.partial for v in self.views], self.boxes, self.c_cam, self.c_par,
+                       self.out, self.masks if update_masks else None)
+        return self.out
+
+    def backward(self, dout, grads: Sequence[GaussianParams], accumulate=False):
+        states = [v.state(g) for v, g in zip(self.views, grads)]
+        B.sx_backward(states, self.boxes, self.c_cam, self.c_par, dout,
+                      B.SX_BWD_ACCUMULATE if accumulate else 0)

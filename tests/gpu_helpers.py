@@ -1,0 +1,80 @@
+"""Shared helpers for the GPU parity tests (kernel path vs FP64 oracle)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+INF = 1e30
+
+
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_18588_amd import binding
+    binding.lib()
+
+
+def big_box():
+    return synth.Cell((-INF, -INF, -INF), (INF, INF, INF))
+
+
+def rec_fields(rec):
+    """Split the [n,12] float record into named numpy arrays."""
+    r = rec.detach().cpu().numpy()
+    return dict(mean2d_c=r[:, 0:2], conic=r[:, 2:5], opacity=r[:, 5], rgb=r[:, 6:9],
+                depth=r[:, 9])
+
+
+def jump_bound(settings, cmax):
+    """Largest change a single pair crossing a threshold within rounding can
+    make to a pixel: alpha_min * max|c - R| plus the termination bound."""
+    return settings.alpha_min * 2.0 * cmax + settings.t_min * cmax + 1e-4
+
+
+def compare_image(got, ref, flags, tol=1e-4, bound=None):
+    """max-abs on unflagged pixels <= tol; flagged pixels within `bound`.
+    Returns (max unflagged error, number flagged)."""
+    err = np.abs(got - ref)
+    if err.ndim == 3:
+        err = err.max(-1)
+    fl = flags != 0
+    e_un = float(err[~fl].max()) if (~fl).any() else 0.0
+    assert e_un <= tol, f"unflagged max-abs {e_un} > {tol}"
+    if bound is not None and fl.any():
+        e_fl = float(err[fl].max())
+        assert e_fl <= bound, f"flagged max-abs {e_fl} > jump bound {bound}"
+    return e_un, int(fl.sum())
+
+
+def grid_cells_xy(xe, ye):
+    return [synth.Cell((float(xe[i]), float(ye[j]), -INF), (float(xe[i + 1]), float(ye[j + 1]), INF))
+            for j in range(len(ye) - 1) for i in range(len(xe) - 1)]
+
+
+def rel_err(got, ref):
+    scale = max(float(np.abs(ref).max()), 1e-30)
+    return float(np.abs(got - ref).max()) / scale
+
+
+def assert_same(got, ref, what):
+    """Bit-exact comparison with a short message."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    assert got.shape == ref.shape, f"{what}: shape {got.shape} != {ref.shape}"
+    bad = np.nonzero(got != ref)
+    if len(bad[0]):
+        i = tuple(b[0] for b in bad)
+        raise AssertionError(f"{what}: {len(bad[0])} mismatches, first at {i}: "
+                             f"{got[i]} != {ref[i]}")
+
+
+def assert_ranges(got, ref):
+    """Tile ranges: non-empty ranges equal; empty ones have start == end."""
+    got = np.asarray(got).astype(np.int64)
+    ref = np.asarray(ref).astype(np.int64)
+    ne = ref[:, 1] > ref[:, 0]
+    assert_same(got[ne], ref[ne], "non-empty tile ranges")
+    assert_same(got[~ne, 0], got[~ne, 1], "empty tile ranges")

@@ -1,0 +1,475 @@
+"""GPU parity of every hot-path step against the FP64 oracle, through the
+C ABI (ctypes binding), at the tiny workload (5k Gaussians, 128x128, 16x16
+tiles: 64 tiles with a ragged tail of sizes per tile) and on edge cases.
+
+Tolerances: integer/byte/index work bit-exact (tile counts, footprints,
+sort keys, values, ranges, masks); pixels max-abs 1e-4 on pixels the oracle
+does not flag as ambiguous (a pair within rounding reach of alpha_min, a
+transmittance within reach of t_min, an ambiguous float32 depth rounding or
+composite order), flagged pixels within the jump bound; gradients within
+1e-3 of the largest entry of their parameter family.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import (assert_ranges, assert_same, big_box, compare_image,
+                         grid_cells_xy, jump_bound, need_gpu, rec_fields,
+                         rel_err)
+
+pytestmark = pytest.mark.gpu
+ST = synth.RenderSettings()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    need_gpu()
+    import torch
+    return torch
+
+
+def _cell_view(torch, scene, cam, st=ST, keep_keys=True):
+    from paper_2606_18588_amd.pipeline import CellView, GaussianParams
+    p = GaussianParams.from_scene(scene)
+    v = CellView(p, cam, st, keep_keys=keep_keys)
+    return p, v
+
+
+def test_library_version(torch_gpu):
+    from paper_2606_18588_amd import binding as B
+    print("case: version", B.sx_version(), flush=True)
+    assert "gfx950" in B.sx_version()
+
+
+# -------------------------------------------------------------------- a1 --
+def test_preprocess_matches_oracle(torch_gpu):
+    print("case: preprocess tiny seed 0", flush=True)
+    torch = torch_gpu
+    scene, cam = synth.tiny_scene(), synth.tiny_camera()
+    _, v = _cell_view(torch, scene, cam)
+    v.preprocess()
+    torch.cuda.synchronize()
+    ref = oracle.preprocess(scene, cam, ST)
+    nt = v.n_tiles.cpu().numpy().astype(np.int64)
+    assert_same(nt, ref["n_tiles"], "tiles touched")
+    vis = ref["valid"] == 1
+    rect = v.rect.cpu().numpy().astype(np.int64)[vis]
+    tr = ref["tile_rect"][vis]
+    assert_same(rect[:, :2], tr[:, :2], "rect lo")
+    assert_same(rect[:, 2:], tr[:, 2:] + 1, "rect hi")
+    f = rec_fields(v.rec)
+    assert_same(f["depth"][vis], ref["depth"][vis].astype(np.float32), "depth")
+    mc = ref["mean2d"][vis] - np.array([cam.cx, cam.cy])
+    assert np.abs(f["mean2d_c"][vis] - mc).max() <= 1e-6 * (1 + np.abs(mc).max())
+    np.testing.assert_allclose(f["conic"][vis], ref["conic"][vis], rtol=2e-6, atol=1e-9)
+    np.testing.assert_allclose(f["opacity"][vis], ref["opacity"][vis], rtol=2e-7)
+    np.testing.assert_allclose(f["rgb"][vis], ref["rgb"][vis], atol=2e-7)
+
+
+def test_preprocess_sh3_colour(torch_gpu):
+    """SH degree 3 evaluation (polynomial basis in the kernel, Legendre
+    construction in the oracle) on a ground scene seen from the aerial
+    camera."""
+    print("case: preprocess sh3 ground 20k", flush=True)
+    torch = torch_gpu
+    scene = synth.make_ground_scene(21, 20000, half_extent=60.0)
+    cam = synth.aerial_camera((0.0, -60.0, 40.0), 0.0, math.radians(30), 320, 180)
+    _, v = _cell_view(torch, scene, cam)
+    v.preprocess()
+    torch.cuda.synchronize()
+    ref = oracle.preprocess(scene, cam, ST)
+    vis = ref["valid"] == 1
+    assert vis.sum() > 1000
+    assert_same(v.n_tiles.cpu().numpy().astype(np.int64), ref["n_tiles"], "tiles touched")
+    f = rec_fields(v.rec)
+    np.testing.assert_allclose(f["rgb"][vis], ref["rgb"][vis], atol=1e-6)
+    np.testing.assert_allclose(f["conic"][vis], ref["conic"][vis], rtol=5e-6, atol=1e-9)
+
+
+# ------------------------------------------------------------------ a2-a4 --
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 8)])
+def test_sort_keys_vals_ranges_bit_exact(torch_gpu, tile):
+    print(f"case: sort tiny tile={tile}", flush=True)
+    torch = torch_gpu
+    st = synth.RenderSettings(tile_w=tile[0], tile_h=tile[1])
+    scene, cam = synth.tiny_scene(), synth.tiny_camera()
+    _, v = _cell_view(torch, scene, cam, st)
+    v.preprocess()
+    counts = v.sort(sync=True)
+    torch.cuda.synchronize()
+    keys, vals, ranges = oracle.sort_keys(scene, cam, st)
+    ref_vis = int(oracle.preprocess(scene, cam, st)["valid"].sum())
+    assert counts == (ref_vis, len(keys))
+    n = len(keys)
+    gk = v.keys[:n].cpu().numpy().view(np.uint64)
+    gv = v.vals[:n].cpu().numpy().view(np.uint32)
+    assert_same(gk, keys, "keys")
+    assert_same(gv, vals, "vals")
+    assert_ranges(v.ranges.cpu().numpy().view(np.uint32), ranges)
+
+
+def test_sort_ragged_and_capacity(torch_gpu):
+    """Non-multiple image size (ragged tile tail), a capacity that is too
+    small (SX_ECAPACITY, then a retry with grown buffers) and a
+    multi-partition radix sort (instances > 4096 per partition)."""
+    print("case: sort ragged 100x70 capacity", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    from paper_2606_18588_amd.pipeline import CellView, GaussianParams
+    scene = synth.make_cube_scene(5, 30000, log_scale=(-3.3, 0.5))
+    cam = synth.tiny_camera(100, 70)
+    p = GaussianParams.from_scene(scene)
+    v = CellView(p, cam, ST, capacity=1000, keep_keys=True)
+    v.preprocess()
+    with pytest.raises(B.SplaxelError) as ei:
+        B.sx_sort(v.c_proj, p.n, v.c_cam, v.c_par, v.capacity, v.keys, v.vals, v.ranges, v.ws,
+                  sync_counts=True)
+    assert ei.value.code == B.SX_ECAPACITY
+    counts = v.sort(sync=True)
+    keys, vals, ranges = oracle.sort_keys(scene, cam, ST)
+    assert counts[1] == len(keys) and len(keys) > 3 * 4096
+    n = len(keys)
+    assert_same(v.keys[:n].cpu().numpy().view(np.uint64), keys, "keys")
+    assert_same(v.vals[:n].cpu().numpy().view(np.uint32), vals, "vals")
+    assert_ranges(v.ranges.cpu().numpy().view(np.uint32), ranges)
+    c4 = B.sx_sort_counts(v.ws, p.n)
+    assert c4[2] == 0 and c4[3] == 0
+
+
+def test_sort_async_overflow_flag(torch_gpu):
+    """Without the synchronous count check an overflow sorts the first
+    `capacity` instances, stays in bounds and raises the overflow flag."""
+    print("case: sort async overflow", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    from paper_2606_18588_amd.pipeline import CellView, GaussianParams
+    scene = synth.tiny_scene()
+    cam = synth.tiny_camera()
+    p = GaussianParams.from_scene(scene)
+    v = CellView(p, cam, ST, capacity=2000)
+    v.preprocess()
+    v.sort(sync=False)
+    c4 = B.sx_sort_counts(v.ws, p.n)
+    assert c4[1] > 2000 and c4[2] == 1 and c4[3] == 0
+    r = v.ranges.cpu().numpy().view(np.uint32)
+    assert r.max() <= 2000
+
+
+# -------------------------------------------------------------------- a5 --
+def _render(torch, scene, cam, st=ST, mask=None):
+    _, v = _cell_view(torch, scene, cam, st, keep_keys=False)
+    v.preprocess()
+    v.sort(sync=True)
+    v.render(mask, want_depth=True)
+    torch.cuda.synchronize()
+    return v
+
+
+def test_render_matches_oracle(torch_gpu):
+    print("case: render tiny", flush=True)
+    torch = torch_gpu
+    scene, cam = synth.tiny_scene(), synth.tiny_camera()
+    v = _render(torch, scene, cam)
+    ref = oracle.render(scene, cam, ST)
+    part = v.partial.cpu().numpy()
+    cmax = float(oracle.preprocess(scene, cam, ST)["rgb"].max())
+    e, nf = compare_image(part[..., :3], ref["C"], ref["flags"], 1e-4, jump_bound(ST, cmax))
+    compare_image(part[..., 3], ref["T"], ref["flags"], 1e-4, 1.0)
+    compare_image(v.depth.cpu().numpy(), ref["D"], ref["flags"], 1e-3 * 4.0, None)
+    fl = ref["flags"] != 0
+    nb = v.nblend.cpu().numpy()
+    assert_same(nb[~fl], ref["nblend"][~fl], "blended pairs per pixel")
+    print(f"render tiny: max-abs {e:.3g}, flagged {nf}", flush=True)
+
+
+@pytest.mark.parametrize("tile", [(32, 8), (8, 32), (32, 16), (16, 32), (8, 8)])
+def test_render_tile_shape_bit_identical(torch_gpu, tile):
+    """Tiling invariance: every supported tile shape gives bit-identical
+    pixels (the per-pixel list and arithmetic do not depend on tiling)."""
+    print(f"case: render tile {tile}", flush=True)
+    torch = torch_gpu
+    scene, cam = synth.tiny_scene(), synth.tiny_camera()
+    a = _render(torch, scene, cam).partial.cpu().numpy()
+    st = synth.RenderSettings(tile_w=tile[0], tile_h=tile[1])
+    b = _render(torch, scene, cam, st).partial.cpu().numpy()
+    assert_same(a, b, "partials across tile shapes")
+
+
+def test_render_constant_colour_invariant(torch_gpu):
+    """C = c0 (1 - T) for constant colour (telescoping of Eq. 2)."""
+    print("case: render constant colour", flush=True)
+    torch = torch_gpu
+    scene = synth.tiny_scene()
+    scene.sh[:] = np.float32((0.6 - 0.5) * 2.0 * math.sqrt(math.pi))
+    v = _render(torch, scene, synth.tiny_camera())
+    part = v.partial.cpu().numpy().astype(np.float64)
+    c0 = float(rec_fields(v.rec)["rgb"][v.n_tiles.cpu().numpy() > 0][0, 0])
+    assert np.abs(part[..., 0] - c0 * (1 - part[..., 3])).max() < 2e-6
+
+
+def test_render_single_gaussian_closed_form(torch_gpu):
+    """A Gaussian on a pixel centre: alpha there equals its opacity."""
+    print("case: render single gaussian", flush=True)
+    torch = torch_gpu
+    sc = synth.Scene(np.zeros((1, 3), np.float32), np.full((1, 3), -3.0, np.float32),
+                     np.array([[1, 0, 0, 0]], np.float32), np.array([0.3], np.float32),
+                     (np.array([[[0.2, 0.4, 0.6]]]) - 0.5).astype(np.float32) * np.float32(2 * math.sqrt(math.pi)))
+    cam = synth.camera_from_rows(np.eye(3), (0, 0, -3), 64, 64, 50.0, cx=32.5, cy=32.5)
+    v = _render(torch, sc, cam)
+    part = v.partial.cpu().numpy()
+    o = 1 / (1 + math.exp(-float(np.float32(0.3))))
+    col = sc.sh[0, 0].astype(np.float64) / (2 * math.sqrt(math.pi)) + 0.5
+    assert np.abs(part[32, 32, :3] - col * o).max() < 1e-6
+    assert abs(part[32, 32, 3] - (1 - o)) < 1e-6
+
+
+def test_render_empty_and_all_culled(torch_gpu):
+    """n = 0 and a camera facing away: identity partials (C=0, T=1)."""
+    print("case: render empty", flush=True)
+    torch = torch_gpu
+    cam = synth.tiny_camera(48, 40)
+    empty = synth.tiny_scene(n=1).subset(np.zeros(0, np.int64))
+    v = _render(torch, empty, cam)
+    p = v.partial.cpu().numpy()
+    assert np.all(p[..., :3] == 0) and np.all(p[..., 3] == 1)
+    away = synth.tiny_scene()
+    away.means[:, 2] = -10.0
+    v = _render(torch, away, cam)
+    p = v.partial.cpu().numpy()
+    assert np.all(p[..., :3] == 0) and np.all(p[..., 3] == 1)
+    assert int(v.counts[0]) == 0
+
+
+def test_render_mask(torch_gpu):
+    """Masked pixels output the identity; unmasked pixels are unchanged."""
+    print("case: render mask", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    scene, cam = synth.tiny_scene(), synth.tiny_camera()
+    full = _render(torch, scene, cam).partial.cpu().numpy()
+    rng = np.random.default_rng(0)
+    bits = rng.integers(0, 2, size=cam.width * cam.height).astype(np.uint8)
+    words = np.packbits(bits, bitorder="little").view(np.uint32).astype(np.int64)
+    mask = torch.as_tensor(words.astype(np.uint32).view(np.int32)).cuda()
+    m = _render(torch, scene, cam, mask=mask).partial.cpu().numpy()
+    on = bits.reshape(cam.height, cam.width) == 1
+    assert_same(m[on], full[on], "unmasked pixels")
+    assert np.all(m[~on][:, :3] == 0) and np.all(m[~on][:, 3] == 1)
+
+
+# -------------------------------------------------------------------- a6 --
+def _frame(torch, scenes, boxes, cam, st=ST, flags=0):
+    from paper_2606_18588_amd.pipeline import Frame, GaussianParams
+    params = [GaussianParams.from_scene(s) for s in scenes]
+    return Frame(params, boxes, cam, st, flags=flags), params
+
+
+def test_composite_k8_grid_matches_oracle(torch_gpu):
+    """Eq. 5 over a 4x2 grid of prisms (cells ordered per pixel by ray entry)
+    against the oracle's composition of its own partials."""
+    print("case: composite k8 grid tiny", flush=True)
+    torch = torch_gpu
+    scene = synth.make_cube_scene(3, 8000, log_scale=(-3.6, 0.5))
+    cam = synth.camera_from_rows(
+        np.array([[1, 0, 0], [0, 0.9950, -0.0998], [0, 0.0998, 0.9950]]), (0.13, 0.21, -3.0),
+        96, 80, 70.0)
+    xe, ye = [-1.0, -0.5, 0.0, 0.5, 1.0], [-1.0, 0.0, 1.0]
+    part = synth.grid_partition(scene, xe, ye)
+    boxes = grid_cells_xy(xe, ye)
+    part.cells = boxes
+    scenes = part.cell_scenes(scene)
+    fr, _ = _frame(torch, scenes, boxes, cam)
+    fr.init_masks()
+    out = fr.forward(update_masks=True).cpu().numpy()
+    torch.cuda.synchronize()
+    ref = oracle.forward(scenes, boxes, cam, ST)
+    fl = ref.comp["flags"].copy()
+    for p in ref.parts:
+        fl |= p["flags"]
+    cmax = max(float(oracle.preprocess(s, cam, ST)["rgb"].max()) for s in scenes)
+    e, nf = compare_image(out[..., :3], ref.comp["rgb"], fl, 1e-4, 8 * jump_bound(ST, cmax))
+    compare_image(out[..., 3], ref.comp["T"], fl, 1e-4, 1.0)
+    masks = fr.masks.cpu().numpy().view(np.uint32)
+    bits = np.unpackbits(masks.view(np.uint8), bitorder="little").reshape(8, -1)[:, :cam.width * cam.height]
+    refm = ref.comp["mask"].reshape(8, -1)
+    okpix = (fl.reshape(-1) == 0)
+    assert_same(bits[:, okpix], refm[:, okpix], "saturation masks")
+    print(f"composite k8: max-abs {e:.3g} flagged {nf} inactive pairs {(refm == 0).sum()}", flush=True)
+
+
+def test_slab_composite_equals_single_pass(torch_gpu):
+    """The paper's Eq. 5 = Eq. 2 claim on the GPU: with t_min = 0, the
+    composition of depth-separated slab partials equals the single-pass
+    render up to FP32 reassociation."""
+    print("case: slab composite", flush=True)
+    torch = torch_gpu
+    st0 = synth.RenderSettings(t_min=0.0)
+    scene, cam = synth.tiny_scene(), synth.tiny_camera()
+    edges = synth.quantile_edges(scene.means[:, 2], 8)
+    part = synth.axis_slab_partition(scene, 2, edges)
+    fr, _ = _frame(torch, part.cell_scenes(scene), part.cells, cam, st0)
+    out = fr.forward().cpu().numpy()
+    single = _render(torch, scene, cam, st0).partial.cpu().numpy()
+    assert np.abs(out[..., :3] - single[..., :3]).max() <= 1e-5
+    assert np.abs(out[..., 3] - single[..., 3]).max() <= 1e-5
+
+
+def test_saturation_culling_next_render(torch_gpu):
+    """Temporal saturation masks: the next render with the masks skips the
+    saturated (cell, pixel) pairs; the image changes by at most t_min * max c
+    and matches the same-frame-culled composition."""
+    print("case: saturation masks", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    scene = synth.make_cube_scene(11, 6000, log_scale=(-3.2, 0.4), logit_sigma=2.0)
+    cam = synth.tiny_camera(64, 64)
+    edges = synth.quantile_edges(scene.means[:, 2], 4)
+    part = synth.axis_slab_partition(scene, 2, edges)
+    scenes = part.cell_scenes(scene)
+    fr, _ = _frame(torch, scenes, part.cells, cam)
+    fr.init_masks()
+    first = fr.forward(update_masks=True).cpu().numpy()
+    second = fr.forward(use_masks=True).cpu().numpy()
+    frc, _ = _frame(torch, scenes, part.cells, cam, flags=B.SX_FLAG_SAME_FRAME_CULL)
+    culled = frc.forward().cpu().numpy()
+    ref = oracle.forward(scenes, part.cells, cam, ST)
+    assert (ref.comp["mask"] == 0).sum() > 0
+    assert np.abs(second - culled).max() <= 1e-6
+    assert np.abs(second[..., :3] - first[..., :3]).max() <= ST.t_min * 2.0 + 1e-6
+
+
+# -------------------------------------------------------------- a7 - a9 --
+def _fd_scene(seed0, cam, cells_fn):
+    for seed in range(seed0, seed0 + 40):
+        sc = synth.fd_scene(seed)
+        part = cells_fn(sc)
+        fr = oracle.forward(part.cell_scenes(sc), part.cells, cam, ST, delta_q=1e-3)
+        fl = np.bitwise_or.reduce([p["flags"] for p in fr.parts])
+        if not np.any(fl) and not np.any(fr.comp["flags"]):
+            return sc, part
+    raise AssertionError("no flag-free scene")
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_backward_matches_oracle_and_fd(torch_gpu, K):
+    """Kernel gradients (FP32, through sx_backward) against the oracle's
+    analytic FP64 gradients, and the oracle against central differences, on
+    flag-free 64-Gaussian scenes split into K depth slabs."""
+    print(f"case: backward fd scene K={K}", flush=True)
+    torch = torch_gpu
+    cam = synth.fd_camera()
+
+    def cells(s):
+        return synth.axis_slab_partition(s, 2, np.linspace(-0.7, 0.7, K + 1))
+    sc, part = _fd_scene(300 + 50 * K, cam, cells)
+    scenes = part.cell_scenes(sc)
+    fr, params = _frame(torch, scenes, part.cells, cam)
+    out = fr.forward()
+    rng = np.random.default_rng(K)
+    w = rng.normal(size=(cam.height, cam.width, 4)).astype(np.float32)
+    dout = torch.as_tensor(w).cuda()
+    grads = [p.zeros_like() for p in params]
+    fr.backward(dout, grads)
+    torch.cuda.synchronize()
+    ref = oracle.forward(scenes, part.cells, cam, ST)
+    np.testing.assert_allclose(out.cpu().numpy()[..., :3], ref.comp["rgb"], atol=1e-5)
+    gref = oracle.backward(scenes, part.cells, cam, ST, ref, w[..., :3].astype(np.float64),
+                           w[..., 3].astype(np.float64))
+    for k in range(K):
+        for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            got = getattr(grads[k], name).cpu().numpy().astype(np.float64)
+            e = rel_err(got, gref[k][name])
+            assert e <= 1e-3, (k, name, e)
+
+
+def test_backward_screen_space_matches_oracle(torch_gpu):
+    """Per-Gaussian screen-space gradients (mean2d, conic, opacity, colour)
+    of the render backward against the oracle on the tiny workload, excluding
+    Gaussians that touch a flagged pixel."""
+    print("case: backward screen-space tiny", flush=True)
+    torch = torch_gpu
+    scene, cam = synth.tiny_scene(), synth.tiny_camera()
+    fr, params = _frame(torch, [scene], [big_box()], cam)
+    out = fr.forward()
+    target = torch.as_tensor(synth.random_image(101, cam.width, cam.height)).cuda()
+    from paper_2606_18588_amd import binding as B
+    dout = torch.empty_like(out)
+    B.sx_l1_loss(out, target, cam.width, cam.height, dout, None)
+    grads = [params[0].zeros_like()]
+    fr.backward(dout, grads)
+    torch.cuda.synchronize()
+    d = dout.cpu().numpy()
+    ref = oracle.forward([scene], [big_box()], cam, ST)
+    rb = oracle.render_backward(scene, cam, ST, d[..., :3].astype(np.float64), None, None)
+    g2d = fr.views[0].g2d.cpu().numpy()[:, :10]
+    pr = oracle.preprocess(scene, cam, ST)
+    fl = ref.parts[0]["flags"] != 0
+    bad = np.zeros(scene.n, bool)
+    ys, xs = np.nonzero(fl)
+    for y, x in zip(ys, xs):
+        pr_r = pr["pix_rect"]
+        bad |= (pr_r[:, 0] <= x) & (x <= pr_r[:, 2]) & (pr_r[:, 1] <= y) & (y <= pr_r[:, 3])
+    ok = (pr["valid"] == 1) & ~bad
+    for c in range(9):
+        e = rel_err(g2d[ok, c], rb["g2d"][ok, c])
+        assert e <= 2e-3, (c, e)
+    for name in ("means", "opacity_logits", "sh"):
+        got = getattr(grads[0], name).cpu().numpy()[ok]
+        assert rel_err(got, rb[name][ok]) <= 2e-3, name
+
+
+# ------------------------------------------------------------------- a10 --
+def test_adam_matches_oracle(torch_gpu):
+    print("case: adam", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    rng = np.random.default_rng(0)
+    for n in (1, 3, 1027, 100003):
+        p = rng.normal(size=n).astype(np.float32)
+        m = np.zeros(n)
+        v = np.zeros(n)
+        pt = torch.as_tensor(p.copy()).cuda()
+        mt = torch.zeros(n, device="cuda")
+        vt = torch.zeros(n, device="cuda")
+        pr = p.astype(np.float64)
+        for step in range(1, 4):
+            g = rng.normal(size=n).astype(np.float32)
+            B.sx_adam(pt, torch.as_tensor(g).cuda(), mt, vt, step, 1e-2)
+            oracle.adam_step(pr, g.astype(np.float64), m, v, step, 1e-2)
+        np.testing.assert_allclose(pt.cpu().numpy(), pr, atol=1e-5)
+
+
+def test_l1_matches_oracle(torch_gpu):
+    print("case: l1", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    rng = np.random.default_rng(1)
+    H, W = 37, 53
+    out = rng.uniform(size=(H, W, 4)).astype(np.float32)
+    tgt = rng.uniform(size=(H, W, 3)).astype(np.float32)
+    ot = torch.as_tensor(out).cuda()
+    dt = torch.empty_like(ot)
+    ls = torch.zeros(1, device="cuda")
+    B.sx_l1_loss(ot, torch.as_tensor(tgt).cuda(), W, H, dt, ls)
+    L, g = oracle.l1_loss(out[..., :3], tgt)
+    assert abs(float(ls.item()) - L) < 1e-5
+    np.testing.assert_allclose(dt.cpu().numpy()[..., :3], g, rtol=1e-6)
+    assert np.all(dt.cpu().numpy()[..., 3] == 0)
+
+
+def test_invalid_arguments_rejected(torch_gpu):
+    print("case: invalid args", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    scene, cam = synth.tiny_scene(n=10), synth.tiny_camera()
+    _, v = _cell_view(torch, scene, cam)
+    bad = B.params(synth.RenderSettings(tile_w=12), 0)
+    with pytest.raises(B.SplaxelError) as ei:
+        B.sx_preprocess(v.c_g, v.c_cam, bad, v.c_proj)
+    assert ei.value.code == B.SX_EINVAL
+    bad = B.params(ST, 4)
+    with pytest.raises(B.SplaxelError):
+        B.sx_preprocess(v.c_g, v.c_cam, bad, v.c_proj)
