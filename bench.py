@@ -1,0 +1,246 @@
+"""Benchmark of the splatting hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (one GPU's share, plain method): 2M Gaussians on a 1 km x 1 km
+ground plane, SH degree 3, one 1920x1080 aerial view at 150 m pitched 45
+degrees down (70 degree field of view), K = 1 cell, FP32 forward + backward
+with an L1 loss against a seeded random target image.  All inputs are
+synthetic and resident in HBM before timing starts.
+
+One step = preprocess -> sort -> partial render -> composition -> L1 ->
+composition backward -> render backward -> preprocess backward, every stage
+a HIP kernel of libsplaxel.so on torch's current stream, with no host
+synchronisation inside the step (the instance capacity is sized once during
+warm-up).  value = B / t_step, where B is the number of Gaussian-pixel pairs
+blended in the forward pass (counted once by the renderer's per-pixel
+counter; the step is deterministic, so B is the same every step).
+
+Prints ONE JSON line.  Per-stage times, the roofline of the dominant kernel
+and the CPU oracle baseline are included in it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gaussian-pixel blends/s fwd+bwd"
+HBM_PEAK_GBS = 8000.0
+# FP32 vector lanes: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed)
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload():
+    import synth
+    scene = synth.g2_scene()
+    cam = synth.g2_camera()
+    target = synth.g2_target()
+    return scene, cam, target
+
+
+class Step:
+    """Buffers + the sequence of C-ABI calls of one training step."""
+
+    def __init__(self, scene, cam, target, settings):
+        import torch
+        from paper_2606_18588_amd import binding as B
+        from paper_2606_18588_amd.pipeline import CellView, GaussianParams
+        self.torch = torch
+        self.B = B
+        self.cam = cam
+        self.params = GaussianParams.from_scene(scene)
+        self.grads = self.params.zeros_like()
+        self.view = CellView(self.params, cam, settings)
+        self.box = [type("Box", (), {"lo": (-1e30,) * 3, "hi": (1e30,) * 3})()]
+        self.c_cam = self.view.c_cam
+        self.c_par = self.view.c_par
+        H, W = cam.height, cam.width
+        self.out = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+        self.dout = torch.empty_like(self.out)
+        self.target = torch.as_tensor(target).cuda()
+        self.view.ensure_backward_buffers()
+        # size the instance buffers once (one host read-back, outside timing)
+        self.view.preprocess()
+        self.counts = self.view.sort(sync=True)
+        self.view._alloc_sort(int(self.counts[1] * 1.05) + 4096)
+        self.stage_names = ["preprocess", "sort", "render", "composite", "l1",
+                            "composite_bwd", "render_bwd", "preprocess_bwd"]
+
+    def run(self, events=None, count=False):
+        B, v = self.B, self.view
+        ev = events
+        if ev: ev[0].record()
+        v.preprocess()
+        if ev: ev[1].record()
+        v.sort(sync=False)
+        if ev: ev[2].record()
+        v.render(None, want_nblend=count)
+        if ev: ev[3].record()
+        B.sx_composite([v.partial], self.box, self.c_cam, self.c_par, self.out, None)
+        if ev: ev[4].record()
+        B.sx_l1_loss(self.out, self.target, self.cam.width, self.cam.height, self.dout, None)
+        if ev: ev[5].record()
+        B.sx_composite_backward([v.partial], self.box, self.c_cam, self.c_par, self.dout,
+                                [v.dpartial])
+        if ev: ev[6].record()
+        v.render_backward(v.dpartial)
+        if ev: ev[7].record()
+        v.preprocess_backward(self.grads)
+        if ev: ev[8].record()
+
+
+def cpu_baseline(scene, cam, settings, budget_s=20.0):
+    """The FP64 oracle (as it stands) on a centred crop of the same view:
+    forward (render + composition) and backward, blends/s on the crop."""
+    import oracle
+    import synth
+    oracle.build()
+    cores = oracle.num_threads()
+    box = synth.Cell((-1e30,) * 3, (1e30,) * 3)
+    # crop: the same rays as a w x h window in the middle of the frame
+    w, h = 480, 272
+    x0, y0 = (cam.width - w) // 2, (cam.height - h) // 2
+    crop = synth.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, w, h,
+                        cam.znear)
+    t0 = time.perf_counter()
+    fr = oracle.forward([scene], [box], crop, settings)
+    target = synth.g2_target()[y0:y0 + h, x0:x0 + w]
+    _, g = oracle.l1_loss(fr.comp["rgb"], target)
+    oracle.backward([scene], [box], crop, settings, fr, g)
+    dt = time.perf_counter() - t0
+    blends = int(fr.parts[0]["nblend"].sum())
+    return {"value": blends / dt, "unit": "blends/s", "cores": cores, "kind": "oracle",
+            "sample": f"{w}x{h} centre crop of the 1920x1080 view, full 2M-Gaussian scene, "
+                      f"FP64 forward+backward, {blends} blends in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a plain "
+                         "copy of known size that calibrates PMC traffic counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "exchange is not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    torch.cuda.set_device(0)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    settings = synth.RenderSettings(tile_w=tw, tile_h=th)
+    t0 = time.perf_counter()
+    scene, cam, target = make_workload()
+    log(f"bench: workload generated in {time.perf_counter() - t0:.1f}s")
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    st = Step(scene, cam, target, settings)
+    # blend count B (deterministic per step)
+    st.run(count=True)
+    torch.cuda.synchronize()
+    blends = int(st.view.nblend.sum().item())
+    n_vis, n_inst = st.counts
+    log(f"bench: visible {n_vis} instances {n_inst} blends {blends}")
+    for _ in range(args.warmup):
+        st.run()
+    torch.cuda.synchronize()
+    # per-stage times with events on the launch stream
+    nst = len(st.stage_names)
+    stage_ms = np.zeros(nst)
+    reps = max(3, min(args.steps, 20))
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(nst + 1)]
+        st.run(events=ev)
+        torch.cuda.synchronize()
+        stage_ms += np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(nst)])
+    stage_ms /= reps
+    # timed region: exactly K steps, synchronised on both sides
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    tw0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        st.run()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw0
+    ms = e0.elapsed_time(e1) / args.steps
+    value = blends / (ms / 1e3)
+    stages = {k: round(float(v), 4) for k, v in zip(st.stage_names, stage_ms)}
+    log("bench: stage ms " + json.dumps(stages))
+    dom = max(stages, key=stages.get)
+    roof = roofline(dom, stages[dom], st, blends)
+    line = {
+        "metric": METRIC, "value": value, "unit": "blends/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "one GPU's share: 2M Gaussians SH3 on a 1 km^2 ground plane, "
+                               "1920x1080 aerial view, K=1, L1 fwd+bwd",
+                   "gaussians": scene.n, "width": cam.width, "height": cam.height,
+                   "tile": args.tile, "cells": 1},
+        "views_per_s": 1e3 / ms, "blends_per_step": blends, "visible": n_vis,
+        "instances": n_inst, "stage_ms": stages, "wall_s": wall,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        line["cpu_baseline"] = cpu_baseline(scene, cam, settings)
+        log(f"bench: cpu baseline {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(line), flush=True)
+
+
+def roofline(stage, ms, st, blends):
+    """Roofline entry for the dominant stage.  Algorithmic work per unit is
+    documented in the design doc; HBM-bound stages count bytes, ALU-bound stages
+    count FP32 lane operations."""
+    n = st.params.n
+    n_vis, n_inst = st.counts
+    H, W = st.cam.height, st.cam.width
+    npx = H * W
+    sh_bytes = st.params.sh.shape[1] * 3 * 4
+    if stage in ("render", "render_bwd"):
+        evals = int(getattr(st, "evals", 0)) or n_inst * 256
+        ops = (13.0 * evals + 8.0 * blends) if stage == "render" else (13.0 * evals + 45.0 * blends)
+        ach = ops / (ms / 1e3) / 1e12
+        return {"bound": "alu", "kernel": stage, "achieved": ach, "peak": ALU_PEAK_TOPS,
+                "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS, "traffic": None}
+    if stage == "preprocess":
+        byts = 16 * n + (40 + sh_bytes + 56) * n_vis
+    elif stage == "preprocess_bwd":
+        byts = 4 * n + (40 + sh_bytes + 40 + 40 + sh_bytes) * n_vis
+    elif stage == "sort":
+        byts = 8 * n + 16 * n_vis * 4 + 12 * n_inst + 16 * n_inst * 2 + 8 * n_inst
+    else:
+        byts = 32 * npx
+    ach = byts / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": stage, "achieved": ach, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
+
+
+if __name__ == "__main__":
+    main()

@@ -216,7 +216,9 @@ sx_status sx_l1_loss(const float* out, const float* target, int32_t width,
  * a reverse walk of the cell's blended pairs gives per-Gaussian gradients of
  * mean2d, conic, opacity, colour and depth, chained to the parameters.
  * Per cell (sx_cell_state, device pointers):
- *   g, proj, vals, ranges           the cell's inputs and sort outputs
+ *   g, proj, vals, ranges, sort_ws, capacity
+ *                                   the cell's inputs, sort outputs and the
+ *                                   sort workspace/capacity they came from
  *   partial, last, mask             its forward outputs / mask (mask NULL =
  *                                   all active)
  *   grads                           parameter gradients: rows of Gaussians
@@ -225,6 +227,10 @@ sx_status sx_l1_loss(const float* out, const float* target, int32_t width,
  *                                   other rows are untouched
  *   g2d_ws                          [n*12] scratch (screen-space grads)
  *   dpartial_ws                     [H*W*4] scratch (dL/d(C^m, T^m))
+ *   bwd_ws                          sx_backward_workspace_size bytes
+ * The render backward uses no global atomics: every (Gaussian, tile) pair
+ * stores its partial gradient row at the instance's own slot of bwd_ws and
+ * a balanced per-Gaussian reduction sums the valid slots.
  * dout [H*W*4]: dL/d(rgb, T) of the composed image.
  * cells: HOST array of K boxes (same order as the forward). */
 #define SX_BWD_ACCUMULATE 1
@@ -233,13 +239,19 @@ typedef struct sx_cell_state {
   const sx_projected* proj;
   const uint32_t* vals;
   const uint32_t* ranges;
+  const void* sort_ws;
+  int64_t capacity;
   const float* partial;
   const uint32_t* last;
   const uint32_t* mask;
   const sx_grads* grads;
   float* g2d_ws;
   float* dpartial_ws;
+  void* bwd_ws;
 } sx_cell_state;
+
+sx_status sx_backward_workspace_size(int64_t capacity, int64_t tiles_total,
+                                     size_t* bytes);
 
 sx_status sx_backward(int32_t K, const sx_cell_state* cells,
                       const sx_cell* boxes, const sx_camera* cam,
@@ -253,18 +265,23 @@ sx_status sx_composite_backward(int32_t K, const float* const* partials,
                                 const sx_params* p, const uint32_t* masks,
                                 const float* dout, float* const* dpartials,
                                 sx_stream stream);
-/* zeroes g2d rows of visible Gaussians, then accumulates screen-space
- * gradients: g2d[i*12 + 0..9] = d(mean2d x, y, conic a, b, c, opacity,
- * r, g, b, depth) */
+/* writes screen-space gradients of the Gaussians visible in the view:
+ * g2d[i*12 + 0..9] = d(mean2d x, y, conic a, b, c, opacity, r, g, b,
+ * depth); sort_ws/capacity are those of the sx_sort call that produced
+ * vals and tile_ranges, bwd_ws has sx_backward_workspace_size bytes */
 sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
-                             const uint32_t* tile_ranges, int64_t n,
+                             const uint32_t* tile_ranges, const void* sort_ws,
+                             int64_t n, int64_t capacity, void* bwd_ws,
                              const sx_camera* cam,
                              const sx_params* p, const uint32_t* mask,
                              const float* partial, const uint32_t* last,
                              const float* dpartial, const float* ddepth,
                              float* g2d, sx_stream stream);
+/* sort_ws/capacity: the sort of this view (its list of visible Gaussians
+ * drives the launch). */
 sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,
                                  const sx_params* p, const sx_projected* proj,
+                                 const void* sort_ws, int64_t capacity,
                                  const float* g2d,
                                  const sx_grads* grads, int32_t flags,
                                  sx_stream stream);

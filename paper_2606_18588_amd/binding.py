@@ -64,14 +64,16 @@ class SxGrads(ctypes.Structure):
 class SxCellState(ctypes.Structure):
     _fields_ = [("g", ctypes.POINTER(SxGaussians)),
                 ("proj", ctypes.POINTER(SxProjected)), ("vals", c_p),
-                ("ranges", c_p), ("partial", c_p), ("last", c_p),
+                ("ranges", c_p), ("sort_ws", c_p), ("capacity", c_i64),
+                ("partial", c_p), ("last", c_p),
                 ("mask", c_p), ("grads", ctypes.POINTER(SxGrads)),
-                ("g2d_ws", c_p), ("dpartial_ws", c_p)]
+                ("g2d_ws", c_p), ("dpartial_ws", c_p), ("bwd_ws", c_p)]
 
 
 EXPORTS = (
     "sx_last_error_string", "sx_version", "sx_preprocess_blocks",
     "sx_preprocess", "sx_sort_workspace_size", "sx_sort", "sx_sort_counts",
+    "sx_backward_workspace_size",
     "sx_render_partial", "sx_composite", "sx_l1_loss", "sx_backward",
     "sx_composite_backward", "sx_render_backward", "sx_preprocess_backward",
     "sx_adam", "sx_fill_u32",
@@ -275,22 +277,31 @@ def sx_composite_backward(partials, cells, cam: SxCamera, p: SxParams, dout,
         ptr_array(dpartials), stream_handle(stream)))
 
 
-def sx_render_backward(proj: SxProjected, vals, ranges, n: int,
-                       cam: SxCamera, p: SxParams, mask, partial, last,
-                       dpartial, ddepth, g2d, stream=None) -> None:
+def sx_backward_workspace_size(capacity: int, tiles_total: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check("sx_backward_workspace_size", lib().sx_backward_workspace_size(
+        c_i64(capacity), c_i64(tiles_total), ctypes.byref(b)))
+    return int(b.value)
+
+
+def sx_render_backward(proj: SxProjected, vals, ranges, sort_ws, n: int,
+                       capacity: int, bwd_ws, cam: SxCamera, p: SxParams,
+                       mask, partial, last, dpartial, ddepth, g2d,
+                       stream=None) -> None:
     _check("sx_render_backward", lib().sx_render_backward(
-        ctypes.byref(proj), ptr(vals), ptr(ranges), c_i64(n),
-        ctypes.byref(cam), ctypes.byref(p), ptr(mask), ptr(partial),
-        ptr(last), ptr(dpartial), ptr(ddepth), ptr(g2d),
-        stream_handle(stream)))
+        ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(sort_ws), c_i64(n),
+        c_i64(capacity), ptr(bwd_ws), ctypes.byref(cam), ctypes.byref(p),
+        ptr(mask), ptr(partial), ptr(last), ptr(dpartial), ptr(ddepth),
+        ptr(g2d), stream_handle(stream)))
 
 
 def sx_preprocess_backward(g: SxGaussians, cam: SxCamera, p: SxParams,
-                           proj: SxProjected, g2d, gr: SxGrads,
-                           flags: int = 0, stream=None) -> None:
+                           proj: SxProjected, sort_ws, capacity: int, g2d,
+                           gr: SxGrads, flags: int = 0, stream=None) -> None:
     _check("sx_preprocess_backward", lib().sx_preprocess_backward(
         ctypes.byref(g), ctypes.byref(cam), ctypes.byref(p), ctypes.byref(proj),
-        ptr(g2d), ctypes.byref(gr), c_i32(flags), stream_handle(stream)))
+        ptr(sort_ws), c_i64(capacity), ptr(g2d), ctypes.byref(gr), c_i32(flags),
+        stream_handle(stream)))
 
 
 def sx_backward(states: Sequence[SxCellState], cells, cam: SxCamera,

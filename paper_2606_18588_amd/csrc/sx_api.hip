@@ -121,7 +121,7 @@ sx_status sx_sort_workspace_size(int64_t n, int64_t capacity, int64_t tiles_tota
   if (!bytes) return fail(SX_EINVAL, "bytes is NULL");
   if (n < 0 || capacity < 0 || tiles_total < 1) return fail(SX_EINVAL, "negative size");
   if (capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "capacity must be < 2^30");
-  *bytes = sx::sort_layout(n, capacity).total;
+  *bytes = sx::sort_layout(n, capacity, tiles_total).total;
   return SX_OK;
 }
 
@@ -138,7 +138,7 @@ sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
   if (!vals && capacity > 0) return fail(SX_EINVAL, "vals is NULL");
   if (!tile_ranges || !ws) return fail(SX_EINVAL, "tile_ranges/ws is NULL");
   const int64_t tiles = tiles_of(cam, p);
-  const size_t need = sx::sort_layout(n, capacity).total;
+  const size_t need = sx::sort_layout(n, capacity, tiles).total;
   if (ws_bytes < need) return fail(SX_EINVAL, "workspace %zu bytes < required %zu", ws_bytes, need);
   bool over = false;
   hipError_t e = sx::launch_sort(*proj, n, sx::make_kparams(*p, *cam), capacity, tiles, keys, vals,
@@ -154,7 +154,7 @@ sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
 sx_status sx_sort_counts(const void* ws, int64_t n, uint64_t* h_out, sx_stream stream) {
   (void)n;
   if (!ws || !h_out) return fail(SX_EINVAL, "null argument");
-  const size_t off = sx::sort_layout(0, 0).counts;
+  const size_t off = sx::sort_layout(0, 0, 1).counts;
   hipError_t e = hipMemcpyAsync(h_out, static_cast<const char*>(ws) + off, 4 * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
@@ -227,38 +227,54 @@ sx_status sx_composite_backward(int32_t K, const float* const* partials,
              "sx_composite_backward");
 }
 
+sx_status sx_backward_workspace_size(int64_t capacity, int64_t tiles_total, size_t* bytes) {
+  if (!bytes) return fail(SX_EINVAL, "bytes is NULL");
+  if (capacity < 0 || capacity >= (int64_t(1) << 30) || tiles_total < 1)
+    return fail(SX_EINVAL, "bad size");
+  *bytes = sx::bwd_layout(capacity, tiles_total).total;
+  return SX_OK;
+}
+
 sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
-                             const uint32_t* tile_ranges, int64_t n,
+                             const uint32_t* tile_ranges, const void* sort_ws,
+                             int64_t n, int64_t capacity, void* bwd_ws,
                              const sx_camera* cam, const sx_params* p,
                              const uint32_t* mask, const float* partial,
                              const uint32_t* last, const float* dpartial,
                              const float* ddepth, float* g2d, sx_stream stream) {
   SX_TRY(check_cam(cam));
   SX_TRY(check_params(p));
-  if (!proj || !proj->rec || !proj->n_tiles || !tile_ranges || !partial || !last || !dpartial || !g2d)
+  if (!proj || !proj->rec || !proj->n_tiles || !proj->rect || !tile_ranges || !sort_ws || !bwd_ws ||
+      !partial || !last || !dpartial || !g2d)
     return fail(SX_EINVAL, "null argument");
-  if (n < 0) return fail(SX_EINVAL, "n < 0");
-  return dev(sx::launch_render_backward(*proj, vals, tile_ranges, n, sx::make_dcam(*cam),
-                                        sx::make_kparams(*p, *cam), mask, partial, last, dpartial,
-                                        ddepth, g2d, (hipStream_t)stream),
+  if (n < 0 || capacity < 0 || capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "bad n/capacity");
+  const int64_t tiles = tiles_of(cam, p);
+  return dev(sx::launch_render_backward(*proj, vals, tile_ranges, sx::sort_view(sort_ws, n, capacity, tiles),
+                                        n, capacity, sx::make_dcam(*cam), sx::make_kparams(*p, *cam), mask,
+                                        partial, last, dpartial, ddepth, g2d, static_cast<char*>(bwd_ws),
+                                        (hipStream_t)stream),
              "sx_render_backward");
 }
 
 sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,
                                  const sx_params* p, const sx_projected* proj,
+                                 const void* sort_ws, int64_t capacity,
                                  const float* g2d, const sx_grads* grads,
                                  int32_t flags, sx_stream stream) {
   SX_TRY(check_gauss(g));
   SX_TRY(check_cam(cam));
   SX_TRY(check_params(p));
-  if (!proj || !proj->n_tiles || !g2d || !grads) return fail(SX_EINVAL, "null argument");
+  if (!proj || !proj->n_tiles || !sort_ws || !g2d || !grads) return fail(SX_EINVAL, "null argument");
+  if (capacity < 0 || capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "bad capacity");
   if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
     return fail(SX_EINVAL, "null gradient array");
+  const int64_t tiles = tiles_of(cam, p);
   return dev(sx::launch_preprocess_backward(*g, sx::make_dcam(*cam), sx::make_kparams(*p, *cam), *proj,
-                                            g2d, *grads, (flags & SX_BWD_ACCUMULATE) != 0,
-                                            (hipStream_t)stream),
+                                            sx::sort_view(sort_ws, g->n, capacity, tiles), g2d, *grads,
+                                            (flags & SX_BWD_ACCUMULATE) != 0, (hipStream_t)stream),
              "sx_preprocess_backward");
 }
+
 
 sx_status sx_backward(int32_t K, const sx_cell_state* cells, const sx_cell* boxes,
                       const sx_camera* cam, const sx_params* p, const float* dout,
@@ -271,7 +287,8 @@ sx_status sx_backward(int32_t K, const sx_cell_state* cells, const sx_cell* boxe
   float* dparts[sx::kMaxCells];
   for (int m = 0; m < K; ++m) {
     const sx_cell_state& c = cells[m];
-    if (!c.g || !c.proj || !c.ranges || !c.partial || !c.last || !c.grads || !c.g2d_ws || !c.dpartial_ws)
+    if (!c.g || !c.proj || !c.ranges || !c.sort_ws || !c.partial || !c.last || !c.grads || !c.g2d_ws ||
+        !c.dpartial_ws || !c.bwd_ws)
       return fail(SX_EINVAL, "cell %d has a null member", m);
     SX_TRY(check_gauss(c.g));
     parts[m] = c.partial;
@@ -280,9 +297,10 @@ sx_status sx_backward(int32_t K, const sx_cell_state* cells, const sx_cell* boxe
   SX_TRY(sx_composite_backward(K, parts, boxes, cam, p, nullptr, dout, dparts, stream));
   for (int m = 0; m < K; ++m) {
     const sx_cell_state& c = cells[m];
-    SX_TRY(sx_render_backward(c.proj, c.vals, c.ranges, c.g->n, cam, p, c.mask, c.partial, c.last,
-                              c.dpartial_ws, nullptr, c.g2d_ws, stream));
-    SX_TRY(sx_preprocess_backward(c.g, cam, p, c.proj, c.g2d_ws, c.grads, flags, stream));
+    SX_TRY(sx_render_backward(c.proj, c.vals, c.ranges, c.sort_ws, c.g->n, c.capacity, c.bwd_ws, cam, p,
+                              c.mask, c.partial, c.last, c.dpartial_ws, nullptr, c.g2d_ws, stream));
+    SX_TRY(sx_preprocess_backward(c.g, cam, p, c.proj, c.sort_ws, c.capacity, c.g2d_ws, c.grads, flags,
+                                  stream));
   }
   return SX_OK;
 }

@@ -16,6 +16,11 @@ constexpr int kSortBlock = 256;  // threads per radix-sort block
 constexpr int kSortItems = 16;   // keys per thread
 constexpr int kSortTile = kSortBlock * kSortItems;  // keys per partition
 constexpr int kRadixBins = 256;
+constexpr int kScanTile = 2048;   // Gaussians per offset-scan partition
+constexpr int kEmitChunk = 4096;  // output instances per emit block
+static_assert(kEmitChunk == kSortTile, "emission chunks are radix partitions");
+constexpr int kDiffParts = 64;    // LDS copies of the tile difference grid
+constexpr int kDiffMaxCells = 16384;  // largest grid kept in LDS (64 KB)
 constexpr int kMaxCells = 16;
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -52,15 +57,38 @@ struct SortLayout {
   size_t counters;     // uint32[16] partition counters
   size_t dstatus;      // uint32[4][dparts][256]
   size_t tstatus;      // uint32[3][tparts][256]
-  size_t estatus;      // uint64[eparts] emit look-back
+  size_t estatus;      // uint64[eparts] offset-scan look-back
+  size_t diff;         // int32[(tiles_y+1)*(tiles_x+1)] tile-rect difference grid
   size_t zero_end;
+  size_t diffparts;    // int32[kDiffParts][cells] per-block difference grids
+  size_t offs;         // uint32[n] instance offsets of the depth-sorted Gaussians
+  size_t goffs;        // uint32[n] instance offset of each visible Gaussian (by index)
+  size_t chunk_first;  // uint32[cap/kEmitChunk + 2] owner of each chunk's first slot
   size_t tkey[2];      // uint32[cap] tile ids (ping-pong)
   size_t tval[2];      // uint32[cap] Gaussian indices (ping-pong)
-  size_t tsorted;      // uint32[cap] sorted tile ids (for ranges)
   size_t total;
   int64_t nb, dparts, tparts, eparts;
 };
-SortLayout sort_layout(int64_t n, int64_t capacity);
+SortLayout sort_layout(int64_t n, int64_t capacity, int64_t tiles_total);
+
+// backward workspace: per-instance gradient rows (indexed by emission
+// position) and, per tile, the sort key of the last entry its walk visited
+struct BwdLayout {
+  size_t gpart;     // float[cap][kG2dFloats]
+  size_t last_key;  // uint64[tiles]
+  size_t total;
+};
+BwdLayout bwd_layout(int64_t capacity, int64_t tiles_total);
+
+// what the backward needs from a cell's sort workspace
+struct SortView {
+  const uint64_t* counts;
+  const uint32_t* didx;   // depth-sorted visible Gaussians
+  const uint32_t* offs;   // their exclusive instance offsets
+  const uint32_t* goffs;  // instance offset by Gaussian index
+  const uint32_t* chunk_first;
+};
+SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_total);
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -189,6 +217,23 @@ __device__ __forceinline__ void quat_rot(double w, double x, double y,
   R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+// First and last depth-sorted Gaussian owning slots of chunk [c0, c1)
+// (c0 a multiple of kEmitChunk): the owner of slot c0 comes from the table
+// k_offsets wrote; the last one owns slot c1 - 1, i.e. it is the owner of
+// the next chunk's first slot unless that Gaussian starts exactly at c1.
+__device__ __forceinline__ void chunk_bounds(const uint32_t* chunk_first, const uint32_t* offs,
+                                             uint64_t nvis, uint64_t ninst, uint64_t c0,
+                                             uint64_t c1, uint32_t* lohi) {
+  const uint64_t c = c0 / kEmitChunk;
+  lohi[0] = chunk_first[c];
+  if (c1 >= ninst) {
+    lohi[1] = (uint32_t)nvis - 1;  // the last chunk ends with the last Gaussian
+  } else {
+    const uint32_t nx = chunk_first[c + 1];
+    lohi[1] = offs[nx] < c1 ? nx : nx - 1;
+  }
+}
+
 // Per-pixel alpha of one Gaussian (Eq. 1 with the clamp): the forward and
 // the backward kernels call this same function so their decisions agree
 // bit for bit.
@@ -217,9 +262,10 @@ namespace sx {
 hipError_t launch_preprocess(const sx_gaussians& g, const DCam& cam,
                              const KParams& p, const sx_projected& out,
                              hipStream_t st);
+struct SortView;
 hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
                                       const KParams& p,
-                                      const sx_projected& proj,
+                                      const sx_projected& proj, const SortView& sv,
                                       const float* g2d, const sx_grads& gr,
                                       bool accumulate, hipStream_t st);
 hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
@@ -234,10 +280,11 @@ hipError_t launch_render(const sx_projected& proj, const uint32_t* vals,
                          uint32_t* nblend, hipStream_t st);
 hipError_t launch_render_backward(const sx_projected& proj,
                                   const uint32_t* vals, const uint32_t* ranges,
-                                  int64_t n, const DCam& cam, const KParams& p,
+                                  const SortView& sv, int64_t n, int64_t capacity,
+                                  const DCam& cam, const KParams& p,
                                   const uint32_t* mask, const float* partial,
                                   const uint32_t* last, const float* dpartial,
-                                  const float* ddepth, float* g2d,
+                                  const float* ddepth, float* g2d, char* bws,
                                   hipStream_t st);
 hipError_t launch_composite(int K, const float* const* partials,
                             const sx_cell* cells, const DCam& cam,

@@ -8,6 +8,8 @@
 // to the last bit.  A Gaussian culled by its mean depth costs one 12-byte
 // read and a 4-byte write; only visible ones read rotation, scale, opacity
 // and SH coefficients.
+#include <cmath>
+
 #include "sx_internal.h"
 
 namespace sx {
@@ -21,6 +23,9 @@ struct PreArgs {
   const float* __restrict__ sh;
   DCam cam;
   KParams p;
+  struct {
+    float R[9], t[3], fx, fy, cx, cy, znear, logit_min, tau_max, eps2d;
+  } cull;
   float* __restrict__ rec;
   uint16_t* __restrict__ rect;
   uint32_t* __restrict__ n_tiles;
@@ -115,6 +120,40 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ means
   return true;
 }
 
+// Cheap conservative test run by every Gaussian before the FP64 projection:
+// mean depth, opacity, and whether the footprint can reach the image.  For
+// any direction u, u^T Sigma2D u <= s_max^2 |J|_F^2 + eps2d, and
+// tau <= 2 ln(1/alpha_min), so the half-extent of the alpha >= alpha_min
+// footprint is at most E = sqrt(tau_max (s_max^2 |J|_F^2 + eps2d)); a mean
+// projected farther than E outside the image cannot touch a pixel.  The test
+// runs in FP32 with margins far above its rounding error (it only has to
+// never drop a Gaussian the exact FP64 test in project_one would keep).
+__device__ __forceinline__ bool maybe_visible(const PreArgs& a, int64_t i) {
+  const float mx = a.means[i * 3 + 0], my = a.means[i * 3 + 1], mz = a.means[i * 3 + 2];
+  const float* R = a.cull.R;
+  const float p6 = R[6] * mx, p7 = R[7] * my, p8 = R[8] * mz;
+  const float tz = p6 + p7 + p8 + a.cull.t[2];
+  const float zslack = 1e-5f * (fabsf(p6) + fabsf(p7) + fabsf(p8) + fabsf(a.cull.t[2])) + 1e-6f;
+  if (tz + zslack <= a.cull.znear) return false;
+  if (a.logits[i] < a.cull.logit_min) return false;
+  const float tzc = fmaxf(tz, a.cull.znear * 0.5f);
+  const float tx = R[0] * mx + R[1] * my + R[2] * mz + a.cull.t[0];
+  const float ty = R[3] * mx + R[4] * my + R[5] * mz + a.cull.t[1];
+  const float ls = fmaxf(fmaxf(a.log_scales[i * 3 + 0], a.log_scales[i * 3 + 1]),
+                         a.log_scales[i * 3 + 2]);
+  const float s2 = __expf(2.f * ls);
+  const float iz = 1.f / tzc;
+  const float jx = a.cull.fx * iz, jy = a.cull.fy * iz;
+  const float jf = jx * jx * (1.f + tx * tx * iz * iz) + jy * jy * (1.f + ty * ty * iz * iz);
+  const float E = sqrtf(a.cull.tau_max * (s2 * jf + a.cull.eps2d)) * 1.01f + 2.f;
+  const float ux = a.cull.fx * tx * iz + a.cull.cx, uy = a.cull.fy * ty * iz + a.cull.cy;
+  const float mxs = E + 1e-4f * fabsf(ux), mys = E + 1e-4f * fabsf(uy);
+  if (ux + mxs < 0.f || ux - mxs > (float)a.cam.W) return false;
+  if (uy + mys < 0.f || uy - mys > (float)a.cam.H) return false;
+  return true;
+}
+
+template <int D>
 __device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
   Proj64 g;
   if (!project_geometry(a.means, a.log_scales, a.quats, i, a.cam, a.p.eps2d, g)) return 0;
@@ -136,12 +175,12 @@ __device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
   const int tx0 = (int)x0 / a.p.tile_w, tx1 = (int)x1 / a.p.tile_w;
   const int ty0 = (int)y0 / a.p.tile_h, ty1 = (int)y1 / a.p.tile_h;
   // colour: max(0, sum_lm k_lm Y_lm(dir) + 0.5)
-  const int deg = a.p.sh_degree;
-  const int nc = (deg + 1) * (deg + 1);
+  constexpr int nc = (D + 1) * (D + 1);
   double Y[16];
-  sh_basis(deg, g.dir[0], g.dir[1], g.dir[2], Y);
+  sh_basis(D, g.dir[0], g.dir[1], g.dir[2], Y);
   const float* __restrict__ shp = a.sh + (size_t)i * nc * 3;
   double col[3] = {0.0, 0.0, 0.0};
+#pragma unroll
   for (int k = 0; k < nc; ++k) {
     col[0] += (double)shp[k * 3 + 0] * Y[k];
     col[1] += (double)shp[k * 3 + 1] * Y[k];
@@ -162,21 +201,43 @@ __device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
   return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 }
 
+// Block-level compaction: lanes whose Gaussian may be visible are packed to
+// the front of the block, so the FP64 projection runs in full wavefronts
+// even when only a few percent of the scene is in view.
+template <int D>
 __global__ __launch_bounds__(kPreBlock) void k_preprocess(PreArgs a) {
+  __shared__ uint32_t s_cand[kPreBlock];
+  __shared__ uint32_t s_w[kPreBlock / 64];
+  __shared__ uint32_t sv[kPreBlock / 64], sc[kPreBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
-  uint32_t cnt = 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bool cand = false;
   if (i < a.n) {
-    cnt = project_one(a, i);
-    a.n_tiles[i] = cnt;
+    cand = maybe_visible(a, i);
+    if (!cand) a.n_tiles[i] = 0;
+  }
+  const uint64_t bal = __ballot(cand);
+  if (lane == 0) s_w[w] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t pre = 0, ncand = 0;
+  for (int k = 0; k < kPreBlock / 64; ++k) {
+    if (k < w) pre += s_w[k];
+    ncand += s_w[k];
+  }
+  if (cand) s_cand[pre + __popcll(bal & ((1ull << lane) - 1))] = threadIdx.x;
+  __syncthreads();
+  uint32_t cnt = 0;
+  if (threadIdx.x < ncand) {
+    const int64_t ii = (int64_t)blockIdx.x * kPreBlock + s_cand[threadIdx.x];
+    cnt = project_one<D>(a, ii);
+    a.n_tiles[ii] = cnt;
   }
   uint32_t vis = cnt > 0 ? 1u : 0u;
   for (int o = 32; o >= 1; o >>= 1) {
     vis += __shfl_xor(vis, o, 64);
     cnt += __shfl_xor(cnt, o, 64);
   }
-  __shared__ uint32_t sv[kPreBlock / 64], sc[kPreBlock / 64];
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sv[w] = vis, sc[w] = cnt;
+  if (lane == 0) sv[w] = vis, sc[w] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t a0 = 0, a1 = 0;
@@ -195,10 +256,24 @@ hipError_t launch_preprocess(const sx_gaussians& g, const DCam& cam,
   a.means = g.means, a.log_scales = g.log_scales, a.quats = g.quats;
   a.logits = g.opacity_logits, a.sh = g.sh;
   a.cam = cam, a.p = p;
+  for (int k = 0; k < 9; ++k) a.cull.R[k] = (float)cam.R[k];
+  for (int k = 0; k < 3; ++k) a.cull.t[k] = (float)cam.t[k];
+  a.cull.fx = (float)cam.fx, a.cull.fy = (float)cam.fy;
+  a.cull.cx = (float)cam.cx, a.cull.cy = (float)cam.cy;
+  a.cull.znear = (float)cam.znear;
+  // o < alpha_min  <=>  logit < ln(alpha_min / (1 - alpha_min)); keep a margin
+  a.cull.logit_min = (float)(std::log(p.alpha_min_d / (1.0 - p.alpha_min_d)) - 1e-3);
+  a.cull.tau_max = (float)(2.0 * std::log(1.0 / p.alpha_min_d));
+  a.cull.eps2d = (float)p.eps2d;
   a.rec = out.rec, a.rect = out.rect, a.n_tiles = out.n_tiles;
   a.block_sums = out.block_sums;
   const int64_t blocks = (g.n + kPreBlock - 1) / kPreBlock;
-  hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(kPreBlock), 0, st, a);
+  switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3((unsigned)blocks), dim3(kPreBlock), 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3((unsigned)blocks), dim3(kPreBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3((unsigned)blocks), dim3(kPreBlock), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, dim3((unsigned)blocks), dim3(kPreBlock), 0, st, a); break;
+  }
   return hipGetLastError();
 }
 
@@ -211,6 +286,8 @@ struct PreBwdArgs {
   const float* __restrict__ logits;
   const float* __restrict__ sh;
   const uint32_t* __restrict__ n_tiles;
+  const uint32_t* __restrict__ vis;  // compacted visible Gaussians
+  const uint64_t* vis_count;
   const float* __restrict__ g2d;
   DCam cam;
   KParams p;
@@ -222,8 +299,9 @@ struct PreBwdArgs {
   int accumulate;
 };
 
-__device__ __forceinline__ void put(float* p, double v, bool acc) {
-  if (acc)
+template <bool ACC>
+__device__ __forceinline__ void put(float* p, double v) {
+  if (ACC)
     *p += (float)v;
   else
     *p = (float)v;
@@ -234,10 +312,8 @@ __device__ __forceinline__ void put(float* p, double v, bool acc) {
 // (dM = J^T G_S J, dJ = 2 G_S J M), M -> Sigma (W^T dM W), Sigma = L L^T
 // with L = R(q) S (dL = 2 dSigma L) -> log-scales and the quaternion; the
 // mean through mean2d, J(t), depth and the SH view direction.
-__global__ __launch_bounds__(128) void k_preprocess_backward(PreBwdArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
-  if (i >= a.n || a.n_tiles[i] == 0) return;
-  const bool acc = a.accumulate != 0;
+template <int D, bool ACC>
+__device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
   Proj64 g;
   if (!project_geometry(a.means, a.log_scales, a.quats, i, a.cam, a.p.eps2d, g)) return;
   const float* gr = a.g2d + (size_t)i * kG2dFloats;
@@ -247,22 +323,24 @@ __global__ __launch_bounds__(128) void k_preprocess_backward(PreBwdArgs a) {
   const double gmx = g0.x, gmy = g0.y, ga = g0.z, gb = g0.w, gc = g1.x, gop = g1.y;
   const double gcol[3] = {g1.z, g1.w, g2.x};
   const double gz = g2.y;
-  const int deg = a.p.sh_degree;
-  const int nc = (deg + 1) * (deg + 1);
+  constexpr int nc = (D + 1) * (D + 1);
   // colour -> SH coefficients and direction
   double Y[16], dY[48];
-  sh_basis(deg, g.dir[0], g.dir[1], g.dir[2], Y);
-  sh_basis_grad(deg, g.dir[0], g.dir[1], g.dir[2], dY);
+  sh_basis(D, g.dir[0], g.dir[1], g.dir[2], Y);
+  sh_basis_grad(D, g.dir[0], g.dir[1], g.dir[2], dY);
   const float* __restrict__ shp = a.sh + (size_t)i * nc * 3;
   float* gshp = a.gsh + (size_t)i * nc * 3;
   double gdir[3] = {0.0, 0.0, 0.0};
+#pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     double v = 0.0;
+#pragma unroll
     for (int k = 0; k < nc; ++k) v += (double)shp[k * 3 + ch] * Y[k];
     const bool pos = v + 0.5 > 0.0;
     const double gcv = pos ? gcol[ch] : 0.0;
+#pragma unroll
     for (int k = 0; k < nc; ++k) {
-      put(&gshp[k * 3 + ch], gcv * Y[k], acc);
+      put<ACC>(&gshp[k * 3 + ch], gcv * Y[k]);
       const double w = gcv * (double)shp[k * 3 + ch];
       gdir[0] += w * dY[k * 3 + 0];
       gdir[1] += w * dY[k * 3 + 1];
@@ -276,7 +354,7 @@ __global__ __launch_bounds__(128) void k_preprocess_backward(PreBwdArgs a) {
   }
   // opacity through the sigmoid
   const double o = 1.0 / (1.0 + exp(-(double)a.logits[i]));
-  put(&a.glogits[i], gop * o * (1.0 - o), acc);
+  put<ACC>(&a.glogits[i], gop * o * (1.0 - o));
   // conic -> covariance
   const double A[4] = {g.conic[0], g.conic[1], g.conic[1], g.conic[2]};
   const double Gc[4] = {ga, 0.5 * gb, 0.5 * gb, gc};
@@ -327,7 +405,7 @@ __global__ __launch_bounds__(128) void k_preprocess_backward(PreBwdArgs a) {
   for (int k = 0; k < 3; ++k) {
     double v = 0;
     for (int r = 0; r < 3; ++r) v += dLm[r * 3 + k] * g.Rq[r * 3 + k];
-    put(&a.glog_scales[i * 3 + k], v * g.s[k], acc);
+    put<ACC>(&a.glog_scales[i * 3 + k], v * g.s[k]);
   }
   double dR[9];
   for (int r = 0; r < 3; ++r)
@@ -343,7 +421,7 @@ __global__ __launch_bounds__(128) void k_preprocess_backward(PreBwdArgs a) {
                  y * dR[5] + x * dR[6] + y * dR[7]);
   {
     const double dd = dq[0] * g.qh[0] + dq[1] * g.qh[1] + dq[2] * g.qh[2] + dq[3] * g.qh[3];
-    for (int k = 0; k < 4; ++k) put(&a.gquats[i * 4 + k], (dq[k] - dd * g.qh[k]) / g.qn, acc);
+    for (int k = 0; k < 4; ++k) put<ACC>(&a.gquats[i * 4 + k], (dq[k] - dd * g.qh[k]) / g.qn);
   }
   // mean: mean2d, J(t), depth; then world = W^T dt (+ SH direction term)
   const double z = g.t[2], fx = a.cam.fx, fy = a.cam.fy;
@@ -355,17 +433,30 @@ __global__ __launch_bounds__(128) void k_preprocess_backward(PreBwdArgs a) {
           dJ[2] * (2.0 * fx * tx / (z * z * z)) + dJ[4] * (-fy / (z * z)) +
           dJ[5] * (2.0 * fy * ty / (z * z * z)) + gz;
   for (int k = 0; k < 3; ++k)
-    put(&a.gmeans[i * 3 + k], W[0 * 3 + k] * dt[0] + W[1 * 3 + k] * dt[1] + W[2 * 3 + k] * dt[2] + gmu[k],
-        acc);
+    put<ACC>(&a.gmeans[i * 3 + k],
+             W[0 * 3 + k] * dt[0] + W[1 * 3 + k] * dt[1] + W[2 * 3 + k] * dt[2] + gmu[k]);
+}
+
+// One lane per visible Gaussian, taken from the sort's compacted list, so
+// the FP64 chain runs in full wavefronts.
+template <int D, bool ACC>
+__global__ __launch_bounds__(kPreBlock) void k_preprocess_backward(PreBwdArgs a) {
+  const uint64_t i = (uint64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  if (i >= a.vis_count[0]) return;
+  const uint32_t g = a.vis[i];
+  if (a.n_tiles[g] == 0) return;
+  backward_one<D, ACC>(a, (int64_t)g);
 }
 
 hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
                                       const KParams& p,
-                                      const sx_projected& proj,
+                                      const sx_projected& proj, const SortView& sv,
                                       const float* g2d, const sx_grads& gr,
                                       bool accumulate, hipStream_t st) {
   if (g.n == 0) return hipSuccess;
   PreBwdArgs a;
+  a.vis = sv.didx;
+  a.vis_count = sv.counts;
   a.n = g.n;
   a.means = g.means, a.log_scales = g.log_scales, a.quats = g.quats;
   a.logits = g.opacity_logits, a.sh = g.sh;
@@ -375,8 +466,21 @@ hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
   a.gmeans = gr.means, a.glog_scales = gr.log_scales, a.gquats = gr.quats;
   a.glogits = gr.opacity_logits, a.gsh = gr.sh;
   a.accumulate = accumulate ? 1 : 0;
-  const int64_t blocks = (g.n + 127) / 128;
-  hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)blocks), dim3(128), 0, st, a);
+  const dim3 grid((unsigned)((g.n + kPreBlock - 1) / kPreBlock));
+#define SX_PB(D)                                                                               \
+  do {                                                                                         \
+    if (accumulate)                                                                            \
+      hipLaunchKernelGGL((k_preprocess_backward<D, true>), grid, dim3(kPreBlock), 0, st, a);   \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_preprocess_backward<D, false>), grid, dim3(kPreBlock), 0, st, a);  \
+  } while (0)
+  switch (p.sh_degree) {
+    case 0: SX_PB(0); break;
+    case 1: SX_PB(1); break;
+    case 2: SX_PB(2); break;
+    default: SX_PB(3); break;
+  }
+#undef SX_PB
   return hipGetLastError();
 }
 

@@ -89,7 +89,11 @@ struct RenderBwdArgs {
   const uint32_t* __restrict__ last;
   const float4* __restrict__ dpartial;
   const float* __restrict__ ddepth;
-  float* g2d;
+  const uint16_t* __restrict__ rect;
+  const uint32_t* __restrict__ goffs;
+  uint64_t cap;
+  float* __restrict__ gpart;
+  uint64_t* __restrict__ last_key;
 };
 
 // Reverse walk of each pixel's blended pairs.  With R the colour behind pair
@@ -99,87 +103,247 @@ struct RenderBwdArgs {
 //   dalpha_i = T_i [G.(c_i - R) + g_D (z_i - RD)] - g_T T_final / (1 - alpha_i)
 // then alpha = o exp(-q/2) gives do = dalpha exp(-q/2), dq = -alpha/2 dalpha
 // (zero when alpha was clamped), and q gives the mean2d and conic terms.
-// Gradients are summed over the wavefront (DPP) and added with one atomic
-// per (Gaussian, wavefront, field).
+//
+// One wavefront per tile; each lane owns TW*TH/64 pixels and sums their
+// contributions in registers, then one cross-lane reduction (DPP) per
+// (Gaussian, tile).  No atomics: the tile's partial gradient row is stored
+// at the instance's position in emission order, e = (first instance of the
+// Gaussian) + (row-major index of the tile within its rectangle), a slot no
+// other tile writes; rows of visited entries without any contribution are
+// stored as zeros.  The tile records the sort key of the last entry it
+// visited, which tells the per-Gaussian reduction which slots are valid.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderBwdArgs a) {
+__global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
+  constexpr int PPT = TW * TH / 64;
   const int ntile = a.tiles_x * a.tiles_y;
   const int tile = xcd_tile(blockIdx.x, ntile);
   if (tile >= ntile) return;
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-  const int px = tx * TW + lx, py = ty * TH + ly;
-  const bool inside = px < a.W && py < a.H;
-  const uint32_t pix = inside ? (uint32_t)py * a.W + px : 0u;
-  bool active = inside;
-  if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
-  const float fx = (float)px + 0.5f - a.cx, fy = (float)py + 0.5f - a.cy;
+  const int lane = threadIdx.x;
   const uint2 rg = a.ranges[tile];
-  float Tfin = 1.f;
-  float4 gC = make_float4(0.f, 0.f, 0.f, 0.f);
-  float gD = 0.f;
-  uint32_t my_last = 0;
-  if (active) {
-    Tfin = a.partial[pix].w;
-    gC = a.dpartial[pix];
-    if (a.ddepth) gD = a.ddepth[pix];
-    my_last = a.last[pix];
+  float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
+  float gx[PPT], gy[PPT], gz[PPT], gt[PPT], gd[PPT], Tf[PPT];
+  uint32_t lst[PPT];
+  uint32_t mx = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int li = lane + 64 * k;
+    const int px = tx * TW + li % TW, py = ty * TH + li / TW;
+    const bool inside = px < a.W && py < a.H;
+    const uint32_t pix = inside ? (uint32_t)py * a.W + px : 0u;
+    bool active = inside;
+    if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
+    fx[k] = (float)px + 0.5f - a.cx;
+    fy[k] = (float)py + 0.5f - a.cy;
+    Tf[k] = 1.f, gx[k] = gy[k] = gz[k] = gt[k] = gd[k] = 0.f;
+    lst[k] = 0;
+    if (active) {
+      Tf[k] = a.partial[pix].w;
+      const float4 g = a.dpartial[pix];
+      gx[k] = g.x, gy[k] = g.y, gz[k] = g.z, gt[k] = g.w;
+      if (a.ddepth) gd[k] = a.ddepth[pix];
+      lst[k] = a.last[pix];
+    }
+    T[k] = Tf[k];
+    R0[k] = R1[k] = R2[k] = RD[k] = 0.f;
+    mx = lst[k] > mx ? lst[k] : mx;
   }
-  const uint32_t wave_last = wave_max_u32(my_last);
-  const bool lane63 = (threadIdx.x & 63) == 63;
-  float T = Tfin, R0 = 0.f, R1 = 0.f, R2 = 0.f, RD = 0.f;
-  for (int k = (int)wave_last - 1; k >= 0; --k) {
-    const uint32_t j = rg.x + (uint32_t)k;
-    const uint32_t g = a.vals[j];
+  const uint32_t wave_last = wave_max_u32(mx);
+  if (lane == 0) {
+    uint64_t key = 0;
+    if (wave_last > 0) {
+      const uint32_t gl = a.vals[rg.x + wave_last - 1];
+      key = ((uint64_t)__float_as_uint(a.rec[(size_t)gl * kRecFloats + 9]) << 32) | gl;
+    }
+    a.last_key[tile] = key;
+  }
+  for (int j = (int)wave_last - 1; j >= 0; --j) {
+    const uint32_t g = a.vals[rg.x + (uint32_t)j];
     const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)g * kRecFloats);
     const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-    const float dx = fx - r0.x, dy = fy - r0.y;
-    const AlphaEval ae = eval_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-    const bool contrib = (uint32_t)k < my_last && ae.alpha >= a.alpha_min;
-    if (__ballot(contrib) == 0) continue;
+    const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[g];
+    const uint32_t e = a.goffs[g] + ((uint32_t)ty - rc.y) * ((uint32_t)rc.z - rc.x) + ((uint32_t)tx - rc.x);
+    float4* dst = reinterpret_cast<float4*>(a.gpart + (size_t)e * kG2dFloats);
+    const bool in_cap = (uint64_t)e < a.cap;
     float v[10];
 #pragma unroll
     for (int m = 0; m < 10; ++m) v[m] = 0.f;
-    if (contrib) {
-      const float om = 1.f - ae.alpha;
-      const float rom = 1.f / om;
-      const float Ti = T * rom;
-      const float w = ae.alpha * Ti;
-      v[6] = w * gC.x;
-      v[7] = w * gC.y;
-      v[8] = w * gC.z;
-      v[9] = w * gD;
-      float da = gC.x * (r1.z - R0) + gC.y * (r1.w - R1) + gC.z * (r2.x - R2) + gD * (r2.y - RD);
-      da = Ti * da - gC.w * (Tfin * rom);
-      R0 = fmaf(r1.z, ae.alpha, om * R0);
-      R1 = fmaf(r1.w, ae.alpha, om * R1);
-      R2 = fmaf(r2.x, ae.alpha, om * R2);
-      RD = fmaf(r2.y, ae.alpha, om * RD);
-      T = Ti;
-      if (!ae.clamped) {
-        v[5] = da * ae.G;
-        const float dq = -0.5f * ae.alpha * da;
-        v[0] = -2.f * dq * (r0.z * dx + r0.w * dy);
-        v[1] = -2.f * dq * (r0.w * dx + r1.x * dy);
-        v[2] = dq * dx * dx;
-        v[3] = 2.f * dq * dx * dy;
-        v[4] = dq * dy * dy;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const float dx = fx[k] - r0.x, dy = fy[k] - r0.y;
+      const AlphaEval ae = eval_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
+      if ((uint32_t)j < lst[k] && ae.alpha >= a.alpha_min) {
+        any = true;
+        const float om = 1.f - ae.alpha;
+        const float rom = 1.f / om;
+        const float Ti = T[k] * rom;
+        const float w = ae.alpha * Ti;
+        v[6] += w * gx[k];
+        v[7] += w * gy[k];
+        v[8] += w * gz[k];
+        v[9] += w * gd[k];
+        float da = gx[k] * (r1.z - R0[k]) + gy[k] * (r1.w - R1[k]) + gz[k] * (r2.x - R2[k]) +
+                   gd[k] * (r2.y - RD[k]);
+        da = Ti * da - gt[k] * (Tf[k] * rom);
+        R0[k] = fmaf(r1.z, ae.alpha, om * R0[k]);
+        R1[k] = fmaf(r1.w, ae.alpha, om * R1[k]);
+        R2[k] = fmaf(r2.x, ae.alpha, om * R2[k]);
+        RD[k] = fmaf(r2.y, ae.alpha, om * RD[k]);
+        T[k] = Ti;
+        if (!ae.clamped) {
+          v[5] += da * ae.G;
+          const float dq = -0.5f * ae.alpha * da;
+          v[0] += -2.f * dq * (r0.z * dx + r0.w * dy);
+          v[1] += -2.f * dq * (r0.w * dx + r1.x * dy);
+          v[2] += dq * dx * dx;
+          v[3] += 2.f * dq * dx * dy;
+          v[4] += dq * dy * dy;
+        }
       }
     }
-    float* dst = a.g2d + (size_t)g * kG2dFloats;
+    if (__ballot(any) == 0) {
+      if (lane == 63 && in_cap) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        dst[0] = z, dst[1] = z, dst[2] = z;
+      }
+      continue;
+    }
+    float sum[10];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) {
-      const float s = wave_sum_to_lane63(v[m]);
-      if (lane63) unsafeAtomicAdd(dst + m, s);
+    for (int m = 0; m < 10; ++m) sum[m] = wave_sum_to_lane63(v[m]);
+    if (lane == 63 && in_cap) {
+      dst[0] = make_float4(sum[0], sum[1], sum[2], sum[3]);
+      dst[1] = make_float4(sum[4], sum[5], sum[6], sum[7]);
+      dst[2] = make_float4(sum[8], sum[9], 0.f, 0.f);
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_zero_g2d(const uint32_t* __restrict__ n_tiles, int64_t n,
+// Per-Gaussian sum of the partial gradient rows.  Balanced like the
+// emission: every block owns instances [c0, c0 + kEmitChunk) in emission
+// order, where each Gaussian's instances are contiguous.  An instance's row
+// is valid iff its tile visited it, i.e. (depth bits, index) of the
+// Gaussian <= the tile's last visited key.  Sums are formed in LDS; a
+// Gaussian lying wholly inside the chunk is stored with plain stores, one
+// that straddles a chunk boundary is added atomically into its
+// (pre-zeroed) row, so atomics occur at most twice per chunk.
+struct ReduceArgs {
+  const uint32_t* __restrict__ didx;
+  const uint32_t* __restrict__ offs;
+  const uint32_t* __restrict__ chunk_first;
+  const uint64_t* counts;
+  const uint16_t* __restrict__ rect;
+  const uint32_t* __restrict__ n_tiles;
+  const float* __restrict__ rec;
+  const float* __restrict__ gpart;
+  const uint64_t* __restrict__ last_key;
+  int tiles_x;
+  uint64_t cap;
+  float* __restrict__ g2d;
+};
+
+__global__ __launch_bounds__(256) void k_grad_reduce(ReduceArgs a) {
+  __shared__ uint32_t s_off[257], s_end[256], s_g[256], s_x0[256], s_y0[256], s_w[256];
+  __shared__ unsigned long long s_key[256];
+  __shared__ float s_acc[256 * 10];
+  __shared__ uint32_t s_lohi[2];
+  const int tid = threadIdx.x;
+  if (a.counts[2] != 0) return;
+  const uint64_t ninst = a.counts[1] < a.cap ? a.counts[1] : a.cap;
+  const uint64_t nvis = a.counts[0];
+  const uint64_t c0 = (uint64_t)blockIdx.x * kEmitChunk;
+  if (c0 >= ninst) return;
+  const uint64_t c1 = c0 + kEmitChunk < ninst ? c0 + kEmitChunk : ninst;
+  if (tid == 0) chunk_bounds(a.chunk_first, a.offs, nvis, ninst, c0, c1, s_lohi);
+  __syncthreads();
+  const uint32_t slo = s_lohi[0], shi = s_lohi[1];
+  for (uint32_t w0 = slo; w0 <= shi; w0 += 256) {
+    const uint32_t wn = (shi - w0 + 1) < 256u ? (shi - w0 + 1) : 256u;
+    if ((uint32_t)tid < wn) {
+      const uint32_t sidx = w0 + tid;
+      const uint32_t g = a.didx[sidx];
+      const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[g];
+      s_off[tid] = a.offs[sidx];
+      s_end[tid] = a.offs[sidx] + a.n_tiles[g];
+      s_g[tid] = g;
+      s_x0[tid] = rc.x, s_y0[tid] = rc.y, s_w[tid] = (uint32_t)rc.z - rc.x;
+      s_key[tid] = ((unsigned long long)__float_as_uint(a.rec[(size_t)g * kRecFloats + 9]) << 32) | g;
+#pragma unroll
+      for (int m = 0; m < 10; ++m) s_acc[tid * 10 + m] = 0.f;
+    }
+    if (tid == 0) {
+      const uint64_t e = (uint64_t)w0 + wn < nvis ? (uint64_t)a.offs[w0 + wn] : ninst;
+      s_off[wn] = (uint32_t)(e < c1 ? e : c1);
+    }
+    __syncthreads();
+    const uint64_t k0 = (uint64_t)s_off[0] > c0 ? (uint64_t)s_off[0] : c0;
+    const uint64_t k1 = s_off[wn];
+    // runs of consecutive slots per thread: sums stay in registers while the
+    // run stays on one Gaussian and go to LDS when it moves on
+    const uint32_t run = ((uint32_t)(k1 - k0) + 255) / 256;
+    uint64_t k = k0 + (uint64_t)tid * run;
+    const uint64_t kend = k + run < k1 ? k + run : k1;
+    if (k < kend) {
+      int j = 0, hi = (int)wn - 1;
+      while (j < hi) {
+        const int mid = (j + hi + 1) >> 1;
+        if (s_off[mid] <= k) j = mid; else hi = mid - 1;
+      }
+      uint32_t wj = s_w[j];
+      const uint32_t r = (uint32_t)(k - s_off[j]);
+      uint32_t ty = r / wj, tx = r - ty * wj;
+      float acc[10];
+#pragma unroll
+      for (int m = 0; m < 10; ++m) acc[m] = 0.f;
+      bool dirty = false;
+      for (; k < kend; ++k) {
+        if (k == s_off[j + 1]) {
+          if (dirty) {
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(s_acc + j * 10 + m, acc[m]), acc[m] = 0.f;
+            dirty = false;
+          }
+          ++j;
+          wj = s_w[j], tx = 0, ty = 0;
+        }
+        const uint32_t tile = (s_y0[j] + ty) * (uint32_t)a.tiles_x + s_x0[j] + tx;
+        if (s_key[j] <= a.last_key[tile]) {
+          const float4* src = reinterpret_cast<const float4*>(a.gpart + (size_t)k * kG2dFloats);
+          const float4 p0 = src[0], p1 = src[1], p2 = src[2];
+          acc[0] += p0.x, acc[1] += p0.y, acc[2] += p0.z, acc[3] += p0.w, acc[4] += p1.x;
+          acc[5] += p1.y, acc[6] += p1.z, acc[7] += p1.w, acc[8] += p2.x, acc[9] += p2.y;
+          dirty = true;
+        }
+        if (++tx == wj) tx = 0, ++ty;
+      }
+      if (dirty) {
+#pragma unroll
+        for (int m = 0; m < 10; ++m) atomicAdd(s_acc + j * 10 + m, acc[m]);
+      }
+    }
+    __syncthreads();
+    if ((uint32_t)tid < wn) {
+      float* dst = a.g2d + (size_t)s_g[tid] * kG2dFloats;
+      const bool interior = s_off[tid] >= c0 && s_end[tid] <= c1;
+      if (interior) {
+#pragma unroll
+        for (int m = 0; m < 10; ++m) dst[m] = s_acc[tid * 10 + m];
+      } else {
+#pragma unroll
+        for (int m = 0; m < 10; ++m) unsafeAtomicAdd(dst + m, s_acc[tid * 10 + m]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero_g2d(const uint32_t* __restrict__ vis,
+                                                  const uint64_t* vis_count,
                                                   float* __restrict__ g2d) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n || n_tiles[i] == 0) return;
-  float4* d = reinterpret_cast<float4*>(g2d + (size_t)i * kG2dFloats);
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= vis_count[0]) return;
+  float4* d = reinterpret_cast<float4*>(g2d + (size_t)vis[i] * kG2dFloats);
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   d[0] = z, d[1] = z, d[2] = z;
 }
@@ -199,7 +363,7 @@ template <int TW, int TH>
 static void launch_bwd_t(const RenderBwdArgs& a, hipStream_t st) {
   const int ntile = a.tiles_x * a.tiles_y;
   const int grid = ((ntile + 7) >> 3) * 8;
-  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, a);
+  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(64), 0, st, a);
 }
 
 #define SX_DISPATCH_TILE(tw, th, FN, ARGS, ST)           \
@@ -233,14 +397,19 @@ hipError_t launch_render(const sx_projected& proj, const uint32_t* vals,
 
 hipError_t launch_render_backward(const sx_projected& proj,
                                   const uint32_t* vals, const uint32_t* ranges,
-                                  int64_t n, const DCam& cam, const KParams& p,
+                                  const SortView& sv, int64_t n, int64_t capacity,
+                                  const DCam& cam, const KParams& p,
                                   const uint32_t* mask, const float* partial,
                                   const uint32_t* last, const float* dpartial,
-                                  const float* ddepth, float* g2d,
+                                  const float* ddepth, float* g2d, char* bws,
                                   hipStream_t st) {
+  const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
+  const BwdLayout BL = bwd_layout(capacity, tiles);
+  float* gpart = reinterpret_cast<float*>(bws + BL.gpart);
+  uint64_t* last_key = reinterpret_cast<uint64_t*>(bws + BL.last_key);
   if (n > 0)
     hipLaunchKernelGGL(k_zero_g2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       proj.n_tiles, n, g2d);
+                       sv.didx, sv.counts, g2d);
   RenderBwdArgs a;
   a.rec = proj.rec;
   a.vals = vals;
@@ -253,8 +422,21 @@ hipError_t launch_render_backward(const sx_projected& proj,
   a.last = last;
   a.dpartial = reinterpret_cast<const float4*>(dpartial);
   a.ddepth = ddepth;
-  a.g2d = g2d;
+  a.rect = proj.rect;
+  a.goffs = sv.goffs;
+  a.cap = (uint64_t)capacity;
+  a.gpart = gpart;
+  a.last_key = last_key;
   SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_t, a, st);
+  ReduceArgs r;
+  r.didx = sv.didx, r.offs = sv.offs, r.counts = sv.counts, r.chunk_first = sv.chunk_first;
+  r.rect = proj.rect, r.n_tiles = proj.n_tiles, r.rec = proj.rec;
+  r.gpart = gpart, r.last_key = last_key;
+  r.tiles_x = p.tiles_x;
+  r.cap = (uint64_t)capacity;
+  r.g2d = g2d;
+  const int64_t rb = (capacity + kEmitChunk - 1) / kEmitChunk;
+  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)(rb > 0 ? rb : 1)), dim3(256), 0, st, r);
   return hipGetLastError();
 }
 

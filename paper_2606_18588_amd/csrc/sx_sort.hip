@@ -10,6 +10,11 @@
 //   2. instances are emitted in that depth order, so only the tile digits
 //      remain, sorted stably over the duplicated list (ceil(bits/8) passes,
 //      e.g. 2 for a 1080p frame's 8160 tiles).
+// Per-tile instance counts come from a 2D difference grid of the Gaussians'
+// tile rectangles (four atomics per visible Gaussian, then a 2D prefix sum),
+// which yields the tile ranges and the tile-digit histograms without reading
+// the instance list.  Instances are emitted by blocks that each own a fixed
+// chunk of the output (balanced however many tiles a Gaussian covers).
 // Each pass is a single "onesweep" kernel: per-partition digit ranking with
 // wavefront ballots (wave64 match), a decoupled look-back across partitions
 // for the global offsets, and an LDS reorder so that global writes are
@@ -67,7 +72,7 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s4,
 
 }  // namespace
 
-SortLayout sort_layout(int64_t n, int64_t cap) {
+SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_total) {
   SortLayout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -78,7 +83,7 @@ SortLayout sort_layout(int64_t n, int64_t cap) {
   L.nb = (n + kPreBlock - 1) / kPreBlock;
   L.dparts = (n + kSortTile - 1) / kSortTile;
   L.tparts = (cap + kSortTile - 1) / kSortTile;
-  L.eparts = (n + kSortBlock - 1) / kSortBlock;
+  L.eparts = (n + kScanTile - 1) / kScanTile;
   if (L.dparts < 1) L.dparts = 1;
   if (L.tparts < 1) L.tparts = 1;
   if (L.eparts < 1) L.eparts = 1;
@@ -90,15 +95,45 @@ SortLayout sort_layout(int64_t n, int64_t cap) {
   L.dstatus = take((size_t)4 * L.dparts * kRadixBins * 4);
   L.tstatus = take((size_t)3 * L.tparts * kRadixBins * 4);
   L.estatus = take((size_t)L.eparts * 8);
+  L.diff = take((size_t)(2 * tiles_total + 2) * 4);
   L.zero_end = off;
+  L.diffparts = take((size_t)kDiffParts * (2 * tiles_total + 2) * 4);
+  L.offs = take((size_t)(n > 0 ? n : 1) * 4);
+  L.goffs = take((size_t)(n > 0 ? n : 1) * 4);
+  L.chunk_first = take((size_t)((cap + kEmitChunk - 1) / kEmitChunk + 2) * 4);
   L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
   for (int k = 0; k < 2; ++k) L.dkey[k] = take((size_t)(n > 0 ? n : 1) * 4);
   for (int k = 0; k < 2; ++k) L.didx[k] = take((size_t)(n > 0 ? n : 1) * 4);
   for (int k = 0; k < 2; ++k) L.tkey[k] = take((size_t)(cap > 0 ? cap : 1) * 4);
   for (int k = 0; k < 2; ++k) L.tval[k] = take((size_t)(cap > 0 ? cap : 1) * 4);
-  L.tsorted = take((size_t)(cap > 0 ? cap : 1) * 4);
   L.total = off;
   return L;
+}
+
+BwdLayout bwd_layout(int64_t cap, int64_t tiles_total) {
+  BwdLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  L.gpart = take((size_t)(cap > 0 ? cap : 1) * kG2dFloats * 4);
+  L.last_key = take((size_t)(tiles_total > 0 ? tiles_total : 1) * 8);
+  L.total = off;
+  return L;
+}
+
+SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_total) {
+  const SortLayout L = sort_layout(n, capacity, tiles_total);
+  const char* b = static_cast<const char*>(ws);
+  SortView v;
+  v.counts = reinterpret_cast<const uint64_t*>(b + L.counts);
+  v.didx = reinterpret_cast<const uint32_t*>(b + L.didx[0]);
+  v.offs = reinterpret_cast<const uint32_t*>(b + L.offs);
+  v.goffs = reinterpret_cast<const uint32_t*>(b + L.goffs);
+  v.chunk_first = reinterpret_cast<const uint32_t*>(b + L.chunk_first);
+  return v;
 }
 
 // ------------------------------------------------------------- counting --
@@ -149,11 +184,17 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict
 
 // Compacted (depth bits, Gaussian index) list of visible Gaussians in index
 // order.
+// Also adds each visible Gaussian's tile rectangle to the 2D difference grid
+// diff[(tiles_y+1) x (tiles_x+1)]: +1 at (x0,y0) and (x1,y1), -1 at (x1,y0)
+// and (x0,y1); its 2D prefix sum is the number of instances per tile.
 __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restrict__ n_tiles,
-                                                       const float* __restrict__ rec, int64_t n,
+                                                       const float* __restrict__ rec,
+                                                       const uint16_t* __restrict__ rect, int64_t n,
                                                        const uint32_t* __restrict__ vis_off,
                                                        uint32_t* __restrict__ dkey,
-                                                       uint32_t* __restrict__ didx) {
+                                                       uint32_t* __restrict__ didx,
+                                                       int* __restrict__ diff, int gw,
+                                                       int use_global_diff) {
   __shared__ uint32_t sw[kPreBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   const bool v = i < n && n_tiles[i] > 0;
@@ -168,6 +209,202 @@ __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restric
     const uint32_t pos = vis_off[blockIdx.x] + pre + rank;
     dkey[pos] = __float_as_uint(rec[(size_t)i * kRecFloats + 9]);
     didx[pos] = (uint32_t)i;
+    if (use_global_diff) {
+      const ushort4 rc = reinterpret_cast<const ushort4*>(rect)[i];
+      atomicAdd(&diff[rc.y * gw + rc.x], 1);
+      atomicAdd(&diff[rc.y * gw + rc.z], -1);
+      atomicAdd(&diff[rc.w * gw + rc.x], -1);
+      atomicAdd(&diff[rc.w * gw + rc.z], 1);
+    }
+  }
+}
+
+// Difference grid without global atomics (used when the grid fits in LDS):
+// each of kDiffParts blocks accumulates a contiguous share of the visible
+// Gaussians into an LDS copy of the grid and stores it to its own slot;
+// k_tile_counts adds the slots.
+__global__ __launch_bounds__(1024) void k_tile_diff(const uint32_t* __restrict__ didx,
+                                                    const uint16_t* __restrict__ rect,
+                                                    const uint64_t* counts, int gw, int cells,
+                                                    int* __restrict__ parts) {
+  extern __shared__ int s_grid[];
+  for (int c = threadIdx.x; c < cells; c += 1024) s_grid[c] = 0;
+  __syncthreads();
+  const uint64_t nvis = counts[0];
+  const uint64_t per = (nvis + gridDim.x - 1) / gridDim.x;
+  const uint64_t beg = (uint64_t)blockIdx.x * per;
+  const uint64_t end = beg + per < nvis ? beg + per : nvis;
+  for (uint64_t i = beg + threadIdx.x; i < end; i += 1024) {
+    const ushort4 rc = reinterpret_cast<const ushort4*>(rect)[didx[i]];
+    atomicAdd(&s_grid[rc.y * gw + rc.x], 1);
+    atomicAdd(&s_grid[rc.y * gw + rc.z], -1);
+    atomicAdd(&s_grid[rc.w * gw + rc.x], -1);
+    atomicAdd(&s_grid[rc.w * gw + rc.z], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cells; c += 1024) parts[(size_t)blockIdx.x * cells + c] = s_grid[c];
+}
+
+// Sum of the per-block difference grids (one lane per grid cell).
+__global__ __launch_bounds__(256) void k_diff_sum(const int* __restrict__ parts, int nparts,
+                                                  int cells, int* __restrict__ diff) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cells) return;
+  int acc = 0;
+#pragma unroll 8
+  for (int b = 0; b < nparts; ++b) acc += parts[(size_t)b * cells + c];
+  diff[c] = acc;
+}
+
+// One block: per-tile instance counts from the difference grid, tile ranges
+// [start, end) by an exclusive scan in tile order, and the histograms of the
+// tile digits used by the radix passes.  If the instance count overflowed
+// the caller's capacity every range is left empty.
+__global__ __launch_bounds__(1024) void k_tile_counts(int* __restrict__ diff, int tiles_x,
+                                                      int tiles_y, const uint64_t* counts,
+                                                      uint32_t* __restrict__ ranges,
+                                                      uint32_t* __restrict__ thist, int npass,
+                                                      int sh0, int b0, int sh1, int b1, int sh2,
+                                                      int b2) {
+  __shared__ uint32_t h[3][kRadixBins];
+  __shared__ uint32_t s_part[1024];
+  const int tid = threadIdx.x;
+  const int gw = tiles_x + 1, gh = tiles_y;  // the last grid row is never summed
+  const int lane = tid & 63, w = tid >> 6;
+  for (int k = tid; k < 3 * kRadixBins; k += 1024) (&h[0][0])[k] = 0;
+
+  // row prefix sums: one wavefront per row, 64 columns at a time
+  for (int r = w; r < gh; r += 16) {
+    int carry = 0;
+    for (int c0 = 0; c0 < gw; c0 += 64) {
+      const int c = c0 + lane;
+      int x = c < gw ? diff[r * gw + c] : 0;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (c < gw) diff[r * gw + c] = x + carry;
+      carry += __shfl(x, 63, 64);
+    }
+  }
+  __syncthreads();
+  // column prefix sums: one lane per column, eight rows in flight
+  for (int c = tid; c < gw; c += 1024) {
+    int acc = 0;
+    for (int r0 = 0; r0 < gh; r0 += 8) {
+      int v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = r0 + k < gh ? diff[(r0 + k) * gw + c] : 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        acc += v[k];
+        if (r0 + k < gh) diff[(r0 + k) * gw + c] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  const bool over = counts[2] != 0;
+  const int T = tiles_x * tiles_y;
+  const int chunk = (T + 1023) / 1024;
+  const int beg = tid * chunk, end = beg + chunk < T ? beg + chunk : T;
+  uint32_t sum = 0;
+  for (int t = beg; t < end; ++t) sum += (uint32_t)diff[(t / tiles_x) * gw + (t % tiles_x)];
+  s_part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t v = tid >= o ? s_part[tid - o] : 0u;
+    __syncthreads();
+    s_part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = s_part[tid] - sum;
+  const int shs[3] = {sh0, sh1, sh2}, bs[3] = {b0, b1, b2};
+  for (int t = beg; t < end; ++t) {
+    const uint32_t c = (uint32_t)diff[(t / tiles_x) * gw + (t % tiles_x)];
+    ranges[2 * (size_t)t] = over ? 0u : run;
+    ranges[2 * (size_t)t + 1] = over ? 0u : run + c;
+    run += c;
+    if (c)
+      for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(t >> shs[p]) & ((1 << bs[p]) - 1)], c);
+  }
+  __syncthreads();
+  for (int k = tid; k < npass * kRadixBins; k += 1024) thist[k] = over ? 0u : (&h[0][0])[k];
+}
+
+// Exclusive scan of the tile counts of the depth-sorted visible Gaussians
+// (single pass, decoupled look-back over partitions of kScanTile).
+__global__ __launch_bounds__(kSortBlock) void k_offsets(const uint32_t* __restrict__ didx,
+                                                        const uint32_t* __restrict__ n_tiles,
+                                                        const uint64_t* counts,
+                                                        uint32_t* __restrict__ offs,
+                                                        uint32_t* __restrict__ goffs,
+                                                        uint32_t* __restrict__ chunk_first,
+                                                        uint64_t cap,
+                                                        uint64_t* status, uint32_t* part_counter,
+                                                        uint64_t* err) {
+  __shared__ uint32_t s_scan[4];
+  __shared__ uint32_t s_part;
+  __shared__ unsigned long long s_base;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_part = atomicAdd(part_counter, 1u);
+  __syncthreads();
+  const uint32_t part = s_part;
+  const uint64_t nvis = counts[0];
+  const uint64_t base_s = (uint64_t)part * kScanTile;
+  if (base_s >= nvis) return;
+  constexpr int IT = kScanTile / kSortBlock;
+  uint32_t c[IT], gi[IT];
+  uint32_t tsum = 0;
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const uint64_t sidx = base_s + (uint64_t)tid * IT + k;
+    gi[k] = sidx < nvis ? didx[sidx] : 0u;
+    c[k] = sidx < nvis ? n_tiles[gi[k]] : 0u;
+    tsum += c[k];
+  }
+  uint32_t total;
+  const uint32_t pre = block_excl_scan256(tsum, s_scan, &total);
+  if (tid == 0) {
+    uint64_t excl = 0;
+    if (part == 0) {
+      st_rel64(&status[0], kEFlagIncl | total);
+    } else {
+      st_rel64(&status[part], kEFlagAgg | total);
+      int64_t j = (int64_t)part - 1;
+      int spins = 0;
+      while (j >= 0) {
+        const uint64_t st = ld_acq64(&status[j]);
+        if ((st & ~kEValMask) == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr((unsigned long long*)err, 1ull);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += st & kEValMask;
+        if ((st & kEFlagIncl) != 0) break;
+        --j;
+      }
+      st_rel64(&status[part], kEFlagIncl | (excl + total));
+    }
+    s_base = excl;
+  }
+  __syncthreads();
+  uint32_t run = (uint32_t)s_base + pre;
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const uint64_t sidx = base_s + (uint64_t)tid * IT + k;
+    if (sidx < nvis) {
+      offs[sidx] = run;
+      goffs[gi[k]] = run;
+      // this Gaussian owns the first slot of every chunk that starts inside
+      // its instance range
+      uint64_t cb = ((uint64_t)run + kEmitChunk - 1) / kEmitChunk;
+      const uint64_t ce = (uint64_t)run + c[k];
+      for (; cb * kEmitChunk < ce && cb * kEmitChunk < cap; ++cb) chunk_first[cb] = (uint32_t)sidx;
+    }
+    run += c[k];
   }
 }
 
@@ -198,6 +435,81 @@ __global__ __launch_bounds__(kSortBlock) void k_hist_depth(const uint32_t* __res
 }
 
 // ------------------------------------------------------------- onesweep --
+// Instance emission in depth order: a Gaussian's tiles, row-major over its
+// rectangle, occupy slots [offs[s], offs[s] + n_tiles) of the emission order.
+struct EmitArgs {
+  const uint32_t* __restrict__ didx;  // depth-sorted visible Gaussians
+  const uint32_t* __restrict__ offs;  // exclusive instance offsets
+  const uint32_t* __restrict__ chunk_first;  // owner of each chunk's first slot
+  const uint64_t* counts;
+  const uint16_t* __restrict__ rect;
+  int tiles_x;
+  uint32_t tile_base;
+  uint64_t cap;
+  uint32_t* __restrict__ tkey;
+  uint32_t* __restrict__ tval;
+};
+
+// Enumerate emission slots [c0, c1) as (tile id, Gaussian index) pairs into
+// out_key/out_val[k - c0]: find the depth-sorted Gaussians covering the
+// slots by binary search over the offsets, stage windows of 256 of them in
+// LDS, and map each slot to its Gaussian and tile.  Called by every thread
+// of a 256-thread block.
+__device__ __forceinline__ void emit_range(const EmitArgs& a, uint64_t c0, uint64_t c1,
+                                           uint32_t* out_key, uint32_t* out_val,
+                                           uint32_t* s_off, uint32_t* s_g, uint32_t* s_x0,
+                                           uint32_t* s_y0, uint32_t* s_w, uint32_t* s_lohi) {
+  const int tid = threadIdx.x;
+  const uint64_t nvis = a.counts[0];
+  const uint64_t ninst = a.counts[1];
+  if (tid == 0) chunk_bounds(a.chunk_first, a.offs, nvis, ninst, c0, c1, s_lohi);
+  __syncthreads();
+  const uint32_t slo = s_lohi[0], shi = s_lohi[1];
+  for (uint32_t w0 = slo; w0 <= shi; w0 += kSortBlock) {
+    const uint32_t wn = (shi - w0 + 1) < (uint32_t)kSortBlock ? (shi - w0 + 1) : (uint32_t)kSortBlock;
+    if ((uint32_t)tid < wn) {
+      const uint32_t sidx = w0 + tid;
+      const uint32_t g = a.didx[sidx];
+      const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[g];
+      s_off[tid] = a.offs[sidx];
+      s_g[tid] = g;
+      s_x0[tid] = rc.x, s_y0[tid] = rc.y, s_w[tid] = (uint32_t)rc.z - rc.x;
+    }
+    if (tid == 0) {
+      const uint64_t e = (uint64_t)w0 + wn < nvis ? (uint64_t)a.offs[w0 + wn] : ninst;
+      s_off[wn] = (uint32_t)(e < c1 ? e : c1);
+    }
+    __syncthreads();
+    const uint64_t k0 = (uint64_t)s_off[0] > c0 ? (uint64_t)s_off[0] : c0;
+    const uint64_t k1 = s_off[wn];
+    // each thread takes a run of consecutive slots (odd length, so the LDS
+    // writes of a wavefront fall in distinct banks); one search and one
+    // division per run, then the tile index advances row-major
+    const uint32_t run = ((uint32_t)(k1 - k0) + kSortBlock - 1) / kSortBlock | 1u;
+    uint64_t k = k0 + (uint64_t)tid * run;
+    const uint64_t kend = k + run < k1 ? k + run : k1;
+    if (k < kend) {
+      int j = 0, hi = (int)wn - 1;  // largest j with s_off[j] <= k
+      while (j < hi) {
+        const int mid = (j + hi + 1) >> 1;
+        if (s_off[mid] <= k) j = mid; else hi = mid - 1;
+      }
+      uint32_t wj = s_w[j];
+      const uint32_t r = (uint32_t)(k - s_off[j]);
+      uint32_t ty = r / wj, tx = r - ty * wj;
+      for (; k < kend; ++k) {
+        if (k == s_off[j + 1]) {
+          ++j;
+          wj = s_w[j], tx = 0, ty = 0;
+        }
+        out_key[k - c0] = a.tile_base + (s_y0[j] + ty) * (uint32_t)a.tiles_x + s_x0[j] + tx;
+        out_val[k - c0] = s_g[j];
+        if (++tx == wj) tx = 0, ++ty;
+      }
+    }
+    __syncthreads();
+  }
+}
 struct SweepArgs {
   const uint32_t* __restrict__ keys_in;
   const uint32_t* __restrict__ vals_in;
@@ -205,6 +517,7 @@ struct SweepArgs {
   uint32_t* __restrict__ vals_out;
   const uint64_t* count;
   uint64_t cap;
+  const uint64_t* skip;  // if non-null and *skip != 0, the pass sorts nothing
   int shift, bits;
   const uint32_t* __restrict__ hist;
   uint32_t* status;
@@ -214,34 +527,56 @@ struct SweepArgs {
   const float* __restrict__ rec;
 };
 
-__global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
+// FROM_EMIT: the pass reads no input array; each partition enumerates its
+// kSortTile emission slots itself (fusing the emission into the first tile
+// pass).
+template <bool FROM_EMIT>
+__global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a, EmitArgs em) {
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ uint32_t s_vals[kSortTile];
-  __shared__ uint32_t s_wh[4][kRadixBins];
-  __shared__ uint32_t s_dst[kRadixBins];
-  __shared__ uint32_t s_loc[kRadixBins];
+  // per-wave digit counters, then destinations and local offsets; the emit
+  // staging arrays of the fused pass live in the same words before ranking
+  __shared__ uint32_t s_aux[6 * kRadixBins + 8];
+  uint32_t(*s_wh)[kRadixBins] = reinterpret_cast<uint32_t(*)[kRadixBins]>(s_aux);
+  uint32_t* s_dst = s_aux + 4 * kRadixBins;
+  uint32_t* s_loc = s_aux + 5 * kRadixBins;
   __shared__ uint32_t s_scan[4];
   __shared__ uint32_t s_part;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   uint64_t n64 = *a.count;
   if (n64 > a.cap) n64 = a.cap;
+  if (a.skip && *a.skip != 0) n64 = 0;
   const uint32_t n = (uint32_t)n64;
   if (tid == 0) s_part = atomicAdd(a.part_counter, 1u);
-  for (int k = tid; k < 4 * kRadixBins; k += kSortBlock) (&s_wh[0][0])[k] = 0;
   __syncthreads();
   const uint32_t part = s_part;
   const uint64_t base = (uint64_t)part * kSortTile;
   if (base >= n) return;
   const uint32_t tile_n = (n - base) < (uint64_t)kSortTile ? (uint32_t)(n - base) : (uint32_t)kSortTile;
   const uint32_t dmask = (1u << a.bits) - 1u;
+  if (FROM_EMIT)  // ends with a barrier, after which the staging words are free
+    emit_range(em, base, base + tile_n, s_keys, s_vals, s_aux, s_aux + 257, s_aux + 513,
+               s_aux + 769, s_aux + 1025, s_aux + 1281);
+  for (int k = tid; k < 4 * kRadixBins; k += kSortBlock) s_aux[k] = 0;
+  __syncthreads();
 
   uint32_t k[kSortItems], v[kSortItems], rk[kSortItems], dg[kSortItems];
+  if (FROM_EMIT) {
 #pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
-    const uint32_t idx = (uint32_t)w * (kSortTile / 4) + it * 64 + lane;
-    const bool valid = idx < tile_n;
-    k[it] = valid ? a.keys_in[base + idx] : 0u;
-    v[it] = valid ? a.vals_in[base + idx] : 0u;
+    for (int it = 0; it < kSortItems; ++it) {
+      const uint32_t idx = (uint32_t)w * (kSortTile / 4) + it * 64 + lane;
+      const bool valid = idx < tile_n;
+      k[it] = valid ? s_keys[idx] : 0u;
+      v[it] = valid ? s_vals[idx] : 0u;
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+      const uint32_t idx = (uint32_t)w * (kSortTile / 4) + it * 64 + lane;
+      const bool valid = idx < tile_n;
+      k[it] = valid ? a.keys_in[base + idx] : 0u;
+      v[it] = valid ? a.vals_in[base + idx] : 0u;
+    }
   }
   const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
@@ -322,123 +657,6 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
   }
 }
 
-// ----------------------------------------------------------------- emit --
-struct EmitArgs {
-  const uint32_t* __restrict__ didx;  // depth-sorted visible Gaussians
-  const uint64_t* counts;
-  const uint32_t* __restrict__ n_tiles;
-  const uint16_t* __restrict__ rect;
-  int tiles_x;
-  uint32_t tile_base;
-  uint64_t cap;
-  uint32_t* __restrict__ tkey;
-  uint32_t* __restrict__ tval;
-  uint32_t* __restrict__ thist;  // [3][256]
-  int npass;
-  int shift[3], bits[3];
-  uint64_t* status;
-  uint32_t* part_counter;
-  uint64_t* err;
-};
-
-__global__ __launch_bounds__(kSortBlock) void k_emit(EmitArgs a) {
-  __shared__ uint32_t s_off[kSortBlock + 1];
-  __shared__ uint32_t s_g[kSortBlock];
-  __shared__ uint32_t s_x0[kSortBlock], s_y0[kSortBlock], s_w[kSortBlock];
-  __shared__ uint32_t s_h[3][kRadixBins];
-  __shared__ uint32_t s_scan[4];
-  __shared__ uint32_t s_part;
-  __shared__ unsigned long long s_base;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_part = atomicAdd(a.part_counter, 1u);
-  for (int k = tid; k < 3 * kRadixBins; k += kSortBlock) (&s_h[0][0])[k] = 0;
-  __syncthreads();
-  const uint32_t part = s_part;
-  const uint64_t nvis = a.counts[0];
-  const uint64_t s = (uint64_t)part * kSortBlock + tid;
-  if ((uint64_t)part * kSortBlock >= nvis) return;
-  uint32_t g = 0, cnt = 0, x0 = 0, y0 = 0, wd = 1;
-  if (s < nvis) {
-    g = a.didx[s];
-    cnt = a.n_tiles[g];
-    const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[g];
-    x0 = rc.x, y0 = rc.y, wd = (uint32_t)rc.z - rc.x;
-  }
-  uint32_t total;
-  const uint32_t off = block_excl_scan256(cnt, s_scan, &total);
-  s_off[tid] = off, s_g[tid] = g, s_x0[tid] = x0, s_y0[tid] = y0, s_w[tid] = wd;
-  if (tid == 0) {
-    s_off[kSortBlock] = total;
-    uint64_t excl = 0;
-    if (part == 0) {
-      st_rel64(&a.status[0], kEFlagIncl | total);
-    } else {
-      st_rel64(&a.status[part], kEFlagAgg | total);
-      int64_t j = (int64_t)part - 1;
-      int spins = 0;
-      while (j >= 0) {
-        const uint64_t st = ld_acq64(&a.status[j]);
-        if ((st & ~kEValMask) == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr((unsigned long long*)a.err, 1ull);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += st & kEValMask;
-        if ((st & kEFlagIncl) != 0) break;
-        --j;
-      }
-      st_rel64(&a.status[part], kEFlagIncl | (excl + total));
-    }
-    s_base = excl;
-  }
-  __syncthreads();
-  const uint64_t base = s_base;
-  for (uint32_t k = tid; k < total; k += kSortBlock) {
-    int lo = 0, hi = kSortBlock - 1;  // largest j with s_off[j] <= k
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= k)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const uint32_t r = k - s_off[lo];
-    const uint32_t wj = s_w[lo];
-    const uint32_t ty = r / wj, tx = r - ty * wj;
-    const uint32_t tile = a.tile_base + (s_y0[lo] + ty) * (uint32_t)a.tiles_x + s_x0[lo] + tx;
-    const uint64_t pos = base + k;
-    if (pos < a.cap) {
-      a.tkey[pos] = tile;
-      a.tval[pos] = s_g[lo];
-      for (int p = 0; p < a.npass; ++p)
-        atomicAdd(&s_h[p][(tile >> a.shift[p]) & ((1u << a.bits[p]) - 1u)], 1u);
-    }
-  }
-  __syncthreads();
-  for (int k = tid; k < a.npass * kRadixBins; k += kSortBlock) {
-    const uint32_t c = (&s_h[0][0])[k];
-    if (c) atomicAdd(&a.thist[k], c);
-  }
-}
-
-// --------------------------------------------------------------- ranges --
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tiles,
-                                                const uint64_t* counts, uint64_t cap,
-                                                uint32_t tiles_total,
-                                                uint32_t* __restrict__ ranges) {
-  uint64_t n = counts[1];
-  if (n > cap) n = cap;
-  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t t = tiles[i];
-  if (t >= tiles_total) return;
-  if (i == 0 || tiles[i - 1] != t) ranges[2 * (size_t)t] = (uint32_t)i;
-  if (i + 1 == n || tiles[i + 1] != t) ranges[2 * (size_t)t + 1] = (uint32_t)(i + 1);
-}
-
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * 256 * 4;
   for (uint64_t i = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 4; i < n; i += stride) {
@@ -470,13 +688,13 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
                        uint64_t* h_counts, bool* over_capacity,
                        hipStream_t st) {
   *over_capacity = false;
-  const SortLayout L = sort_layout(n, capacity);
+  const SortLayout L = sort_layout(n, capacity, tiles_total);
   hipError_t e;
   auto u32 = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   uint64_t* counts = reinterpret_cast<uint64_t*>(ws + L.counts);
   if ((e = launch_fill(u32(L.zero_begin), (int64_t)((L.zero_end - L.zero_begin) / 4), 0, st))) return e;
-  if ((e = launch_fill(ranges, tiles_total * 2, 0, st))) return e;
   if (n == 0) {
+    if ((e = launch_fill(ranges, tiles_total * 2, 0, st))) return e;
     if (h_counts) h_counts[0] = h_counts[1] = 0;
     return hipSuccess;
   }
@@ -494,8 +712,35 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
       return hipSuccess;
     }
   }
+  const int gw = p.tiles_x + 1;
+  const int cells = gw * (p.tiles_y + 1);
+  const bool lds_diff = cells <= kDiffMaxCells;
+  int* diff = reinterpret_cast<int*>(ws + L.diff);
+  int* dparts = reinterpret_cast<int*>(ws + L.diffparts);
   hipLaunchKernelGGL(k_compact, dim3((unsigned)L.nb), dim3(kPreBlock), 0, st, proj.n_tiles,
-                     proj.rec, n, u32(L.vis_off), u32(L.dkey[0]), u32(L.didx[0]));
+                     proj.rec, proj.rect, n, u32(L.vis_off), u32(L.dkey[0]), u32(L.didx[0]),
+                     diff, gw, lds_diff ? 0 : 1);
+  if (lds_diff) {
+    hipLaunchKernelGGL(k_tile_diff, dim3(kDiffParts), dim3(1024), (size_t)cells * 4, st,
+                       u32(L.didx[0]), proj.rect, counts, gw, cells, dparts);
+    hipLaunchKernelGGL(k_diff_sum, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
+                       (const int*)dparts, kDiffParts, cells, diff);
+  }
+  // tile digits: ceil(bits/8) balanced passes
+  const int tbits = bit_width((uint64_t)tiles_total);
+  const int npass = (tbits + 7) / 8;
+  int shs[3] = {0, 0, 0}, bs[3] = {1, 1, 1};
+  {
+    int sh = 0;
+    for (int k = 0; k < npass; ++k) {
+      bs[k] = tbits / npass + (k < tbits % npass ? 1 : 0);
+      shs[k] = sh;
+      sh += bs[k];
+    }
+  }
+  hipLaunchKernelGGL(k_tile_counts, dim3(1), dim3(1024), 0, st, diff, p.tiles_x, p.tiles_y,
+                     counts, ranges, u32(L.thist), npass, shs[0], bs[0], shs[1], bs[1], shs[2],
+                     bs[2]);
   hipLaunchKernelGGL(k_hist_depth, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st,
                      u32(L.dkey[0]), counts, u32(L.dhist));
   uint32_t* counters = u32(L.counters);
@@ -509,64 +754,52 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     a.vals_out = u32(L.didx[(ps + 1) & 1]);
     a.count = counts;
     a.cap = (uint64_t)n;
+    a.skip = nullptr;
     a.shift = 8 * ps;
     a.bits = ps == 3 ? 7 : 8;
     a.hist = u32(L.dhist) + ps * kRadixBins;
     a.status = u32(L.dstatus) + (size_t)ps * L.dparts * kRadixBins;
     a.part_counter = counters + ps;
     a.err = err;
-    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st, a);
+    hipLaunchKernelGGL(k_onesweep<false>, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st, a,
+                       EmitArgs{});
   }
-  // tile digits
-  const int tbits = bit_width((uint64_t)tiles_total);
-  const int npass = (tbits + 7) / 8;
+  hipLaunchKernelGGL(k_offsets, dim3((unsigned)L.eparts), dim3(kSortBlock), 0, st,
+                     u32(L.didx[0]), proj.n_tiles, counts, u32(L.offs), u32(L.goffs),
+                     u32(L.chunk_first), (uint64_t)capacity,
+                     reinterpret_cast<uint64_t*>(ws + L.estatus), counters + 4, err);
   EmitArgs em{};
   em.didx = u32(L.didx[0]);
+  em.offs = u32(L.offs);
+  em.chunk_first = u32(L.chunk_first);
   em.counts = counts;
-  em.n_tiles = proj.n_tiles;
   em.rect = proj.rect;
   em.tiles_x = p.tiles_x;
   em.tile_base = 0;
-  em.cap = (uint64_t)capacity;
-  em.tkey = u32(L.tkey[0]);
-  em.tval = u32(L.tval[0]);
-  em.thist = u32(L.thist);
-  em.npass = npass;
-  {
-    int sh = 0;
-    for (int k = 0; k < npass; ++k) {
-      const int b = tbits / npass + (k < tbits % npass ? 1 : 0);
-      em.shift[k] = sh;
-      em.bits[k] = b;
-      sh += b;
-    }
-  }
-  em.status = reinterpret_cast<uint64_t*>(ws + L.estatus);
-  em.part_counter = counters + 4;
-  em.err = err;
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)L.eparts), dim3(kSortBlock), 0, st, em);
   for (int ps = 0; ps < npass; ++ps) {
     const bool last = ps == npass - 1;
     SweepArgs a{};
     a.keys_in = u32(L.tkey[ps & 1]);
     a.vals_in = u32(L.tval[ps & 1]);
-    a.keys_out = last ? u32(L.tsorted) : u32(L.tkey[(ps + 1) & 1]);
+    a.keys_out = last ? nullptr : u32(L.tkey[(ps + 1) & 1]);
     a.vals_out = last ? vals : u32(L.tval[(ps + 1) & 1]);
     a.count = counts + 1;
     a.cap = (uint64_t)capacity;
-    a.shift = em.shift[ps];
-    a.bits = em.bits[ps];
+    a.skip = counts + 2;
+    a.shift = shs[ps];
+    a.bits = bs[ps];
     a.hist = u32(L.thist) + ps * kRadixBins;
     a.status = u32(L.tstatus) + (size_t)ps * L.tparts * kRadixBins;
     a.part_counter = counters + 5 + ps;
     a.err = err;
     a.keys64_out = last ? keys : nullptr;
     a.rec = proj.rec;
-    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)L.tparts), dim3(kSortBlock), 0, st, a);
+    if (ps == 0)
+      hipLaunchKernelGGL(k_onesweep<true>, dim3((unsigned)L.tparts), dim3(kSortBlock), 0, st, a, em);
+    else
+      hipLaunchKernelGGL(k_onesweep<false>, dim3((unsigned)L.tparts), dim3(kSortBlock), 0, st, a,
+                         em);
   }
-  const int64_t rb = (capacity + 255) / 256;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)(rb > 0 ? rb : 1)), dim3(256), 0, st,
-                     u32(L.tsorted), counts, (uint64_t)capacity, (uint32_t)tiles_total, ranges);
   return hipGetLastError();
 }
 

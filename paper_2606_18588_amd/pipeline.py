@@ -111,6 +111,7 @@ class CellView:
                      if self.keep_keys else None)
         nbytes = B.sx_sort_workspace_size(self.params.n, self.capacity, self.tiles)
         self.ws = torch.empty((nbytes,), dtype=torch.uint8, device=self.device)
+        self.bwd_ws = None
 
     # ---------------------------------------------------------------- steps
     def preprocess(self):
@@ -153,17 +154,20 @@ class CellView:
                                    device=self.device)
             self.dpartial = torch.empty((self.H, self.W, 4), dtype=torch.float32,
                                         device=self.device)
+        if self.bwd_ws is None:
+            nb = B.sx_backward_workspace_size(self.capacity, self.tiles)
+            self.bwd_ws = torch.empty((nb,), dtype=torch.uint8, device=self.device)
 
     def render_backward(self, dpartial, ddepth=None):
         self.ensure_backward_buffers()
-        B.sx_render_backward(self.c_proj, self.vals, self.ranges, self.params.n, self.c_cam,
-                             self.c_par, self.mask, self.partial, self.last, dpartial, ddepth,
-                             self.g2d)
+        B.sx_render_backward(self.c_proj, self.vals, self.ranges, self.ws, self.params.n,
+                             self.capacity, self.bwd_ws, self.c_cam, self.c_par, self.mask,
+                             self.partial, self.last, dpartial, ddepth, self.g2d)
         return self.g2d
 
     def preprocess_backward(self, grads: GaussianParams, accumulate=False):
-        B.sx_preprocess_backward(self.c_g, self.c_cam, self.c_par, self.c_proj, self.g2d,
-                                 grads.grad_struct(),
+        B.sx_preprocess_backward(self.c_g, self.c_cam, self.c_par, self.c_proj, self.ws,
+                                 self.capacity, self.g2d, grads.grad_struct(),
                                  B.SX_BWD_ACCUMULATE if accumulate else 0)
 
     def state(self, grads: GaussianParams) -> B.SxCellState:
@@ -175,6 +179,9 @@ class CellView:
         s.proj = ctypes_pointer(self.c_proj)
         s.vals = B.ptr(self.vals)
         s.ranges = B.ptr(self.ranges)
+        s.sort_ws = B.ptr(self.ws)
+        s.capacity = self.capacity
+        s.bwd_ws = B.ptr(self.bwd_ws)
         s.partial = B.ptr(self.partial)
         s.last = B.ptr(self.last)
         s.mask = B.ptr(self.mask) if self.mask is not None else None

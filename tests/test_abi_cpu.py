@@ -1,0 +1,146 @@
+"""CPU-only checks of the C ABI: the library loads, exports every entry point
+include/splaxel.h declares, answers size queries, and rejects invalid
+arguments on the host (SX_EINVAL) before anything reaches a device.  No
+compute call is made (there is no GPU here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "splaxel.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_18588_amd import binding as B
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2606_18588_amd import build
+        build.build(verbose=False)
+    return B.lib()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path_calls():
+    names = declared_symbols()
+    for n in ("sx_preprocess", "sx_sort", "sx_render_partial", "sx_composite", "sx_backward"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", L._name], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\b(sx_[a-z0-9_]+)\b", out))
+    missing = [n for n in declared_symbols() if n not in exported]
+    assert not missing, missing
+    for n in declared_symbols():
+        getattr(L, n)
+
+
+def test_library_is_built_for_gfx950(L):
+    out = subprocess.run(["strings", L._name], capture_output=True, text=True).stdout
+    assert "gfx950" in out
+
+
+def test_version(L):
+    from paper_2606_18588_amd import binding as B
+    assert "gfx950" in B.sx_version()
+
+
+def test_size_queries(L):
+    from paper_2606_18588_amd import binding as B
+    assert B.sx_preprocess_blocks(0) == 1
+    assert B.sx_preprocess_blocks(257) == 2
+    a = B.sx_sort_workspace_size(1000, 5000, 64)
+    b = B.sx_sort_workspace_size(1000, 50000, 64)
+    assert 0 < a < b
+    c = B.sx_backward_workspace_size(5000, 64)
+    assert c >= 5000 * 48
+    with pytest.raises(B.SplaxelError) as e:
+        B.sx_sort_workspace_size(-1, 10, 4)
+    assert e.value.code == B.SX_EINVAL
+    with pytest.raises(B.SplaxelError):
+        B.sx_sort_workspace_size(10, 1 << 30, 4)
+
+
+def _cam(B):
+    import synth
+    return B.camera(synth.tiny_camera())
+
+
+def test_invalid_arguments_are_rejected_on_host(L):
+    from paper_2606_18588_amd import binding as B
+    import synth
+    cam = _cam(B)
+    good = B.params(synth.RenderSettings(), 0)
+    g = B.SxGaussians()
+    g.n = 10  # null arrays with n > 0
+    out = B.SxProjected()
+    assert L.sx_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(good),
+                           ctypes.byref(out), None) == B.SX_EINVAL
+    assert b"null" in L.sx_last_error_string()
+    g.n = 0
+    bad_tile = B.params(synth.RenderSettings(tile_w=12), 0)
+    assert L.sx_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(bad_tile),
+                           ctypes.byref(out), None) == B.SX_EINVAL
+    bad_sh = B.params(synth.RenderSettings(), 4)
+    assert L.sx_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(bad_sh),
+                           ctypes.byref(out), None) == B.SX_EINVAL
+    bad_alpha = B.params(synth.RenderSettings(alpha_min=0.5, alpha_max=0.4), 0)
+    assert L.sx_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(bad_alpha),
+                           ctypes.byref(out), None) == B.SX_EINVAL
+    bad_cam = B.camera(synth.tiny_camera())
+    bad_cam.width = 0
+    assert L.sx_preprocess(ctypes.byref(g), ctypes.byref(bad_cam), ctypes.byref(good),
+                           ctypes.byref(out), None) == B.SX_EINVAL
+    # composite: K out of range, empty box
+    parts = (ctypes.c_void_p * 1)(1)
+    cells = (B.SxCell * 1)()
+    assert L.sx_composite(ctypes.c_int32(0), parts, cells, ctypes.byref(cam),
+                          ctypes.byref(good), ctypes.c_void_p(1), None, None) == B.SX_EINVAL
+    assert L.sx_composite(ctypes.c_int32(17), parts, cells, ctypes.byref(cam),
+                          ctypes.byref(good), ctypes.c_void_p(1), None, None) == B.SX_EINVAL
+    cells[0].lo[0], cells[0].hi[0] = 1.0, 0.0
+    assert L.sx_composite(ctypes.c_int32(1), parts, cells, ctypes.byref(cam),
+                          ctypes.byref(good), ctypes.c_void_p(1), None, None) == B.SX_EINVAL
+    # sort: undersized workspace
+    proj = B.SxProjected()
+    proj.rec = proj.rect = proj.n_tiles = proj.block_sums = ctypes.c_void_p(1)
+    assert L.sx_sort(ctypes.byref(proj), ctypes.c_int64(10), ctypes.byref(cam),
+                     ctypes.byref(good), ctypes.c_int64(100), None, ctypes.c_void_p(1),
+                     ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_size_t(16), None,
+                     None) == B.SX_EINVAL
+    assert b"workspace" in L.sx_last_error_string()
+    # adam: step must be >= 1
+    assert L.sx_adam(ctypes.c_int64(4), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                     ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_int32(0),
+                     ctypes.c_float(1e-3), ctypes.c_float(0.9), ctypes.c_float(0.999),
+                     ctypes.c_float(1e-8), None) == B.SX_EINVAL
+    # backward: K out of range
+    assert L.sx_backward(ctypes.c_int32(0), None, None, ctypes.byref(cam), ctypes.byref(good),
+                         None, ctypes.c_int32(0), None) == B.SX_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_2606_18588_amd import binding as B
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", os.path.join(ROOT, "does_not_exist.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        B.lib()
+
+
+def test_product_path_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2606_18588_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", src, re.M), f
+                assert "splat_oracle" not in src, f
