@@ -137,6 +137,13 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a plain "
                          "copy of known size that calibrates PMC traffic counters)")
+    ap.add_argument("--form", choices=("plain", "batched", "serve"), default="plain",
+                    help="plain: the headline single-view step; batched: 16-view training "
+                         "step (15M Gaussians) batched vs per-view; serve: request trace "
+                         "(30M Gaussians) served batched vs per-view")
+    ap.add_argument("--requests", type=int, default=800,
+                    help="serve: measured requests (after 200 warm-up requests)")
+    ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -145,6 +152,10 @@ def main():
     import torch
     import synth
     torch.cuda.set_device(0)
+    if args.form == "batched":
+        return bench_batched(args)
+    if args.form == "serve":
+        return bench_serve(args)
     tw, th = (int(x) for x in args.tile.split("x"))
     settings = synth.RenderSettings(tile_w=tw, tile_h=th)
     t0 = time.perf_counter()
@@ -211,6 +222,125 @@ def main():
         t0 = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(scene, cam, settings)
         log(f"bench: cpu baseline {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(line), flush=True)
+
+
+def bench_batched(args):
+    """16 views of uneven resolution of a 15M-Gaussian scene: one training
+    step = every view's forward, L1 against its target, backward, then one
+    Adam update.  Batched (autotuned tile shape and views per persistent
+    launch) against the plain per-view calls."""
+    import torch
+    import synth
+    from paper_2606_18588_amd.batched import MultiViewStep, autotune, time_step
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    t0 = time.perf_counter()
+    scene = synth.g15_scene()
+    cams = synth.g15_cameras()
+    params = GaussianParams.from_scene(scene)
+    del scene
+    grads = params.zeros_like()
+    targets = [torch.as_tensor(synth.random_image(300 + k, c.width, c.height)).cuda()
+               for k, c in enumerate(cams)]
+    log(f"bench: 15M scene + 16 views ready in {time.perf_counter() - t0:.1f}s")
+
+    def settings(tw, th):
+        return synth.RenderSettings(tile_w=tw, tile_h=th)
+    tuned = []
+    if args.no_tune:
+        tw, th = (int(x) for x in args.tile.split("x"))
+        best_tile, best_batch = args.tile, 16
+    else:
+        tuned = autotune(params, grads, cams, targets, settings, log=log)
+        best_tile, best_batch = tuned[0].tile, tuned[0].batch
+    tw, th = (int(x) for x in best_tile.split("x"))
+    step = MultiViewStep(params, grads, cams, targets, settings(tw, th), batch=best_batch)
+    blends = step.run(1e-7, count_blends=True, check=True)
+    inst = sum(c[1] for c in step.counts)
+    ms_b = time_step(step, reps=args.steps, warmup=args.warmup)
+    step.run(1e-7, check=True)
+    del step
+    torch.cuda.empty_cache()
+    plain = MultiViewStep(params, grads, cams, targets, settings(16, 16), plain=True)
+    plain.run(1e-7, check=True)
+    ms_p = time_step(plain, reps=args.steps, warmup=args.warmup)
+    plain.run(1e-7, check=True)
+    del plain
+    V = len(cams)
+    line = {
+        "metric": "views/s, 16-view training step (fwd+bwd+Adam)", "value": V / (ms_b / 1e3),
+        "unit": "views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "15M Gaussians SH3 on a 1 km^2 ground plane, 16 views of "
+                               "uneven resolution (960x540..2048x1365) on a 200 m orbit, "
+                               "L1 fwd+bwd per view, one Adam update",
+                   "gaussians": params.n, "views": V, "tile": best_tile, "batch": best_batch,
+                   "pixels": int(sum(c.width * c.height for c in cams))},
+        "plain_views_per_s": V / (ms_p / 1e3), "plain_ms_per_step": ms_p,
+        "speedup_vs_plain": ms_p / ms_b, "blends_per_step": blends,
+        "blends_per_s": blends / (ms_b / 1e3), "instances_per_step": inst,
+        "autotune": [{"tile": r.tile, "batch": r.batch, "ms": r.ms} for r in tuned],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Poisson request trace (200 req/s, resolutions 640x360..3840x2160) on a
+    resident 30M-Gaussian scene: continuous batching against plain per-view
+    service, open loop (latency) and closed loop (max frames/s)."""
+    import torch
+    import synth
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    from paper_2606_18588_amd.serve import Server, summarize
+    t0 = time.perf_counter()
+    scene = synth.g30_scene()
+    params = GaussianParams.from_scene(scene)
+    del scene
+    warm_n = 200
+    trace = synth.serve_trace(warm_n + args.requests)
+    log(f"bench: 30M scene + {len(trace)} requests ready in {time.perf_counter() - t0:.1f}s")
+    st = synth.RenderSettings()
+
+    def rebase(reqs):
+        a0 = reqs[0].arrival_s
+        return [synth.Request(r.arrival_s - a0, r.camera, r.rid) for r in reqs]
+    res = {}
+    for mode in ("batched", "plain"):
+        srv = Server(params, st, plain=(mode == "plain"), arena_bytes=40 << 30)
+        srv.calibrate(trace[0].camera)
+        srv.serve(rebase(trace[:warm_n]), open_loop=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        done = srv.serve(rebase(trace[warm_n:]), open_loop=True)
+        open_s = summarize(done)
+        log(f"bench: serve {mode} open loop {open_s} in {time.perf_counter() - t1:.1f}s")
+        t1 = time.perf_counter()
+        done = srv.serve(rebase(trace[warm_n:]), open_loop=False)
+        closed_wall = time.perf_counter() - t1
+        closed = summarize(done, wall_s=max(d.done_s for d in done))
+        log(f"bench: serve {mode} closed loop {closed['frames_per_s']:.1f} frames/s")
+        res[mode] = {"open_loop": open_s, "closed_loop_frames_per_s": closed["frames_per_s"],
+                     "batches": srv.n_batches, "overflows": srv.overflows}
+        del srv
+        torch.cuda.empty_cache()
+    b, p = res["batched"], res["plain"]
+    line = {
+        "metric": "serve p50 latency ms", "value": b["open_loop"]["p50_ms"], "unit": "ms",
+        "n_gpus": 1, "steps": args.requests, "warmup": warm_n,
+        "ms_per_step": b["open_loop"]["mean_ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "resident 30M Gaussians SH3 on a 2 km x 2 km ground plane, "
+                               "Poisson 200 req/s, resolutions uniform over 640x360, "
+                               "1280x720, 1920x1080, 3840x2160, forward render + composition",
+                   "gaussians": params.n, "requests": args.requests},
+        "p99_ms": b["open_loop"]["p99_ms"], "frames_per_s": b["open_loop"]["frames_per_s"],
+        "closed_loop_frames_per_s": b["closed_loop_frames_per_s"],
+        "plain": p,
+        "speedup_closed_loop_vs_plain": b["closed_loop_frames_per_s"] /
+        p["closed_loop_frames_per_s"],
+        "batched": b,
+    }
     print(json.dumps(line), flush=True)
 
 

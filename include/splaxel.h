@@ -137,24 +137,34 @@ sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
                         sx_stream stream);
 
 /* ------------------------------------------------------------- a2-a4 --
- * Depth sort (paper, background: sorting step) as a radix sort of 64-bit
- * keys  key = tile_id << 32 | bits(float32 depth)  with ties by Gaussian
- * index, done as two LSD phases: the low (depth) digits on the visible
- * Gaussians before duplication, then the tile digits on the duplicated
- * instances.  Produces vals[i] = Gaussian index of the i-th instance,
- * optionally keys[i], and tile_ranges[t] = [start, end) per tile
+ * Depth sort (paper, background: sorting step): the result of a stable
+ * sort of the 64-bit keys  key = tile_id << 32 | bits(float32 depth)  with
+ * ties by Gaussian index.  The depth digits are radix sorted on the visible
+ * Gaussians before duplication; the depth-ordered list is then split by
+ * tile through a hierarchy of 4 x 4 bins, each level keeping the order.
+ * Produces vals[i] = Gaussian index of the i-th instance, optionally
+ * keys[i], and tile_ranges[t] = [start, end) per tile
  * (tile_id = ty * tiles_x + tx; an empty tile has start == end).
  *   capacity   instances the caller allocated in keys/vals.
- *   ws         workspace of sx_sort_workspace_size(n, capacity, tiles).
+ *   ws         workspace of sx_sort_workspace_size(n, capacity, tiles_x,
+ *              tiles_y) for this view's tile grid.
  *   h_counts   HOST uint64[2] or NULL.  If non-NULL the call synchronises
  *              the stream once after counting, writes {visible,
  *              instances} and returns SX_ECAPACITY (with nothing sorted)
  *              when instances > capacity.  If NULL the call is fully
  *              asynchronous; an overflow sorts only the first `capacity`
  *              instances and raises a flag read by sx_sort_counts().
+ * The workspace begins with uint64 {visible, instances, overflow, error}
+ * (32 bytes, valid once the call's work has completed), so a caller may
+ * also copy them to pinned host memory asynchronously.
  * keys may be NULL. */
+/* Bytes of the sort workspace for n Gaussians, `capacity` instances and a
+ * tiles_x x tiles_y grid: about 24 bytes per Gaussian plus 4 bytes per
+ * instance (8 once the grid is wider or taller than 16 tiles) for the lists
+ * of the tile binning. */
 sx_status sx_sort_workspace_size(int64_t n, int64_t capacity,
-                                 int64_t tiles_total, size_t* bytes);
+                                 int32_t tiles_x, int32_t tiles_y,
+                                 size_t* bytes);
 sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
                   const sx_params* p, int64_t capacity, uint64_t* keys,
                   uint32_t* vals, uint32_t* tile_ranges, void* ws,
@@ -298,6 +308,63 @@ sx_status sx_adam(int64_t n, float* param, const float* grad, float* m,
 /* Fill n uint32 words with a value (kernel, safe inside graph capture). */
 sx_status sx_fill_u32(uint32_t* ptr, int64_t n, uint32_t value,
                       sx_stream stream);
+
+/* ----------------------------------------------------------------- a11 --
+ * Batched views.  The paper spreads the views of a training batch over
+ * GPUs and groups views whose participant cells do not overlap (Sec. 4.4,
+ * view bucketing); on one GPU the views of a batch share the device, so the
+ * batched calls below run the per-view stages of up to SX_MAX_VIEWS views of
+ * ONE cell in one launch each, pulling (view, tile) work items from a
+ * shared queue ordered by cost.  Results are bit-identical to the per-view
+ * calls (every work item owns its pixels; the per-Gaussian gradient rows of
+ * each view are reduced separately). */
+#define SX_MAX_VIEWS 16
+
+/* One view of a batched call.  Every pointer refers to that view's buffers
+ * exactly as the matching per-view call takes them (sizes follow cam). */
+typedef struct sx_view {
+  sx_camera cam;
+  sx_projected proj;           /* sx_preprocess(_multi) output          */
+  const uint32_t* vals;        /* sx_sort output                        */
+  const uint32_t* tile_ranges; /* sx_sort output                        */
+  const void* sort_ws;         /* this view's sort workspace            */
+  int64_t capacity;            /* its instance capacity                 */
+  const uint32_t* mask;        /* optional active-pixel bits, or NULL   */
+  float* partial;              /* [H*W*4] (C, T)                        */
+  float* depth;                /* optional [H*W], or NULL               */
+  uint32_t* last;              /* [H*W]                                 */
+  uint32_t* nblend;            /* optional [H*W], or NULL               */
+  const float* dpartial;       /* backward: [H*W*4] upstream gradient   */
+  float* g2d;                  /* backward: [n*12] screen gradients     */
+  void* bwd_ws;                /* backward: sx_backward_workspace_size  */
+} sx_view;
+
+/* Preprocess of one cell's Gaussians for V views in one launch (Eq. 1
+ * projection and SH colour per view).  outs[v] is laid out as for
+ * sx_preprocess with cams[v]; host arrays cams[V], outs[V]. */
+sx_status sx_preprocess_multi(const sx_gaussians* g, int32_t V,
+                              const sx_camera* cams, const sx_params* p,
+                              sx_projected* outs, sx_stream stream);
+
+/* Workspace of the shared work queue: bytes for V views with cams[V]. */
+sx_status sx_multi_workspace_size(int32_t V, const sx_camera* cams,
+                                  const sx_params* p, size_t* bytes);
+
+/* Partial render (Eq. 3-4) of V views in one persistent launch; each view
+ * needs proj, vals, tile_ranges, mask, partial, depth, last, nblend.
+ * views: host array [V]; ws: device workspace (contents scratch). */
+sx_status sx_render_multi(int32_t V, const sx_view* views,
+                          const sx_params* p, void* ws, size_t ws_bytes,
+                          sx_stream stream);
+
+/* Render backward (Eq. 6-7 through each view's local render) of V views of
+ * one cell of n Gaussians in one persistent launch, then each view's
+ * per-Gaussian reduction into views[v].g2d; each view needs every member.
+ * Follow with sx_preprocess_backward per view (SX_BWD_ACCUMULATE after the
+ * first) to sum the views' parameter gradients. */
+sx_status sx_render_backward_multi(int32_t V, const sx_view* views, int64_t n,
+                                   const sx_params* p, void* ws,
+                                   size_t ws_bytes, sx_stream stream);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,211 @@
+"""Batched multi-view training step and its autotuner.
+
+A training step over V views of one cell (paper Sec. 4.4 batches views;
+on one GPU the views of a batch share the device): every view is rendered,
+compared with its target image (L1), back-propagated, and the views'
+parameter gradients are summed before one Adam update.
+
+Batched form: the views are cut into groups of `batch`; each group runs one
+preprocess launch for all its views, a sort per view, one persistent render
+launch and one persistent render-backward launch over the group's (view,
+tile) work items.  Plain form: the per-view calls one view after another.
+Both forms give bit-identical images and gradients.
+
+Per-instance buffers (instance values, sort workspace, backward rows) are
+the bulk of the memory; groups run one after another on one stream, so all
+groups share one arena sized for the largest group.  Capacities come from a
+counting pass at set-up plus a margin; `check()` verifies that no view
+overflowed.
+"""
+from __future__ import annotations
+
+import itertools
+import time
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import binding as B
+from .pipeline import BatchedViews, CellView, GaussianParams
+
+_ALIGN = 256
+
+
+def _align(n: int) -> int:
+    return (n + _ALIGN - 1) // _ALIGN * _ALIGN
+
+
+def count_instances(view: CellView) -> tuple:
+    """(visible, instances) of a view: preprocess plus a counting sort call
+    into a zero capacity (nothing is emitted)."""
+    view.preprocess()
+    try:
+        B.sx_sort(view.c_proj, view.params.n, view.c_cam, view.c_par, 0, None, view.vals,
+                  view.ranges, view.ws, sync_counts=True)
+        return (0, 0)
+    except B.SplaxelError as e:
+        if e.code != B.SX_ECAPACITY:
+            raise
+    c = B.sx_sort_counts(view.ws, view.params.n)
+    return (c[0], c[1])
+
+
+class MultiViewStep:
+    def __init__(self, params: GaussianParams, grads: GaussianParams, cams: Sequence, targets,
+                 settings, batch: int = 16, plain: bool = False, margin: float = 1.1,
+                 device="cuda"):
+        self.params, self.grads = params, grads
+        self.settings = settings
+        self.plain = plain
+        self.batch = 1 if plain else int(batch)
+        self.views = [CellView(params, c, settings, capacity=0, device=device) for c in cams]
+        self.targets = list(targets)
+        self.counts = [count_instances(v) for v in self.views]
+        self.caps = [int(inst * margin) + 4096 for _, inst in self.counts]
+        self.groups = [list(range(i, min(i + self.batch, len(cams))))
+                       for i in range(0, len(cams), self.batch)]
+        need = 0
+        layout = {}
+        for g in self.groups:
+            off = 0
+            for i in g:
+                v, cap = self.views[i], self.caps[i]
+                parts = (4 * cap, v.sort_bytes(cap), v.backward_bytes(cap))
+                layout[i] = (off, parts)
+                off += sum(_align(p) for p in parts)
+            need = max(need, off)
+        self.arena_bytes = need
+        self.arena = torch.empty((max(need, 1),), dtype=torch.uint8, device=device)
+        for i, (off, (nv, ns, nb)) in layout.items():
+            a = self.arena
+            vals = a[off:off + nv].view(torch.int32)
+            off += _align(nv)
+            ws = a[off:off + ns]
+            off += _align(ns)
+            bw = a[off:off + nb]
+            self.views[i].bind_instance_buffers(self.caps[i], vals, ws, bw)
+        for v in self.views:
+            v.ensure_backward_buffers()
+            v.out = torch.empty_like(v.partial)
+            v.dout = torch.empty_like(v.partial)
+        self.box = [_Box()]
+        self.batches = [BatchedViews.from_views([self.views[i] for i in g]) for g in self.groups]
+        self.adam_m = [torch.zeros_like(t) for t in params.tensors()]
+        self.adam_v = [torch.zeros_like(t) for t in params.tensors()]
+        self.t = 0
+        self.blends = None
+
+    @property
+    def n_views(self):
+        return len(self.views)
+
+    def _loss_and_grad(self, v: CellView, target):
+        B.sx_composite([v.partial], self.box, v.c_cam, v.c_par, v.out, None)
+        B.sx_l1_loss(v.out, target, v.W, v.H, v.dout, None)
+        B.sx_composite_backward([v.partial], self.box, v.c_cam, v.c_par, v.dout, [v.dpartial])
+
+    def run(self, lr: float = 1e-4, count_blends: bool = False, check: bool = False):
+        """One step; with check, synchronises after each group and raises if
+        any view's instances overflowed its capacity."""
+        for t in self.grads.tensors():
+            B.sx_fill_u32(t, 0)
+        blends = 0
+        if self.plain:
+            for i, v in enumerate(self.views):
+                v.preprocess()
+                v.sort(sync=False)
+                v.render(None, want_nblend=count_blends)
+                self._loss_and_grad(v, self.targets[i])
+                v.render_backward(v.dpartial)
+                v.preprocess_backward(self.grads, accumulate=True)
+                if check:
+                    self._check([i])
+                if count_blends:
+                    blends += int(v.nblend.sum().item())
+        else:
+            for g, bv in zip(self.groups, self.batches):
+                bv.preprocess()
+                bv.sort(sync=False)
+                bv.render(want_nblend=count_blends)
+                for i in g:
+                    self._loss_and_grad(self.views[i], self.targets[i])
+                bv.render_backward()
+                bv.preprocess_backward(self.grads, accumulate=True)
+                if check:
+                    self._check(g)
+                if count_blends:
+                    blends += sum(int(self.views[i].nblend.sum().item()) for i in g)
+        self.t += 1
+        for p, gr, m, vv in zip(self.params.tensors(), self.grads.tensors(), self.adam_m,
+                                self.adam_v):
+            B.sx_adam(p, gr, m, vv, self.t, lr)
+        if count_blends:
+            self.blends = blends
+        return blends
+
+    def _check(self, group):
+        for i in group:
+            c = B.sx_sort_counts(self.views[i].ws, self.params.n)
+            if c[2] or c[1] > self.caps[i]:
+                raise RuntimeError(f"view {i}: {c[1]} instances overflow capacity {self.caps[i]}")
+
+
+class _Box:
+    lo = (-1e30,) * 3
+    hi = (1e30,) * 3
+
+
+@dataclass
+class TuneResult:
+    tile: str
+    batch: int
+    ms: float
+
+
+def time_step(step: MultiViewStep, reps: int = 3, warmup: int = 1, lr: float = 1e-7) -> float:
+    for _ in range(warmup):
+        step.run(lr)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step.run(lr)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def autotune(params: GaussianParams, grads: GaussianParams, cams, targets, make_settings,
+             tiles=("16x16", "32x8", "16x32"), batches=(2, 4, 8, 16),
+             mem_budget: Optional[int] = None, reps: int = 2, log=None) -> List[TuneResult]:
+    """Time one batched step per (tile shape, batch size) that fits the
+    memory budget (bytes of free device memory if None) and return the
+    results sorted fastest first.  The parameters are restored after each
+    trial, so tuning leaves no trace in the model."""
+    saved = [t.clone() for t in params.tensors()]
+    out = []
+    for tile, b in itertools.product(tiles, batches):
+        tw, th = (int(x) for x in tile.split("x"))
+        st = make_settings(tw, th)
+        try:
+            step = MultiViewStep(params, grads, cams, targets, st, batch=b)
+        except torch.cuda.OutOfMemoryError:
+            if log:
+                log(f"autotune: tile {tile} batch {b}: out of memory")
+            torch.cuda.empty_cache()
+            continue
+        budget = mem_budget if mem_budget is not None else torch.cuda.mem_get_info()[0]
+        if step.arena_bytes > budget:
+            del step
+            continue
+        ms = time_step(step, reps=reps)
+        out.append(TuneResult(tile, b, ms))
+        if log:
+            log(f"autotune: tile {tile} batch {b}: {ms:.2f} ms/step")
+        del step
+        for t, s in zip(params.tensors(), saved):
+            t.copy_(s)
+        torch.cuda.empty_cache()
+    out.sort(key=lambda r: r.ms)
+    return out

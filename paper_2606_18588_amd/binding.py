@@ -70,13 +70,23 @@ class SxCellState(ctypes.Structure):
                 ("g2d_ws", c_p), ("dpartial_ws", c_p), ("bwd_ws", c_p)]
 
 
+class SxView(ctypes.Structure):
+    _fields_ = [("cam", SxCamera), ("proj", SxProjected), ("vals", c_p),
+                ("tile_ranges", c_p), ("sort_ws", c_p), ("capacity", c_i64),
+                ("mask", c_p), ("partial", c_p), ("depth", c_p), ("last", c_p),
+                ("nblend", c_p), ("dpartial", c_p), ("g2d", c_p), ("bwd_ws", c_p)]
+
+
+SX_MAX_VIEWS = 16
+
 EXPORTS = (
     "sx_last_error_string", "sx_version", "sx_preprocess_blocks",
     "sx_preprocess", "sx_sort_workspace_size", "sx_sort", "sx_sort_counts",
     "sx_backward_workspace_size",
     "sx_render_partial", "sx_composite", "sx_l1_loss", "sx_backward",
     "sx_composite_backward", "sx_render_backward", "sx_preprocess_backward",
-    "sx_adam", "sx_fill_u32",
+    "sx_adam", "sx_fill_u32", "sx_preprocess_multi", "sx_multi_workspace_size",
+    "sx_render_multi", "sx_render_backward_multi",
 )
 
 _lib = None
@@ -216,10 +226,10 @@ def sx_preprocess(g: SxGaussians, cam: SxCamera, p: SxParams,
         stream_handle(stream)))
 
 
-def sx_sort_workspace_size(n: int, capacity: int, tiles_total: int) -> int:
+def sx_sort_workspace_size(n: int, capacity: int, tiles_x: int, tiles_y: int) -> int:
     b = ctypes.c_size_t(0)
     _check("sx_sort_workspace_size", lib().sx_sort_workspace_size(
-        c_i64(n), c_i64(capacity), c_i64(tiles_total), ctypes.byref(b)))
+        c_i64(n), c_i64(capacity), c_i32(tiles_x), c_i32(tiles_y), ctypes.byref(b)))
     return int(b.value)
 
 
@@ -324,3 +334,36 @@ def sx_fill_u32(t: torch.Tensor, value: int, stream=None) -> None:
     _check("sx_fill_u32", lib().sx_fill_u32(
         ptr(t), c_i64(t.numel() * t.element_size() // 4),
         ctypes.c_uint32(value & 0xFFFFFFFF), stream_handle(stream)))
+
+
+def sx_preprocess_multi(g: SxGaussians, cams: Sequence[SxCamera], p: SxParams,
+                        outs: Sequence[SxProjected], stream=None) -> None:
+    ca = (SxCamera * len(cams))(*cams)
+    oa = (SxProjected * len(outs))(*outs)
+    _check("sx_preprocess_multi", lib().sx_preprocess_multi(
+        ctypes.byref(g), c_i32(len(cams)), ca, ctypes.byref(p), oa,
+        stream_handle(stream)))
+
+
+def sx_multi_workspace_size(cams: Sequence[SxCamera], p: SxParams) -> int:
+    ca = (SxCamera * len(cams))(*cams)
+    b = ctypes.c_size_t(0)
+    _check("sx_multi_workspace_size", lib().sx_multi_workspace_size(
+        c_i32(len(cams)), ca, ctypes.byref(p), ctypes.byref(b)))
+    return int(b.value)
+
+
+def sx_render_multi(views: Sequence[SxView], p: SxParams, ws: torch.Tensor,
+                    stream=None) -> None:
+    va = (SxView * len(views))(*views)
+    _check("sx_render_multi", lib().sx_render_multi(
+        c_i32(len(views)), va, ctypes.byref(p), ptr(ws),
+        ctypes.c_size_t(ws.numel() * ws.element_size()), stream_handle(stream)))
+
+
+def sx_render_backward_multi(views: Sequence[SxView], n: int, p: SxParams,
+                             ws: torch.Tensor, stream=None) -> None:
+    va = (SxView * len(views))(*views)
+    _check("sx_render_backward_multi", lib().sx_render_backward_multi(
+        c_i32(len(views)), va, c_i64(n), ctypes.byref(p), ptr(ws),
+        ctypes.c_size_t(ws.numel() * ws.element_size()), stream_handle(stream)))

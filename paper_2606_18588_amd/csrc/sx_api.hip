@@ -116,12 +116,12 @@ sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
              "sx_preprocess");
 }
 
-sx_status sx_sort_workspace_size(int64_t n, int64_t capacity, int64_t tiles_total,
+sx_status sx_sort_workspace_size(int64_t n, int64_t capacity, int32_t tiles_x, int32_t tiles_y,
                                  size_t* bytes) {
   if (!bytes) return fail(SX_EINVAL, "bytes is NULL");
-  if (n < 0 || capacity < 0 || tiles_total < 1) return fail(SX_EINVAL, "negative size");
+  if (n < 0 || capacity < 0 || tiles_x < 1 || tiles_y < 1) return fail(SX_EINVAL, "negative size");
   if (capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "capacity must be < 2^30");
-  *bytes = sx::sort_layout(n, capacity, tiles_total).total;
+  *bytes = sx::sort_layout(n, capacity, tiles_x, tiles_y).total;
   return SX_OK;
 }
 
@@ -138,7 +138,8 @@ sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
   if (!vals && capacity > 0) return fail(SX_EINVAL, "vals is NULL");
   if (!tile_ranges || !ws) return fail(SX_EINVAL, "tile_ranges/ws is NULL");
   const int64_t tiles = tiles_of(cam, p);
-  const size_t need = sx::sort_layout(n, capacity, tiles).total;
+  const sx::KParams kp = sx::make_kparams(*p, *cam);
+  const size_t need = sx::sort_layout(n, capacity, kp.tiles_x, kp.tiles_y).total;
   if (ws_bytes < need) return fail(SX_EINVAL, "workspace %zu bytes < required %zu", ws_bytes, need);
   bool over = false;
   hipError_t e = sx::launch_sort(*proj, n, sx::make_kparams(*p, *cam), capacity, tiles, keys, vals,
@@ -154,7 +155,7 @@ sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
 sx_status sx_sort_counts(const void* ws, int64_t n, uint64_t* h_out, sx_stream stream) {
   (void)n;
   if (!ws || !h_out) return fail(SX_EINVAL, "null argument");
-  const size_t off = sx::sort_layout(0, 0, 1).counts;
+  const size_t off = sx::sort_layout(0, 0, 1, 1).counts;
   hipError_t e = hipMemcpyAsync(h_out, static_cast<const char*>(ws) + off, 4 * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
@@ -248,9 +249,9 @@ sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
       !partial || !last || !dpartial || !g2d)
     return fail(SX_EINVAL, "null argument");
   if (n < 0 || capacity < 0 || capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "bad n/capacity");
-  const int64_t tiles = tiles_of(cam, p);
-  return dev(sx::launch_render_backward(*proj, vals, tile_ranges, sx::sort_view(sort_ws, n, capacity, tiles),
-                                        n, capacity, sx::make_dcam(*cam), sx::make_kparams(*p, *cam), mask,
+  const sx::KParams kp = sx::make_kparams(*p, *cam);
+  return dev(sx::launch_render_backward(*proj, vals, tile_ranges, sx::sort_view(sort_ws, n, capacity, kp.tiles_x, kp.tiles_y),
+                                        n, capacity, sx::make_dcam(*cam), kp, mask,
                                         partial, last, dpartial, ddepth, g2d, static_cast<char*>(bwd_ws),
                                         (hipStream_t)stream),
              "sx_render_backward");
@@ -268,9 +269,9 @@ sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,
   if (capacity < 0 || capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "bad capacity");
   if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
     return fail(SX_EINVAL, "null gradient array");
-  const int64_t tiles = tiles_of(cam, p);
-  return dev(sx::launch_preprocess_backward(*g, sx::make_dcam(*cam), sx::make_kparams(*p, *cam), *proj,
-                                            sx::sort_view(sort_ws, g->n, capacity, tiles), g2d, *grads,
+  const sx::KParams kp = sx::make_kparams(*p, *cam);
+  return dev(sx::launch_preprocess_backward(*g, sx::make_dcam(*cam), kp, *proj,
+                                            sx::sort_view(sort_ws, g->n, capacity, kp.tiles_x, kp.tiles_y), g2d, *grads,
                                             (flags & SX_BWD_ACCUMULATE) != 0, (hipStream_t)stream),
              "sx_preprocess_backward");
 }
@@ -302,6 +303,107 @@ sx_status sx_backward(int32_t K, const sx_cell_state* cells, const sx_cell* boxe
     SX_TRY(sx_preprocess_backward(c.g, cam, p, c.proj, c.sort_ws, c.capacity, c.g2d_ws, c.grads, flags,
                                   stream));
   }
+  return SX_OK;
+}
+
+static_assert(SX_MAX_VIEWS == sx::kMaxViews, "view limit");
+
+// ------------------------------------------------------------ batched views
+static sx_status check_views(int32_t V, const sx_view* views, const sx_params* p, bool backward) {
+  if (V < 1 || V > sx::kMaxViews) return fail(SX_EINVAL, "V=%d outside 1..%d", V, sx::kMaxViews);
+  if (!views) return fail(SX_EINVAL, "views is NULL");
+  SX_TRY(check_params(p));
+  for (int v = 0; v < V; ++v) {
+    const sx_view& w = views[v];
+    SX_TRY(check_cam(&w.cam));
+    if (tiles_of(&w.cam, p) >= (int64_t(1) << 24)) return fail(SX_EINVAL, "view %d has too many tiles", v);
+    if (!w.proj.rec || !w.tile_ranges || !w.partial || !w.last)
+      return fail(SX_EINVAL, "view %d: null forward buffer", v);
+    if (w.capacity < 0 || w.capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "view %d: bad capacity", v);
+    if (backward && (!w.proj.rect || !w.proj.n_tiles || !w.sort_ws || !w.dpartial || !w.g2d || !w.bwd_ws))
+      return fail(SX_EINVAL, "view %d: null backward buffer", v);
+  }
+  return SX_OK;
+}
+
+static void to_multi(int32_t V, const sx_view* views, const sx_params* p, sx::MultiView* mv) {
+  for (int v = 0; v < V; ++v) {
+    const sx_view& w = views[v];
+    sx::MultiView& m = mv[v];
+    m.cam = sx::make_dcam(w.cam);
+    const sx::KParams k = sx::make_kparams(*p, w.cam);
+    m.tiles_x = k.tiles_x, m.tiles_y = k.tiles_y;
+    m.proj = w.proj;
+    m.vals = w.vals, m.ranges = w.tile_ranges, m.mask = w.mask;
+    m.partial = w.partial, m.depth = w.depth, m.last = w.last, m.nblend = w.nblend;
+    m.sort_ws = w.sort_ws, m.capacity = w.capacity;
+    m.dpartial = w.dpartial, m.g2d = w.g2d, m.bwd_ws = w.bwd_ws;
+  }
+}
+
+static size_t multi_ws_need(int32_t V, const sx_camera* cams, int stride, const sx_params* p) {
+  int64_t items = 0;
+  for (int v = 0; v < V; ++v)
+    items += tiles_of(reinterpret_cast<const sx_camera*>(reinterpret_cast<const char*>(cams) + (size_t)v * stride), p);
+  return sx::multi_workspace_bytes(items);
+}
+
+sx_status sx_preprocess_multi(const sx_gaussians* g, int32_t V, const sx_camera* cams,
+                              const sx_params* p, sx_projected* outs, sx_stream stream) {
+  SX_TRY(check_gauss(g));
+  SX_TRY(check_params(p));
+  if (V < 1 || V > sx::kMaxViews) return fail(SX_EINVAL, "V=%d outside 1..%d", V, sx::kMaxViews);
+  if (!cams || !outs) return fail(SX_EINVAL, "null cams/outs");
+  for (int v = 0; v < V; ++v) {
+    SX_TRY(check_cam(&cams[v]));
+    const int64_t tx = (cams[v].width + p->tile_w - 1) / p->tile_w;
+    const int64_t ty = (cams[v].height + p->tile_h - 1) / p->tile_h;
+    if (tx > 65535 || ty > 65535) return fail(SX_EINVAL, "tile grid too large for uint16 rects");
+    if (g->n > 0 && (!outs[v].rec || !outs[v].rect || !outs[v].n_tiles || !outs[v].block_sums))
+      return fail(SX_EINVAL, "view %d: null projected output array", v);
+  }
+  return dev(sx::launch_preprocess_multi(*g, V, cams, sx::make_kparams(*p, cams[0]), outs,
+                                         (hipStream_t)stream),
+             "sx_preprocess_multi");
+}
+
+sx_status sx_multi_workspace_size(int32_t V, const sx_camera* cams, const sx_params* p,
+                                  size_t* bytes) {
+  if (!bytes || !cams) return fail(SX_EINVAL, "null argument");
+  SX_TRY(check_params(p));
+  if (V < 1 || V > sx::kMaxViews) return fail(SX_EINVAL, "V=%d outside 1..%d", V, sx::kMaxViews);
+  for (int v = 0; v < V; ++v) SX_TRY(check_cam(&cams[v]));
+  *bytes = multi_ws_need(V, cams, sizeof(sx_camera), p);
+  return SX_OK;
+}
+
+sx_status sx_render_multi(int32_t V, const sx_view* views, const sx_params* p, void* ws,
+                          size_t ws_bytes, sx_stream stream) {
+  SX_TRY(check_views(V, views, p, false));
+  if (!ws) return fail(SX_EINVAL, "ws is NULL");
+  const size_t need = multi_ws_need(V, &views[0].cam, sizeof(sx_view), p);
+  if (ws_bytes < need) return fail(SX_EINVAL, "workspace %zu bytes < required %zu", ws_bytes, need);
+  sx::MultiView mv[sx::kMaxViews];
+  to_multi(V, views, p, mv);
+  return dev(sx::launch_render_multi(V, mv, sx::make_kparams(*p, views[0].cam), static_cast<char*>(ws),
+                                     (hipStream_t)stream),
+             "sx_render_multi");
+}
+
+sx_status sx_render_backward_multi(int32_t V, const sx_view* views, int64_t n, const sx_params* p,
+                                   void* ws, size_t ws_bytes, sx_stream stream) {
+  SX_TRY(check_views(V, views, p, true));
+  if (!ws) return fail(SX_EINVAL, "ws is NULL");
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "n out of range");
+  const size_t need = multi_ws_need(V, &views[0].cam, sizeof(sx_view), p);
+  if (ws_bytes < need) return fail(SX_EINVAL, "workspace %zu bytes < required %zu", ws_bytes, need);
+  sx::MultiView mv[sx::kMaxViews];
+  to_multi(V, views, p, mv);
+  const sx::KParams kp = sx::make_kparams(*p, views[0].cam);
+  SX_TRY(dev(sx::launch_render_backward_multi(V, mv, n, kp, static_cast<char*>(ws), (hipStream_t)stream),
+             "sx_render_backward_multi"));
+  for (int v = 0; v < V; ++v)
+    SX_TRY(dev(sx::launch_grad_reduce_view(mv[v], n, kp, (hipStream_t)stream), "sx_render_backward_multi"));
   return SX_OK;
 }
 

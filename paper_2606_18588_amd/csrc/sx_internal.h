@@ -17,11 +17,11 @@ constexpr int kSortItems = 16;   // keys per thread
 constexpr int kSortTile = kSortBlock * kSortItems;  // keys per partition
 constexpr int kRadixBins = 256;
 constexpr int kScanTile = 2048;   // Gaussians per offset-scan partition
-constexpr int kEmitChunk = 4096;  // output instances per emit block
-static_assert(kEmitChunk == kSortTile, "emission chunks are radix partitions");
-constexpr int kDiffParts = 64;    // LDS copies of the tile difference grid
-constexpr int kDiffMaxCells = 16384;  // largest grid kept in LDS (64 KB)
+constexpr int kEmitChunk = 4096;  // instance slots per chunk of the backward reduction
+constexpr int kReduceLdsTiles = 8192;  // tiles whose visited depth the reduction keeps in LDS
 constexpr int kMaxCells = 16;
+constexpr int kMaxViews = 16;  // views per batched launch
+constexpr int kBinSeg = 1024;   // entries per segment of a bin list (tile binning)
 constexpr float kLog2e = 1.4426950408889634f;
 
 // Camera in double (exact widening of the caller's float values) plus the
@@ -53,23 +53,23 @@ struct SortLayout {
   size_t didx[2];      // uint32[n]    Gaussian indices (ping-pong)
   size_t zero_begin;   // start of the region cleared on every call
   size_t dhist;        // uint32[4][256] depth digit histograms
-  size_t thist;        // uint32[3][256] tile digit histograms
   size_t counters;     // uint32[16] partition counters
   size_t dstatus;      // uint32[4][dparts][256]
-  size_t tstatus;      // uint32[3][tparts][256]
   size_t estatus;      // uint64[eparts] offset-scan look-back
-  size_t diff;         // int32[(tiles_y+1)*(tiles_x+1)] tile-rect difference grid
   size_t zero_end;
-  size_t diffparts;    // int32[kDiffParts][cells] per-block difference grids
   size_t offs;         // uint32[n] instance offsets of the depth-sorted Gaussians
   size_t goffs;        // uint32[n] instance offset of each visible Gaussian (by index)
   size_t chunk_first;  // uint32[cap/kEmitChunk + 2] owner of each chunk's first slot
-  size_t tkey[2];      // uint32[cap] tile ids (ping-pong)
-  size_t tval[2];      // uint32[cap] Gaussian indices (ping-pong)
+  size_t bl_list[2];   // uint32[cap] bin lists of the inner levels (ping-pong)
+  size_t bl_bins[2];   // uint2[bins] (start, length) per bin (ping-pong)
+  size_t bl_seg[2];    // uint32[bins + 2] first segment per bin (ping-pong)
+  size_t bl_tot;       // uint32[tiles] entries per child bin
+  size_t bl_cnt;       // uint32[segments][16] entries per (segment, child)
   size_t total;
-  int64_t nb, dparts, tparts, eparts;
+  int64_t nb, dparts, eparts;
+  int bl_levels;       // levels of 4x4 subdivision above the tiles (>= 1)
 };
-SortLayout sort_layout(int64_t n, int64_t capacity, int64_t tiles_total);
+SortLayout sort_layout(int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
 
 // backward workspace: per-instance gradient rows (indexed by emission
 // position) and, per tile, the sort key of the last entry its walk visited
@@ -88,7 +88,7 @@ struct SortView {
   const uint32_t* goffs;  // instance offset by Gaussian index
   const uint32_t* chunk_first;
 };
-SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_total);
+SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -166,41 +166,41 @@ __device__ __forceinline__ void sh_basis(int deg, double x, double y, double z,
 }
 
 // gradient of each polynomial above with respect to (x, y, z): dY[k*3+c]
-__device__ __forceinline__ void sh_basis_grad(int deg, double x, double y,
-                                              double z, double* dY) {
-  for (int k = 0; k < 3; ++k) dY[k] = 0.0;
+template <typename T>
+__device__ __forceinline__ void sh_basis_grad(int deg, T x, T y, T z, T* dY) {
+  for (int k = 0; k < 3; ++k) dY[k] = T(0.0);
   if (deg < 1) return;
-  dY[3 + 0] = 0.0, dY[3 + 1] = -SHC::c1, dY[3 + 2] = 0.0;
-  dY[6 + 0] = 0.0, dY[6 + 1] = 0.0, dY[6 + 2] = SHC::c1;
-  dY[9 + 0] = -SHC::c1, dY[9 + 1] = 0.0, dY[9 + 2] = 0.0;
+  dY[3 + 0] = T(0.0), dY[3 + 1] = (T)-SHC::c1, dY[3 + 2] = T(0.0);
+  dY[6 + 0] = T(0.0), dY[6 + 1] = T(0.0), dY[6 + 2] = (T)SHC::c1;
+  dY[9 + 0] = (T)-SHC::c1, dY[9 + 1] = T(0.0), dY[9 + 2] = T(0.0);
   if (deg < 2) return;
-  const double a = SHC::c2a, b = SHC::c2b, c = SHC::c2c;
-  dY[12 + 0] = a * y, dY[12 + 1] = a * x, dY[12 + 2] = 0.0;
-  dY[15 + 0] = 0.0, dY[15 + 1] = -a * z, dY[15 + 2] = -a * y;
-  dY[18 + 0] = -2.0 * b * x, dY[18 + 1] = -2.0 * b * y, dY[18 + 2] = 4.0 * b * z;
-  dY[21 + 0] = -a * z, dY[21 + 1] = 0.0, dY[21 + 2] = -a * x;
-  dY[24 + 0] = 2.0 * c * x, dY[24 + 1] = -2.0 * c * y, dY[24 + 2] = 0.0;
+  const T a = (T)SHC::c2a, b = (T)SHC::c2b, c = (T)SHC::c2c;
+  dY[12 + 0] = a * y, dY[12 + 1] = a * x, dY[12 + 2] = T(0.0);
+  dY[15 + 0] = T(0.0), dY[15 + 1] = -a * z, dY[15 + 2] = -a * y;
+  dY[18 + 0] = -T(2.0) * b * x, dY[18 + 1] = -T(2.0) * b * y, dY[18 + 2] = T(4.0) * b * z;
+  dY[21 + 0] = -a * z, dY[21 + 1] = T(0.0), dY[21 + 2] = -a * x;
+  dY[24 + 0] = T(2.0) * c * x, dY[24 + 1] = -T(2.0) * c * y, dY[24 + 2] = T(0.0);
   if (deg < 3) return;
-  const double e = -SHC::c3a, f = SHC::c3b, g = -SHC::c3c, h = SHC::c3d,
-               k = SHC::c3e;
-  const double xx = x * x, yy = y * y, zz = z * z;
+  const T e = (T)-SHC::c3a, f = (T)SHC::c3b, g = (T)-SHC::c3c, h = (T)SHC::c3d,
+          k = (T)SHC::c3e;
+  const T xx = x * x, yy = y * y, zz = z * z;
   // e (3 x^2 y - y^3)
-  dY[27 + 0] = 6.0 * e * x * y, dY[27 + 1] = e * (3.0 * xx - 3.0 * yy), dY[27 + 2] = 0.0;
+  dY[27 + 0] = T(6.0) * e * x * y, dY[27 + 1] = e * (T(3.0) * xx - T(3.0) * yy), dY[27 + 2] = T(0.0);
   // f x y z
   dY[30 + 0] = f * y * z, dY[30 + 1] = f * x * z, dY[30 + 2] = f * x * y;
   // g (4 y z^2 - x^2 y - y^3)
-  dY[33 + 0] = -2.0 * g * x * y, dY[33 + 1] = g * (4.0 * zz - xx - 3.0 * yy),
-          dY[33 + 2] = 8.0 * g * y * z;
+  dY[33 + 0] = -T(2.0) * g * x * y, dY[33 + 1] = g * (T(4.0) * zz - xx - T(3.0) * yy),
+          dY[33 + 2] = T(8.0) * g * y * z;
   // h (2 z^3 - 3 x^2 z - 3 y^2 z)
-  dY[36 + 0] = -6.0 * h * x * z, dY[36 + 1] = -6.0 * h * y * z,
-          dY[36 + 2] = h * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+  dY[36 + 0] = -T(6.0) * h * x * z, dY[36 + 1] = -T(6.0) * h * y * z,
+          dY[36 + 2] = h * (T(6.0) * zz - T(3.0) * xx - T(3.0) * yy);
   // g (4 x z^2 - x^3 - x y^2)
-  dY[39 + 0] = g * (4.0 * zz - 3.0 * xx - yy), dY[39 + 1] = -2.0 * g * x * y,
-          dY[39 + 2] = 8.0 * g * x * z;
+  dY[39 + 0] = g * (T(4.0) * zz - T(3.0) * xx - yy), dY[39 + 1] = -T(2.0) * g * x * y,
+          dY[39 + 2] = T(8.0) * g * x * z;
   // k (x^2 z - y^2 z)
-  dY[42 + 0] = 2.0 * k * x * z, dY[42 + 1] = -2.0 * k * y * z, dY[42 + 2] = k * (xx - yy);
+  dY[42 + 0] = T(2.0) * k * x * z, dY[42 + 1] = -T(2.0) * k * y * z, dY[42 + 2] = k * (xx - yy);
   // e (x^3 - 3 x y^2)
-  dY[45 + 0] = e * (3.0 * xx - 3.0 * yy), dY[45 + 1] = -6.0 * e * x * y, dY[45 + 2] = 0.0;
+  dY[45 + 0] = e * (T(3.0) * xx - T(3.0) * yy), dY[45 + 1] = -T(6.0) * e * x * y, dY[45 + 2] = T(0.0);
 }
 
 // Rotation matrix of a unit quaternion (w, x, y, z), row-major.
@@ -263,6 +263,8 @@ hipError_t launch_preprocess(const sx_gaussians& g, const DCam& cam,
                              const KParams& p, const sx_projected& out,
                              hipStream_t st);
 struct SortView;
+hipError_t launch_preprocess_multi(const sx_gaussians& g, int V, const sx_camera* cams,
+                                   const KParams& p, const sx_projected* outs, hipStream_t st);
 hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
                                       const KParams& p,
                                       const sx_projected& proj, const SortView& sv,
@@ -286,6 +288,31 @@ hipError_t launch_render_backward(const sx_projected& proj,
                                   const uint32_t* last, const float* dpartial,
                                   const float* ddepth, float* g2d, char* bws,
                                   hipStream_t st);
+// one view of a batched call, in kernel-ready form
+struct MultiView {
+  DCam cam;
+  int tiles_x, tiles_y;
+  sx_projected proj;
+  const uint32_t* vals;
+  const uint32_t* ranges;
+  const uint32_t* mask;
+  float* partial;
+  float* depth;
+  uint32_t* last;
+  uint32_t* nblend;
+  const void* sort_ws;
+  int64_t capacity;
+  const float* dpartial;
+  float* g2d;
+  void* bwd_ws;
+};
+size_t multi_workspace_bytes(int64_t items);
+hipError_t launch_render_multi(int V, const MultiView* mv, const KParams& p, char* ws,
+                               hipStream_t st);
+hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, const KParams& p,
+                                        char* ws, hipStream_t st);
+hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams& p,
+                                   hipStream_t st);
 hipError_t launch_composite(int K, const float* const* partials,
                             const sx_cell* cells, const DCam& cam,
                             const KParams& p, float* out, uint32_t* masks,

@@ -205,11 +205,11 @@ __device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
 // the front of the block, so the FP64 projection runs in full wavefronts
 // even when only a few percent of the scene is in view.
 template <int D>
-__global__ __launch_bounds__(kPreBlock) void k_preprocess(PreArgs a) {
+__device__ __forceinline__ void preprocess_block(const PreArgs& a, int64_t blk) {
   __shared__ uint32_t s_cand[kPreBlock];
   __shared__ uint32_t s_w[kPreBlock / 64];
   __shared__ uint32_t sv[kPreBlock / 64], sc[kPreBlock / 64];
-  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  const int64_t i = blk * kPreBlock + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   bool cand = false;
   if (i < a.n) {
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kPreBlock) void k_preprocess(PreArgs a) {
   __syncthreads();
   uint32_t cnt = 0;
   if (threadIdx.x < ncand) {
-    const int64_t ii = (int64_t)blockIdx.x * kPreBlock + s_cand[threadIdx.x];
+    const int64_t ii = blk * kPreBlock + s_cand[threadIdx.x];
     cnt = project_one<D>(a, ii);
     a.n_tiles[ii] = cnt;
   }
@@ -242,9 +242,105 @@ __global__ __launch_bounds__(kPreBlock) void k_preprocess(PreArgs a) {
   if (threadIdx.x == 0) {
     uint32_t a0 = 0, a1 = 0;
     for (int k = 0; k < kPreBlock / 64; ++k) a0 += sv[k], a1 += sc[k];
-    a.block_sums[2 * (size_t)blockIdx.x + 0] = a0;
-    a.block_sums[2 * (size_t)blockIdx.x + 1] = a1;
+    a.block_sums[2 * (size_t)blk + 0] = a0;
+    a.block_sums[2 * (size_t)blk + 1] = a1;
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(kPreBlock) void k_preprocess(PreArgs a) {
+  preprocess_block<D>(a, blockIdx.x);
+}
+
+// Several views in one launch: each workgroup takes one block of Gaussians
+// and projects it for every view in turn, so the block's parameters come
+// from HBM once and from the caches for the other views.
+struct PreView {
+  float R[9], t[3];
+  float fx, fy, cx, cy, znear;
+  int W, H, tiles_x, tiles_y;
+  float* rec;
+  uint16_t* rect;
+  uint32_t* n_tiles;
+  uint32_t* block_sums;
+};
+struct PreMultiArgs {
+  int64_t n;
+  int V;
+  const float* __restrict__ means;
+  const float* __restrict__ log_scales;
+  const float* __restrict__ quats;
+  const float* __restrict__ logits;
+  const float* __restrict__ sh;
+  KParams p;  // tiles_x / tiles_y are per view
+  float logit_min, tau_max;
+  PreView v[kMaxViews];
+};
+
+template <int D>
+__device__ __forceinline__ void preprocess_view(const PreMultiArgs& m, int v, int64_t blk) {
+  const PreView& pv = m.v[v];
+  PreArgs a;
+  a.n = m.n;
+  a.means = m.means, a.log_scales = m.log_scales, a.quats = m.quats;
+  a.logits = m.logits, a.sh = m.sh;
+  for (int k = 0; k < 9; ++k) a.cam.R[k] = pv.R[k];
+  for (int k = 0; k < 3; ++k) a.cam.t[k] = pv.t[k];
+  a.cam.fx = pv.fx, a.cam.fy = pv.fy, a.cam.cx = pv.cx, a.cam.cy = pv.cy, a.cam.znear = pv.znear;
+  for (int j = 0; j < 3; ++j)
+    a.cam.C[j] = -(a.cam.R[0 * 3 + j] * a.cam.t[0] + a.cam.R[1 * 3 + j] * a.cam.t[1] +
+                   a.cam.R[2 * 3 + j] * a.cam.t[2]);
+  a.cam.W = pv.W, a.cam.H = pv.H;
+  a.p = m.p;
+  a.p.tiles_x = pv.tiles_x, a.p.tiles_y = pv.tiles_y;
+  for (int k = 0; k < 9; ++k) a.cull.R[k] = pv.R[k];
+  for (int k = 0; k < 3; ++k) a.cull.t[k] = pv.t[k];
+  a.cull.fx = pv.fx, a.cull.fy = pv.fy, a.cull.cx = pv.cx, a.cull.cy = pv.cy;
+  a.cull.znear = pv.znear;
+  a.cull.logit_min = m.logit_min, a.cull.tau_max = m.tau_max, a.cull.eps2d = (float)m.p.eps2d;
+  a.rec = pv.rec, a.rect = pv.rect, a.n_tiles = pv.n_tiles, a.block_sums = pv.block_sums;
+  preprocess_block<D>(a, blk);
+}
+
+template <int D>
+__global__ __launch_bounds__(kPreBlock) void k_preprocess_multi(PreMultiArgs m) {
+  for (int v = 0; v < m.V; ++v) {
+    preprocess_view<D>(m, v, blockIdx.x);
+    __syncthreads();  // the next view reuses the block's LDS
+  }
+}
+
+hipError_t launch_preprocess_multi(const sx_gaussians& g, int V, const sx_camera* cams,
+                                   const KParams& p, const sx_projected* outs, hipStream_t st) {
+  if (g.n == 0 || V == 0) return hipSuccess;
+  PreMultiArgs m;
+  m.n = g.n;
+  m.V = V;
+  m.means = g.means, m.log_scales = g.log_scales, m.quats = g.quats;
+  m.logits = g.opacity_logits, m.sh = g.sh;
+  m.p = p;
+  m.logit_min = (float)(std::log(p.alpha_min_d / (1.0 - p.alpha_min_d)) - 1e-3);
+  m.tau_max = (float)(2.0 * std::log(1.0 / p.alpha_min_d));
+  for (int v = 0; v < V; ++v) {
+    const sx_camera& c = cams[v];
+    PreView& pv = m.v[v];
+    for (int k = 0; k < 9; ++k) pv.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) pv.t[k] = c.t[k];
+    pv.fx = c.fx, pv.fy = c.fy, pv.cx = c.cx, pv.cy = c.cy, pv.znear = c.znear;
+    pv.W = c.width, pv.H = c.height;
+    pv.tiles_x = (c.width + p.tile_w - 1) / p.tile_w;
+    pv.tiles_y = (c.height + p.tile_h - 1) / p.tile_h;
+    pv.rec = outs[v].rec, pv.rect = outs[v].rect, pv.n_tiles = outs[v].n_tiles;
+    pv.block_sums = outs[v].block_sums;
+  }
+  const dim3 grid((unsigned)((g.n + kPreBlock - 1) / kPreBlock));
+  switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess_multi<0>, grid, dim3(kPreBlock), 0, st, m); break;
+    case 1: hipLaunchKernelGGL(k_preprocess_multi<1>, grid, dim3(kPreBlock), 0, st, m); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_multi<2>, grid, dim3(kPreBlock), 0, st, m); break;
+    default: hipLaunchKernelGGL(k_preprocess_multi<3>, grid, dim3(kPreBlock), 0, st, m); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_preprocess(const sx_gaussians& g, const DCam& cam,
@@ -324,29 +420,61 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
   const double gcol[3] = {g1.z, g1.w, g2.x};
   const double gz = g2.y;
   constexpr int nc = (D + 1) * (D + 1);
-  // colour -> SH coefficients and direction
-  double Y[16], dY[48];
+  constexpr int nf = nc * 3;
+  // colour -> SH coefficients and direction.  The clamp decision uses the
+  // forward's FP64 sum; the direction gradient runs in FP32.  Rows of nf
+  // floats are moved as float4 where nf is a multiple of 4 (SH1, SH3).
+  double Y[16];
   sh_basis(D, g.dir[0], g.dir[1], g.dir[2], Y);
-  sh_basis_grad(D, g.dir[0], g.dir[1], g.dir[2], dY);
-  const float* __restrict__ shp = a.sh + (size_t)i * nc * 3;
-  float* gshp = a.gsh + (size_t)i * nc * 3;
-  double gdir[3] = {0.0, 0.0, 0.0};
+  float dY[48];
+  sh_basis_grad<float>(D, (float)g.dir[0], (float)g.dir[1], (float)g.dir[2], dY);
+  float sh[nf];
+  const float* __restrict__ shp = a.sh + (size_t)i * nf;
+  if constexpr (nf % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < nf / 4; ++j) {
+      const float4 q = reinterpret_cast<const float4*>(shp)[j];
+      sh[4 * j] = q.x, sh[4 * j + 1] = q.y, sh[4 * j + 2] = q.z, sh[4 * j + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < nf; ++j) sh[j] = shp[j];
+  }
+  float gcv[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < nc; ++k) v += (double)shp[k * 3 + ch] * Y[k];
-    const bool pos = v + 0.5 > 0.0;
-    const double gcv = pos ? gcol[ch] : 0.0;
-#pragma unroll
-    for (int k = 0; k < nc; ++k) {
-      put<ACC>(&gshp[k * 3 + ch], gcv * Y[k]);
-      const double w = gcv * (double)shp[k * 3 + ch];
-      gdir[0] += w * dY[k * 3 + 0];
-      gdir[1] += w * dY[k * 3 + 1];
-      gdir[2] += w * dY[k * 3 + 2];
-    }
+    for (int k = 0; k < nc; ++k) v += (double)sh[k * 3 + ch] * Y[k];
+    gcv[ch] = v + 0.5 > 0.0 ? (float)gcol[ch] : 0.f;
   }
+  float gdf[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < nc; ++k)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float w = gcv[ch] * sh[k * 3 + ch];
+      gdf[0] += w * dY[k * 3 + 0];
+      gdf[1] += w * dY[k * 3 + 1];
+      gdf[2] += w * dY[k * 3 + 2];
+    }
+  float* gshp = a.gsh + (size_t)i * nf;
+  auto gsh_at = [&](int j) { return (float)((double)gcv[j % 3] * Y[j / 3]); };
+  if constexpr (nf % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < nf / 4; ++j) {
+      float4 q = make_float4(gsh_at(4 * j), gsh_at(4 * j + 1), gsh_at(4 * j + 2), gsh_at(4 * j + 3));
+      if (ACC) {
+        const float4 o = reinterpret_cast<const float4*>(gshp)[j];
+        q.x += o.x, q.y += o.y, q.z += o.z, q.w += o.w;
+      }
+      reinterpret_cast<float4*>(gshp)[j] = q;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < nf; ++j) put<ACC>(&gshp[j], (double)gsh_at(j));
+  }
+  const double gdir[3] = {gdf[0], gdf[1], gdf[2]};
   double gmu[3];
   {
     const double dd = gdir[0] * g.dir[0] + gdir[1] * g.dir[1] + gdir[2] * g.dir[2];

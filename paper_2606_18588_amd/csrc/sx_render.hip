@@ -34,13 +34,17 @@ __device__ __forceinline__ int xcd_tile(int b, int ntile) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Records are staged per wavefront in batches of 64: lane i gathers the
+// record of list entry jb+i with vector loads (64 gathers in flight, which
+// hides their latency), writes it to the wavefront's own LDS slice, and the
+// wavefront then walks the batch reading each record as a broadcast.  Each
+// wavefront owns its slice, so no workgroup barrier is needed.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
-  const int ntile = a.tiles_x * a.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, ntile);
-  if (tile >= ntile) return;
+__device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
+                                            float4 (*s_rec)[3][64]) {
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int px = tx * TW + lx, py = ty * TH + ly;
   const bool inside = px < a.W && py < a.H;
   const uint32_t pix = (uint32_t)py * a.W + px;
@@ -51,23 +55,33 @@ __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   uint32_t lst = 0, nb = 0;
   bool done = !active;
-  for (uint32_t j = rg.x; j < rg.y; ++j) {
+  for (uint32_t jb = rg.x; jb < rg.y; jb += 64) {
     if (__ballot(!done) == 0) break;
-    const uint32_t g = a.vals[j];
-    const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)g * kRecFloats);
-    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-    const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-    if (!done && ae.alpha >= a.alpha_min) {
-      const float w = ae.alpha * T;
-      C0 = fmaf(r1.z, w, C0);
-      C1 = fmaf(r1.w, w, C1);
-      C2 = fmaf(r2.x, w, C2);
-      D = fmaf(r2.y, w, D);
-      T = T * (1.f - ae.alpha);
-      ++nb;
-      lst = j - rg.x + 1;
-      if (T < a.t_min) done = true;
+    const uint32_t cnt = rg.y - jb < 64u ? rg.y - jb : 64u;
+    if ((uint32_t)lane < cnt) {
+      const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)a.vals[jb + lane] * kRecFloats);
+      s_rec[w][0][lane] = r[0];
+      s_rec[w][1][lane] = r[1];
+      s_rec[w][2][lane] = r[2];
     }
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t k = 0; k < cnt; ++k) {
+      if (__ballot(!done) == 0) break;
+      const float4 r0 = s_rec[w][0][k], r1 = s_rec[w][1][k], r2 = s_rec[w][2][k];
+      const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
+      if (!done && ae.alpha >= a.alpha_min) {
+        const float wt = ae.alpha * T;
+        C0 = fmaf(r1.z, wt, C0);
+        C1 = fmaf(r1.w, wt, C1);
+        C2 = fmaf(r2.x, wt, C2);
+        D = fmaf(r2.y, wt, D);
+        T = T * (1.f - ae.alpha);
+        ++nb;
+        lst = jb + k - rg.x + 1;
+        if (T < a.t_min) done = true;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   if (inside) {
     a.partial[pix] = make_float4(C0, C1, C2, T);
@@ -75,6 +89,15 @@ __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
     if (a.depth) a.depth[pix] = D;
     if (a.nblend) a.nblend[pix] = nb;
   }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
+  __shared__ float4 s_rec[TW * TH / 64][3][64];
+  const int ntile = a.tiles_x * a.tiles_y;
+  const int tile = xcd_tile(blockIdx.x, ntile);
+  if (tile >= ntile) return;
+  render_tile<TW, TH>(a, tile, s_rec);
 }
 
 struct RenderBwdArgs {
@@ -113,11 +136,9 @@ struct RenderBwdArgs {
 // stored as zeros.  The tile records the sort key of the last entry it
 // visited, which tells the per-Gaussian reduction which slots are valid.
 template <int TW, int TH>
-__global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
+__device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile,
+                                                float4 (*s_rec)[64], uint32_t* s_e) {
   constexpr int PPT = TW * TH / 64;
-  const int ntile = a.tiles_x * a.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, ntile);
-  if (tile >= ntile) return;
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int lane = threadIdx.x;
   const uint2 rg = a.ranges[tile];
@@ -157,12 +178,26 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
     }
     a.last_key[tile] = key;
   }
-  for (int j = (int)wave_last - 1; j >= 0; --j) {
-    const uint32_t g = a.vals[rg.x + (uint32_t)j];
-    const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)g * kRecFloats);
-    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-    const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[g];
-    const uint32_t e = a.goffs[g] + ((uint32_t)ty - rc.y) * ((uint32_t)rc.z - rc.x) + ((uint32_t)tx - rc.x);
+  for (int jend = (int)wave_last; jend > 0; jend -= 64) {
+    // stage entries [jend - cnt, jend): lane i gathers entry jend - cnt + i
+    // and its gradient slot e = (first instance of the Gaussian) + (index of
+    // this tile in the Gaussian's rectangle, row-major)
+    const int cnt = jend < 64 ? jend : 64;
+    const int j0 = jend - cnt;
+    if (lane < cnt) {
+      const uint32_t gl = a.vals[rg.x + (uint32_t)(j0 + lane)];
+      const float4* rr = reinterpret_cast<const float4*>(a.rec + (size_t)gl * kRecFloats);
+      s_rec[0][lane] = rr[0];
+      s_rec[1][lane] = rr[1];
+      s_rec[2][lane] = rr[2];
+      const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[gl];
+      s_e[lane] = a.goffs[gl] + ((uint32_t)ty - rc.y) * ((uint32_t)rc.z - rc.x) + ((uint32_t)tx - rc.x);
+    }
+    __builtin_amdgcn_wave_barrier();
+  for (int kk = cnt - 1; kk >= 0; --kk) {
+    const int j = j0 + kk;
+    const float4 r0 = s_rec[0][kk], r1 = s_rec[1][kk], r2 = s_rec[2][kk];
+    const uint32_t e = s_e[kk];
     float4* dst = reinterpret_cast<float4*>(a.gpart + (size_t)e * kG2dFloats);
     const bool in_cap = (uint64_t)e < a.cap;
     float v[10];
@@ -218,6 +253,18 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
       dst[2] = make_float4(sum[8], sum[9], 0.f, 0.f);
     }
   }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
+  __shared__ float4 s_rec[3][64];
+  __shared__ uint32_t s_e[64];
+  const int ntile = a.tiles_x * a.tiles_y;
+  const int tile = xcd_tile(blockIdx.x, ntile);
+  if (tile >= ntile) return;
+  render_tile_bwd<TW, TH>(a, tile, s_rec, s_e);
 }
 
 // Per-Gaussian sum of the partial gradient rows.  Balanced like the
@@ -238,7 +285,7 @@ struct ReduceArgs {
   const float* __restrict__ rec;
   const float* __restrict__ gpart;
   const uint64_t* __restrict__ last_key;
-  int tiles_x;
+  int tiles_x, tiles;
   uint64_t cap;
   float* __restrict__ g2d;
 };
@@ -248,8 +295,12 @@ __global__ __launch_bounds__(256) void k_grad_reduce(ReduceArgs a) {
   __shared__ unsigned long long s_key[256];
   __shared__ float s_acc[256 * 10];
   __shared__ uint32_t s_lohi[2];
+  extern __shared__ uint32_t s_ldep[];  // per tile: depth bits of the last visited entry
   const int tid = threadIdx.x;
   if (a.counts[2] != 0) return;
+  const bool staged = a.tiles <= kReduceLdsTiles;
+  if (staged)
+    for (int t = tid; t < a.tiles; t += 256) s_ldep[t] = (uint32_t)(a.last_key[t] >> 32);
   const uint64_t ninst = a.counts[1] < a.cap ? a.counts[1] : a.cap;
   const uint64_t nvis = a.counts[0];
   const uint64_t c0 = (uint64_t)blockIdx.x * kEmitChunk;
@@ -308,7 +359,14 @@ __global__ __launch_bounds__(256) void k_grad_reduce(ReduceArgs a) {
           wj = s_w[j], tx = 0, ty = 0;
         }
         const uint32_t tile = (s_y0[j] + ty) * (uint32_t)a.tiles_x + s_x0[j] + tx;
-        if (s_key[j] <= a.last_key[tile]) {
+        bool visited;
+        if (staged) {
+          const uint32_t dg = (uint32_t)(s_key[j] >> 32), dt = s_ldep[tile];
+          visited = dg < dt || (dg == dt && s_key[j] <= a.last_key[tile]);
+        } else {
+          visited = s_key[j] <= a.last_key[tile];
+        }
+        if (visited) {
           const float4* src = reinterpret_cast<const float4*>(a.gpart + (size_t)k * kG2dFloats);
           const float4 p0 = src[0], p1 = src[1], p2 = src[2];
           acc[0] += p0.x, acc[1] += p0.y, acc[2] += p0.z, acc[3] += p0.w, acc[4] += p1.x;
@@ -347,6 +405,120 @@ __global__ __launch_bounds__(256) void k_zero_g2d(const uint32_t* __restrict__ v
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   d[0] = z, d[1] = z, d[2] = z;
 }
+
+// ------------------------------------------------------------ multi-view --
+// Many views in one persistent launch: the (view, tile) work items of all
+// views are ordered by descending cost class (bit length of the tile's list
+// length) and workgroups take items from a global counter until none is
+// left, so large and small views share the GPU with no per-view tail.
+struct WorkArgs {
+  int V;
+  uint32_t base[kMaxViews + 1];  // first work item of each view
+  const uint2* ranges[kMaxViews];
+  uint32_t* hist;    // [32] items per cost class
+  uint32_t* cursor;  // [32]
+  uint32_t* items;   // [n] (view << 24) | tile
+};
+
+__device__ __forceinline__ int work_view(const WorkArgs& w, uint32_t item) {
+  int v = 0;
+  while (v + 1 < w.V && item >= w.base[v + 1]) ++v;
+  return v;
+}
+
+__device__ __forceinline__ int cost_class(uint2 r) {
+  const uint32_t c = r.y - r.x;
+  return c == 0 ? 0 : 32 - __clz(c);
+}
+
+__global__ __launch_bounds__(256) void k_work_hist(WorkArgs w) {
+  __shared__ uint32_t h[33];
+  if (threadIdx.x < 33) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t item = blockIdx.x * 256 + threadIdx.x;
+  if (item < w.base[w.V]) {
+    const int v = work_view(w, item);
+    atomicAdd(&h[cost_class(w.ranges[v][item - w.base[v]])], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 33 && h[threadIdx.x]) atomicAdd(&w.hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_work_scatter(WorkArgs w) {
+  __shared__ uint32_t h[33], start[33], mine[33];
+  if (threadIdx.x < 33) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t item = blockIdx.x * 256 + threadIdx.x;
+  int cls = -1, v = 0;
+  uint32_t rank = 0;
+  if (item < w.base[w.V]) {
+    v = work_view(w, item);
+    cls = cost_class(w.ranges[v][item - w.base[v]]);
+    rank = atomicAdd(&h[cls], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 33) {
+    // classes are laid out from the most expensive down
+    uint32_t s0 = 0;
+    for (int c = 32; c > (int)threadIdx.x; --c) s0 += w.hist[c];
+    start[threadIdx.x] = s0;
+    mine[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&w.cursor[threadIdx.x], h[threadIdx.x]) : 0u;
+  }
+  __syncthreads();
+  if (cls >= 0)
+    w.items[start[cls] + mine[cls] + rank] = ((uint32_t)v << 24) | (item - w.base[v]);
+}
+
+static_assert(sizeof(WorkArgs) <= 1024, "work-list arguments");
+
+struct RenderMultiArgs {
+  int V;
+  uint32_t n_items;
+  const uint32_t* __restrict__ items;
+  uint32_t* counter;
+  RenderArgs view[kMaxViews];
+};
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_render_multi(RenderMultiArgs m) {
+  __shared__ float4 s_rec[TW * TH / 64][3][64];
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(m.counter, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    __syncthreads();
+    if (it >= m.n_items) break;
+    const uint32_t code = m.items[it];
+    render_tile<TW, TH>(m.view[code >> 24], (int)(code & 0xFFFFFF), s_rec);
+  }
+}
+
+struct RenderBwdMultiArgs {
+  int V;
+  uint32_t n_items;
+  const uint32_t* __restrict__ items;
+  uint32_t* counter;
+  RenderBwdArgs view[kMaxViews];
+};
+
+static_assert(sizeof(RenderMultiArgs) <= 4096, "kernel argument block too large");
+
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void k_render_bwd_multi(RenderBwdMultiArgs m) {
+  __shared__ float4 s_rec[3][64];
+  __shared__ uint32_t s_e[64];
+  for (;;) {
+    uint32_t it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(m.counter, 1u);
+    it = __shfl(it, 0, 64);
+    if (it >= m.n_items) break;
+    const uint32_t code = m.items[it];
+    render_tile_bwd<TW, TH>(m.view[code >> 24], (int)(code & 0xFFFFFF), s_rec, s_e);
+  }
+}
+
+static_assert(sizeof(RenderBwdMultiArgs) <= 4096, "kernel argument block too large");
 
 bool tile_shape_supported(int tw, int th) {
   return (tw == 16 && th == 16) || (tw == 32 && th == 8) || (tw == 8 && th == 32) ||
@@ -395,21 +567,30 @@ hipError_t launch_render(const sx_projected& proj, const uint32_t* vals,
   return hipGetLastError();
 }
 
-hipError_t launch_render_backward(const sx_projected& proj,
-                                  const uint32_t* vals, const uint32_t* ranges,
-                                  const SortView& sv, int64_t n, int64_t capacity,
-                                  const DCam& cam, const KParams& p,
-                                  const uint32_t* mask, const float* partial,
-                                  const uint32_t* last, const float* dpartial,
-                                  const float* ddepth, float* g2d, char* bws,
-                                  hipStream_t st) {
+static RenderArgs make_render_args(const sx_projected& proj, const uint32_t* vals,
+                                   const uint32_t* ranges, const DCam& cam, const KParams& p,
+                                   const uint32_t* mask, float* partial, float* depth,
+                                   uint32_t* last, uint32_t* nblend) {
+  RenderArgs a;
+  a.rec = proj.rec;
+  a.vals = vals;
+  a.ranges = reinterpret_cast<const uint2*>(ranges);
+  a.mask = mask;
+  a.W = cam.W, a.H = cam.H, a.tiles_x = p.tiles_x, a.tiles_y = p.tiles_y;
+  a.cx = (float)cam.cx, a.cy = (float)cam.cy;
+  a.alpha_min = p.alpha_min, a.alpha_max = p.alpha_max, a.t_min = p.t_min;
+  a.partial = reinterpret_cast<float4*>(partial);
+  a.depth = depth, a.last = last, a.nblend = nblend;
+  return a;
+}
+
+static RenderBwdArgs make_bwd_args(const sx_projected& proj, const uint32_t* vals,
+                                   const uint32_t* ranges, const SortView& sv, int64_t capacity,
+                                   const DCam& cam, const KParams& p, const uint32_t* mask,
+                                   const float* partial, const uint32_t* last,
+                                   const float* dpartial, const float* ddepth, char* bws) {
   const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
   const BwdLayout BL = bwd_layout(capacity, tiles);
-  float* gpart = reinterpret_cast<float*>(bws + BL.gpart);
-  uint64_t* last_key = reinterpret_cast<uint64_t*>(bws + BL.last_key);
-  if (n > 0)
-    hipLaunchKernelGGL(k_zero_g2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       sv.didx, sv.counts, g2d);
   RenderBwdArgs a;
   a.rec = proj.rec;
   a.vals = vals;
@@ -425,19 +606,143 @@ hipError_t launch_render_backward(const sx_projected& proj,
   a.rect = proj.rect;
   a.goffs = sv.goffs;
   a.cap = (uint64_t)capacity;
-  a.gpart = gpart;
-  a.last_key = last_key;
-  SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_t, a, st);
+  a.gpart = reinterpret_cast<float*>(bws + BL.gpart);
+  a.last_key = reinterpret_cast<uint64_t*>(bws + BL.last_key);
+  return a;
+}
+
+// zero the visible rows of g2d, then sum each Gaussian's valid partial rows
+static hipError_t launch_grad_reduce(const sx_projected& proj, const SortView& sv, int64_t n,
+                                     int64_t capacity, const KParams& p, float* g2d, char* bws,
+                                     hipStream_t st) {
+  const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
+  const BwdLayout BL = bwd_layout(capacity, tiles);
+  if (n > 0)
+    hipLaunchKernelGGL(k_zero_g2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       sv.didx, sv.counts, g2d);
   ReduceArgs r;
   r.didx = sv.didx, r.offs = sv.offs, r.counts = sv.counts, r.chunk_first = sv.chunk_first;
   r.rect = proj.rect, r.n_tiles = proj.n_tiles, r.rec = proj.rec;
-  r.gpart = gpart, r.last_key = last_key;
+  r.gpart = reinterpret_cast<const float*>(bws + BL.gpart);
+  r.last_key = reinterpret_cast<const uint64_t*>(bws + BL.last_key);
   r.tiles_x = p.tiles_x;
+  r.tiles = (int)tiles;
   r.cap = (uint64_t)capacity;
   r.g2d = g2d;
   const int64_t rb = (capacity + kEmitChunk - 1) / kEmitChunk;
-  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)(rb > 0 ? rb : 1)), dim3(256), 0, st, r);
+  const size_t lds = tiles <= kReduceLdsTiles ? (size_t)tiles * 4 : 0;
+  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)(rb > 0 ? rb : 1)), dim3(256), lds, st, r);
   return hipGetLastError();
+}
+
+hipError_t launch_render_backward(const sx_projected& proj,
+                                  const uint32_t* vals, const uint32_t* ranges,
+                                  const SortView& sv, int64_t n, int64_t capacity,
+                                  const DCam& cam, const KParams& p,
+                                  const uint32_t* mask, const float* partial,
+                                  const uint32_t* last, const float* dpartial,
+                                  const float* ddepth, float* g2d, char* bws,
+                                  hipStream_t st) {
+  RenderBwdArgs a = make_bwd_args(proj, vals, ranges, sv, capacity, cam, p, mask, partial, last,
+                                  dpartial, ddepth, bws);
+  SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_t, a, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_grad_reduce(proj, sv, n, capacity, p, g2d, bws, st);
+}
+
+// ------------------------------------------------------------ multi-view --
+// work-list workspace: a 512-byte head (hist[33], cursor[33], two work
+// counters) followed by one u32 item per (view, tile)
+constexpr int kWorkHeadWords = 128;
+size_t multi_workspace_bytes(int64_t items) {
+  return kWorkHeadWords * 4 + (size_t)(items > 0 ? items : 1) * 4;
+}
+
+static hipError_t build_worklist(int V, const MultiView* mv, const KParams& p, char* ws,
+                                 WorkArgs& w, hipStream_t st) {
+  uint32_t* head = reinterpret_cast<uint32_t*>(ws);
+  w.V = V;
+  uint32_t base = 0;
+  for (int v = 0; v < V; ++v) {
+    w.base[v] = base;
+    w.ranges[v] = reinterpret_cast<const uint2*>(mv[v].ranges);
+    base += (uint32_t)(mv[v].tiles_x * mv[v].tiles_y);
+  }
+  w.base[V] = base;
+  w.hist = head;
+  w.cursor = head + 33;
+  w.items = reinterpret_cast<uint32_t*>(ws + kWorkHeadWords * 4);
+  hipError_t e = launch_fill(head, kWorkHeadWords, 0, st);  // hist, cursor, work counters
+  if (e) return e;
+  const unsigned nb = (base + 255) / 256;
+  hipLaunchKernelGGL(k_work_hist, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, w);
+  hipLaunchKernelGGL(k_work_scatter, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, w);
+  return hipGetLastError();
+}
+
+template <int TW, int TH>
+static void launch_fwd_multi_t(const RenderMultiArgs& m, hipStream_t st) {
+  const unsigned grid = m.n_items < 2048u ? m.n_items : 2048u;
+  hipLaunchKernelGGL((k_render_multi<TW, TH>), dim3(grid > 0 ? grid : 1), dim3(TW * TH), 0, st, m);
+}
+template <int TW, int TH>
+static void launch_bwd_multi_t(const RenderBwdMultiArgs& m, hipStream_t st) {
+  const unsigned grid = m.n_items < 5120u ? m.n_items : 5120u;
+  hipLaunchKernelGGL((k_render_bwd_multi<TW, TH>), dim3(grid > 0 ? grid : 1), dim3(64), 0, st, m);
+}
+
+hipError_t launch_render_multi(int V, const MultiView* mv, const KParams& p, char* ws,
+                               hipStream_t st) {
+  WorkArgs w;
+  hipError_t e = build_worklist(V, mv, p, ws, w, st);
+  if (e) return e;
+  RenderMultiArgs m;
+  m.V = V;
+  m.n_items = w.base[V];
+  m.items = w.items;
+  m.counter = w.hist + 66;
+  for (int v = 0; v < V; ++v) {
+    KParams pv = p;
+    pv.tiles_x = mv[v].tiles_x, pv.tiles_y = mv[v].tiles_y;
+    m.view[v] = make_render_args(mv[v].proj, mv[v].vals, mv[v].ranges, mv[v].cam, pv,
+                                 mv[v].mask, mv[v].partial, mv[v].depth, mv[v].last,
+                                 mv[v].nblend);
+  }
+  SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_fwd_multi_t, m, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, const KParams& p,
+                                        char* ws, hipStream_t st) {
+  WorkArgs w;
+  hipError_t e = build_worklist(V, mv, p, ws, w, st);
+  if (e) return e;
+  RenderBwdMultiArgs m;
+  m.V = V;
+  m.n_items = w.base[V];
+  m.items = w.items;
+  m.counter = w.hist + 67;
+  for (int v = 0; v < V; ++v) {
+    KParams pv = p;
+    pv.tiles_x = mv[v].tiles_x, pv.tiles_y = mv[v].tiles_y;
+    const int64_t tiles = (int64_t)pv.tiles_x * pv.tiles_y;
+    m.view[v] = make_bwd_args(mv[v].proj, mv[v].vals, mv[v].ranges,
+                              sort_view(mv[v].sort_ws, n, mv[v].capacity, pv.tiles_x, pv.tiles_y), mv[v].capacity,
+                              mv[v].cam, pv, mv[v].mask, mv[v].partial, mv[v].last,
+                              mv[v].dpartial, nullptr, static_cast<char*>(mv[v].bwd_ws));
+  }
+  SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_multi_t, m, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams& p,
+                                   hipStream_t st) {
+  KParams pv = p;
+  pv.tiles_x = v.tiles_x, pv.tiles_y = v.tiles_y;
+  const int64_t tiles = (int64_t)pv.tiles_x * pv.tiles_y;
+  return launch_grad_reduce(v.proj, sort_view(v.sort_ws, n, v.capacity, pv.tiles_x, pv.tiles_y), n, v.capacity,
+                            pv, v.g2d, static_cast<char*>(v.bwd_ws), st);
 }
 
 }  // namespace sx

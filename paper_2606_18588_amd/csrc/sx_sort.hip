@@ -3,25 +3,23 @@
 // The result equals a stable sort of 64-bit keys
 //     key = tile_id << 32 | bits(float32 depth)
 // over instances emitted in Gaussian-index order, i.e. the order
-// (tile, depth bits, Gaussian index).  Because the 32 depth bits are the same
-// for every instance of a Gaussian, the LSD radix sort is split in two:
-//   1. the low (depth) digits are applied to the compacted list of visible
-//      Gaussians *before* duplication (4 passes over ~N_vis elements);
-//   2. instances are emitted in that depth order, so only the tile digits
-//      remain, sorted stably over the duplicated list (ceil(bits/8) passes,
-//      e.g. 2 for a 1080p frame's 8160 tiles).
-// Per-tile instance counts come from a 2D difference grid of the Gaussians'
-// tile rectangles (four atomics per visible Gaussian, then a 2D prefix sum),
-// which yields the tile ranges and the tile-digit histograms without reading
-// the instance list.  Instances are emitted by blocks that each own a fixed
-// chunk of the output (balanced however many tiles a Gaussian covers).
-// Each pass is a single "onesweep" kernel: per-partition digit ranking with
-// wavefront ballots (wave64 match), a decoupled look-back across partitions
-// for the global offsets, and an LDS reorder so that global writes are
-// coalesced runs.  Partitions take their index from an atomic counter, so a
-// partition only ever waits on partitions that are already running, and
-// every wait is bounded (a spin limit raises an error flag instead of
-// hanging).
+// (tile, depth bits, Gaussian index).  It is built in two phases:
+//   1. the depth digits are radix sorted on the compacted list of visible
+//      Gaussians before duplication (4 LSD passes over ~N_vis elements, one
+//      "onesweep" kernel each: wave64 ballot ranking, decoupled look-back
+//      with bounded waits, LDS reorder for coalesced writes);
+//   2. the depth-ordered list is split by tile through a hierarchy of bins
+//      (bins of 4^L x 4^L tiles, each bin having 4 x 4 child bins): the
+//      list of a bin is cut into segments, and for every segment each of 16
+//      wavefronts ballot-filters the entries whose tile rectangle meets its
+//      child bin.  A count pass and an exclusive scan give every (segment,
+//      child) its output offset, and a write pass stores the entries in
+//      order, so each child's list stays depth-ordered and every store is a
+//      contiguous run of a wavefront.  The last level's bins are single
+//      tiles; their lists are the instance values and the scan gives the
+//      tile ranges.
+// No step uses atomics on the output; every wait is bounded (a spin limit
+// raises an error flag instead of hanging).
 #include "sx_internal.h"
 
 namespace sx {
@@ -72,8 +70,9 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s4,
 
 }  // namespace
 
-SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_total) {
+SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y) {
   SortLayout L;
+  const int64_t tiles_total = tiles_x * tiles_y;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -82,30 +81,37 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_total) {
   };
   L.nb = (n + kPreBlock - 1) / kPreBlock;
   L.dparts = (n + kSortTile - 1) / kSortTile;
-  L.tparts = (cap + kSortTile - 1) / kSortTile;
   L.eparts = (n + kScanTile - 1) / kScanTile;
   if (L.dparts < 1) L.dparts = 1;
-  if (L.tparts < 1) L.tparts = 1;
   if (L.eparts < 1) L.eparts = 1;
   L.zero_begin = off;
-  L.counts = take(4 * sizeof(uint64_t));
+  L.counts = take(4 * sizeof(uint64_t));  // offset 0: part of the ABI
   L.dhist = take(4 * kRadixBins * 4);
-  L.thist = take(3 * kRadixBins * 4);
   L.counters = take(16 * 4);
   L.dstatus = take((size_t)4 * L.dparts * kRadixBins * 4);
-  L.tstatus = take((size_t)3 * L.tparts * kRadixBins * 4);
   L.estatus = take((size_t)L.eparts * 8);
-  L.diff = take((size_t)(2 * tiles_total + 2) * 4);
   L.zero_end = off;
-  L.diffparts = take((size_t)kDiffParts * (2 * tiles_total + 2) * 4);
   L.offs = take((size_t)(n > 0 ? n : 1) * 4);
   L.goffs = take((size_t)(n > 0 ? n : 1) * 4);
   L.chunk_first = take((size_t)((cap + kEmitChunk - 1) / kEmitChunk + 2) * 4);
   L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
   for (int k = 0; k < 2; ++k) L.dkey[k] = take((size_t)(n > 0 ? n : 1) * 4);
   for (int k = 0; k < 2; ++k) L.didx[k] = take((size_t)(n > 0 ? n : 1) * 4);
-  for (int k = 0; k < 2; ++k) L.tkey[k] = take((size_t)(cap > 0 ? cap : 1) * 4);
-  for (int k = 0; k < 2; ++k) L.tval[k] = take((size_t)(cap > 0 ? cap : 1) * 4);
+  // binning: levels of 4x4 bins until one bin covers the grid; every entry of
+  // an inner level is a (Gaussian, bin) pair with at least one instance in
+  // the bin, so an inner list never exceeds the instance count
+  const int64_t big = tiles_x > tiles_y ? tiles_x : tiles_y;
+  int levels = 1;
+  while ((int64_t(1) << (2 * levels)) < big) ++levels;
+  L.bl_levels = levels;
+  const int64_t bins = ((tiles_x + 3) / 4) * ((tiles_y + 3) / 4);
+  const size_t list_bytes = (size_t)(cap > 0 ? cap : 1) * 4;
+  L.bl_list[1] = levels >= 2 ? take(list_bytes) : off;  // level 1 writes list[1]
+  L.bl_list[0] = levels >= 3 ? take(list_bytes) : off;
+  for (int k = 0; k < 2; ++k) L.bl_bins[k] = take((size_t)(bins + 1) * 8);
+  for (int k = 0; k < 2; ++k) L.bl_seg[k] = take((size_t)(bins + 2) * 4);
+  L.bl_tot = take((size_t)(tiles_total > 0 ? tiles_total : 1) * 4);
+  L.bl_cnt = take((size_t)(cap / kBinSeg + bins + 2) * 16 * 4);
   L.total = off;
   return L;
 }
@@ -124,8 +130,8 @@ BwdLayout bwd_layout(int64_t cap, int64_t tiles_total) {
   return L;
 }
 
-SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_total) {
-  const SortLayout L = sort_layout(n, capacity, tiles_total);
+SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y) {
+  const SortLayout L = sort_layout(n, capacity, tiles_x, tiles_y);
   const char* b = static_cast<const char*>(ws);
   SortView v;
   v.counts = reinterpret_cast<const uint64_t*>(b + L.counts);
@@ -184,17 +190,11 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict
 
 // Compacted (depth bits, Gaussian index) list of visible Gaussians in index
 // order.
-// Also adds each visible Gaussian's tile rectangle to the 2D difference grid
-// diff[(tiles_y+1) x (tiles_x+1)]: +1 at (x0,y0) and (x1,y1), -1 at (x1,y0)
-// and (x0,y1); its 2D prefix sum is the number of instances per tile.
 __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restrict__ n_tiles,
-                                                       const float* __restrict__ rec,
-                                                       const uint16_t* __restrict__ rect, int64_t n,
+                                                       const float* __restrict__ rec, int64_t n,
                                                        const uint32_t* __restrict__ vis_off,
                                                        uint32_t* __restrict__ dkey,
-                                                       uint32_t* __restrict__ didx,
-                                                       int* __restrict__ diff, int gw,
-                                                       int use_global_diff) {
+                                                       uint32_t* __restrict__ didx) {
   __shared__ uint32_t sw[kPreBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
   const bool v = i < n && n_tiles[i] > 0;
@@ -209,126 +209,7 @@ __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restric
     const uint32_t pos = vis_off[blockIdx.x] + pre + rank;
     dkey[pos] = __float_as_uint(rec[(size_t)i * kRecFloats + 9]);
     didx[pos] = (uint32_t)i;
-    if (use_global_diff) {
-      const ushort4 rc = reinterpret_cast<const ushort4*>(rect)[i];
-      atomicAdd(&diff[rc.y * gw + rc.x], 1);
-      atomicAdd(&diff[rc.y * gw + rc.z], -1);
-      atomicAdd(&diff[rc.w * gw + rc.x], -1);
-      atomicAdd(&diff[rc.w * gw + rc.z], 1);
-    }
   }
-}
-
-// Difference grid without global atomics (used when the grid fits in LDS):
-// each of kDiffParts blocks accumulates a contiguous share of the visible
-// Gaussians into an LDS copy of the grid and stores it to its own slot;
-// k_tile_counts adds the slots.
-__global__ __launch_bounds__(1024) void k_tile_diff(const uint32_t* __restrict__ didx,
-                                                    const uint16_t* __restrict__ rect,
-                                                    const uint64_t* counts, int gw, int cells,
-                                                    int* __restrict__ parts) {
-  extern __shared__ int s_grid[];
-  for (int c = threadIdx.x; c < cells; c += 1024) s_grid[c] = 0;
-  __syncthreads();
-  const uint64_t nvis = counts[0];
-  const uint64_t per = (nvis + gridDim.x - 1) / gridDim.x;
-  const uint64_t beg = (uint64_t)blockIdx.x * per;
-  const uint64_t end = beg + per < nvis ? beg + per : nvis;
-  for (uint64_t i = beg + threadIdx.x; i < end; i += 1024) {
-    const ushort4 rc = reinterpret_cast<const ushort4*>(rect)[didx[i]];
-    atomicAdd(&s_grid[rc.y * gw + rc.x], 1);
-    atomicAdd(&s_grid[rc.y * gw + rc.z], -1);
-    atomicAdd(&s_grid[rc.w * gw + rc.x], -1);
-    atomicAdd(&s_grid[rc.w * gw + rc.z], 1);
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < cells; c += 1024) parts[(size_t)blockIdx.x * cells + c] = s_grid[c];
-}
-
-// Sum of the per-block difference grids (one lane per grid cell).
-__global__ __launch_bounds__(256) void k_diff_sum(const int* __restrict__ parts, int nparts,
-                                                  int cells, int* __restrict__ diff) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= cells) return;
-  int acc = 0;
-#pragma unroll 8
-  for (int b = 0; b < nparts; ++b) acc += parts[(size_t)b * cells + c];
-  diff[c] = acc;
-}
-
-// One block: per-tile instance counts from the difference grid, tile ranges
-// [start, end) by an exclusive scan in tile order, and the histograms of the
-// tile digits used by the radix passes.  If the instance count overflowed
-// the caller's capacity every range is left empty.
-__global__ __launch_bounds__(1024) void k_tile_counts(int* __restrict__ diff, int tiles_x,
-                                                      int tiles_y, const uint64_t* counts,
-                                                      uint32_t* __restrict__ ranges,
-                                                      uint32_t* __restrict__ thist, int npass,
-                                                      int sh0, int b0, int sh1, int b1, int sh2,
-                                                      int b2) {
-  __shared__ uint32_t h[3][kRadixBins];
-  __shared__ uint32_t s_part[1024];
-  const int tid = threadIdx.x;
-  const int gw = tiles_x + 1, gh = tiles_y;  // the last grid row is never summed
-  const int lane = tid & 63, w = tid >> 6;
-  for (int k = tid; k < 3 * kRadixBins; k += 1024) (&h[0][0])[k] = 0;
-
-  // row prefix sums: one wavefront per row, 64 columns at a time
-  for (int r = w; r < gh; r += 16) {
-    int carry = 0;
-    for (int c0 = 0; c0 < gw; c0 += 64) {
-      const int c = c0 + lane;
-      int x = c < gw ? diff[r * gw + c] : 0;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-      }
-      if (c < gw) diff[r * gw + c] = x + carry;
-      carry += __shfl(x, 63, 64);
-    }
-  }
-  __syncthreads();
-  // column prefix sums: one lane per column, eight rows in flight
-  for (int c = tid; c < gw; c += 1024) {
-    int acc = 0;
-    for (int r0 = 0; r0 < gh; r0 += 8) {
-      int v[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = r0 + k < gh ? diff[(r0 + k) * gw + c] : 0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        acc += v[k];
-        if (r0 + k < gh) diff[(r0 + k) * gw + c] = acc;
-      }
-    }
-  }
-  __syncthreads();
-  const bool over = counts[2] != 0;
-  const int T = tiles_x * tiles_y;
-  const int chunk = (T + 1023) / 1024;
-  const int beg = tid * chunk, end = beg + chunk < T ? beg + chunk : T;
-  uint32_t sum = 0;
-  for (int t = beg; t < end; ++t) sum += (uint32_t)diff[(t / tiles_x) * gw + (t % tiles_x)];
-  s_part[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint32_t v = tid >= o ? s_part[tid - o] : 0u;
-    __syncthreads();
-    s_part[tid] += v;
-    __syncthreads();
-  }
-  uint32_t run = s_part[tid] - sum;
-  const int shs[3] = {sh0, sh1, sh2}, bs[3] = {b0, b1, b2};
-  for (int t = beg; t < end; ++t) {
-    const uint32_t c = (uint32_t)diff[(t / tiles_x) * gw + (t % tiles_x)];
-    ranges[2 * (size_t)t] = over ? 0u : run;
-    ranges[2 * (size_t)t + 1] = over ? 0u : run + c;
-    run += c;
-    if (c)
-      for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(t >> shs[p]) & ((1 << bs[p]) - 1)], c);
-  }
-  __syncthreads();
-  for (int k = tid; k < npass * kRadixBins; k += 1024) thist[k] = over ? 0u : (&h[0][0])[k];
 }
 
 // Exclusive scan of the tile counts of the depth-sorted visible Gaussians
@@ -435,81 +316,6 @@ __global__ __launch_bounds__(kSortBlock) void k_hist_depth(const uint32_t* __res
 }
 
 // ------------------------------------------------------------- onesweep --
-// Instance emission in depth order: a Gaussian's tiles, row-major over its
-// rectangle, occupy slots [offs[s], offs[s] + n_tiles) of the emission order.
-struct EmitArgs {
-  const uint32_t* __restrict__ didx;  // depth-sorted visible Gaussians
-  const uint32_t* __restrict__ offs;  // exclusive instance offsets
-  const uint32_t* __restrict__ chunk_first;  // owner of each chunk's first slot
-  const uint64_t* counts;
-  const uint16_t* __restrict__ rect;
-  int tiles_x;
-  uint32_t tile_base;
-  uint64_t cap;
-  uint32_t* __restrict__ tkey;
-  uint32_t* __restrict__ tval;
-};
-
-// Enumerate emission slots [c0, c1) as (tile id, Gaussian index) pairs into
-// out_key/out_val[k - c0]: find the depth-sorted Gaussians covering the
-// slots by binary search over the offsets, stage windows of 256 of them in
-// LDS, and map each slot to its Gaussian and tile.  Called by every thread
-// of a 256-thread block.
-__device__ __forceinline__ void emit_range(const EmitArgs& a, uint64_t c0, uint64_t c1,
-                                           uint32_t* out_key, uint32_t* out_val,
-                                           uint32_t* s_off, uint32_t* s_g, uint32_t* s_x0,
-                                           uint32_t* s_y0, uint32_t* s_w, uint32_t* s_lohi) {
-  const int tid = threadIdx.x;
-  const uint64_t nvis = a.counts[0];
-  const uint64_t ninst = a.counts[1];
-  if (tid == 0) chunk_bounds(a.chunk_first, a.offs, nvis, ninst, c0, c1, s_lohi);
-  __syncthreads();
-  const uint32_t slo = s_lohi[0], shi = s_lohi[1];
-  for (uint32_t w0 = slo; w0 <= shi; w0 += kSortBlock) {
-    const uint32_t wn = (shi - w0 + 1) < (uint32_t)kSortBlock ? (shi - w0 + 1) : (uint32_t)kSortBlock;
-    if ((uint32_t)tid < wn) {
-      const uint32_t sidx = w0 + tid;
-      const uint32_t g = a.didx[sidx];
-      const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[g];
-      s_off[tid] = a.offs[sidx];
-      s_g[tid] = g;
-      s_x0[tid] = rc.x, s_y0[tid] = rc.y, s_w[tid] = (uint32_t)rc.z - rc.x;
-    }
-    if (tid == 0) {
-      const uint64_t e = (uint64_t)w0 + wn < nvis ? (uint64_t)a.offs[w0 + wn] : ninst;
-      s_off[wn] = (uint32_t)(e < c1 ? e : c1);
-    }
-    __syncthreads();
-    const uint64_t k0 = (uint64_t)s_off[0] > c0 ? (uint64_t)s_off[0] : c0;
-    const uint64_t k1 = s_off[wn];
-    // each thread takes a run of consecutive slots (odd length, so the LDS
-    // writes of a wavefront fall in distinct banks); one search and one
-    // division per run, then the tile index advances row-major
-    const uint32_t run = ((uint32_t)(k1 - k0) + kSortBlock - 1) / kSortBlock | 1u;
-    uint64_t k = k0 + (uint64_t)tid * run;
-    const uint64_t kend = k + run < k1 ? k + run : k1;
-    if (k < kend) {
-      int j = 0, hi = (int)wn - 1;  // largest j with s_off[j] <= k
-      while (j < hi) {
-        const int mid = (j + hi + 1) >> 1;
-        if (s_off[mid] <= k) j = mid; else hi = mid - 1;
-      }
-      uint32_t wj = s_w[j];
-      const uint32_t r = (uint32_t)(k - s_off[j]);
-      uint32_t ty = r / wj, tx = r - ty * wj;
-      for (; k < kend; ++k) {
-        if (k == s_off[j + 1]) {
-          ++j;
-          wj = s_w[j], tx = 0, ty = 0;
-        }
-        out_key[k - c0] = a.tile_base + (s_y0[j] + ty) * (uint32_t)a.tiles_x + s_x0[j] + tx;
-        out_val[k - c0] = s_g[j];
-        if (++tx == wj) tx = 0, ++ty;
-      }
-    }
-    __syncthreads();
-  }
-}
 struct SweepArgs {
   const uint32_t* __restrict__ keys_in;
   const uint32_t* __restrict__ vals_in;
@@ -523,19 +329,13 @@ struct SweepArgs {
   uint32_t* status;
   uint32_t* part_counter;
   uint64_t* err;
-  uint64_t* __restrict__ keys64_out;  // final tile pass: tile<<32 | depth bits
-  const float* __restrict__ rec;
 };
 
-// FROM_EMIT: the pass reads no input array; each partition enumerates its
-// kSortTile emission slots itself (fusing the emission into the first tile
-// pass).
-template <bool FROM_EMIT>
-__global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a, EmitArgs em) {
+// One stable LSD pass over `bits` digits at `shift` of the keys.
+__global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ uint32_t s_vals[kSortTile];
-  // per-wave digit counters, then destinations and local offsets; the emit
-  // staging arrays of the fused pass live in the same words before ranking
+  // per-wave digit counters, then destinations and local offsets
   __shared__ uint32_t s_aux[6 * kRadixBins + 8];
   uint32_t(*s_wh)[kRadixBins] = reinterpret_cast<uint32_t(*)[kRadixBins]>(s_aux);
   uint32_t* s_dst = s_aux + 4 * kRadixBins;
@@ -554,29 +354,16 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a, EmitArgs e
   if (base >= n) return;
   const uint32_t tile_n = (n - base) < (uint64_t)kSortTile ? (uint32_t)(n - base) : (uint32_t)kSortTile;
   const uint32_t dmask = (1u << a.bits) - 1u;
-  if (FROM_EMIT)  // ends with a barrier, after which the staging words are free
-    emit_range(em, base, base + tile_n, s_keys, s_vals, s_aux, s_aux + 257, s_aux + 513,
-               s_aux + 769, s_aux + 1025, s_aux + 1281);
   for (int k = tid; k < 4 * kRadixBins; k += kSortBlock) s_aux[k] = 0;
   __syncthreads();
 
   uint32_t k[kSortItems], v[kSortItems], rk[kSortItems], dg[kSortItems];
-  if (FROM_EMIT) {
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-      const uint32_t idx = (uint32_t)w * (kSortTile / 4) + it * 64 + lane;
-      const bool valid = idx < tile_n;
-      k[it] = valid ? s_keys[idx] : 0u;
-      v[it] = valid ? s_vals[idx] : 0u;
-    }
-  } else {
-#pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-      const uint32_t idx = (uint32_t)w * (kSortTile / 4) + it * 64 + lane;
-      const bool valid = idx < tile_n;
-      k[it] = valid ? a.keys_in[base + idx] : 0u;
-      v[it] = valid ? a.vals_in[base + idx] : 0u;
-    }
+  for (int it = 0; it < kSortItems; ++it) {
+    const uint32_t idx = (uint32_t)w * (kSortTile / 4) + it * 64 + lane;
+    const bool valid = idx < tile_n;
+    k[it] = valid ? a.keys_in[base + idx] : 0u;
+    v[it] = valid ? a.vals_in[base + idx] : 0u;
   }
   const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
@@ -650,10 +437,188 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a, EmitArgs e
     const uint32_t val = s_vals[i];
     const uint32_t o = s_dst[(key >> a.shift) & dmask] + i;
     if (o >= n) continue;  // only reachable if the counts were inconsistent
-    if (a.keys_out) a.keys_out[o] = key;
+    a.keys_out[o] = key;
     a.vals_out[o] = val;
-    if (a.keys64_out)
-      a.keys64_out[o] = ((uint64_t)key << 32) | __float_as_uint(a.rec[(size_t)val * kRecFloats + 9]);
+  }
+}
+
+// ------------------------------------------------------------ binning --
+// One level of the tile hierarchy: parents are bins of 4*side x 4*side
+// tiles (grid pgx x pgy, lists in `in`), children bins of side x side
+// (grid cgx x cgy).  Child (cx, cy) belongs to parent (cx/4, cy/4) at slot
+// (cy%4)*4 + cx%4.  Parent lists are cut into segments of kBinSeg entries;
+// pseg[p] is the first segment of parent p and pseg[nparents] the total.
+struct BinLevel {
+  const uint32_t* __restrict__ in;
+  const uint2* __restrict__ pbins;   // (start, length) per parent
+  const uint32_t* __restrict__ pseg;
+  int pgx, pgy, cgx, cgy, side, tiles_x, tiles_y;
+  const uint16_t* __restrict__ rect;
+  const uint64_t* counts;
+  uint32_t* __restrict__ cnt;   // [segments][16]
+  uint32_t* __restrict__ tot;   // [children]
+  uint2* __restrict__ cbins;    // (start, length) per child (inner levels)
+  uint32_t* __restrict__ cseg;  // segment starts of the children (inner levels)
+  uint32_t* __restrict__ out;   // child lists; the instance values at the last level
+  uint32_t* __restrict__ ranges;  // last level: [tiles][2]
+  uint64_t* __restrict__ keys;    // last level, optional
+  const float* __restrict__ rec;
+  int last;
+};
+
+__global__ void k_bin_root(const uint64_t* counts, uint2* bins, uint32_t* seg) {
+  if (threadIdx.x != 0) return;
+  const uint32_t nvis = counts[2] != 0 ? 0u : (uint32_t)counts[0];
+  bins[0] = make_uint2(0u, nvis);
+  seg[0] = 0;
+  seg[1] = (nvis + kBinSeg - 1) / kBinSeg;
+}
+
+// Segment `sg`: its parent, first entry and entry count.
+__device__ __forceinline__ int bin_segment(const BinLevel& a, uint32_t sg, uint32_t* lo,
+                                           uint32_t* m) {
+  int l = 0, h = a.pgx * a.pgy - 1;  // largest p with pseg[p] <= sg
+  while (l < h) {
+    const int mid = (l + h + 1) >> 1;
+    if (a.pseg[mid] <= sg) l = mid; else h = mid - 1;
+  }
+  const uint2 pb = a.pbins[l];
+  const uint32_t off = (sg - a.pseg[l]) * (uint32_t)kBinSeg;
+  *lo = pb.x + off;
+  const uint32_t rest = pb.y - off;
+  *m = rest < (uint32_t)kBinSeg ? rest : (uint32_t)kBinSeg;
+  return l;
+}
+
+// Tile region of the child bin of parent p at slot w; false if outside.
+__device__ __forceinline__ bool bin_child(const BinLevel& a, int p, int w, int* c, int* rx0,
+                                          int* rx1, int* ry0, int* ry1) {
+  const int cx = (p % a.pgx) * 4 + (w & 3), cy = (p / a.pgx) * 4 + (w >> 2);
+  if (cx >= a.cgx || cy >= a.cgy) return false;
+  *c = cy * a.cgx + cx;
+  *rx0 = cx * a.side, *ry0 = cy * a.side;
+  *rx1 = min(*rx0 + a.side, a.tiles_x), *ry1 = min(*ry0 + a.side, a.tiles_y);
+  return true;
+}
+
+// Stage one segment (Gaussian ids and tile rectangles) in LDS.
+__device__ __forceinline__ void bin_stage(const BinLevel& a, uint32_t lo, uint32_t m,
+                                          uint32_t* s_g, ushort4* s_rc) {
+  __syncthreads();  // the previous segment is consumed
+  for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+    const uint32_t g = a.in[lo + i];
+    s_g[i] = g;
+    s_rc[i] = reinterpret_cast<const ushort4*>(a.rect)[g];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool meets(ushort4 rc, int rx0, int rx1, int ry0, int ry1) {
+  return (int)rc.x < rx1 && rx0 < (int)rc.z && (int)rc.y < ry1 && ry0 < (int)rc.w;
+}
+
+// Count pass: entries of each (segment, child).
+__global__ __launch_bounds__(1024) void k_bin_count(BinLevel a) {
+  __shared__ uint32_t s_g[kBinSeg];
+  __shared__ ushort4 s_rc[kBinSeg];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t nseg = a.pseg[a.pgx * a.pgy];
+  for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    uint32_t lo, m;
+    const int p = bin_segment(a, sg, &lo, &m);
+    bin_stage(a, lo, m, s_g, s_rc);
+    int c, rx0, rx1, ry0, ry1;
+    uint32_t n = 0;
+    if (bin_child(a, p, w, &c, &rx0, &rx1, &ry0, &ry1))
+      for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
+        const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
+        n += (uint32_t)__popcll(__ballot(hit));
+      }
+    if (lane == 0) a.cnt[(size_t)sg * 16 + w] = n;
+  }
+}
+
+// Per child: total entries over its parent's segments.
+__global__ __launch_bounds__(256) void k_bin_totals(BinLevel a) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= a.cgx * a.cgy) return;
+  const int cx = c % a.cgx, cy = c / a.cgx;
+  const int p = (cy >> 2) * a.pgx + (cx >> 2), slot = (cy & 3) * 4 + (cx & 3);
+  uint32_t t = 0;
+  for (uint32_t sg = a.pseg[p]; sg < a.pseg[p + 1]; ++sg) t += a.cnt[(size_t)sg * 16 + slot];
+  a.tot[c] = t;
+}
+
+// One block: exclusive scan of the children's totals (their list starts;
+// tile ranges at the last level) and, for inner levels, of their segment
+// counts.
+__global__ __launch_bounds__(1024) void k_bin_scan(BinLevel a) {
+  __shared__ uint32_t s_a[1024], s_b[1024];
+  const int tid = threadIdx.x;
+  const int C = a.cgx * a.cgy;
+  const int chunk = (C + 1023) / 1024;
+  const int beg = tid * chunk, end = beg + chunk < C ? beg + chunk : C;
+  uint32_t sa = 0, sb = 0;
+  for (int c = beg; c < end; ++c) {
+    const uint32_t t = a.tot[c];
+    sa += t;
+    sb += (t + kBinSeg - 1) / kBinSeg;
+  }
+  s_a[tid] = sa, s_b[tid] = sb;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t va = tid >= o ? s_a[tid - o] : 0u, vb = tid >= o ? s_b[tid - o] : 0u;
+    __syncthreads();
+    s_a[tid] += va, s_b[tid] += vb;
+    __syncthreads();
+  }
+  uint32_t ra = s_a[tid] - sa, rb = s_b[tid] - sb;
+  for (int c = beg; c < end; ++c) {
+    const uint32_t t = a.tot[c];
+    if (a.last) {
+      a.ranges[2 * (size_t)c] = ra;
+      a.ranges[2 * (size_t)c + 1] = ra + t;
+    } else {
+      a.cbins[c] = make_uint2(ra, t);
+      a.cseg[c] = rb;
+    }
+    ra += t;
+    rb += (t + kBinSeg - 1) / kBinSeg;
+  }
+  if (!a.last && tid == 1023) a.cseg[C] = s_b[1023];
+}
+
+// Write pass: every wavefront appends the entries of its child in order.
+__global__ __launch_bounds__(1024) void k_bin_write(BinLevel a) {
+  __shared__ uint32_t s_g[kBinSeg];
+  __shared__ ushort4 s_rc[kBinSeg];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t nseg = a.pseg[a.pgx * a.pgy];
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    uint32_t lo, m;
+    const int p = bin_segment(a, sg, &lo, &m);
+    bin_stage(a, lo, m, s_g, s_rc);
+    int c, rx0, rx1, ry0, ry1;
+    if (!bin_child(a, p, w, &c, &rx0, &rx1, &ry0, &ry1)) continue;
+    // start of this (segment, child): the child's start plus the entries
+    // the parent's earlier segments gave it
+    uint32_t base = 0;
+    for (uint32_t q = a.pseg[p] + lane; q < sg; q += 64) base += a.cnt[(size_t)q * 16 + w];
+    for (int o = 32; o >= 1; o >>= 1) base += __shfl_xor(base, o, 64);
+    base += a.last ? a.ranges[2 * (size_t)c] : a.cbins[c].x;
+    const uint64_t zkey = (uint64_t)c << 32;
+    for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
+      const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
+      const uint64_t b = __ballot(hit);
+      if (hit) {
+        const uint32_t pos = base + (uint32_t)__popcll(b & lt);
+        const uint32_t g = s_g[j];
+        a.out[pos] = g;
+        if (a.keys) a.keys[pos] = zkey | __float_as_uint(a.rec[(size_t)g * kRecFloats + 9]);
+      }
+      base += (uint32_t)__popcll(b);
+    }
   }
 }
 
@@ -676,19 +641,13 @@ hipError_t launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-static int bit_width(uint64_t v) {
-  int b = 0;
-  while ((1ull << b) < v) ++b;
-  return b < 1 ? 1 : b;
-}
-
 hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
                        int64_t capacity, int64_t tiles_total, uint64_t* keys,
                        uint32_t* vals, uint32_t* ranges, char* ws,
                        uint64_t* h_counts, bool* over_capacity,
                        hipStream_t st) {
   *over_capacity = false;
-  const SortLayout L = sort_layout(n, capacity, tiles_total);
+  const SortLayout L = sort_layout(n, capacity, p.tiles_x, p.tiles_y);
   hipError_t e;
   auto u32 = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   uint64_t* counts = reinterpret_cast<uint64_t*>(ws + L.counts);
@@ -712,40 +671,13 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
       return hipSuccess;
     }
   }
-  const int gw = p.tiles_x + 1;
-  const int cells = gw * (p.tiles_y + 1);
-  const bool lds_diff = cells <= kDiffMaxCells;
-  int* diff = reinterpret_cast<int*>(ws + L.diff);
-  int* dparts = reinterpret_cast<int*>(ws + L.diffparts);
+  // phase 1: depth digits (bits 0..30; depth > 0, sign bit clear) in 8,8,8,7
   hipLaunchKernelGGL(k_compact, dim3((unsigned)L.nb), dim3(kPreBlock), 0, st, proj.n_tiles,
-                     proj.rec, proj.rect, n, u32(L.vis_off), u32(L.dkey[0]), u32(L.didx[0]),
-                     diff, gw, lds_diff ? 0 : 1);
-  if (lds_diff) {
-    hipLaunchKernelGGL(k_tile_diff, dim3(kDiffParts), dim3(1024), (size_t)cells * 4, st,
-                       u32(L.didx[0]), proj.rect, counts, gw, cells, dparts);
-    hipLaunchKernelGGL(k_diff_sum, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
-                       (const int*)dparts, kDiffParts, cells, diff);
-  }
-  // tile digits: ceil(bits/8) balanced passes
-  const int tbits = bit_width((uint64_t)tiles_total);
-  const int npass = (tbits + 7) / 8;
-  int shs[3] = {0, 0, 0}, bs[3] = {1, 1, 1};
-  {
-    int sh = 0;
-    for (int k = 0; k < npass; ++k) {
-      bs[k] = tbits / npass + (k < tbits % npass ? 1 : 0);
-      shs[k] = sh;
-      sh += bs[k];
-    }
-  }
-  hipLaunchKernelGGL(k_tile_counts, dim3(1), dim3(1024), 0, st, diff, p.tiles_x, p.tiles_y,
-                     counts, ranges, u32(L.thist), npass, shs[0], bs[0], shs[1], bs[1], shs[2],
-                     bs[2]);
+                     proj.rec, n, u32(L.vis_off), u32(L.dkey[0]), u32(L.didx[0]));
   hipLaunchKernelGGL(k_hist_depth, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st,
                      u32(L.dkey[0]), counts, u32(L.dhist));
   uint32_t* counters = u32(L.counters);
   uint64_t* err = counts + 3;
-  // depth digits: bits 0..30 (depth > 0, sign bit clear) in 8,8,8,7
   for (int ps = 0; ps < 4; ++ps) {
     SweepArgs a{};
     a.keys_in = u32(L.dkey[ps & 1]);
@@ -761,44 +693,54 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     a.status = u32(L.dstatus) + (size_t)ps * L.dparts * kRadixBins;
     a.part_counter = counters + ps;
     a.err = err;
-    hipLaunchKernelGGL(k_onesweep<false>, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st, a,
-                       EmitArgs{});
+    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st, a);
   }
+  // instance offsets in depth order (used by the backward)
   hipLaunchKernelGGL(k_offsets, dim3((unsigned)L.eparts), dim3(kSortBlock), 0, st,
                      u32(L.didx[0]), proj.n_tiles, counts, u32(L.offs), u32(L.goffs),
                      u32(L.chunk_first), (uint64_t)capacity,
                      reinterpret_cast<uint64_t*>(ws + L.estatus), counters + 4, err);
-  EmitArgs em{};
-  em.didx = u32(L.didx[0]);
-  em.offs = u32(L.offs);
-  em.chunk_first = u32(L.chunk_first);
-  em.counts = counts;
-  em.rect = proj.rect;
-  em.tiles_x = p.tiles_x;
-  em.tile_base = 0;
-  for (int ps = 0; ps < npass; ++ps) {
-    const bool last = ps == npass - 1;
-    SweepArgs a{};
-    a.keys_in = u32(L.tkey[ps & 1]);
-    a.vals_in = u32(L.tval[ps & 1]);
-    a.keys_out = last ? nullptr : u32(L.tkey[(ps + 1) & 1]);
-    a.vals_out = last ? vals : u32(L.tval[(ps + 1) & 1]);
-    a.count = counts + 1;
-    a.cap = (uint64_t)capacity;
-    a.skip = counts + 2;
-    a.shift = shs[ps];
-    a.bits = bs[ps];
-    a.hist = u32(L.thist) + ps * kRadixBins;
-    a.status = u32(L.tstatus) + (size_t)ps * L.tparts * kRadixBins;
-    a.part_counter = counters + 5 + ps;
-    a.err = err;
-    a.keys64_out = last ? keys : nullptr;
+  // phase 2: split the depth-ordered list by tile, level by level
+  uint2* bins[2] = {reinterpret_cast<uint2*>(ws + L.bl_bins[0]),
+                    reinterpret_cast<uint2*>(ws + L.bl_bins[1])};
+  uint32_t* seg[2] = {u32(L.bl_seg[0]), u32(L.bl_seg[1])};
+  uint32_t* lists[2] = {u32(L.bl_list[0]), u32(L.bl_list[1])};
+  hipLaunchKernelGGL(k_bin_root, dim3(1), dim3(64), 0, st, counts, bins[0], seg[0]);
+  const uint32_t* in = u32(L.didx[0]);
+  int cur = 0;
+  for (int lev = L.bl_levels - 1; lev >= 0; --lev) {
+    const int side = 1 << (2 * lev);
+    BinLevel a{};
+    a.in = in;
+    a.pbins = bins[cur];
+    a.pseg = seg[cur];
+    a.cgx = (p.tiles_x + side - 1) / side;
+    a.cgy = (p.tiles_y + side - 1) / side;
+    a.pgx = (a.cgx + 3) / 4;
+    a.pgy = (a.cgy + 3) / 4;
+    a.side = side;
+    a.tiles_x = p.tiles_x, a.tiles_y = p.tiles_y;
+    a.rect = proj.rect;
+    a.counts = counts;
+    a.cnt = u32(L.bl_cnt);
+    a.tot = u32(L.bl_tot);
+    a.cbins = bins[cur ^ 1];
+    a.cseg = seg[cur ^ 1];
+    a.last = lev == 0;
+    a.out = a.last ? vals : lists[lev & 1];
+    a.ranges = ranges;
+    a.keys = a.last ? keys : nullptr;
     a.rec = proj.rec;
-    if (ps == 0)
-      hipLaunchKernelGGL(k_onesweep<true>, dim3((unsigned)L.tparts), dim3(kSortBlock), 0, st, a, em);
-    else
-      hipLaunchKernelGGL(k_onesweep<false>, dim3((unsigned)L.tparts), dim3(kSortBlock), 0, st, a,
-                         em);
+    const int64_t nparents = (int64_t)a.pgx * a.pgy;
+    const int64_t segs_max = capacity / kBinSeg + nparents + 1;
+    const unsigned grid = (unsigned)(segs_max < 4096 ? segs_max : 4096);
+    const int C = a.cgx * a.cgy;
+    hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_bin_totals, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_bin_write, dim3(grid), dim3(1024), 0, st, a);
+    in = a.out;
+    cur ^= 1;
   }
   return hipGetLastError();
 }

@@ -109,9 +109,26 @@ class CellView:
         self.vals = torch.empty((max(self.capacity, 1),), dtype=torch.int32, device=self.device)
         self.keys = (torch.empty((max(self.capacity, 1),), dtype=torch.int64, device=self.device)
                      if self.keep_keys else None)
-        nbytes = B.sx_sort_workspace_size(self.params.n, self.capacity, self.tiles)
-        self.ws = torch.empty((nbytes,), dtype=torch.uint8, device=self.device)
+        self.ws = torch.empty((self.sort_bytes(self.capacity),), dtype=torch.uint8,
+                              device=self.device)
         self.bwd_ws = None
+
+    def sort_bytes(self, capacity: int) -> int:
+        return B.sx_sort_workspace_size(self.params.n, capacity, self.tiles_x, self.tiles_y)
+
+    def backward_bytes(self, capacity: int) -> int:
+        return B.sx_backward_workspace_size(capacity, self.tiles)
+
+    def bind_instance_buffers(self, capacity: int, vals, ws, bwd_ws=None):
+        """Use caller-owned per-instance buffers (e.g. slices of an arena
+        shared by views that are not in flight together)."""
+        if ws.numel() < self.sort_bytes(capacity) or vals.numel() < max(capacity, 1):
+            raise ValueError("instance buffers too small for the capacity")
+        if bwd_ws is not None and bwd_ws.numel() < self.backward_bytes(capacity):
+            raise ValueError("backward workspace too small for the capacity")
+        self.capacity = int(capacity)
+        self.vals, self.ws, self.bwd_ws = vals, ws, bwd_ws
+        self.keys = None
 
     # ---------------------------------------------------------------- steps
     def preprocess(self):
@@ -155,8 +172,8 @@ class CellView:
             self.dpartial = torch.empty((self.H, self.W, 4), dtype=torch.float32,
                                         device=self.device)
         if self.bwd_ws is None:
-            nb = B.sx_backward_workspace_size(self.capacity, self.tiles)
-            self.bwd_ws = torch.empty((nb,), dtype=torch.uint8, device=self.device)
+            self.bwd_ws = torch.empty((self.backward_bytes(self.capacity),), dtype=torch.uint8,
+                                      device=self.device)
 
     def render_backward(self, dpartial, ddepth=None):
         self.ensure_backward_buffers()
@@ -244,3 +261,99 @@ class Frame:
         states = [v.state(g) for v, g in zip(self.views, grads)]
         B.sx_backward(states, self.boxes, self.c_cam, self.c_par, dout,
                       B.SX_BWD_ACCUMULATE if accumulate else 0)
+
+
+class BatchedViews:
+    """V views of one cell stepped together: one preprocess launch for all
+    views, a sort per view, one persistent render launch and one persistent
+    render-backward launch over a shared (view, tile) queue, and the views'
+    parameter gradients summed by the preprocess backward."""
+
+    def __init__(self, params: GaussianParams, cams: Sequence, settings, capacities=None,
+                 flags=0, device="cuda"):
+        if not 1 <= len(cams) <= B.SX_MAX_VIEWS:
+            raise ValueError(f"1..{B.SX_MAX_VIEWS} views per batch")
+        self.params = params
+        self.cams = list(cams)
+        self.settings = settings
+        self.views = [CellView(params, c, settings,
+                               None if capacities is None else capacities[v], flags=flags,
+                               device=device)
+                      for v, c in enumerate(self.cams)]
+        self.c_par = self.views[0].c_par
+        self.c_cams = [v.c_cam for v in self.views]
+        nb = B.sx_multi_workspace_size(self.c_cams, self.c_par)
+        self.ws = torch.empty((nb,), dtype=torch.uint8, device=device)
+        self.masks = [None] * len(self.views)
+
+    @classmethod
+    def from_views(cls, views: Sequence[CellView]) -> "BatchedViews":
+        """Batch existing views of one cell (their buffers are used as is)."""
+        if not 1 <= len(views) <= B.SX_MAX_VIEWS:
+            raise ValueError(f"1..{B.SX_MAX_VIEWS} views per batch")
+        self = cls.__new__(cls)
+        self.params = views[0].params
+        self.cams = [v.cam for v in views]
+        self.settings = views[0].settings
+        self.views = list(views)
+        self.c_par = self.views[0].c_par
+        self.c_cams = [v.c_cam for v in self.views]
+        nb = B.sx_multi_workspace_size(self.c_cams, self.c_par)
+        self.ws = torch.empty((nb,), dtype=torch.uint8, device=views[0].device)
+        self.masks = [None] * len(self.views)
+        return self
+
+    @property
+    def V(self):
+        return len(self.views)
+
+    def preprocess(self):
+        B.sx_preprocess_multi(self.views[0].c_g, self.c_cams, self.c_par,
+                              [v.c_proj for v in self.views])
+
+    def sort(self, sync=True):
+        return [v.sort(sync=sync) for v in self.views]
+
+    def _structs(self, backward=False, want_nblend=True):
+        out = []
+        for v, m in zip(self.views, self.masks):
+            s = B.SxView()
+            s.cam = v.c_cam
+            s.proj = v.c_proj
+            s.vals = B.ptr(v.vals)
+            s.tile_ranges = B.ptr(v.ranges)
+            s.sort_ws = B.ptr(v.ws)
+            s.capacity = v.capacity
+            s.mask = B.ptr(m)
+            s.partial = B.ptr(v.partial)
+            s.depth = None
+            s.last = B.ptr(v.last)
+            s.nblend = B.ptr(v.nblend) if want_nblend else None
+            if backward:
+                v.ensure_backward_buffers()
+                s.dpartial = B.ptr(v.dpartial)
+                s.g2d = B.ptr(v.g2d)
+                s.bwd_ws = B.ptr(v.bwd_ws)
+            out.append(s)
+        return out
+
+    def render(self, masks=None, want_nblend=True):
+        self.masks = list(masks) if masks is not None else [None] * self.V
+        for v, m in zip(self.views, self.masks):
+            v.mask = m
+        B.sx_render_multi(self._structs(want_nblend=want_nblend), self.c_par, self.ws)
+        return [v.partial for v in self.views]
+
+    def render_backward(self):
+        """Each view's upstream gradient must already be in view.dpartial."""
+        B.sx_render_backward_multi(self._structs(backward=True), self.params.n, self.c_par,
+                                   self.ws)
+
+    def preprocess_backward(self, grads: GaussianParams, accumulate=False):
+        """Sum of the views' parameter gradients into grads (cleared first
+        unless accumulate: the per-view call touches visible rows only)."""
+        if not accumulate:
+            for t in grads.tensors():
+                B.sx_fill_u32(t, 0)
+        for v in self.views:
+            v.preprocess_backward(grads, accumulate=True)

@@ -58,16 +58,22 @@ def test_size_queries(L):
     from paper_2606_18588_amd import binding as B
     assert B.sx_preprocess_blocks(0) == 1
     assert B.sx_preprocess_blocks(257) == 2
-    a = B.sx_sort_workspace_size(1000, 5000, 64)
-    b = B.sx_sort_workspace_size(1000, 50000, 64)
+    a = B.sx_sort_workspace_size(1000, 5000, 8, 8)
+    b = B.sx_sort_workspace_size(1000, 50000, 8, 8)
     assert 0 < a < b
+    # per instance: one bin list of 4 bytes for grids of two levels, two
+    # from three levels on (plus a little segment bookkeeping)
+    c = B.sx_sort_workspace_size(1000, 50000, 241, 136)
+    d = B.sx_sort_workspace_size(1000, 60000, 241, 136)
+    assert 8 * 10000 <= d - c <= 9 * 10000
+    assert 4 * 10000 <= b - a <= 5 * 45000
     c = B.sx_backward_workspace_size(5000, 64)
     assert c >= 5000 * 48
     with pytest.raises(B.SplaxelError) as e:
-        B.sx_sort_workspace_size(-1, 10, 4)
+        B.sx_sort_workspace_size(-1, 10, 2, 2)
     assert e.value.code == B.SX_EINVAL
     with pytest.raises(B.SplaxelError):
-        B.sx_sort_workspace_size(10, 1 << 30, 4)
+        B.sx_sort_workspace_size(10, 1 << 30, 2, 2)
 
 
 def _cam(B):

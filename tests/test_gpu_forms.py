@@ -1,0 +1,313 @@
+"""GPU tests of the usage forms built on the hot path: batched views (one
+preprocess launch, one persistent render launch and one persistent
+render-backward launch for V views of a cell) against the per-view calls,
+and the torch.autograd form against the FP64 oracle.
+
+Batched vs per-view is bit-exact for every forward output (projected
+records, tile counts, instance values, partial pixels, last index, blend
+counts): each (view, tile) work item owns its pixels.  Gradients agree to
+1e-5 of their largest entry: a Gaussian whose instance rows straddle a
+reduction chunk is summed with FP32 atomics, so its last bits depend on the
+order in which chunks finish, in either form.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import assert_same, big_box, compare_image, jump_bound, need_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+ST = synth.RenderSettings()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    need_gpu()
+    import torch
+    return torch
+
+
+def _orbit_cams():
+    """Three views of the tiny cube scene with ragged tile grids."""
+    sizes = [(128, 128), (96, 80), (168, 104)]
+    cams = []
+    for k, (w, h) in enumerate(sizes):
+        a = 0.7 + 2.1 * k
+        cams.append(synth.look_at_camera((3.2 * math.cos(a), 3.2 * math.sin(a), 0.9 + 0.3 * k),
+                                         (0.05, -0.02, 0.0), w, h, hfov_deg=60.0))
+    return cams
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("tile", ["16x16", "32x8"])
+def test_batched_views_bit_identical_to_per_view(torch_gpu, tile):
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    from paper_2606_18588_amd.pipeline import BatchedViews, CellView, GaussianParams
+    tw, th = (int(x) for x in tile.split("x"))
+    st = synth.RenderSettings(tile_w=tw, tile_h=th)
+    print(f"case: batched vs per-view tiny 3 views tile {tile}", flush=True)
+    scene = synth.tiny_scene(seed=5, n=6000)
+    cams = _orbit_cams()
+    params = GaussianParams.from_scene(scene)
+    bv = BatchedViews(params, cams, st)
+    solo = [CellView(params, c, st) for c in cams]
+    # forward: batched
+    bv.preprocess()
+    bv.sort(sync=True)
+    masks = [None, None, None]
+    # a mask on the second view: clear every third word of bits
+    words = (cams[1].width * cams[1].height + 31) // 32
+    m = torch.full((words,), -1, dtype=torch.int32, device="cuda")
+    m[::3] = 0x0F0F0F0F
+    masks[1] = m
+    bv.render(masks)
+    # forward: per view
+    for v, mk in zip(solo, masks):
+        v.preprocess()
+        v.sort(sync=True)
+        v.render(mk)
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(bv.views, solo)):
+        assert a.counts == b.counts, k
+        assert_same(_np(a.n_tiles), _np(b.n_tiles), f"tile counts view {k}")
+        vis = _np(a.n_tiles) > 0  # records of culled Gaussians are not written
+        assert_same(_np(a.rec)[vis], _np(b.rec)[vis], f"records view {k}")
+        assert_same(_np(a.rect)[vis], _np(b.rect)[vis], f"rects view {k}")
+        assert_same(_np(a.vals)[:a.counts[1]], _np(b.vals)[:b.counts[1]], f"values view {k}")
+        assert_same(_np(a.partial), _np(b.partial), f"partial view {k}")
+        assert_same(_np(a.last), _np(b.last), f"last view {k}")
+        assert_same(_np(a.nblend), _np(b.nblend), f"blend counts view {k}")
+    # one view against the oracle as well
+    ref = oracle.render(scene, cams[2], st)
+    compare_image(_np(bv.views[2].partial)[..., :3], ref["C"], ref["flags"],
+                  bound=jump_bound(st, 1.5))
+    # backward
+    rng = np.random.default_rng(7)
+    for a, b in zip(bv.views, solo):
+        a.ensure_backward_buffers()
+        b.ensure_backward_buffers()
+        d = torch.as_tensor(rng.normal(size=(a.H, a.W, 4)).astype(np.float32)).cuda()
+        a.dpartial.copy_(d)
+        b.dpartial.copy_(d)
+    gb = params.zeros_like()
+    bv.render_backward()
+    bv.preprocess_backward(gb)
+    gs = params.zeros_like()
+    for k, v in enumerate(solo):
+        v.render_backward(v.dpartial)
+        v.preprocess_backward(gs, accumulate=True)
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(bv.views, solo)):
+        vis = _np(a.n_tiles) > 0
+        e = rel_err(_np(a.g2d)[vis][:, :10], _np(b.g2d)[vis][:, :10])
+        assert e <= 1e-5, (f"screen-space grads view {k}", e)
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        e = rel_err(_np(getattr(gb, name)), _np(getattr(gs, name)))
+        assert e <= 1e-5, (name, e)
+
+
+def test_batched_views_sixteen_uneven(torch_gpu):
+    """The largest batch (16 views of uneven size, some empty) in one
+    launch each, per-view outputs bit-identical to the per-view calls."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.pipeline import BatchedViews, CellView, GaussianParams
+    print("case: batched 16 uneven views", flush=True)
+    scene = synth.tiny_scene(seed=9, n=4000)
+    rng = np.random.default_rng(11)
+    cams = []
+    for k in range(16):
+        w, h = int(rng.integers(17, 200)), int(rng.integers(9, 150))
+        a = rng.uniform(0, 2 * math.pi)
+        if k == 5:  # looks away from the scene: no visible Gaussian
+            cams.append(synth.look_at_camera((4 * math.cos(a), 4 * math.sin(a), 0.5),
+                                             (8 * math.cos(a), 8 * math.sin(a), 0.5), w, h))
+        else:
+            cams.append(synth.look_at_camera((3.5 * math.cos(a), 3.5 * math.sin(a), 1.0),
+                                             (0.0, 0.0, 0.0), w, h, hfov_deg=55.0))
+    params = GaussianParams.from_scene(scene)
+    bv = BatchedViews(params, cams, ST)
+    bv.preprocess()
+    bv.sort(sync=True)
+    bv.render()
+    torch.cuda.synchronize()
+    assert bv.views[5].counts[0] == 0
+    for k, c in enumerate(cams):
+        v = CellView(params, c, ST)
+        v.preprocess()
+        v.sort(sync=True)
+        v.render()
+        torch.cuda.synchronize()
+        assert_same(_np(bv.views[k].partial), _np(v.partial), f"partial view {k}")
+        assert_same(_np(bv.views[k].nblend), _np(v.nblend), f"blends view {k}")
+
+
+def test_batched_rejects_bad_batches(torch_gpu):
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    from paper_2606_18588_amd.pipeline import BatchedViews, GaussianParams
+    print("case: batched invalid", flush=True)
+    params = GaussianParams.from_scene(synth.tiny_scene(n=10))
+    with pytest.raises(ValueError):
+        BatchedViews(params, [synth.tiny_camera()] * 17, ST)
+    bv = BatchedViews(params, [synth.tiny_camera()] * 2, ST)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.SplaxelError) as e:
+        B.sx_render_multi(bv._structs(), bv.c_par, small)
+    assert e.value.code == B.SX_EINVAL
+
+
+# --------------------------------------------------------------- autograd --
+def test_autograd_gradients_match_oracle(torch_gpu):
+    """d(sum w * image)/d(params) through torch.autograd equals the oracle's
+    FP64 analytic gradient (itself pinned by central differences) on a
+    flag-free 64-Gaussian scene, K = 2 slab cells."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.autograd import render
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    print("case: autograd fd scene K=2", flush=True)
+    cam = synth.fd_camera()
+    for seed in range(700, 760):
+        sc = synth.fd_scene(seed)
+        part = synth.axis_slab_partition(sc, 2, np.linspace(-0.7, 0.7, 3))
+        scenes = part.cell_scenes(sc)
+        ref = oracle.forward(scenes, part.cells, cam, ST)
+        fl = np.bitwise_or.reduce([p["flags"] for p in ref.parts])
+        if not np.any(fl) and not np.any(ref.comp["flags"]):
+            break
+    else:
+        raise AssertionError("no flag-free scene")
+    params = [GaussianParams.from_scene(s) for s in scenes]
+    for p in params:
+        for t in p.tensors():
+            t.requires_grad_(True)
+    rgb, T = render(params, part.cells, cam, ST)
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=(cam.height, cam.width, 4))
+    wt = torch.as_tensor(w.astype(np.float32)).cuda()
+    loss = (rgb * wt[..., :3]).sum() + (T * wt[..., 3]).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(_np(rgb), ref.comp["rgb"], atol=1e-5)
+    gref = oracle.backward(scenes, part.cells, cam, ST, ref, w[..., :3], w[..., 3])
+    for k, p in enumerate(params):
+        for name, t in zip(("means", "log_scales", "quats", "opacity_logits", "sh"), p.tensors()):
+            assert t.grad is not None, (k, name)
+            e = rel_err(_np(t.grad).astype(np.float64), gref[k][name])
+            assert e <= 1e-3, (k, name, e)
+
+
+def test_autograd_training_reduces_loss(torch_gpu):
+    """A few Adam steps (sx_adam) on the L1 loss of a rendered target lower
+    the loss: the forward, the backward and the optimiser agree in sign."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.autograd import Adam, render
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    print("case: autograd training tiny", flush=True)
+    cam = synth.tiny_camera(64, 64)
+    target_scene = synth.tiny_scene(seed=21, n=800)
+    tp = GaussianParams.from_scene(target_scene)
+    with torch.no_grad():
+        trgb, _ = render([tp], [big_box()], cam, ST)
+    target = trgb.detach().clone()
+    start = synth.tiny_scene(seed=22, n=800)
+    p = GaussianParams.from_scene(start)
+    for t in p.tensors():
+        t.requires_grad_(True)
+    opt = Adam(p.tensors(), lr=5e-3)
+    losses = []
+    for _ in range(30):
+        rgb, _ = render([p], [big_box()], cam, ST)
+        loss = (rgb - target).abs().mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss.item()))
+    assert losses[-1] < 0.8 * losses[0], losses
+
+
+# ---------------------------------------------------------------- serving --
+def _requests(n, seed=13):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    t = 0.0
+    for k in range(n):
+        w, h = int(rng.integers(24, 200)), int(rng.integers(16, 160))
+        a = rng.uniform(0, 2 * math.pi)
+        cam = synth.look_at_camera((3.4 * math.cos(a), 3.4 * math.sin(a), rng.uniform(0.2, 1.5)),
+                                   (0.0, 0.0, 0.0), w, h, hfov_deg=rng.uniform(40, 75))
+        t += rng.exponential(2e-3)
+        reqs.append(synth.Request(t, cam, k))
+    return reqs
+
+
+def _server(torch, params, **kw):
+    from paper_2606_18588_amd.serve import Server
+    return Server(params, ST, max_width=200, max_height=160, **kw)
+
+
+def test_server_alone_vs_mix_bit_identical(torch_gpu):
+    """A request's image does not depend on the batch it was served in:
+    served in mixed batches (closed loop), alone, and by the plain per-view
+    path, the images are bit-identical; one is checked against the oracle."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    print("case: server alone vs mix", flush=True)
+    scene = synth.tiny_scene(seed=17, n=5000)
+    params = GaussianParams.from_scene(scene)
+    reqs = _requests(24)
+    srv = _server(torch, params, arena_bytes=256 << 20)
+    srv.calibrate(reqs[0].camera)
+    done = srv.serve(reqs, open_loop=False, keep_images=True)
+    assert sorted(d.rid for d in done) == list(range(len(reqs)))
+    assert srv.n_batches < len(reqs)  # requests were batched
+    mixed = srv.images
+    solo = _server(torch, params, max_batch=1, arena_bytes=256 << 20)
+    solo.calibrate(reqs[0].camera)
+    solo.serve(reqs, open_loop=False, keep_images=True)
+    plain = _server(torch, params, plain=True, arena_bytes=256 << 20)
+    plain.calibrate(reqs[0].camera)
+    plain.serve(reqs, open_loop=False, keep_images=True)
+    for r in reqs:
+        assert_same(_np(mixed[r.rid]), _np(solo.images[r.rid]), f"request {r.rid} alone")
+        assert_same(_np(mixed[r.rid]), _np(plain.images[r.rid]), f"request {r.rid} plain")
+    r = reqs[3]
+    ref = oracle.forward([scene], [big_box()], r.camera, ST)
+    compare_image(_np(mixed[r.rid])[..., :3], ref.comp["rgb"], ref.parts[0]["flags"],
+                  bound=jump_bound(ST, 1.5))
+
+
+def test_server_overflow_requeue_and_admission(torch_gpu):
+    """Under-estimated instance counts overflow the sort buffers: those
+    requests are re-queued with the exact count and their images still
+    match; a small arena splits the queue into many batches."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    print("case: server overflow + admission", flush=True)
+    scene = synth.tiny_scene(seed=17, n=5000)
+    params = GaussianParams.from_scene(scene)
+    reqs = _requests(20, seed=5)
+    ref = _server(torch, params, arena_bytes=256 << 20)
+    ref.calibrate(reqs[0].camera)
+    ref.serve(reqs, open_loop=False, keep_images=True)
+    srv = _server(torch, params, arena_bytes=256 << 20, safety=0.05)
+    srv.recent.append(1e-3)
+    done = srv.serve(reqs[:10], open_loop=False, keep_images=True)
+    assert srv.overflows > 0
+    assert sorted(d.rid for d in done) == list(range(10))
+    for r in reqs[:10]:
+        assert_same(_np(srv.images[r.rid]), _np(ref.images[r.rid]), f"request {r.rid}")
+    small = _server(torch, params, arena_bytes=6 << 20)
+    small.calibrate(reqs[0].camera)
+    done = small.serve(reqs, open_loop=True, keep_images=True)
+    assert small.n_batches > 4
+    for r in reqs:
+        assert_same(_np(small.images[r.rid]), _np(ref.images[r.rid]), f"request {r.rid}")
+    lat = [d.latency_s for d in done]
+    assert min(lat) >= 0.0

@@ -139,6 +139,26 @@ def test_sort_ragged_and_capacity(torch_gpu):
     assert c4[2] == 0 and c4[3] == 0
 
 
+def test_sort_radix_fallback_large_grid(torch_gpu):
+    """A tile grid too large for the LDS-resident counting emission (here
+    2048x1152 with 8x8 tiles: 36864 tiles) takes the onesweep tile-digit
+    passes; keys, values and ranges are still bit-exact."""
+    print("case: sort radix fallback 2048x1152 8x8", flush=True)
+    torch = torch_gpu
+    st = synth.RenderSettings(tile_w=8, tile_h=8)
+    scene = synth.make_cube_scene(8, 20000, log_scale=(-3.0, 0.6))
+    cam = synth.tiny_camera(2048, 1152)
+    _, v = _cell_view(torch, scene, cam, st)
+    v.preprocess()
+    counts = v.sort(sync=True)
+    keys, vals, ranges = oracle.sort_keys(scene, cam, st)
+    assert counts[1] == len(keys) and len(keys) > 4 * 4096
+    n = len(keys)
+    assert_same(v.keys[:n].cpu().numpy().view(np.uint64), keys, "keys")
+    assert_same(v.vals[:n].cpu().numpy().view(np.uint32), vals, "vals")
+    assert_ranges(v.ranges.cpu().numpy().view(np.uint32), ranges)
+
+
 def test_sort_async_overflow_flag(torch_gpu):
     """Without the synchronous count check an overflow sorts the first
     `capacity` instances, stays in bounds and raises the overflow flag."""
