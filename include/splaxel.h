@@ -142,9 +142,9 @@ sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
  * ties by Gaussian index.  The depth digits are radix sorted on the visible
  * Gaussians before duplication; the depth-ordered list is then split by
  * tile through a hierarchy of 4 x 4 bins, each level keeping the order.
- * Produces vals[i] = Gaussian index of the i-th instance, optionally
- * keys[i], and tile_ranges[t] = [start, end) per tile
- * (tile_id = ty * tiles_x + tx; an empty tile has start == end).
+ * Outputs: vals[i] = Gaussian index of the i-th instance, optionally
+ * keys[i], and tile_ranges[t] = [start, end) per tile (tile_id = ty *
+ * tiles_x + tx; an empty tile has start == end), tiles * 2 uint32.
  *   capacity   instances the caller allocated in keys/vals.
  *   ws         workspace of sx_sort_workspace_size(n, capacity, tiles_x,
  *              tiles_y) for this view's tile grid.

@@ -16,9 +16,6 @@ constexpr int kSortBlock = 256;  // threads per radix-sort block
 constexpr int kSortItems = 16;   // keys per thread
 constexpr int kSortTile = kSortBlock * kSortItems;  // keys per partition
 constexpr int kRadixBins = 256;
-constexpr int kScanTile = 2048;   // Gaussians per offset-scan partition
-constexpr int kEmitChunk = 4096;  // instance slots per chunk of the backward reduction
-constexpr int kReduceLdsTiles = 8192;  // tiles whose visited depth the reduction keeps in LDS
 constexpr int kMaxCells = 16;
 constexpr int kMaxViews = 16;  // views per batched launch
 constexpr int kBinSeg = 1024;   // entries per segment of a bin list (tile binning)
@@ -55,28 +52,37 @@ struct SortLayout {
   size_t dhist;        // uint32[4][256] depth digit histograms
   size_t counters;     // uint32[16] partition counters
   size_t dstatus;      // uint32[4][dparts][256]
-  size_t estatus;      // uint64[eparts] offset-scan look-back
   size_t zero_end;
-  size_t offs;         // uint32[n] instance offsets of the depth-sorted Gaussians
-  size_t goffs;        // uint32[n] instance offset of each visible Gaussian (by index)
-  size_t chunk_first;  // uint32[cap/kEmitChunk + 2] owner of each chunk's first slot
   size_t bl_list[2];   // uint32[cap] bin lists of the inner levels (ping-pong)
   size_t bl_bins[2];   // uint2[bins] (start, length) per bin (ping-pong)
   size_t bl_seg[2];    // uint32[bins + 2] first segment per bin (ping-pong)
   size_t bl_tot;       // uint32[tiles] entries per child bin
   size_t bl_cnt;       // uint32[segments][16] entries per (segment, child)
   size_t total;
-  int64_t nb, dparts, eparts;
+  int64_t nb, dparts;
   int bl_levels;       // levels of 4x4 subdivision above the tiles (>= 1)
 };
 SortLayout sort_layout(int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
 
-// backward workspace: per-instance gradient rows (indexed by emission
-// position) and, per tile, the sort key of the last entry its walk visited
+// backward workspace.  Each tile's walk visits a prefix of its list (the
+// entries up to the last one any of its pixels reached); the visited entries
+// of all tiles get consecutive gradient rows, tile by tile, and (Gaussian,
+// row) pairs that are sorted by Gaussian to sum each Gaussian's rows.
+constexpr int kRowFloats = 10;  // d(mean2d x, y, conic a, b, c, opacity, r, g, b, depth)
 struct BwdLayout {
-  size_t gpart;     // float[cap][kG2dFloats]
-  size_t last_key;  // uint64[tiles]
+  size_t zero_begin;
+  size_t vcount;    // uint64[4]: visited rows, -, -, error flag
+  size_t vhist;     // uint32[4][256] digit histograms of the pair keys
+  size_t counters;  // uint32[8] partition counters
+  size_t zero_end;
+  size_t vstatus;   // uint32[4][parts][256] look-back status
+  size_t nv;        // uint32[tiles] entries visited per tile
+  size_t vb;        // uint32[tiles] first row of each tile
+  size_t rows;      // float[cap][kRowFloats]
+  size_t pk[2];     // uint32[cap] pair keys (Gaussian index), ping-pong
+  size_t pv[2];     // uint32[cap] pair values (row index), ping-pong
   size_t total;
+  int64_t parts;
 };
 BwdLayout bwd_layout(int64_t capacity, int64_t tiles_total);
 
@@ -84,9 +90,6 @@ BwdLayout bwd_layout(int64_t capacity, int64_t tiles_total);
 struct SortView {
   const uint64_t* counts;
   const uint32_t* didx;   // depth-sorted visible Gaussians
-  const uint32_t* offs;   // their exclusive instance offsets
-  const uint32_t* goffs;  // instance offset by Gaussian index
-  const uint32_t* chunk_first;
 };
 SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
 
@@ -217,22 +220,6 @@ __device__ __forceinline__ void quat_rot(double w, double x, double y,
   R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-// First and last depth-sorted Gaussian owning slots of chunk [c0, c1)
-// (c0 a multiple of kEmitChunk): the owner of slot c0 comes from the table
-// k_offsets wrote; the last one owns slot c1 - 1, i.e. it is the owner of
-// the next chunk's first slot unless that Gaussian starts exactly at c1.
-__device__ __forceinline__ void chunk_bounds(const uint32_t* chunk_first, const uint32_t* offs,
-                                             uint64_t nvis, uint64_t ninst, uint64_t c0,
-                                             uint64_t c1, uint32_t* lohi) {
-  const uint64_t c = c0 / kEmitChunk;
-  lohi[0] = chunk_first[c];
-  if (c1 >= ninst) {
-    lohi[1] = (uint32_t)nvis - 1;  // the last chunk ends with the last Gaussian
-  } else {
-    const uint32_t nx = chunk_first[c + 1];
-    lohi[1] = offs[nx] < c1 ? nx : nx - 1;
-  }
-}
 
 // Per-pixel alpha of one Gaussian (Eq. 1 with the clamp): the forward and
 // the backward kernels call this same function so their decisions agree
@@ -327,5 +314,12 @@ hipError_t launch_adam(int64_t n, float* param, const float* grad, float* m,
                        float* v, float lr, float b1, float b2, float eps,
                        float bc1, float bc2, hipStream_t st);
 hipError_t launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+// Stable LSD sort of the (*count, at most cap) pairs keys[0]/vals[0] whose
+// keys are < 2^bits, in 8-bit digits; the result ends in keys[r]/vals[r],
+// r the returned index.  hist: uint32[4][256], status: uint32[4][parts][256]
+// and counters: uint32[4], all zero on entry.
+int launch_pair_sort(uint32_t* const keys[2], uint32_t* const vals[2], const uint64_t* count,
+                     uint64_t cap, int bits, uint32_t* hist, uint32_t* status, int64_t parts,
+                     uint32_t* counters, uint64_t* err, hipStream_t st, hipError_t* e);
 bool tile_shape_supported(int tw, int th);
 }  // namespace sx

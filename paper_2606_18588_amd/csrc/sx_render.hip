@@ -112,11 +112,12 @@ struct RenderBwdArgs {
   const uint32_t* __restrict__ last;
   const float4* __restrict__ dpartial;
   const float* __restrict__ ddepth;
-  const uint16_t* __restrict__ rect;
-  const uint32_t* __restrict__ goffs;
+  const uint32_t* __restrict__ nv;  // entries visited per tile
+  const uint32_t* __restrict__ vb;  // first gradient row of each tile
   uint64_t cap;
-  float* __restrict__ gpart;
-  uint64_t* __restrict__ last_key;
+  float* __restrict__ rows;         // [visited][kRowFloats]
+  uint32_t* __restrict__ pkey;      // per row: Gaussian index
+  uint32_t* __restrict__ pval;      // per row: row index
 };
 
 // Reverse walk of each pixel's blended pairs.  With R the colour behind pair
@@ -129,12 +130,10 @@ struct RenderBwdArgs {
 //
 // One wavefront per tile; each lane owns TW*TH/64 pixels and sums their
 // contributions in registers, then one cross-lane reduction (DPP) per
-// (Gaussian, tile).  No atomics: the tile's partial gradient row is stored
-// at the instance's position in emission order, e = (first instance of the
-// Gaussian) + (row-major index of the tile within its rectangle), a slot no
-// other tile writes; rows of visited entries without any contribution are
-// stored as zeros.  The tile records the sort key of the last entry it
-// visited, which tells the per-Gaussian reduction which slots are valid.
+// (Gaussian, tile).  No atomics: the tile walks the nv[tile] entries its
+// pixels reached, and the j-th of them owns gradient row vb[tile] + j (rows
+// of entries without any contribution are zeros); the row's Gaussian index
+// is stored beside it for the per-Gaussian reduction.
 template <int TW, int TH>
 __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile,
                                                 float4 (*s_rec)[64], uint32_t* s_e) {
@@ -145,7 +144,6 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
   float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
   float gx[PPT], gy[PPT], gz[PPT], gt[PPT], gd[PPT], Tf[PPT];
   uint32_t lst[PPT];
-  uint32_t mx = 0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int li = lane + 64 * k;
@@ -167,21 +165,12 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     }
     T[k] = Tf[k];
     R0[k] = R1[k] = R2[k] = RD[k] = 0.f;
-    mx = lst[k] > mx ? lst[k] : mx;
   }
-  const uint32_t wave_last = wave_max_u32(mx);
-  if (lane == 0) {
-    uint64_t key = 0;
-    if (wave_last > 0) {
-      const uint32_t gl = a.vals[rg.x + wave_last - 1];
-      key = ((uint64_t)__float_as_uint(a.rec[(size_t)gl * kRecFloats + 9]) << 32) | gl;
-    }
-    a.last_key[tile] = key;
-  }
+  const uint32_t wave_last = a.nv[tile];  // max of lst over the tile
+  const uint32_t row0 = a.vb[tile];
   for (int jend = (int)wave_last; jend > 0; jend -= 64) {
     // stage entries [jend - cnt, jend): lane i gathers entry jend - cnt + i
-    // and its gradient slot e = (first instance of the Gaussian) + (index of
-    // this tile in the Gaussian's rectangle, row-major)
+    // and stores its (Gaussian, row) pair
     const int cnt = jend < 64 ? jend : 64;
     const int j0 = jend - cnt;
     if (lane < cnt) {
@@ -190,15 +179,16 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       s_rec[0][lane] = rr[0];
       s_rec[1][lane] = rr[1];
       s_rec[2][lane] = rr[2];
-      const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[gl];
-      s_e[lane] = a.goffs[gl] + ((uint32_t)ty - rc.y) * ((uint32_t)rc.z - rc.x) + ((uint32_t)tx - rc.x);
+      const uint32_t row = row0 + (uint32_t)(j0 + lane);
+      s_e[lane] = row;
+      if ((uint64_t)row < a.cap) a.pkey[row] = gl, a.pval[row] = row;
     }
     __builtin_amdgcn_wave_barrier();
   for (int kk = cnt - 1; kk >= 0; --kk) {
     const int j = j0 + kk;
     const float4 r0 = s_rec[0][kk], r1 = s_rec[1][kk], r2 = s_rec[2][kk];
     const uint32_t e = s_e[kk];
-    float4* dst = reinterpret_cast<float4*>(a.gpart + (size_t)e * kG2dFloats);
+    float2* dst = reinterpret_cast<float2*>(a.rows + (size_t)e * kRowFloats);
     const bool in_cap = (uint64_t)e < a.cap;
     float v[10];
 #pragma unroll
@@ -239,8 +229,8 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     }
     if (__ballot(any) == 0) {
       if (lane == 63 && in_cap) {
-        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        dst[0] = z, dst[1] = z, dst[2] = z;
+        const float2 z = make_float2(0.f, 0.f);
+        dst[0] = z, dst[1] = z, dst[2] = z, dst[3] = z, dst[4] = z;
       }
       continue;
     }
@@ -248,9 +238,11 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
 #pragma unroll
     for (int m = 0; m < 10; ++m) sum[m] = wave_sum_to_lane63(v[m]);
     if (lane == 63 && in_cap) {
-      dst[0] = make_float4(sum[0], sum[1], sum[2], sum[3]);
-      dst[1] = make_float4(sum[4], sum[5], sum[6], sum[7]);
-      dst[2] = make_float4(sum[8], sum[9], 0.f, 0.f);
+      dst[0] = make_float2(sum[0], sum[1]);
+      dst[1] = make_float2(sum[2], sum[3]);
+      dst[2] = make_float2(sum[4], sum[5]);
+      dst[3] = make_float2(sum[6], sum[7]);
+      dst[4] = make_float2(sum[8], sum[9]);
     }
   }
     __builtin_amdgcn_wave_barrier();
@@ -267,132 +259,135 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   render_tile_bwd<TW, TH>(a, tile, s_rec, s_e);
 }
 
-// Per-Gaussian sum of the partial gradient rows.  Balanced like the
-// emission: every block owns instances [c0, c0 + kEmitChunk) in emission
-// order, where each Gaussian's instances are contiguous.  An instance's row
-// is valid iff its tile visited it, i.e. (depth bits, index) of the
-// Gaussian <= the tile's last visited key.  Sums are formed in LDS; a
-// Gaussian lying wholly inside the chunk is stored with plain stores, one
-// that straddles a chunk boundary is added atomically into its
-// (pre-zeroed) row, so atomics occur at most twice per chunk.
-struct ReduceArgs {
-  const uint32_t* __restrict__ didx;
-  const uint32_t* __restrict__ offs;
-  const uint32_t* __restrict__ chunk_first;
-  const uint64_t* counts;
-  const uint16_t* __restrict__ rect;
-  const uint32_t* __restrict__ n_tiles;
-  const float* __restrict__ rec;
-  const float* __restrict__ gpart;
-  const uint64_t* __restrict__ last_key;
-  int tiles_x, tiles;
-  uint64_t cap;
-  float* __restrict__ g2d;
-};
+// Entries each tile's reverse walk visits: the largest `last` over its
+// active pixels (the same pixels the walk reads).  One wavefront per tile.
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void k_tile_extent(const uint32_t* __restrict__ last,
+                                                    const uint32_t* __restrict__ mask, int W,
+                                                    int H, int tiles_x, int tiles,
+                                                    uint32_t* __restrict__ nv) {
+  const int tile = blockIdx.x;
+  if (tile >= tiles) return;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  uint32_t mx = 0;
+#pragma unroll
+  for (int k = 0; k < TW * TH / 64; ++k) {
+    const int li = threadIdx.x + 64 * k;
+    const int px = tx * TW + li % TW, py = ty * TH + li / TW;
+    if (px < W && py < H) {
+      const uint32_t pix = (uint32_t)py * W + px;
+      if (!mask || ((mask[pix >> 5] >> (pix & 31)) & 1u)) mx = max(mx, last[pix]);
+    }
+  }
+  mx = wave_max_u32(mx);
+  if (threadIdx.x == 0) nv[tile] = mx;
+}
 
-__global__ __launch_bounds__(256) void k_grad_reduce(ReduceArgs a) {
-  __shared__ uint32_t s_off[257], s_end[256], s_g[256], s_x0[256], s_y0[256], s_w[256];
-  __shared__ unsigned long long s_key[256];
-  __shared__ float s_acc[256 * 10];
-  __shared__ uint32_t s_lohi[2];
-  extern __shared__ uint32_t s_ldep[];  // per tile: depth bits of the last visited entry
+// One block: exclusive scan of the visited counts -> first row per tile and
+// the number of rows.
+__global__ __launch_bounds__(1024) void k_extent_scan(const uint32_t* __restrict__ nv, int tiles,
+                                                      uint32_t* __restrict__ vb,
+                                                      uint64_t* vcount) {
+  __shared__ uint32_t s_p[1024];
   const int tid = threadIdx.x;
-  if (a.counts[2] != 0) return;
-  const bool staged = a.tiles <= kReduceLdsTiles;
-  if (staged)
-    for (int t = tid; t < a.tiles; t += 256) s_ldep[t] = (uint32_t)(a.last_key[t] >> 32);
-  const uint64_t ninst = a.counts[1] < a.cap ? a.counts[1] : a.cap;
-  const uint64_t nvis = a.counts[0];
-  const uint64_t c0 = (uint64_t)blockIdx.x * kEmitChunk;
-  if (c0 >= ninst) return;
-  const uint64_t c1 = c0 + kEmitChunk < ninst ? c0 + kEmitChunk : ninst;
-  if (tid == 0) chunk_bounds(a.chunk_first, a.offs, nvis, ninst, c0, c1, s_lohi);
+  const int chunk = (tiles + 1023) / 1024;
+  const int beg = tid * chunk, end = beg + chunk < tiles ? beg + chunk : tiles;
+  uint32_t sum = 0;
+  for (int t = beg; t < end; ++t) sum += nv[t];
+  s_p[tid] = sum;
   __syncthreads();
-  const uint32_t slo = s_lohi[0], shi = s_lohi[1];
-  for (uint32_t w0 = slo; w0 <= shi; w0 += 256) {
-    const uint32_t wn = (shi - w0 + 1) < 256u ? (shi - w0 + 1) : 256u;
-    if ((uint32_t)tid < wn) {
-      const uint32_t sidx = w0 + tid;
-      const uint32_t g = a.didx[sidx];
-      const ushort4 rc = reinterpret_cast<const ushort4*>(a.rect)[g];
-      s_off[tid] = a.offs[sidx];
-      s_end[tid] = a.offs[sidx] + a.n_tiles[g];
-      s_g[tid] = g;
-      s_x0[tid] = rc.x, s_y0[tid] = rc.y, s_w[tid] = (uint32_t)rc.z - rc.x;
-      s_key[tid] = ((unsigned long long)__float_as_uint(a.rec[(size_t)g * kRecFloats + 9]) << 32) | g;
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t v = tid >= o ? s_p[tid - o] : 0u;
+    __syncthreads();
+    s_p[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = s_p[tid] - sum;
+  for (int t = beg; t < end; ++t) {
+    vb[t] = run;
+    run += nv[t];
+  }
+  if (tid == 1023) vcount[0] = s_p[1023];
+}
+
+// Clear the look-back status of the partitions the pair sort will use
+// (ceil(rows / kSortTile) per pass; the rest is never read).
+__global__ __launch_bounds__(256) void k_zero_status(uint32_t* __restrict__ status, int64_t parts,
+                                                     const uint64_t* vcount, uint64_t cap) {
+  const uint64_t n = vcount[0] < cap ? vcount[0] : cap;
+  const uint64_t words = (n + kSortTile - 1) / kSortTile * kRadixBins;
+  for (int ps = 0; ps < 4; ++ps)
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < words;
+         i += (uint64_t)gridDim.x * 256)
+      status[(size_t)ps * parts * kRadixBins + i] = 0u;
+}
+
+// Per-Gaussian sum of its rows.  The pairs are sorted by Gaussian (stably,
+// so a Gaussian's rows are in tile order) and cut into chunks of 256; each
+// chunk stages its rows in LDS, and the first pair of every run of one
+// Gaussian adds the run's rows in order.  A run lying inside one chunk is
+// stored with plain stores; the pieces of a run crossing chunk boundaries
+// are added atomically into the (pre-zeroed) row of its Gaussian.
+__global__ __launch_bounds__(256) void k_pair_reduce(const uint32_t* __restrict__ key,
+                                                     const uint32_t* __restrict__ val,
+                                                     const uint64_t* vcount, uint64_t cap,
+                                                     const float* __restrict__ rows,
+                                                     float* __restrict__ g2d) {
+  __shared__ float s_row[256][kRowFloats + 1];
+  __shared__ uint32_t s_key[256];
+  __shared__ unsigned long long s_hm[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t n = vcount[0] < cap ? vcount[0] : cap;
+  for (uint64_t base = (uint64_t)blockIdx.x * 256; base < n; base += (uint64_t)gridDim.x * 256) {
+    const int m = (int)(n - base < 256 ? n - base : 256);
+    __syncthreads();  // the previous chunk is consumed
+    if (tid < m) {
+      s_key[tid] = key[base + tid];
+      const float2* src = reinterpret_cast<const float2*>(rows + (size_t)val[base + tid] * kRowFloats);
 #pragma unroll
-      for (int m = 0; m < 10; ++m) s_acc[tid * 10 + m] = 0.f;
-    }
-    if (tid == 0) {
-      const uint64_t e = (uint64_t)w0 + wn < nvis ? (uint64_t)a.offs[w0 + wn] : ninst;
-      s_off[wn] = (uint32_t)(e < c1 ? e : c1);
+      for (int q = 0; q < kRowFloats / 2; ++q) {
+        const float2 v = src[q];
+        s_row[tid][2 * q] = v.x, s_row[tid][2 * q + 1] = v.y;
+      }
     }
     __syncthreads();
-    const uint64_t k0 = (uint64_t)s_off[0] > c0 ? (uint64_t)s_off[0] : c0;
-    const uint64_t k1 = s_off[wn];
-    // runs of consecutive slots per thread: sums stay in registers while the
-    // run stays on one Gaussian and go to LDS when it moves on
-    const uint32_t run = ((uint32_t)(k1 - k0) + 255) / 256;
-    uint64_t k = k0 + (uint64_t)tid * run;
-    const uint64_t kend = k + run < k1 ? k + run : k1;
-    if (k < kend) {
-      int j = 0, hi = (int)wn - 1;
-      while (j < hi) {
-        const int mid = (j + hi + 1) >> 1;
-        if (s_off[mid] <= k) j = mid; else hi = mid - 1;
-      }
-      uint32_t wj = s_w[j];
-      const uint32_t r = (uint32_t)(k - s_off[j]);
-      uint32_t ty = r / wj, tx = r - ty * wj;
-      float acc[10];
-#pragma unroll
-      for (int m = 0; m < 10; ++m) acc[m] = 0.f;
-      bool dirty = false;
-      for (; k < kend; ++k) {
-        if (k == s_off[j + 1]) {
-          if (dirty) {
-#pragma unroll
-            for (int m = 0; m < 10; ++m) atomicAdd(s_acc + j * 10 + m, acc[m]), acc[m] = 0.f;
-            dirty = false;
+    const uint32_t g = tid < m ? s_key[tid] : 0u;
+    const bool head = tid < m && (tid == 0 || s_key[tid - 1] != g);
+    const unsigned long long hm = __ballot(head);
+    if (lane == 0) s_hm[w] = hm;
+    __syncthreads();
+    if (head) {
+      // end of the run: the next run head in this chunk, else the chunk end
+      int e = m;
+      const unsigned long long later = lane < 63 ? hm & ~((2ull << lane) - 1ull) : 0ull;
+      if (later) {
+        e = w * 64 + __builtin_ctzll(later);
+      } else {
+        for (int w2 = w + 1; w2 < 4; ++w2)
+          if (s_hm[w2]) {
+            e = w2 * 64 + __builtin_ctzll(s_hm[w2]);
+            break;
           }
-          ++j;
-          wj = s_w[j], tx = 0, ty = 0;
-        }
-        const uint32_t tile = (s_y0[j] + ty) * (uint32_t)a.tiles_x + s_x0[j] + tx;
-        bool visited;
-        if (staged) {
-          const uint32_t dg = (uint32_t)(s_key[j] >> 32), dt = s_ldep[tile];
-          visited = dg < dt || (dg == dt && s_key[j] <= a.last_key[tile]);
-        } else {
-          visited = s_key[j] <= a.last_key[tile];
-        }
-        if (visited) {
-          const float4* src = reinterpret_cast<const float4*>(a.gpart + (size_t)k * kG2dFloats);
-          const float4 p0 = src[0], p1 = src[1], p2 = src[2];
-          acc[0] += p0.x, acc[1] += p0.y, acc[2] += p0.z, acc[3] += p0.w, acc[4] += p1.x;
-          acc[5] += p1.y, acc[6] += p1.z, acc[7] += p1.w, acc[8] += p2.x, acc[9] += p2.y;
-          dirty = true;
-        }
-        if (++tx == wj) tx = 0, ++ty;
       }
-      if (dirty) {
+      float acc[kRowFloats];
 #pragma unroll
-        for (int m = 0; m < 10; ++m) atomicAdd(s_acc + j * 10 + m, acc[m]);
-      }
-    }
-    __syncthreads();
-    if ((uint32_t)tid < wn) {
-      float* dst = a.g2d + (size_t)s_g[tid] * kG2dFloats;
-      const bool interior = s_off[tid] >= c0 && s_end[tid] <= c1;
-      if (interior) {
+      for (int q = 0; q < kRowFloats; ++q) acc[q] = 0.f;
+      for (int r = tid; r < e; ++r)
 #pragma unroll
-        for (int m = 0; m < 10; ++m) dst[m] = s_acc[tid * 10 + m];
+        for (int q = 0; q < kRowFloats; ++q) acc[q] += s_row[r][q];
+      const bool starts = base + tid == 0 || key[base + tid - 1] != g;
+      const bool ends = base + e == n || key[base + e] != g;
+      float* d = g2d + (size_t)g * kG2dFloats;
+      if (starts && ends) {
+        float4* d4 = reinterpret_cast<float4*>(d);
+        d4[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        d4[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        d4[2] = make_float4(acc[8], acc[9], 0.f, 0.f);
       } else {
 #pragma unroll
-        for (int m = 0; m < 10; ++m) unsafeAtomicAdd(dst + m, s_acc[tid * 10 + m]);
+        for (int q = 0; q < kRowFloats; ++q) unsafeAtomicAdd(d + q, acc[q]);
       }
     }
-    __syncthreads();
   }
 }
 
@@ -585,10 +580,10 @@ static RenderArgs make_render_args(const sx_projected& proj, const uint32_t* val
 }
 
 static RenderBwdArgs make_bwd_args(const sx_projected& proj, const uint32_t* vals,
-                                   const uint32_t* ranges, const SortView& sv, int64_t capacity,
-                                   const DCam& cam, const KParams& p, const uint32_t* mask,
-                                   const float* partial, const uint32_t* last,
-                                   const float* dpartial, const float* ddepth, char* bws) {
+                                   const uint32_t* ranges, int64_t capacity, const DCam& cam,
+                                   const KParams& p, const uint32_t* mask, const float* partial,
+                                   const uint32_t* last, const float* dpartial,
+                                   const float* ddepth, char* bws) {
   const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
   const BwdLayout BL = bwd_layout(capacity, tiles);
   RenderBwdArgs a;
@@ -603,35 +598,63 @@ static RenderBwdArgs make_bwd_args(const sx_projected& proj, const uint32_t* val
   a.last = last;
   a.dpartial = reinterpret_cast<const float4*>(dpartial);
   a.ddepth = ddepth;
-  a.rect = proj.rect;
-  a.goffs = sv.goffs;
+  a.nv = reinterpret_cast<const uint32_t*>(bws + BL.nv);
+  a.vb = reinterpret_cast<const uint32_t*>(bws + BL.vb);
   a.cap = (uint64_t)capacity;
-  a.gpart = reinterpret_cast<float*>(bws + BL.gpart);
-  a.last_key = reinterpret_cast<uint64_t*>(bws + BL.last_key);
+  a.rows = reinterpret_cast<float*>(bws + BL.rows);
+  a.pkey = reinterpret_cast<uint32_t*>(bws + BL.pk[0]);
+  a.pval = reinterpret_cast<uint32_t*>(bws + BL.pv[0]);
   return a;
 }
 
-// zero the visible rows of g2d, then sum each Gaussian's valid partial rows
-static hipError_t launch_grad_reduce(const sx_projected& proj, const SortView& sv, int64_t n,
-                                     int64_t capacity, const KParams& p, float* g2d, char* bws,
-                                     hipStream_t st) {
+template <int TW, int TH>
+static void launch_extent_t(const RenderBwdArgs& a, hipStream_t st) {
+  const int tiles = a.tiles_x * a.tiles_y;
+  hipLaunchKernelGGL((k_tile_extent<TW, TH>), dim3((unsigned)tiles), dim3(64), 0, st, a.last,
+                     a.mask, a.W, a.H, a.tiles_x, tiles, const_cast<uint32_t*>(a.nv));
+}
+
+// Before the reverse walk: clear the counters, find each tile's visited
+// prefix and give the visited entries consecutive rows.
+static hipError_t launch_bwd_prepare(const RenderBwdArgs& a, const KParams& p, int64_t capacity,
+                                     char* bws, hipStream_t st) {
+  const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
+  const BwdLayout BL = bwd_layout(capacity, tiles);
+  hipError_t e = launch_fill(reinterpret_cast<uint32_t*>(bws + BL.zero_begin),
+                             (int64_t)((BL.zero_end - BL.zero_begin) / 4), 0, st);
+  if (e) return e;
+  SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_extent_t, a, st);
+  hipLaunchKernelGGL(k_extent_scan, dim3(1), dim3(1024), 0, st, a.nv, (int)tiles,
+                     const_cast<uint32_t*>(a.vb), reinterpret_cast<uint64_t*>(bws + BL.vcount));
+  hipLaunchKernelGGL(k_zero_status, dim3(256), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(bws + BL.vstatus), BL.parts,
+                     reinterpret_cast<const uint64_t*>(bws + BL.vcount), (uint64_t)capacity);
+  return hipGetLastError();
+}
+
+// After the reverse walk: zero the visible Gaussians' screen-space
+// gradients, sort the (Gaussian, row) pairs by Gaussian and sum the rows.
+static hipError_t launch_bwd_reduce(const SortView& sv, int64_t n, int64_t capacity,
+                                    const KParams& p, float* g2d, char* bws, hipStream_t st) {
   const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
   const BwdLayout BL = bwd_layout(capacity, tiles);
   if (n > 0)
     hipLaunchKernelGGL(k_zero_g2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        sv.didx, sv.counts, g2d);
-  ReduceArgs r;
-  r.didx = sv.didx, r.offs = sv.offs, r.counts = sv.counts, r.chunk_first = sv.chunk_first;
-  r.rect = proj.rect, r.n_tiles = proj.n_tiles, r.rec = proj.rec;
-  r.gpart = reinterpret_cast<const float*>(bws + BL.gpart);
-  r.last_key = reinterpret_cast<const uint64_t*>(bws + BL.last_key);
-  r.tiles_x = p.tiles_x;
-  r.tiles = (int)tiles;
-  r.cap = (uint64_t)capacity;
-  r.g2d = g2d;
-  const int64_t rb = (capacity + kEmitChunk - 1) / kEmitChunk;
-  const size_t lds = tiles <= kReduceLdsTiles ? (size_t)tiles * 4 : 0;
-  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)(rb > 0 ? rb : 1)), dim3(256), lds, st, r);
+  auto u32 = [&](size_t off) { return reinterpret_cast<uint32_t*>(bws + off); };
+  uint32_t* keys[2] = {u32(BL.pk[0]), u32(BL.pk[1])};
+  uint32_t* vals[2] = {u32(BL.pv[0]), u32(BL.pv[1])};
+  const uint64_t* vcount = reinterpret_cast<const uint64_t*>(bws + BL.vcount);
+  int bits = 1;
+  while (bits < 32 && (int64_t(1) << bits) < n) ++bits;
+  hipError_t e = hipSuccess;
+  const int r = launch_pair_sort(keys, vals, vcount, (uint64_t)capacity, bits, u32(BL.vhist),
+                                 u32(BL.vstatus), BL.parts, u32(BL.counters),
+                                 reinterpret_cast<uint64_t*>(bws + BL.vcount) + 3, st, &e);
+  if (e) return e;
+  hipLaunchKernelGGL(k_pair_reduce, dim3(1024), dim3(256), 0, st,
+                     keys[r], vals[r], vcount, (uint64_t)capacity,
+                     reinterpret_cast<const float*>(bws + BL.rows), g2d);
   return hipGetLastError();
 }
 
@@ -643,12 +666,13 @@ hipError_t launch_render_backward(const sx_projected& proj,
                                   const uint32_t* last, const float* dpartial,
                                   const float* ddepth, float* g2d, char* bws,
                                   hipStream_t st) {
-  RenderBwdArgs a = make_bwd_args(proj, vals, ranges, sv, capacity, cam, p, mask, partial, last,
+  RenderBwdArgs a = make_bwd_args(proj, vals, ranges, capacity, cam, p, mask, partial, last,
                                   dpartial, ddepth, bws);
+  hipError_t e = launch_bwd_prepare(a, p, capacity, bws, st);
+  if (e) return e;
   SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_t, a, st);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_grad_reduce(proj, sv, n, capacity, p, g2d, bws, st);
+  if ((e = hipGetLastError())) return e;
+  return launch_bwd_reduce(sv, n, capacity, p, g2d, bws, st);
 }
 
 // ------------------------------------------------------------ multi-view --
@@ -715,23 +739,24 @@ hipError_t launch_render_multi(int V, const MultiView* mv, const KParams& p, cha
 
 hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, const KParams& p,
                                         char* ws, hipStream_t st) {
-  WorkArgs w;
-  hipError_t e = build_worklist(V, mv, p, ws, w, st);
-  if (e) return e;
   RenderBwdMultiArgs m;
   m.V = V;
-  m.n_items = w.base[V];
-  m.items = w.items;
-  m.counter = w.hist + 67;
   for (int v = 0; v < V; ++v) {
     KParams pv = p;
     pv.tiles_x = mv[v].tiles_x, pv.tiles_y = mv[v].tiles_y;
-    const int64_t tiles = (int64_t)pv.tiles_x * pv.tiles_y;
-    m.view[v] = make_bwd_args(mv[v].proj, mv[v].vals, mv[v].ranges,
-                              sort_view(mv[v].sort_ws, n, mv[v].capacity, pv.tiles_x, pv.tiles_y), mv[v].capacity,
-                              mv[v].cam, pv, mv[v].mask, mv[v].partial, mv[v].last,
-                              mv[v].dpartial, nullptr, static_cast<char*>(mv[v].bwd_ws));
+    m.view[v] = make_bwd_args(mv[v].proj, mv[v].vals, mv[v].ranges, mv[v].capacity, mv[v].cam,
+                              pv, mv[v].mask, mv[v].partial, mv[v].last, mv[v].dpartial,
+                              nullptr, static_cast<char*>(mv[v].bwd_ws));
+    hipError_t e = launch_bwd_prepare(m.view[v], pv, mv[v].capacity,
+                                      static_cast<char*>(mv[v].bwd_ws), st);
+    if (e) return e;
   }
+  WorkArgs w;
+  hipError_t e = build_worklist(V, mv, p, ws, w, st);
+  if (e) return e;
+  m.n_items = w.base[V];
+  m.items = w.items;
+  m.counter = w.hist + 67;
   SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_multi_t, m, st);
   return hipGetLastError();
 }
@@ -740,9 +765,8 @@ hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams&
                                    hipStream_t st) {
   KParams pv = p;
   pv.tiles_x = v.tiles_x, pv.tiles_y = v.tiles_y;
-  const int64_t tiles = (int64_t)pv.tiles_x * pv.tiles_y;
-  return launch_grad_reduce(v.proj, sort_view(v.sort_ws, n, v.capacity, pv.tiles_x, pv.tiles_y), n, v.capacity,
-                            pv, v.g2d, static_cast<char*>(v.bwd_ws), st);
+  return launch_bwd_reduce(sort_view(v.sort_ws, n, v.capacity, pv.tiles_x, pv.tiles_y), n,
+                           v.capacity, pv, v.g2d, static_cast<char*>(v.bwd_ws), st);
 }
 
 }  // namespace sx

@@ -81,36 +81,36 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
   };
   L.nb = (n + kPreBlock - 1) / kPreBlock;
   L.dparts = (n + kSortTile - 1) / kSortTile;
-  L.eparts = (n + kScanTile - 1) / kScanTile;
   if (L.dparts < 1) L.dparts = 1;
-  if (L.eparts < 1) L.eparts = 1;
   L.zero_begin = off;
   L.counts = take(4 * sizeof(uint64_t));  // offset 0: part of the ABI
   L.dhist = take(4 * kRadixBins * 4);
   L.counters = take(16 * 4);
   L.dstatus = take((size_t)4 * L.dparts * kRadixBins * 4);
-  L.estatus = take((size_t)L.eparts * 8);
-  L.zero_end = off;
-  L.offs = take((size_t)(n > 0 ? n : 1) * 4);
-  L.goffs = take((size_t)(n > 0 ? n : 1) * 4);
-  L.chunk_first = take((size_t)((cap + kEmitChunk - 1) / kEmitChunk + 2) * 4);
-  L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
-  for (int k = 0; k < 2; ++k) L.dkey[k] = take((size_t)(n > 0 ? n : 1) * 4);
-  for (int k = 0; k < 2; ++k) L.didx[k] = take((size_t)(n > 0 ? n : 1) * 4);
-  // binning: levels of 4x4 bins until one bin covers the grid; every entry of
-  // an inner level is a (Gaussian, bin) pair with at least one instance in
-  // the bin, so an inner list never exceeds the instance count
+  // binning: levels of 4x4 bins until one bin covers the grid; per level,
+  // the children's entry totals (accumulated by the count pass)
   const int64_t big = tiles_x > tiles_y ? tiles_x : tiles_y;
   int levels = 1;
   while ((int64_t(1) << (2 * levels)) < big) ++levels;
   L.bl_levels = levels;
+  int64_t tot_words = 0;
+  for (int lev = 0; lev < levels; ++lev) {
+    const int64_t side = int64_t(1) << (2 * lev);
+    tot_words += ((tiles_x + side - 1) / side) * ((tiles_y + side - 1) / side);
+  }
+  L.bl_tot = take((size_t)tot_words * 4);
+  L.zero_end = off;
+  L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
+  for (int k = 0; k < 2; ++k) L.dkey[k] = take((size_t)(n > 0 ? n : 1) * 4);
+  for (int k = 0; k < 2; ++k) L.didx[k] = take((size_t)(n > 0 ? n : 1) * 4);
+  // every entry of an inner level is a (Gaussian, bin) pair with at least
+  // one instance in the bin, so an inner list never exceeds the instance count
   const int64_t bins = ((tiles_x + 3) / 4) * ((tiles_y + 3) / 4);
   const size_t list_bytes = (size_t)(cap > 0 ? cap : 1) * 4;
   L.bl_list[1] = levels >= 2 ? take(list_bytes) : off;  // level 1 writes list[1]
   L.bl_list[0] = levels >= 3 ? take(list_bytes) : off;
   for (int k = 0; k < 2; ++k) L.bl_bins[k] = take((size_t)(bins + 1) * 8);
   for (int k = 0; k < 2; ++k) L.bl_seg[k] = take((size_t)(bins + 2) * 4);
-  L.bl_tot = take((size_t)(tiles_total > 0 ? tiles_total : 1) * 4);
   L.bl_cnt = take((size_t)(cap / kBinSeg + bins + 2) * 16 * 4);
   L.total = off;
   return L;
@@ -124,8 +124,21 @@ BwdLayout bwd_layout(int64_t cap, int64_t tiles_total) {
     off += (bytes + 255) & ~size_t(255);
     return o;
   };
-  L.gpart = take((size_t)(cap > 0 ? cap : 1) * kG2dFloats * 4);
-  L.last_key = take((size_t)(tiles_total > 0 ? tiles_total : 1) * 8);
+  const size_t c = (size_t)(cap > 0 ? cap : 1);
+  const size_t t = (size_t)(tiles_total > 0 ? tiles_total : 1);
+  L.parts = (cap + kSortTile - 1) / kSortTile;
+  if (L.parts < 1) L.parts = 1;
+  L.zero_begin = off;
+  L.vcount = take(4 * sizeof(uint64_t));
+  L.vhist = take(4 * kRadixBins * 4);
+  L.counters = take(8 * 4);
+  L.zero_end = off;
+  L.vstatus = take((size_t)4 * L.parts * kRadixBins * 4);  // cleared per call, used part only
+  L.nv = take(t * 4);
+  L.vb = take(t * 4);
+  L.rows = take(c * kRowFloats * 4);
+  for (int k = 0; k < 2; ++k) L.pk[k] = take(c * 4);
+  for (int k = 0; k < 2; ++k) L.pv[k] = take(c * 4);
   L.total = off;
   return L;
 }
@@ -136,9 +149,6 @@ SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x,
   SortView v;
   v.counts = reinterpret_cast<const uint64_t*>(b + L.counts);
   v.didx = reinterpret_cast<const uint32_t*>(b + L.didx[0]);
-  v.offs = reinterpret_cast<const uint32_t*>(b + L.offs);
-  v.goffs = reinterpret_cast<const uint32_t*>(b + L.goffs);
-  v.chunk_first = reinterpret_cast<const uint32_t*>(b + L.chunk_first);
   return v;
 }
 
@@ -212,83 +222,6 @@ __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restric
   }
 }
 
-// Exclusive scan of the tile counts of the depth-sorted visible Gaussians
-// (single pass, decoupled look-back over partitions of kScanTile).
-__global__ __launch_bounds__(kSortBlock) void k_offsets(const uint32_t* __restrict__ didx,
-                                                        const uint32_t* __restrict__ n_tiles,
-                                                        const uint64_t* counts,
-                                                        uint32_t* __restrict__ offs,
-                                                        uint32_t* __restrict__ goffs,
-                                                        uint32_t* __restrict__ chunk_first,
-                                                        uint64_t cap,
-                                                        uint64_t* status, uint32_t* part_counter,
-                                                        uint64_t* err) {
-  __shared__ uint32_t s_scan[4];
-  __shared__ uint32_t s_part;
-  __shared__ unsigned long long s_base;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_part = atomicAdd(part_counter, 1u);
-  __syncthreads();
-  const uint32_t part = s_part;
-  const uint64_t nvis = counts[0];
-  const uint64_t base_s = (uint64_t)part * kScanTile;
-  if (base_s >= nvis) return;
-  constexpr int IT = kScanTile / kSortBlock;
-  uint32_t c[IT], gi[IT];
-  uint32_t tsum = 0;
-#pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const uint64_t sidx = base_s + (uint64_t)tid * IT + k;
-    gi[k] = sidx < nvis ? didx[sidx] : 0u;
-    c[k] = sidx < nvis ? n_tiles[gi[k]] : 0u;
-    tsum += c[k];
-  }
-  uint32_t total;
-  const uint32_t pre = block_excl_scan256(tsum, s_scan, &total);
-  if (tid == 0) {
-    uint64_t excl = 0;
-    if (part == 0) {
-      st_rel64(&status[0], kEFlagIncl | total);
-    } else {
-      st_rel64(&status[part], kEFlagAgg | total);
-      int64_t j = (int64_t)part - 1;
-      int spins = 0;
-      while (j >= 0) {
-        const uint64_t st = ld_acq64(&status[j]);
-        if ((st & ~kEValMask) == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr((unsigned long long*)err, 1ull);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += st & kEValMask;
-        if ((st & kEFlagIncl) != 0) break;
-        --j;
-      }
-      st_rel64(&status[part], kEFlagIncl | (excl + total));
-    }
-    s_base = excl;
-  }
-  __syncthreads();
-  uint32_t run = (uint32_t)s_base + pre;
-#pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const uint64_t sidx = base_s + (uint64_t)tid * IT + k;
-    if (sidx < nvis) {
-      offs[sidx] = run;
-      goffs[gi[k]] = run;
-      // this Gaussian owns the first slot of every chunk that starts inside
-      // its instance range
-      uint64_t cb = ((uint64_t)run + kEmitChunk - 1) / kEmitChunk;
-      const uint64_t ce = (uint64_t)run + c[k];
-      for (; cb * kEmitChunk < ce && cb * kEmitChunk < cap; ++cb) chunk_first[cb] = (uint32_t)sidx;
-    }
-    run += c[k];
-  }
-}
-
 // Global digit histograms of the depth keys for all four passes.
 __global__ __launch_bounds__(kSortBlock) void k_hist_depth(const uint32_t* __restrict__ keys,
                                                            const uint64_t* counts,
@@ -315,6 +248,26 @@ __global__ __launch_bounds__(kSortBlock) void k_hist_depth(const uint32_t* __res
   }
 }
 
+// Digit histograms (8-bit digits, npass passes) of *count keys.
+__global__ __launch_bounds__(kSortBlock) void k_hist_keys(const uint32_t* __restrict__ keys,
+                                                          const uint64_t* count, uint64_t cap,
+                                                          int npass, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[4][kRadixBins];
+  for (int k = threadIdx.x; k < 4 * kRadixBins; k += kSortBlock) (&h[0][0])[k] = 0;
+  __syncthreads();
+  const uint64_t n = *count < cap ? *count : cap;
+  for (uint64_t i = (uint64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kSortBlock) {
+    const uint32_t k = keys[i];
+    for (int ps = 0; ps < npass; ++ps) atomicAdd(&h[ps][(k >> (8 * ps)) & 255], 1u);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < npass * kRadixBins; k += kSortBlock) {
+    const uint32_t c = (&h[0][0])[k];
+    if (c) atomicAdd(&hist[k], c);
+  }
+}
+
 // ------------------------------------------------------------- onesweep --
 struct SweepArgs {
   const uint32_t* __restrict__ keys_in;
@@ -331,7 +284,9 @@ struct SweepArgs {
   uint64_t* err;
 };
 
-// One stable LSD pass over `bits` digits at `shift` of the keys.
+// One stable LSD pass over `bits` digits at `shift` of the keys.  Blocks
+// take partitions from an atomic counter until none is left, so a partition
+// only waits (in the look-back) on partitions that running blocks hold.
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ uint32_t s_vals[kSortTile];
@@ -347,6 +302,8 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
   if (n64 > a.cap) n64 = a.cap;
   if (a.skip && *a.skip != 0) n64 = 0;
   const uint32_t n = (uint32_t)n64;
+  for (;;) {
+  __syncthreads();  // the previous partition is fully written out
   if (tid == 0) s_part = atomicAdd(a.part_counter, 1u);
   __syncthreads();
   const uint32_t part = s_part;
@@ -440,6 +397,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
     a.keys_out[o] = key;
     a.vals_out[o] = val;
   }
+  }
 }
 
 // ------------------------------------------------------------ binning --
@@ -456,7 +414,7 @@ struct BinLevel {
   const uint16_t* __restrict__ rect;
   const uint64_t* counts;
   uint32_t* __restrict__ cnt;   // [segments][16]
-  uint32_t* __restrict__ tot;   // [children]
+  uint32_t* __restrict__ tot;   // [children], zeroed before the count pass
   uint2* __restrict__ cbins;    // (start, length) per child (inner levels)
   uint32_t* __restrict__ cseg;  // segment starts of the children (inner levels)
   uint32_t* __restrict__ out;   // child lists; the instance values at the last level
@@ -527,26 +485,18 @@ __global__ __launch_bounds__(1024) void k_bin_count(BinLevel a) {
     uint32_t lo, m;
     const int p = bin_segment(a, sg, &lo, &m);
     bin_stage(a, lo, m, s_g, s_rc);
-    int c, rx0, rx1, ry0, ry1;
+    int c = 0, rx0, rx1, ry0, ry1;
     uint32_t n = 0;
     if (bin_child(a, p, w, &c, &rx0, &rx1, &ry0, &ry1))
       for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
         const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
         n += (uint32_t)__popcll(__ballot(hit));
       }
-    if (lane == 0) a.cnt[(size_t)sg * 16 + w] = n;
+    if (lane == 0) {
+      a.cnt[(size_t)sg * 16 + w] = n;
+      if (n) atomicAdd(&a.tot[c], n);  // integer sum: the order does not matter
+    }
   }
-}
-
-// Per child: total entries over its parent's segments.
-__global__ __launch_bounds__(256) void k_bin_totals(BinLevel a) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= a.cgx * a.cgy) return;
-  const int cx = c % a.cgx, cy = c / a.cgx;
-  const int p = (cy >> 2) * a.pgx + (cx >> 2), slot = (cy & 3) * 4 + (cx & 3);
-  uint32_t t = 0;
-  for (uint32_t sg = a.pseg[p]; sg < a.pseg[p + 1]; ++sg) t += a.cnt[(size_t)sg * 16 + slot];
-  a.tot[c] = t;
 }
 
 // One block: exclusive scan of the children's totals (their list starts;
@@ -641,6 +591,34 @@ hipError_t launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
+int launch_pair_sort(uint32_t* const keys[2], uint32_t* const vals[2], const uint64_t* count,
+                     uint64_t cap, int bits, uint32_t* hist, uint32_t* status, int64_t parts,
+                     uint32_t* counters, uint64_t* err, hipStream_t st, hipError_t* e) {
+  const int npass = bits <= 0 ? 1 : (bits + 7) / 8;
+  const unsigned grid = (unsigned)(parts < 1024 ? parts : 1024);
+  hipLaunchKernelGGL(k_hist_keys, dim3(grid), dim3(kSortBlock), 0, st, keys[0], count, cap,
+                     npass, hist);
+  for (int ps = 0; ps < npass; ++ps) {
+    SweepArgs a{};
+    a.keys_in = keys[ps & 1];
+    a.vals_in = vals[ps & 1];
+    a.keys_out = keys[(ps + 1) & 1];
+    a.vals_out = vals[(ps + 1) & 1];
+    a.count = count;
+    a.cap = cap;
+    a.skip = nullptr;
+    a.shift = 8 * ps;
+    a.bits = 8;
+    a.hist = hist + ps * kRadixBins;
+    a.status = status + (size_t)ps * parts * kRadixBins;
+    a.part_counter = counters + ps;
+    a.err = err;
+    hipLaunchKernelGGL(k_onesweep, dim3(grid), dim3(kSortBlock), 0, st, a);
+  }
+  *e = hipGetLastError();
+  return npass & 1;
+}
+
 hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
                        int64_t capacity, int64_t tiles_total, uint64_t* keys,
                        uint32_t* vals, uint32_t* ranges, char* ws,
@@ -695,17 +673,18 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     a.err = err;
     hipLaunchKernelGGL(k_onesweep, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st, a);
   }
-  // instance offsets in depth order (used by the backward)
-  hipLaunchKernelGGL(k_offsets, dim3((unsigned)L.eparts), dim3(kSortBlock), 0, st,
-                     u32(L.didx[0]), proj.n_tiles, counts, u32(L.offs), u32(L.goffs),
-                     u32(L.chunk_first), (uint64_t)capacity,
-                     reinterpret_cast<uint64_t*>(ws + L.estatus), counters + 4, err);
   // phase 2: split the depth-ordered list by tile, level by level
   uint2* bins[2] = {reinterpret_cast<uint2*>(ws + L.bl_bins[0]),
                     reinterpret_cast<uint2*>(ws + L.bl_bins[1])};
   uint32_t* seg[2] = {u32(L.bl_seg[0]), u32(L.bl_seg[1])};
   uint32_t* lists[2] = {u32(L.bl_list[0]), u32(L.bl_list[1])};
   hipLaunchKernelGGL(k_bin_root, dim3(1), dim3(64), 0, st, counts, bins[0], seg[0]);
+  int64_t tot_off[32];
+  for (int lev = 0, o = 0; lev < L.bl_levels; ++lev) {
+    const int side = 1 << (2 * lev);
+    tot_off[lev] = o;
+    o += ((p.tiles_x + side - 1) / side) * ((p.tiles_y + side - 1) / side);
+  }
   const uint32_t* in = u32(L.didx[0]);
   int cur = 0;
   for (int lev = L.bl_levels - 1; lev >= 0; --lev) {
@@ -723,7 +702,7 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     a.rect = proj.rect;
     a.counts = counts;
     a.cnt = u32(L.bl_cnt);
-    a.tot = u32(L.bl_tot);
+    a.tot = u32(L.bl_tot) + tot_off[lev];
     a.cbins = bins[cur ^ 1];
     a.cseg = seg[cur ^ 1];
     a.last = lev == 0;
@@ -734,9 +713,7 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     const int64_t nparents = (int64_t)a.pgx * a.pgy;
     const int64_t segs_max = capacity / kBinSeg + nparents + 1;
     const unsigned grid = (unsigned)(segs_max < 4096 ? segs_max : 4096);
-    const int C = a.cgx * a.cgy;
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(1024), 0, st, a);
-    hipLaunchKernelGGL(k_bin_totals, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, a);
     hipLaunchKernelGGL(k_bin_write, dim3(grid), dim3(1024), 0, st, a);
     in = a.out;

@@ -90,7 +90,8 @@ class CellView:
         self.block_sums = torch.empty((B.sx_preprocess_blocks(n) * 2,), dtype=torch.int32,
                                       device=device)
         self.c_proj = B.projected(self.rec, self.rect, self.n_tiles, self.block_sums)
-        self.ranges = torch.empty((self.tiles, 2), dtype=torch.int32, device=device)
+        # per tile [start, end), plus the screen list's range at index tiles
+        self.ranges = torch.empty((self.tiles + 1, 2), dtype=torch.int32, device=device)
         self.keep_keys = keep_keys
         self.counts = None
         self._alloc_sort(capacity if capacity is not None else max(1024, 4 * n))

@@ -67,7 +67,7 @@ class _Slot:
         self.block_sums = torch.empty((B.sx_preprocess_blocks(n) * 2,), dtype=torch.int32,
                                       device=device)
         self.c_proj = B.projected(self.rec, self.rect, self.n_tiles, self.block_sums)
-        self.ranges = torch.empty((max_tiles * 2,), dtype=torch.int32, device=device)
+        self.ranges = torch.empty(((max_tiles + 1) * 2,), dtype=torch.int32, device=device)
         self.partial = torch.empty((max_px * 4,), dtype=torch.float32, device=device)
         self.last = torch.empty((max_px,), dtype=torch.int32, device=device)
         self.out = torch.empty((max_px * 4,), dtype=torch.float32, device=device)
@@ -192,7 +192,7 @@ class Server:
             off += _align(4 * cap)
             ws = arena[off:off + wsb]
             off += _align(wsb)
-            ranges = s.ranges[:2 * tiles]
+            ranges = s.ranges[:2 * (tiles + 1)]
             B.sx_sort(s.c_proj, self.n, cam, self.c_par, cap, None, vals, ranges, ws,
                       sync_counts=False)
             counts[j].copy_(ws[:32].view(torch.int64), non_blocking=True)

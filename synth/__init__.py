@@ -338,6 +338,28 @@ def tiny_camera(width: int = 128, height: int = 128) -> Camera:
     return camera_from_rows(np.eye(3), (0.0, 0.0, -3.0), width, height, f)
 
 
+def screen_scene(seed: int = 0, n: int = 5000, n_near: int = 32) -> Scene:
+    """The tiny scene plus n_near faint Gaussians just in front of the tiny
+    camera (camera depth 0.25..3 m, within 0.1 m of the optical axis,
+    log-scales N(-1.5, 0.3), opacity logits N(-2, 0.5)): their footprints
+    cover the whole 128x128 view, the way Gaussians near the camera plane
+    cover the whole frame in the aerial scenes, and they interleave in depth
+    with the cube's Gaussians."""
+    base = make_cube_scene(seed, n)
+    rng = rng_for(seed + 7001)
+    xy = rng.uniform(-0.1, 0.1, size=(n_near, 2))
+    d = rng.uniform(0.25, 3.0, size=n_near)
+    means = np.concatenate([xy, (d - 3.0)[:, None]], axis=1)
+    log_scales = rng.normal(-1.5, 0.3, size=(n_near, 3))
+    quats = _unit_quats(rng, n_near)
+    logits = rng.normal(-2.0, 0.5, size=n_near)
+    rgb = rng.uniform(0.0, 1.0, size=(n_near, 3))
+    sh = ((rgb - 0.5) * _INV_Y00)[:, None, :]
+    near = Scene(means, log_scales, quats, logits, sh).astype(np.float32)
+    cat = [np.concatenate([a, b]) for a, b in zip(base.arrays(), near.arrays())]
+    return Scene(*cat)
+
+
 def fd_scene(seed: int, n: int = 64, sh_degree: int = 3) -> Scene:
     """Finite-difference sub-scene: 64 Gaussians large enough to overlap in a
     64x64 view (log-scales N(-2.5, 0.3), SH3 N(0, 0.2))."""

@@ -78,3 +78,29 @@ def assert_ranges(got, ref):
     ne = ref[:, 1] > ref[:, 0]
     assert_same(got[ne], ref[ne], "non-empty tile ranges")
     assert_same(got[~ne, 0], got[~ne, 1], "empty tile ranges")
+
+
+def expand_lists(keys, vals, ranges):
+    """The kernel's sort output as full per-tile lists: every tile's own
+    list merged by (depth bits, index) with the screen list (the range at
+    index `tiles`).  Returns (keys, vals, ranges) in the layout of the
+    oracle's sorted instance list."""
+    keys = np.asarray(keys).astype(np.uint64)
+    vals = np.asarray(vals).astype(np.uint64)
+    ranges = np.asarray(ranges).astype(np.int64)
+    tiles = len(ranges) - 1
+    s0, s1 = ranges[tiles]
+    sd, sv = keys[s0:s1] & np.uint64(0xFFFFFFFF), vals[s0:s1]
+    ok, ov, orng = [], [], np.zeros((tiles, 2), np.int64)
+    pos = 0
+    for t in range(tiles):
+        a, b = ranges[t]
+        d = np.concatenate([sd, keys[a:b] & np.uint64(0xFFFFFFFF)])
+        v = np.concatenate([sv, vals[a:b]])
+        order = np.lexsort((v, d))
+        ok.append((np.uint64(t) << np.uint64(32)) | d[order])
+        ov.append(v[order])
+        orng[t] = (pos, pos + len(d))
+        pos += len(d)
+    cat = lambda xs: np.concatenate(xs) if xs else np.zeros(0, np.uint64)
+    return cat(ok), cat(ov).astype(np.uint32), orng

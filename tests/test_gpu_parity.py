@@ -17,8 +17,8 @@ import pytest
 import oracle
 import synth
 from gpu_helpers import (assert_ranges, assert_same, big_box, compare_image,
-                         grid_cells_xy, jump_bound, need_gpu, rec_fields,
-                         rel_err)
+                         expand_lists, grid_cells_xy, jump_bound, need_gpu,
+                         rec_fields, rel_err)
 
 pytestmark = pytest.mark.gpu
 ST = synth.RenderSettings()
@@ -102,13 +102,18 @@ def test_sort_keys_vals_ranges_bit_exact(torch_gpu, tile):
     torch.cuda.synchronize()
     keys, vals, ranges = oracle.sort_keys(scene, cam, st)
     ref_vis = int(oracle.preprocess(scene, cam, st)["valid"].sum())
-    assert counts == (ref_vis, len(keys))
+    assert counts[0] == ref_vis
+    _check_lists(v, counts, keys, vals, ranges)
+
+
+def _check_lists(v, counts, keys, vals, ranges):
+    """Instance count, keys, values and tile ranges equal the oracle's
+    sorted instances bit for bit."""
+    assert counts[1] == len(keys)
     n = len(keys)
-    gk = v.keys[:n].cpu().numpy().view(np.uint64)
-    gv = v.vals[:n].cpu().numpy().view(np.uint32)
-    assert_same(gk, keys, "keys")
-    assert_same(gv, vals, "vals")
-    assert_ranges(v.ranges.cpu().numpy().view(np.uint32), ranges)
+    assert_same(v.keys[:n].cpu().numpy().view(np.uint64), keys, "keys")
+    assert_same(v.vals[:n].cpu().numpy().view(np.uint32), vals, "vals")
+    assert_ranges(v.ranges.cpu().numpy().view(np.uint32)[:-1], ranges)
 
 
 def test_sort_ragged_and_capacity(torch_gpu):
@@ -130,20 +135,16 @@ def test_sort_ragged_and_capacity(torch_gpu):
     assert ei.value.code == B.SX_ECAPACITY
     counts = v.sort(sync=True)
     keys, vals, ranges = oracle.sort_keys(scene, cam, ST)
-    assert counts[1] == len(keys) and len(keys) > 3 * 4096
-    n = len(keys)
-    assert_same(v.keys[:n].cpu().numpy().view(np.uint64), keys, "keys")
-    assert_same(v.vals[:n].cpu().numpy().view(np.uint32), vals, "vals")
-    assert_ranges(v.ranges.cpu().numpy().view(np.uint32), ranges)
+    assert len(keys) > 3 * 4096
+    _check_lists(v, counts, keys, vals, ranges)
     c4 = B.sx_sort_counts(v.ws, p.n)
     assert c4[2] == 0 and c4[3] == 0
 
 
-def test_sort_radix_fallback_large_grid(torch_gpu):
-    """A tile grid too large for the LDS-resident counting emission (here
-    2048x1152 with 8x8 tiles: 36864 tiles) takes the onesweep tile-digit
-    passes; keys, values and ranges are still bit-exact."""
-    print("case: sort radix fallback 2048x1152 8x8", flush=True)
+def test_sort_large_grid(torch_gpu):
+    """A large tile grid (2048x1152 with 8x8 tiles: 36864 tiles, five levels
+    of 4x4 bins): keys, values and ranges are still bit-exact."""
+    print("case: sort large grid 2048x1152 8x8", flush=True)
     torch = torch_gpu
     st = synth.RenderSettings(tile_w=8, tile_h=8)
     scene = synth.make_cube_scene(8, 20000, log_scale=(-3.0, 0.6))
@@ -152,11 +153,8 @@ def test_sort_radix_fallback_large_grid(torch_gpu):
     v.preprocess()
     counts = v.sort(sync=True)
     keys, vals, ranges = oracle.sort_keys(scene, cam, st)
-    assert counts[1] == len(keys) and len(keys) > 4 * 4096
-    n = len(keys)
-    assert_same(v.keys[:n].cpu().numpy().view(np.uint64), keys, "keys")
-    assert_same(v.vals[:n].cpu().numpy().view(np.uint32), vals, "vals")
-    assert_ranges(v.ranges.cpu().numpy().view(np.uint32), ranges)
+    assert len(keys) > 4 * 4096
+    _check_lists(v, counts, keys, vals, ranges)
 
 
 def test_sort_async_overflow_flag(torch_gpu):
@@ -493,3 +491,67 @@ def test_invalid_arguments_rejected(torch_gpu):
     bad = B.params(ST, 4)
     with pytest.raises(B.SplaxelError):
         B.sx_preprocess(v.c_g, v.c_cam, bad, v.c_proj)
+
+
+# ------------------------------------------------- screen list (merged walk)
+@pytest.mark.skip(reason="the screen-list path is switched off: the run that introduced it "
+                         "ended in a GPU memory fault whose cause is not yet shown")
+@pytest.mark.parametrize("n_near", [32, 400])
+def test_screen_list_sort_render_backward(torch_gpu, n_near):
+    """Gaussians whose footprint covers the whole view are kept once in the
+    screen list and merged into every tile's walk by (depth, index).  With
+    32 near-camera Gaussians (9 cover the view) and with 400 (screen list
+    and walks longer than one 64-entry batch): the expanded lists equal the
+    oracle's sorted instances, pixels match the oracle, pixels are equal
+    across tile shapes, and screen-space gradients match the oracle."""
+    print(f"case: screen list tiny n_near={n_near}", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    scene, cam = synth.screen_scene(n_near=n_near), synth.tiny_camera()
+    _, v = _cell_view(torch, scene, cam)
+    v.preprocess()
+    counts = v.sort(sync=True)
+    torch.cuda.synchronize()
+    r = v.ranges.cpu().numpy().view(np.uint32)
+    n_screen = int(r[-1][1])
+    assert n_screen >= (9 if n_near == 32 else 65), n_screen
+    keys, vals, ranges = oracle.sort_keys(scene, cam, ST)
+    _check_lists(v, counts, keys, vals, ranges)
+    # forward
+    v.render(None, want_depth=True)
+    torch.cuda.synchronize()
+    ref = oracle.render(scene, cam, ST)
+    part = v.partial.cpu().numpy()
+    cmax = float(oracle.preprocess(scene, cam, ST)["rgb"].max())
+    compare_image(part[..., :3], ref["C"], ref["flags"], 1e-4, jump_bound(ST, cmax))
+    compare_image(part[..., 3], ref["T"], ref["flags"], 1e-4, 1.0)
+    fl = ref["flags"] != 0
+    assert_same(v.nblend.cpu().numpy()[~fl], ref["nblend"][~fl], "blended pairs per pixel")
+    if n_near == 400:
+        assert int(v.last.max().item()) > 64  # walks span several merge batches
+    for tile in ((32, 8), (8, 8)):
+        st2 = synth.RenderSettings(tile_w=tile[0], tile_h=tile[1])
+        assert_same(_render(torch, scene, cam, st2).partial.cpu().numpy(), part,
+                    f"partials across tile shapes {tile}")
+    # backward (screen-space gradients of the render)
+    fr, params = _frame(torch, [scene], [big_box()], cam)
+    out = fr.forward()
+    target = torch.as_tensor(synth.random_image(101, cam.width, cam.height)).cuda()
+    dout = torch.empty_like(out)
+    B.sx_l1_loss(out, target, cam.width, cam.height, dout, None)
+    grads = [params[0].zeros_like()]
+    fr.backward(dout, grads)
+    torch.cuda.synchronize()
+    d = dout.cpu().numpy()
+    rb = oracle.render_backward(scene, cam, ST, d[..., :3].astype(np.float64), None, None)
+    g2d = fr.views[0].g2d.cpu().numpy()[:, :10]
+    pr = oracle.preprocess(scene, cam, ST)
+    bad = np.zeros(scene.n, bool)
+    for y, x in zip(*np.nonzero(fl)):
+        pr_r = pr["pix_rect"]
+        bad |= (pr_r[:, 0] <= x) & (x <= pr_r[:, 2]) & (pr_r[:, 1] <= y) & (y <= pr_r[:, 3])
+    ok = (pr["valid"] == 1) & ~bad
+    assert ok[-n_near:].any()
+    for c in range(9):
+        e = rel_err(g2d[ok, c], rb["g2d"][ok, c])
+        assert e <= 2e-3, (c, e)
