@@ -61,6 +61,26 @@ class GaussianParams:
         return B.grads(*self.tensors())
 
 
+def spatial_order(means: np.ndarray, bits: int = 10) -> np.ndarray:
+    """Permutation that stores Gaussians in Morton (Z-curve) order of their
+    means, quantised to 2^bits cells per axis over the bounding box.  The
+    Gaussians one view sees then occupy few contiguous index ranges, so the
+    projection and its backward read and write whole cache lines instead of
+    one short row per line.  Rendering is unchanged (up to the index order of
+    exactly equal depths)."""
+    m = np.asarray(means, np.float64)
+    lo, hi = m.min(0), m.max(0)
+    q = ((m - lo) / np.maximum(hi - lo, 1e-30) * ((1 << bits) - 1)).astype(np.uint64)
+
+    def spread(x):  # insert two zero bits between the low 10 bits
+        x = (x | (x << np.uint64(16))) & np.uint64(0x030000FF)
+        x = (x | (x << np.uint64(8))) & np.uint64(0x0300F00F)
+        x = (x | (x << np.uint64(4))) & np.uint64(0x030C30C3)
+        return (x | (x << np.uint64(2))) & np.uint64(0x09249249)
+    code = spread(q[:, 0]) | (spread(q[:, 1]) << np.uint64(1)) | (spread(q[:, 2]) << np.uint64(2))
+    return np.argsort(code, kind="stable")
+
+
 def tiles_of(cam, settings):
     tx = (cam.width + settings.tile_w - 1) // settings.tile_w
     ty = (cam.height + settings.tile_h - 1) // settings.tile_h
