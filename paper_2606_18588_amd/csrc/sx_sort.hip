@@ -33,6 +33,7 @@ constexpr uint64_t kEFlagAgg = 1ull << 62;
 constexpr uint64_t kEFlagIncl = 2ull << 62;
 constexpr uint64_t kEValMask = (1ull << 62) - 1;
 constexpr int kSpinLimit = 1 << 20;
+constexpr int kLookback = 8;  // predecessor statuses read per look-back round trip
 
 __device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -355,24 +356,44 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
   const uint32_t loc = block_excl_scan256(tot, s_scan, nullptr);
   const uint32_t gex = block_excl_scan256(a.hist[d], s_scan, nullptr);
   s_loc[d] = loc;
-  // decoupled look-back over earlier partitions for this digit
+  // decoupled look-back over earlier partitions for this digit, reading a
+  // window of kLookback predecessors per round trip: their sum is taken down
+  // to the nearest inclusive prefix; a predecessor not yet published ends
+  // the window and is waited for (bounded spin)
   uint32_t excl = 0;
   if (part > 0) {
     int64_t j = (int64_t)part - 1;
     int spins = 0;
     while (j >= 0) {
-      const uint32_t s = ld_acq(&a.status[(size_t)j * kRadixBins + d]);
-      if ((s & ~kValMask) == 0) {
+      uint32_t st[kLookback];
+#pragma unroll
+      for (int q = 0; q < kLookback; ++q)
+        st[q] = j - q >= 0 ? ld_acq(&a.status[(size_t)(j - q) * kRadixBins + d]) : kFlagIncl;
+      bool stop = false;
+      int used = 0;
+#pragma unroll
+      for (int q = 0; q < kLookback; ++q) {
+        if (stop) continue;
+        if ((st[q] & ~kValMask) == 0) {  // not published yet: wait on it
+          stop = true;
+          continue;
+        }
+        excl += st[q] & kValMask;
+        ++used;
+        if ((st[q] & kFlagIncl) != 0) {
+          stop = true;
+          j = -1;  // done
+        }
+      }
+      if (j < 0) break;
+      j -= used;
+      if (used == 0) {
         if (++spins > kSpinLimit) {
           atomicOr((unsigned long long*)a.err, 1ull);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      excl += s & kValMask;
-      if ((s & kFlagIncl) != 0) break;
-      --j;
     }
     st_rel(&a.status[(size_t)part * kRadixBins + d], kFlagIncl | ((excl + tot) & kValMask));
   }
