@@ -120,7 +120,7 @@ sx_status sx_sort_workspace_size(int64_t n, int64_t capacity, int32_t tiles_x, i
                                  size_t* bytes) {
   if (!bytes) return fail(SX_EINVAL, "bytes is NULL");
   if (n < 0 || capacity < 0 || tiles_x < 1 || tiles_y < 1) return fail(SX_EINVAL, "negative size");
-  if (capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "capacity must be < 2^30");
+  if (capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "capacity must be < 2^31");
   *bytes = sx::sort_layout(n, capacity, tiles_x, tiles_y).total;
   return SX_OK;
 }
@@ -134,7 +134,7 @@ sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
   if (!proj || (n > 0 && (!proj->rec || !proj->rect || !proj->n_tiles || !proj->block_sums)))
     return fail(SX_EINVAL, "null projected array");
   if (n < 0 || n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "n out of range");
-  if (capacity < 0 || capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "capacity must be in [0, 2^30)");
+  if (capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "capacity must be in [0, 2^31)");
   if (!vals && capacity > 0) return fail(SX_EINVAL, "vals is NULL");
   if (!tile_ranges || !ws) return fail(SX_EINVAL, "tile_ranges/ws is NULL");
   const int64_t tiles = tiles_of(cam, p);
@@ -230,7 +230,7 @@ sx_status sx_composite_backward(int32_t K, const float* const* partials,
 
 sx_status sx_backward_workspace_size(int64_t capacity, int64_t tiles_total, size_t* bytes) {
   if (!bytes) return fail(SX_EINVAL, "bytes is NULL");
-  if (capacity < 0 || capacity >= (int64_t(1) << 30) || tiles_total < 1)
+  if (capacity < 0 || capacity >= (int64_t(1) << 31) || tiles_total < 1)
     return fail(SX_EINVAL, "bad size");
   *bytes = sx::bwd_layout(capacity, tiles_total).total;
   return SX_OK;
@@ -248,7 +248,7 @@ sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
   if (!proj || !proj->rec || !proj->n_tiles || !proj->rect || !tile_ranges || !sort_ws || !bwd_ws ||
       !partial || !last || !dpartial || !g2d)
     return fail(SX_EINVAL, "null argument");
-  if (n < 0 || capacity < 0 || capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "bad n/capacity");
+  if (n < 0 || capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "bad n/capacity");
   const sx::KParams kp = sx::make_kparams(*p, *cam);
   return dev(sx::launch_render_backward(*proj, vals, tile_ranges, sx::sort_view(sort_ws, n, capacity, kp.tiles_x, kp.tiles_y),
                                         n, capacity, sx::make_dcam(*cam), kp, mask,
@@ -266,7 +266,7 @@ sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,
   SX_TRY(check_cam(cam));
   SX_TRY(check_params(p));
   if (!proj || !proj->n_tiles || !sort_ws || !g2d || !grads) return fail(SX_EINVAL, "null argument");
-  if (capacity < 0 || capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "bad capacity");
+  if (capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "bad capacity");
   if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
     return fail(SX_EINVAL, "null gradient array");
   const sx::KParams kp = sx::make_kparams(*p, *cam);
@@ -319,7 +319,7 @@ static sx_status check_views(int32_t V, const sx_view* views, const sx_params* p
     if (tiles_of(&w.cam, p) >= (int64_t(1) << 24)) return fail(SX_EINVAL, "view %d has too many tiles", v);
     if (!w.proj.rec || !w.tile_ranges || !w.partial || !w.last)
       return fail(SX_EINVAL, "view %d: null forward buffer", v);
-    if (w.capacity < 0 || w.capacity >= (int64_t(1) << 30)) return fail(SX_EINVAL, "view %d: bad capacity", v);
+    if (w.capacity < 0 || w.capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "view %d: bad capacity", v);
     if (backward && (!w.proj.rect || !w.proj.n_tiles || !w.sort_ws || !w.dpartial || !w.g2d || !w.bwd_ws))
       return fail(SX_EINVAL, "view %d: null backward buffer", v);
   }

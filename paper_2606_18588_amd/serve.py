@@ -36,6 +36,7 @@ from . import binding as B
 from .pipeline import GaussianParams
 
 _ALIGN = 256
+_MAX_CAPACITY = (1 << 31) - 1  # largest instance capacity the sort accepts
 
 
 def _align(n: int) -> int:
@@ -145,7 +146,7 @@ class Server:
         if it.need:
             return it.need
         r = max(self.recent) if self.recent else (self.ratio or 64.0)
-        return int(math.ceil(r * px * self.safety)) + 4096
+        return min(int(math.ceil(r * px * self.safety)) + 4096, _MAX_CAPACITY)
 
     def _bytes(self, it: _Item, cap: int) -> int:
         tx, ty = _tile_grid(it.cam, self.settings)
@@ -225,8 +226,11 @@ class Server:
         for j, (it, cap) in enumerate(zip(b.items, b.caps)):
             vis, inst, over = (int(x) for x in b.counts[j, :3])
             if over or inst > cap:
+                if inst > _MAX_CAPACITY:
+                    raise RuntimeError(f"request {it.rid}: {inst} instances exceed the sort's "
+                                       f"limit of {_MAX_CAPACITY}")
                 self.overflows += 1
-                it.need = inst + 1024
+                it.need = min(inst + 1024, _MAX_CAPACITY)
                 requeue.append(it)
                 continue
             self.recent.append(inst / float(b.pixels[j]))

@@ -73,7 +73,7 @@ def test_size_queries(L):
         B.sx_sort_workspace_size(-1, 10, 2, 2)
     assert e.value.code == B.SX_EINVAL
     with pytest.raises(B.SplaxelError):
-        B.sx_sort_workspace_size(10, 1 << 30, 2, 2)
+        B.sx_sort_workspace_size(10, 1 << 31, 2, 2)
 
 
 def _cam(B):
