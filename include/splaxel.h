@@ -67,6 +67,10 @@ typedef struct sx_params {
                         also the saturation threshold of the composition  */
   float eps2d;       /* added to the diagonal of the 2D covariance (0.3)  */
   float bg[3];       /* background colour composed behind the last cell   */
+  float fov_guard;   /* frustum cull by the mean: a Gaussian is culled when
+                        its mean projects farther from the principal point
+                        than fov_guard times the image's half-extent on that
+                        side (1.3); 0 disables the lateral test            */
 } sx_params;
 
 /* treat (cell, pixel) pairs behind a saturated prefix as the identity in
@@ -360,11 +364,26 @@ sx_status sx_render_multi(int32_t V, const sx_view* views,
 /* Render backward (Eq. 6-7 through each view's local render) of V views of
  * one cell of n Gaussians in one persistent launch, then each view's
  * per-Gaussian reduction into views[v].g2d; each view needs every member.
- * Follow with sx_preprocess_backward per view (SX_BWD_ACCUMULATE after the
- * first) to sum the views' parameter gradients. */
+ * Follow with sx_preprocess_backward_multi (or sx_preprocess_backward per
+ * view) to sum the views' parameter gradients. */
 sx_status sx_render_backward_multi(int32_t V, const sx_view* views, int64_t n,
                                    const sx_params* p, void* ws,
                                    size_t ws_bytes, sx_stream stream);
+
+/* Parameter gradients (chain of the projection, Eq. 1, and of the SH
+ * colour) summed over V views of the Gaussians g in one launch; each view
+ * needs cam, proj.n_tiles (its sx_preprocess output) and g2d (its
+ * sx_render_backward output).  Per Gaussian the views' contributions are
+ * added in view order, so the result equals sx_preprocess_backward called
+ * per view with SX_BWD_ACCUMULATE on the same grads, bit for bit.  flags:
+ * SX_BWD_ACCUMULATE adds to grads (rows of Gaussians no view sees are left
+ * untouched); without it grads are overwritten with the sum (zero rows for
+ * Gaussians no view sees), so no clearing pass is needed.
+ * views: host array [V], V in 1..SX_MAX_VIEWS. */
+sx_status sx_preprocess_backward_multi(const sx_gaussians* g, int32_t V,
+                                       const sx_view* views, const sx_params* p,
+                                       const sx_grads* grads, int32_t flags,
+                                       sx_stream stream);
 
 #ifdef __cplusplus
 }

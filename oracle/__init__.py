@@ -63,7 +63,8 @@ class _Params(ctypes.Structure):
                 ("same_frame_cull", ctypes.c_int32),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("t_min", ctypes.c_double), ("eps2d", ctypes.c_double),
-                ("bg", ctypes.c_double * 3), ("delta_q", ctypes.c_double)]
+                ("bg", ctypes.c_double * 3), ("delta_q", ctypes.c_double),
+                ("fov_guard", ctypes.c_double)]
 
 
 _lib = None
@@ -114,6 +115,7 @@ def _params(settings, sh_degree: int, same_frame_cull: bool = False,
     for i in range(3):
         p.bg[i] = float(np.float32(settings.bg[i]))
     p.delta_q = float(delta_q)
+    p.fov_guard = float(np.float32(settings.fov_guard))
     return p
 
 

@@ -25,7 +25,9 @@
 //   alpha = min(alpha_max, o*exp(-q/2)); a pair is skipped iff alpha <
 //   alpha_min; after each blend the walk stops once T < t_min ("blend, then
 //   stop"); Sigma2D gets eps2d*I added; culling by mean depth z <= znear, by
-//   degenerate covariance, by o < alpha_min and by an empty footprint; colour
+//   a mean that projects outside the field of view widened by the guard
+//   factor fov_guard (0 = no lateral test), by degenerate covariance, by
+//   o < alpha_min and by an empty footprint; colour
 //   is the orthonormal real spherical-harmonic expansion plus 0.5, clamped at
 //   0; the partial depth is D = sum z_i alpha_i T_i; cells are ordered per
 //   pixel by the ray's entry parameter into their box (max(0, t_near)), ties
@@ -57,6 +59,7 @@ struct Params {
   double alpha_min, alpha_max, t_min, eps2d;
   double bg[3];
   double delta_q;  // extra absolute half-width of the alpha-threshold band
+  double fov_guard;  // field-of-view cull: half-extents scaled by this (0 = off)
 };
 
 // Per-Gaussian projected record, all double.
@@ -237,6 +240,15 @@ static void preprocess_one(const Gauss& g, const Cam& cam, const Params& P,
   o.depth = t[2];
   o.zf = (float)t[2];
   if (!(t[2] > cam.znear)) return;
+  // frustum cull by the mean (background, projection step): the mean's
+  // offset from the principal point, fx*x/z and fy*y/z in pixels, must lie
+  // within the image's half-extents on each side, scaled by fov_guard
+  if (P.fov_guard > 0.0) {
+    const double ux = cam.fx * t[0] / t[2], uy = cam.fy * t[1] / t[2];
+    if (ux < -(P.fov_guard * cam.cx) || ux > P.fov_guard * ((double)cam.width - cam.cx) ||
+        uy < -(P.fov_guard * cam.cy) || uy > P.fov_guard * ((double)cam.height - cam.cy))
+      return;
+  }
   double qn = std::sqrt(g.q[0] * g.q[0] + g.q[1] * g.q[1] + g.q[2] * g.q[2] +
                         g.q[3] * g.q[3]);
   if (qn < 1e-12) return;

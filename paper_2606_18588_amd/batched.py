@@ -108,10 +108,10 @@ class MultiViewStep:
     def run(self, lr: float = 1e-4, count_blends: bool = False, check: bool = False):
         """One step; with check, synchronises after each group and raises if
         any view's instances overflowed its capacity."""
-        for t in self.grads.tensors():
-            B.sx_fill_u32(t, 0)
         blends = 0
         if self.plain:
+            for t in self.grads.tensors():
+                B.sx_fill_u32(t, 0)
             for i, v in enumerate(self.views):
                 v.preprocess()
                 v.sort(sync=False)
@@ -131,7 +131,8 @@ class MultiViewStep:
                 for i in g:
                     self._loss_and_grad(self.views[i], self.targets[i])
                 bv.render_backward()
-                bv.preprocess_backward(self.grads, accumulate=True)
+                # the first group overwrites the gradients, later ones add
+                bv.preprocess_backward(self.grads, accumulate=g is not self.groups[0])
                 if check:
                     self._check(g)
                 if count_blends:

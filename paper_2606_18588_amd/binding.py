@@ -39,7 +39,7 @@ class SxCamera(ctypes.Structure):
 class SxParams(ctypes.Structure):
     _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("sh_degree", c_i32),
                 ("flags", c_i32), ("alpha_min", c_f), ("alpha_max", c_f),
-                ("t_min", c_f), ("eps2d", c_f), ("bg", c_f * 3)]
+                ("t_min", c_f), ("eps2d", c_f), ("bg", c_f * 3), ("fov_guard", c_f)]
 
 
 class SxGaussians(ctypes.Structure):
@@ -86,7 +86,7 @@ EXPORTS = (
     "sx_render_partial", "sx_composite", "sx_l1_loss", "sx_backward",
     "sx_composite_backward", "sx_render_backward", "sx_preprocess_backward",
     "sx_adam", "sx_fill_u32", "sx_preprocess_multi", "sx_multi_workspace_size",
-    "sx_render_multi", "sx_render_backward_multi",
+    "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
 )
 
 _lib = None
@@ -167,6 +167,7 @@ def params(settings, sh_degree: int, flags: int = 0) -> SxParams:
     p.t_min, p.eps2d = float(settings.t_min), float(settings.eps2d)
     for i in range(3):
         p.bg[i] = float(settings.bg[i])
+    p.fov_guard = float(settings.fov_guard)
     return p
 
 
@@ -359,6 +360,14 @@ def sx_render_multi(views: Sequence[SxView], p: SxParams, ws: torch.Tensor,
     _check("sx_render_multi", lib().sx_render_multi(
         c_i32(len(views)), va, ctypes.byref(p), ptr(ws),
         ctypes.c_size_t(ws.numel() * ws.element_size()), stream_handle(stream)))
+
+
+def sx_preprocess_backward_multi(g: SxGaussians, views: Sequence[SxView], p: SxParams,
+                                 gr: SxGrads, flags: int = 0, stream=None) -> None:
+    va = (SxView * len(views))(*views)
+    _check("sx_preprocess_backward_multi", lib().sx_preprocess_backward_multi(
+        ctypes.byref(g), c_i32(len(views)), va, ctypes.byref(p), ctypes.byref(gr),
+        c_i32(flags), stream_handle(stream)))
 
 
 def sx_render_backward_multi(views: Sequence[SxView], n: int, p: SxParams,

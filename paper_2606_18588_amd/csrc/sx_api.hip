@@ -46,6 +46,7 @@ sx_status check_params(const sx_params* p) {
   if (!(p->alpha_min > 0.f) || !(p->alpha_max > p->alpha_min) || !(p->alpha_max < 1.f))
     return fail(SX_EINVAL, "need 0 < alpha_min < alpha_max < 1");
   if (!(p->t_min >= 0.f) || !(p->eps2d >= 0.f)) return fail(SX_EINVAL, "t_min, eps2d must be >= 0");
+  if (!(p->fov_guard >= 0.f && p->fov_guard <= 1e6f)) return fail(SX_EINVAL, "fov_guard must be in [0, 1e6]");
   return SX_OK;
 }
 
@@ -87,7 +88,7 @@ KParams make_kparams(const sx_params& p, const sx_camera& c) {
   k.tiles_y = (c.height + p.tile_h - 1) / p.tile_h;
   k.sh_degree = p.sh_degree, k.flags = p.flags;
   k.alpha_min = p.alpha_min, k.alpha_max = p.alpha_max, k.t_min = p.t_min;
-  k.eps2d = p.eps2d, k.alpha_min_d = p.alpha_min;
+  k.eps2d = p.eps2d, k.alpha_min_d = p.alpha_min, k.fov_guard = p.fov_guard;
   for (int i = 0; i < 3; ++i) k.bg[i] = p.bg[i];
   return k;
 }
@@ -405,6 +406,33 @@ sx_status sx_render_backward_multi(int32_t V, const sx_view* views, int64_t n, c
   for (int v = 0; v < V; ++v)
     SX_TRY(dev(sx::launch_grad_reduce_view(mv[v], n, kp, (hipStream_t)stream), "sx_render_backward_multi"));
   return SX_OK;
+}
+
+sx_status sx_preprocess_backward_multi(const sx_gaussians* g, int32_t V, const sx_view* views,
+                                       const sx_params* p, const sx_grads* grads, int32_t flags,
+                                       sx_stream stream) {
+  SX_TRY(check_gauss(g));
+  SX_TRY(check_params(p));
+  if (V < 1 || V > sx::kMaxViews) return fail(SX_EINVAL, "V=%d outside 1..%d", V, sx::kMaxViews);
+  if (!views || !grads) return fail(SX_EINVAL, "null argument");
+  if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
+    return fail(SX_EINVAL, "null gradient array");
+  sx::DCam cams[sx::kMaxViews];
+  const uint32_t* n_tiles[sx::kMaxViews];
+  const float* g2d[sx::kMaxViews];
+  for (int v = 0; v < V; ++v) {
+    SX_TRY(check_cam(&views[v].cam));
+    if (g->n > 0 && (!views[v].proj.n_tiles || !views[v].g2d))
+      return fail(SX_EINVAL, "view %d: null n_tiles/g2d", v);
+    cams[v] = sx::make_dcam(views[v].cam);
+    n_tiles[v] = views[v].proj.n_tiles;
+    g2d[v] = views[v].g2d;
+  }
+  return dev(sx::launch_preprocess_backward_multi(*g, V, cams, n_tiles, g2d,
+                                                  sx::make_kparams(*p, views[0].cam), *grads,
+                                                  (flags & SX_BWD_ACCUMULATE) != 0,
+                                                  (hipStream_t)stream),
+             "sx_preprocess_backward_multi");
 }
 
 sx_status sx_adam(int64_t n, float* param, const float* grad, float* m, float* v,

@@ -34,7 +34,7 @@ struct DCam {
 struct KParams {
   int32_t tile_w, tile_h, tiles_x, tiles_y, sh_degree, flags;
   float alpha_min, alpha_max, t_min;
-  double eps2d, alpha_min_d;
+  double eps2d, alpha_min_d, fov_guard;
   float bg[3];
 };
 
@@ -46,8 +46,10 @@ KParams make_kparams(const sx_params& p, const sx_camera& c);
 struct SortLayout {
   size_t counts;       // uint64[4]: visible, instances, overflow, error
   size_t vis_off;      // uint32[nb]   exclusive visible offsets per block
+  size_t scan_part;    // uint64[tiles][2] per-tile (visible, instance) sums
   size_t dkey[2];      // uint32[n]    depth keys (ping-pong)
   size_t didx[2];      // uint32[n]    Gaussian indices (ping-pong)
+  size_t vidx;         // uint32[n]    visible Gaussians in index order
   size_t zero_begin;   // start of the region cleared on every call
   size_t dhist;        // uint32[4][256] depth digit histograms
   size_t counters;     // uint32[16] partition counters
@@ -90,6 +92,7 @@ BwdLayout bwd_layout(int64_t capacity, int64_t tiles_total);
 struct SortView {
   const uint64_t* counts;
   const uint32_t* didx;   // depth-sorted visible Gaussians
+  const uint32_t* vidx;   // the same Gaussians in index order
 };
 SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
 
@@ -252,6 +255,10 @@ hipError_t launch_preprocess(const sx_gaussians& g, const DCam& cam,
 struct SortView;
 hipError_t launch_preprocess_multi(const sx_gaussians& g, int V, const sx_camera* cams,
                                    const KParams& p, const sx_projected* outs, hipStream_t st);
+hipError_t launch_preprocess_backward_multi(const sx_gaussians& g, int V, const DCam* cams,
+                                            const uint32_t* const* n_tiles,
+                                            const float* const* g2d, const KParams& p,
+                                            const sx_grads& gr, bool accumulate, hipStream_t st);
 hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
                                       const KParams& p,
                                       const sx_projected& proj, const SortView& sv,

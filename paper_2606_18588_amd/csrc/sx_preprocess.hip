@@ -159,6 +159,12 @@ __device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
   if (!project_geometry(a.means, a.log_scales, a.quats, i, a.cam, a.p.eps2d, g)) return 0;
   const double z = g.t[2];
   const double mx2 = a.cam.fx * g.t[0] / z, my2 = a.cam.fy * g.t[1] / z;
+  // frustum cull by the mean: its offset from the principal point must lie
+  // within the image's half-extents on each side, widened by fov_guard
+  const double gd = a.p.fov_guard;
+  if (gd > 0.0 && (mx2 < -(gd * a.cam.cx) || mx2 > gd * ((double)a.cam.W - a.cam.cx) ||
+                   my2 < -(gd * a.cam.cy) || my2 > gd * ((double)a.cam.H - a.cam.cy)))
+    return 0;
   const double mux = mx2 + a.cam.cx, muy = my2 + a.cam.cy;
   const double o = 1.0 / (1.0 + exp(-(double)a.logits[i]));
   if (o < a.p.alpha_min_d) return 0;
@@ -395,9 +401,8 @@ struct PreBwdArgs {
   int accumulate;
 };
 
-template <bool ACC>
-__device__ __forceinline__ void put(float* p, double v) {
-  if (ACC)
+__device__ __forceinline__ void put(float* p, double v, bool acc) {
+  if (acc)
     *p += (float)v;
   else
     *p = (float)v;
@@ -408,8 +413,8 @@ __device__ __forceinline__ void put(float* p, double v) {
 // (dM = J^T G_S J, dJ = 2 G_S J M), M -> Sigma (W^T dM W), Sigma = L L^T
 // with L = R(q) S (dL = 2 dSigma L) -> log-scales and the quaternion; the
 // mean through mean2d, J(t), depth and the SH view direction.
-template <int D, bool ACC>
-__device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
+template <int D>
+__device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i, bool acc) {
   Proj64 g;
   if (!project_geometry(a.means, a.log_scales, a.quats, i, a.cam, a.p.eps2d, g)) return;
   const float* gr = a.g2d + (size_t)i * kG2dFloats;
@@ -464,7 +469,7 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
 #pragma unroll
     for (int j = 0; j < nf / 4; ++j) {
       float4 q = make_float4(gsh_at(4 * j), gsh_at(4 * j + 1), gsh_at(4 * j + 2), gsh_at(4 * j + 3));
-      if (ACC) {
+      if (acc) {
         const float4 o = reinterpret_cast<const float4*>(gshp)[j];
         q.x += o.x, q.y += o.y, q.z += o.z, q.w += o.w;
       }
@@ -472,7 +477,7 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < nf; ++j) put<ACC>(&gshp[j], (double)gsh_at(j));
+    for (int j = 0; j < nf; ++j) put(&gshp[j], (double)gsh_at(j), acc);
   }
   const double gdir[3] = {gdf[0], gdf[1], gdf[2]};
   double gmu[3];
@@ -482,7 +487,7 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
   }
   // opacity through the sigmoid
   const double o = 1.0 / (1.0 + exp(-(double)a.logits[i]));
-  put<ACC>(&a.glogits[i], gop * o * (1.0 - o));
+  put(&a.glogits[i], gop * o * (1.0 - o), acc);
   // conic -> covariance
   const double A[4] = {g.conic[0], g.conic[1], g.conic[1], g.conic[2]};
   const double Gc[4] = {ga, 0.5 * gb, 0.5 * gb, gc};
@@ -533,7 +538,7 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
   for (int k = 0; k < 3; ++k) {
     double v = 0;
     for (int r = 0; r < 3; ++r) v += dLm[r * 3 + k] * g.Rq[r * 3 + k];
-    put<ACC>(&a.glog_scales[i * 3 + k], v * g.s[k]);
+    put(&a.glog_scales[i * 3 + k], v * g.s[k], acc);
   }
   double dR[9];
   for (int r = 0; r < 3; ++r)
@@ -549,7 +554,7 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
                  y * dR[5] + x * dR[6] + y * dR[7]);
   {
     const double dd = dq[0] * g.qh[0] + dq[1] * g.qh[1] + dq[2] * g.qh[2] + dq[3] * g.qh[3];
-    for (int k = 0; k < 4; ++k) put<ACC>(&a.gquats[i * 4 + k], (dq[k] - dd * g.qh[k]) / g.qn);
+    for (int k = 0; k < 4; ++k) put(&a.gquats[i * 4 + k], (dq[k] - dd * g.qh[k]) / g.qn, acc);
   }
   // mean: mean2d, J(t), depth; then world = W^T dt (+ SH direction term)
   const double z = g.t[2], fx = a.cam.fx, fy = a.cam.fy;
@@ -561,19 +566,20 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i) {
           dJ[2] * (2.0 * fx * tx / (z * z * z)) + dJ[4] * (-fy / (z * z)) +
           dJ[5] * (2.0 * fy * ty / (z * z * z)) + gz;
   for (int k = 0; k < 3; ++k)
-    put<ACC>(&a.gmeans[i * 3 + k],
-             W[0 * 3 + k] * dt[0] + W[1 * 3 + k] * dt[1] + W[2 * 3 + k] * dt[2] + gmu[k]);
+    put(&a.gmeans[i * 3 + k],
+             W[0 * 3 + k] * dt[0] + W[1 * 3 + k] * dt[1] + W[2 * 3 + k] * dt[2] + gmu[k], acc);
 }
 
-// One lane per visible Gaussian, taken from the sort's compacted list, so
-// the FP64 chain runs in full wavefronts.
+// One lane per visible Gaussian, taken from the sort's compacted list in
+// index order, so the FP64 chain runs in full wavefronts and neighbouring
+// lanes read and write neighbouring parameter rows.
 template <int D, bool ACC>
 __global__ __launch_bounds__(kPreBlock) void k_preprocess_backward(PreBwdArgs a) {
   const uint64_t i = (uint64_t)blockIdx.x * kPreBlock + threadIdx.x;
   if (i >= a.vis_count[0]) return;
   const uint32_t g = a.vis[i];
   if (a.n_tiles[g] == 0) return;
-  backward_one<D, ACC>(a, (int64_t)g);
+  backward_one<D>(a, (int64_t)g, ACC);
 }
 
 hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
@@ -583,7 +589,7 @@ hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
                                       bool accumulate, hipStream_t st) {
   if (g.n == 0) return hipSuccess;
   PreBwdArgs a;
-  a.vis = sv.didx;
+  a.vis = sv.vidx;
   a.vis_count = sv.counts;
   a.n = g.n;
   a.means = g.means, a.log_scales = g.log_scales, a.quats = g.quats;
@@ -609,6 +615,111 @@ hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
     default: SX_PB(3); break;
   }
 #undef SX_PB
+  return hipGetLastError();
+}
+
+// Several views of one set of Gaussians in one launch: each workgroup takes
+// a block of Gaussians and, view after view, packs the ones the view sees to
+// the front of the block and runs the chain for them.  The parameter rows
+// come from HBM once and the gradient rows stay in the caches between the
+// views.  Each Gaussian receives its views' contributions in view order, as
+// it would from one accumulating call per view, so the sums are the same to
+// the last bit.
+struct PreBwdView {
+  DCam cam;
+  const uint32_t* n_tiles;
+  const float* g2d;
+};
+struct PreBwdMultiArgs {
+  int64_t n;
+  int V;
+  int accumulate;
+  const float* __restrict__ means;
+  const float* __restrict__ log_scales;
+  const float* __restrict__ quats;
+  const float* __restrict__ logits;
+  const float* __restrict__ sh;
+  KParams p;
+  float* gmeans;
+  float* glog_scales;
+  float* gquats;
+  float* glogits;
+  float* gsh;
+  PreBwdView v[kMaxViews];
+};
+static_assert(sizeof(PreBwdMultiArgs) <= 3584, "kernel arguments exceed the launch limit");
+
+template <int D>
+__global__ __launch_bounds__(kPreBlock) void k_preprocess_backward_multi(PreBwdMultiArgs m) {
+  __shared__ uint32_t s_cand[kPreBlock];
+  __shared__ uint32_t s_w[kPreBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bool seen = m.accumulate != 0;  // this lane's Gaussian already holds a sum
+  PreBwdArgs a;
+  a.n = m.n;
+  a.means = m.means, a.log_scales = m.log_scales, a.quats = m.quats;
+  a.logits = m.logits, a.sh = m.sh;
+  a.p = m.p;
+  a.gmeans = m.gmeans, a.glog_scales = m.glog_scales, a.gquats = m.gquats;
+  a.glogits = m.glogits, a.gsh = m.gsh;
+  for (int v = 0; v < m.V; ++v) {
+    const bool vis = i < m.n && m.v[v].n_tiles[i] > 0;
+    const uint64_t bal = __ballot(vis);
+    if (lane == 0) s_w[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t pre = 0, cnt = 0;
+    for (int k = 0; k < kPreBlock / 64; ++k) {
+      if (k < w) pre += s_w[k];
+      cnt += s_w[k];
+    }
+    // slot -> (thread, whether the Gaussian already holds a sum)
+    if (vis) s_cand[pre + __popcll(bal & ((1ull << lane) - 1))] = threadIdx.x | (seen ? 0x80000000u : 0u);
+    seen = seen || vis;
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      const uint32_t c = s_cand[threadIdx.x];
+      a.cam = m.v[v].cam;
+      a.g2d = m.v[v].g2d;
+      backward_one<D>(a, (int64_t)blockIdx.x * kPreBlock + (c & 0x7FFFFFFFu), (c >> 31) != 0);
+    }
+    __syncthreads();  // the next view's sums read these rows; s_cand is reused
+  }
+  if (!seen && i < m.n) {  // overwrite mode, no view sees this Gaussian
+    constexpr int nf = (D + 1) * (D + 1) * 3;
+    for (int k = 0; k < 3; ++k) m.gmeans[i * 3 + k] = 0.f, m.glog_scales[i * 3 + k] = 0.f;
+    for (int k = 0; k < 4; ++k) m.gquats[i * 4 + k] = 0.f;
+    m.glogits[i] = 0.f;
+    for (int k = 0; k < nf; ++k) m.gsh[i * nf + k] = 0.f;
+  }
+}
+
+hipError_t launch_preprocess_backward_multi(const sx_gaussians& g, int V, const DCam* cams,
+                                            const uint32_t* const* n_tiles,
+                                            const float* const* g2d, const KParams& p,
+                                            const sx_grads& gr, bool accumulate, hipStream_t st) {
+  if (g.n == 0 || V == 0) return hipSuccess;
+  PreBwdMultiArgs m;
+  m.n = g.n;
+  m.V = V;
+  m.accumulate = accumulate ? 1 : 0;
+  m.means = g.means, m.log_scales = g.log_scales, m.quats = g.quats;
+  m.logits = g.opacity_logits, m.sh = g.sh;
+  m.p = p;
+  m.gmeans = gr.means, m.glog_scales = gr.log_scales, m.gquats = gr.quats;
+  m.glogits = gr.opacity_logits, m.gsh = gr.sh;
+  for (int v = 0; v < V; ++v) {
+    m.v[v].cam = cams[v];
+    m.v[v].n_tiles = n_tiles[v];
+    m.v[v].g2d = g2d[v];
+  }
+  const dim3 grid((unsigned)((g.n + kPreBlock - 1) / kPreBlock));
+  switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess_backward_multi<0>, grid, dim3(kPreBlock), 0, st, m); break;
+    case 1: hipLaunchKernelGGL(k_preprocess_backward_multi<1>, grid, dim3(kPreBlock), 0, st, m); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_backward_multi<2>, grid, dim3(kPreBlock), 0, st, m); break;
+    default: hipLaunchKernelGGL(k_preprocess_backward_multi<3>, grid, dim3(kPreBlock), 0, st, m); break;
+  }
   return hipGetLastError();
 }
 

@@ -640,7 +640,7 @@ static hipError_t launch_bwd_reduce(const SortView& sv, int64_t n, int64_t capac
   const BwdLayout BL = bwd_layout(capacity, tiles);
   if (n > 0)
     hipLaunchKernelGGL(k_zero_g2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       sv.didx, sv.counts, g2d);
+                       sv.vidx, sv.counts, g2d);
   auto u32 = [&](size_t off) { return reinterpret_cast<uint32_t*>(bws + off); };
   uint32_t* keys[2] = {u32(BL.pk[0]), u32(BL.pk[1])};
   uint32_t* vals[2] = {u32(BL.pv[0]), u32(BL.pv[1])};

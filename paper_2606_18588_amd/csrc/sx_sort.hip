@@ -34,6 +34,8 @@ constexpr uint64_t kEFlagIncl = 2ull << 62;
 constexpr uint64_t kEValMask = (1ull << 62) - 1;
 constexpr int kSpinLimit = 1 << 20;
 constexpr int kLookback = 8;  // predecessor statuses read per look-back round trip
+constexpr int kScanItems = 16;  // preprocess blocks per thread in the count scan
+constexpr int kScanTile = 256 * kScanItems;
 
 __device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -102,8 +104,10 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
   L.bl_tot = take((size_t)tot_words * 4);
   L.zero_end = off;
   L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
+  L.scan_part = take((size_t)((L.nb + kScanTile - 1) / kScanTile + 1) * 16);
   for (int k = 0; k < 2; ++k) L.dkey[k] = take((size_t)(n > 0 ? n : 1) * 4);
   for (int k = 0; k < 2; ++k) L.didx[k] = take((size_t)(n > 0 ? n : 1) * 4);
+  L.vidx = take((size_t)(n > 0 ? n : 1) * 4);
   // every entry of an inner level is a (Gaussian, bin) pair with at least
   // one instance in the bin, so an inner list never exceeds the instance count
   const int64_t bins = ((tiles_x + 3) / 4) * ((tiles_y + 3) / 4);
@@ -150,57 +154,80 @@ SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x,
   SortView v;
   v.counts = reinterpret_cast<const uint64_t*>(b + L.counts);
   v.didx = reinterpret_cast<const uint32_t*>(b + L.didx[0]);
+  v.vidx = reinterpret_cast<const uint32_t*>(b + L.vidx);
   return v;
 }
 
 // ------------------------------------------------------------- counting --
-// One block: exclusive scan of the per-preprocess-block visible counts and
-// the total instance count.
-__global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict__ bsum,
-                                                      int64_t nb, uint32_t* __restrict__ vis_off,
-                                                      uint64_t* counts, int64_t cap) {
-  __shared__ uint32_t sw[16];
-  __shared__ unsigned long long si[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t chunk = (nb + 1023) / 1024;
-  const int64_t beg = tid * chunk, end = beg + chunk < nb ? beg + chunk : nb;
-  uint32_t sv = 0;
-  unsigned long long sinst = 0;
-  for (int64_t k = beg; k < end; ++k) {
-    sv += bsum[2 * k];
-    sinst += bsum[2 * k + 1];
-  }
-  uint32_t x = sv;
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  unsigned long long r = sinst;
-  for (int o = 32; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
-  if (lane == 63) sw[w] = x;
-  if (lane == 0) si[w] = r;
+// Exclusive scan of the per-preprocess-block visible counts and the total
+// instance count, in two launches over tiles of kScanTile blocks: per-tile
+// sums, then every tile adds the sums of the tiles before it.
+__device__ __forceinline__ uint64_t block_sum256_u64(uint64_t v, unsigned long long* s4) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   __syncthreads();
-  uint32_t pre = 0, tot = 0;
-  unsigned long long itot = 0;
-  for (int k = 0; k < 16; ++k) {
-    if (k < w) pre += sw[k];
-    tot += sw[k];
-    itot += si[k];
+  if (lane == 0) s4[w] = v;
+  __syncthreads();
+  return s4[0] + s4[1] + s4[2] + s4[3];
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ bsum, int64_t nb,
+                                                     uint64_t* __restrict__ part) {
+  __shared__ unsigned long long s4[4];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint64_t sv = 0, si = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j)
+    if (b0 + j < nb) {
+      sv += bsum[2 * (b0 + j)];
+      si += bsum[2 * (b0 + j) + 1];
+    }
+  sv = block_sum256_u64(sv, s4);
+  si = block_sum256_u64(si, s4);
+  if (threadIdx.x == 0) part[2 * blockIdx.x] = sv, part[2 * blockIdx.x + 1] = si;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ bsum, int64_t nb,
+                                                    const uint64_t* __restrict__ part,
+                                                    uint32_t* __restrict__ vis_off,
+                                                    uint64_t* counts, int64_t cap) {
+  __shared__ unsigned long long s4[4];
+  __shared__ uint32_t s_scan[4];
+  const bool last = blockIdx.x == gridDim.x - 1;
+  uint64_t pv = 0, pi = 0;  // earlier tiles (the last tile: instances of all tiles)
+  for (uint32_t k = threadIdx.x; k < (last ? gridDim.x : blockIdx.x); k += 256) {
+    if (k < blockIdx.x) pv += part[2 * k];
+    pi += part[2 * k + 1];
   }
-  uint32_t run = pre + x - sv;
-  for (int64_t k = beg; k < end; ++k) {
-    vis_off[k] = run;
-    run += bsum[2 * k];
+  pv = block_sum256_u64(pv, s4);
+  if (last) pi = block_sum256_u64(pi, s4);
+  const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t tsum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = b0 + j < nb ? bsum[2 * (b0 + j)] : 0u;
+    tsum += v[j];
   }
-  if (tid == 0) {
-    counts[0] = tot;
-    counts[1] = itot;
-    counts[2] = itot > (unsigned long long)cap ? 1ull : 0ull;
+  uint32_t total;
+  uint32_t run = (uint32_t)pv + block_excl_scan256(tsum, s_scan, &total);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j)
+    if (b0 + j < nb) {
+      vis_off[b0 + j] = run;
+      run += v[j];
+    }
+  if (last && threadIdx.x == 0) {
+    counts[0] = pv + total;
+    counts[1] = pi;
+    counts[2] = pi > (uint64_t)cap ? 1ull : 0ull;
   }
 }
 
 // Compacted (depth bits, Gaussian index) list of visible Gaussians in index
-// order.
+// order.  The index list stays untouched by the depth passes (the first one
+// reads it): the backward walks the visible Gaussians in this order, where
+// neighbouring lanes read neighbouring parameter rows.
 __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restrict__ n_tiles,
                                                        const float* __restrict__ rec, int64_t n,
                                                        const uint32_t* __restrict__ vis_off,
@@ -656,8 +683,14 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     if (h_counts) h_counts[0] = h_counts[1] = 0;
     return hipSuccess;
   }
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, proj.block_sums, (int64_t)L.nb,
-                     u32(L.vis_off), counts, (int64_t)capacity);
+  {
+    const unsigned tiles = (unsigned)((L.nb + kScanTile - 1) / kScanTile);
+    uint64_t* part = reinterpret_cast<uint64_t*>(ws + L.scan_part);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(256), 0, st, proj.block_sums,
+                       (int64_t)L.nb, part);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, st, proj.block_sums,
+                       (int64_t)L.nb, part, u32(L.vis_off), counts, (int64_t)capacity);
+  }
   if ((e = hipGetLastError())) return e;
   if (h_counts) {
     uint64_t c[2];
@@ -672,7 +705,7 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
   }
   // phase 1: depth digits (bits 0..30; depth > 0, sign bit clear) in 8,8,8,7
   hipLaunchKernelGGL(k_compact, dim3((unsigned)L.nb), dim3(kPreBlock), 0, st, proj.n_tiles,
-                     proj.rec, n, u32(L.vis_off), u32(L.dkey[0]), u32(L.didx[0]));
+                     proj.rec, n, u32(L.vis_off), u32(L.dkey[0]), u32(L.vidx));
   hipLaunchKernelGGL(k_hist_depth, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st,
                      u32(L.dkey[0]), counts, u32(L.dhist));
   uint32_t* counters = u32(L.counters);
@@ -680,7 +713,7 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
   for (int ps = 0; ps < 4; ++ps) {
     SweepArgs a{};
     a.keys_in = u32(L.dkey[ps & 1]);
-    a.vals_in = u32(L.didx[ps & 1]);
+    a.vals_in = ps == 0 ? u32(L.vidx) : u32(L.didx[ps & 1]);
     a.keys_out = u32(L.dkey[(ps + 1) & 1]);
     a.vals_out = u32(L.didx[(ps + 1) & 1]);
     a.count = counts;

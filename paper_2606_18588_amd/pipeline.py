@@ -371,10 +371,10 @@ class BatchedViews:
                                    self.ws)
 
     def preprocess_backward(self, grads: GaussianParams, accumulate=False):
-        """Sum of the views' parameter gradients into grads (cleared first
-        unless accumulate: the per-view call touches visible rows only)."""
-        if not accumulate:
-            for t in grads.tensors():
-                B.sx_fill_u32(t, 0)
-        for v in self.views:
-            v.preprocess_backward(grads, accumulate=True)
+        """Sum of the views' parameter gradients, in one launch: written
+        into grads (zero where no view sees a Gaussian), or added to them
+        with accumulate."""
+        self._gs = grads.grad_struct()
+        B.sx_preprocess_backward_multi(self.views[0].c_g, self._structs(backward=True),
+                                       self.c_par, self._gs,
+                                       B.SX_BWD_ACCUMULATE if accumulate else 0)

@@ -314,6 +314,7 @@ ALPHA_MIN = 1.0 / 255.0
 ALPHA_MAX = 0.99
 T_MIN = 1e-4
 EPS2D = 0.3
+FOV_GUARD = 1.3  # field-of-view cull by the mean: half-extents widened by 30%
 
 
 @dataclass
@@ -325,6 +326,7 @@ class RenderSettings:
     t_min: float = T_MIN
     eps2d: float = EPS2D
     bg: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    fov_guard: float = FOV_GUARD
 
 
 def tiny_scene(seed: int = 0, n: int = 5000) -> Scene:

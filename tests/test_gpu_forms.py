@@ -54,6 +54,7 @@ def test_batched_views_bit_identical_to_per_view(torch_gpu, tile):
     st = synth.RenderSettings(tile_w=tw, tile_h=th)
     print(f"case: batched vs per-view tiny 3 views tile {tile}", flush=True)
     scene = synth.tiny_scene(seed=5, n=6000)
+    scene.means[::97] += np.float32(500.0)  # out of every view: no gradient
     cams = _orbit_cams()
     params = GaussianParams.from_scene(scene)
     bv = BatchedViews(params, cams, st)
@@ -111,6 +112,28 @@ def test_batched_views_bit_identical_to_per_view(torch_gpu, tile):
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         e = rel_err(_np(getattr(gb, name)), _np(getattr(gs, name)))
         assert e <= 1e-5, (name, e)
+    # the one-launch parameter pass equals per-view accumulating calls on the
+    # same screen-space gradients bit for bit, overwriting (rows no view sees
+    # become zero) and accumulating
+    unseen = np.ones(params.n, bool)
+    for a in bv.views:
+        unseen &= _np(a.n_tiles) == 0
+    assert unseen.sum() >= 60
+    ref, ref_acc, over, acc = (params.zeros_like() for _ in range(4))
+    for t in over.tensors():
+        t.fill_(3.0)
+    for t in ref_acc.tensors() + acc.tensors():
+        t.fill_(0.25)
+    for v in bv.views:
+        v.preprocess_backward(ref, accumulate=True)
+        v.preprocess_backward(ref_acc, accumulate=True)
+    bv.preprocess_backward(over)
+    bv.preprocess_backward(acc, accumulate=True)
+    torch.cuda.synchronize()
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        assert_same(_np(getattr(over, name)), _np(getattr(ref, name)), f"overwrite {name}")
+        assert_same(_np(getattr(acc, name)), _np(getattr(ref_acc, name)), f"accumulate {name}")
+        assert not np.any(_np(getattr(over, name))[unseen]), name
 
 
 def test_batched_views_sixteen_uneven(torch_gpu):

@@ -1,0 +1,123 @@
+"""Parity at the full one-GPU workload the benchmark times: 2M Gaussians,
+SH degree 3, on the 1 km ground plane in Morton order, one 1920x1080 aerial
+view, 16x16 tiles, through the same calls.
+
+- preprocess: the tile count of every Gaussian bit-exact; the records of a
+  sample of visible Gaussians within FP32 rounding of the oracle's FP64;
+- sort: visible and instance counts, then every key and value of the 32M
+  instances and every tile range, bit-exact;
+- render: a sample of tiles (random ones plus the corners and the ragged
+  bottom row) against the oracle restricted to those tiles by its pixel mask;
+- backward: an upstream gradient that is non-zero only on unflagged pixels
+  of the sampled tiles, so the oracle's screen-space and parameter gradients
+  are exact references for the kernel's full-image backward.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import (assert_ranges, assert_same, compare_image, jump_bound, need_gpu,
+                         rec_fields, rel_err)
+
+pytestmark = pytest.mark.gpu
+ST = synth.RenderSettings()
+
+
+@pytest.fixture(scope="module")
+def g2():
+    need_gpu()
+    import torch
+    from paper_2606_18588_amd.pipeline import CellView, GaussianParams, spatial_order
+    print("case: full-size 2M Gaussians 1920x1080, building the scene", flush=True)
+    scene = synth.g2_scene()
+    scene = scene.subset(spatial_order(scene.means))
+    cam = synth.g2_camera()
+    params = GaussianParams.from_scene(scene)
+    v = CellView(params, cam, ST, keep_keys=True)
+    v.preprocess()
+    counts = v.sort(sync=True)
+    v.render(None, want_depth=False)
+    torch.cuda.synchronize()
+    return dict(torch=torch, scene=scene, cam=cam, params=params, view=v, counts=counts)
+
+
+def _sample_tiles(cam, seed=3, count=40):
+    tx = (cam.width + ST.tile_w - 1) // ST.tile_w
+    ty = (cam.height + ST.tile_h - 1) // ST.tile_h
+    rng = np.random.default_rng(seed)
+    t = set(int(x) for x in rng.choice(tx * ty, size=count, replace=False))
+    t |= {0, tx - 1, (ty - 1) * tx, ty * tx - 1}           # corners
+    t |= {(ty - 1) * tx + int(x) for x in rng.choice(tx, size=4, replace=False)}  # ragged row
+    return sorted(t), tx, ty
+
+
+def _tile_mask(cam, tiles, tx):
+    m = np.zeros((cam.height, cam.width), np.uint8)
+    for t in tiles:
+        x0, y0 = (t % tx) * ST.tile_w, (t // tx) * ST.tile_h
+        m[y0:y0 + ST.tile_h, x0:x0 + ST.tile_w] = 1
+    return m
+
+
+def test_fullsize_preprocess_and_sort(g2):
+    print("case: full-size preprocess + sort", flush=True)
+    scene, cam, v, counts = g2["scene"], g2["cam"], g2["view"], g2["counts"]
+    ref = oracle.preprocess(scene, cam, ST)
+    assert_same(v.n_tiles.cpu().numpy().astype(np.int64), ref["n_tiles"], "tiles touched")
+    vis = np.nonzero(ref["valid"] == 1)[0]
+    assert counts[0] == len(vis)
+    pick = np.random.default_rng(1).choice(vis, size=min(4096, len(vis)), replace=False)
+    f = rec_fields(v.rec)
+    assert_same(f["depth"][pick], ref["depth"][pick].astype(np.float32), "depth")
+    np.testing.assert_allclose(f["conic"][pick], ref["conic"][pick], rtol=5e-6, atol=1e-9)
+    np.testing.assert_allclose(f["opacity"][pick], ref["opacity"][pick], rtol=2e-7)
+    np.testing.assert_allclose(f["rgb"][pick], ref["rgb"][pick], atol=1e-6)
+    del ref
+    keys, vals, ranges = oracle.sort_keys(scene, cam, ST)
+    print(f"full-size sort: {counts[0]} visible, {len(keys)} instances", flush=True)
+    assert counts[1] == len(keys)
+    n = len(keys)
+    assert_same(v.keys[:n].cpu().numpy().view(np.uint64), keys, "keys")
+    assert_same(v.vals[:n].cpu().numpy().view(np.uint32), vals, "vals")
+    assert_ranges(v.ranges.cpu().numpy().view(np.uint32)[:-1], ranges)
+
+
+def test_fullsize_render_and_backward(g2):
+    print("case: full-size render + backward on sampled tiles", flush=True)
+    torch, scene, cam, v = g2["torch"], g2["scene"], g2["cam"], g2["view"]
+    tiles, tx, ty = _sample_tiles(cam)
+    m = _tile_mask(cam, tiles, tx)
+    ref = oracle.render(scene, cam, ST, mask=m)
+    on = m == 1
+    part = v.partial.cpu().numpy()
+    cmax = float(rec_fields(v.rec)["rgb"][v.n_tiles.cpu().numpy() > 0].max())
+    e, nf = compare_image(part[on][:, :3], ref["C"][on], ref["flags"][on], 1e-4,
+                          jump_bound(ST, cmax))
+    compare_image(part[on][:, 3], ref["T"][on], ref["flags"][on], 1e-4, 1.0)
+    nb = v.nblend.cpu().numpy()
+    ok = on & (ref["flags"] == 0)
+    assert_same(nb[ok], ref["nblend"][ok], "blended pairs per pixel")
+    print(f"full-size render: {len(tiles)} tiles, max-abs {e:.3g}, flagged {nf}", flush=True)
+    # backward: upstream gradient on the unflagged sampled pixels only
+    rng = np.random.default_rng(17)
+    d = rng.normal(size=(cam.height, cam.width, 4)) * ok[..., None]
+    d32 = d.astype(np.float32)
+    v.ensure_backward_buffers()
+    v.dpartial.copy_(torch.as_tensor(d32).cuda())
+    grads = g2["params"].zeros_like()
+    v.render_backward(v.dpartial)
+    v.preprocess_backward(grads)
+    torch.cuda.synchronize()
+    rb = oracle.render_backward(scene, cam, ST, d32[..., :3].astype(np.float64),
+                                d32[..., 3].astype(np.float64), None, mask=m)
+    g2d = v.g2d.cpu().numpy()[:, :10]
+    hit = np.abs(rb["g2d"]).max(1) > 0
+    assert hit.sum() > 100
+    vis = v.n_tiles.cpu().numpy() > 0
+    for c in range(9):
+        e = rel_err(g2d[vis, c], rb["g2d"][vis, c])
+        assert e <= 2e-3, (c, e)
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        got = getattr(grads, name).cpu().numpy()[vis]
+        assert rel_err(got, rb[name][vis]) <= 2e-3, name

@@ -89,6 +89,27 @@ def test_preprocess_sh3_colour(torch_gpu):
     np.testing.assert_allclose(f["conic"][vis], ref["conic"][vis], rtol=5e-6, atol=1e-9)
 
 
+def test_preprocess_frustum_cull(torch_gpu):
+    """Frustum cull by the mean with the guard off, at the literal field of
+    view and at the default guard: tile counts bit-exact against the oracle
+    on a scene spread far beyond the view, with large footprints."""
+    print("case: preprocess frustum cull guards", flush=True)
+    torch = torch_gpu
+    scene = synth.make_cube_scene(17, 20000, log_scale=(-1.5, 0.5))
+    scene.means *= np.float32(3.0)
+    cam = synth.tiny_camera(120, 90)
+    kept = []
+    for guard in (0.0, 1.0, 1.3):
+        st = synth.RenderSettings(fov_guard=guard)
+        _, v = _cell_view(torch, scene, cam, st)
+        v.preprocess()
+        torch.cuda.synchronize()
+        ref = oracle.preprocess(scene, cam, st)
+        assert_same(v.n_tiles.cpu().numpy().astype(np.int64), ref["n_tiles"], f"guard {guard}")
+        kept.append(int((ref["valid"] == 1).sum()))
+    assert kept[0] > kept[2] > kept[1] > 0, kept
+
+
 # ------------------------------------------------------------------ a2-a4 --
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 8)])
 def test_sort_keys_vals_ranges_bit_exact(torch_gpu, tile):

@@ -89,6 +89,39 @@ def test_on_axis_ewa_closed_form(orc):
         assert abs(r["C"][py, px, 0] - _col(sc)[0] * a) < 1e-15
 
 
+def test_frustum_cull_by_mean(orc):
+    """Projection step: Gaussians whose mean lies outside the camera's field
+    of view are discarded by their mean.  With an off-centre principal point
+    (cx=20 of 64, cy=30 of 48, f=50, z=3) the pixel offset of a mean is
+    50 x / 3; the field of view widened by the guard g spans
+    [-g cx, g (W - cx)] x [-g cy, g (H - cy)].  Every Gaussian below has a
+    footprint that reaches the image, so only the mean test decides."""
+    cam = synth.camera_from_rows(np.eye(3), (0, 0, -3), 64, 48, 50.0, cx=20.0, cy=30.0)
+    pts = [(-1.50, 0.0, True), (-1.62, 0.0, False),   # left:   -25 | -27 vs -26
+           (3.30, 0.0, True), (3.60, 0.0, False),     # right:   55 |  60 vs 57.2
+           (0.0, -2.20, True), (0.0, -2.50, False),   # top:  -36.7 | -41.7 vs -39
+           (0.0, 1.30, True), (0.0, 1.50, False),     # bottom: 21.7 | 25 vs 23.4
+           (0.6, 0.6, True)]                          # (10, 10): inside for g >= 1
+    sc = _one([(x, y, 0.0) for x, y, _ in pts], (0.0, 0.0, 0.0), (1, 0, 0, 0), 4.0,
+              (0.5, 0.5, 0.5))
+    want = np.array([k for _, _, k in pts])
+    pr = orc.preprocess(sc, cam, ST)  # guard 1.3
+    assert_equal = np.testing.assert_array_equal
+    assert_equal(pr["valid"] == 1, want)
+    assert np.all(pr["n_tiles"][want] > 0)
+    off = synth.RenderSettings(fov_guard=0.0)  # the lateral test switched off
+    pr0 = orc.preprocess(sc, cam, off)
+    assert np.all(pr0["valid"] == 1)  # every footprint reaches the image
+    one = synth.RenderSettings(fov_guard=1.0)  # the literal field of view
+    pr1 = orc.preprocess(sc, cam, one)
+    assert_equal(pr1["valid"] == 1, [False] * 8 + [True])
+    # a culled Gaussian contributes nothing: the image equals the render of
+    # the kept ones alone
+    full = orc.render(sc, cam, ST)
+    kept = orc.render(sc.subset(np.nonzero(want)[0]), cam, ST)
+    assert np.array_equal(full["C"], kept["C"]) and np.array_equal(full["T"], kept["T"])
+
+
 def test_rotation_matches_library(orc):
     """Sigma = R S S^T R^T with R from the unit quaternion (w,x,y,z): checked
     against scipy's rotation for a Gaussian on the optical axis, where the
