@@ -96,7 +96,10 @@ typedef struct sx_gaussians {
 /* Per-Gaussian projection written by sx_preprocess (caller-allocated):
  *   rec[n*12]   float record: mean2d - (cx, cy) (2), conic a, b, c of the
  *               inverse 2D covariance (3), opacity, rgb (3), camera depth,
- *               2 unused.  Valid only where n_tiles > 0.
+ *               then the pixel box [x0, x1] x [y0, y1] of the exact
+ *               alpha >= alpha_min footprint as two uint32 words
+ *               x0 | x1 << 16 and y0 | y1 << 16 (the render blends a pixel
+ *               only inside it).  Valid only where n_tiles > 0.
  *   rect[n*4]   uint16 tile rectangle [x0, y0, x1, y1) of the exact
  *               alpha >= alpha_min footprint.
  *   n_tiles[n]  tiles touched; 0 = culled.

@@ -39,6 +39,24 @@ __device__ __forceinline__ int xcd_tile(int b, int ntile) {
 // hides their latency), writes it to the wavefront's own LDS slice, and the
 // wavefront then walks the batch reading each record as a broadcast.  Each
 // wavefront owns its slice, so no workgroup barrier is needed.
+//
+// A pixel blends a Gaussian only inside the pixel box of its exact
+// alpha >= alpha_min footprint (outside it alpha < alpha_min in exact
+// arithmetic).  While staging a batch every lane tests its entry's box
+// against the wavefront's pixel rectangle; the ballot of the results is the
+// set of entries the wavefront walks, in order, with the next entry's
+// record read from LDS while the current one is blended.
+__device__ __forceinline__ bool in_box(int px, int py, float bxw, float byw) {
+  const uint32_t bx = __float_as_uint(bxw), by = __float_as_uint(byw);
+  return (uint32_t)px - (bx & 0xFFFFu) <= (bx >> 16) - (bx & 0xFFFFu) &&
+         (uint32_t)py - (by & 0xFFFFu) <= (by >> 16) - (by & 0xFFFFu);
+}
+// The box meets the pixel rectangle [x0, x1] x [y0, y1].
+__device__ __forceinline__ bool box_meets(float bxw, float byw, int x0, int x1, int y0, int y1) {
+  const uint32_t bx = __float_as_uint(bxw), by = __float_as_uint(byw);
+  return (int)(bx & 0xFFFFu) <= x1 && (int)(bx >> 16) >= x0 && (int)(by & 0xFFFFu) <= y1 &&
+         (int)(by >> 16) >= y0;
+}
 template <int TW, int TH>
 __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
                                             float4 (*s_rec)[3][64]) {
@@ -51,6 +69,10 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
   bool active = inside;
   if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
   const float fx = (float)px + 0.5f - a.cx, fy = (float)py + 0.5f - a.cy;
+  // pixel rectangle of this wavefront (64 consecutive pixels of the tile)
+  constexpr int WR = 64 / TW;  // rows per wavefront
+  const int wx0 = tx * TW, wx1 = wx0 + TW - 1;
+  const int wy0 = ty * TH + w * WR, wy1 = wy0 + WR - 1;
   const uint2 rg = a.ranges[tile];
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   uint32_t lst = 0, nb = 0;
@@ -58,28 +80,42 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
   for (uint32_t jb = rg.x; jb < rg.y; jb += 64) {
     if (__ballot(!done) == 0) break;
     const uint32_t cnt = rg.y - jb < 64u ? rg.y - jb : 64u;
+    bool meets = false;
     if ((uint32_t)lane < cnt) {
       const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)a.vals[jb + lane] * kRecFloats);
-      s_rec[w][0][lane] = r[0];
-      s_rec[w][1][lane] = r[1];
-      s_rec[w][2][lane] = r[2];
+      const float4 q0 = r[0], q1 = r[1], q2 = r[2];
+      s_rec[w][0][lane] = q0;
+      s_rec[w][1][lane] = q1;
+      s_rec[w][2][lane] = q2;
+      meets = box_meets(q2.z, q2.w, wx0, wx1, wy0, wy1);
     }
+    uint64_t todo = __ballot(meets);
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t k = 0; k < cnt; ++k) {
+    int k = todo ? __builtin_ctzll(todo) : 0;
+    float4 n0 = s_rec[w][0][k], n1 = s_rec[w][1][k], n2 = s_rec[w][2][k];
+    while (todo) {
       if (__ballot(!done) == 0) break;
-      const float4 r0 = s_rec[w][0][k], r1 = s_rec[w][1][k], r2 = s_rec[w][2][k];
-      const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-      if (!done && ae.alpha >= a.alpha_min) {
-        const float wt = ae.alpha * T;
-        C0 = fmaf(r1.z, wt, C0);
-        C1 = fmaf(r1.w, wt, C1);
-        C2 = fmaf(r2.x, wt, C2);
-        D = fmaf(r2.y, wt, D);
-        T = T * (1.f - ae.alpha);
-        ++nb;
-        lst = jb + k - rg.x + 1;
-        if (T < a.t_min) done = true;
+      const float4 r0 = n0, r1 = n1, r2 = n2;
+      const int kc = k;
+      todo &= todo - 1;
+      if (todo) {
+        k = __builtin_ctzll(todo);
+        n0 = s_rec[w][0][k], n1 = s_rec[w][1][k], n2 = s_rec[w][2][k];
       }
+      const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
+      // branch-free blend: a lane that does not blend uses alpha = 0, which
+      // leaves C, D and T unchanged exactly
+      const bool use = !done && ae.alpha >= a.alpha_min && in_box(px, py, r2.z, r2.w);
+      const float al = use ? ae.alpha : 0.f;
+      const float wt = al * T;
+      C0 = fmaf(r1.z, wt, C0);
+      C1 = fmaf(r1.w, wt, C1);
+      C2 = fmaf(r2.x, wt, C2);
+      D = fmaf(r2.y, wt, D);
+      T = T * (1.f - al);
+      nb += use ? 1u : 0u;
+      lst = use ? jb + (uint32_t)kc - rg.x + 1 : lst;
+      done = done || (use && T < a.t_min);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -120,6 +156,44 @@ struct RenderBwdArgs {
   uint32_t* __restrict__ pval;      // per row: row index
 };
 
+// Sum of ten per-lane values over the wavefront, stored to dst[0..9].  The
+// values are reduced together by transposition: a 32-lane swap pairs value
+// 2p (kept in lanes 0-31) with 2p+1 (lanes 32-63), a 16-lane swap pairs two
+// such registers so each 16-lane row carries one value, and four DPP steps
+// finish every row; one lane per row stores its value.
+__device__ __forceinline__ float swap_add32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);  // lanes 0-31: a, 32-63: b
+}
+__device__ __forceinline__ float swap_add16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);  // rows: a.lo, b.lo, a.hi, b.hi
+}
+__device__ __forceinline__ float row_sum16(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, true));
+  return v;
+}
+__device__ __forceinline__ void wave_sum10_store(const float (&v)[10], float* dst, int lane,
+                                                 bool ok) {
+  const float u0 = swap_add32(v[0], v[1]), u1 = swap_add32(v[2], v[3]);
+  const float u2 = swap_add32(v[4], v[5]), u3 = swap_add32(v[6], v[7]);
+  const float u4 = swap_add32(v[8], v[9]);
+  // rows of w0: values 0, 2, 1, 3; of w1: 4, 6, 5, 7; of w2: 8, -, 9, -
+  const float w0 = row_sum16(swap_add16(u0, u1));
+  const float w1 = row_sum16(swap_add16(u2, u3));
+  const float w2 = row_sum16(swap_add16(u4, 0.f));
+  const int r = lane >> 4;
+  if ((lane & 15) == 0 && ok) {
+    const int q = ((r & 1) << 1) | (r >> 1);
+    dst[q] = w0;
+    dst[4 + q] = w1;
+    if ((r & 1) == 0) dst[8 + (r >> 1)] = w2;
+  }
+}
+
 // Reverse walk of each pixel's blended pairs.  With R the colour behind pair
 // i (normalised by T_{i+1}), T_final the partial transmittance and
 // (G, g_T, g_D) the gradients of (C^m, T^m, D^m):
@@ -136,13 +210,15 @@ struct RenderBwdArgs {
 // is stored beside it for the per-Gaussian reduction.
 template <int TW, int TH>
 __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile,
-                                                float4 (*s_rec)[64], uint32_t* s_e) {
+                                                float4 (*s_rec)[64]) {
   constexpr int PPT = TW * TH / 64;
+  constexpr int WR = 64 / TW;  // rows per group of 64 pixels
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int lane = threadIdx.x;
   const uint2 rg = a.ranges[tile];
+  int ipx[PPT], ipy[PPT];
   float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
-  float gx[PPT], gy[PPT], gz[PPT], gt[PPT], gd[PPT], Tf[PPT];
+  float gx[PPT], gy[PPT], gz[PPT], gt[PPT], gd[PPT], Tf[PPT], gtf[PPT];
   uint32_t lst[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -152,6 +228,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     const uint32_t pix = inside ? (uint32_t)py * a.W + px : 0u;
     bool active = inside;
     if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
+    ipx[k] = px, ipy[k] = py;
     fx[k] = (float)px + 0.5f - a.cx;
     fy[k] = (float)py + 0.5f - a.cy;
     Tf[k] = 1.f, gx[k] = gy[k] = gz[k] = gt[k] = gd[k] = 0.f;
@@ -164,30 +241,44 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       lst[k] = a.last[pix];
     }
     T[k] = Tf[k];
+    gtf[k] = gt[k] * Tf[k];
     R0[k] = R1[k] = R2[k] = RD[k] = 0.f;
   }
   const uint32_t wave_last = a.nv[tile];  // max of lst over the tile
   const uint32_t row0 = a.vb[tile];
   for (int jend = (int)wave_last; jend > 0; jend -= 64) {
-    // stage entries [jend - cnt, jend): lane i gathers entry jend - cnt + i
-    // and stores its (Gaussian, row) pair
+    // stage entries [jend - cnt, jend): lane i gathers entry jend - cnt + i,
+    // stores its (Gaussian, row) pair and tests its pixel box against each
+    // pixel group; gm[k] bit i = entry j0 + i can reach group k
     const int cnt = jend < 64 ? jend : 64;
     const int j0 = jend - cnt;
+    bool mk[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) mk[k] = false;
     if (lane < cnt) {
       const uint32_t gl = a.vals[rg.x + (uint32_t)(j0 + lane)];
       const float4* rr = reinterpret_cast<const float4*>(a.rec + (size_t)gl * kRecFloats);
-      s_rec[0][lane] = rr[0];
-      s_rec[1][lane] = rr[1];
-      s_rec[2][lane] = rr[2];
+      const float4 q0 = rr[0], q1 = rr[1], q2 = rr[2];
+      s_rec[0][lane] = q0;
+      s_rec[1][lane] = q1;
+      s_rec[2][lane] = q2;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k)
+        mk[k] = box_meets(q2.z, q2.w, tx * TW, tx * TW + TW - 1, ty * TH + k * WR,
+                          ty * TH + k * WR + WR - 1);
       const uint32_t row = row0 + (uint32_t)(j0 + lane);
-      s_e[lane] = row;
       if ((uint64_t)row < a.cap) a.pkey[row] = gl, a.pval[row] = row;
     }
+    uint64_t gm[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) gm[k] = __ballot(mk[k]);
     __builtin_amdgcn_wave_barrier();
+    float4 n0 = s_rec[0][cnt - 1], n1 = s_rec[1][cnt - 1], n2 = s_rec[2][cnt - 1];
   for (int kk = cnt - 1; kk >= 0; --kk) {
     const int j = j0 + kk;
-    const float4 r0 = s_rec[0][kk], r1 = s_rec[1][kk], r2 = s_rec[2][kk];
-    const uint32_t e = s_e[kk];
+    const float4 r0 = n0, r1 = n1, r2 = n2;
+    if (kk > 0) n0 = s_rec[0][kk - 1], n1 = s_rec[1][kk - 1], n2 = s_rec[2][kk - 1];
+    const uint32_t e = row0 + (uint32_t)j;
     float2* dst = reinterpret_cast<float2*>(a.rows + (size_t)e * kRowFloats);
     const bool in_cap = (uint64_t)e < a.cap;
     float v[10];
@@ -196,36 +287,46 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
+      if (((gm[k] >> kk) & 1ull) == 0) continue;  // the box misses pixel group k
+      // branch-free: a lane whose pixel does not blend this entry runs the
+      // same instructions with alpha = 0, which leaves T, R and the sums
+      // unchanged exactly (fma(0, x, s) = s, x * 1 = x)
       const float dx = fx[k] - r0.x, dy = fy[k] - r0.y;
       const AlphaEval ae = eval_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-      if ((uint32_t)j < lst[k] && ae.alpha >= a.alpha_min) {
-        any = true;
-        const float om = 1.f - ae.alpha;
-        const float rom = 1.f / om;
-        const float Ti = T[k] * rom;
-        const float w = ae.alpha * Ti;
-        v[6] += w * gx[k];
-        v[7] += w * gy[k];
-        v[8] += w * gz[k];
-        v[9] += w * gd[k];
-        float da = gx[k] * (r1.z - R0[k]) + gy[k] * (r1.w - R1[k]) + gz[k] * (r2.x - R2[k]) +
-                   gd[k] * (r2.y - RD[k]);
-        da = Ti * da - gt[k] * (Tf[k] * rom);
-        R0[k] = fmaf(r1.z, ae.alpha, om * R0[k]);
-        R1[k] = fmaf(r1.w, ae.alpha, om * R1[k]);
-        R2[k] = fmaf(r2.x, ae.alpha, om * R2[k]);
-        RD[k] = fmaf(r2.y, ae.alpha, om * RD[k]);
-        T[k] = Ti;
-        if (!ae.clamped) {
-          v[5] += da * ae.G;
-          const float dq = -0.5f * ae.alpha * da;
-          v[0] += -2.f * dq * (r0.z * dx + r0.w * dy);
-          v[1] += -2.f * dq * (r0.w * dx + r1.x * dy);
-          v[2] += dq * dx * dx;
-          v[3] += 2.f * dq * dx * dy;
-          v[4] += dq * dy * dy;
-        }
-      }
+      const bool use =
+          (uint32_t)j < lst[k] && ae.alpha >= a.alpha_min && in_box(ipx[k], ipy[k], r2.z, r2.w);
+      any = any || use;
+      const float al = use ? ae.alpha : 0.f;
+      const float om = 1.f - al;  // >= 1 - alpha_max
+      const float rom = __builtin_amdgcn_rcpf(om);
+      const float Ti = T[k] * rom;
+      const float w = al * Ti;
+      v[6] = fmaf(w, gx[k], v[6]);
+      v[7] = fmaf(w, gy[k], v[7]);
+      v[8] = fmaf(w, gz[k], v[8]);
+      v[9] = fmaf(w, gd[k], v[9]);
+      const float d0 = r1.z - R0[k], d1 = r1.w - R1[k], d2 = r2.x - R2[k], dd = r2.y - RD[k];
+      float da = gx[k] * d0;
+      da = fmaf(gy[k], d1, da);
+      da = fmaf(gz[k], d2, da);
+      da = fmaf(gd[k], dd, da);
+      da = fmaf(Ti, da, -(gtf[k] * rom));
+      // R <- alpha c + (1 - alpha) R
+      R0[k] = fmaf(al, d0, R0[k]);
+      R1[k] = fmaf(al, d1, R1[k]);
+      R2[k] = fmaf(al, d2, R2[k]);
+      RD[k] = fmaf(al, dd, RD[k]);
+      T[k] = Ti;
+      const float dae = use && !ae.clamped ? da : 0.f;  // alpha clamped: no o, q terms
+      v[5] = fmaf(dae, ae.G, v[5]);
+      const float dq = -0.5f * al * dae;
+      const float m2 = -2.f * dq;
+      v[0] = fmaf(m2, fmaf(r0.z, dx, r0.w * dy), v[0]);
+      v[1] = fmaf(m2, fmaf(r0.w, dx, r1.x * dy), v[1]);
+      const float qx = dq * dx, qy = dq * dy;
+      v[2] = fmaf(qx, dx, v[2]);
+      v[3] = fmaf(qx + qx, dy, v[3]);
+      v[4] = fmaf(qy, dy, v[4]);
     }
     if (__ballot(any) == 0) {
       if (lane == 63 && in_cap) {
@@ -234,16 +335,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       }
       continue;
     }
-    float sum[10];
-#pragma unroll
-    for (int m = 0; m < 10; ++m) sum[m] = wave_sum_to_lane63(v[m]);
-    if (lane == 63 && in_cap) {
-      dst[0] = make_float2(sum[0], sum[1]);
-      dst[1] = make_float2(sum[2], sum[3]);
-      dst[2] = make_float2(sum[4], sum[5]);
-      dst[3] = make_float2(sum[6], sum[7]);
-      dst[4] = make_float2(sum[8], sum[9]);
-    }
+    wave_sum10_store(v, reinterpret_cast<float*>(dst), lane, in_cap);
   }
     __builtin_amdgcn_wave_barrier();
   }
@@ -252,11 +344,10 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   __shared__ float4 s_rec[3][64];
-  __shared__ uint32_t s_e[64];
   const int ntile = a.tiles_x * a.tiles_y;
   const int tile = xcd_tile(blockIdx.x, ntile);
   if (tile >= ntile) return;
-  render_tile_bwd<TW, TH>(a, tile, s_rec, s_e);
+  render_tile_bwd<TW, TH>(a, tile, s_rec);
 }
 
 // Entries each tile's reverse walk visits: the largest `last` over its
@@ -502,14 +593,13 @@ static_assert(sizeof(RenderMultiArgs) <= 4096, "kernel argument block too large"
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_render_bwd_multi(RenderBwdMultiArgs m) {
   __shared__ float4 s_rec[3][64];
-  __shared__ uint32_t s_e[64];
   for (;;) {
     uint32_t it = 0;
     if (threadIdx.x == 0) it = atomicAdd(m.counter, 1u);
     it = __shfl(it, 0, 64);
     if (it >= m.n_items) break;
     const uint32_t code = m.items[it];
-    render_tile_bwd<TW, TH>(m.view[code >> 24], (int)(code & 0xFFFFFF), s_rec, s_e);
+    render_tile_bwd<TW, TH>(m.view[code >> 24], (int)(code & 0xFFFFFF), s_rec);
   }
 }
 
