@@ -80,8 +80,10 @@ class Step:
         self.view.preprocess()
         self.counts = self.view.sort(sync=True)
         self.view._alloc_sort(int(self.counts[1] * 1.05) + 4096)
+        self.view.ensure_backward_buffers()  # sized for the new capacity
         self.stage_names = ["preprocess", "sort", "render", "composite", "l1",
-                            "composite_bwd", "render_bwd", "preprocess_bwd"]
+                            "composite_bwd", "render_bwd_prep", "render_bwd_walk",
+                            "render_bwd_reduce", "preprocess_bwd"]
 
     def run(self, events=None, count=False):
         B, v = self.B, self.view
@@ -100,30 +102,40 @@ class Step:
         B.sx_composite_backward([v.partial], self.box, self.c_cam, self.c_par, self.dout,
                                 [v.dpartial])
         if ev: ev[6].record()
-        v.render_backward(v.dpartial)
-        if ev: ev[7].record()
+        # the three stages of sx_render_backward, called one by one so that
+        # events bracket the reverse walk alone
+        for i, stage in enumerate((B.SX_RB_PREPARE, B.SX_RB_WALK, B.SX_RB_REDUCE)):
+            B.sx_render_backward_stages(v.c_proj, v.vals, v.ranges, v.ws, v.params.n,
+                                        v.capacity, v.bwd_ws, self.c_cam, self.c_par, None,
+                                        v.partial, v.last, v.dpartial, None, v.g2d, stage)
+            if ev: ev[7 + i].record()
         v.preprocess_backward(self.grads)
-        if ev: ev[8].record()
+        if ev: ev[10].record()
 
 
-def cpu_baseline(scene, cam, settings):
+def cpu_baseline(scene, cam, settings, min_s=10.0, max_steps=20):
     """The FP64 oracle (as it stands, all host threads) on the same step:
     the full 1920x1080 view of the 2M-Gaussian scene, forward (projection,
-    binned render, composition), L1 loss and backward; blends/s."""
+    binned render, composition), L1 loss and backward, repeated until
+    `min_s` seconds have passed (at most `max_steps` steps); blends/s."""
     import oracle
     import synth
     oracle.build()
     cores = oracle.num_threads()
     box = synth.Cell((-1e30,) * 3, (1e30,) * 3)
+    target = synth.g2_target()
+    blends, steps = 0, 0
     t0 = time.perf_counter()
-    fr = oracle.forward([scene], [box], cam, settings)
-    _, g = oracle.l1_loss(fr.comp["rgb"], synth.g2_target())
-    oracle.backward([scene], [box], cam, settings, fr, g)
+    while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_s):
+        fr = oracle.forward([scene], [box], cam, settings)
+        _, g = oracle.l1_loss(fr.comp["rgb"], target)
+        oracle.backward([scene], [box], cam, settings, fr, g)
+        blends += int(fr.parts[0]["nblend"].sum())
+        steps += 1
     dt = time.perf_counter() - t0
-    blends = int(fr.parts[0]["nblend"].sum())
     return {"value": blends / dt, "unit": "blends/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full step: the 1920x1080 view of the 2M-Gaussian scene, FP64 "
-                      f"forward + L1 + backward, {blends} blends in {dt:.2f} s"}
+            "sample": f"{steps} full steps: the 1920x1080 view of the 2M-Gaussian scene, "
+                      f"FP64 forward + L1 + backward, {blends} blends in {dt:.2f} s"}
 
 
 def main():
@@ -172,6 +184,7 @@ def main():
     st.run(count=True)
     torch.cuda.synchronize()
     blends = int(st.view.nblend.sum().item())
+    st.blends = blends
     n_vis, n_inst = st.counts
     log(f"bench: visible {n_vis} instances {n_inst} blends {blends}")
     for _ in range(args.warmup):
@@ -347,6 +360,7 @@ KERNEL_OF_STAGE = {
     "preprocess": ("k_preprocess<3>", "sx_preprocess.hip"),
     "preprocess_bwd": ("k_preprocess_backward<3, false>", "sx_preprocess.hip"),
     "render": ("k_render<16, 16>", "sx_render.hip"),
+    "render_bwd_walk": ("k_render_bwd<16, 16>", "sx_render.hip"),
 }
 PMC_FILE = os.path.join(ROOT, "profiles", "g2_pmc_traffic.txt")
 
@@ -383,12 +397,18 @@ def roofline(st, stage_ms):
     stage = max(KERNEL_OF_STAGE, key=lambda k: stage_ms[k])
     ms = stage_ms[stage]
     kernel, src = KERNEL_OF_STAGE[stage]
-    if stage == "render":
-        evals = n_inst * 256
-        ops = 13.0 * evals
+    if stage in ("render", "render_bwd_walk"):
+        # FP32 lane-operation slots (a transcendental or reciprocal takes 4):
+        # forward 15 per pair evaluation (every instance x tile pixels) and 8
+        # more per blend; reverse walk 53 per blend
+        if stage == "render":
+            ops = 15.0 * n_inst * 256 + 8.0 * st.blends
+        else:
+            ops = 53.0 * st.blends
         ach = ops / (ms / 1e3) / 1e12
         return {"bound": "alu", "kernel": kernel, "achieved": ach, "peak": ALU_PEAK_TOPS,
-                "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS, "traffic": None}
+                "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS, "traffic": pmc_traffic(kernel, src),
+                "algorithmic_ops": ops}
     if stage == "preprocess":
         # every Gaussian: mean read (12 B), tile count written (4 B); the
         # visible ones also read logit, scales, rotation and SH and write the

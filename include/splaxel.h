@@ -294,6 +294,28 @@ sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
                              const float* partial, const uint32_t* last,
                              const float* dpartial, const float* ddepth,
                              float* g2d, sx_stream stream);
+/* The three stages of sx_render_backward, for callers that schedule or time
+ * them separately; stages is a mask of SX_RB_* bits and the stages must run
+ * in this order on one stream with the same arguments:
+ *   SX_RB_PREPARE  entries each tile's reverse walk visits (the largest
+ *                  `last` over its pixels) and the first gradient row of
+ *                  each tile;
+ *   SX_RB_WALK     the reverse walk (Eq. 6-7): one gradient row per visited
+ *                  entry in bwd_ws;
+ *   SX_RB_REDUCE   the rows summed per Gaussian into g2d.
+ * sx_render_backward is this call with SX_RB_ALL. */
+#define SX_RB_PREPARE 1
+#define SX_RB_WALK 2
+#define SX_RB_REDUCE 4
+#define SX_RB_ALL 7
+sx_status sx_render_backward_stages(const sx_projected* proj, const uint32_t* vals,
+                                    const uint32_t* tile_ranges, const void* sort_ws,
+                                    int64_t n, int64_t capacity, void* bwd_ws,
+                                    const sx_camera* cam, const sx_params* p,
+                                    const uint32_t* mask, const float* partial,
+                                    const uint32_t* last, const float* dpartial,
+                                    const float* ddepth, float* g2d, int32_t stages,
+                                    sx_stream stream);
 /* sort_ws/capacity: the sort of this view (its list of visible Gaussians
  * drives the launch). */
 sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,

@@ -23,6 +23,7 @@ SX_ECAPACITY = -2
 SX_EDEVICE = -3
 SX_FLAG_SAME_FRAME_CULL = 1
 SX_BWD_ACCUMULATE = 1
+SX_RB_PREPARE, SX_RB_WALK, SX_RB_REDUCE, SX_RB_ALL = 1, 2, 4, 7
 
 c_f = ctypes.c_float
 c_i32 = ctypes.c_int32
@@ -87,6 +88,7 @@ EXPORTS = (
     "sx_composite_backward", "sx_render_backward", "sx_preprocess_backward",
     "sx_adam", "sx_fill_u32", "sx_preprocess_multi", "sx_multi_workspace_size",
     "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
+    "sx_render_backward_stages",
 )
 
 _lib = None
@@ -304,6 +306,17 @@ def sx_render_backward(proj: SxProjected, vals, ranges, sort_ws, n: int,
         c_i64(capacity), ptr(bwd_ws), ctypes.byref(cam), ctypes.byref(p),
         ptr(mask), ptr(partial), ptr(last), ptr(dpartial), ptr(ddepth),
         ptr(g2d), stream_handle(stream)))
+
+
+def sx_render_backward_stages(proj: SxProjected, vals, ranges, sort_ws, n: int,
+                              capacity: int, bwd_ws, cam: SxCamera, p: SxParams,
+                              mask, partial, last, dpartial, ddepth, g2d, stages: int,
+                              stream=None) -> None:
+    _check("sx_render_backward_stages", lib().sx_render_backward_stages(
+        ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(sort_ws), c_i64(n),
+        c_i64(capacity), ptr(bwd_ws), ctypes.byref(cam), ctypes.byref(p),
+        ptr(mask), ptr(partial), ptr(last), ptr(dpartial), ptr(ddepth),
+        ptr(g2d), c_i32(stages), stream_handle(stream)))
 
 
 def sx_preprocess_backward(g: SxGaussians, cam: SxCamera, p: SxParams,

@@ -237,6 +237,29 @@ sx_status sx_backward_workspace_size(int64_t capacity, int64_t tiles_total, size
   return SX_OK;
 }
 
+sx_status sx_render_backward_stages(const sx_projected* proj, const uint32_t* vals,
+                                    const uint32_t* tile_ranges, const void* sort_ws,
+                                    int64_t n, int64_t capacity, void* bwd_ws,
+                                    const sx_camera* cam, const sx_params* p,
+                                    const uint32_t* mask, const float* partial,
+                                    const uint32_t* last, const float* dpartial,
+                                    const float* ddepth, float* g2d, int32_t stages,
+                                    sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  if (!proj || !proj->rec || !proj->n_tiles || !proj->rect || !tile_ranges || !sort_ws || !bwd_ws ||
+      !partial || !last || !dpartial || !g2d)
+    return fail(SX_EINVAL, "null argument");
+  if (n < 0 || capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "bad n/capacity");
+  if (stages & ~SX_RB_ALL) return fail(SX_EINVAL, "unknown stage bits 0x%x", stages);
+  const sx::KParams kp = sx::make_kparams(*p, *cam);
+  return dev(sx::launch_render_backward(*proj, vals, tile_ranges, sx::sort_view(sort_ws, n, capacity, kp.tiles_x, kp.tiles_y),
+                                        n, capacity, sx::make_dcam(*cam), kp, mask,
+                                        partial, last, dpartial, ddepth, g2d, static_cast<char*>(bwd_ws),
+                                        stages, (hipStream_t)stream),
+             "sx_render_backward");
+}
+
 sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
                              const uint32_t* tile_ranges, const void* sort_ws,
                              int64_t n, int64_t capacity, void* bwd_ws,
@@ -244,18 +267,8 @@ sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
                              const uint32_t* mask, const float* partial,
                              const uint32_t* last, const float* dpartial,
                              const float* ddepth, float* g2d, sx_stream stream) {
-  SX_TRY(check_cam(cam));
-  SX_TRY(check_params(p));
-  if (!proj || !proj->rec || !proj->n_tiles || !proj->rect || !tile_ranges || !sort_ws || !bwd_ws ||
-      !partial || !last || !dpartial || !g2d)
-    return fail(SX_EINVAL, "null argument");
-  if (n < 0 || capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "bad n/capacity");
-  const sx::KParams kp = sx::make_kparams(*p, *cam);
-  return dev(sx::launch_render_backward(*proj, vals, tile_ranges, sx::sort_view(sort_ws, n, capacity, kp.tiles_x, kp.tiles_y),
-                                        n, capacity, sx::make_dcam(*cam), kp, mask,
-                                        partial, last, dpartial, ddepth, g2d, static_cast<char*>(bwd_ws),
-                                        (hipStream_t)stream),
-             "sx_render_backward");
+  return sx_render_backward_stages(proj, vals, tile_ranges, sort_ws, n, capacity, bwd_ws, cam, p,
+                                   mask, partial, last, dpartial, ddepth, g2d, SX_RB_ALL, stream);
 }
 
 sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,

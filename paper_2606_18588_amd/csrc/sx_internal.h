@@ -280,7 +280,7 @@ hipError_t launch_render_backward(const sx_projected& proj,
                                   const DCam& cam, const KParams& p,
                                   const uint32_t* mask, const float* partial,
                                   const uint32_t* last, const float* dpartial,
-                                  const float* ddepth, float* g2d, char* bws,
+                                  const float* ddepth, float* g2d, char* bws, int stages,
                                   hipStream_t st);
 // one view of a batched call, in kernel-ready form
 struct MultiView {

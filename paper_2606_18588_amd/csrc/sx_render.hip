@@ -754,15 +754,18 @@ hipError_t launch_render_backward(const sx_projected& proj,
                                   const DCam& cam, const KParams& p,
                                   const uint32_t* mask, const float* partial,
                                   const uint32_t* last, const float* dpartial,
-                                  const float* ddepth, float* g2d, char* bws,
+                                  const float* ddepth, float* g2d, char* bws, int stages,
                                   hipStream_t st) {
   RenderBwdArgs a = make_bwd_args(proj, vals, ranges, capacity, cam, p, mask, partial, last,
                                   dpartial, ddepth, bws);
-  hipError_t e = launch_bwd_prepare(a, p, capacity, bws, st);
-  if (e) return e;
-  SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_t, a, st);
-  if ((e = hipGetLastError())) return e;
-  return launch_bwd_reduce(sv, n, capacity, p, g2d, bws, st);
+  hipError_t e = hipSuccess;
+  if ((stages & SX_RB_PREPARE) && (e = launch_bwd_prepare(a, p, capacity, bws, st))) return e;
+  if (stages & SX_RB_WALK) {
+    SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_t, a, st);
+    if ((e = hipGetLastError())) return e;
+  }
+  if (stages & SX_RB_REDUCE) return launch_bwd_reduce(sv, n, capacity, p, g2d, bws, st);
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------ multi-view --
