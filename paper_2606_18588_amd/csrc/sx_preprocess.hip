@@ -199,8 +199,8 @@ __device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
   r1.z = (float)fmax(col[0] + 0.5, 0.0), r1.w = (float)fmax(col[1] + 0.5, 0.0);
   r2.x = (float)fmax(col[2] + 0.5, 0.0), r2.y = (float)z;
   // pixel box of the footprint (inside the image, so 16-bit coordinates)
-  r2.z = __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16));
-  r2.w = __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16));
+  r2.z = __uint_as_float((uint32_t)x0 | ((uint32_t)(x1 - x0) << 16));
+  r2.w = __uint_as_float((uint32_t)y0 | ((uint32_t)(y1 - y0) << 16));
   reinterpret_cast<float4*>(r)[0] = r0;
   reinterpret_cast<float4*>(r)[1] = r1;
   reinterpret_cast<float4*>(r)[2] = r2;

@@ -44,18 +44,18 @@ __device__ __forceinline__ int xcd_tile(int b, int ntile) {
 // alpha >= alpha_min footprint (outside it alpha < alpha_min in exact
 // arithmetic).  While staging a batch every lane tests its entry's box
 // against the wavefront's pixel rectangle; the ballot of the results is the
-// set of entries the wavefront walks, in order, with the next entry's
-// record read from LDS while the current one is blended.
+// set of entries the wavefront walks, in order, two records per LDS round
+// trip.
+// The box words hold (x0 | (x1 - x0) << 16) and (y0 | (y1 - y0) << 16).
 __device__ __forceinline__ bool in_box(int px, int py, float bxw, float byw) {
   const uint32_t bx = __float_as_uint(bxw), by = __float_as_uint(byw);
-  return (uint32_t)px - (bx & 0xFFFFu) <= (bx >> 16) - (bx & 0xFFFFu) &&
-         (uint32_t)py - (by & 0xFFFFu) <= (by >> 16) - (by & 0xFFFFu);
+  return (uint32_t)px - (bx & 0xFFFFu) <= (bx >> 16) && (uint32_t)py - (by & 0xFFFFu) <= (by >> 16);
 }
 // The box meets the pixel rectangle [x0, x1] x [y0, y1].
 __device__ __forceinline__ bool box_meets(float bxw, float byw, int x0, int x1, int y0, int y1) {
   const uint32_t bx = __float_as_uint(bxw), by = __float_as_uint(byw);
-  return (int)(bx & 0xFFFFu) <= x1 && (int)(bx >> 16) >= x0 && (int)(by & 0xFFFFu) <= y1 &&
-         (int)(by >> 16) >= y0;
+  const int bx0 = (int)(bx & 0xFFFFu), by0 = (int)(by & 0xFFFFu);
+  return bx0 <= x1 && bx0 + (int)(bx >> 16) >= x0 && by0 <= y1 && by0 + (int)(by >> 16) >= y0;
 }
 template <int TW, int TH>
 __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
@@ -91,20 +91,10 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
     }
     uint64_t todo = __ballot(meets);
     __builtin_amdgcn_wave_barrier();
-    int k = todo ? __builtin_ctzll(todo) : 0;
-    float4 n0 = s_rec[w][0][k], n1 = s_rec[w][1][k], n2 = s_rec[w][2][k];
-    while (todo) {
-      if (__ballot(!done) == 0) break;
-      const float4 r0 = n0, r1 = n1, r2 = n2;
-      const int kc = k;
-      todo &= todo - 1;
-      if (todo) {
-        k = __builtin_ctzll(todo);
-        n0 = s_rec[w][0][k], n1 = s_rec[w][1][k], n2 = s_rec[w][2][k];
-      }
+    // branch-free blend: a lane that does not blend uses alpha = 0, which
+    // leaves C, D and T unchanged exactly
+    auto blend = [&](const float4& r0, const float4& r1, const float4& r2, uint32_t kc) {
       const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-      // branch-free blend: a lane that does not blend uses alpha = 0, which
-      // leaves C, D and T unchanged exactly
       const bool use = !done && ae.alpha >= a.alpha_min && in_box(px, py, r2.z, r2.w);
       const float al = use ? ae.alpha : 0.f;
       const float wt = al * T;
@@ -114,8 +104,21 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
       D = fmaf(r2.y, wt, D);
       T = T * (1.f - al);
       nb += use ? 1u : 0u;
-      lst = use ? jb + (uint32_t)kc - rg.x + 1 : lst;
+      lst = use ? jb + kc - rg.x + 1 : lst;
       done = done || (use && T < a.t_min);
+    };
+    // two entries per LDS round trip
+    while (todo) {
+      if (__ballot(!done) == 0) break;
+      const uint32_t k1 = (uint32_t)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      const bool two = todo != 0;
+      const uint32_t k2 = two ? (uint32_t)__builtin_ctzll(todo) : k1;
+      todo &= two ? todo - 1 : todo;
+      const float4 p0 = s_rec[w][0][k1], p1 = s_rec[w][1][k1], p2 = s_rec[w][2][k1];
+      const float4 q0 = s_rec[w][0][k2], q1 = s_rec[w][1][k2], q2 = s_rec[w][2][k2];
+      blend(p0, p1, p2, k1);
+      if (two) blend(q0, q1, q2, k2);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -273,11 +276,8 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
 #pragma unroll
     for (int k = 0; k < PPT; ++k) gm[k] = __ballot(mk[k]);
     __builtin_amdgcn_wave_barrier();
-    float4 n0 = s_rec[0][cnt - 1], n1 = s_rec[1][cnt - 1], n2 = s_rec[2][cnt - 1];
-  for (int kk = cnt - 1; kk >= 0; --kk) {
+    auto entry = [&](const float4& r0, const float4& r1, const float4& r2, int kk) {
     const int j = j0 + kk;
-    const float4 r0 = n0, r1 = n1, r2 = n2;
-    if (kk > 0) n0 = s_rec[0][kk - 1], n1 = s_rec[1][kk - 1], n2 = s_rec[2][kk - 1];
     const uint32_t e = row0 + (uint32_t)j;
     float2* dst = reinterpret_cast<float2*>(a.rows + (size_t)e * kRowFloats);
     const bool in_cap = (uint64_t)e < a.cap;
@@ -333,10 +333,19 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
         const float2 z = make_float2(0.f, 0.f);
         dst[0] = z, dst[1] = z, dst[2] = z, dst[3] = z, dst[4] = z;
       }
-      continue;
+      return;
     }
     wave_sum10_store(v, reinterpret_cast<float*>(dst), lane, in_cap);
-  }
+    };
+    // two entries per LDS round trip, back to front
+    for (int kk = cnt - 1; kk >= 0; kk -= 2) {
+      const bool two = kk >= 1;
+      const int k2 = two ? kk - 1 : kk;
+      const float4 p0 = s_rec[0][kk], p1 = s_rec[1][kk], p2 = s_rec[2][kk];
+      const float4 q0 = s_rec[0][k2], q1 = s_rec[1][k2], q2 = s_rec[2][k2];
+      entry(p0, p1, p2, kk);
+      if (two) entry(q0, q1, q2, k2);
+    }
     __builtin_amdgcn_wave_barrier();
   }
 }
