@@ -211,7 +211,9 @@ __device__ __forceinline__ void wave_sum10_store(const float (&v)[10], float* ds
 // pixels reached, and the j-th of them owns gradient row vb[tile] + j (rows
 // of entries without any contribution are zeros); the row's Gaussian index
 // is stored beside it for the per-Gaussian reduction.
-template <int TW, int TH>
+// DG: a depth gradient is given (otherwise its terms are compiled out,
+// which frees the registers of two per-pixel quantities).
+template <int TW, int TH, bool DG>
 __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile,
                                                 float4 (*s_rec)[64]) {
   constexpr int PPT = TW * TH / 64;
@@ -219,9 +221,9 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int lane = threadIdx.x;
   const uint2 rg = a.ranges[tile];
-  int ipx[PPT], ipy[PPT];
+  uint32_t pxy[PPT];  // pixel x | y << 16
   float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
-  float gx[PPT], gy[PPT], gz[PPT], gt[PPT], gd[PPT], Tf[PPT], gtf[PPT];
+  float gx[PPT], gy[PPT], gz[PPT], gd[PPT], gtf[PPT];
   uint32_t lst[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -231,20 +233,21 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     const uint32_t pix = inside ? (uint32_t)py * a.W + px : 0u;
     bool active = inside;
     if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
-    ipx[k] = px, ipy[k] = py;
+    pxy[k] = (uint32_t)px | ((uint32_t)py << 16);
     fx[k] = (float)px + 0.5f - a.cx;
     fy[k] = (float)py + 0.5f - a.cy;
-    Tf[k] = 1.f, gx[k] = gy[k] = gz[k] = gt[k] = gd[k] = 0.f;
+    float Tf = 1.f, gt = 0.f;
+    gx[k] = gy[k] = gz[k] = gd[k] = 0.f;
     lst[k] = 0;
     if (active) {
-      Tf[k] = a.partial[pix].w;
+      Tf = a.partial[pix].w;
       const float4 g = a.dpartial[pix];
-      gx[k] = g.x, gy[k] = g.y, gz[k] = g.z, gt[k] = g.w;
-      if (a.ddepth) gd[k] = a.ddepth[pix];
+      gx[k] = g.x, gy[k] = g.y, gz[k] = g.z, gt = g.w;
+      if (DG) gd[k] = a.ddepth[pix];
       lst[k] = a.last[pix];
     }
-    T[k] = Tf[k];
-    gtf[k] = gt[k] * Tf[k];
+    T[k] = Tf;
+    gtf[k] = gt * Tf;
     R0[k] = R1[k] = R2[k] = RD[k] = 0.f;
   }
   const uint32_t wave_last = a.nv[tile];  // max of lst over the tile
@@ -293,8 +296,8 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       // unchanged exactly (fma(0, x, s) = s, x * 1 = x)
       const float dx = fx[k] - r0.x, dy = fy[k] - r0.y;
       const AlphaEval ae = eval_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-      const bool use =
-          (uint32_t)j < lst[k] && ae.alpha >= a.alpha_min && in_box(ipx[k], ipy[k], r2.z, r2.w);
+      const bool use = (uint32_t)j < lst[k] && ae.alpha >= a.alpha_min &&
+                       in_box((int)(pxy[k] & 0xFFFFu), (int)(pxy[k] >> 16), r2.z, r2.w);
       any = any || use;
       const float al = use ? ae.alpha : 0.f;
       const float om = 1.f - al;  // >= 1 - alpha_max
@@ -304,18 +307,21 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       v[6] = fmaf(w, gx[k], v[6]);
       v[7] = fmaf(w, gy[k], v[7]);
       v[8] = fmaf(w, gz[k], v[8]);
-      v[9] = fmaf(w, gd[k], v[9]);
-      const float d0 = r1.z - R0[k], d1 = r1.w - R1[k], d2 = r2.x - R2[k], dd = r2.y - RD[k];
+      const float d0 = r1.z - R0[k], d1 = r1.w - R1[k], d2 = r2.x - R2[k];
       float da = gx[k] * d0;
       da = fmaf(gy[k], d1, da);
       da = fmaf(gz[k], d2, da);
-      da = fmaf(gd[k], dd, da);
+      if constexpr (DG) {
+        const float dd = r2.y - RD[k];
+        v[9] = fmaf(w, gd[k], v[9]);
+        da = fmaf(gd[k], dd, da);
+        RD[k] = fmaf(al, dd, RD[k]);
+      }
       da = fmaf(Ti, da, -(gtf[k] * rom));
       // R <- alpha c + (1 - alpha) R
       R0[k] = fmaf(al, d0, R0[k]);
       R1[k] = fmaf(al, d1, R1[k]);
       R2[k] = fmaf(al, d2, R2[k]);
-      RD[k] = fmaf(al, dd, RD[k]);
       T[k] = Ti;
       const float dae = use && !ae.clamped ? da : 0.f;  // alpha clamped: no o, q terms
       v[5] = fmaf(dae, ae.G, v[5]);
@@ -350,13 +356,13 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool DG>
 __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   __shared__ float4 s_rec[3][64];
   const int ntile = a.tiles_x * a.tiles_y;
   const int tile = xcd_tile(blockIdx.x, ntile);
   if (tile >= ntile) return;
-  render_tile_bwd<TW, TH>(a, tile, s_rec);
+  render_tile_bwd<TW, TH, DG>(a, tile, s_rec);
 }
 
 // Entries each tile's reverse walk visits: the largest `last` over its
@@ -608,7 +614,8 @@ __global__ __launch_bounds__(64) void k_render_bwd_multi(RenderBwdMultiArgs m) {
     it = __shfl(it, 0, 64);
     if (it >= m.n_items) break;
     const uint32_t code = m.items[it];
-    render_tile_bwd<TW, TH>(m.view[code >> 24], (int)(code & 0xFFFFFF), s_rec);
+    // batched views carry no depth gradient
+    render_tile_bwd<TW, TH, false>(m.view[code >> 24], (int)(code & 0xFFFFFF), s_rec);
   }
 }
 
@@ -629,7 +636,10 @@ template <int TW, int TH>
 static void launch_bwd_t(const RenderBwdArgs& a, hipStream_t st) {
   const int ntile = a.tiles_x * a.tiles_y;
   const int grid = ((ntile + 7) >> 3) * 8;
-  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(64), 0, st, a);
+  if (a.ddepth)
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3(grid), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3(grid), dim3(64), 0, st, a);
 }
 
 #define SX_DISPATCH_TILE(tw, th, FN, ARGS, ST)           \
