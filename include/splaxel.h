@@ -376,19 +376,22 @@ sx_status sx_preprocess_multi(const sx_gaussians* g, int32_t V,
                               const sx_camera* cams, const sx_params* p,
                               sx_projected* outs, sx_stream stream);
 
-/* Workspace of the shared work queue: bytes for V views with cams[V]. */
+/* Workspace of the batched launches: bytes for V views with cams[V] (the
+ * current launches need only a small block; callers size it with this query
+ * so the layout can change without an interface change). */
 sx_status sx_multi_workspace_size(int32_t V, const sx_camera* cams,
                                   const sx_params* p, size_t* bytes);
 
-/* Partial render (Eq. 3-4) of V views in one persistent launch; each view
- * needs proj, vals, tile_ranges, mask, partial, depth, last, nblend.
+/* Partial render (Eq. 3-4) of V views in one launch (one workgroup per
+ * (view, tile)); each view needs proj, vals, tile_ranges, mask, partial,
+ * depth, last, nblend.
  * views: host array [V]; ws: device workspace (contents scratch). */
 sx_status sx_render_multi(int32_t V, const sx_view* views,
                           const sx_params* p, void* ws, size_t ws_bytes,
                           sx_stream stream);
 
 /* Render backward (Eq. 6-7 through each view's local render) of V views of
- * one cell of n Gaussians in one persistent launch, then each view's
+ * one cell of n Gaussians in one launch, then each view's
  * per-Gaussian reduction into views[v].g2d; each view needs every member.
  * Follow with sx_preprocess_backward_multi (or sx_preprocess_backward per
  * view) to sum the views' parameter gradients. */

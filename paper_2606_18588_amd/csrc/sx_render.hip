@@ -1,16 +1,14 @@
 // Partial render of one cell (Eq. 1-4) and its backward (Eq. 6-7, the part
 // local to one cell).
 //
-// One workgroup per screen tile, one lane per pixel.  Every lane of a tile
-// walks the same depth-sorted list, so the Gaussian index and its 48-byte
-// record are wavefront-uniform: they are fetched with scalar loads into
-// SGPRs and feed the VALU directly as scalar operands.  No LDS staging and
-// no workgroup barrier is needed; each wavefront leaves the list as soon as
-// a ballot says all its pixels are saturated (T < t_min) or masked.
-//
-// Workgroups are dispatched round-robin over the 8 XCDs of the chip; the
-// block -> tile map gives every XCD a contiguous band of tiles so that
-// neighbouring tiles, which share most of their Gaussians, share an L2.
+// One workgroup per screen tile, in raster order (workgroup b renders tile
+// b).  Every lane of a tile walks the same depth-sorted list: records are
+// staged per wavefront in LDS and read as broadcasts, no workgroup barrier
+// is needed, and each wavefront leaves the list as soon as a ballot says
+// all its pixels are saturated (T < t_min) or masked.  (A block -> tile map
+// that gave each XCD a contiguous band of tiles, for L2 sharing, measured
+// 1.7x slower: the rasterizers are bound by VALU issue, and the bands
+// differ in cost, so the XCDs finished at different times.)
 #include "sx_internal.h"
 
 namespace sx {
@@ -29,10 +27,7 @@ struct RenderArgs {
   uint32_t* __restrict__ nblend;
 };
 
-__device__ __forceinline__ int xcd_tile(int b, int ntile) {
-  const int per = (ntile + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
-}
+
 
 // Records are staged per wavefront in batches of 64: lane i gathers the
 // record of list entry jb+i with vector loads (64 gathers in flight, which
@@ -134,7 +129,7 @@ template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
   __shared__ float4 s_rec[TW * TH / 64][3][64];
   const int ntile = a.tiles_x * a.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, ntile);
+  const int tile = blockIdx.x;
   if (tile >= ntile) return;
   render_tile<TW, TH>(a, tile, s_rec);
 }
@@ -360,7 +355,7 @@ template <int TW, int TH, bool DG>
 __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   __shared__ float4 s_rec[3][64];
   const int ntile = a.tiles_x * a.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, ntile);
+  const int tile = blockIdx.x;
   if (tile >= ntile) return;
   render_tile_bwd<TW, TH, DG>(a, tile, s_rec);
 }
@@ -508,98 +503,34 @@ __global__ __launch_bounds__(256) void k_zero_g2d(const uint32_t* __restrict__ v
 }
 
 // ------------------------------------------------------------ multi-view --
-// Many views in one persistent launch: the (view, tile) work items of all
-// views are ordered by descending cost class (bit length of the tile's list
-// length) and workgroups take items from a global counter until none is
-// left, so large and small views share the GPU with no per-view tail.
-struct WorkArgs {
-  int V;
-  uint32_t base[kMaxViews + 1];  // first work item of each view
-  const uint2* ranges[kMaxViews];
-  uint32_t* hist;    // [32] items per cost class
-  uint32_t* cursor;  // [32]
-  uint32_t* items;   // [n] (view << 24) | tile
-};
-
-__device__ __forceinline__ int work_view(const WorkArgs& w, uint32_t item) {
+// Many views in one launch: workgroup b takes the b-th (view, tile) item of
+// the views laid end to end, tiles in raster order within a view.  (Ordering
+// the items by list length and pulling them from a device counter measured
+// slower than this plain order.)
+__device__ __forceinline__ int item_view(const uint32_t* base, int V, uint32_t b) {
   int v = 0;
-  while (v + 1 < w.V && item >= w.base[v + 1]) ++v;
+  while (v + 1 < V && b >= base[v + 1]) ++v;
   return v;
 }
 
-__device__ __forceinline__ int cost_class(uint2 r) {
-  const uint32_t c = r.y - r.x;
-  return c == 0 ? 0 : 32 - __clz(c);
-}
-
-__global__ __launch_bounds__(256) void k_work_hist(WorkArgs w) {
-  __shared__ uint32_t h[33];
-  if (threadIdx.x < 33) h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t item = blockIdx.x * 256 + threadIdx.x;
-  if (item < w.base[w.V]) {
-    const int v = work_view(w, item);
-    atomicAdd(&h[cost_class(w.ranges[v][item - w.base[v]])], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x < 33 && h[threadIdx.x]) atomicAdd(&w.hist[threadIdx.x], h[threadIdx.x]);
-}
-
-__global__ __launch_bounds__(256) void k_work_scatter(WorkArgs w) {
-  __shared__ uint32_t h[33], start[33], mine[33];
-  if (threadIdx.x < 33) h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t item = blockIdx.x * 256 + threadIdx.x;
-  int cls = -1, v = 0;
-  uint32_t rank = 0;
-  if (item < w.base[w.V]) {
-    v = work_view(w, item);
-    cls = cost_class(w.ranges[v][item - w.base[v]]);
-    rank = atomicAdd(&h[cls], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x < 33) {
-    // classes are laid out from the most expensive down
-    uint32_t s0 = 0;
-    for (int c = 32; c > (int)threadIdx.x; --c) s0 += w.hist[c];
-    start[threadIdx.x] = s0;
-    mine[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&w.cursor[threadIdx.x], h[threadIdx.x]) : 0u;
-  }
-  __syncthreads();
-  if (cls >= 0)
-    w.items[start[cls] + mine[cls] + rank] = ((uint32_t)v << 24) | (item - w.base[v]);
-}
-
-static_assert(sizeof(WorkArgs) <= 1024, "work-list arguments");
-
 struct RenderMultiArgs {
   int V;
-  uint32_t n_items;
-  const uint32_t* __restrict__ items;
-  uint32_t* counter;
+  uint32_t base[kMaxViews + 1];  // first item of each view; base[V] = all items
   RenderArgs view[kMaxViews];
 };
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_render_multi(RenderMultiArgs m) {
   __shared__ float4 s_rec[TW * TH / 64][3][64];
-  __shared__ uint32_t s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(m.counter, 1u);
-    __syncthreads();
-    const uint32_t it = s_item;
-    __syncthreads();
-    if (it >= m.n_items) break;
-    const uint32_t code = m.items[it];
-    render_tile<TW, TH>(m.view[code >> 24], (int)(code & 0xFFFFFF), s_rec);
-  }
+  const uint32_t b = blockIdx.x;
+  if (b >= m.base[m.V]) return;
+  const int v = item_view(m.base, m.V, b);
+  render_tile<TW, TH>(m.view[v], (int)(b - m.base[v]), s_rec);
 }
 
 struct RenderBwdMultiArgs {
   int V;
-  uint32_t n_items;
-  const uint32_t* __restrict__ items;
-  uint32_t* counter;
+  uint32_t base[kMaxViews + 1];
   RenderBwdArgs view[kMaxViews];
 };
 
@@ -608,15 +539,11 @@ static_assert(sizeof(RenderMultiArgs) <= 4096, "kernel argument block too large"
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_render_bwd_multi(RenderBwdMultiArgs m) {
   __shared__ float4 s_rec[3][64];
-  for (;;) {
-    uint32_t it = 0;
-    if (threadIdx.x == 0) it = atomicAdd(m.counter, 1u);
-    it = __shfl(it, 0, 64);
-    if (it >= m.n_items) break;
-    const uint32_t code = m.items[it];
-    // batched views carry no depth gradient
-    render_tile_bwd<TW, TH, false>(m.view[code >> 24], (int)(code & 0xFFFFFF), s_rec);
-  }
+  const uint32_t b = blockIdx.x;
+  if (b >= m.base[m.V]) return;
+  const int v = item_view(m.base, m.V, b);
+  // batched views carry no depth gradient
+  render_tile_bwd<TW, TH, false>(m.view[v], (int)(b - m.base[v]), s_rec);
 }
 
 static_assert(sizeof(RenderBwdMultiArgs) <= 4096, "kernel argument block too large");
@@ -628,14 +555,12 @@ bool tile_shape_supported(int tw, int th) {
 
 template <int TW, int TH>
 static void launch_fwd_t(const RenderArgs& a, hipStream_t st) {
-  const int ntile = a.tiles_x * a.tiles_y;
-  const int grid = ((ntile + 7) >> 3) * 8;
+  const int grid = a.tiles_x * a.tiles_y;
   hipLaunchKernelGGL((k_render<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, a);
 }
 template <int TW, int TH>
 static void launch_bwd_t(const RenderBwdArgs& a, hipStream_t st) {
-  const int ntile = a.tiles_x * a.tiles_y;
-  const int grid = ((ntile + 7) >> 3) * 8;
+  const int grid = a.tiles_x * a.tiles_y;
   if (a.ddepth)
     hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3(grid), dim3(64), 0, st, a);
   else
@@ -790,54 +715,41 @@ hipError_t launch_render_backward(const sx_projected& proj,
 // ------------------------------------------------------------ multi-view --
 // work-list workspace: a 512-byte head (hist[33], cursor[33], two work
 // counters) followed by one u32 item per (view, tile)
-constexpr int kWorkHeadWords = 128;
+// The batched launches need no scratch memory; the workspace argument of
+// the batched entry points is kept (one small block) so callers size it
+// once and the layout can change without an interface change.
 size_t multi_workspace_bytes(int64_t items) {
-  return kWorkHeadWords * 4 + (size_t)(items > 0 ? items : 1) * 4;
-}
-
-static hipError_t build_worklist(int V, const MultiView* mv, const KParams& p, char* ws,
-                                 WorkArgs& w, hipStream_t st) {
-  uint32_t* head = reinterpret_cast<uint32_t*>(ws);
-  w.V = V;
-  uint32_t base = 0;
-  for (int v = 0; v < V; ++v) {
-    w.base[v] = base;
-    w.ranges[v] = reinterpret_cast<const uint2*>(mv[v].ranges);
-    base += (uint32_t)(mv[v].tiles_x * mv[v].tiles_y);
-  }
-  w.base[V] = base;
-  w.hist = head;
-  w.cursor = head + 33;
-  w.items = reinterpret_cast<uint32_t*>(ws + kWorkHeadWords * 4);
-  hipError_t e = launch_fill(head, kWorkHeadWords, 0, st);  // hist, cursor, work counters
-  if (e) return e;
-  const unsigned nb = (base + 255) / 256;
-  hipLaunchKernelGGL(k_work_hist, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, w);
-  hipLaunchKernelGGL(k_work_scatter, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, w);
-  return hipGetLastError();
+  (void)items;
+  return 256;
 }
 
 template <int TW, int TH>
 static void launch_fwd_multi_t(const RenderMultiArgs& m, hipStream_t st) {
-  const unsigned grid = m.n_items < 2048u ? m.n_items : 2048u;
+  const unsigned grid = m.base[m.V];
   hipLaunchKernelGGL((k_render_multi<TW, TH>), dim3(grid > 0 ? grid : 1), dim3(TW * TH), 0, st, m);
 }
 template <int TW, int TH>
 static void launch_bwd_multi_t(const RenderBwdMultiArgs& m, hipStream_t st) {
-  const unsigned grid = m.n_items < 5120u ? m.n_items : 5120u;
+  const unsigned grid = m.base[m.V];
   hipLaunchKernelGGL((k_render_bwd_multi<TW, TH>), dim3(grid > 0 ? grid : 1), dim3(64), 0, st, m);
+}
+
+template <typename Args>
+static void set_bases(int V, const MultiView* mv, Args& m) {
+  m.V = V;
+  uint32_t base = 0;
+  for (int v = 0; v < V; ++v) {
+    m.base[v] = base;
+    base += (uint32_t)(mv[v].tiles_x * mv[v].tiles_y);
+  }
+  m.base[V] = base;
 }
 
 hipError_t launch_render_multi(int V, const MultiView* mv, const KParams& p, char* ws,
                                hipStream_t st) {
-  WorkArgs w;
-  hipError_t e = build_worklist(V, mv, p, ws, w, st);
-  if (e) return e;
+  (void)ws;
   RenderMultiArgs m;
-  m.V = V;
-  m.n_items = w.base[V];
-  m.items = w.items;
-  m.counter = w.hist + 66;
+  set_bases(V, mv, m);
   for (int v = 0; v < V; ++v) {
     KParams pv = p;
     pv.tiles_x = mv[v].tiles_x, pv.tiles_y = mv[v].tiles_y;
@@ -851,8 +763,9 @@ hipError_t launch_render_multi(int V, const MultiView* mv, const KParams& p, cha
 
 hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, const KParams& p,
                                         char* ws, hipStream_t st) {
+  (void)ws, (void)n;
   RenderBwdMultiArgs m;
-  m.V = V;
+  set_bases(V, mv, m);
   for (int v = 0; v < V; ++v) {
     KParams pv = p;
     pv.tiles_x = mv[v].tiles_x, pv.tiles_y = mv[v].tiles_y;
@@ -863,12 +776,6 @@ hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, c
                                       static_cast<char*>(mv[v].bwd_ws), st);
     if (e) return e;
   }
-  WorkArgs w;
-  hipError_t e = build_worklist(V, mv, p, ws, w, st);
-  if (e) return e;
-  m.n_items = w.base[V];
-  m.items = w.items;
-  m.counter = w.hist + 67;
   SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_multi_t, m, st);
   return hipGetLastError();
 }
