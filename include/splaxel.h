@@ -400,14 +400,14 @@ sx_status sx_render_backward_multi(int32_t V, const sx_view* views, int64_t n,
                                    size_t ws_bytes, sx_stream stream);
 
 /* Parameter gradients (chain of the projection, Eq. 1, and of the SH
- * colour) summed over V views of the Gaussians g in one launch; each view
- * needs cam, proj.n_tiles (its sx_preprocess output) and g2d (its
- * sx_render_backward output).  Per Gaussian the views' contributions are
- * added in view order, so the result equals sx_preprocess_backward called
- * per view with SX_BWD_ACCUMULATE on the same grads, bit for bit.  flags:
- * SX_BWD_ACCUMULATE adds to grads (rows of Gaussians no view sees are left
- * untouched); without it grads are overwritten with the sum (zero rows for
- * Gaussians no view sees), so no clearing pass is needed.
+ * colour) summed over V views of the Gaussians g; each view needs cam,
+ * proj.n_tiles (its sx_preprocess output), sort_ws/capacity (its sx_sort)
+ * and g2d (its sx_render_backward output).  Per Gaussian the views'
+ * contributions are added in view order: the result equals
+ * sx_preprocess_backward called per view with SX_BWD_ACCUMULATE on the same
+ * grads, bit for bit.  flags: SX_BWD_ACCUMULATE adds to grads (rows of
+ * Gaussians no view sees are left untouched); without it grads are
+ * overwritten with the sum (zero rows for Gaussians no view sees).
  * views: host array [V], V in 1..SX_MAX_VIEWS. */
 sx_status sx_preprocess_backward_multi(const sx_gaussians* g, int32_t V,
                                        const sx_view* views, const sx_params* p,

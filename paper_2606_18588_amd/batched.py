@@ -6,10 +6,11 @@ compared with its target image (L1), back-propagated, and the views'
 parameter gradients are summed before one Adam update.
 
 Batched form: the views are cut into groups of `batch`; each group runs one
-preprocess launch for all its views, a sort per view, one persistent render
-launch and one persistent render-backward launch over the group's (view,
-tile) work items.  Plain form: the per-view calls one view after another.
-Both forms give bit-identical images and gradients.
+preprocess launch for all its views, a sort per view, one render launch and
+one render-backward launch over the group's (view, tile) work items, and
+the views' parameter gradients summed in view order.  Plain form: the
+per-view calls one view after another.  Both forms give bit-identical
+images; gradients agree to 1e-5 (see the render backward's reduction).
 
 Per-instance buffers (instance values, sort workspace, backward rows) are
 the bulk of the memory; groups run one after another on one stream, so all

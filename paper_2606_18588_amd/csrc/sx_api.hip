@@ -431,17 +431,22 @@ sx_status sx_preprocess_backward_multi(const sx_gaussians* g, int32_t V, const s
   if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
     return fail(SX_EINVAL, "null gradient array");
   sx::DCam cams[sx::kMaxViews];
-  const uint32_t* n_tiles[sx::kMaxViews];
+  sx_projected projs[sx::kMaxViews];
+  sx::SortView svs[sx::kMaxViews];
   const float* g2d[sx::kMaxViews];
   for (int v = 0; v < V; ++v) {
-    SX_TRY(check_cam(&views[v].cam));
-    if (g->n > 0 && (!views[v].proj.n_tiles || !views[v].g2d))
-      return fail(SX_EINVAL, "view %d: null n_tiles/g2d", v);
-    cams[v] = sx::make_dcam(views[v].cam);
-    n_tiles[v] = views[v].proj.n_tiles;
-    g2d[v] = views[v].g2d;
+    const sx_view& w = views[v];
+    SX_TRY(check_cam(&w.cam));
+    if (g->n > 0 && (!w.proj.n_tiles || !w.g2d || !w.sort_ws))
+      return fail(SX_EINVAL, "view %d: null n_tiles/g2d/sort_ws", v);
+    if (w.capacity < 0 || w.capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "view %d: bad capacity", v);
+    const sx::KParams kv = sx::make_kparams(*p, w.cam);
+    cams[v] = sx::make_dcam(w.cam);
+    projs[v] = w.proj;
+    svs[v] = sx::sort_view(w.sort_ws, g->n, w.capacity, kv.tiles_x, kv.tiles_y);
+    g2d[v] = w.g2d;
   }
-  return dev(sx::launch_preprocess_backward_multi(*g, V, cams, n_tiles, g2d,
+  return dev(sx::launch_preprocess_backward_multi(*g, V, cams, projs, svs, g2d,
                                                   sx::make_kparams(*p, views[0].cam), *grads,
                                                   (flags & SX_BWD_ACCUMULATE) != 0,
                                                   (hipStream_t)stream),

@@ -256,7 +256,7 @@ struct SortView;
 hipError_t launch_preprocess_multi(const sx_gaussians& g, int V, const sx_camera* cams,
                                    const KParams& p, const sx_projected* outs, hipStream_t st);
 hipError_t launch_preprocess_backward_multi(const sx_gaussians& g, int V, const DCam* cams,
-                                            const uint32_t* const* n_tiles,
+                                            const sx_projected* projs, const SortView* svs,
                                             const float* const* g2d, const KParams& p,
                                             const sx_grads& gr, bool accumulate, hipStream_t st);
 hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,

@@ -621,109 +621,31 @@ hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
   return hipGetLastError();
 }
 
-// Several views of one set of Gaussians in one launch: each workgroup takes
-// a block of Gaussians and, view after view, packs the ones the view sees to
-// the front of the block and runs the chain for them.  The parameter rows
-// come from HBM once and the gradient rows stay in the caches between the
-// views.  Each Gaussian receives its views' contributions in view order, as
-// it would from one accumulating call per view, so the sums are the same to
-// the last bit.
-struct PreBwdView {
-  DCam cam;
-  const uint32_t* n_tiles;
-  const float* g2d;
-};
-struct PreBwdMultiArgs {
-  int64_t n;
-  int V;
-  int accumulate;
-  const float* __restrict__ means;
-  const float* __restrict__ log_scales;
-  const float* __restrict__ quats;
-  const float* __restrict__ logits;
-  const float* __restrict__ sh;
-  KParams p;
-  float* gmeans;
-  float* glog_scales;
-  float* gquats;
-  float* glogits;
-  float* gsh;
-  PreBwdView v[kMaxViews];
-};
-static_assert(sizeof(PreBwdMultiArgs) <= 3584, "kernel arguments exceed the launch limit");
-
-template <int D>
-__global__ __launch_bounds__(kPreBlock) void k_preprocess_backward_multi(PreBwdMultiArgs m) {
-  __shared__ uint32_t s_cand[kPreBlock];
-  __shared__ uint32_t s_w[kPreBlock / 64];
-  const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  bool seen = m.accumulate != 0;  // this lane's Gaussian already holds a sum
-  PreBwdArgs a;
-  a.n = m.n;
-  a.means = m.means, a.log_scales = m.log_scales, a.quats = m.quats;
-  a.logits = m.logits, a.sh = m.sh;
-  a.p = m.p;
-  a.gmeans = m.gmeans, a.glog_scales = m.glog_scales, a.gquats = m.gquats;
-  a.glogits = m.glogits, a.gsh = m.gsh;
-  for (int v = 0; v < m.V; ++v) {
-    const bool vis = i < m.n && m.v[v].n_tiles[i] > 0;
-    const uint64_t bal = __ballot(vis);
-    if (lane == 0) s_w[w] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t pre = 0, cnt = 0;
-    for (int k = 0; k < kPreBlock / 64; ++k) {
-      if (k < w) pre += s_w[k];
-      cnt += s_w[k];
-    }
-    // slot -> (thread, whether the Gaussian already holds a sum)
-    if (vis) s_cand[pre + __popcll(bal & ((1ull << lane) - 1))] = threadIdx.x | (seen ? 0x80000000u : 0u);
-    seen = seen || vis;
-    __syncthreads();
-    if (threadIdx.x < cnt) {
-      const uint32_t c = s_cand[threadIdx.x];
-      a.cam = m.v[v].cam;
-      a.g2d = m.v[v].g2d;
-      backward_one<D>(a, (int64_t)blockIdx.x * kPreBlock + (c & 0x7FFFFFFFu), (c >> 31) != 0);
-    }
-    __syncthreads();  // the next view's sums read these rows; s_cand is reused
-  }
-  if (!seen && i < m.n) {  // overwrite mode, no view sees this Gaussian
-    constexpr int nf = (D + 1) * (D + 1) * 3;
-    for (int k = 0; k < 3; ++k) m.gmeans[i * 3 + k] = 0.f, m.glog_scales[i * 3 + k] = 0.f;
-    for (int k = 0; k < 4; ++k) m.gquats[i * 4 + k] = 0.f;
-    m.glogits[i] = 0.f;
-    for (int k = 0; k < nf; ++k) m.gsh[i * nf + k] = 0.f;
-  }
-}
-
+// Several views of one set of Gaussians: the per-view kernel once per view,
+// in view order, accumulating, so each Gaussian receives its views'
+// contributions in that order (the same sums as one accumulating call per
+// view).  Without accumulation the gradients are cleared first.  (One
+// launch that looped over the views inside each workgroup, to read the
+// parameters once, measured slower: per view only the lanes of Gaussians
+// that view sees were busy between workgroup barriers.)
 hipError_t launch_preprocess_backward_multi(const sx_gaussians& g, int V, const DCam* cams,
-                                            const uint32_t* const* n_tiles,
+                                            const sx_projected* projs, const SortView* svs,
                                             const float* const* g2d, const KParams& p,
                                             const sx_grads& gr, bool accumulate, hipStream_t st) {
   if (g.n == 0 || V == 0) return hipSuccess;
-  PreBwdMultiArgs m;
-  m.n = g.n;
-  m.V = V;
-  m.accumulate = accumulate ? 1 : 0;
-  m.means = g.means, m.log_scales = g.log_scales, m.quats = g.quats;
-  m.logits = g.opacity_logits, m.sh = g.sh;
-  m.p = p;
-  m.gmeans = gr.means, m.glog_scales = gr.log_scales, m.gquats = gr.quats;
-  m.glogits = gr.opacity_logits, m.gsh = gr.sh;
-  for (int v = 0; v < V; ++v) {
-    m.v[v].cam = cams[v];
-    m.v[v].n_tiles = n_tiles[v];
-    m.v[v].g2d = g2d[v];
+  hipError_t e = hipSuccess;
+  if (!accumulate) {
+    const int nf = (p.sh_degree + 1) * (p.sh_degree + 1) * 3;
+    if ((e = launch_fill(reinterpret_cast<uint32_t*>(gr.means), g.n * 3, 0, st))) return e;
+    if ((e = launch_fill(reinterpret_cast<uint32_t*>(gr.log_scales), g.n * 3, 0, st))) return e;
+    if ((e = launch_fill(reinterpret_cast<uint32_t*>(gr.quats), g.n * 4, 0, st))) return e;
+    if ((e = launch_fill(reinterpret_cast<uint32_t*>(gr.opacity_logits), g.n, 0, st))) return e;
+    if ((e = launch_fill(reinterpret_cast<uint32_t*>(gr.sh), g.n * nf, 0, st))) return e;
   }
-  const dim3 grid((unsigned)((g.n + kPreBlock - 1) / kPreBlock));
-  switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_preprocess_backward_multi<0>, grid, dim3(kPreBlock), 0, st, m); break;
-    case 1: hipLaunchKernelGGL(k_preprocess_backward_multi<1>, grid, dim3(kPreBlock), 0, st, m); break;
-    case 2: hipLaunchKernelGGL(k_preprocess_backward_multi<2>, grid, dim3(kPreBlock), 0, st, m); break;
-    default: hipLaunchKernelGGL(k_preprocess_backward_multi<3>, grid, dim3(kPreBlock), 0, st, m); break;
-  }
-  return hipGetLastError();
+  for (int v = 0; v < V; ++v)
+    if ((e = launch_preprocess_backward(g, cams[v], p, projs[v], svs[v], g2d[v], gr, true, st)))
+      return e;
+  return hipSuccess;
 }
 
 }  // namespace sx

@@ -110,7 +110,7 @@ class CellView:
         self.block_sums = torch.empty((B.sx_preprocess_blocks(n) * 2,), dtype=torch.int32,
                                       device=device)
         self.c_proj = B.projected(self.rec, self.rect, self.n_tiles, self.block_sums)
-        # per tile [start, end), plus the screen list's range at index tiles
+        # per tile [start, end), plus the one spare range the sort may write
         self.ranges = torch.empty((self.tiles + 1, 2), dtype=torch.int32, device=device)
         self.keep_keys = keep_keys
         self.counts = None
@@ -286,9 +286,9 @@ class Frame:
 
 class BatchedViews:
     """V views of one cell stepped together: one preprocess launch for all
-    views, a sort per view, one persistent render launch and one persistent
-    render-backward launch over a shared (view, tile) queue, and the views'
-    parameter gradients summed by the preprocess backward."""
+    views, a sort per view, one render launch and one render-backward launch
+    over all (view, tile) items, and the views' parameter gradients summed
+    by the preprocess backward."""
 
     def __init__(self, params: GaussianParams, cams: Sequence, settings, capacities=None,
                  flags=0, device="cuda"):
@@ -371,7 +371,7 @@ class BatchedViews:
                                    self.ws)
 
     def preprocess_backward(self, grads: GaussianParams, accumulate=False):
-        """Sum of the views' parameter gradients, in one launch: written
+        """Sum of the views' parameter gradients in view order: written
         into grads (zero where no view sees a Gaussian), or added to them
         with accumulate."""
         self._gs = grads.grad_struct()

@@ -8,7 +8,7 @@ the GPU at once; a batch takes up to `max_batch` queued requests in arrival
 order while their estimated sort buffers (instance values + sort workspace)
 fit into the batch's arena of `arena_bytes`.  A batch runs one preprocess
 launch for all its views, one asynchronous sort per view into its arena
-slice, one persistent render launch over all (view, tile) work items and a
+slice, one render launch over all (view, tile) work items and a
 composition per view (K = 1: background under the residual transmittance).
 Completion is seen on the host by polling the batch's event.  The instance
 estimate is learned from completed requests; a request whose instances
