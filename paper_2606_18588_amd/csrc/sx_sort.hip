@@ -310,7 +310,63 @@ struct SweepArgs {
   uint32_t* status;
   uint32_t* part_counter;
   uint64_t* err;
+  // reduce-then-scan form: status holds, digit-major with row length
+  // pstride, each partition's first output position per digit (no look-back)
+  int offsets;
+  uint32_t pstride;
 };
+
+// Reduce-then-scan form of a pass, used when there are many partitions (a
+// look-back chain grows with the partition count): every partition's digit
+// counts, then per digit a scan over the partitions, then the scatter of
+// k_onesweep with those positions.
+__device__ __forceinline__ uint32_t sweep_n(const SweepArgs& a) {
+  uint64_t n64 = *a.count;
+  if (n64 > a.cap) n64 = a.cap;
+  if (a.skip && *a.skip != 0) n64 = 0;
+  return (uint32_t)n64;
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_part_hist(SweepArgs a) {
+  __shared__ uint32_t h[kRadixBins];
+  const uint32_t n = sweep_n(a);
+  const uint32_t parts = (n + kSortTile - 1) / kSortTile;
+  const uint32_t dmask = (1u << a.bits) - 1u;
+  for (uint32_t part = blockIdx.x; part < parts; part += gridDim.x) {
+    __syncthreads();
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)part * kSortTile;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kSortTile; i += kSortBlock)
+      if (base + i < n) atomicAdd(&h[(a.keys_in[base + i] >> a.shift) & dmask], 1u);
+    __syncthreads();
+    a.status[(size_t)threadIdx.x * a.pstride + part] = h[threadIdx.x];
+  }
+}
+
+// One block per digit: the digit's global start (the counts of smaller
+// digits) plus an exclusive scan of its per-partition counts.
+__global__ __launch_bounds__(kSortBlock) void k_part_scan(SweepArgs a) {
+  __shared__ uint32_t s4[4];
+  __shared__ uint32_t s_tot;
+  const uint32_t n = sweep_n(a);
+  const uint32_t parts = (n + kSortTile - 1) / kSortTile;
+  const uint32_t d = blockIdx.x;
+  uint32_t gtot;
+  const uint32_t gex = block_excl_scan256(a.hist[threadIdx.x], s4, &gtot);
+  if (threadIdx.x == d) s_tot = gex;
+  __syncthreads();
+  uint32_t run = s_tot;
+  uint32_t* row = a.status + (size_t)d * a.pstride;
+  for (uint32_t p0 = 0; p0 < parts; p0 += kSortBlock) {
+    const uint32_t p = p0 + threadIdx.x;
+    const uint32_t c = p < parts ? row[p] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan256(c, s4, &tot);
+    if (p < parts) row[p] = run + ex;
+    run += tot;
+  }
+}
 
 // One stable LSD pass over `bits` digits at `shift` of the keys.  Blocks
 // take partitions from an atomic counter until none is left, so a partition
@@ -326,10 +382,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
   __shared__ uint32_t s_scan[4];
   __shared__ uint32_t s_part;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint64_t n64 = *a.count;
-  if (n64 > a.cap) n64 = a.cap;
-  if (a.skip && *a.skip != 0) n64 = 0;
-  const uint32_t n = (uint32_t)n64;
+  const uint32_t n = sweep_n(a);
   for (;;) {
   __syncthreads();  // the previous partition is fully written out
   if (tid == 0) s_part = atomicAdd(a.part_counter, 1u);
@@ -374,21 +427,24 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
   const uint32_t d = tid;
   const uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
   const uint32_t tot = c0 + c1 + c2 + c3;
-  if (part == 0)
-    st_rel(&a.status[d], kFlagIncl | tot);
-  else
-    st_rel(&a.status[(size_t)part * kRadixBins + d], kFlagAgg | tot);
+  if (!a.offsets) {
+    if (part == 0)
+      st_rel(&a.status[d], kFlagIncl | tot);
+    else
+      st_rel(&a.status[(size_t)part * kRadixBins + d], kFlagAgg | tot);
+  }
   __syncthreads();
   s_wh[0][d] = 0, s_wh[1][d] = c0, s_wh[2][d] = c0 + c1, s_wh[3][d] = c0 + c1 + c2;
   const uint32_t loc = block_excl_scan256(tot, s_scan, nullptr);
-  const uint32_t gex = block_excl_scan256(a.hist[d], s_scan, nullptr);
+  const uint32_t gex =
+      a.offsets ? a.status[(size_t)d * a.pstride + part] : block_excl_scan256(a.hist[d], s_scan, nullptr);
   s_loc[d] = loc;
   // decoupled look-back over earlier partitions for this digit, reading a
   // window of kLookback predecessors per round trip: their sum is taken down
   // to the nearest inclusive prefix; a predecessor not yet published ends
   // the window and is waited for (bounded spin)
   uint32_t excl = 0;
-  if (part > 0) {
+  if (!a.offsets && part > 0) {
     int64_t j = (int64_t)part - 1;
     int spins = 0;
     while (j >= 0) {
@@ -639,6 +695,21 @@ hipError_t launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// One pass over at most `parts` partitions: with few partitions the
+// look-back form, otherwise reduce-then-scan (status must then hold
+// parts * kRadixBins words, which the look-back form needs as well).
+constexpr uint32_t kLookbackParts = 512;
+static void launch_pass(SweepArgs a, uint32_t parts, hipStream_t st) {
+  const unsigned grid = parts < 1024u ? parts : 1024u;
+  if (parts > kLookbackParts) {
+    a.offsets = 1;
+    a.pstride = parts;
+    hipLaunchKernelGGL(k_part_hist, dim3(parts < 2048u ? parts : 2048u), dim3(kSortBlock), 0, st, a);
+    hipLaunchKernelGGL(k_part_scan, dim3(kRadixBins), dim3(kSortBlock), 0, st, a);
+  }
+  hipLaunchKernelGGL(k_onesweep, dim3(grid > 0 ? grid : 1), dim3(kSortBlock), 0, st, a);
+}
+
 int launch_pair_sort(uint32_t* const keys[2], uint32_t* const vals[2], const uint64_t* count,
                      uint64_t cap, int bits, uint32_t* hist, uint32_t* status, int64_t parts,
                      uint32_t* counters, uint64_t* err, hipStream_t st, hipError_t* e) {
@@ -661,7 +732,7 @@ int launch_pair_sort(uint32_t* const keys[2], uint32_t* const vals[2], const uin
     a.status = status + (size_t)ps * parts * kRadixBins;
     a.part_counter = counters + ps;
     a.err = err;
-    hipLaunchKernelGGL(k_onesweep, dim3(grid), dim3(kSortBlock), 0, st, a);
+    launch_pass(a, (uint32_t)parts, st);
   }
   *e = hipGetLastError();
   return npass & 1;
@@ -725,7 +796,7 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     a.status = u32(L.dstatus) + (size_t)ps * L.dparts * kRadixBins;
     a.part_counter = counters + ps;
     a.err = err;
-    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st, a);
+    launch_pass(a, (uint32_t)L.dparts, st);
   }
   // phase 2: split the depth-ordered list by tile, level by level
   uint2* bins[2] = {reinterpret_cast<uint2*>(ws + L.bl_bins[0]),
