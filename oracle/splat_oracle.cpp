@@ -659,12 +659,21 @@ int or_composite(int K, const double* Cparts, const double* Tparts,
                      [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
                        return a.first < b.first;
                      });
-    for (int j = 0; j + 1 < K; ++j) {
-      const double a = ks[j].first, b = ks[j + 1].first;
-      if (!(a == 0.0 && b == 0.0) &&
-          std::fabs(b - a) <= 1e-6 * std::max(std::fabs(a), std::fabs(b)))
-        if (flags) flags[p] |= FLAG_ORDER;
-    }
+    // an order within rounding reach of a tie matters only between two
+    // cells that both contribute here: a cell with C = 0 and T = 1 commutes
+    // with any other in Eq. 5
+    auto contributes = [&](int m) {
+      const double* cm = Cparts + ((int64_t)m * HW + p) * 3;
+      return cm[0] != 0.0 || cm[1] != 0.0 || cm[2] != 0.0 || Tparts[(int64_t)m * HW + p] != 1.0;
+    };
+    for (int j = 0; j + 1 < K; ++j)
+      for (int j2 = j + 1; j2 < K; ++j2) {
+        const double a = ks[j].first, b = ks[j2].first;
+        if (!(a == 0.0 && b == 0.0) &&
+            std::fabs(b - a) <= 1e-6 * std::max(std::fabs(a), std::fabs(b)) &&
+            contributes(ks[j].second) && contributes(ks[j2].second))
+          if (flags) flags[p] |= FLAG_ORDER;
+      }
     double Pj = 1.0, c[3] = {0, 0, 0};
     for (int j = 0; j < K; ++j) {
       const int m = ks[j].second;

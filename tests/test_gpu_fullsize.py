@@ -121,3 +121,73 @@ def test_fullsize_render_and_backward(g2):
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         got = getattr(grads, name).cpu().numpy()[vis]
         assert rel_err(got, rb[name][vis]) <= 2e-3, name
+
+
+# ------------------------------------------------------------ K = 8 cells --
+@pytest.fixture(scope="module")
+def g8():
+    need_gpu()
+    import torch
+    from paper_2606_18588_amd.pipeline import Frame, GaussianParams, spatial_order
+    print("case: full-size K=8 cells, 8M Gaussians 1600x1200, building the scene", flush=True)
+    scene = synth.g8_scene()
+    part = synth.grid_partition(scene, synth.GRID_X, synth.GRID_Y)
+    scenes = [c.subset(spatial_order(c.means)) for c in part.cell_scenes(scene)]
+    del scene
+    cam = synth.g8_cameras(1600, 1200)[1]
+    params = [GaussianParams.from_scene(c) for c in scenes]
+    fr = Frame(params, part.cells, cam, ST)
+    fr.init_masks()
+    out = fr.forward(update_masks=True)
+    torch.cuda.synchronize()
+    return dict(torch=torch, scenes=scenes, cells=part.cells, cam=cam, params=params, frame=fr,
+                out=out.cpu().numpy())
+
+
+def test_fullsize_k8_composite_and_backward(g8):
+    """The K = 8 benchmark configuration: every cell rendered, composed by
+    ray entry order with the saturation masks written, and back-propagated;
+    compared with the oracle on sampled tiles (the oracle renders only
+    those, through its per-pixel masks)."""
+    print("case: full-size K=8 composite + backward on sampled tiles", flush=True)
+    torch, scenes, cells, cam, fr = g8["torch"], g8["scenes"], g8["cells"], g8["cam"], g8["frame"]
+    tiles, tx, ty = _sample_tiles(cam, seed=5, count=24)
+    m = _tile_mask(cam, tiles, tx)
+    K = len(scenes)
+    ref = oracle.forward(scenes, cells, cam, ST, masks=np.broadcast_to(m, (K,) + m.shape).copy())
+    on = m == 1
+    fl = ref.comp["flags"].copy()
+    for p in ref.parts:
+        fl |= p["flags"]
+    cmax = max(float(rec_fields(v.rec)["rgb"][v.n_tiles.cpu().numpy() > 0].max()) for v in fr.views)
+    out = g8["out"]
+    e, nf = compare_image(out[on][:, :3], ref.comp["rgb"][on], fl[on], 1e-4,
+                          K * jump_bound(ST, cmax))
+    compare_image(out[on][:, 3], ref.comp["T"][on], fl[on], 1e-4, 1.0)
+    masks = fr.masks.cpu().numpy().view(np.uint32)
+    bits = np.unpackbits(masks.view(np.uint8), bitorder="little").reshape(K, -1)[:, :cam.width * cam.height]
+    ok = (on & (fl == 0)).reshape(-1)
+    assert_same(bits[:, ok], ref.comp["mask"].reshape(K, -1)[:, ok], "saturation masks")
+    print(f"full-size K=8: {len(tiles)} tiles, max-abs {e:.3g}, flagged {nf}, "
+          f"inactive pairs {(ref.comp['mask'].reshape(K, -1)[:, ok] == 0).sum()}", flush=True)
+    # backward with an upstream gradient on the unflagged sampled pixels
+    okp = on & (fl == 0)
+    d = (np.random.default_rng(23).normal(size=(cam.height, cam.width, 4)) * okp[..., None])
+    d32 = d.astype(np.float32)
+    grads = [p.zeros_like() for p in g8["params"]]
+    fr.backward(torch.as_tensor(d32).cuda(), grads)
+    torch.cuda.synchronize()
+    gref = oracle.backward(scenes, cells, cam, ST, ref, d32[..., :3].astype(np.float64),
+                           d32[..., 3].astype(np.float64),
+                           masks=np.broadcast_to(m, (K,) + m.shape).copy())
+    hit = 0
+    for k in range(K):
+        vis = fr.views[k].n_tiles.cpu().numpy() > 0
+        g2d = fr.views[k].g2d.cpu().numpy()[:, :10]
+        hit += int((np.abs(gref[k]["g2d"]).max(1) > 0).sum())
+        for c in range(9):
+            assert rel_err(g2d[vis, c], gref[k]["g2d"][vis, c]) <= 2e-3, (k, c)
+        for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            got = getattr(grads[k], name).cpu().numpy()[vis]
+            assert rel_err(got, gref[k][name][vis]) <= 2e-3, (k, name)
+    assert hit > 100
