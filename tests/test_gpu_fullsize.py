@@ -184,8 +184,11 @@ def test_fullsize_k8_composite_and_backward(g8):
     hit = 0
     for k in range(K):
         vis = fr.views[k].n_tiles.cpu().numpy() > 0
-        g2d = fr.views[k].g2d.cpu().numpy()[:, :10]
         hit += int((np.abs(gref[k]["g2d"]).max(1) > 0).sum())
+        if not vis.any():  # the cell is out of view: nothing to compare
+            assert not np.any(gref[k]["g2d"])
+            continue
+        g2d = fr.views[k].g2d.cpu().numpy()[:, :10]
         for c in range(9):
             assert rel_err(g2d[vis, c], gref[k]["g2d"][vis, c]) <= 2e-3, (k, c)
         for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
