@@ -305,8 +305,9 @@ def bench_cells(args):
     """The K = 8 composition workload: 8M Gaussians split by centre into a
     4 x 2 grid of cells on the ground plane, 8 views from (10, 20, 150) m.
     One training step = for every view, each cell's preprocess, sort and
-    partial render (restricted by the view's saturation masks from its
-    previous step), composition (Eq. 5, updating the masks), L1, the
+    partial render (restricted to the pixels where the cell's box is
+    geometrically visible and, from the view's previous step, not behind a
+    saturated prefix), composition (Eq. 5, updating the masks), L1, the
     composition backward and every cell's backward; then one Adam update of
     every cell.  Views/s at 1920x1080 (the metric's resolution) and at
     1600x1200 (the configuration's)."""
@@ -333,8 +334,8 @@ def bench_cells(args):
         frames = [Frame(params, part.cells, c, st) for c in cams]
         dout = torch.empty((h, w, 4), dtype=torch.float32, device="cuda")
         for f in frames:  # size every cell's instance buffers once, with headroom
-            f.init_masks()
-            f.forward(sync=True)
+            f.init_masks(geometric=True)
+            f.forward(use_masks=True, sync=True)
             for v in f.views:
                 v._alloc_sort(int(v.counts[1] * 1.1) + 4096)
         torch.cuda.synchronize()
@@ -384,7 +385,8 @@ def bench_cells(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "8M Gaussians SH3 on a 1 km^2 ground plane in K=8 cells "
                                "(4x2 grid), 8 aerial views, fwd + L1 + bwd per view with "
-                               "temporal saturation masks, one Adam update per step",
+                               "geometric visibility and temporal saturation masks, one "
+                               "Adam update per step",
                    "gaussians": int(sum(p.n for p in params)), "cells": len(params),
                    "views": 8},
         "resolutions": out,

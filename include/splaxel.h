@@ -199,6 +199,18 @@ sx_status sx_render_partial(const sx_projected* proj, const uint32_t* vals,
                             float* partial, float* depth, uint32_t* last,
                             uint32_t* nblend, sx_stream stream);
 
+/* Geometric visibility of K cell boxes for one view (redundancy reduction
+ * section, spatial part): the part of a box inside the view frustum is
+ * convex, and its projection onto the image is the set of pixels whose
+ * centre ray meets it (between the near plane and infinity).  Writes masks
+ * [K * ceil(H*W/32)] uint32 words, cell-major, bit (m, p) = 1 where cell m
+ * is visible at pixel p, in the layout of sx_composite's saturation masks:
+ * initialising those masks with this map restricts every render and
+ * composition of the view to the cells' visible regions.  cells: HOST array
+ * of K boxes (bounds may be infinite), K in 1..16. */
+sx_status sx_visibility(int32_t K, const sx_cell* cells, const sx_camera* cam,
+                        uint32_t* masks, sx_stream stream);
+
 /* ------------------------------------------------------------------ a6 --
  * Composition of K partial buffers (Eq. 5).  Per pixel the cells are
  * ordered by the ray's entry parameter into their box, max(0, t_near)

@@ -36,6 +36,7 @@ FLAG_TERMINATE = 2
 FLAG_DEPTH_ROUND = 4
 FLAG_ORDER = 8
 FLAG_CLAMP = 16
+FLAG_VISIBILITY = 32
 
 
 def build(force: bool = False) -> str:
@@ -207,9 +208,25 @@ def render(scene, cam, settings, mode: str = "binned",
 
 
 def _cells_lohi(cells):
-    lo = np.ascontiguousarray(np.array([c.lo for c in cells], np.float64))
-    hi = np.ascontiguousarray(np.array([c.hi for c in cells], np.float64))
+    # the FP32 path receives the box bounds as float32; the oracle uses the
+    # same values
+    lo = np.ascontiguousarray(np.array([c.lo for c in cells], np.float32).astype(np.float64))
+    hi = np.ascontiguousarray(np.array([c.hi for c in cells], np.float32).astype(np.float64))
     return lo, hi
+
+
+def visibility(cells, cam) -> dict:
+    """Geometric visibility of each cell box (redundancy reduction section,
+    spatial part): vis [K,H,W] uint8, 1 where the pixel's centre ray meets
+    the part of the box inside the view frustum; flags [H,W] mark decisions
+    within rounding reach of flipping."""
+    K = len(cells)
+    lo, hi = _cells_lohi(cells)
+    H, W = cam.height, cam.width
+    out = dict(vis=np.zeros((K, H, W), np.uint8), flags=np.zeros((H, W), np.uint8))
+    lib().or_visibility(ctypes.c_int(K), _p(lo), _p(hi), ctypes.byref(_cam(cam)),
+                        _p(out["vis"]), _p(out["flags"]))
+    return out
 
 
 def composite(Cparts: np.ndarray, Tparts: np.ndarray, cells, cam, settings,

@@ -426,6 +426,7 @@ enum : uint8_t {
   FLAG_DEPTH_ROUND = 4,  // float32(depth) rounding could go either way
   FLAG_ORDER = 8,        // two cell entry keys within 1e-6 relative
   FLAG_CLAMP = 16,       // alpha within 1e-6 relative of the alpha_max clamp
+  FLAG_VISIBILITY = 32,  // a cell box's geometric visibility within rounding of flipping
 };
 
 struct Blend {  // one blended pair on a pixel's ray
@@ -513,6 +514,40 @@ static double entry_key(const Cam& cam, int px, int py, const double lo[3],
     if (tm > tn) tn = tm;
   }
   return tn > 0.0 ? tn : 0.0;
+}
+
+// Geometric visibility of a cell box (redundancy reduction section,
+// spatial part): the part of the box inside the view frustum is convex, and
+// its projection onto the image is the set of pixels whose centre ray meets
+// it.  With the camera-space depth of the ray point C + s d equal to s, the
+// ray meets (box within the frustum) iff the slab interval [s_in, s_out] of
+// the box, cut below by the near plane (s >= znear), is not empty.  An axis
+// the ray runs parallel to keeps the whole ray if the centre lies in that
+// slab and removes it otherwise.  `margin` returns how far the decision is
+// from flipping: s_out - max(s_in, znear).
+static bool ray_meets_box(const Cam& cam, int px, int py, const double lo[3], const double hi[3],
+                          double* margin) {
+  double O[3];
+  cam_center(cam, O);
+  const double u = (px + 0.5 - cam.cx) / cam.fx, v = (py + 0.5 - cam.cy) / cam.fy;
+  double d[3];
+  for (int j = 0; j < 3; ++j)
+    d[j] = cam.R[0 * 3 + j] * u + cam.R[1 * 3 + j] * v + cam.R[2 * 3 + j] * 1.0;
+  double s_in = cam.znear, s_out = INFINITY;
+  for (int j = 0; j < 3; ++j) {
+    if (d[j] == 0.0) {
+      if (O[j] < lo[j] || O[j] > hi[j]) {
+        *margin = -INFINITY;
+        return false;
+      }
+      continue;
+    }
+    const double t1 = (lo[j] - O[j]) / d[j], t2 = (hi[j] - O[j]) / d[j];
+    s_in = std::max(s_in, std::min(t1, t2));
+    s_out = std::min(s_out, std::max(t1, t2));
+  }
+  *margin = s_out - s_in;
+  return s_in <= s_out;
 }
 
 }  // namespace
@@ -944,6 +979,28 @@ int or_render_backward(int64_t n, const double* means, const double* log_scales,
       double v = 0;
       for (int r = 0; r < 3; ++r) v += cam->R[r * 3 + k] * dt[r];
       gmeans[i * 3 + k] += v + gmu[k];
+    }
+  }
+  return 0;
+}
+
+// Visible-pixel maps of K cell boxes for one camera: vis [K][H*W] bytes
+// (1 = the pixel's centre ray meets the part of the box inside the
+// frustum); flags [H*W] gets FLAG_VISIBILITY where a decision lies within
+// 1e-9 relative of flipping.
+int or_visibility(int K, const double* lo, const double* hi, const Cam* cam, uint8_t* vis,
+                  uint8_t* flags) {
+  const int W = cam->width, H = cam->height;
+  const int64_t HW = (int64_t)W * H;
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < HW; ++p) {
+    const int px = (int)(p % W), py = (int)(p / W);
+    for (int m = 0; m < K; ++m) {
+      double margin;
+      const bool in = ray_meets_box(*cam, px, py, lo + m * 3, hi + m * 3, &margin);
+      vis[(int64_t)m * HW + p] = in ? 1 : 0;
+      if (flags && std::isfinite(margin) && std::fabs(margin) <= 1e-9 * (1.0 + std::fabs(margin)))
+        flags[p] |= FLAG_VISIBILITY;
     }
   }
   return 0;

@@ -88,7 +88,7 @@ EXPORTS = (
     "sx_composite_backward", "sx_render_backward", "sx_preprocess_backward",
     "sx_adam", "sx_fill_u32", "sx_preprocess_multi", "sx_multi_workspace_size",
     "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
-    "sx_render_backward_stages",
+    "sx_render_backward_stages", "sx_visibility",
 )
 
 _lib = None
@@ -334,6 +334,12 @@ def sx_backward(states: Sequence[SxCellState], cells, cam: SxCamera,
     _check("sx_backward", lib().sx_backward(
         c_i32(len(states)), arr, cells_array(cells), ctypes.byref(cam),
         ctypes.byref(p), ptr(dout), c_i32(flags), stream_handle(stream)))
+
+
+def sx_visibility(cells, cam: SxCamera, masks, stream=None) -> None:
+    arr = cells_array(cells)
+    _check("sx_visibility", lib().sx_visibility(c_i32(len(cells)), arr, ctypes.byref(cam),
+                                                ptr(masks), stream_handle(stream)))
 
 
 def sx_adam(param, grad, m, v, step: int, lr: float, beta1: float = 0.9,

@@ -188,6 +188,18 @@ static sx_status check_cells(int32_t K, const void* partials, const sx_cell* cel
   return SX_OK;
 }
 
+sx_status sx_visibility(int32_t K, const sx_cell* cells, const sx_camera* cam, uint32_t* masks,
+                        sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  if (K < 1 || K > sx::kMaxCells) return fail(SX_EINVAL, "K=%d outside 1..%d", K, sx::kMaxCells);
+  if (!cells || !masks) return fail(SX_EINVAL, "null argument");
+  for (int m = 0; m < K; ++m)
+    for (int j = 0; j < 3; ++j)
+      if (!(cells[m].lo[j] <= cells[m].hi[j])) return fail(SX_EINVAL, "cell %d: lo > hi or NaN", m);
+  return dev(sx::launch_visibility(K, cells, sx::make_dcam(*cam), masks, (hipStream_t)stream),
+             "sx_visibility");
+}
+
 sx_status sx_composite(int32_t K, const float* const* partials,
                        const sx_cell* cells, const sx_camera* cam,
                        const sx_params* p, float* out, uint32_t* masks,

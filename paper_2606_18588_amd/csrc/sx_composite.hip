@@ -186,6 +186,75 @@ static CompArgs comp_args(int K, const float* const* partials, const sx_cell* ce
   return a;
 }
 
+// ---------------------------------------------------- geometric visibility
+// Visible-pixel maps of the cell boxes (redundancy reduction, spatial part):
+// the part of a box inside the view frustum is convex and projects onto the
+// pixels whose centre ray meets it.  The ray point C + s d has camera depth
+// s, so the ray meets (box within the frustum) iff the box's slab interval
+// cut below by the near plane is not empty.  FP64 throughout, with the same
+// operations in the same order as the oracle, so the maps agree bit for
+// bit.  One lane per pixel; a wavefront covers two mask words and writes
+// them from one ballot.
+struct VisArgs {
+  int K;
+  double lo[kMaxCells][3], hi[kMaxCells][3];
+  DCam cam;
+  uint32_t* masks;
+  uint32_t words;
+};
+
+__device__ __forceinline__ bool ray_meets_box(const DCam& c, int px, int py, const double lo[3],
+                                              const double hi[3]) {
+  const double u = ((double)px + 0.5 - c.cx) / c.fx, v = ((double)py + 0.5 - c.cy) / c.fy;
+  double d[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) d[j] = c.R[0 * 3 + j] * u + c.R[1 * 3 + j] * v + c.R[2 * 3 + j] * 1.0;
+  double s_in = c.znear, s_out = INFINITY;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (d[j] == 0.0) {
+      if (c.C[j] < lo[j] || c.C[j] > hi[j]) return false;
+      continue;
+    }
+    const double t1 = (lo[j] - c.C[j]) / d[j], t2 = (hi[j] - c.C[j]) / d[j];
+    s_in = fmax(s_in, fmin(t1, t2));
+    s_out = fmin(s_out, fmax(t1, t2));
+  }
+  return s_in <= s_out;
+}
+
+__global__ __launch_bounds__(256) void k_visibility(VisArgs a) {
+  const uint32_t HW = (uint32_t)a.cam.W * a.cam.H;
+  const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+  const bool inside = p < HW;
+  const uint32_t pp = inside ? p : 0u;
+  const int px = (int)(pp % a.cam.W), py = (int)(pp / a.cam.W);
+  const int lane = threadIdx.x & 63;
+  const uint32_t w0 = (p - lane) >> 5;
+  for (int m = 0; m < a.K; ++m) {
+    const bool vis = inside && ray_meets_box(a.cam, px, py, a.lo[m], a.hi[m]);
+    const uint64_t b = __ballot(vis);
+    if (lane == 0 || lane == 32) {
+      const uint32_t w = w0 + (lane >> 5);
+      if (w < a.words) a.masks[(size_t)m * a.words + w] = (uint32_t)(b >> lane);
+    }
+  }
+}
+
+hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint32_t* masks,
+                             hipStream_t st) {
+  VisArgs a;
+  a.K = K;
+  for (int m = 0; m < K; ++m)
+    for (int j = 0; j < 3; ++j) a.lo[m][j] = cells[m].lo[j], a.hi[m][j] = cells[m].hi[j];
+  a.cam = cam;
+  a.masks = masks;
+  const uint64_t HW = (uint64_t)cam.W * cam.H;
+  a.words = (uint32_t)((HW + 31) / 32);
+  hipLaunchKernelGGL(k_visibility, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_composite(int K, const float* const* partials,
                             const sx_cell* cells, const DCam& cam,
                             const KParams& p, float* out, uint32_t* masks,

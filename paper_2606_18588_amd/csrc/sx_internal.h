@@ -307,6 +307,8 @@ hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, c
                                         char* ws, hipStream_t st);
 hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams& p,
                                    hipStream_t st);
+hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint32_t* masks,
+                             hipStream_t st);
 hipError_t launch_composite(int K, const float* const* partials,
                             const sx_cell* cells, const DCam& cam,
                             const KParams& p, float* out, uint32_t* masks,

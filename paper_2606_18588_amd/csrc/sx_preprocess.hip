@@ -46,27 +46,41 @@ struct Proj64 {
   double dir[3], dist;
 };
 
+// One Gaussian's geometric parameters, read with independent loads issued
+// together (one memory round trip instead of one per culling test).
+struct GIn {
+  float m[3], ls[3], q[4], logit;
+};
+__device__ __forceinline__ GIn load_gin(const float* __restrict__ means,
+                                        const float* __restrict__ log_scales,
+                                        const float* __restrict__ quats,
+                                        const float* __restrict__ logits, int64_t i) {
+  GIn r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.m[k] = means[i * 3 + k], r.ls[k] = log_scales[i * 3 + k];
+  const float4 q = reinterpret_cast<const float4*>(quats)[i];
+  r.q[0] = q.x, r.q[1] = q.y, r.q[2] = q.z, r.q[3] = q.w;
+  r.logit = logits[i];
+  return r;
+}
+
 // Camera transform, culling and the EWA covariance.  Returns false when the
 // Gaussian is culled (mean behind znear, zero quaternion, singular 2D
 // covariance).
-__device__ __forceinline__ bool project_geometry(const float* __restrict__ means,
-                                                 const float* __restrict__ log_scales,
-                                                 const float* __restrict__ quats,
-                                                 int64_t i, const DCam& cam,
-                                                 double eps2d, Proj64& g) {
-  const double mx = means[i * 3 + 0], my = means[i * 3 + 1], mz = means[i * 3 + 2];
+__device__ __forceinline__ bool project_geometry(const GIn& gi, const DCam& cam, double eps2d,
+                                                 Proj64& g) {
+  const double mx = gi.m[0], my = gi.m[1], mz = gi.m[2];
   for (int r = 0; r < 3; ++r)
     g.t[r] = cam.R[r * 3 + 0] * mx + cam.R[r * 3 + 1] * my + cam.R[r * 3 + 2] * mz + cam.t[r];
   if (!(g.t[2] > cam.znear)) return false;
-  const double qw = quats[i * 4 + 0], qx = quats[i * 4 + 1], qy = quats[i * 4 + 2],
-               qz = quats[i * 4 + 3];
+  const double qw = gi.q[0], qx = gi.q[1], qy = gi.q[2], qz = gi.q[3];
   g.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   if (g.qn < 1e-12) return false;
   g.qh[0] = qw / g.qn, g.qh[1] = qx / g.qn, g.qh[2] = qy / g.qn, g.qh[3] = qz / g.qn;
   quat_rot(g.qh[0], g.qh[1], g.qh[2], g.qh[3], g.Rq);
   double s2[3];
   for (int k = 0; k < 3; ++k) {
-    g.s[k] = exp((double)log_scales[i * 3 + k]);
+    g.s[k] = exp((double)gi.ls[k]);
     s2[k] = g.s[k] * g.s[k];
   }
   double Sig[9];
@@ -129,18 +143,20 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ means
 // runs in FP32 with margins far above its rounding error (it only has to
 // never drop a Gaussian the exact FP64 test in project_one would keep).
 __device__ __forceinline__ bool maybe_visible(const PreArgs& a, int64_t i) {
+  // every value the test reads is loaded before the first branch
   const float mx = a.means[i * 3 + 0], my = a.means[i * 3 + 1], mz = a.means[i * 3 + 2];
+  const float lgt = a.logits[i];
+  const float ls = fmaxf(fmaxf(a.log_scales[i * 3 + 0], a.log_scales[i * 3 + 1]),
+                         a.log_scales[i * 3 + 2]);
   const float* R = a.cull.R;
   const float p6 = R[6] * mx, p7 = R[7] * my, p8 = R[8] * mz;
   const float tz = p6 + p7 + p8 + a.cull.t[2];
   const float zslack = 1e-5f * (fabsf(p6) + fabsf(p7) + fabsf(p8) + fabsf(a.cull.t[2])) + 1e-6f;
   if (tz + zslack <= a.cull.znear) return false;
-  if (a.logits[i] < a.cull.logit_min) return false;
+  if (lgt < a.cull.logit_min) return false;
   const float tzc = fmaxf(tz, a.cull.znear * 0.5f);
   const float tx = R[0] * mx + R[1] * my + R[2] * mz + a.cull.t[0];
   const float ty = R[3] * mx + R[4] * my + R[5] * mz + a.cull.t[1];
-  const float ls = fmaxf(fmaxf(a.log_scales[i * 3 + 0], a.log_scales[i * 3 + 1]),
-                         a.log_scales[i * 3 + 2]);
   const float s2 = __expf(2.f * ls);
   const float iz = 1.f / tzc;
   const float jx = a.cull.fx * iz, jy = a.cull.fy * iz;
@@ -155,8 +171,9 @@ __device__ __forceinline__ bool maybe_visible(const PreArgs& a, int64_t i) {
 
 template <int D>
 __device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
+  const GIn gi = load_gin(a.means, a.log_scales, a.quats, a.logits, i);
   Proj64 g;
-  if (!project_geometry(a.means, a.log_scales, a.quats, i, a.cam, a.p.eps2d, g)) return 0;
+  if (!project_geometry(gi, a.cam, a.p.eps2d, g)) return 0;
   const double z = g.t[2];
   const double mx2 = a.cam.fx * g.t[0] / z, my2 = a.cam.fy * g.t[1] / z;
   // frustum cull by the mean: its offset from the principal point must lie
@@ -166,7 +183,7 @@ __device__ __forceinline__ uint32_t project_one(const PreArgs& a, int64_t i) {
                    my2 < -(gd * a.cam.cy) || my2 > gd * ((double)a.cam.H - a.cam.cy)))
     return 0;
   const double mux = mx2 + a.cam.cx, muy = my2 + a.cam.cy;
-  const double o = 1.0 / (1.0 + exp(-(double)a.logits[i]));
+  const double o = 1.0 / (1.0 + exp(-(double)gi.logit));
   if (o < a.p.alpha_min_d) return 0;
   // exact footprint of alpha >= alpha_min: q <= tau with tau = 2 ln(o/alpha_min)
   const double tau = 2.0 * log(o / a.p.alpha_min_d);
@@ -418,8 +435,9 @@ __device__ __forceinline__ void put(float* p, double v, bool acc) {
 // mean through mean2d, J(t), depth and the SH view direction.
 template <int D>
 __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i, bool acc) {
+  const GIn gi = load_gin(a.means, a.log_scales, a.quats, a.logits, i);
   Proj64 g;
-  if (!project_geometry(a.means, a.log_scales, a.quats, i, a.cam, a.p.eps2d, g)) return;
+  if (!project_geometry(gi, a.cam, a.p.eps2d, g)) return;
   const float* gr = a.g2d + (size_t)i * kG2dFloats;
   const float4 g0 = reinterpret_cast<const float4*>(gr)[0];
   const float4 g1 = reinterpret_cast<const float4*>(gr)[1];
@@ -489,7 +507,7 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i, boo
     for (int k = 0; k < 3; ++k) gmu[k] = (gdir[k] - dd * g.dir[k]) / g.dist;
   }
   // opacity through the sigmoid
-  const double o = 1.0 / (1.0 + exp(-(double)a.logits[i]));
+  const double o = 1.0 / (1.0 + exp(-(double)gi.logit));
   put(&a.glogits[i], gop * o * (1.0 - o), acc);
   // conic -> covariance
   const double A[4] = {g.conic[0], g.conic[1], g.conic[1], g.conic[2]};

@@ -259,10 +259,16 @@ class Frame:
     def K(self):
         return len(self.cells)
 
-    def init_masks(self):
+    def init_masks(self, geometric=False):
+        """Every (cell, pixel) pair active, or with geometric, only the pairs
+        where the cell's box is visible (sx_visibility); the composition
+        then clears the pairs behind saturated prefixes."""
         words = (self.cam.width * self.cam.height + 31) // 32
         self.masks = torch.empty((self.K, words), dtype=torch.int32, device=self.out.device)
-        B.sx_fill_u32(self.masks, 0xFFFFFFFF)
+        if geometric:
+            B.sx_visibility(self.boxes, self.c_cam, self.masks)
+        else:
+            B.sx_fill_u32(self.masks, 0xFFFFFFFF)
         return self.masks
 
     def forward(self, use_masks=False, update_masks=False, sync=True):

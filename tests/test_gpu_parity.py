@@ -339,6 +339,76 @@ def test_composite_k8_grid_matches_oracle(torch_gpu):
     print(f"composite k8: max-abs {e:.3g} flagged {nf} inactive pairs {(refm == 0).sum()}", flush=True)
 
 
+def test_visibility_maps_bit_exact(torch_gpu):
+    """Geometric visibility maps (redundancy reduction, spatial part) equal
+    the oracle's bit for bit: the 4x2 ground grid from an aerial camera at a
+    ragged size, and boxes of the cube scene (one behind the camera, one
+    holding it, one half-infinite) from a rotated camera."""
+    print("case: visibility maps", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    xe, ye = synth.GRID_X, synth.GRID_Y
+    grid = [synth.Cell((xe[i], ye[j], -math.inf), (xe[i + 1], ye[j + 1], math.inf))
+            for j in range(2) for i in range(4)]
+    boxes = [synth.Cell((-0.6, -0.3, -0.4), (0.5, 0.7, 0.2)),
+             synth.Cell((3.0, -5.0, 1.0), (9.0, 5.0, 9.0)),
+             synth.Cell((2.0, -2.0, 0.0), (3.0, -1.0, 2.0)),
+             synth.Cell((0.3, -math.inf, -math.inf), (math.inf, math.inf, 0.25))]
+    cases = [(grid, synth.aerial_camera((10.0, 20.0, 150.0), 0.7, math.radians(45.0), 333, 217)),
+             (boxes, synth.look_at_camera((2.5, -1.7, 1.3), (0.1, 0.2, -0.1), 150, 101,
+                                          hfov_deg=60.0))]
+    for cells, cam in cases:
+        K, H, W = len(cells), cam.height, cam.width
+        words = (H * W + 31) // 32
+        m = torch.zeros((K, words), dtype=torch.int32, device="cuda")
+        B.sx_visibility(cells, B.camera(cam), m)
+        torch.cuda.synchronize()
+        bits = np.unpackbits(m.cpu().numpy().view(np.uint8), bitorder="little").reshape(K, -1)[:, :H * W]
+        ref = oracle.visibility(cells, cam)
+        assert not ref["flags"].any()
+        assert_same(bits, ref["vis"].reshape(K, -1), "visibility bits")
+        print(f"visibility {K} cells {W}x{H}: visible pairs {int(bits.sum())} of {bits.size}",
+              flush=True)
+
+
+def test_composite_with_visibility_matches_oracle(torch_gpu):
+    """A K = 8 frame whose masks start from the geometric visibility maps:
+    each cell renders only where its box is visible, and the composition
+    and its saturation masks match the oracle given the same maps."""
+    print("case: composite k8 with visibility", flush=True)
+    torch = torch_gpu
+    scene = synth.make_cube_scene(3, 8000, log_scale=(-3.6, 0.5))
+    cam = synth.camera_from_rows(
+        np.array([[1, 0, 0], [0, 0.9950, -0.0998], [0, 0.0998, 0.9950]]), (0.13, 0.21, -3.0),
+        96, 80, 70.0)
+    xe, ye = [-1.0, -0.5, 0.0, 0.5, 1.0], [-1.0, 0.0, 1.0]
+    part = synth.grid_partition(scene, xe, ye)
+    boxes = grid_cells_xy(xe, ye)
+    part.cells = boxes
+    scenes = part.cell_scenes(scene)
+    fr, _ = _frame(torch, scenes, boxes, cam)
+    fr.init_masks(geometric=True)
+    out = fr.forward(use_masks=True, update_masks=True).cpu().numpy()
+    torch.cuda.synchronize()
+    vis = oracle.visibility(boxes, cam)
+    assert not vis["flags"].any()
+    assert 0 < vis["vis"].sum() < vis["vis"].size
+    ref = oracle.forward(scenes, boxes, cam, ST, masks=vis["vis"])
+    fl = ref.comp["flags"].copy()
+    for p in ref.parts:
+        fl |= p["flags"]
+    cmax = max(float(oracle.preprocess(s, cam, ST)["rgb"].max()) for s in scenes)
+    e, nf = compare_image(out[..., :3], ref.comp["rgb"], fl, 1e-4, 8 * jump_bound(ST, cmax))
+    compare_image(out[..., 3], ref.comp["T"], fl, 1e-4, 1.0)
+    masks = fr.masks.cpu().numpy().view(np.uint32)
+    bits = np.unpackbits(masks.view(np.uint8), bitorder="little").reshape(8, -1)[:, :cam.width * cam.height]
+    refm = (ref.comp["mask"] & vis["vis"]).reshape(8, -1)
+    okpix = fl.reshape(-1) == 0
+    assert_same(bits[:, okpix], refm[:, okpix], "visibility and saturation masks")
+    print(f"composite k8 + visibility: max-abs {e:.3g} flagged {nf} "
+          f"invisible pairs {(vis['vis'] == 0).sum()}", flush=True)
+
+
 def test_slab_composite_equals_single_pass(torch_gpu):
     """The paper's Eq. 5 = Eq. 2 claim on the GPU: with t_min = 0, the
     composition of depth-separated slab partials equals the single-pass

@@ -122,6 +122,43 @@ def test_frustum_cull_by_mean(orc):
     assert np.array_equal(full["C"], kept["C"]) and np.array_equal(full["T"], kept["T"])
 
 
+def test_geometric_visibility(orc):
+    """Redundancy reduction, spatial part: a cell box is visible at the
+    pixels whose centre ray meets the part of the box inside the frustum.
+    Axis camera at (0,0,-3), f = 61, principal point (32, 32): the box
+    [-0.5,0.5] x [-0.25,0.25] x [0,1] spans ray depths 3..4, so a ray
+    (u, v, 1) meets it iff |u| <= 0.5/3 and |v| <= 0.25/3, i.e. pixel
+    columns 22..41 and rows 27..36.  A box behind the camera or between it
+    and the near plane is invisible; a box holding the camera is visible
+    everywhere; and the projection of a convex set is convex (each row and
+    column of the map is one run)."""
+    cam = synth.camera_from_rows(np.eye(3), (0, 0, -3), 64, 64, 61.0, cx=32.0, cy=32.0)
+    inf = math.inf
+    boxes = [synth.Cell((-0.5, -0.25, 0.0), (0.5, 0.25, 1.0)),   # in front
+             synth.Cell((-1.0, -1.0, -9.0), (1.0, 1.0, -4.0)),   # behind
+             synth.Cell((-1.0, -1.0, -2.95), (1.0, 1.0, -2.9)),  # before the near plane
+             synth.Cell((-1.0, -1.0, -4.0), (1.0, 1.0, -2.0)),   # holds the camera
+             synth.Cell((0.2, -inf, -inf), (inf, inf, inf))]     # half-space x >= 0.2
+    r = orc.visibility(boxes, cam)
+    assert not r["flags"].any()
+    want = np.zeros((64, 64), np.uint8)
+    want[27:37, 22:42] = 1
+    np.testing.assert_array_equal(r["vis"][0], want)
+    assert not r["vis"][1].any() and not r["vis"][2].any()
+    assert r["vis"][3].all()
+    # x >= 0.2: from x = 0 a ray with u > 0 reaches it, u <= 0 never does
+    cols = (np.arange(64) + 0.5 - 32.0) > 0
+    np.testing.assert_array_equal(r["vis"][4], np.broadcast_to(cols, (64, 64)).astype(np.uint8))
+    # convexity on a rotated, off-axis view of a box
+    cam2 = synth.look_at_camera((2.5, -1.7, 1.3), (0.1, 0.2, -0.1), 96, 72, hfov_deg=60.0)
+    v = orc.visibility([synth.Cell((-0.6, -0.3, -0.4), (0.5, 0.7, 0.2))], cam2)["vis"][0]
+    assert 100 < v.sum() < v.size
+    for line in list(v) + list(v.T):
+        idx = np.nonzero(line)[0]
+        if len(idx):
+            assert idx[-1] - idx[0] + 1 == len(idx)
+
+
 def test_rotation_matches_library(orc):
     """Sigma = R S S^T R^T with R from the unit quaternion (w,x,y,z): checked
     against scipy's rotation for a Gaussian on the optical axis, where the
