@@ -215,6 +215,8 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
   constexpr int WR = 64 / TW;  // rows per group of 64 pixels
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int lane = threadIdx.x;
+  const uint32_t wave_last = a.nv[tile];  // max of the pixels' `last` over the tile
+  if (wave_last == 0) return;             // nothing blended here: no rows, no pixel reads
   const uint2 rg = a.ranges[tile];
   uint32_t pxy[PPT];  // pixel x | y << 16
   float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
@@ -245,7 +247,6 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     gtf[k] = gt * Tf;
     R0[k] = R1[k] = R2[k] = RD[k] = 0.f;
   }
-  const uint32_t wave_last = a.nv[tile];  // max of lst over the tile
   const uint32_t row0 = a.vb[tile];
   for (int jend = (int)wave_last; jend > 0; jend -= 64) {
     // stage entries [jend - cnt, jend): lane i gathers entry jend - cnt + i,
