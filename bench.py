@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--requests", type=int, default=800,
                     help="serve: measured requests (after 200 warm-up requests)")
     ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
+    ap.add_argument("--partition", choices=("grid", "kd"), default="grid",
+                    help="cells: the 4 x 2 ground grid of the configuration, or KD-tree cells")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -317,8 +319,15 @@ def bench_cells(args):
     from paper_2606_18588_amd.pipeline import Frame, GaussianParams, spatial_order
     t0 = time.perf_counter()
     scene = synth.g8_scene()
-    part = synth.grid_partition(scene, synth.GRID_X, synth.GRID_Y)
-    cell_scenes = [c.subset(spatial_order(c.means)) for c in part.cell_scenes(scene)]
+    if args.partition == "kd":  # the paper's KD-tree cells instead of the 4 x 2 grid
+        boxes_t, cell_of = B.sx_kd_partition(scene.means, 8)
+        cells = [synth.Cell(lo, hi) for lo, hi in boxes_t]
+        cell_scenes = [scene.subset(np.nonzero(cell_of == k)[0]) for k in range(8)]
+    else:
+        part = synth.grid_partition(scene, synth.GRID_X, synth.GRID_Y)
+        cells = part.cells
+        cell_scenes = part.cell_scenes(scene)
+    cell_scenes = [c.subset(spatial_order(c.means)) for c in cell_scenes]
     del scene
     params = [GaussianParams.from_scene(c) for c in cell_scenes]
     del cell_scenes
@@ -331,7 +340,7 @@ def bench_cells(args):
         cams = synth.g8_cameras(w, h)
         targets = [torch.as_tensor(synth.random_image(500 + k, w, h)).cuda()
                    for k in range(len(cams))]
-        frames = [Frame(params, part.cells, c, st) for c in cams]
+        frames = [Frame(params, cells, c, st) for c in cams]
         dout = torch.empty((h, w, 4), dtype=torch.float32, device="cuda")
         for f in frames:  # size every cell's instance buffers once, with headroom
             f.init_masks(geometric=True)
@@ -384,7 +393,8 @@ def bench_cells(args):
         "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "8M Gaussians SH3 on a 1 km^2 ground plane in K=8 cells "
-                               "(4x2 grid), 8 aerial views, fwd + L1 + bwd per view with "
+                               f"({'KD-tree' if args.partition == 'kd' else '4x2 grid'}), "
+                               "8 aerial views, fwd + L1 + bwd per view with "
                                "geometric visibility and temporal saturation masks, one "
                                "Adam update per step",
                    "gaussians": int(sum(p.n for p in params)), "cells": len(params),

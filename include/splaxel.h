@@ -199,6 +199,18 @@ sx_status sx_render_partial(const sx_projected* proj, const uint32_t* vals,
                             float* partial, float* depth, uint32_t* last,
                             uint32_t* nblend, sx_stream stream);
 
+/* KD-tree partition of n Gaussians into K convex cells by their means (the
+ * paper's partition strategy): recursive binary splits, each along the axis
+ * on which the node's means have the largest extent, at the quantile that
+ * gives the two halves their share of cells (the median for K a power of
+ * two); means < split go left.  Cells are numbered depth first, left
+ * before right; the boxes are disjoint half-open boxes that cover space
+ * (outermost bounds infinite).  HOST arrays: means [n*3], cells [K] (out),
+ * cell_of [n] (out).  K in 1..16.  Runs on the host; allocates host memory
+ * only. */
+sx_status sx_kd_partition(int64_t n, const float* means, int32_t K, sx_cell* cells,
+                          int32_t* cell_of);
+
 /* Geometric visibility of K cell boxes for one view (redundancy reduction
  * section, spatial part): the part of a box inside the view frustum is
  * convex, and its projection onto the image is the set of pixels whose

@@ -20,6 +20,7 @@ Paper anchors (the paper's own numbering of equations):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -213,6 +214,47 @@ def _cells_lohi(cells):
     lo = np.ascontiguousarray(np.array([c.lo for c in cells], np.float32).astype(np.float64))
     hi = np.ascontiguousarray(np.array([c.hi for c in cells], np.float32).astype(np.float64))
     return lo, hi
+
+
+def kd_partition(means, K: int):
+    """Partition strategy of the paper's robustness study: recursive binary
+    splits of the Gaussians by their means, each along the axis on which the
+    node's means have the largest extent (first axis on ties), at the value
+    of rank floor(n * K_left / K) among the node's means on that axis
+    (K_left = floor(K / 2) cells go left: the median for K a power of two);
+    means below it go left.  Cells numbered depth first, left first; an
+    empty node keeps its box in its first cell and gives the others empty
+    boxes.  Returns (boxes [(lo, hi)], cell_of int32 [n])."""
+    m = np.asarray(means, np.float32).reshape(-1, 3)
+    cell_of = np.zeros(len(m), np.int32)
+    boxes = [None] * K
+
+    def node(idx, k, lo, hi, first):
+        if k == 1 or len(idx) == 0:
+            for c in range(k):
+                boxes[first + c] = (tuple(lo), tuple(hi) if c == 0 else tuple(lo))
+            cell_of[idx] = first
+            return
+        pts = m[idx]
+        ext = pts.max(0) - pts.min(0)  # float32, as the means are
+        ax = int(np.argmax(ext))
+        kl = k // 2
+        s = np.sort(pts[:, ax])[len(idx) * kl // k]
+        go_left = pts[:, ax] < s
+        lo_r, hi_l = list(lo), list(hi)
+        hi_l[ax] = float(s)
+        lo_r[ax] = float(s)
+        node(idx[go_left], kl, lo, hi_l, first)
+        node(idx[~go_left], k - kl, lo_r, hi, first + kl)
+
+    node(np.arange(len(m)), K, [-math.inf] * 3, [math.inf] * 3, 0)
+    return boxes, cell_of
+
+
+def imbalance(cell_of, K: int) -> float:
+    """N_max / mean(N) - 1 over the K cells' Gaussian counts."""
+    counts = np.bincount(np.asarray(cell_of), minlength=K)
+    return float(counts.max() / counts.mean() - 1.0)
 
 
 def visibility(cells, cam) -> dict:

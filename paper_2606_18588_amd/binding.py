@@ -88,7 +88,7 @@ EXPORTS = (
     "sx_composite_backward", "sx_render_backward", "sx_preprocess_backward",
     "sx_adam", "sx_fill_u32", "sx_preprocess_multi", "sx_multi_workspace_size",
     "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
-    "sx_render_backward_stages", "sx_visibility",
+    "sx_render_backward_stages", "sx_visibility", "sx_kd_partition",
 )
 
 _lib = None
@@ -334,6 +334,21 @@ def sx_backward(states: Sequence[SxCellState], cells, cam: SxCamera,
     _check("sx_backward", lib().sx_backward(
         c_i32(len(states)), arr, cells_array(cells), ctypes.byref(cam),
         ctypes.byref(p), ptr(dout), c_i32(flags), stream_handle(stream)))
+
+
+def sx_kd_partition(means, K: int):
+    """KD-tree cells of host means [n,3] (float32): returns (boxes as
+    (lo, hi) tuples, cell_of int32 [n])."""
+    import numpy as np
+    m = np.ascontiguousarray(np.asarray(means, np.float32).reshape(-1, 3))
+    n = m.shape[0]
+    cells = (SxCell * K)()
+    cell_of = np.zeros(n, np.int32)
+    _check("sx_kd_partition", lib().sx_kd_partition(
+        c_i64(n), m.ctypes.data_as(ctypes.c_void_p), c_i32(K), cells,
+        cell_of.ctypes.data_as(ctypes.c_void_p)))
+    boxes = [(tuple(c.lo), tuple(c.hi)) for c in cells]
+    return boxes, cell_of
 
 
 def sx_visibility(cells, cam: SxCamera, masks, stream=None) -> None:

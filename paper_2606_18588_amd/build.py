@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsplaxel.so")
 SOURCES = ["sx_api.hip", "sx_preprocess.hip", "sx_sort.hip", "sx_render.hip",
-           "sx_composite.hip"]
+           "sx_composite.hip", "sx_partition.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SX_OFFLOAD_ARCH", "gfx950")
 

@@ -188,6 +188,20 @@ static sx_status check_cells(int32_t K, const void* partials, const sx_cell* cel
   return SX_OK;
 }
 
+sx_status sx_kd_partition(int64_t n, const float* means, int32_t K, sx_cell* cells,
+                          int32_t* cell_of) {
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "n out of range");
+  if (K < 1 || K > sx::kMaxCells) return fail(SX_EINVAL, "K=%d outside 1..%d", K, sx::kMaxCells);
+  if (!cells || (n > 0 && (!means || !cell_of))) return fail(SX_EINVAL, "null argument");
+  for (int64_t i = 0; i < n * 3; ++i)
+    if (!std::isfinite(means[i])) return fail(SX_EINVAL, "mean %lld is not finite", (long long)(i / 3));
+  float lo[sx::kMaxCells * 3], hi[sx::kMaxCells * 3];
+  sx::kd_partition(n, means, K, lo, hi, cell_of);
+  for (int m = 0; m < K; ++m)
+    for (int j = 0; j < 3; ++j) cells[m].lo[j] = lo[m * 3 + j], cells[m].hi[j] = hi[m * 3 + j];
+  return SX_OK;
+}
+
 sx_status sx_visibility(int32_t K, const sx_cell* cells, const sx_camera* cam, uint32_t* masks,
                         sx_stream stream) {
   SX_TRY(check_cam(cam));

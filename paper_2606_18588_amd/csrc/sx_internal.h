@@ -307,6 +307,8 @@ hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, c
                                         char* ws, hipStream_t st);
 hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams& p,
                                    hipStream_t st);
+// host: KD-tree partition of n means [n*3] into K boxes lo/hi [K*3], cell_of [n]
+void kd_partition(int64_t n, const float* means, int K, float* lo, float* hi, int32_t* cell_of);
 hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint32_t* masks,
                              hipStream_t st);
 hipError_t launch_composite(int K, const float* const* partials,

@@ -150,3 +150,26 @@ def test_product_path_never_touches_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", src, re.M), f
                 assert "splat_oracle" not in src, f
+
+
+def test_kd_partition_matches_oracle(L):
+    """The library's KD-tree partitioner (host code) gives the oracle's cells
+    and boxes exactly, for several K, and rejects bad arguments."""
+    import numpy as np
+    import oracle
+    import synth
+    from paper_2606_18588_amd import binding as B
+    sc = synth.make_ground_scene(11, 60000)
+    for K in (1, 2, 5, 8, 16):
+        b_ref, c_ref = oracle.kd_partition(sc.means, K)
+        b, c = B.sx_kd_partition(sc.means, K)
+        assert np.array_equal(c, c_ref), K
+        for (lo, hi), (lo_r, hi_r) in zip(b, b_ref):
+            assert np.array_equal(np.float32(lo), np.float32(lo_r))
+            assert np.array_equal(np.float32(hi), np.float32(hi_r))
+    with pytest.raises(B.SplaxelError):
+        B.sx_kd_partition(sc.means, 17)
+    bad = sc.means.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(B.SplaxelError):
+        B.sx_kd_partition(bad, 4)

@@ -159,6 +159,34 @@ def test_geometric_visibility(orc):
             assert idx[-1] - idx[0] + 1 == len(idx)
 
 
+def test_kd_partition(orc):
+    """Partition strategy: 8 means on the x axis at 0..7 split at the
+    median 4 (K = 2), then at 2 and 6 (K = 4), numbered depth first; on a
+    ground scene the counts are balanced, every mean lies in its half-open
+    box, and the boxes tile space (each probe point is in exactly one)."""
+    pts = np.zeros((8, 3), np.float32)
+    pts[:, 0] = np.arange(8)
+    boxes, cell = orc.kd_partition(pts, 2)
+    np.testing.assert_array_equal(cell, [0, 0, 0, 0, 1, 1, 1, 1])
+    assert boxes[0][1][0] == 4.0 and boxes[1][0][0] == 4.0 and boxes[0][0][0] == -math.inf
+    boxes, cell = orc.kd_partition(pts[::-1], 4)
+    np.testing.assert_array_equal(cell, [3, 3, 2, 2, 1, 1, 0, 0])
+    assert [b[1][0] for b in boxes[:3]] == [2.0, 4.0, 6.0]
+    sc = synth.make_ground_scene(3, 40000)
+    for K in (3, 8, 16):
+        boxes, cell = orc.kd_partition(sc.means, K)
+        cnt = np.bincount(cell, minlength=K)
+        assert cnt.max() - cnt.min() <= 2, cnt
+        assert orc.imbalance(cell, K) < 1e-3
+        lo = np.array([b[0] for b in boxes])
+        hi = np.array([b[1] for b in boxes])
+        m = sc.means.astype(np.float64)
+        assert np.all((lo[cell] <= m) & (m < hi[cell]))
+        probe = np.random.default_rng(K).uniform(-600, 600, size=(5000, 3))
+        inside = ((lo[None] <= probe[:, None]) & (probe[:, None] < hi[None])).all(-1)
+        np.testing.assert_array_equal(inside.sum(1), 1)
+
+
 def test_rotation_matches_library(orc):
     """Sigma = R S S^T R^T with R from the unit quaternion (w,x,y,z): checked
     against scipy's rotation for a Gaussian on the optical axis, where the
