@@ -18,3 +18,11 @@ def orc():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="module")
+def torch_gpu_fs():
+    from gpu_helpers import need_gpu
+    need_gpu()
+    import torch
+    return torch
