@@ -243,6 +243,36 @@ sx_status sx_composite(int32_t K, const float* const* partials,
                        const sx_params* p, float* out, uint32_t* masks,
                        sx_stream stream);
 
+/* Composition with the saturation state carried between renders of a view
+ * and its speculative re-evaluation (appendix, experimental analysis:
+ * saturation stability during training), so that pairs pruned by
+ * saturation come back when the transmittance in front of them recovers.
+ * Same order, output and K range as sx_composite; per pixel, with P the
+ * incoming transmittance of the cells rendered now:
+ *   - a pair whose masks bit is set (rendered now) keeps it while
+ *     P >= t_min; otherwise the bit is cleared and budget[m*H*W + p] =
+ *     P (1 - T_m), its transmittance consumption;
+ *   - a pair whose bit is clear and whose box the ray meets (omega bit set,
+ *     or omega NULL) is re-activated, in entry order, while the residual
+ *     R = P - S reaches t_min and R >= its budget (S: budgets of the pairs
+ *     re-activated before it on this ray); the first that fails ends the
+ *     scan for the pixel;
+ *   - other pairs are cleared.
+ *   masks   [K * ceil(H*W/32)] words, read and rewritten (bits past H*W
+ *           cleared); partials of cleared pairs must be the identity
+ *           (0, 0, 0, 1), as sx_render writes them.
+ *   omega   the geometric map of sx_visibility, same layout, or NULL.
+ *   budget  [K * H * W] floats owned by the caller, zero-initialised once
+ *           per view and kept with its masks: read for pairs pruned in an
+ *           earlier render, written for pairs pruned now.
+ * A pair cleared by other means (sx_composite, sx_visibility, the caller)
+ * is tested with whatever budget the buffer holds for it (zero after
+ * initialisation). */
+sx_status sx_composite_reeval(int32_t K, const float* const* partials,
+                              const sx_cell* cells, const sx_camera* cam,
+                              const sx_params* p, float* out, uint32_t* masks,
+                              const uint32_t* omega, float* budget, sx_stream stream);
+
 /* L1 loss of the composed image (the RGB term of the paper's loss):
  * dout[H*W*4] = (sign(rgb - target) / (3HW), 0); loss_sum (device float,
  * may be NULL) receives += the mean absolute error.  target [H*W*3]. */

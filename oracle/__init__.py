@@ -38,6 +38,7 @@ FLAG_DEPTH_ROUND = 4
 FLAG_ORDER = 8
 FLAG_CLAMP = 16
 FLAG_VISIBILITY = 32
+FLAG_SATURATION = 64
 
 
 def build(force: bool = False) -> str:
@@ -290,6 +291,38 @@ def composite(Cparts: np.ndarray, Tparts: np.ndarray, cells, cam, settings,
                        ctypes.byref(_params(settings, 0, same_frame_cull)),
                        _p(out["rgb"]), _p(out["T"]), _p(out["order"]),
                        _p(out["mask"]), _p(out["flags"]))
+    return out
+
+
+def composite_reeval(Cparts: np.ndarray, Tparts: np.ndarray, cells, cam, settings,
+                     mask_in: np.ndarray, budget: np.ndarray,
+                     omega: Optional[np.ndarray] = None,
+                     same_frame_cull: bool = False) -> dict:
+    """Eq. 5 with the saturation state carried between renders of a view and
+    its speculative re-evaluation (appendix, saturation stability during
+    training).  mask_in [K,H,W] (1 = cell rendered at the pixel), omega
+    [K,H,W] (1 = the pixel's ray meets the cell's box; None = every box),
+    budget [K,H,W] the stale transmittance consumption of pruned pairs
+    (updated in place for the pairs pruned now).  Returns rgb, T, mask (the
+    state for the next render), flips [H,W] (re-activated cells per pixel)
+    and flags."""
+    K = len(cells)
+    H, W = cam.height, cam.width
+    Cp = np.ascontiguousarray(np.asarray(Cparts, np.float64))
+    Tp = np.ascontiguousarray(np.asarray(Tparts, np.float64))
+    lo, hi = _cells_lohi(cells)
+    mi = np.ascontiguousarray(mask_in.astype(np.uint8))
+    om = None if omega is None else np.ascontiguousarray(omega.astype(np.uint8))
+    assert budget.dtype == np.float64 and budget.flags.c_contiguous
+    assert budget.shape == (K, H, W) and mi.shape == (K, H, W)
+    out = dict(rgb=np.zeros((H, W, 3)), T=np.zeros((H, W)),
+               mask=np.zeros((K, H, W), np.uint8), flips=np.zeros((H, W), np.int32),
+               flags=np.zeros((H, W), np.uint8))
+    lib().or_composite_reeval(ctypes.c_int(K), _p(Cp), _p(Tp), _p(lo), _p(hi),
+                              ctypes.byref(_cam(cam)),
+                              ctypes.byref(_params(settings, 0, same_frame_cull)),
+                              _p(mi), _p(om), _p(budget), _p(out["rgb"]), _p(out["T"]),
+                              _p(out["mask"]), _p(out["flips"]), _p(out["flags"]))
     return out
 
 

@@ -427,6 +427,8 @@ enum : uint8_t {
   FLAG_ORDER = 8,        // two cell entry keys within 1e-6 relative
   FLAG_CLAMP = 16,       // alpha within 1e-6 relative of the alpha_max clamp
   FLAG_VISIBILITY = 32,  // a cell box's geometric visibility within rounding of flipping
+  FLAG_SATURATION = 64,  // a saturation or re-activation test within 1e-3 relative
+                         // of its threshold
 };
 
 struct Blend {  // one blended pair on a pixel's ray
@@ -714,6 +716,7 @@ int or_composite(int K, const double* Cparts, const double* Tparts,
       const int m = ks[j].second;
       if (order) order[p * K + j] = m;
       bool active = true;
+      if (flags && std::fabs(Pj - P->t_min) <= 1e-3 * P->t_min) flags[p] |= FLAG_SATURATION;
       if (Pj < P->t_min) {
         active = false;
         if (mask_out) mask_out[(int64_t)m * HW + p] = 0;
@@ -726,6 +729,92 @@ int or_composite(int K, const double* Cparts, const double* Tparts,
     }
     for (int k = 0; k < 3; ++k) out_rgb[p * 3 + k] = c[k] + Pj * P->bg[k];
     out_T[p] = Pj;
+  }
+  return 0;
+}
+
+// Composition with the saturation state carried from one render of a view
+// to the next, and its speculative re-evaluation (appendix, experimental
+// analysis: saturation stability during training).  Per pixel, in entry
+// order, with P the incoming transmittance of the cells rendered now:
+//   * a cell active at this pixel (mask_in bit set) is composited; if
+//     P < t_min it is pruned for the next render and its transmittance
+//     consumption P (1 - T_j) is kept as its budget;
+//   * a pruned cell whose box the pixel's ray meets (omega set, or omega
+//     null) is tested with the residual R = P - S, S being the budgets of
+//     the cells re-activated before it on this ray: it is re-activated when
+//     R >= t_min and R covers its whole budget, and S grows by that budget;
+//     the first pruned cell that fails ends the scan for the pixel;
+//   * any other cell stays inactive.
+// Cells rendered with their bit cleared have C = 0, T = 1 and are skipped.
+//   mask_in, omega, mask_out [K][H*W] bytes; budget [K][H*W] in/out
+//   (written for pairs pruned now, read for pairs pruned before); flips
+//   [H*W] counts the re-activated cells of each pixel.
+int or_composite_reeval(int K, const double* Cparts, const double* Tparts,
+                        const double* lo, const double* hi, const Cam* cam,
+                        const Params* P, const uint8_t* mask_in, const uint8_t* omega,
+                        double* budget, double* out_rgb, double* out_T,
+                        uint8_t* mask_out, int32_t* flips, uint8_t* flags) {
+  const int W = cam->width, H = cam->height;
+  const int64_t HW = (int64_t)W * H;
+  const double band = 1e-3 * P->t_min;
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < HW; ++p) {
+    const int px = (int)(p % W), py = (int)(p / W);
+    std::vector<std::pair<double, int>> ks(K);
+    for (int m = 0; m < K; ++m)
+      ks[m] = {entry_key(*cam, px, py, lo + m * 3, hi + m * 3), m};
+    std::stable_sort(ks.begin(), ks.end(),
+                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+                       return a.first < b.first;
+                     });
+    // an order within rounding of a tie is ambiguous for any two cells that
+    // take part here (composited or tested)
+    auto takes_part = [&](int m) {
+      return mask_in[(int64_t)m * HW + p] || !omega || omega[(int64_t)m * HW + p];
+    };
+    for (int j = 0; j + 1 < K; ++j)
+      for (int j2 = j + 1; j2 < K; ++j2) {
+        const double a = ks[j].first, b = ks[j2].first;
+        if (!(a == 0.0 && b == 0.0) &&
+            std::fabs(b - a) <= 1e-6 * std::max(std::fabs(a), std::fabs(b)) &&
+            takes_part(ks[j].second) && takes_part(ks[j2].second))
+          flags[p] |= FLAG_ORDER;
+      }
+    double Pj = 1.0, S = 0.0, c[3] = {0, 0, 0};
+    bool scanning = true;
+    int32_t nflip = 0;
+    for (int j = 0; j < K; ++j) {
+      const int64_t mp = (int64_t)ks[j].second * HW + p;
+      if (mask_in[mp]) {
+        const double Tm = Tparts[mp];
+        if (std::fabs(Pj - P->t_min) <= band) flags[p] |= FLAG_SATURATION;
+        const bool active = Pj >= P->t_min;
+        mask_out[mp] = active ? 1 : 0;
+        if (!active) budget[mp] = Pj * (1.0 - Tm);
+        if (!active && P->same_frame_cull) continue;
+        for (int k = 0; k < 3; ++k) c[k] += Pj * Cparts[mp * 3 + k];
+        Pj *= Tm;
+      } else if (!omega || omega[mp]) {
+        const double R = Pj - S, b = budget[mp];
+        if (scanning &&
+            (std::fabs(R - P->t_min) <= band || std::fabs(R - b) <= 1e-3 * std::max(R, b)))
+          flags[p] |= FLAG_SATURATION;
+        if (scanning && R >= P->t_min && R >= b) {
+          mask_out[mp] = 1;
+          S += b;
+          ++nflip;
+        } else {
+          scanning = false;
+          mask_out[mp] = 0;
+        }
+      } else {
+        mask_out[mp] = 0;
+      }
+    }
+    for (int k = 0; k < 3; ++k) out_rgb[p * 3 + k] = c[k] + Pj * P->bg[k];
+    out_T[p] = Pj;
+    flips[p] = nflip;
   }
   return 0;
 }

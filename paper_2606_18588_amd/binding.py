@@ -89,6 +89,7 @@ EXPORTS = (
     "sx_adam", "sx_fill_u32", "sx_preprocess_multi", "sx_multi_workspace_size",
     "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
     "sx_render_backward_stages", "sx_visibility", "sx_kd_partition",
+    "sx_composite_reeval",
 )
 
 _lib = None
@@ -273,6 +274,14 @@ def sx_composite(partials: Sequence[torch.Tensor], cells, cam: SxCamera,
         c_i32(len(partials)), ptr_array(partials), cells_array(cells),
         ctypes.byref(cam), ctypes.byref(p), ptr(out), ptr(masks),
         stream_handle(stream)))
+
+
+def sx_composite_reeval(partials: Sequence[torch.Tensor], cells, cam: SxCamera,
+                        p: SxParams, out, masks, omega, budget, stream=None) -> None:
+    _check("sx_composite_reeval", lib().sx_composite_reeval(
+        c_i32(len(partials)), ptr_array(partials), cells_array(cells),
+        ctypes.byref(cam), ctypes.byref(p), ptr(out), ptr(masks), ptr(omega),
+        ptr(budget), stream_handle(stream)))
 
 
 def sx_l1_loss(out, target, width: int, height: int, dout, loss_sum,

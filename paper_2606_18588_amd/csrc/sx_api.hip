@@ -225,8 +225,23 @@ sx_status sx_composite(int32_t K, const float* const* partials,
   for (int m = 0; m < K; ++m)
     if (!partials[m]) return fail(SX_EINVAL, "partial %d is NULL", m);
   return dev(sx::launch_composite(K, partials, cells, sx::make_dcam(*cam), sx::make_kparams(*p, *cam),
-                                  out, masks, (hipStream_t)stream),
+                                  out, masks, nullptr, nullptr, (hipStream_t)stream),
              "sx_composite");
+}
+
+sx_status sx_composite_reeval(int32_t K, const float* const* partials,
+                              const sx_cell* cells, const sx_camera* cam,
+                              const sx_params* p, float* out, uint32_t* masks,
+                              const uint32_t* omega, float* budget, sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  SX_TRY(check_cells(K, partials, cells));
+  if (!out || !masks || !budget) return fail(SX_EINVAL, "out, masks and budget are required");
+  for (int m = 0; m < K; ++m)
+    if (!partials[m]) return fail(SX_EINVAL, "partial %d is NULL", m);
+  return dev(sx::launch_composite(K, partials, cells, sx::make_dcam(*cam), sx::make_kparams(*p, *cam),
+                                  out, masks, omega, budget, (hipStream_t)stream),
+             "sx_composite_reeval");
 }
 
 sx_status sx_l1_loss(const float* out, const float* target, int32_t width,

@@ -26,6 +26,8 @@ struct CompArgs {
   float4* out;
   uint32_t* masks;
   uint32_t words;
+  const uint32_t* omega;  // re-evaluation: boxes the pixel rays meet (NULL = all)
+  float* budget;          // re-evaluation: [K][H*W] stale consumption of pruned pairs
   // backward
   const float4* dout;
   float4* dpart[kMaxCells];
@@ -68,7 +70,16 @@ __device__ __forceinline__ void cell_ranks(const CompArgs& a, int px, int py,
   }
 }
 
-template <int KM>
+// RE = false: the saturation test only clears mask bits.  RE = true: the
+// masks are the per-pair state carried between renders of the view and are
+// rewritten whole: a rendered pair stays set while its incoming
+// transmittance P reaches t_min, and is pruned otherwise with its
+// consumption P (1 - T) kept as its budget; a pruned pair whose box the ray
+// meets is re-activated while the residual R = P - S (S: budgets of the
+// pairs re-activated before it on the ray) reaches t_min and covers its
+// budget, the first that fails ending the scan (appendix, experimental
+// analysis: speculative re-evaluation of saturation).
+template <int KM, bool RE>
 __global__ __launch_bounds__(256) void k_composite(CompArgs a) {
   const uint32_t HW = (uint32_t)a.W * a.H;
   const uint32_t p = blockIdx.x * 256 + threadIdx.x;
@@ -81,19 +92,46 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a) {
 #pragma unroll
   for (int m = 0; m < KM; ++m)
     cm[m] = (inside && m < a.K) ? a.part[m][pp] : make_float4(0.f, 0.f, 0.f, 1.f);
-  float P = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+  // RE: bit m of `on` = pair rendered now, of `vis` = the ray meets box m
+  uint32_t on = ~0u, vis = ~0u;
+  if (RE) {
+    const uint32_t wi = pp >> 5, bi = pp & 31;
+    on = 0;
+#pragma unroll
+    for (int m = 0; m < KM; ++m)
+      if (m < a.K) on |= ((a.masks[(size_t)m * a.words + wi] >> bi) & 1u) << m;
+    if (a.omega) {
+      vis = 0;
+#pragma unroll
+      for (int m = 0; m < KM; ++m)
+        if (m < a.K) vis |= ((a.omega[(size_t)m * a.words + wi] >> bi) & 1u) << m;
+    }
+  }
+  float P = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, S = 0.f;
+  bool scanning = true;
   bool act[KM];
 #pragma unroll
   for (int j = 0; j < KM; ++j) {
 #pragma unroll
     for (int m = 0; m < KM; ++m) {
       if (m < a.K && rank[m] == j) {
-        act[m] = P >= a.t_min;
-        if (act[m] || !a.same_frame) {
-          c0 = fmaf(P, cm[m].x, c0);
-          c1 = fmaf(P, cm[m].y, c1);
-          c2 = fmaf(P, cm[m].z, c2);
-          P = P * cm[m].w;
+        if (!RE || ((on >> m) & 1u)) {
+          act[m] = P >= a.t_min;
+          if (RE && !act[m] && inside) a.budget[(size_t)m * HW + p] = P * (1.f - cm[m].w);
+          if (act[m] || !a.same_frame) {
+            c0 = fmaf(P, cm[m].x, c0);
+            c1 = fmaf(P, cm[m].y, c1);
+            c2 = fmaf(P, cm[m].z, c2);
+            P = P * cm[m].w;
+          }
+        } else if ((vis >> m) & 1u) {
+          const float R = P - S;
+          const float b = (scanning && inside) ? a.budget[(size_t)m * HW + p] : 0.f;
+          act[m] = scanning && R >= a.t_min && R >= b;
+          if (act[m]) S += b;
+          scanning = act[m];
+        } else {
+          act[m] = false;
         }
       }
     }
@@ -105,12 +143,17 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a) {
 #pragma unroll
     for (int m = 0; m < KM; ++m) {
       if (m >= a.K) break;
-      const uint64_t keep = __ballot(!inside || act[m]);
+      // RE rewrites the words (bits past the image cleared); otherwise the
+      // pairs that stay active are kept
+      const uint64_t keep = __ballot(RE ? (inside && act[m]) : (!inside || act[m]));
       if (lane == 0 || lane == 32) {
         const uint32_t w = w0 + (lane >> 5);
         if (w < a.words) {
           uint32_t* word = a.masks + (size_t)m * a.words + w;
-          *word &= (uint32_t)(keep >> lane);
+          if (RE)
+            *word = (uint32_t)(keep >> lane);
+          else
+            *word &= (uint32_t)(keep >> lane);
         }
       }
     }
@@ -255,26 +298,36 @@ hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint3
   return hipGetLastError();
 }
 
+template <bool RE>
+static void launch_comp_k(int K, dim3 grid, const CompArgs& a, hipStream_t st) {
+  if (K <= 1)
+    hipLaunchKernelGGL((k_composite<1, RE>), grid, dim3(256), 0, st, a);
+  else if (K <= 2)
+    hipLaunchKernelGGL((k_composite<2, RE>), grid, dim3(256), 0, st, a);
+  else if (K <= 4)
+    hipLaunchKernelGGL((k_composite<4, RE>), grid, dim3(256), 0, st, a);
+  else if (K <= 8)
+    hipLaunchKernelGGL((k_composite<8, RE>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_composite<16, RE>), grid, dim3(256), 0, st, a);
+}
+
 hipError_t launch_composite(int K, const float* const* partials,
                             const sx_cell* cells, const DCam& cam,
                             const KParams& p, float* out, uint32_t* masks,
-                            hipStream_t st) {
+                            const uint32_t* omega, float* budget, hipStream_t st) {
   CompArgs a = comp_args(K, partials, cells, cam, p);
   a.out = reinterpret_cast<float4*>(out);
   a.masks = masks;
+  a.omega = omega;
+  a.budget = budget;
   const uint32_t HW = (uint32_t)cam.W * cam.H;
   a.words = (HW + 31) / 32;
   const dim3 grid((HW + 255) / 256);
-  if (K <= 1)
-    hipLaunchKernelGGL(k_composite<1>, grid, dim3(256), 0, st, a);
-  else if (K <= 2)
-    hipLaunchKernelGGL(k_composite<2>, grid, dim3(256), 0, st, a);
-  else if (K <= 4)
-    hipLaunchKernelGGL(k_composite<4>, grid, dim3(256), 0, st, a);
-  else if (K <= 8)
-    hipLaunchKernelGGL(k_composite<8>, grid, dim3(256), 0, st, a);
+  if (budget)
+    launch_comp_k<true>(K, grid, a, st);
   else
-    hipLaunchKernelGGL(k_composite<16>, grid, dim3(256), 0, st, a);
+    launch_comp_k<false>(K, grid, a, st);
   return hipGetLastError();
 }
 

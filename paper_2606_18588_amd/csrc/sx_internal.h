@@ -311,10 +311,11 @@ hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams&
 void kd_partition(int64_t n, const float* means, int K, float* lo, float* hi, int32_t* cell_of);
 hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint32_t* masks,
                              hipStream_t st);
+// budget non-NULL selects the re-evaluating form (masks then required)
 hipError_t launch_composite(int K, const float* const* partials,
                             const sx_cell* cells, const DCam& cam,
                             const KParams& p, float* out, uint32_t* masks,
-                            hipStream_t st);
+                            const uint32_t* omega, float* budget, hipStream_t st);
 hipError_t launch_composite_backward(int K, const float* const* partials,
                                      const sx_cell* cells, const DCam& cam,
                                      const KParams& p, const float* dout,

@@ -190,7 +190,9 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ bsum, int64_t nb,
                                                     const uint64_t* __restrict__ part,
                                                     uint32_t* __restrict__ vis_off,
-                                                    uint64_t* counts, int64_t cap) {
+                                                    uint64_t* counts, int64_t cap,
+                                                    uint2* __restrict__ root_bin,
+                                                    uint32_t* __restrict__ root_seg) {
   __shared__ unsigned long long s4[4];
   __shared__ uint32_t s_scan[4];
   const bool last = blockIdx.x == gridDim.x - 1;
@@ -218,9 +220,16 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
       run += v[j];
     }
   if (last && threadIdx.x == 0) {
+    const bool over = pi > (uint64_t)cap;
     counts[0] = pv + total;
     counts[1] = pi;
-    counts[2] = pi > (uint64_t)cap ? 1ull : 0ull;
+    counts[2] = over ? 1ull : 0ull;
+    // the root of the binning: one bin holding every visible Gaussian in
+    // depth order (none when the instances overflow the buffer)
+    const uint32_t nvis = over ? 0u : (uint32_t)(pv + total);
+    root_bin[0] = make_uint2(0u, nvis);
+    root_seg[0] = 0;
+    root_seg[1] = (nvis + kBinSeg - 1) / kBinSeg;
   }
 }
 
@@ -528,14 +537,6 @@ struct BinLevel {
   int last;
 };
 
-__global__ void k_bin_root(const uint64_t* counts, uint2* bins, uint32_t* seg) {
-  if (threadIdx.x != 0) return;
-  const uint32_t nvis = counts[2] != 0 ? 0u : (uint32_t)counts[0];
-  bins[0] = make_uint2(0u, nvis);
-  seg[0] = 0;
-  seg[1] = (nvis + kBinSeg - 1) / kBinSeg;
-}
-
 // Segment `sg`: its parent, first entry and entry count.
 __device__ __forceinline__ int bin_segment(const BinLevel& a, uint32_t sg, uint32_t* lo,
                                            uint32_t* m) {
@@ -760,7 +761,8 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(256), 0, st, proj.block_sums,
                        (int64_t)L.nb, part);
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, st, proj.block_sums,
-                       (int64_t)L.nb, part, u32(L.vis_off), counts, (int64_t)capacity);
+                       (int64_t)L.nb, part, u32(L.vis_off), counts, (int64_t)capacity,
+                       reinterpret_cast<uint2*>(ws + L.bl_bins[0]), u32(L.bl_seg[0]));
   }
   if ((e = hipGetLastError())) return e;
   if (h_counts) {
@@ -803,7 +805,7 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
                     reinterpret_cast<uint2*>(ws + L.bl_bins[1])};
   uint32_t* seg[2] = {u32(L.bl_seg[0]), u32(L.bl_seg[1])};
   uint32_t* lists[2] = {u32(L.bl_list[0]), u32(L.bl_list[1])};
-  hipLaunchKernelGGL(k_bin_root, dim3(1), dim3(64), 0, st, counts, bins[0], seg[0]);
+  // (the root bin, bins[0] and seg[0], was written with the visible count)
   int64_t tot_off[32];
   for (int lev = 0, o = 0; lev < L.bl_levels; ++lev) {
     const int side = 1 << (2 * lev);

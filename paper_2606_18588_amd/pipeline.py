@@ -254,34 +254,51 @@ class Frame:
         self.c_par = B.params(settings, sh_deg, flags)
         self.out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=device)
         self.masks = None
+        self.omega = None   # geometric maps kept for re-evaluation
+        self.budget = None  # [K, H*W] stale consumption of pruned pairs
 
     @property
     def K(self):
         return len(self.cells)
 
-    def init_masks(self, geometric=False):
+    def init_masks(self, geometric=False, reeval=False):
         """Every (cell, pixel) pair active, or with geometric, only the pairs
         where the cell's box is visible (sx_visibility); the composition
-        then clears the pairs behind saturated prefixes."""
+        then clears the pairs behind saturated prefixes.  With reeval the
+        masks become the view's saturation state: pruned pairs keep their
+        transmittance consumption and come back when the transmittance in
+        front of them recovers (sx_composite_reeval)."""
         words = (self.cam.width * self.cam.height + 31) // 32
         self.masks = torch.empty((self.K, words), dtype=torch.int32, device=self.out.device)
         if geometric:
             B.sx_visibility(self.boxes, self.c_cam, self.masks)
         else:
             B.sx_fill_u32(self.masks, 0xFFFFFFFF)
+        self.omega = self.masks.clone() if (reeval and geometric) else None
+        self.budget = (torch.zeros((self.K, self.cam.width * self.cam.height),
+                                   dtype=torch.float32, device=self.out.device)
+                       if reeval else None)
         return self.masks
 
     def forward(self, use_masks=False, update_masks=False, sync=True):
         """Render every cell (optionally restricted to the active mask bits
         from the previous render of this view) and compose them; with
-        update_masks the composition clears the bits of saturated pairs."""
+        update_masks the composition clears the bits of saturated pairs, or,
+        after init_masks(reeval=True), re-evaluates the view's state."""
+        if update_masks and self.budget is not None and not use_masks:
+            raise ValueError("re-evaluation needs the renders restricted to the masks")
         for k, v in enumerate(self.views):
             v.preprocess()
             v.sort(sync=sync)
             m = self.masks[k] if (use_masks and self.masks is not None) else None
             v.render(m)
-        B.sx_composite([v.partial for v in self.views], self.boxes, self.c_cam, self.c_par,
-                       self.out, self.masks if update_masks else None)
+        parts = [v.partial for v in self.views]
+        if update_masks and self.budget is not None:
+            B.sx_composite_reeval(parts, self.boxes, self.c_cam, self.c_par, self.out,
+                                  self.masks, self.omega, self.budget)
+        else:
+            B.sx_composite(parts, self.boxes, self.c_cam, self.c_par, self.out,
+                           self.masks if update_masks else None)
         return self.out
 
     def backward(self, dout, grads: Sequence[GaussianParams], accumulate=False):

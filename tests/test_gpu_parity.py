@@ -409,6 +409,65 @@ def test_composite_with_visibility_matches_oracle(torch_gpu):
           f"invisible pairs {(vis['vis'] == 0).sum()}", flush=True)
 
 
+def test_composite_reeval_three_renders_match_oracle(torch_gpu):
+    """Saturation carried across three renders of one view with speculative
+    re-evaluation: KD cells starting from their geometric maps; render 1
+    prunes pairs behind saturated prefixes and keeps their budgets; the
+    opacities are then lowered, and render 2 re-activates the pairs the
+    fresh residual covers; render 3 renders them.  Image, masks and budgets
+    match the oracle run on its own state at every render (pixels flagged
+    at any render excluded from then on)."""
+    print("case: composite re-evaluation, three renders", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    scene = synth.make_cube_scene(4, 9000, log_scale=(-3.2, 0.4), logit_sigma=2.0)
+    cam = synth.look_at_camera((2.4, -2.9, 1.6), (0.0, 0.1, 0.0), 112, 84, hfov_deg=55.0)
+    boxes_t, cell_of = B.sx_kd_partition(scene.means, 8)
+    boxes = [synth.Cell(lo, hi) for lo, hi in boxes_t]
+    scenes = [scene.subset(np.nonzero(cell_of == k)[0]) for k in range(8)]
+    K, H, W = 8, cam.height, cam.width
+    fr, params = _frame(torch, scenes, boxes, cam)
+    fr.init_masks(geometric=True, reeval=True)
+    vis = oracle.visibility(boxes, cam)
+    assert not vis["flags"].any()
+    om = vis["vis"]
+    state, budget = om.copy(), np.zeros((K, H, W))
+    faded = [s.subset(np.arange(s.n)) for s in scenes]
+    for s in faded:
+        s.opacity_logits = s.opacity_logits - 0.7
+    bad = np.zeros((H, W), bool)
+    stats = []
+    for r, scs in enumerate((scenes, faded, faded)):
+        if r == 1:
+            for prm in params:
+                prm.opacity_logits -= 0.7
+        out = fr.forward(use_masks=True, update_masks=True).cpu().numpy()
+        torch.cuda.synchronize()
+        ref = oracle.forward(scs, boxes, cam, ST, masks=state)
+        rr = oracle.composite_reeval(ref.Cparts, ref.Tparts, boxes, cam, ST, state, budget,
+                                     omega=om)
+        for p in ref.parts:
+            bad |= p["flags"] != 0
+        bad |= rr["flags"] != 0
+        fl = bad.astype(np.uint8)
+        cmax = max(float(oracle.preprocess(s, cam, ST)["rgb"].max()) for s in scs)
+        e, nf = compare_image(out[..., :3], rr["rgb"], fl, 1e-4, 8 * jump_bound(ST, cmax))
+        compare_image(out[..., 3], rr["T"], fl, 1e-4, 1.0)
+        bits = np.unpackbits(fr.masks.cpu().numpy().view(np.uint8),
+                             bitorder="little").reshape(K, -1)[:, :H * W]
+        ok = ~bad.reshape(-1)
+        assert_same(bits[:, ok], rr["mask"].reshape(K, -1)[:, ok], f"masks after render {r + 1}")
+        got_b = fr.budget.cpu().numpy().reshape(K, -1)[:, ok]
+        np.testing.assert_allclose(got_b, budget.reshape(K, -1)[:, ok], rtol=1e-3, atol=1e-10)
+        pruned = int(((rr["mask"] == 0) & (om == 1)).sum())
+        stats.append((pruned, int(rr["flips"].sum())))
+        print(f"render {r + 1}: max-abs {e:.3g}, flagged {int(bad.sum())}, pruned {pruned}, "
+              f"re-activated {stats[-1][1]}", flush=True)
+        state = rr["mask"]
+    assert stats[0][0] > 1000 and stats[0][1] == 0
+    assert stats[1][1] > 500 and stats[1][0] > 1000
+
+
 def test_composite_kd_cells_matches_oracle(torch_gpu):
     """K = 8 cells from the KD-tree partitioner (boxes bounded on some axes,
     unbounded at the scene's outside): the composition by ray entry order

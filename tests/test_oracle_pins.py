@@ -502,6 +502,111 @@ def test_saturation_culling_bound(orc):
     assert np.all(nxt.Tparts[inactive] == 1.0)
 
 
+def test_reeval_hand_cases(orc):
+    """Speculative re-evaluation of pruned pairs (appendix, saturation
+    stability): three cells in entry order on every ray, the first rendered,
+    the other two pruned with stale budgets; each case's outcome worked out
+    by hand from the rule (residual R = P - S must reach t_min and cover the
+    budget; the first failure ends the scan)."""
+    cam = synth.tiny_camera(1, 1)
+    cells = _zslab_cells([-2.0, -1.0, 0.0, 1.0])
+    t = 1e-4
+    st = synth.RenderSettings(t_min=np.float32(t))
+    t = float(np.float32(t))  # the oracle compares against t_min as float32
+    # (T of cell 0, budgets of cells 1 and 2) -> expected masks, flips
+    cases = [
+        (0.5, 3e-5, 5e-5, (1, 1, 1), 2),      # R = 0.5 covers both
+        (1.5e-4, 3e-5, 5e-5, (1, 1, 1), 2),   # 1.5e-4 -> 1.2e-4 >= t_min
+        (1.2e-4, 3e-5, 5e-5, (1, 1, 0), 1),   # 1.2e-4 -> 0.9e-4 < t_min: stop
+        (1.5e-4, 2e-4, 1e-5, (1, 0, 0), 0),   # budget 2e-4 not covered: stop
+        (0.9e-4, 1e-5, 1e-5, (1, 0, 0), 0),   # residual below t_min already
+    ]
+    for T0, b1, b2, want, nf in cases:
+        Cp = np.zeros((3, 1, 1, 3))
+        Cp[0] = 0.25
+        Tp = np.ones((3, 1, 1))
+        Tp[0] = T0
+        mask_in = np.array([1, 0, 0], np.uint8).reshape(3, 1, 1)
+        budget = np.array([0.0, b1, b2]).reshape(3, 1, 1)
+        out = orc.composite_reeval(Cp, Tp, cells, cam, st, mask_in, budget)
+        assert tuple(out["mask"].reshape(-1)) == want, (T0, b1, b2)
+        assert out["flips"][0, 0] == nf
+        assert out["rgb"][0, 0, 0] == 0.25 and out["T"][0, 0] == T0
+        np.testing.assert_array_equal(budget.reshape(-1), [0.0, b1, b2])  # nothing pruned now
+    # pruning now: cell 0 leaves 5e-5, so cell 1 (rendered, T = 0.3) is
+    # pruned with budget 5e-5 * (1 - 0.3); cell 2 (pruned, budget 1e-6) is
+    # tested with R = 5e-5 * 0.3 and stays pruned; cell 0 stays active
+    Tp = np.array([5e-5, 0.3, 1.0]).reshape(3, 1, 1)
+    Cp = np.zeros((3, 1, 1, 3))
+    budget = np.array([0.0, 0.0, 1e-6]).reshape(3, 1, 1)
+    out = orc.composite_reeval(Cp, Tp, cells, cam, st,
+                               np.array([1, 1, 0], np.uint8).reshape(3, 1, 1), budget)
+    assert tuple(out["mask"].reshape(-1)) == (1, 0, 0)
+    assert budget[1, 0, 0] == 5e-5 * (1 - 0.3) and budget[2, 0, 0] == 1e-6
+    assert out["T"][0, 0] == 5e-5 * 0.3
+    # a box the ray misses (omega 0) is never re-activated
+    out = orc.composite_reeval(np.zeros((3, 1, 1, 3)), np.ones((3, 1, 1)), cells, cam, st,
+                               np.array([1, 0, 0], np.uint8).reshape(3, 1, 1),
+                               np.zeros((3, 1, 1)),
+                               omega=np.array([1, 0, 1], np.uint8).reshape(3, 1, 1))
+    assert tuple(out["mask"].reshape(-1)) == (1, 0, 1)
+
+
+def test_reeval_reduces_to_composite_and_is_stable(orc):
+    """With every pair rendered the re-evaluating composition is Eq. 5 with
+    the saturation test (the same image and masks); rendering the view again
+    from its own masks and budgets, with the scene unchanged, re-activates
+    nothing (the residual is the transmittance that pruned the pairs) and
+    gives the same image.  Lowering the opacity of the front cell's
+    Gaussians then re-activates pairs behind it, and only where the fresh
+    residual reaches t_min."""
+    sc = synth.make_cube_scene(11, 6000, log_scale=(-3.2, 0.4), logit_sigma=2.0)
+    cam = synth.tiny_camera(64, 64)
+    edges = synth.quantile_edges(sc.means[:, 2], 4)
+    part = synth.axis_slab_partition(sc, 2, edges)
+    scenes = part.cell_scenes(sc)
+    K = len(scenes)
+    fr = orc.forward(scenes, part.cells, cam, ST)
+    ones = np.ones((K, cam.height, cam.width), np.uint8)
+    budget = np.zeros((K, cam.height, cam.width))
+    r1 = orc.composite_reeval(fr.Cparts, fr.Tparts, part.cells, cam, ST, ones, budget)
+    np.testing.assert_array_equal(r1["rgb"], fr.comp["rgb"])
+    np.testing.assert_array_equal(r1["T"], fr.comp["T"])
+    np.testing.assert_array_equal(r1["mask"], fr.comp["mask"])
+    pruned = r1["mask"] == 0
+    assert pruned.sum() > 100 and np.all(r1["flips"] == 0)
+    # a budget is P_j (1 - T_j) with P_j < t_min (zero where the cell is
+    # transparent on the ray)
+    assert np.all(budget[pruned] >= 0) and np.all(budget[pruned] < ST.t_min)
+    assert (budget[pruned] > 0).mean() > 0.5
+    assert np.all(budget[~pruned] == 0)
+    # the same view again, from its own state
+    f2 = orc.forward(scenes, part.cells, cam, ST, masks=r1["mask"])
+    b2 = budget.copy()
+    r2 = orc.composite_reeval(f2.Cparts, f2.Tparts, part.cells, cam, ST, r1["mask"], b2)
+    assert np.all(r2["flips"] == 0)
+    np.testing.assert_array_equal(r2["mask"], r1["mask"])
+    np.testing.assert_array_equal(b2, budget)
+    assert np.abs(r2["rgb"] - r1["rgb"]).max() <= ST.t_min
+    # fade the front cell (order 0 on every ray of this camera)
+    assert np.all(fr.comp["order"][..., 0] == 0)
+    faded = [s for s in scenes]
+    faded[0] = scenes[0].subset(np.arange(scenes[0].n))
+    faded[0].opacity_logits = faded[0].opacity_logits - 6.0
+    f3 = orc.forward(faded, part.cells, cam, ST, masks=r1["mask"])
+    b3 = budget.copy()
+    r3 = orc.composite_reeval(f3.Cparts, f3.Tparts, part.cells, cam, ST, r1["mask"], b3)
+    flipped = (r3["mask"] == 1) & pruned
+    assert flipped.sum() > 0 and flipped.sum() == r3["flips"].sum()
+    # a pixel re-activates its first pruned cell iff the fresh residual
+    # after its rendered cells reaches t_min (budgets are below t_min)
+    for py, px in zip(*np.nonzero(pruned.any(0))):
+        first = next(int(m) for m in fr.comp["order"][py, px] if pruned[m, py, px])
+        R = r3["T"][py, px]
+        if abs(R - ST.t_min) > 1e-3 * ST.t_min:
+            assert bool(r3["mask"][first, py, px]) == (R >= np.float32(ST.t_min))
+
+
 # ------------------------------------------------------------ Eq. 6-7 -----
 def _flag_free_fd_scene(orc, seed0, cam, cells_fn):
     for seed in range(seed0, seed0 + 40):
