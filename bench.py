@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--requests", type=int, default=800,
                     help="serve: measured requests (after 200 warm-up requests)")
     ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
+    ap.add_argument("--reeval", action="store_true",
+                    help="cells: carry the saturation state with speculative re-evaluation")
     ap.add_argument("--partition", choices=("grid", "kd"), default="grid",
                     help="cells: the 4 x 2 ground grid of the configuration, or KD-tree cells")
     args = ap.parse_args()
@@ -343,12 +345,17 @@ def bench_cells(args):
         frames = [Frame(params, cells, c, st) for c in cams]
         dout = torch.empty((h, w, 4), dtype=torch.float32, device="cuda")
         for f in frames:  # size every cell's instance buffers once, with headroom
-            f.init_masks(geometric=True)
+            f.init_masks(geometric=True, reeval=args.reeval)
             f.forward(use_masks=True, sync=True)
             for v in f.views:
                 v._alloc_sort(int(v.counts[1] * 1.1) + 4096)
         torch.cuda.synchronize()
         t_adam = [0]
+        flips = [0, 0]  # re-activated pairs, pairs pruned before the step (counted step)
+        pop8 = torch.tensor([bin(i).count("1") for i in range(256)], device="cuda")
+
+        def popcount(words):
+            return int(pop8[words.contiguous().view(torch.uint8).long()].sum().item())
 
         def step(count=False):
             for g in grads:
@@ -356,11 +363,15 @@ def bench_cells(args):
                     B.sx_fill_u32(t, 0)
             blends = 0
             for f, tg in zip(frames, targets):
+                before = f.masks.clone() if (count and f.omega is not None) else None
                 f.forward(use_masks=True, update_masks=True, sync=False)
                 B.sx_l1_loss(f.out, tg, w, h, dout, None)
                 f.backward(dout, grads, accumulate=True)
                 if count:
                     blends += sum(int(v.nblend.sum().item()) for v in f.views)
+                    if before is not None:
+                        flips[0] += popcount(f.masks & ~before)
+                        flips[1] += popcount(f.omega & ~before)
             t_adam[0] += 1
             k = 0
             for p, g in zip(params, grads):
@@ -382,8 +393,12 @@ def bench_cells(args):
         ms = e0.elapsed_time(e1) / args.steps
         out[f"{w}x{h}"] = {"ms_per_step": ms, "views_per_s": len(cams) / (ms / 1e3),
                            "blends_per_step": blends, "blends_per_s": blends / (ms / 1e3)}
+        if args.reeval:
+            out[f"{w}x{h}"].update(reactivated=flips[0], pruned_before=flips[1],
+                                   flip_rate=flips[0] / max(flips[1], 1))
         log(f"bench: cells {w}x{h}: {ms:.2f} ms per 8-view step, "
-            f"{len(cams) / (ms / 1e3):.1f} views/s, {blends} blends")
+            f"{len(cams) / (ms / 1e3):.1f} views/s, {blends} blends"
+            + (f", re-activated {flips[0]} of {flips[1]} pruned pairs" if args.reeval else ""))
         del frames
         torch.cuda.empty_cache()
     m = out["1920x1080"]
@@ -395,8 +410,9 @@ def bench_cells(args):
         "config": {"workload": "8M Gaussians SH3 on a 1 km^2 ground plane in K=8 cells "
                                f"({'KD-tree' if args.partition == 'kd' else '4x2 grid'}), "
                                "8 aerial views, fwd + L1 + bwd per view with "
-                               "geometric visibility and temporal saturation masks, one "
-                               "Adam update per step",
+                               "geometric visibility and temporal saturation masks"
+                               + (" re-evaluated every render" if args.reeval else "")
+                               + ", one Adam update per step",
                    "gaussians": int(sum(p.n for p in params)), "cells": len(params),
                    "views": 8},
         "resolutions": out,

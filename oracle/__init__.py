@@ -39,6 +39,7 @@ FLAG_ORDER = 8
 FLAG_CLAMP = 16
 FLAG_VISIBILITY = 32
 FLAG_SATURATION = 64
+FLAG_CROSS = 128
 
 
 def build(force: bool = False) -> str:
@@ -189,10 +190,21 @@ def sort_keys(scene, cam, settings):
     return keys, vals, ranges
 
 
+def _xfilter_args(xfilter):
+    if xfilter is None:
+        return None, None, None
+    return (np.ascontiguousarray(xfilter["xf"], np.uint32),
+            np.ascontiguousarray(xfilter["amb"], np.uint32),
+            np.ascontiguousarray(xfilter["pixbits"], np.uint32).reshape(-1))
+
+
 def render(scene, cam, settings, mode: str = "binned",
-           mask: Optional[np.ndarray] = None, delta_q: float = 0.0) -> dict:
+           mask: Optional[np.ndarray] = None, delta_q: float = 0.0,
+           xfilter: Optional[dict] = None) -> dict:
     """Partial render of one cell (Eq. 3-4).  Returns C [H,W,3], T [H,W],
-    D [H,W], nblend [H,W] (blended pairs) and flags [H,W]."""
+    D [H,W], nblend [H,W] (blended pairs) and flags [H,W].  ``xfilter``
+    (xf, amb from cross_filter; pixbits from pixel_bits) removes
+    cross-boundary Gaussians from the rays it selects."""
     H, W = cam.height, cam.width
     s = _scene64(scene)
     c = _cam(cam)
@@ -201,12 +213,42 @@ def render(scene, cam, settings, mode: str = "binned",
                nblend=np.zeros((H, W), np.int32),
                flags=np.zeros((H, W), np.uint8))
     m = None if mask is None else np.ascontiguousarray(mask.astype(np.uint8))
+    xf, xa, pb = _xfilter_args(xfilter)
     lib().or_render(ctypes.c_int64(scene.n), *[_p(a) for a in s],
                     ctypes.byref(c), ctypes.byref(p),
                     ctypes.c_int(0 if mode == "brute" else 1), _p(m),
                     _p(out["C"]), _p(out["T"]), _p(out["D"]),
-                    _p(out["nblend"]), _p(out["flags"]))
+                    _p(out["nblend"]), _p(out["flags"]), _p(xf), _p(xa), _p(pb))
     return out
+
+
+def cross_filter(scene, cam, settings, cells, cell: int) -> dict:
+    """Cross-boundary filter bits of the Gaussians of cell ``cell`` for one
+    view (appendix, implementation details: cross-boundary Gaussians): bit s
+    of xf[i] when Gaussian i is visible, its 3-sigma support box meets box s
+    and its depth lies in the overlap of the camera-z ranges of the two
+    boxes; amb[i] marks decisions within rounding reach."""
+    K = len(cells)
+    lo, hi = _cells_lohi(cells)
+    s = _scene64(scene)
+    out = dict(xf=np.zeros(scene.n, np.uint32), amb=np.zeros(scene.n, np.uint32))
+    lib().or_cross_filter(ctypes.c_int64(scene.n), *[_p(a) for a in s],
+                          ctypes.byref(_cam(cam)),
+                          ctypes.byref(_params(settings, _sh_degree(scene))),
+                          ctypes.c_int(K), _p(lo), _p(hi), ctypes.c_int(cell),
+                          _p(out["xf"]), _p(out["amb"]))
+    return out
+
+
+def pixel_bits(vis: np.ndarray, cell: int) -> np.ndarray:
+    """Per pixel, the cells whose box its ray meets (bit s = vis[s]), zero
+    where the ray misses cell ``cell``'s own box: the pixel region of the
+    cross-boundary filter, where both visibility maps cover the pixel."""
+    K = vis.shape[0]
+    bits = np.zeros(vis.shape[1:], np.uint32)
+    for s in range(K):
+        bits |= vis[s].astype(np.uint32) << np.uint32(s)
+    return np.where(vis[cell] != 0, bits, np.uint32(0)).astype(np.uint32)
 
 
 def _cells_lohi(cells):
@@ -346,7 +388,7 @@ def composite_backward(Cparts, Tparts, order, cam, settings, drgb,
 
 
 def render_backward(scene, cam, settings, dC=None, dT=None, dD=None,
-                    mask=None) -> dict:
+                    mask=None, xfilter=None) -> dict:
     """Gradients of one cell's partial render with respect to the screen
     quantities (g2d [n,10]: mean2d x/y, conic a/b/c, opacity, rgb, depth) and
     the raw parameters (means, log_scales, quats, opacity_logits, sh)."""
@@ -360,12 +402,13 @@ def render_backward(scene, cam, settings, dC=None, dT=None, dD=None,
     def arr(a):
         return None if a is None else np.ascontiguousarray(np.asarray(a, np.float64))
     m = None if mask is None else np.ascontiguousarray(mask.astype(np.uint8))
+    xf, _, pb = _xfilter_args(xfilter)
     lib().or_render_backward(
         ctypes.c_int64(n), *[_p(a) for a in s], ctypes.byref(_cam(cam)),
         ctypes.byref(_params(settings, _sh_degree(scene))), _p(m),
         _p(arr(dC)), _p(arr(dT)), _p(arr(dD)), _p(out["g2d"]),
         _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]),
-        _p(out["opacity_logits"]), _p(out["sh"]))
+        _p(out["opacity_logits"]), _p(out["sh"]), _p(xf), _p(pb))
     return out
 
 
@@ -381,13 +424,27 @@ class Frame:
     Tparts: np.ndarray
 
 
+def cross_filters(cell_scenes: Sequence, cells, cam, settings) -> List[dict]:
+    """The cross-boundary filter of every cell's render for one view, with
+    the pixel regions taken from the geometric visibility maps."""
+    vis = visibility(cells, cam)["vis"]
+    out = []
+    for k, sc in enumerate(cell_scenes):
+        f = cross_filter(sc, cam, settings, cells, k)
+        f["pixbits"] = pixel_bits(vis, k)
+        out.append(f)
+    return out
+
+
 def forward(cell_scenes: Sequence, cells, cam, settings,
             masks: Optional[np.ndarray] = None, same_frame_cull=False,
-            delta_q: float = 0.0) -> Frame:
+            delta_q: float = 0.0, xfilters: Optional[List[dict]] = None) -> Frame:
     """Render every cell (Eq. 3-4) and compose them (Eq. 5).  ``masks``
-    [K,H,W] (1 = active) restricts each cell's render."""
+    [K,H,W] (1 = active) restricts each cell's render; ``xfilters`` (from
+    cross_filters) removes cross-boundary Gaussians per ray."""
     parts = [render(sc, cam, settings, "binned",
-                    None if masks is None else masks[k], delta_q)
+                    None if masks is None else masks[k], delta_q,
+                    None if xfilters is None else xfilters[k])
              for k, sc in enumerate(cell_scenes)]
     Cp = np.stack([p["C"] for p in parts])
     Tp = np.stack([p["T"] for p in parts])
@@ -396,14 +453,15 @@ def forward(cell_scenes: Sequence, cells, cam, settings,
 
 
 def backward(cell_scenes, cells, cam, settings, frame: Frame, drgb, dT=None,
-             masks=None, same_frame_cull=False) -> List[dict]:
+             masks=None, same_frame_cull=False, xfilters=None) -> List[dict]:
     """Gradients for every cell's Gaussians through the composition (Eq. 6-7)
     and each cell's local render."""
     dC, dTp = composite_backward(frame.Cparts, frame.Tparts,
                                  frame.comp["order"], cam, settings, drgb, dT,
                                  frame.comp["mask"], same_frame_cull)
     return [render_backward(sc, cam, settings, dC[k], dTp[k], None,
-                            None if masks is None else masks[k])
+                            None if masks is None else masks[k],
+                            None if xfilters is None else xfilters[k])
             for k, sc in enumerate(cell_scenes)]
 
 

@@ -429,6 +429,18 @@ enum : uint8_t {
   FLAG_VISIBILITY = 32,  // a cell box's geometric visibility within rounding of flipping
   FLAG_SATURATION = 64,  // a saturation or re-activation test within 1e-3 relative
                          // of its threshold
+  FLAG_CROSS = 128,      // a cross-boundary filter decision within rounding reach
+};
+
+// Per-ray cross-boundary filter of one cell's render (appendix,
+// implementation details: cross-boundary Gaussians): pair (g, pixel) is
+// dropped when xf[g] & pbits != 0, pbits being the cells whose box the
+// pixel's ray meets (zero where it misses the rendering cell's own box);
+// xamb[g] marks the bits whose decision is within rounding reach.
+struct XFilter {
+  const uint32_t* xf;
+  const uint32_t* xamb;
+  uint32_t pbits;
 };
 
 struct Blend {  // one blended pair on a pixel's ray
@@ -456,7 +468,7 @@ template <class List>
 static void walk_pixel(const std::vector<Proj>& pr, const List& list, int px,
                        int py, const Cam& cam, const Params& P, double C[3],
                        double* Tout, double* Dout, int* nblend, uint8_t* flags,
-                       std::vector<Blend>* blends) {
+                       std::vector<Blend>* blends, const XFilter* xfil = nullptr) {
   double T = 1.0, D = 0.0;
   C[0] = C[1] = C[2] = 0.0;
   int nb = 0;
@@ -482,6 +494,10 @@ static void walk_pixel(const std::vector<Proj>& pr, const List& list, int px,
     const bool clamped = araw > P.alpha_max;
     const double alpha = clamped ? P.alpha_max : araw;
     if (alpha < P.alpha_min) continue;
+    if (xfil) {
+      if (xfil->xamb[g] & xfil->pbits) fl |= FLAG_CROSS;
+      if (xfil->xf[g] & xfil->pbits) continue;  // removed from this ray
+    }
     if (std::fabs(araw - P.alpha_max) <= 1e-6 * P.alpha_max) fl |= FLAG_CLAMP;
     if (depth_round_ambiguous(p.depth, p.zerr)) fl |= FLAG_DEPTH_ROUND;
     if (blends) blends->push_back({g, alpha, gval, T, dx, dy, clamped});
@@ -632,7 +648,8 @@ int or_render(int64_t n, const double* means, const double* log_scales,
               const double* quats, const double* logits, const double* sh,
               const Cam* cam, const Params* P, int mode, const uint8_t* mask,
               double* C, double* T, double* D, int32_t* nblend,
-              uint8_t* flags) {
+              uint8_t* flags, const uint32_t* xf, const uint32_t* xamb,
+              const uint32_t* pixbits) {
   SceneIn s{n, means, log_scales, quats, logits, sh};
   std::vector<Proj> pr = preprocess_all(s, *cam, *P);
   const int W = cam->width, H = cam->height;
@@ -649,8 +666,9 @@ int or_render(int64_t n, const double* means, const double* log_scales,
           nblend[p] = 0;
           continue;
         }
+        const XFilter xfl{xf, xamb, pixbits ? pixbits[p] : 0u};
         walk_pixel(pr, all, px, py, *cam, *P, C + p * 3, T + p, D + p,
-                   nblend + p, flags + p, nullptr);
+                   nblend + p, flags + p, nullptr, xf ? &xfl : nullptr);
       }
   } else {
     Bins b = make_bins(pr, *cam, *P);
@@ -666,8 +684,9 @@ int or_render(int64_t n, const double* means, const double* log_scales,
           continue;
         }
         const auto& list = b.lists[(size_t)(py / P->tile_h) * b.tiles_x + px / P->tile_w];
+        const XFilter xfl{xf, xamb, pixbits ? pixbits[p] : 0u};
         walk_pixel(pr, list, px, py, *cam, *P, C + p * 3, T + p, D + p,
-                   nblend + p, flags + p, nullptr);
+                   nblend + p, flags + p, nullptr, xf ? &xfl : nullptr);
       }
   }
   return 0;
@@ -876,7 +895,8 @@ int or_render_backward(int64_t n, const double* means, const double* log_scales,
                        const Cam* cam, const Params* P, const uint8_t* mask,
                        const double* dC, const double* dT, const double* dD,
                        double* g2d, double* gmeans, double* glog_scales,
-                       double* gquats, double* glogits, double* gsh) {
+                       double* gquats, double* glogits, double* gsh,
+                       const uint32_t* xf, const uint32_t* pixbits) {
   SceneIn s{n, means, log_scales, quats, logits, sh};
   std::vector<Proj> pr = preprocess_all(s, *cam, *P);
   Bins b = make_bins(pr, *cam, *P);
@@ -895,7 +915,8 @@ int or_render_backward(int64_t n, const double* means, const double* log_scales,
         int nb;
         uint8_t fl = 0;
         const auto& list = b.lists[(size_t)(py / P->tile_h) * b.tiles_x + px / P->tile_w];
-        walk_pixel(pr, list, px, py, *cam, *P, C, &T, &D, &nb, &fl, &bl);
+        const XFilter xfl{xf, xf, pixbits ? pixbits[p] : 0u};  // flags unused here
+        walk_pixel(pr, list, px, py, *cam, *P, C, &T, &D, &nb, &fl, &bl, xf ? &xfl : nullptr);
         const double G[3] = {dC ? dC[p * 3] : 0.0, dC ? dC[p * 3 + 1] : 0.0,
                              dC ? dC[p * 3 + 2] : 0.0};
         const double gT = dT ? dT[p] : 0.0, gD = dD ? dD[p] : 0.0;
@@ -1077,6 +1098,83 @@ int or_render_backward(int64_t n, const double* means, const double* log_scales,
 // (1 = the pixel's centre ray meets the part of the box inside the
 // frustum); flags [H*W] gets FLAG_VISIBILITY where a decision lies within
 // 1e-9 relative of flipping.
+// Cross-boundary filter bits of one cell's Gaussians for a view (appendix,
+// implementation details: cross-boundary Gaussians).  Readings: a
+// Gaussian's spatial support is the axis-aligned box of its 3-sigma extent,
+// mean +- 3 sqrt(Sigma_aa); its support spans cell s when that box meets
+// box s (strict inequalities); its depth is the camera z of its mean; the
+// overlapped depth interval of cells k and s is the intersection of the
+// camera-z ranges of the two boxes (a box unbounded along an axis the depth
+// varies on has an unbounded range).  Bit s of xf[i] (s != cell) is set when
+// Gaussian i is visible in the view, its support spans cell s and its depth
+// lies in the overlapped interval of (cell, s).  xamb[i] marks the bits
+// whose comparisons lie within 1e-5 relative of flipping.
+int or_cross_filter(int64_t n, const double* means, const double* log_scales,
+                    const double* quats, const double* logits, const double* sh,
+                    const Cam* cam, const Params* P, int K, const double* lo,
+                    const double* hi, int cell, uint32_t* xf, uint32_t* xamb) {
+  SceneIn s{n, means, log_scales, quats, logits, sh};
+  std::vector<Proj> pr = preprocess_all(s, *cam, *P);
+  // camera-z range of every box: z = R[2] . x + t[2], linear over the box
+  std::vector<double> zlo(K), zhi(K);
+  for (int m = 0; m < K; ++m) {
+    double a = cam->t[2], b = cam->t[2];
+    for (int j = 0; j < 3; ++j) {
+      const double r = cam->R[6 + j];
+      if (r == 0.0) continue;
+      const double u = r * lo[m * 3 + j], v = r * hi[m * 3 + j];
+      a += std::min(u, v);
+      b += std::max(u, v);
+    }
+    zlo[m] = a, zhi[m] = b;
+  }
+  // x < y decided, and whether it is within rounding reach
+  auto near = [](double x, double y, double scale) {
+    return std::isfinite(y) && std::fabs(x - y) <= 1e-5 * scale;
+  };
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    xf[i] = xamb[i] = 0;
+    if (!pr[i].valid) continue;
+    double q[4];
+    double qn = 0.0;
+    for (int k = 0; k < 4; ++k) qn += quats[i * 4 + k] * quats[i * 4 + k];
+    qn = std::sqrt(qn);
+    for (int k = 0; k < 4; ++k) q[k] = quats[i * 4 + k] / qn;
+    double Rq[9];
+    quat_to_rot(q, Rq);
+    double h[3];
+    for (int a = 0; a < 3; ++a) {
+      double v = 0.0;
+      for (int b = 0; b < 3; ++b) {
+        const double e = Rq[a * 3 + b] * std::exp(log_scales[i * 3 + b]);
+        v += e * e;
+      }
+      h[a] = 3.0 * std::sqrt(v);
+    }
+    const double* mu = means + i * 3;
+    const double d = pr[i].depth;
+    for (int sc = 0; sc < K; ++sc) {
+      if (sc == cell) continue;
+      bool meets = true, amb = false;
+      for (int a = 0; a < 3; ++a) {
+        const double l = mu[a] - h[a], r = mu[a] + h[a];
+        const double scale = std::fabs(mu[a]) + h[a];
+        meets = meets && l < hi[sc * 3 + a] && r > lo[sc * 3 + a];
+        amb = amb || near(l, hi[sc * 3 + a], scale + std::fabs(hi[sc * 3 + a])) ||
+              near(r, lo[sc * 3 + a], scale + std::fabs(lo[sc * 3 + a]));
+      }
+      const double Dlo = std::max(zlo[cell], zlo[sc]), Dhi = std::min(zhi[cell], zhi[sc]);
+      const bool in = d >= Dlo && d <= Dhi;
+      amb = amb || near(d, Dlo, std::fabs(d) + std::fabs(Dlo)) ||
+            near(d, Dhi, std::fabs(d) + std::fabs(Dhi));
+      if (meets && in) xf[i] |= 1u << sc;
+      if (amb) xamb[i] |= 1u << sc;
+    }
+  }
+  return 0;
+}
+
 int or_visibility(int K, const double* lo, const double* hi, const Cam* cam, uint8_t* vis,
                   uint8_t* flags) {
   const int W = cam->width, H = cam->height;

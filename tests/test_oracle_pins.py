@@ -607,6 +607,133 @@ def test_reeval_reduces_to_composite_and_is_stable(orc):
             assert bool(r3["mask"][first, py, px]) == (R >= np.float32(ST.t_min))
 
 
+def _scene_of(means, scales, opac=0.8):
+    n = len(means)
+    sh = np.zeros((n, 1, 3), np.float32)
+    sh[:, 0, :] = 1.0
+    return synth.Scene(np.asarray(means, np.float32),
+                       np.log(np.asarray(scales, np.float32))[:, None].repeat(3, 1),
+                       np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)),
+                       np.full(n, math.log(opac / (1 - opac)), np.float32), sh)
+
+
+def test_cross_filter_hand_cases(orc):
+    """Cross-boundary filter bits (appendix, cross-boundary Gaussians) worked
+    out by hand: two cells split at x = 0, camera looking +z from z = -3
+    (camera depth = world z + 3).  An isotropic Gaussian spans the other
+    cell when its mean lies within 3 sigma of the plane; with boxes
+    unbounded in z every depth is in the overlapped interval, with boxes
+    z in [-1, 1] and [0.5, 3] (depths [2, 4] and [3.5, 6]) only depths in
+    [3.5, 4] are."""
+    cam = synth.camera_from_rows(np.eye(3), (-0.5, 0.0, -3.0), 48, 32, 40.0)
+    inf = math.inf
+    open_cells = [synth.Cell((-inf, -inf, -inf), (0.0, inf, inf)),
+                  synth.Cell((0.0, -inf, -inf), (inf, inf, inf))]
+    # cell 0: A spans (0.3 > 0.1), B does not (0.15 < 0.6); cell 1: C spans
+    sc0 = _scene_of([(-0.1, 0.0, 0.0), (-0.6, 0.2, 0.0)], [0.1, 0.05])
+    sc1 = _scene_of([(0.05, -0.2, 0.5)], [0.05])
+    st = synth.RenderSettings(fov_guard=0.0)
+    f0 = orc.cross_filter(sc0, cam, st, open_cells, 0)
+    f1 = orc.cross_filter(sc1, cam, st, open_cells, 1)
+    assert list(f0["xf"]) == [0b10, 0] and list(f1["xf"]) == [0b01]
+    assert not f0["amb"].any() and not f1["amb"].any()
+    boxed = [synth.Cell((-inf, -inf, -1.0), (0.0, inf, 1.0)),
+             synth.Cell((0.0, -inf, 0.5), (inf, inf, 3.0))]
+    # depths 3 (out), 3.8 (in), 4.5 (out: beyond cell 0's range)
+    sc = _scene_of([(-0.1, 0.0, 0.0), (-0.1, 0.0, 0.8), (-0.1, 0.0, 1.5)], [0.1, 0.1, 0.1])
+    f = orc.cross_filter(sc, cam, st, boxed, 0)
+    assert list(f["xf"]) == [0, 0b10, 0]
+    # a culled Gaussian (behind the camera) carries no bits
+    f = orc.cross_filter(_scene_of([(-0.1, 0.0, -5.0)], [0.1]), cam, st, open_cells, 0)
+    assert list(f["xf"]) == [0]
+
+
+def test_cross_filter_render_drops_exactly_the_pair(orc):
+    """The pixel region of the filter is where both cells' visibility maps
+    cover the pixel: from a camera at x = -0.5, the rays that reach x >= 0
+    are those heading to +x (pixel centre right of cx).  There the filtered
+    render of cell 0 equals the render without the spanning Gaussian; on
+    the other pixels it equals the unfiltered render (bit for bit)."""
+    cam = synth.camera_from_rows(np.eye(3), (-0.5, 0.0, -3.0), 48, 32, 40.0)
+    inf = math.inf
+    cells = [synth.Cell((-inf, -inf, -inf), (0.0, inf, inf)),
+             synth.Cell((0.0, -inf, -inf), (inf, inf, inf))]
+    sc0 = _scene_of([(-0.1, 0.0, 0.0), (-0.6, 0.2, 0.0), (-0.4, -0.1, 0.3)],
+                    [0.1, 0.05, 0.08])
+    st = synth.RenderSettings(fov_guard=0.0)
+    vis = orc.visibility(cells, cam)
+    assert not vis["flags"].any()
+    pb = orc.pixel_bits(vis["vis"], 0)
+    px = np.arange(cam.width) + 0.5
+    right = np.broadcast_to(px > cam.cx, (cam.height, cam.width))
+    assert np.array_equal(pb, np.where(right, 3, 1).astype(np.uint32))
+    f = orc.cross_filter(sc0, cam, st, cells, 0)
+    assert list(f["xf"]) == [0b10, 0, 0]
+    f["pixbits"] = pb
+    filt = orc.render(sc0, cam, st, xfilter=f)
+    plain = orc.render(sc0, cam, st)
+    without = orc.render(sc0.subset(np.array([1, 2])), cam, st)
+    assert not filt["flags"].any()
+    for key in ("C", "T", "D"):
+        np.testing.assert_array_equal(filt[key][right], without[key][right])
+        np.testing.assert_array_equal(filt[key][~right], plain[key][~right])
+    assert (plain["nblend"] - filt["nblend"])[right].sum() > 20
+
+
+def test_backward_with_cross_filter_matches_finite_differences(orc):
+    """Eq. 6-7 through two cells split at x = 0 with the cross-boundary
+    filter on (held fixed, as the gradient treats it): Gaussians near the
+    plane are removed from the rays where both cells are visible, and the
+    gradients of the remaining pairs match central differences."""
+    cam = synth.camera_from_rows(np.eye(3), (-0.3, 0.0, -3.0), 64, 64,
+                                 32.0 / math.tan(math.radians(30.0)))
+    inf = math.inf
+    cells = [synth.Cell((-inf, -inf, -inf), (0.0, inf, inf)),
+             synth.Cell((0.0, -inf, -inf), (inf, inf, inf))]
+    for seed in range(300, 340):
+        sc = synth.fd_scene(seed).astype(np.float64)
+        left = np.nonzero(sc.means[:, 0] < 0)[0]
+        right = np.nonzero(sc.means[:, 0] >= 0)[0]
+        scenes = [sc.subset(left), sc.subset(right)]
+        xfs = orc.cross_filters(scenes, cells, cam, ST)
+        fr = orc.forward(scenes, cells, cam, ST, delta_q=1e-3, xfilters=xfs)
+        fl = np.bitwise_or.reduce([p["flags"] for p in fr.parts]) | fr.comp["flags"]
+        if not fl.any() and sum(int((x["xf"] != 0).sum()) for x in xfs) >= 4:
+            break
+    else:
+        raise AssertionError("no flag-free scene with cross-boundary Gaussians")
+    rng = np.random.default_rng(5)
+    wr = rng.normal(size=(cam.height, cam.width, 3))
+    wt = rng.normal(size=(cam.height, cam.width))
+    fr = orc.forward(scenes, cells, cam, ST, xfilters=xfs)
+    grads = orc.backward(scenes, cells, cam, ST, fr, wr, wt, xfilters=xfs)
+    unf = orc.forward(scenes, cells, cam, ST)
+    assert np.abs(unf.comp["rgb"] - fr.comp["rgb"]).max() > 1e-3  # the filter acts
+
+    def loss():
+        f = orc.forward(scenes, cells, cam, ST, xfilters=xfs)
+        return float((f.comp["rgb"] * wr).sum() + (f.comp["T"] * wt).sum())
+
+    for k, cs in enumerate(scenes):
+        for name in ("means", "opacity_logits", "sh"):
+            flat = getattr(cs, name).reshape(-1)
+            g = grads[k][name].reshape(-1)
+            idx = np.sort(rng.choice(flat.size, min(flat.size, 40), replace=False))
+            fd = np.zeros(len(idx))
+            for j, i in enumerate(idx):
+                h = 1e-6 * max(1.0, abs(flat[i]))
+                old = flat[i]
+                flat[i] = old + h
+                lp = loss()
+                flat[i] = old - h
+                lm = loss()
+                flat[i] = old
+                fd[j] = (lp - lm) / (2 * h)
+            scale = max(np.abs(fd).max(), 1e-12)
+            err = np.abs(g[idx] - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
+            assert err.max() <= 1e-3, (k, name, err.max())
+
+
 # ------------------------------------------------------------ Eq. 6-7 -----
 def _flag_free_fd_scene(orc, seed0, cam, cells_fn):
     for seed in range(seed0, seed0 + 40):
