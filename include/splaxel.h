@@ -111,6 +111,17 @@ typedef struct sx_projected {
   uint16_t* rect;
   uint32_t* n_tiles;
   uint32_t* block_sums;
+  /* optional per-ray cross-boundary filter of this cell's render and its
+   * backward (sx_cross_filter); xf NULL = off.  Only sx_render_partial,
+   * sx_render_backward(_stages) and sx_backward apply it; the batched
+   * multi-view calls reject it.
+   *   xf       [n] filter bits written by sx_cross_filter
+   *   omega    the K geometric maps of the view (sx_visibility layout)
+   *   cell     this cell's index in 0..n_cells-1
+   *   n_cells  K, 1..16 */
+  const uint32_t* xf;
+  const uint32_t* omega;
+  int32_t cell, n_cells;
 } sx_projected;
 
 /* Axis-aligned convex cell (one GPU's partition); bounds may be +-inf. */
@@ -222,6 +233,25 @@ sx_status sx_kd_partition(int64_t n, const float* means, int32_t K, sx_cell* cel
  * of K boxes (bounds may be infinite), K in 1..16. */
 sx_status sx_visibility(int32_t K, const sx_cell* cells, const sx_camera* cam,
                         uint32_t* masks, sx_stream stream);
+
+/* Per-ray cross-boundary filter (appendix, implementation details:
+ * cross-boundary Gaussians).  A Gaussian assigned to cell k by its mean
+ * whose spatial support reaches into cell s is removed from the ray of
+ * pixel p when its depth lies in the overlapped depth interval of k and s
+ * and p lies in both cells' visibility maps, so that the composition of
+ * the two partials does not interleave their Gaussians.  Readings: support
+ * = the axis-aligned box mean +- 3 sqrt(Sigma_aa); depth = camera z of the
+ * mean (the record's depth); overlapped interval = intersection of the
+ * camera-z ranges of the two boxes.
+ * Writes xf[i] (device, [n]): bit s set when Gaussian i is visible in the
+ * view (n_tiles > 0 after sx_preprocess), s != cell, its support box meets
+ * box s and its depth is in the interval of (cell, s).  proj must hold the
+ * preprocess output of this view; cells: HOST array of K boxes (K in
+ * 1..16), cell in 0..K-1.  To apply the filter, set proj->xf, omega, cell
+ * and n_cells for the render and backward calls. */
+sx_status sx_cross_filter(const sx_gaussians* g, const sx_projected* proj, int32_t K,
+                          const sx_cell* cells, int32_t cell, const sx_camera* cam,
+                          uint32_t* xf, sx_stream stream);
 
 /* ------------------------------------------------------------------ a6 --
  * Composition of K partial buffers (Eq. 5).  Per pixel the cells are

@@ -50,7 +50,8 @@ class SxGaussians(ctypes.Structure):
 
 class SxProjected(ctypes.Structure):
     _fields_ = [("rec", c_p), ("rect", c_p), ("n_tiles", c_p),
-                ("block_sums", c_p)]
+                ("block_sums", c_p), ("xf", c_p), ("omega", c_p),
+                ("cell", ctypes.c_int32), ("n_cells", ctypes.c_int32)]
 
 
 class SxCell(ctypes.Structure):
@@ -89,7 +90,7 @@ EXPORTS = (
     "sx_adam", "sx_fill_u32", "sx_preprocess_multi", "sx_multi_workspace_size",
     "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
     "sx_render_backward_stages", "sx_visibility", "sx_kd_partition",
-    "sx_composite_reeval",
+    "sx_composite_reeval", "sx_cross_filter",
 )
 
 _lib = None
@@ -282,6 +283,22 @@ def sx_composite_reeval(partials: Sequence[torch.Tensor], cells, cam: SxCamera,
         c_i32(len(partials)), ptr_array(partials), cells_array(cells),
         ctypes.byref(cam), ctypes.byref(p), ptr(out), ptr(masks), ptr(omega),
         ptr(budget), stream_handle(stream)))
+
+
+def sx_cross_filter(g: "SxGaussians", proj: SxProjected, cells, cell: int, cam: SxCamera,
+                    xf, stream=None) -> None:
+    _check("sx_cross_filter", lib().sx_cross_filter(
+        ctypes.byref(g), ctypes.byref(proj), c_i32(len(cells)), cells_array(cells),
+        c_i32(cell), ctypes.byref(cam), ptr(xf), stream_handle(stream)))
+
+
+def set_cross_filter(proj: SxProjected, xf, omega, cell: int, n_cells: int) -> None:
+    """Turn the per-ray cross-boundary filter of a projection on (xf None:
+    off) for the render and backward calls that take it."""
+    proj.xf = None if xf is None else ptr(xf)
+    proj.omega = None if xf is None else ptr(omega)
+    proj.cell = int(cell) if xf is not None else 0
+    proj.n_cells = int(n_cells) if xf is not None else 0
 
 
 def sx_l1_loss(out, target, width: int, height: int, dout, loss_sum,

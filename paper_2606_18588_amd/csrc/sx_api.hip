@@ -163,6 +163,16 @@ sx_status sx_sort_counts(const void* ws, int64_t n, uint64_t* h_out, sx_stream s
   return dev(e, "sx_sort_counts");
 }
 
+// The optional cross-boundary filter fields of a projection.
+static sx_status check_filter(const sx_projected* proj) {
+  if (!proj->xf) return SX_OK;
+  if (!proj->omega) return fail(SX_EINVAL, "cross-boundary filter without visibility maps");
+  if (proj->n_cells < 1 || proj->n_cells > sx::kMaxCells || proj->cell < 0 ||
+      proj->cell >= proj->n_cells)
+    return fail(SX_EINVAL, "cross-boundary filter: cell %d of %d", proj->cell, proj->n_cells);
+  return SX_OK;
+}
+
 sx_status sx_render_partial(const sx_projected* proj, const uint32_t* vals,
                             const uint32_t* tile_ranges, const sx_camera* cam,
                             const sx_params* p, const uint32_t* mask,
@@ -172,6 +182,7 @@ sx_status sx_render_partial(const sx_projected* proj, const uint32_t* vals,
   SX_TRY(check_params(p));
   if (!proj || !proj->rec || !tile_ranges || !partial || !last)
     return fail(SX_EINVAL, "null argument");
+  SX_TRY(check_filter(proj));
   return dev(sx::launch_render(*proj, vals, tile_ranges, sx::make_dcam(*cam),
                                sx::make_kparams(*p, *cam), mask, partial, depth, last, nblend,
                                (hipStream_t)stream),
@@ -212,6 +223,24 @@ sx_status sx_visibility(int32_t K, const sx_cell* cells, const sx_camera* cam, u
       if (!(cells[m].lo[j] <= cells[m].hi[j])) return fail(SX_EINVAL, "cell %d: lo > hi or NaN", m);
   return dev(sx::launch_visibility(K, cells, sx::make_dcam(*cam), masks, (hipStream_t)stream),
              "sx_visibility");
+}
+
+sx_status sx_cross_filter(const sx_gaussians* g, const sx_projected* proj, int32_t K,
+                          const sx_cell* cells, int32_t cell, const sx_camera* cam,
+                          uint32_t* xf, sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  if (!g || !proj || !cells || !xf) return fail(SX_EINVAL, "null argument");
+  if (g->n < 0 || g->n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "n out of range");
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !proj->rec || !proj->n_tiles))
+    return fail(SX_EINVAL, "null argument");
+  if (K < 1 || K > sx::kMaxCells) return fail(SX_EINVAL, "K=%d outside 1..%d", K, sx::kMaxCells);
+  if (cell < 0 || cell >= K) return fail(SX_EINVAL, "cell %d outside 0..%d", cell, K - 1);
+  for (int m = 0; m < K; ++m)
+    for (int j = 0; j < 3; ++j)
+      if (!(cells[m].lo[j] <= cells[m].hi[j])) return fail(SX_EINVAL, "cell %d: lo > hi or NaN", m);
+  return dev(sx::launch_cross_filter(*g, *proj, K, cells, cell, sx::make_dcam(*cam), xf,
+                                     (hipStream_t)stream),
+             "sx_cross_filter");
 }
 
 sx_status sx_composite(int32_t K, const float* const* partials,
@@ -293,6 +322,7 @@ sx_status sx_render_backward_stages(const sx_projected* proj, const uint32_t* va
     return fail(SX_EINVAL, "null argument");
   if (n < 0 || capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "bad n/capacity");
   if (stages & ~SX_RB_ALL) return fail(SX_EINVAL, "unknown stage bits 0x%x", stages);
+  SX_TRY(check_filter(proj));
   const sx::KParams kp = sx::make_kparams(*p, *cam);
   return dev(sx::launch_render_backward(*proj, vals, tile_ranges, sx::sort_view(sort_ws, n, capacity, kp.tiles_x, kp.tiles_y),
                                         n, capacity, sx::make_dcam(*cam), kp, mask,
@@ -377,6 +407,7 @@ static sx_status check_views(int32_t V, const sx_view* views, const sx_params* p
     if (w.capacity < 0 || w.capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "view %d: bad capacity", v);
     if (backward && (!w.proj.rect || !w.proj.n_tiles || !w.sort_ws || !w.dpartial || !w.g2d || !w.bwd_ws))
       return fail(SX_EINVAL, "view %d: null backward buffer", v);
+    if (w.proj.xf) return fail(SX_EINVAL, "view %d: the batched renders apply no cross-boundary filter", v);
   }
   return SX_OK;
 }

@@ -311,6 +311,9 @@ hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams&
 void kd_partition(int64_t n, const float* means, int K, float* lo, float* hi, int32_t* cell_of);
 hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint32_t* masks,
                              hipStream_t st);
+hipError_t launch_cross_filter(const sx_gaussians& g, const sx_projected& proj, int K,
+                               const sx_cell* cells, int cell, const DCam& cam, uint32_t* xf,
+                               hipStream_t st);
 // budget non-NULL selects the re-evaluating form (masks then required)
 hipError_t launch_composite(int K, const float* const* partials,
                             const sx_cell* cells, const DCam& cam,

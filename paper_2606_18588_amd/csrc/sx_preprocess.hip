@@ -667,3 +667,100 @@ hipError_t launch_preprocess_backward_multi(const sx_gaussians& g, int V, const 
 }
 
 }  // namespace sx
+
+namespace sx {
+
+// ------------------------------------------------- cross-boundary filter --
+// Bits of the per-ray cross-boundary filter of one cell's Gaussians for one
+// view (appendix, implementation details: cross-boundary Gaussians).  Bit s
+// of xf[i] is set when Gaussian i is visible, its 3-sigma support box,
+// mean +- 3 sqrt(Sigma_aa), meets box s (s != cell) and its camera depth
+// lies in [dlo[s], dhi[s]], the overlap of the camera-z ranges of box s and
+// of the cell's own box (computed on the host).  The render removes the
+// Gaussian from the rays whose pixel lies in the visibility maps of both.
+struct XFArgs {
+  const float* __restrict__ means;
+  const float* __restrict__ log_scales;
+  const float4* __restrict__ quats;
+  const float* __restrict__ rec;
+  const uint32_t* __restrict__ n_tiles;
+  int64_t n;
+  int K, cell;
+  float lo[kMaxCells][3], hi[kMaxCells][3];
+  float dlo[kMaxCells], dhi[kMaxCells];
+  uint32_t* __restrict__ xf;
+};
+
+__global__ __launch_bounds__(256) void k_cross_filter(XFArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  uint32_t bits = 0;
+  if (a.n_tiles[i] != 0) {
+    const float4 q4 = a.quats[i];
+    const float qn = sqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
+    const float w = q4.x / qn, x = q4.y / qn, y = q4.z / qn, z = q4.w / qn;
+    const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                        2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                        2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+    float s[3], mu[3], h[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) s[b] = expf(a.log_scales[3 * i + b]), mu[b] = a.means[3 * i + b];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      float v = 0.f;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const float e = R[3 * r + b] * s[b];
+        v = fmaf(e, e, v);
+      }
+      h[r] = 3.f * sqrtf(v);
+    }
+    const float d = a.rec[(size_t)i * kRecFloats + 9];
+    for (int c = 0; c < a.K; ++c) {
+      if (c == a.cell) continue;
+      bool meets = d >= a.dlo[c] && d <= a.dhi[c];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        meets = meets && mu[r] - h[r] < a.hi[c][r] && mu[r] + h[r] > a.lo[c][r];
+      bits |= meets ? 1u << c : 0u;
+    }
+  }
+  a.xf[i] = bits;
+}
+
+hipError_t launch_cross_filter(const sx_gaussians& g, const sx_projected& proj, int K,
+                               const sx_cell* cells, int cell, const DCam& cam, uint32_t* xf,
+                               hipStream_t st) {
+  XFArgs a;
+  a.means = g.means;
+  a.log_scales = g.log_scales;
+  a.quats = reinterpret_cast<const float4*>(g.quats);
+  a.rec = proj.rec;
+  a.n_tiles = proj.n_tiles;
+  a.n = g.n;
+  a.K = K, a.cell = cell;
+  // camera-z range of each box: z = R[2] . x + t[2] is linear over the box
+  double zlo[kMaxCells], zhi[kMaxCells];
+  for (int m = 0; m < K; ++m) {
+    double lo = cam.t[2], hi = cam.t[2];
+    for (int j = 0; j < 3; ++j) {
+      a.lo[m][j] = cells[m].lo[j], a.hi[m][j] = cells[m].hi[j];
+      const double r = cam.R[6 + j];
+      if (r == 0.0) continue;
+      const double u = r * (double)cells[m].lo[j], v = r * (double)cells[m].hi[j];
+      lo += u < v ? u : v;
+      hi += u < v ? v : u;
+    }
+    zlo[m] = lo, zhi[m] = hi;
+  }
+  for (int m = 0; m < K; ++m) {
+    a.dlo[m] = (float)(zlo[m] > zlo[cell] ? zlo[m] : zlo[cell]);
+    a.dhi[m] = (float)(zhi[m] < zhi[cell] ? zhi[m] : zhi[cell]);
+  }
+  a.xf = xf;
+  if (g.n > 0)
+    hipLaunchKernelGGL(k_cross_filter, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace sx

@@ -25,7 +25,24 @@ struct RenderArgs {
   float* __restrict__ depth;
   uint32_t* __restrict__ last;
   uint32_t* __restrict__ nblend;
+  // cross-boundary filter (FILT): bits per Gaussian, the K geometric maps
+  const uint32_t* __restrict__ xf;
+  const uint32_t* __restrict__ omega;
+  uint32_t words;
+  int cell, ncells;
 };
+
+// The cells whose box the ray of pixel `pix` meets (bit s from map s), or
+// none when it misses the rendering cell's own box: a pair (g, pix) is
+// removed from the ray when xf[g] shares a bit with this set.
+__device__ __forceinline__ uint32_t filter_bits(const uint32_t* __restrict__ omega,
+                                                uint32_t words, int ncells, int cell,
+                                                uint32_t pix) {
+  uint32_t b = 0;
+  for (int c = 0; c < ncells; ++c)
+    b |= ((omega[(size_t)c * words + (pix >> 5)] >> (pix & 31)) & 1u) << c;
+  return ((b >> cell) & 1u) ? b : 0u;
+}
 
 
 
@@ -52,9 +69,9 @@ __device__ __forceinline__ bool box_meets(float bxw, float byw, int x0, int x1, 
   const int bx0 = (int)(bx & 0xFFFFu), by0 = (int)(by & 0xFFFFu);
   return bx0 <= x1 && bx0 + (int)(bx >> 16) >= x0 && by0 <= y1 && by0 + (int)(by >> 16) >= y0;
 }
-template <int TW, int TH>
+template <int TW, int TH, bool FILT = false>
 __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
-                                            float4 (*s_rec)[3][64]) {
+                                            float4 (*s_rec)[3][64], uint32_t* s_xf = nullptr) {
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -63,6 +80,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
   const uint32_t pix = (uint32_t)py * a.W + px;
   bool active = inside;
   if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
+  const uint32_t pbits = (FILT && active) ? filter_bits(a.omega, a.words, a.ncells, a.cell, pix) : 0u;
   const float fx = (float)px + 0.5f - a.cx, fy = (float)py + 0.5f - a.cy;
   // pixel rectangle of this wavefront (64 consecutive pixels of the tile)
   constexpr int WR = 64 / TW;  // rows per wavefront
@@ -77,20 +95,24 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
     const uint32_t cnt = rg.y - jb < 64u ? rg.y - jb : 64u;
     bool meets = false;
     if ((uint32_t)lane < cnt) {
-      const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)a.vals[jb + lane] * kRecFloats);
+      const uint32_t gl = a.vals[jb + lane];
+      const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)gl * kRecFloats);
       const float4 q0 = r[0], q1 = r[1], q2 = r[2];
       s_rec[w][0][lane] = q0;
       s_rec[w][1][lane] = q1;
       s_rec[w][2][lane] = q2;
+      if (FILT) s_xf[w * 64 + lane] = a.xf[gl];
       meets = box_meets(q2.z, q2.w, wx0, wx1, wy0, wy1);
     }
     uint64_t todo = __ballot(meets);
     __builtin_amdgcn_wave_barrier();
     // branch-free blend: a lane that does not blend uses alpha = 0, which
     // leaves C, D and T unchanged exactly
-    auto blend = [&](const float4& r0, const float4& r1, const float4& r2, uint32_t kc) {
+    auto blend = [&](const float4& r0, const float4& r1, const float4& r2, uint32_t kc,
+                     uint32_t xe) {
       const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-      const bool use = !done && ae.alpha >= a.alpha_min && in_box(px, py, r2.z, r2.w);
+      const bool use = !done && ae.alpha >= a.alpha_min && in_box(px, py, r2.z, r2.w) &&
+                       (!FILT || (xe & pbits) == 0u);
       const float al = use ? ae.alpha : 0.f;
       const float wt = al * T;
       C0 = fmaf(r1.z, wt, C0);
@@ -112,8 +134,9 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
       todo &= two ? todo - 1 : todo;
       const float4 p0 = s_rec[w][0][k1], p1 = s_rec[w][1][k1], p2 = s_rec[w][2][k1];
       const float4 q0 = s_rec[w][0][k2], q1 = s_rec[w][1][k2], q2 = s_rec[w][2][k2];
-      blend(p0, p1, p2, k1);
-      if (two) blend(q0, q1, q2, k2);
+      const uint32_t x1 = FILT ? s_xf[w * 64 + k1] : 0u, x2 = FILT ? s_xf[w * 64 + k2] : 0u;
+      blend(p0, p1, p2, k1, x1);
+      if (two) blend(q0, q1, q2, k2, x2);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -125,13 +148,14 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool FILT>
 __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
   __shared__ float4 s_rec[TW * TH / 64][3][64];
+  __shared__ uint32_t s_xf[FILT ? TW * TH : 1];
   const int ntile = a.tiles_x * a.tiles_y;
   const int tile = blockIdx.x;
   if (tile >= ntile) return;
-  render_tile<TW, TH>(a, tile, s_rec);
+  render_tile<TW, TH, FILT>(a, tile, s_rec, s_xf);
 }
 
 struct RenderBwdArgs {
@@ -152,6 +176,11 @@ struct RenderBwdArgs {
   float* __restrict__ rows;         // [visited][kRowFloats]
   uint32_t* __restrict__ pkey;      // per row: Gaussian index
   uint32_t* __restrict__ pval;      // per row: row index
+  // cross-boundary filter (FILT), as in RenderArgs
+  const uint32_t* __restrict__ xf;
+  const uint32_t* __restrict__ omega;
+  uint32_t words;
+  int cell, ncells;
 };
 
 // Sum of ten per-lane values over the wavefront, stored to dst[0..9].  The
@@ -208,9 +237,9 @@ __device__ __forceinline__ void wave_sum10_store(const float (&v)[10], float* ds
 // is stored beside it for the per-Gaussian reduction.
 // DG: a depth gradient is given (otherwise its terms are compiled out,
 // which frees the registers of two per-pixel quantities).
-template <int TW, int TH, bool DG>
+template <int TW, int TH, bool DG, bool FILT = false>
 __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile,
-                                                float4 (*s_rec)[64]) {
+                                                float4 (*s_rec)[64], uint32_t* s_xf = nullptr) {
   constexpr int PPT = TW * TH / 64;
   constexpr int WR = 64 / TW;  // rows per group of 64 pixels
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -221,7 +250,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
   uint32_t pxy[PPT];  // pixel x | y << 16
   float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
   float gx[PPT], gy[PPT], gz[PPT], gd[PPT], gtf[PPT];
-  uint32_t lst[PPT];
+  uint32_t lst[PPT], pbits[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int li = lane + 64 * k;
@@ -230,6 +259,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     const uint32_t pix = inside ? (uint32_t)py * a.W + px : 0u;
     bool active = inside;
     if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
+    pbits[k] = (FILT && active) ? filter_bits(a.omega, a.words, a.ncells, a.cell, pix) : 0u;
     pxy[k] = (uint32_t)px | ((uint32_t)py << 16);
     fx[k] = (float)px + 0.5f - a.cx;
     fy[k] = (float)py + 0.5f - a.cy;
@@ -264,6 +294,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       s_rec[0][lane] = q0;
       s_rec[1][lane] = q1;
       s_rec[2][lane] = q2;
+      if (FILT) s_xf[lane] = a.xf[gl];
 #pragma unroll
       for (int k = 0; k < PPT; ++k)
         mk[k] = box_meets(q2.z, q2.w, tx * TW, tx * TW + TW - 1, ty * TH + k * WR,
@@ -275,7 +306,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
 #pragma unroll
     for (int k = 0; k < PPT; ++k) gm[k] = __ballot(mk[k]);
     __builtin_amdgcn_wave_barrier();
-    auto entry = [&](const float4& r0, const float4& r1, const float4& r2, int kk) {
+    auto entry = [&](const float4& r0, const float4& r1, const float4& r2, int kk, uint32_t xe) {
     const int j = j0 + kk;
     const uint32_t e = row0 + (uint32_t)j;
     float2* dst = reinterpret_cast<float2*>(a.rows + (size_t)e * kRowFloats);
@@ -293,7 +324,8 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       const float dx = fx[k] - r0.x, dy = fy[k] - r0.y;
       const AlphaEval ae = eval_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
       const bool use = (uint32_t)j < lst[k] && ae.alpha >= a.alpha_min &&
-                       in_box((int)(pxy[k] & 0xFFFFu), (int)(pxy[k] >> 16), r2.z, r2.w);
+                       in_box((int)(pxy[k] & 0xFFFFu), (int)(pxy[k] >> 16), r2.z, r2.w) &&
+                       (!FILT || (xe & pbits[k]) == 0u);
       any = any || use;
       const float al = use ? ae.alpha : 0.f;
       const float om = 1.f - al;  // >= 1 - alpha_max
@@ -345,20 +377,22 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       const int k2 = two ? kk - 1 : kk;
       const float4 p0 = s_rec[0][kk], p1 = s_rec[1][kk], p2 = s_rec[2][kk];
       const float4 q0 = s_rec[0][k2], q1 = s_rec[1][k2], q2 = s_rec[2][k2];
-      entry(p0, p1, p2, kk);
-      if (two) entry(q0, q1, q2, k2);
+      const uint32_t x1 = FILT ? s_xf[kk] : 0u, x2 = FILT ? s_xf[k2] : 0u;
+      entry(p0, p1, p2, kk, x1);
+      if (two) entry(q0, q1, q2, k2, x2);
     }
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-template <int TW, int TH, bool DG>
+template <int TW, int TH, bool DG, bool FILT>
 __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   __shared__ float4 s_rec[3][64];
+  __shared__ uint32_t s_xf[FILT ? 64 : 1];
   const int ntile = a.tiles_x * a.tiles_y;
   const int tile = blockIdx.x;
   if (tile >= ntile) return;
-  render_tile_bwd<TW, TH, DG>(a, tile, s_rec);
+  render_tile_bwd<TW, TH, DG, FILT>(a, tile, s_rec, s_xf);
 }
 
 // Entries each tile's reverse walk visits: the largest `last` over its
@@ -557,15 +591,24 @@ bool tile_shape_supported(int tw, int th) {
 template <int TW, int TH>
 static void launch_fwd_t(const RenderArgs& a, hipStream_t st) {
   const int grid = a.tiles_x * a.tiles_y;
-  hipLaunchKernelGGL((k_render<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, a);
+  if (a.xf)
+    hipLaunchKernelGGL((k_render<TW, TH, true>), dim3(grid), dim3(TW * TH), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_render<TW, TH, false>), dim3(grid), dim3(TW * TH), 0, st, a);
 }
 template <int TW, int TH>
 static void launch_bwd_t(const RenderBwdArgs& a, hipStream_t st) {
   const int grid = a.tiles_x * a.tiles_y;
-  if (a.ddepth)
-    hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3(grid), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3(grid), dim3(64), 0, st, a);
+  if (a.xf) {
+    if (a.ddepth)
+      hipLaunchKernelGGL((k_render_bwd<TW, TH, true, true>), dim3(grid), dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_render_bwd<TW, TH, false, true>), dim3(grid), dim3(64), 0, st, a);
+  } else if (a.ddepth) {
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, true, false>), dim3(grid), dim3(64), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, false, false>), dim3(grid), dim3(64), 0, st, a);
+  }
 }
 
 #define SX_DISPATCH_TILE(tw, th, FN, ARGS, ST)           \
@@ -577,25 +620,6 @@ static void launch_bwd_t(const RenderBwdArgs& a, hipStream_t st) {
     else if (tw == 16 && th == 32) FN<16, 32>(ARGS, ST); \
     else FN<8, 8>(ARGS, ST);                             \
   } while (0)
-
-hipError_t launch_render(const sx_projected& proj, const uint32_t* vals,
-                         const uint32_t* ranges, const DCam& cam,
-                         const KParams& p, const uint32_t* mask,
-                         float* partial, float* depth, uint32_t* last,
-                         uint32_t* nblend, hipStream_t st) {
-  RenderArgs a;
-  a.rec = proj.rec;
-  a.vals = vals;
-  a.ranges = reinterpret_cast<const uint2*>(ranges);
-  a.mask = mask;
-  a.W = cam.W, a.H = cam.H, a.tiles_x = p.tiles_x, a.tiles_y = p.tiles_y;
-  a.cx = (float)cam.cx, a.cy = (float)cam.cy;
-  a.alpha_min = p.alpha_min, a.alpha_max = p.alpha_max, a.t_min = p.t_min;
-  a.partial = reinterpret_cast<float4*>(partial);
-  a.depth = depth, a.last = last, a.nblend = nblend;
-  SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_fwd_t, a, st);
-  return hipGetLastError();
-}
 
 static RenderArgs make_render_args(const sx_projected& proj, const uint32_t* vals,
                                    const uint32_t* ranges, const DCam& cam, const KParams& p,
@@ -611,7 +635,20 @@ static RenderArgs make_render_args(const sx_projected& proj, const uint32_t* val
   a.alpha_min = p.alpha_min, a.alpha_max = p.alpha_max, a.t_min = p.t_min;
   a.partial = reinterpret_cast<float4*>(partial);
   a.depth = depth, a.last = last, a.nblend = nblend;
+  a.xf = proj.xf, a.omega = proj.omega;
+  a.words = ((uint32_t)cam.W * (uint32_t)cam.H + 31) / 32;
+  a.cell = proj.cell, a.ncells = proj.n_cells;
   return a;
+}
+
+hipError_t launch_render(const sx_projected& proj, const uint32_t* vals,
+                         const uint32_t* ranges, const DCam& cam,
+                         const KParams& p, const uint32_t* mask,
+                         float* partial, float* depth, uint32_t* last,
+                         uint32_t* nblend, hipStream_t st) {
+  RenderArgs a = make_render_args(proj, vals, ranges, cam, p, mask, partial, depth, last, nblend);
+  SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_fwd_t, a, st);
+  return hipGetLastError();
 }
 
 static RenderBwdArgs make_bwd_args(const sx_projected& proj, const uint32_t* vals,
@@ -639,6 +676,9 @@ static RenderBwdArgs make_bwd_args(const sx_projected& proj, const uint32_t* val
   a.rows = reinterpret_cast<float*>(bws + BL.rows);
   a.pkey = reinterpret_cast<uint32_t*>(bws + BL.pk[0]);
   a.pval = reinterpret_cast<uint32_t*>(bws + BL.pv[0]);
+  a.xf = proj.xf, a.omega = proj.omega;
+  a.words = ((uint32_t)cam.W * (uint32_t)cam.H + 31) / 32;
+  a.cell = proj.cell, a.ncells = proj.n_cells;
   return a;
 }
 

@@ -124,6 +124,20 @@ class CellView:
         self.dpartial = None
         self.mask = None
         self._hw = hw
+        self.xf = None  # cross-boundary filter bits, when the filter is on
+
+    def set_cross_filter(self, boxes=None, cell: int = 0, omega=None):
+        """Remove this cell's cross-boundary Gaussians from the rays where
+        both cells are visible (omega: the view's K geometric maps from
+        sx_visibility, kept alive by the caller); omega None turns it off.
+        The bits are recomputed by every preprocess."""
+        if omega is None:
+            self.xf = None
+            B.set_cross_filter(self.c_proj, None, None, 0, 0)
+            return
+        self.xf = torch.empty((max(self.params.n, 1),), dtype=torch.int32, device=self.device)
+        self._xf_boxes, self._xf_cell, self._omega = list(boxes), int(cell), omega
+        B.set_cross_filter(self.c_proj, self.xf, omega, cell, len(self._xf_boxes))
 
     def _alloc_sort(self, capacity: int):
         self.capacity = int(capacity)
@@ -154,6 +168,9 @@ class CellView:
     # ---------------------------------------------------------------- steps
     def preprocess(self):
         B.sx_preprocess(self.c_g, self.c_cam, self.c_par, self.c_proj)
+        if self.xf is not None:
+            B.sx_cross_filter(self.c_g, self.c_proj, self._xf_boxes, self._xf_cell, self.c_cam,
+                              self.xf)
 
     def sort(self, sync=True):
         """With sync, reads the instance count back once and grows the
@@ -238,7 +255,9 @@ class Frame:
     """One view of a scene split into K cells: forward and backward."""
 
     def __init__(self, cells: Sequence[GaussianParams], boxes, cam, settings,
-                 flags=0, capacities=None, keep_keys=False, device="cuda"):
+                 flags=0, capacities=None, keep_keys=False, device="cuda",
+                 cross_filter=False):
+        self.cross_filter = cross_filter
         self.cells = list(cells)
         self.boxes = list(boxes)
         assert len(self.cells) == len(self.boxes)
@@ -254,8 +273,10 @@ class Frame:
         self.c_par = B.params(settings, sh_deg, flags)
         self.out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=device)
         self.masks = None
-        self.omega = None   # geometric maps kept for re-evaluation
+        self.omega = None   # geometric maps (re-evaluation, cross-boundary filter)
         self.budget = None  # [K, H*W] stale consumption of pruned pairs
+        if cross_filter:
+            self._set_omega(self._visibility())
 
     @property
     def K(self):
@@ -268,17 +289,33 @@ class Frame:
         masks become the view's saturation state: pruned pairs keep their
         transmittance consumption and come back when the transmittance in
         front of them recovers (sx_composite_reeval)."""
-        words = (self.cam.width * self.cam.height + 31) // 32
-        self.masks = torch.empty((self.K, words), dtype=torch.int32, device=self.out.device)
         if geometric:
-            B.sx_visibility(self.boxes, self.c_cam, self.masks)
+            vis = self.omega if self.omega is not None else self._visibility()
+            self.masks = vis.clone()
+            if reeval:
+                self._set_omega(vis)
         else:
+            self.masks = torch.empty_like(self._visibility_buffer())
             B.sx_fill_u32(self.masks, 0xFFFFFFFF)
-        self.omega = self.masks.clone() if (reeval and geometric) else None
         self.budget = (torch.zeros((self.K, self.cam.width * self.cam.height),
                                    dtype=torch.float32, device=self.out.device)
                        if reeval else None)
         return self.masks
+
+    def _visibility_buffer(self):
+        words = (self.cam.width * self.cam.height + 31) // 32
+        return torch.empty((self.K, words), dtype=torch.int32, device=self.out.device)
+
+    def _visibility(self):
+        vis = self._visibility_buffer()
+        B.sx_visibility(self.boxes, self.c_cam, vis)
+        return vis
+
+    def _set_omega(self, vis):
+        self.omega = vis
+        if self.cross_filter:
+            for k, v in enumerate(self.views):
+                v.set_cross_filter(self.boxes, k, vis)
 
     def forward(self, use_masks=False, update_masks=False, sync=True):
         """Render every cell (optionally restricted to the active mask bits

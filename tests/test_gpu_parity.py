@@ -468,6 +468,82 @@ def test_composite_reeval_three_renders_match_oracle(torch_gpu):
     assert stats[1][1] > 500 and stats[1][0] > 1000
 
 
+@pytest.mark.parametrize("cells_kind", ["grid", "kd"])
+def test_cross_boundary_filter_matches_oracle(torch_gpu, cells_kind):
+    """Per-ray cross-boundary filtering on K = 8 cells: the filter bits of
+    every Gaussian bit-exact where the oracle's decision is not within
+    rounding reach, and the filtered renders, composition, masks and
+    gradients against the oracle run with its own bits."""
+    print(f"case: cross-boundary filter k8 {cells_kind}", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    scene = synth.make_cube_scene(6, 9000, log_scale=(-3.0, 0.5))
+    if cells_kind == "grid":
+        cam = synth.camera_from_rows(
+            np.array([[1, 0, 0], [0, 0.9950, -0.0998], [0, 0.0998, 0.9950]]), (0.13, 0.21, -3.0),
+            96, 80, 70.0)
+        xe, ye = [-1.0, -0.5, 0.0, 0.5, 1.0], [-1.0, 0.0, 1.0]
+        part = synth.grid_partition(scene, xe, ye)
+        boxes = grid_cells_xy(xe, ye)
+        scenes = part.cell_scenes(scene)
+    else:
+        cam = synth.look_at_camera((2.4, -2.9, 1.6), (0.0, 0.1, 0.0), 112, 84, hfov_deg=55.0)
+        boxes_t, cell_of = B.sx_kd_partition(scene.means, 8)
+        boxes = [synth.Cell(lo, hi) for lo, hi in boxes_t]
+        scenes = [scene.subset(np.nonzero(cell_of == k)[0]) for k in range(8)]
+    K, H, W = 8, cam.height, cam.width
+    from paper_2606_18588_amd.pipeline import Frame, GaussianParams
+    params = [GaussianParams.from_scene(c) for c in scenes]
+    fr = Frame(params, boxes, cam, ST, cross_filter=True)
+    fr.init_masks()
+    out = fr.forward(update_masks=True).cpu().numpy()
+    torch.cuda.synchronize()
+    vis = oracle.visibility(boxes, cam)
+    assert not vis["flags"].any()
+    xfs = oracle.cross_filters(scenes, boxes, cam, ST)
+    nfilt = 0
+    for k in range(K):
+        got = fr.views[k].xf.cpu().numpy().view(np.uint32)[:scenes[k].n]
+        ok = xfs[k]["amb"] == 0
+        assert_same(got[ok], xfs[k]["xf"][ok], f"filter bits of cell {k}")
+        nfilt += int((xfs[k]["xf"] != 0).sum())
+    assert nfilt > 100
+    ref = oracle.forward(scenes, boxes, cam, ST, xfilters=xfs)
+    fl = ref.comp["flags"].copy()
+    for p in ref.parts:
+        fl |= p["flags"]
+    cmax = max(float(oracle.preprocess(c, cam, ST)["rgb"].max()) for c in scenes)
+    e, nf = compare_image(out[..., :3], ref.comp["rgb"], fl, 1e-4, K * jump_bound(ST, cmax))
+    compare_image(out[..., 3], ref.comp["T"], fl, 1e-4, 1.0)
+    unf = oracle.forward(scenes, boxes, cam, ST)
+    changed = np.abs(unf.comp["rgb"] - ref.comp["rgb"]).max(-1) > 1e-3
+    assert changed.sum() > 50  # the filter changes the image
+    ok = fl == 0
+    for k in range(K):
+        assert_same(fr.views[k].nblend.cpu().numpy()[ok], ref.parts[k]["nblend"][ok],
+                    f"blended pairs of cell {k}")
+    bits = np.unpackbits(fr.masks.cpu().numpy().view(np.uint8), bitorder="little").reshape(K, -1)[:, :H * W]
+    assert_same(bits[:, ok.reshape(-1)], ref.comp["mask"].reshape(K, -1)[:, ok.reshape(-1)],
+                "saturation masks")
+    print(f"cross filter {cells_kind}: {nfilt} filtered Gaussians, {int(changed.sum())} pixels "
+          f"changed, max-abs {e:.3g}, flagged {nf}", flush=True)
+    # backward: upstream gradient on unflagged pixels
+    rng = np.random.default_rng(31)
+    d = (rng.normal(size=(H, W, 4)) * ok[..., None]).astype(np.float32)
+    grads = [p.zeros_like() for p in params]
+    fr.backward(torch.as_tensor(d).cuda(), grads)
+    torch.cuda.synchronize()
+    gref = oracle.backward(scenes, boxes, cam, ST, ref, d[..., :3].astype(np.float64),
+                           d[..., 3].astype(np.float64), xfilters=xfs)
+    for k in range(K):
+        v = fr.views[k].n_tiles.cpu().numpy() > 0
+        if not v.any():
+            continue
+        for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            got = getattr(grads[k], name).cpu().numpy()[v]
+            assert rel_err(got, gref[k][name][v]) <= 2e-3, (k, name)
+
+
 def test_composite_kd_cells_matches_oracle(torch_gpu):
     """K = 8 cells from the KD-tree partitioner (boxes bounded on some axes,
     unbounded at the scene's outside): the composition by ray entry order
