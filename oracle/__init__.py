@@ -16,6 +16,11 @@ Paper anchors (the paper's own numbering of equations):
   * Eq. 6-7 gradients of C_p with respect to alpha_i and c_i through Eq. 5
   * saturation redundancy: cells behind prod T^k < eps are inactive for the
     next render of the same view.
+  * geometric visibility of the cell boxes (redundancy reduction, spatial
+    part); KD-tree partition (appendix, partition strategy).
+  * speculative re-evaluation of pruned pairs with stale transmittance
+    budgets (appendix, saturation stability during training).
+  * per-ray cross-boundary filter (appendix, cross-boundary Gaussians).
 """
 from __future__ import annotations
 

@@ -13,6 +13,9 @@
 //   * composition of partials in ray order             (Eq. 5)
 //   * gradients through the composition                (Eq. 6-7)
 //   * transmittance-saturation masks (redundancy reduction, saturation part)
+//     and their speculative re-evaluation (appendix, saturation stability)
+//   * geometric visibility of cell boxes (redundancy reduction, spatial part)
+//   * per-ray cross-boundary filter (appendix, cross-boundary Gaussians)
 //
 // Everything is computed in double precision from the caller's inputs.  The
 // per-pixel list is "every Gaussian whose footprint can reach the pixel",
