@@ -383,11 +383,12 @@ sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
  * them separately; stages is a mask of SX_RB_* bits and the stages must run
  * in this order on one stream with the same arguments:
  *   SX_RB_PREPARE  entries each tile's reverse walk visits (the largest
- *                  `last` over its pixels) and the first gradient row of
- *                  each tile;
- *   SX_RB_WALK     the reverse walk (Eq. 6-7): one gradient row per visited
- *                  entry in bwd_ws;
- *   SX_RB_REDUCE   the rows summed per Gaussian into g2d.
+ *                  `last` over its pixels);
+ *   SX_RB_WALK     the reverse walk (Eq. 6-7): one gradient row per
+ *                  (Gaussian, tile) instance in bwd_ws, at the instance's
+ *                  place in its Gaussian's tile rectangle (zeros for the
+ *                  entries no pixel reached);
+ *   SX_RB_REDUCE   each visible Gaussian's contiguous rows summed into g2d.
  * sx_render_backward is this call with SX_RB_ALL. */
 #define SX_RB_PREPARE 1
 #define SX_RB_WALK 2

@@ -46,6 +46,8 @@ KParams make_kparams(const sx_params& p, const sx_camera& c);
 struct SortLayout {
   size_t counts;       // uint64[4]: visible, instances, overflow, error
   size_t vis_off;      // uint32[nb]   exclusive visible offsets per block
+  size_t inst_off;     // uint32[nb]   exclusive instance offsets per block
+  size_t ioff;         // uint32[n]    first instance of each visible Gaussian
   size_t scan_part;    // uint64[tiles][2] per-tile (visible, instance) sums
   size_t dkey[2];      // uint32[n]    depth keys (ping-pong)
   size_t didx[2];      // uint32[n]    Gaussian indices (ping-pong)
@@ -72,19 +74,10 @@ SortLayout sort_layout(int64_t n, int64_t capacity, int64_t tiles_x, int64_t til
 // row) pairs that are sorted by Gaussian to sum each Gaussian's rows.
 constexpr int kRowFloats = 10;  // d(mean2d x, y, conic a, b, c, opacity, r, g, b, depth)
 struct BwdLayout {
-  size_t zero_begin;
-  size_t vcount;    // uint64[4]: visited rows, -, -, error flag
-  size_t vhist;     // uint32[4][256] digit histograms of the pair keys
-  size_t counters;  // uint32[8] partition counters
-  size_t zero_end;
-  size_t vstatus;   // uint32[4][parts][256] look-back status
   size_t nv;        // uint32[tiles] entries visited per tile
-  size_t vb;        // uint32[tiles] first row of each tile
-  size_t rows;      // float[cap][kRowFloats]
-  size_t pk[2];     // uint32[cap] pair keys (Gaussian index), ping-pong
-  size_t pv[2];     // uint32[cap] pair values (row index), ping-pong
+  size_t rows;      // float[cap][kRowFloats]: one gradient row per (Gaussian, tile)
+                    // instance, Gaussian-major (see SortView::ioff)
   size_t total;
-  int64_t parts;
 };
 BwdLayout bwd_layout(int64_t capacity, int64_t tiles_total);
 
@@ -93,6 +86,7 @@ struct SortView {
   const uint64_t* counts;
   const uint32_t* didx;   // depth-sorted visible Gaussians
   const uint32_t* vidx;   // the same Gaussians in index order
+  const uint32_t* ioff;   // [n] first instance of each visible Gaussian, index order
 };
 SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
 
@@ -329,12 +323,5 @@ hipError_t launch_adam(int64_t n, float* param, const float* grad, float* m,
                        float* v, float lr, float b1, float b2, float eps,
                        float bc1, float bc2, hipStream_t st);
 hipError_t launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
-// Stable LSD sort of the (*count, at most cap) pairs keys[0]/vals[0] whose
-// keys are < 2^bits, in 8-bit digits; the result ends in keys[r]/vals[r],
-// r the returned index.  hist: uint32[4][256], status: uint32[4][parts][256]
-// and counters: uint32[4], all zero on entry.
-int launch_pair_sort(uint32_t* const keys[2], uint32_t* const vals[2], const uint64_t* count,
-                     uint64_t cap, int bits, uint32_t* hist, uint32_t* status, int64_t parts,
-                     uint32_t* counters, uint64_t* err, hipStream_t st, hipError_t* e);
 bool tile_shape_supported(int tw, int th);
 }  // namespace sx

@@ -170,12 +170,11 @@ struct RenderBwdArgs {
   const uint32_t* __restrict__ last;
   const float4* __restrict__ dpartial;
   const float* __restrict__ ddepth;
-  const uint32_t* __restrict__ nv;  // entries visited per tile
-  const uint32_t* __restrict__ vb;  // first gradient row of each tile
+  const uint32_t* __restrict__ nv;    // entries visited per tile
+  const uint32_t* __restrict__ ioff;  // first instance row of each visible Gaussian
+  const ushort4* __restrict__ rect;   // tile rectangles [x0, y0, x1, y1)
   uint64_t cap;
-  float* __restrict__ rows;         // [visited][kRowFloats]
-  uint32_t* __restrict__ pkey;      // per row: Gaussian index
-  uint32_t* __restrict__ pval;      // per row: row index
+  float* __restrict__ rows;           // [instances][kRowFloats], Gaussian-major
   // cross-boundary filter (FILT), as in RenderArgs
   const uint32_t* __restrict__ xf;
   const uint32_t* __restrict__ omega;
@@ -231,22 +230,41 @@ __device__ __forceinline__ void wave_sum10_store(const float (&v)[10], float* ds
 //
 // One wavefront per tile; each lane owns TW*TH/64 pixels and sums their
 // contributions in registers, then one cross-lane reduction (DPP) per
-// (Gaussian, tile).  No atomics: the tile walks the nv[tile] entries its
-// pixels reached, and the j-th of them owns gradient row vb[tile] + j (rows
-// of entries without any contribution are zeros); the row's Gaussian index
-// is stored beside it for the per-Gaussian reduction.
+// (Gaussian, tile).  No atomics: instance (g, tile) owns gradient row
+// ioff[g] + the tile's raster position in g's tile rectangle, so each
+// Gaussian's rows are contiguous and a plain segmented sum finishes them.
+// The tile walks the nv[tile] entries its pixels reached and writes every
+// entry's row (zeros where nothing blended), and zeros for the entries past
+// them.
 // DG: a depth gradient is given (otherwise its terms are compiled out,
 // which frees the registers of two per-pixel quantities).
+__device__ __forceinline__ uint32_t instance_row(const RenderBwdArgs& a, uint32_t g, int tx,
+                                                 int ty) {
+  const ushort4 rc = a.rect[g];
+  return a.ioff[g] + (uint32_t)(ty - (int)rc.y) * (uint32_t)(rc.z - rc.x) +
+         (uint32_t)(tx - (int)rc.x);
+}
+
 template <int TW, int TH, bool DG, bool FILT = false>
 __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile,
-                                                float4 (*s_rec)[64], uint32_t* s_xf = nullptr) {
+                                                float4 (*s_rec)[64], uint32_t* s_e,
+                                                uint32_t* s_xf = nullptr) {
   constexpr int PPT = TW * TH / 64;
   constexpr int WR = 64 / TW;  // rows per group of 64 pixels
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int lane = threadIdx.x;
   const uint32_t wave_last = a.nv[tile];  // max of the pixels' `last` over the tile
-  if (wave_last == 0) return;             // nothing blended here: no rows, no pixel reads
   const uint2 rg = a.ranges[tile];
+  // rows of the entries no pixel reached are zero
+  for (uint32_t j = wave_last + (uint32_t)lane; j < rg.y - rg.x; j += 64) {
+    const uint32_t e = instance_row(a, a.vals[rg.x + j], tx, ty);
+    if ((uint64_t)e < a.cap) {
+      float2* d = reinterpret_cast<float2*>(a.rows + (size_t)e * kRowFloats);
+      const float2 z = make_float2(0.f, 0.f);
+      d[0] = z, d[1] = z, d[2] = z, d[3] = z, d[4] = z;
+    }
+  }
+  if (wave_last == 0) return;  // nothing blended here: no pixel reads
   uint32_t pxy[PPT];  // pixel x | y << 16
   float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
   float gx[PPT], gy[PPT], gz[PPT], gd[PPT], gtf[PPT];
@@ -277,7 +295,6 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     gtf[k] = gt * Tf;
     R0[k] = R1[k] = R2[k] = RD[k] = 0.f;
   }
-  const uint32_t row0 = a.vb[tile];
   for (int jend = (int)wave_last; jend > 0; jend -= 64) {
     // stage entries [jend - cnt, jend): lane i gathers entry jend - cnt + i,
     // stores its (Gaussian, row) pair and tests its pixel box against each
@@ -299,16 +316,15 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       for (int k = 0; k < PPT; ++k)
         mk[k] = box_meets(q2.z, q2.w, tx * TW, tx * TW + TW - 1, ty * TH + k * WR,
                           ty * TH + k * WR + WR - 1);
-      const uint32_t row = row0 + (uint32_t)(j0 + lane);
-      if ((uint64_t)row < a.cap) a.pkey[row] = gl, a.pval[row] = row;
+      s_e[lane] = instance_row(a, gl, tx, ty);
     }
     uint64_t gm[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) gm[k] = __ballot(mk[k]);
     __builtin_amdgcn_wave_barrier();
-    auto entry = [&](const float4& r0, const float4& r1, const float4& r2, int kk, uint32_t xe) {
+    auto entry = [&](const float4& r0, const float4& r1, const float4& r2, int kk, uint32_t xe,
+                     uint32_t e) {
     const int j = j0 + kk;
-    const uint32_t e = row0 + (uint32_t)j;
     float2* dst = reinterpret_cast<float2*>(a.rows + (size_t)e * kRowFloats);
     const bool in_cap = (uint64_t)e < a.cap;
     float v[10];
@@ -378,8 +394,9 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       const float4 p0 = s_rec[0][kk], p1 = s_rec[1][kk], p2 = s_rec[2][kk];
       const float4 q0 = s_rec[0][k2], q1 = s_rec[1][k2], q2 = s_rec[2][k2];
       const uint32_t x1 = FILT ? s_xf[kk] : 0u, x2 = FILT ? s_xf[k2] : 0u;
-      entry(p0, p1, p2, kk, x1);
-      if (two) entry(q0, q1, q2, k2, x2);
+      const uint32_t e1 = s_e[kk], e2 = s_e[k2];
+      entry(p0, p1, p2, kk, x1, e1);
+      if (two) entry(q0, q1, q2, k2, x2, e2);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -388,11 +405,12 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
 template <int TW, int TH, bool DG, bool FILT>
 __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   __shared__ float4 s_rec[3][64];
+  __shared__ uint32_t s_e[64];
   __shared__ uint32_t s_xf[FILT ? 64 : 1];
   const int ntile = a.tiles_x * a.tiles_y;
   const int tile = blockIdx.x;
   if (tile >= ntile) return;
-  render_tile_bwd<TW, TH, DG, FILT>(a, tile, s_rec, s_xf);
+  render_tile_bwd<TW, TH, DG, FILT>(a, tile, s_rec, s_e, s_xf);
 }
 
 // Entries each tile's reverse walk visits: the largest `last` over its
@@ -419,122 +437,70 @@ __global__ __launch_bounds__(64) void k_tile_extent(const uint32_t* __restrict__
   if (threadIdx.x == 0) nv[tile] = mx;
 }
 
-// One block: exclusive scan of the visited counts -> first row per tile and
-// the number of rows.
-__global__ __launch_bounds__(1024) void k_extent_scan(const uint32_t* __restrict__ nv, int tiles,
-                                                      uint32_t* __restrict__ vb,
-                                                      uint64_t* vcount) {
-  __shared__ uint32_t s_p[1024];
-  const int tid = threadIdx.x;
-  const int chunk = (tiles + 1023) / 1024;
-  const int beg = tid * chunk, end = beg + chunk < tiles ? beg + chunk : tiles;
-  uint32_t sum = 0;
-  for (int t = beg; t < end; ++t) sum += nv[t];
-  s_p[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint32_t v = tid >= o ? s_p[tid - o] : 0u;
-    __syncthreads();
-    s_p[tid] += v;
-    __syncthreads();
-  }
-  uint32_t run = s_p[tid] - sum;
-  for (int t = beg; t < end; ++t) {
-    vb[t] = run;
-    run += nv[t];
-  }
-  if (tid == 1023) vcount[0] = s_p[1023];
-}
+// Per-Gaussian sum of its instance rows, which are contiguous (rows
+// ioff[g] .. ioff[g] + n_tiles[g]), into g2d[g]; every visible Gaussian's
+// row is written, so nothing is cleared first.  A lane sums the rows of a
+// Gaussian with few tiles in order; the wavefront shares the rows of each
+// Gaussian with more (strided, then one cross-lane sum).
+constexpr uint32_t kLaneRows = 16;
 
-// Clear the look-back status of the partitions the pair sort will use
-// (ceil(rows / kSortTile) per pass; the rest is never read).
-__global__ __launch_bounds__(256) void k_zero_status(uint32_t* __restrict__ status, int64_t parts,
-                                                     const uint64_t* vcount, uint64_t cap) {
-  const uint64_t n = vcount[0] < cap ? vcount[0] : cap;
-  const uint64_t words = (n + kSortTile - 1) / kSortTile * kRadixBins;
-  for (int ps = 0; ps < 4; ++ps)
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < words;
-         i += (uint64_t)gridDim.x * 256)
-      status[(size_t)ps * parts * kRadixBins + i] = 0u;
-}
-
-// Per-Gaussian sum of its rows.  The pairs are sorted by Gaussian (stably,
-// so a Gaussian's rows are in tile order) and cut into chunks of 256; each
-// chunk stages its rows in LDS, and the first pair of every run of one
-// Gaussian adds the run's rows in order.  A run lying inside one chunk is
-// stored with plain stores; the pieces of a run crossing chunk boundaries
-// are added atomically into the (pre-zeroed) row of its Gaussian.
-__global__ __launch_bounds__(256) void k_pair_reduce(const uint32_t* __restrict__ key,
-                                                     const uint32_t* __restrict__ val,
-                                                     const uint64_t* vcount, uint64_t cap,
-                                                     const float* __restrict__ rows,
+__global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t* __restrict__ vidx,
+                                                     const uint64_t* counts,
+                                                     const uint32_t* __restrict__ ioff,
+                                                     const uint32_t* __restrict__ n_tiles,
+                                                     const float* __restrict__ rows, uint64_t cap,
                                                      float* __restrict__ g2d) {
-  __shared__ float s_row[256][kRowFloats + 1];
-  __shared__ uint32_t s_key[256];
-  __shared__ unsigned long long s_hm[4];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const uint64_t n = vcount[0] < cap ? vcount[0] : cap;
-  for (uint64_t base = (uint64_t)blockIdx.x * 256; base < n; base += (uint64_t)gridDim.x * 256) {
-    const int m = (int)(n - base < 256 ? n - base : 256);
-    __syncthreads();  // the previous chunk is consumed
-    if (tid < m) {
-      s_key[tid] = key[base + tid];
-      const float2* src = reinterpret_cast<const float2*>(rows + (size_t)val[base + tid] * kRowFloats);
-#pragma unroll
-      for (int q = 0; q < kRowFloats / 2; ++q) {
-        const float2 v = src[q];
-        s_row[tid][2 * q] = v.x, s_row[tid][2 * q + 1] = v.y;
-      }
+  const int lane = threadIdx.x & 63;
+  const uint64_t nvis = counts[0];
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256 + (threadIdx.x & ~63u); i0 < nvis;
+       i0 += (uint64_t)gridDim.x * 256) {
+    const uint64_t i = i0 + (uint64_t)lane;
+    uint32_t g = 0, base = 0, cnt = 0;
+    if (i < nvis) {
+      g = vidx[i];
+      base = ioff[g];
+      cnt = n_tiles[g];
+      // rows past the buffer (an instance overflow) are not read
+      const uint64_t end = (uint64_t)base + cnt;
+      cnt = end <= cap ? cnt : (uint32_t)(base < cap ? cap - base : 0);
     }
-    __syncthreads();
-    const uint32_t g = tid < m ? s_key[tid] : 0u;
-    const bool head = tid < m && (tid == 0 || s_key[tid - 1] != g);
-    const unsigned long long hm = __ballot(head);
-    if (lane == 0) s_hm[w] = hm;
-    __syncthreads();
-    if (head) {
-      // end of the run: the next run head in this chunk, else the chunk end
-      int e = m;
-      const unsigned long long later = lane < 63 ? hm & ~((2ull << lane) - 1ull) : 0ull;
-      if (later) {
-        e = w * 64 + __builtin_ctzll(later);
-      } else {
-        for (int w2 = w + 1; w2 < 4; ++w2)
-          if (s_hm[w2]) {
-            e = w2 * 64 + __builtin_ctzll(s_hm[w2]);
-            break;
-          }
-      }
+    const bool wide = i < nvis && cnt > kLaneRows;
+    if (i < nvis && !wide) {
       float acc[kRowFloats];
 #pragma unroll
       for (int q = 0; q < kRowFloats; ++q) acc[q] = 0.f;
-      for (int r = tid; r < e; ++r)
+      for (uint32_t r = 0; r < cnt; ++r) {
+        const float2* src = reinterpret_cast<const float2*>(rows + (size_t)(base + r) * kRowFloats);
 #pragma unroll
-        for (int q = 0; q < kRowFloats; ++q) acc[q] += s_row[r][q];
-      const bool starts = base + tid == 0 || key[base + tid - 1] != g;
-      const bool ends = base + e == n || key[base + e] != g;
-      float* d = g2d + (size_t)g * kG2dFloats;
-      if (starts && ends) {
-        float4* d4 = reinterpret_cast<float4*>(d);
-        d4[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        d4[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-        d4[2] = make_float4(acc[8], acc[9], 0.f, 0.f);
-      } else {
-#pragma unroll
-        for (int q = 0; q < kRowFloats; ++q) unsafeAtomicAdd(d + q, acc[q]);
+        for (int q = 0; q < kRowFloats / 2; ++q) {
+          const float2 v = src[q];
+          acc[2 * q] += v.x, acc[2 * q + 1] += v.y;
+        }
       }
+      float4* d = reinterpret_cast<float4*>(g2d + (size_t)g * kG2dFloats);
+      d[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      d[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+      d[2] = make_float4(acc[8], acc[9], 0.f, 0.f);
+    }
+    for (uint64_t wm = __ballot(wide); wm; wm &= wm - 1) {
+      const int l = __builtin_ctzll(wm);
+      const uint32_t gw = __shfl(g, l, 64), bw = __shfl(base, l, 64), cw = __shfl(cnt, l, 64);
+      float v[kRowFloats];
+#pragma unroll
+      for (int q = 0; q < kRowFloats; ++q) v[q] = 0.f;
+      for (uint32_t r = (uint32_t)lane; r < cw; r += 64) {
+        const float2* src = reinterpret_cast<const float2*>(rows + (size_t)(bw + r) * kRowFloats);
+#pragma unroll
+        for (int q = 0; q < kRowFloats / 2; ++q) {
+          const float2 x = src[q];
+          v[2 * q] += x.x, v[2 * q + 1] += x.y;
+        }
+      }
+      float* d = g2d + (size_t)gw * kG2dFloats;
+      wave_sum10_store(v, d, lane, true);
+      if (lane == 0) d[10] = 0.f, d[11] = 0.f;
     }
   }
-}
-
-__global__ __launch_bounds__(256) void k_zero_g2d(const uint32_t* __restrict__ vis,
-                                                  const uint64_t* vis_count,
-                                                  float* __restrict__ g2d) {
-  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= vis_count[0]) return;
-  float4* d = reinterpret_cast<float4*>(g2d + (size_t)vis[i] * kG2dFloats);
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  d[0] = z, d[1] = z, d[2] = z;
 }
 
 // ------------------------------------------------------------ multi-view --
@@ -574,11 +540,12 @@ static_assert(sizeof(RenderMultiArgs) <= 4096, "kernel argument block too large"
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_render_bwd_multi(RenderBwdMultiArgs m) {
   __shared__ float4 s_rec[3][64];
+  __shared__ uint32_t s_e[64];
   const uint32_t b = blockIdx.x;
   if (b >= m.base[m.V]) return;
   const int v = item_view(m.base, m.V, b);
   // batched views carry no depth gradient
-  render_tile_bwd<TW, TH, false>(m.view[v], (int)(b - m.base[v]), s_rec);
+  render_tile_bwd<TW, TH, false>(m.view[v], (int)(b - m.base[v]), s_rec, s_e);
 }
 
 static_assert(sizeof(RenderBwdMultiArgs) <= 4096, "kernel argument block too large");
@@ -652,10 +619,10 @@ hipError_t launch_render(const sx_projected& proj, const uint32_t* vals,
 }
 
 static RenderBwdArgs make_bwd_args(const sx_projected& proj, const uint32_t* vals,
-                                   const uint32_t* ranges, int64_t capacity, const DCam& cam,
-                                   const KParams& p, const uint32_t* mask, const float* partial,
-                                   const uint32_t* last, const float* dpartial,
-                                   const float* ddepth, char* bws) {
+                                   const uint32_t* ranges, const SortView& sv, int64_t capacity,
+                                   const DCam& cam, const KParams& p, const uint32_t* mask,
+                                   const float* partial, const uint32_t* last,
+                                   const float* dpartial, const float* ddepth, char* bws) {
   const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
   const BwdLayout BL = bwd_layout(capacity, tiles);
   RenderBwdArgs a;
@@ -671,11 +638,10 @@ static RenderBwdArgs make_bwd_args(const sx_projected& proj, const uint32_t* val
   a.dpartial = reinterpret_cast<const float4*>(dpartial);
   a.ddepth = ddepth;
   a.nv = reinterpret_cast<const uint32_t*>(bws + BL.nv);
-  a.vb = reinterpret_cast<const uint32_t*>(bws + BL.vb);
+  a.ioff = sv.ioff;
+  a.rect = reinterpret_cast<const ushort4*>(proj.rect);
   a.cap = (uint64_t)capacity;
   a.rows = reinterpret_cast<float*>(bws + BL.rows);
-  a.pkey = reinterpret_cast<uint32_t*>(bws + BL.pk[0]);
-  a.pval = reinterpret_cast<uint32_t*>(bws + BL.pv[0]);
   a.xf = proj.xf, a.omega = proj.omega;
   a.words = ((uint32_t)cam.W * (uint32_t)cam.H + 31) / 32;
   a.cell = proj.cell, a.ncells = proj.n_cells;
@@ -689,47 +655,25 @@ static void launch_extent_t(const RenderBwdArgs& a, hipStream_t st) {
                      a.mask, a.W, a.H, a.tiles_x, tiles, const_cast<uint32_t*>(a.nv));
 }
 
-// Before the reverse walk: clear the counters, find each tile's visited
-// prefix and give the visited entries consecutive rows.
-static hipError_t launch_bwd_prepare(const RenderBwdArgs& a, const KParams& p, int64_t capacity,
-                                     char* bws, hipStream_t st) {
-  const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
-  const BwdLayout BL = bwd_layout(capacity, tiles);
-  hipError_t e = launch_fill(reinterpret_cast<uint32_t*>(bws + BL.zero_begin),
-                             (int64_t)((BL.zero_end - BL.zero_begin) / 4), 0, st);
-  if (e) return e;
+// Before the reverse walk: each tile's visited prefix.
+static hipError_t launch_bwd_prepare(const RenderBwdArgs& a, const KParams& p, hipStream_t st) {
   SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_extent_t, a, st);
-  hipLaunchKernelGGL(k_extent_scan, dim3(1), dim3(1024), 0, st, a.nv, (int)tiles,
-                     const_cast<uint32_t*>(a.vb), reinterpret_cast<uint64_t*>(bws + BL.vcount));
-  hipLaunchKernelGGL(k_zero_status, dim3(256), dim3(256), 0, st,
-                     reinterpret_cast<uint32_t*>(bws + BL.vstatus), BL.parts,
-                     reinterpret_cast<const uint64_t*>(bws + BL.vcount), (uint64_t)capacity);
   return hipGetLastError();
 }
 
-// After the reverse walk: zero the visible Gaussians' screen-space
-// gradients, sort the (Gaussian, row) pairs by Gaussian and sum the rows.
-static hipError_t launch_bwd_reduce(const SortView& sv, int64_t n, int64_t capacity,
-                                    const KParams& p, float* g2d, char* bws, hipStream_t st) {
+// After the reverse walk: every visible Gaussian's screen-space gradient,
+// the sum of its contiguous instance rows.
+static hipError_t launch_bwd_reduce(const sx_projected& proj, const SortView& sv, int64_t n,
+                                    int64_t capacity, const KParams& p, float* g2d, char* bws,
+                                    hipStream_t st) {
   const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
   const BwdLayout BL = bwd_layout(capacity, tiles);
-  if (n > 0)
-    hipLaunchKernelGGL(k_zero_g2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       sv.vidx, sv.counts, g2d);
-  auto u32 = [&](size_t off) { return reinterpret_cast<uint32_t*>(bws + off); };
-  uint32_t* keys[2] = {u32(BL.pk[0]), u32(BL.pk[1])};
-  uint32_t* vals[2] = {u32(BL.pv[0]), u32(BL.pv[1])};
-  const uint64_t* vcount = reinterpret_cast<const uint64_t*>(bws + BL.vcount);
-  int bits = 1;
-  while (bits < 32 && (int64_t(1) << bits) < n) ++bits;
-  hipError_t e = hipSuccess;
-  const int r = launch_pair_sort(keys, vals, vcount, (uint64_t)capacity, bits, u32(BL.vhist),
-                                 u32(BL.vstatus), BL.parts, u32(BL.counters),
-                                 reinterpret_cast<uint64_t*>(bws + BL.vcount) + 3, st, &e);
-  if (e) return e;
-  hipLaunchKernelGGL(k_pair_reduce, dim3(1024), dim3(256), 0, st,
-                     keys[r], vals[r], vcount, (uint64_t)capacity,
-                     reinterpret_cast<const float*>(bws + BL.rows), g2d);
+  if (n > 0) {
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_slot_reduce, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(256),
+                       0, st, sv.vidx, sv.counts, sv.ioff, proj.n_tiles,
+                       reinterpret_cast<const float*>(bws + BL.rows), (uint64_t)capacity, g2d);
+  }
   return hipGetLastError();
 }
 
@@ -741,15 +685,15 @@ hipError_t launch_render_backward(const sx_projected& proj,
                                   const uint32_t* last, const float* dpartial,
                                   const float* ddepth, float* g2d, char* bws, int stages,
                                   hipStream_t st) {
-  RenderBwdArgs a = make_bwd_args(proj, vals, ranges, capacity, cam, p, mask, partial, last,
+  RenderBwdArgs a = make_bwd_args(proj, vals, ranges, sv, capacity, cam, p, mask, partial, last,
                                   dpartial, ddepth, bws);
   hipError_t e = hipSuccess;
-  if ((stages & SX_RB_PREPARE) && (e = launch_bwd_prepare(a, p, capacity, bws, st))) return e;
+  if ((stages & SX_RB_PREPARE) && (e = launch_bwd_prepare(a, p, st))) return e;
   if (stages & SX_RB_WALK) {
     SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_t, a, st);
     if ((e = hipGetLastError())) return e;
   }
-  if (stages & SX_RB_REDUCE) return launch_bwd_reduce(sv, n, capacity, p, g2d, bws, st);
+  if (stages & SX_RB_REDUCE) return launch_bwd_reduce(proj, sv, n, capacity, p, g2d, bws, st);
   return hipSuccess;
 }
 
@@ -804,17 +748,17 @@ hipError_t launch_render_multi(int V, const MultiView* mv, const KParams& p, cha
 
 hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, const KParams& p,
                                         char* ws, hipStream_t st) {
-  (void)ws, (void)n;
+  (void)ws;
   RenderBwdMultiArgs m;
   set_bases(V, mv, m);
   for (int v = 0; v < V; ++v) {
     KParams pv = p;
     pv.tiles_x = mv[v].tiles_x, pv.tiles_y = mv[v].tiles_y;
-    m.view[v] = make_bwd_args(mv[v].proj, mv[v].vals, mv[v].ranges, mv[v].capacity, mv[v].cam,
-                              pv, mv[v].mask, mv[v].partial, mv[v].last, mv[v].dpartial,
-                              nullptr, static_cast<char*>(mv[v].bwd_ws));
-    hipError_t e = launch_bwd_prepare(m.view[v], pv, mv[v].capacity,
-                                      static_cast<char*>(mv[v].bwd_ws), st);
+    const SortView sv = sort_view(mv[v].sort_ws, n, mv[v].capacity, pv.tiles_x, pv.tiles_y);
+    m.view[v] = make_bwd_args(mv[v].proj, mv[v].vals, mv[v].ranges, sv, mv[v].capacity,
+                              mv[v].cam, pv, mv[v].mask, mv[v].partial, mv[v].last,
+                              mv[v].dpartial, nullptr, static_cast<char*>(mv[v].bwd_ws));
+    hipError_t e = launch_bwd_prepare(m.view[v], pv, st);
     if (e) return e;
   }
   SX_DISPATCH_TILE(p.tile_w, p.tile_h, launch_bwd_multi_t, m, st);
@@ -825,8 +769,8 @@ hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams&
                                    hipStream_t st) {
   KParams pv = p;
   pv.tiles_x = v.tiles_x, pv.tiles_y = v.tiles_y;
-  return launch_bwd_reduce(sort_view(v.sort_ws, n, v.capacity, pv.tiles_x, pv.tiles_y), n,
-                           v.capacity, pv, v.g2d, static_cast<char*>(v.bwd_ws), st);
+  return launch_bwd_reduce(v.proj, sort_view(v.sort_ws, n, v.capacity, pv.tiles_x, pv.tiles_y),
+                           n, v.capacity, pv, v.g2d, static_cast<char*>(v.bwd_ws), st);
 }
 
 }  // namespace sx

@@ -104,6 +104,8 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
   L.bl_tot = take((size_t)tot_words * 4);
   L.zero_end = off;
   L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
+  L.inst_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
+  L.ioff = take((size_t)(n > 0 ? n : 1) * 4);
   L.scan_part = take((size_t)((L.nb + kScanTile - 1) / kScanTile + 1) * 16);
   for (int k = 0; k < 2; ++k) L.dkey[k] = take((size_t)(n > 0 ? n : 1) * 4);
   for (int k = 0; k < 2; ++k) L.didx[k] = take((size_t)(n > 0 ? n : 1) * 4);
@@ -131,19 +133,8 @@ BwdLayout bwd_layout(int64_t cap, int64_t tiles_total) {
   };
   const size_t c = (size_t)(cap > 0 ? cap : 1);
   const size_t t = (size_t)(tiles_total > 0 ? tiles_total : 1);
-  L.parts = (cap + kSortTile - 1) / kSortTile;
-  if (L.parts < 1) L.parts = 1;
-  L.zero_begin = off;
-  L.vcount = take(4 * sizeof(uint64_t));
-  L.vhist = take(4 * kRadixBins * 4);
-  L.counters = take(8 * 4);
-  L.zero_end = off;
-  L.vstatus = take((size_t)4 * L.parts * kRadixBins * 4);  // cleared per call, used part only
   L.nv = take(t * 4);
-  L.vb = take(t * 4);
   L.rows = take(c * kRowFloats * 4);
-  for (int k = 0; k < 2; ++k) L.pk[k] = take(c * 4);
-  for (int k = 0; k < 2; ++k) L.pv[k] = take(c * 4);
   L.total = off;
   return L;
 }
@@ -155,6 +146,7 @@ SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x,
   v.counts = reinterpret_cast<const uint64_t*>(b + L.counts);
   v.didx = reinterpret_cast<const uint32_t*>(b + L.didx[0]);
   v.vidx = reinterpret_cast<const uint32_t*>(b + L.vidx);
+  v.ioff = reinterpret_cast<const uint32_t*>(b + L.ioff);
   return v;
 }
 
@@ -190,34 +182,44 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ bsum, int64_t nb,
                                                     const uint64_t* __restrict__ part,
                                                     uint32_t* __restrict__ vis_off,
+                                                    uint32_t* __restrict__ inst_off,
                                                     uint64_t* counts, int64_t cap,
                                                     uint2* __restrict__ root_bin,
                                                     uint32_t* __restrict__ root_seg) {
   __shared__ unsigned long long s4[4];
   __shared__ uint32_t s_scan[4];
   const bool last = blockIdx.x == gridDim.x - 1;
-  uint64_t pv = 0, pi = 0;  // earlier tiles (the last tile: instances of all tiles)
+  // visible and instance sums of the earlier tiles; the last tile also
+  // sums the instances of all tiles
+  uint64_t pv = 0, pib = 0, pi = 0;
   for (uint32_t k = threadIdx.x; k < (last ? gridDim.x : blockIdx.x); k += 256) {
-    if (k < blockIdx.x) pv += part[2 * k];
+    if (k < blockIdx.x) pv += part[2 * k], pib += part[2 * k + 1];
     pi += part[2 * k + 1];
   }
   pv = block_sum256_u64(pv, s4);
+  pib = block_sum256_u64(pib, s4);
   if (last) pi = block_sum256_u64(pi, s4);
   const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t tsum = 0;
+  uint32_t v[kScanItems], iv[kScanItems];
+  uint32_t tsum = 0, isum = 0;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
     v[j] = b0 + j < nb ? bsum[2 * (b0 + j)] : 0u;
+    iv[j] = b0 + j < nb ? bsum[2 * (b0 + j) + 1] : 0u;
     tsum += v[j];
+    isum += iv[j];
   }
   uint32_t total;
   uint32_t run = (uint32_t)pv + block_excl_scan256(tsum, s_scan, &total);
+  // instance offsets: exact while the instances fit the 2^31 capacity bound
+  uint32_t irun = (uint32_t)pib + block_excl_scan256(isum, s_scan, nullptr);
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j)
     if (b0 + j < nb) {
       vis_off[b0 + j] = run;
+      inst_off[b0 + j] = irun;
       run += v[j];
+      irun += iv[j];
     }
   if (last && threadIdx.x == 0) {
     const bool over = pi > (uint64_t)cap;
@@ -237,25 +239,35 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 // order.  The index list stays untouched by the depth passes (the first one
 // reads it): the backward walks the visible Gaussians in this order, where
 // neighbouring lanes read neighbouring parameter rows.
+// Also gives every visible Gaussian the offset of its first (Gaussian, tile)
+// instance in index order, ioff[i]: the backward stores the gradient row of
+// instance (i, tile) at ioff[i] + the tile's raster position in i's tile
+// rectangle, so that each Gaussian's rows are contiguous.
 __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restrict__ n_tiles,
                                                        const float* __restrict__ rec, int64_t n,
                                                        const uint32_t* __restrict__ vis_off,
+                                                       const uint32_t* __restrict__ inst_off,
                                                        uint32_t* __restrict__ dkey,
-                                                       uint32_t* __restrict__ didx) {
+                                                       uint32_t* __restrict__ didx,
+                                                       uint32_t* __restrict__ ioff) {
+  static_assert(kPreBlock == 256, "the instance scan is a 256-lane block scan");
   __shared__ uint32_t sw[kPreBlock / 64];
+  __shared__ uint32_t s_scan[4];
   const int64_t i = (int64_t)blockIdx.x * kPreBlock + threadIdx.x;
-  const bool v = i < n && n_tiles[i] > 0;
+  const uint32_t nt = i < n ? n_tiles[i] : 0u;
+  const bool v = nt > 0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t b = __ballot(v);
   const uint32_t rank = __popcll(b & ((1ull << lane) - 1));
   if (lane == 0) sw[w] = __popcll(b);
-  __syncthreads();
+  const uint32_t iex = block_excl_scan256(nt, s_scan, nullptr);  // synchronises
   uint32_t pre = 0;
   for (int k = 0; k < w; ++k) pre += sw[k];
   if (v) {
     const uint32_t pos = vis_off[blockIdx.x] + pre + rank;
     dkey[pos] = __float_as_uint(rec[(size_t)i * kRecFloats + 9]);
     didx[pos] = (uint32_t)i;
+    ioff[i] = inst_off[blockIdx.x] + iex;
   }
 }
 
@@ -285,25 +297,6 @@ __global__ __launch_bounds__(kSortBlock) void k_hist_depth(const uint32_t* __res
   }
 }
 
-// Digit histograms (8-bit digits, npass passes) of *count keys.
-__global__ __launch_bounds__(kSortBlock) void k_hist_keys(const uint32_t* __restrict__ keys,
-                                                          const uint64_t* count, uint64_t cap,
-                                                          int npass, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[4][kRadixBins];
-  for (int k = threadIdx.x; k < 4 * kRadixBins; k += kSortBlock) (&h[0][0])[k] = 0;
-  __syncthreads();
-  const uint64_t n = *count < cap ? *count : cap;
-  for (uint64_t i = (uint64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * kSortBlock) {
-    const uint32_t k = keys[i];
-    for (int ps = 0; ps < npass; ++ps) atomicAdd(&h[ps][(k >> (8 * ps)) & 255], 1u);
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < npass * kRadixBins; k += kSortBlock) {
-    const uint32_t c = (&h[0][0])[k];
-    if (c) atomicAdd(&hist[k], c);
-  }
-}
 
 // ------------------------------------------------------------- onesweep --
 struct SweepArgs {
@@ -711,33 +704,6 @@ static void launch_pass(SweepArgs a, uint32_t parts, hipStream_t st) {
   hipLaunchKernelGGL(k_onesweep, dim3(grid > 0 ? grid : 1), dim3(kSortBlock), 0, st, a);
 }
 
-int launch_pair_sort(uint32_t* const keys[2], uint32_t* const vals[2], const uint64_t* count,
-                     uint64_t cap, int bits, uint32_t* hist, uint32_t* status, int64_t parts,
-                     uint32_t* counters, uint64_t* err, hipStream_t st, hipError_t* e) {
-  const int npass = bits <= 0 ? 1 : (bits + 7) / 8;
-  const unsigned grid = (unsigned)(parts < 1024 ? parts : 1024);
-  hipLaunchKernelGGL(k_hist_keys, dim3(grid), dim3(kSortBlock), 0, st, keys[0], count, cap,
-                     npass, hist);
-  for (int ps = 0; ps < npass; ++ps) {
-    SweepArgs a{};
-    a.keys_in = keys[ps & 1];
-    a.vals_in = vals[ps & 1];
-    a.keys_out = keys[(ps + 1) & 1];
-    a.vals_out = vals[(ps + 1) & 1];
-    a.count = count;
-    a.cap = cap;
-    a.skip = nullptr;
-    a.shift = 8 * ps;
-    a.bits = 8;
-    a.hist = hist + ps * kRadixBins;
-    a.status = status + (size_t)ps * parts * kRadixBins;
-    a.part_counter = counters + ps;
-    a.err = err;
-    launch_pass(a, (uint32_t)parts, st);
-  }
-  *e = hipGetLastError();
-  return npass & 1;
-}
 
 hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
                        int64_t capacity, int64_t tiles_total, uint64_t* keys,
@@ -761,7 +727,8 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(256), 0, st, proj.block_sums,
                        (int64_t)L.nb, part);
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, st, proj.block_sums,
-                       (int64_t)L.nb, part, u32(L.vis_off), counts, (int64_t)capacity,
+                       (int64_t)L.nb, part, u32(L.vis_off), u32(L.inst_off), counts,
+                       (int64_t)capacity,
                        reinterpret_cast<uint2*>(ws + L.bl_bins[0]), u32(L.bl_seg[0]));
   }
   if ((e = hipGetLastError())) return e;
@@ -778,7 +745,8 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
   }
   // phase 1: depth digits (bits 0..30; depth > 0, sign bit clear) in 8,8,8,7
   hipLaunchKernelGGL(k_compact, dim3((unsigned)L.nb), dim3(kPreBlock), 0, st, proj.n_tiles,
-                     proj.rec, n, u32(L.vis_off), u32(L.dkey[0]), u32(L.vidx));
+                     proj.rec, n, u32(L.vis_off), u32(L.inst_off), u32(L.dkey[0]), u32(L.vidx),
+                     u32(L.ioff));
   hipLaunchKernelGGL(k_hist_depth, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st,
                      u32(L.dkey[0]), counts, u32(L.dhist));
   uint32_t* counters = u32(L.counters);
