@@ -528,6 +528,7 @@ struct BinLevel {
   uint64_t* __restrict__ keys;    // last level, optional
   const float* __restrict__ rec;
   int last;
+  int inline_scan;  // few children: the write pass scans the totals itself
 };
 
 // Segment `sg`: its parent, first entry and entry count.
@@ -600,8 +601,7 @@ __global__ __launch_bounds__(1024) void k_bin_count(BinLevel a) {
 // One block: exclusive scan of the children's totals (their list starts;
 // tile ranges at the last level) and, for inner levels, of their segment
 // counts.
-__global__ __launch_bounds__(1024) void k_bin_scan(BinLevel a) {
-  __shared__ uint32_t s_a[1024], s_b[1024];
+__device__ __forceinline__ void bin_scan(const BinLevel& a, uint32_t* s_a, uint32_t* s_b) {
   const int tid = threadIdx.x;
   const int C = a.cgx * a.cgy;
   const int chunk = (C + 1023) / 1024;
@@ -636,11 +636,25 @@ __global__ __launch_bounds__(1024) void k_bin_scan(BinLevel a) {
   if (!a.last && tid == 1023) a.cseg[C] = s_b[1023];
 }
 
+__global__ __launch_bounds__(1024) void k_bin_scan(BinLevel a) {
+  __shared__ uint32_t s_a[1024], s_b[1024];
+  bin_scan(a, s_a, s_b);
+}
+
 // Write pass: every wavefront appends the entries of its child in order.
+// With inline_scan (at most kInlineChildren children) there is no scan
+// launch: each wavefront sums the totals of the children before its own,
+// and workgroup 0 also writes the scan's outputs for the next level.
+constexpr int kInlineChildren = 1024;
+
 __global__ __launch_bounds__(1024) void k_bin_write(BinLevel a) {
   __shared__ uint32_t s_g[kBinSeg];
   __shared__ ushort4 s_rc[kBinSeg];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (a.inline_scan && blockIdx.x == 0) {
+    __shared__ uint32_t s_a[1024], s_b[1024];
+    bin_scan(a, s_a, s_b);
+  }
   const uint32_t nseg = a.pseg[a.pgx * a.pgy];
   const uint64_t lt = (1ull << lane) - 1ull;
   for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
@@ -654,7 +668,14 @@ __global__ __launch_bounds__(1024) void k_bin_write(BinLevel a) {
     uint32_t base = 0;
     for (uint32_t q = a.pseg[p] + lane; q < sg; q += 64) base += a.cnt[(size_t)q * 16 + w];
     for (int o = 32; o >= 1; o >>= 1) base += __shfl_xor(base, o, 64);
-    base += a.last ? a.ranges[2 * (size_t)c] : a.cbins[c].x;
+    if (a.inline_scan) {
+      uint32_t start = 0;
+      for (int q = lane; q < c; q += 64) start += a.tot[q];
+      for (int o = 32; o >= 1; o >>= 1) start += __shfl_xor(start, o, 64);
+      base += start;
+    } else {
+      base += a.last ? a.ranges[2 * (size_t)c] : a.cbins[c].x;
+    }
     const uint64_t zkey = (uint64_t)c << 32;
     for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
       const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
@@ -808,8 +829,9 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     const int64_t nparents = (int64_t)a.pgx * a.pgy;
     const int64_t segs_max = capacity / kBinSeg + nparents + 1;
     const unsigned grid = (unsigned)(segs_max < 4096 ? segs_max : 4096);
+    a.inline_scan = a.cgx * a.cgy <= kInlineChildren;
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(1024), 0, st, a);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, a);
+    if (!a.inline_scan) hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, a);
     hipLaunchKernelGGL(k_bin_write, dim3(grid), dim3(1024), 0, st, a);
     in = a.out;
     cur ^= 1;

@@ -133,6 +133,40 @@ def test_invalid_arguments_are_rejected_on_host(L):
     # backward: K out of range
     assert L.sx_backward(ctypes.c_int32(0), None, None, ctypes.byref(cam), ctypes.byref(good),
                          None, ctypes.c_int32(0), None) == B.SX_EINVAL
+    # re-evaluating composition: masks and budget are required
+    cells[0].lo[0], cells[0].hi[0] = 0.0, 1.0
+    assert L.sx_composite_reeval(ctypes.c_int32(1), parts, cells, ctypes.byref(cam),
+                                 ctypes.byref(good), ctypes.c_void_p(1), None, None,
+                                 ctypes.c_void_p(1), None) == B.SX_EINVAL
+    assert L.sx_composite_reeval(ctypes.c_int32(1), parts, cells, ctypes.byref(cam),
+                                 ctypes.byref(good), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                                 None, None, None) == B.SX_EINVAL
+    # cross-boundary filter: cell outside 0..K-1, K out of range, inverted box
+    g.n = 10
+    g.means = g.log_scales = g.quats = ctypes.c_void_p(1)
+    cells2 = (B.SxCell * 2)()
+    for c in cells2:
+        c.hi[0] = c.hi[1] = c.hi[2] = 1.0
+    for K, cell in ((2, 2), (2, -1), (0, 0), (17, 0)):
+        assert L.sx_cross_filter(ctypes.byref(g), ctypes.byref(proj), ctypes.c_int32(K), cells2,
+                                 ctypes.c_int32(cell), ctypes.byref(cam), ctypes.c_void_p(1),
+                                 None) == B.SX_EINVAL, (K, cell)
+    cells2[1].lo[2] = 2.0
+    assert L.sx_cross_filter(ctypes.byref(g), ctypes.byref(proj), ctypes.c_int32(2), cells2,
+                             ctypes.c_int32(0), ctypes.byref(cam), ctypes.c_void_p(1),
+                             None) == B.SX_EINVAL
+    # a projection that asks for the filter must bring the maps and a valid cell
+    proj.xf = ctypes.c_void_p(1)
+    proj.n_cells, proj.cell = 2, 0
+    assert L.sx_render_partial(ctypes.byref(proj), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                               ctypes.byref(cam), ctypes.byref(good), None, ctypes.c_void_p(1),
+                               None, ctypes.c_void_p(1), None, None) == B.SX_EINVAL
+    proj.omega = ctypes.c_void_p(1)
+    proj.cell = 2
+    assert L.sx_render_partial(ctypes.byref(proj), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                               ctypes.byref(cam), ctypes.byref(good), None, ctypes.c_void_p(1),
+                               None, ctypes.c_void_p(1), None, None) == B.SX_EINVAL
+    assert b"cross-boundary" in L.sx_last_error_string()
 
 
 def test_missing_library_fails_loudly(monkeypatch):

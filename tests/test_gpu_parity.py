@@ -544,6 +544,41 @@ def test_cross_boundary_filter_matches_oracle(torch_gpu, cells_kind):
             assert rel_err(got, gref[k][name][v]) <= 2e-3, (k, name)
 
 
+def test_cross_boundary_filter_degenerate_cases(torch_gpu):
+    """One cell (no other box to span): every filter bit is zero and the
+    filtered render equals the unfiltered one bit for bit; an empty cell
+    renders the identity with the filter on; the batched renders refuse a
+    projection that asks for the filter."""
+    print("case: cross-boundary filter k1 / empty / batched", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    from paper_2606_18588_amd.pipeline import Frame, GaussianParams
+    scene, cam = synth.tiny_scene(), synth.tiny_camera(100, 70)
+    box = [big_box()]
+    plain = Frame([GaussianParams.from_scene(scene)], box, cam, ST)
+    filt = Frame([GaussianParams.from_scene(scene)], box, cam, ST, cross_filter=True)
+    a = plain.forward().cpu().numpy()
+    b = filt.forward().cpu().numpy()
+    torch.cuda.synchronize()
+    assert not filt.views[0].xf.cpu().numpy()[:scene.n].any()
+    assert np.array_equal(a, b)
+    empty = Frame([GaussianParams.from_scene(scene.subset(np.array([], np.int64)))], box, cam, ST,
+                  cross_filter=True)
+    out = empty.forward().cpu().numpy()
+    assert np.all(out[..., :3] == 0) and np.all(out[..., 3] == 1)
+    from paper_2606_18588_amd.pipeline import BatchedViews
+    bv = BatchedViews(GaussianParams.from_scene(scene), [cam, cam], ST)
+    bv.preprocess()
+    bv.sort()
+    B.set_cross_filter(bv.views[0].c_proj, filt.views[0].xf, filt.omega, 0, 1)
+    with pytest.raises(B.SplaxelError) as ei:
+        bv.render()
+    assert ei.value.code == B.SX_EINVAL
+    B.set_cross_filter(bv.views[0].c_proj, None, None, 0, 0)
+    bv.render()
+    torch.cuda.synchronize()
+
+
 def test_composite_kd_cells_matches_oracle(torch_gpu):
     """K = 8 cells from the KD-tree partitioner (boxes bounded on some axes,
     unbounded at the scene's outside): the composition by ray entry order
