@@ -143,22 +143,38 @@ __device__ __forceinline__ bool project_geometry(const GIn& gi, const DCam& cam,
 // runs in FP32 with margins far above its rounding error (it only has to
 // never drop a Gaussian the exact FP64 test in project_one would keep).
 __device__ __forceinline__ bool maybe_visible(const PreArgs& a, int64_t i) {
-  // every value the test reads is loaded before the first branch
+  // the mean decides most culls (depth, and the guarded field of view that
+  // project_one applies to the mean), so only the Gaussians that pass it
+  // read their opacity and scales
   const float mx = a.means[i * 3 + 0], my = a.means[i * 3 + 1], mz = a.means[i * 3 + 2];
-  const float lgt = a.logits[i];
-  const float ls = fmaxf(fmaxf(a.log_scales[i * 3 + 0], a.log_scales[i * 3 + 1]),
-                         a.log_scales[i * 3 + 2]);
   const float* R = a.cull.R;
   const float p6 = R[6] * mx, p7 = R[7] * my, p8 = R[8] * mz;
   const float tz = p6 + p7 + p8 + a.cull.t[2];
   const float zslack = 1e-5f * (fabsf(p6) + fabsf(p7) + fabsf(p8) + fabsf(a.cull.t[2])) + 1e-6f;
   if (tz + zslack <= a.cull.znear) return false;
-  if (lgt < a.cull.logit_min) return false;
   const float tzc = fmaxf(tz, a.cull.znear * 0.5f);
-  const float tx = R[0] * mx + R[1] * my + R[2] * mz + a.cull.t[0];
-  const float ty = R[3] * mx + R[4] * my + R[5] * mz + a.cull.t[1];
-  const float s2 = __expf(2.f * ls);
+  const float p0 = R[0] * mx, p1 = R[1] * my, p2 = R[2] * mz;
+  const float p3 = R[3] * mx, p4 = R[4] * my, p5 = R[5] * mz;
+  const float tx = p0 + p1 + p2 + a.cull.t[0];
+  const float ty = p3 + p4 + p5 + a.cull.t[1];
   const float iz = 1.f / tzc;
+  const float gd = (float)a.p.fov_guard;
+  if (gd > 0.f) {
+    // FP32 image of the FP64 test, widened far beyond its rounding error
+    // (relative, and the absolute error of tx, ty scaled to pixels)
+    const float qx = a.cull.fx * tx * iz, qy = a.cull.fy * ty * iz;
+    const float ex = 1e-5f * (fabsf(p0) + fabsf(p1) + fabsf(p2) + fabsf(a.cull.t[0]));
+    const float ey = 1e-5f * (fabsf(p3) + fabsf(p4) + fabsf(p5) + fabsf(a.cull.t[1]));
+    const float mgx = 1e-4f * (fabsf(qx) + gd * (float)a.cam.W) + a.cull.fx * iz * ex + 1.f;
+    const float mgy = 1e-4f * (fabsf(qy) + gd * (float)a.cam.H) + a.cull.fy * iz * ey + 1.f;
+    if (qx < -gd * a.cull.cx - mgx || qx > gd * ((float)a.cam.W - a.cull.cx) + mgx) return false;
+    if (qy < -gd * a.cull.cy - mgy || qy > gd * ((float)a.cam.H - a.cull.cy) + mgy) return false;
+  }
+  const float lgt = a.logits[i];
+  if (lgt < a.cull.logit_min) return false;
+  const float ls = fmaxf(fmaxf(a.log_scales[i * 3 + 0], a.log_scales[i * 3 + 1]),
+                         a.log_scales[i * 3 + 2]);
+  const float s2 = __expf(2.f * ls);
   const float jx = a.cull.fx * iz, jy = a.cull.fy * iz;
   const float jf = jx * jx * (1.f + tx * tx * iz * iz) + jy * jy * (1.f + ty * ty * iz * iz);
   const float E = sqrtf(a.cull.tau_max * (s2 * jf + a.cull.eps2d)) * 1.01f + 2.f;

@@ -636,7 +636,59 @@ __device__ __forceinline__ void bin_scan(const BinLevel& a, uint32_t* s_a, uint3
   if (!a.last && tid == 1023) a.cseg[C] = s_b[1023];
 }
 
+// The same scan for up to kScanLds children: the totals are read once,
+// coalesced, into LDS, and scanned with wavefront shuffles and one
+// cross-wavefront step instead of a barrier per Hillis-Steele round.
+constexpr int kScanLds = 8192;
+
+__device__ __forceinline__ void bin_scan_lds(const BinLevel& a, uint32_t* s_t) {
+  __shared__ uint32_t s_wa[16], s_wb[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int C = a.cgx * a.cgy;
+  for (int c = tid; c < C; c += 1024) s_t[c] = a.tot[c];
+  __syncthreads();
+  constexpr int chunk = kScanLds / 1024;
+  const int beg = tid * chunk, end = beg + chunk < C ? beg + chunk : C;
+  uint32_t sa = 0, sb = 0;
+  for (int c = beg; c < end; ++c) {
+    const uint32_t t = s_t[c];
+    sa += t;
+    sb += (t + kBinSeg - 1) / kBinSeg;
+  }
+  uint32_t xa = sa, xb = sb;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t ya = __shfl_up(xa, o, 64), yb = __shfl_up(xb, o, 64);
+    if (lane >= o) xa += ya, xb += yb;
+  }
+  if (lane == 63) s_wa[w] = xa, s_wb[w] = xb;
+  __syncthreads();
+  uint32_t pa = 0, pb = 0, tb = 0;
+  for (int k = 0; k < 16; ++k) {
+    if (k < w) pa += s_wa[k], pb += s_wb[k];
+    tb += s_wb[k];
+  }
+  uint32_t ra = pa + xa - sa, rb = pb + xb - sb;
+  for (int c = beg; c < end; ++c) {
+    const uint32_t t = s_t[c];
+    if (a.last) {
+      a.ranges[2 * (size_t)c] = ra;
+      a.ranges[2 * (size_t)c + 1] = ra + t;
+    } else {
+      a.cbins[c] = make_uint2(ra, t);
+      a.cseg[c] = rb;
+    }
+    ra += t;
+    rb += (t + kBinSeg - 1) / kBinSeg;
+  }
+  if (!a.last && tid == 0) a.cseg[C] = tb;
+}
+
 __global__ __launch_bounds__(1024) void k_bin_scan(BinLevel a) {
+  if (a.cgx * a.cgy <= kScanLds) {
+    __shared__ uint32_t s_t[kScanLds];
+    bin_scan_lds(a, s_t);
+    return;
+  }
   __shared__ uint32_t s_a[1024], s_b[1024];
   bin_scan(a, s_a, s_b);
 }
