@@ -235,70 +235,6 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
   }
 }
 
-// The same scan in one workgroup when there are at most kScanOne blocks
-// (one launch instead of two; 16 blocks per thread, wavefront shuffles and
-// one cross-wavefront step).
-constexpr int kScanOneItems = 16;
-constexpr int64_t kScanOne = 1024 * kScanOneItems;
-
-__global__ __launch_bounds__(1024) void k_scan_one(const uint32_t* __restrict__ bsum, int64_t nb,
-                                                   uint32_t* __restrict__ vis_off,
-                                                   uint32_t* __restrict__ inst_off,
-                                                   uint64_t* counts, int64_t cap,
-                                                   uint2* __restrict__ root_bin,
-                                                   uint32_t* __restrict__ root_seg) {
-  __shared__ uint32_t s_v[16];
-  __shared__ unsigned long long s_i[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t b0 = (int64_t)tid * kScanOneItems;
-  uint32_t v[kScanOneItems], iv[kScanOneItems];
-  uint32_t tv = 0;
-  uint64_t ti = 0;
-#pragma unroll
-  for (int j = 0; j < kScanOneItems; ++j) {
-    v[j] = b0 + j < nb ? bsum[2 * (b0 + j)] : 0u;
-    iv[j] = b0 + j < nb ? bsum[2 * (b0 + j) + 1] : 0u;
-    tv += v[j];
-    ti += iv[j];
-  }
-  uint32_t xv = tv;
-  uint64_t xi = ti;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t yv = __shfl_up(xv, o, 64);
-    const uint64_t yi = __shfl_up(xi, o, 64);
-    if (lane >= o) xv += yv, xi += yi;
-  }
-  if (lane == 63) s_v[w] = xv, s_i[w] = xi;
-  __syncthreads();
-  uint32_t pv = 0, allv = 0;
-  uint64_t pi = 0, alli = 0;
-  for (int k = 0; k < 16; ++k) {
-    if (k < w) pv += s_v[k], pi += s_i[k];
-    allv += s_v[k];
-    alli += s_i[k];
-  }
-  uint32_t run = pv + xv - tv;
-  uint64_t irun = pi + xi - ti;  // stored as uint32: exact within the capacity bound
-#pragma unroll
-  for (int j = 0; j < kScanOneItems; ++j)
-    if (b0 + j < nb) {
-      vis_off[b0 + j] = run;
-      inst_off[b0 + j] = (uint32_t)irun;
-      run += v[j];
-      irun += iv[j];
-    }
-  if (tid == 0) {
-    const bool over = alli > (uint64_t)cap;
-    counts[0] = allv;
-    counts[1] = alli;
-    counts[2] = over ? 1ull : 0ull;
-    const uint32_t nvis = over ? 0u : allv;
-    root_bin[0] = make_uint2(0u, nvis);
-    root_seg[0] = 0;
-    root_seg[1] = (nvis + kBinSeg - 1) / kBinSeg;
-  }
-}
-
 // Compacted (depth bits, Gaussian index) list of visible Gaussians in index
 // order.  The index list stays untouched by the depth passes (the first one
 // reads it): the backward walks the visible Gaussians in this order, where
@@ -859,20 +795,14 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     return hipSuccess;
   }
   {
-    uint2* root_bin = reinterpret_cast<uint2*>(ws + L.bl_bins[0]);
-    if (L.nb <= kScanOne) {
-      hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, proj.block_sums,
-                         (int64_t)L.nb, u32(L.vis_off), u32(L.inst_off), counts,
-                         (int64_t)capacity, root_bin, u32(L.bl_seg[0]));
-    } else {
-      const unsigned tiles = (unsigned)((L.nb + kScanTile - 1) / kScanTile);
-      uint64_t* part = reinterpret_cast<uint64_t*>(ws + L.scan_part);
-      hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(256), 0, st, proj.block_sums,
-                         (int64_t)L.nb, part);
-      hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, st, proj.block_sums,
-                         (int64_t)L.nb, part, u32(L.vis_off), u32(L.inst_off), counts,
-                         (int64_t)capacity, root_bin, u32(L.bl_seg[0]));
-    }
+    const unsigned tiles = (unsigned)((L.nb + kScanTile - 1) / kScanTile);
+    uint64_t* part = reinterpret_cast<uint64_t*>(ws + L.scan_part);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(256), 0, st, proj.block_sums,
+                       (int64_t)L.nb, part);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, st, proj.block_sums,
+                       (int64_t)L.nb, part, u32(L.vis_off), u32(L.inst_off), counts,
+                       (int64_t)capacity, reinterpret_cast<uint2*>(ws + L.bl_bins[0]),
+                       u32(L.bl_seg[0]));
   }
   if ((e = hipGetLastError())) return e;
   if (h_counts) {
