@@ -801,8 +801,8 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
                        (int64_t)L.nb, part);
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, st, proj.block_sums,
                        (int64_t)L.nb, part, u32(L.vis_off), u32(L.inst_off), counts,
-                       (int64_t)capacity, reinterpret_cast<uint2*>(ws + L.bl_bins[0]),
-                       u32(L.bl_seg[0]));
+                       (int64_t)capacity,
+                       reinterpret_cast<uint2*>(ws + L.bl_bins[0]), u32(L.bl_seg[0]));
   }
   if ((e = hipGetLastError())) return e;
   if (h_counts) {
