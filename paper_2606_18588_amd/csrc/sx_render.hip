@@ -52,17 +52,16 @@ __device__ __forceinline__ uint32_t filter_bits(const uint32_t* __restrict__ ome
 // wavefront then walks the batch reading each record as a broadcast.  Each
 // wavefront owns its slice, so no workgroup barrier is needed.
 //
-// A pixel blends a Gaussian only inside the pixel box of its exact
-// alpha >= alpha_min footprint (outside it alpha < alpha_min in exact
-// arithmetic).  While staging a batch every lane tests its entry's box
-// against the wavefront's pixel rectangle; the ballot of the results is the
-// set of entries the wavefront walks, in order, two records per LDS round
-// trip.
+// Outside the pixel box of a Gaussian's exact alpha >= alpha_min footprint
+// alpha < alpha_min in exact arithmetic.  While staging a batch every lane
+// tests its entry's box against the wavefront's pixel rectangle; the ballot
+// of the results is the set of entries the wavefront walks, in order, two
+// records per LDS round trip.  Inside a walked rectangle the alpha test
+// alone decides (a pixel outside the box can pass it only within FP32
+// rounding of the footprint's edge, where the FP64 decision is ambiguous
+// anyway); the reverse walk partitions the tile into the same rectangles,
+// so forward and backward evaluate the same pairs.
 // The box words hold (x0 | (x1 - x0) << 16) and (y0 | (y1 - y0) << 16).
-__device__ __forceinline__ bool in_box(int px, int py, float bxw, float byw) {
-  const uint32_t bx = __float_as_uint(bxw), by = __float_as_uint(byw);
-  return (uint32_t)px - (bx & 0xFFFFu) <= (bx >> 16) && (uint32_t)py - (by & 0xFFFFu) <= (by >> 16);
-}
 // The box meets the pixel rectangle [x0, x1] x [y0, y1].
 __device__ __forceinline__ bool box_meets(float bxw, float byw, int x0, int x1, int y0, int y1) {
   const uint32_t bx = __float_as_uint(bxw), by = __float_as_uint(byw);
@@ -111,8 +110,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
     auto blend = [&](const float4& r0, const float4& r1, const float4& r2, uint32_t kc,
                      uint32_t xe) {
       const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-      const bool use = !done && ae.alpha >= a.alpha_min && in_box(px, py, r2.z, r2.w) &&
-                       (!FILT || (xe & pbits) == 0u);
+      const bool use = !done && ae.alpha >= a.alpha_min && (!FILT || (xe & pbits) == 0u);
       const float al = use ? ae.alpha : 0.f;
       const float wt = al * T;
       C0 = fmaf(r1.z, wt, C0);
@@ -340,7 +338,6 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       const float dx = fx[k] - r0.x, dy = fy[k] - r0.y;
       const AlphaEval ae = eval_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
       const bool use = (uint32_t)j < lst[k] && ae.alpha >= a.alpha_min &&
-                       in_box((int)(pxy[k] & 0xFFFFu), (int)(pxy[k] >> 16), r2.z, r2.w) &&
                        (!FILT || (xe & pbits[k]) == 0u);
       any = any || use;
       const float al = use ? ae.alpha : 0.f;
