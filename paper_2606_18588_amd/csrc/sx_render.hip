@@ -111,6 +111,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
                      uint32_t xe) {
       const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
       const bool use = !done && ae.alpha >= a.alpha_min && (!FILT || (xe & pbits) == 0u);
+      if (__ballot(use) == 0) return;  // nothing to blend in this rectangle
       const float al = use ? ae.alpha : 0.f;
       const float wt = al * T;
       C0 = fmaf(r1.z, wt, C0);
@@ -339,7 +340,9 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       const AlphaEval ae = eval_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
       const bool use = (uint32_t)j < lst[k] && ae.alpha >= a.alpha_min &&
                        (!FILT || (xe & pbits[k]) == 0u);
-      any = any || use;
+      // no pixel of the group blends: the chain below would change nothing
+      if (__ballot(use) == 0) continue;
+      any = true;
       const float al = use ? ae.alpha : 0.f;
       const float om = 1.f - al;  // >= 1 - alpha_max
       const float rom = __builtin_amdgcn_rcpf(om);
@@ -375,7 +378,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       v[3] = fmaf(qx + qx, dy, v[3]);
       v[4] = fmaf(qy, dy, v[4]);
     }
-    if (__ballot(any) == 0) {
+    if (!any) {
       if (lane == 63 && in_cap) {
         const float2 z = make_float2(0.f, 0.f);
         dst[0] = z, dst[1] = z, dst[2] = z, dst[3] = z, dst[4] = z;
