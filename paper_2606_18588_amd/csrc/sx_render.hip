@@ -294,10 +294,19 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     gtf[k] = gt * Tf;
     R0[k] = R1[k] = R2[k] = RD[k] = 0.f;
   }
+  // per pixel group, the entries any of its pixels reached
+  uint32_t gmax[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    uint32_t m = lst[k];
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    gmax[k] = __builtin_amdgcn_readfirstlane(m);
+  }
   for (int jend = (int)wave_last; jend > 0; jend -= 64) {
     // stage entries [jend - cnt, jend): lane i gathers entry jend - cnt + i,
     // stores its (Gaussian, row) pair and tests its pixel box against each
-    // pixel group; gm[k] bit i = entry j0 + i can reach group k
+    // pixel group; gm[k] bit i = entry j0 + i can reach group k and some
+    // pixel of the group reached the entry
     const int cnt = jend < 64 ? jend : 64;
     const int j0 = jend - cnt;
     bool mk[PPT];
@@ -313,7 +322,8 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       if (FILT) s_xf[lane] = a.xf[gl];
 #pragma unroll
       for (int k = 0; k < PPT; ++k)
-        mk[k] = box_meets(q2.z, q2.w, tx * TW, tx * TW + TW - 1, ty * TH + k * WR,
+        mk[k] = (uint32_t)(j0 + lane) < gmax[k] &&
+                box_meets(q2.z, q2.w, tx * TW, tx * TW + TW - 1, ty * TH + k * WR,
                           ty * TH + k * WR + WR - 1);
       s_e[lane] = instance_row(a, gl, tx, ty);
     }
