@@ -98,9 +98,9 @@ typedef struct sx_gaussians {
  *               inverse 2D covariance (3), opacity, rgb (3), camera depth,
  *               then the pixel box [x0, x1] x [y0, y1] of the exact
  *               alpha >= alpha_min footprint as two uint32 words
- *               x0 | (x1 - x0) << 16 and y0 | (y1 - y0) << 16 (the render
- *               blends a pixel only inside it).  Valid only where
- *               n_tiles > 0.
+ *               x0 | (x1 - x0) << 16 and y0 | (y1 - y0) << 16 (the
+ *               render walks an entry only for the pixel rectangles its
+ *               box meets).  Valid only where n_tiles > 0.
  *   rect[n*4]   uint16 tile rectangle [x0, y0, x1, y1) of the exact
  *               alpha >= alpha_min footprint.
  *   n_tiles[n]  tiles touched; 0 = culled.

@@ -304,9 +304,9 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
   }
   for (int jend = (int)wave_last; jend > 0; jend -= 64) {
     // stage entries [jend - cnt, jend): lane i gathers entry jend - cnt + i,
-    // stores its (Gaussian, row) pair and tests its pixel box against each
-    // pixel group; gm[k] bit i = entry j0 + i can reach group k and some
-    // pixel of the group reached the entry
+    // stores its record and gradient row and tests its pixel box against
+    // each pixel group; gm[k] bit i = entry j0 + i can reach group k and
+    // some pixel of the group reached the entry
     const int cnt = jend < 64 ? jend : 64;
     const int j0 = jend - cnt;
     bool mk[PPT];
