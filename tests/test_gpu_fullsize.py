@@ -195,3 +195,52 @@ def test_fullsize_k8_composite_and_backward(g8):
             got = getattr(grads[k], name).cpu().numpy()[vis]
             assert rel_err(got, gref[k][name][vis]) <= 2e-3, (k, name)
     assert hit > 100
+
+
+def test_fullsize_k8_cross_filter_and_reeval(g8):
+    """The K = 8 benchmark configuration with both options of the redundancy
+    reduction on: per-ray cross-boundary filtering and speculative
+    re-evaluation of the saturation state, starting from the geometric
+    maps.  Filter bits of all 8M Gaussians bit-exact where the oracle's
+    decision is not within rounding reach; on sampled tiles the composed
+    image, the new state and the budgets against the oracle."""
+    print("case: full-size K=8 cross filter + re-evaluation on sampled tiles", flush=True)
+    torch, scenes, cells, cam = g8["torch"], g8["scenes"], g8["cells"], g8["cam"]
+    from paper_2606_18588_amd.pipeline import Frame
+    K, H, W = len(scenes), cam.height, cam.width
+    fr = Frame(g8["params"], cells, cam, ST, cross_filter=True)
+    fr.init_masks(geometric=True, reeval=True)
+    out = fr.forward(use_masks=True, update_masks=True).cpu().numpy()
+    torch.cuda.synchronize()
+    vis = oracle.visibility(cells, cam)
+    om = vis["vis"]
+    xfs = oracle.cross_filters(scenes, cells, cam, ST)
+    nfilt = 0
+    for k in range(K):
+        got = fr.views[k].xf.cpu().numpy().view(np.uint32)[:scenes[k].n]
+        ok = xfs[k]["amb"] == 0
+        assert_same(got[ok], xfs[k]["xf"][ok], f"filter bits of cell {k}")
+        nfilt += int((xfs[k]["xf"] != 0).sum())
+    assert nfilt > 1000
+    tiles, tx, ty = _sample_tiles(cam, seed=9, count=24)
+    m = _tile_mask(cam, tiles, tx)
+    state = (om & m[None]).astype(np.uint8)
+    ref = oracle.forward(scenes, cells, cam, ST, masks=state, xfilters=xfs)
+    budget = np.zeros((K, H, W))
+    rr = oracle.composite_reeval(ref.Cparts, ref.Tparts, cells, cam, ST, state, budget, omega=om)
+    fl = rr["flags"] | (vis["flags"] != 0)
+    for p in ref.parts:
+        fl |= p["flags"]
+    on = m == 1
+    cmax = max(float(rec_fields(v.rec)["rgb"][v.n_tiles.cpu().numpy() > 0].max(initial=0.0))
+               for v in fr.views)
+    e, nf = compare_image(out[on][:, :3], rr["rgb"][on], fl[on], 1e-4, K * jump_bound(ST, cmax))
+    compare_image(out[on][:, 3], rr["T"][on], fl[on], 1e-4, 1.0)
+    ok = (on & (fl == 0)).reshape(-1)
+    bits = np.unpackbits(fr.masks.cpu().numpy().view(np.uint8), bitorder="little").reshape(K, -1)[:, :H * W]
+    assert_same(bits[:, ok], rr["mask"].reshape(K, -1)[:, ok], "state after the render")
+    np.testing.assert_allclose(fr.budget.cpu().numpy().reshape(K, -1)[:, ok],
+                               budget.reshape(K, -1)[:, ok], rtol=1e-3, atol=1e-10)
+    pruned = int(((rr["mask"] == 0) & (om == 1)).reshape(K, -1)[:, ok].sum())
+    print(f"full-size K=8 filtered + re-evaluated: {nfilt} filtered Gaussians, "
+          f"max-abs {e:.3g}, flagged {nf}, pruned pairs {pruned}", flush=True)
