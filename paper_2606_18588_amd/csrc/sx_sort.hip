@@ -306,7 +306,6 @@ struct SweepArgs {
   uint32_t* __restrict__ vals_out;
   const uint64_t* count;
   uint64_t cap;
-  const uint64_t* skip;  // if non-null and *skip != 0, the pass sorts nothing
   int shift, bits;
   const uint32_t* __restrict__ hist;
   uint32_t* status;
@@ -325,7 +324,6 @@ struct SweepArgs {
 __device__ __forceinline__ uint32_t sweep_n(const SweepArgs& a) {
   uint64_t n64 = *a.count;
   if (n64 > a.cap) n64 = a.cap;
-  if (a.skip && *a.skip != 0) n64 = 0;
   return (uint32_t)n64;
 }
 
@@ -832,7 +830,6 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     a.vals_out = u32(L.didx[(ps + 1) & 1]);
     a.count = counts;
     a.cap = (uint64_t)n;
-    a.skip = nullptr;
     a.shift = 8 * ps;
     a.bits = ps == 3 ? 7 : 8;
     a.hist = u32(L.dhist) + ps * kRadixBins;
