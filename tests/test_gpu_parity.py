@@ -409,7 +409,8 @@ def test_composite_with_visibility_matches_oracle(torch_gpu):
           f"invisible pairs {(vis['vis'] == 0).sum()}", flush=True)
 
 
-def test_composite_reeval_three_renders_match_oracle(torch_gpu):
+@pytest.mark.parametrize("geometric", [True, False])
+def test_composite_reeval_three_renders_match_oracle(torch_gpu, geometric):
     """Saturation carried across three renders of one view with speculative
     re-evaluation: KD cells starting from their geometric maps; render 1
     prunes pairs behind saturated prefixes and keeps their budgets; the
@@ -427,10 +428,11 @@ def test_composite_reeval_three_renders_match_oracle(torch_gpu):
     scenes = [scene.subset(np.nonzero(cell_of == k)[0]) for k in range(8)]
     K, H, W = 8, cam.height, cam.width
     fr, params = _frame(torch, scenes, boxes, cam)
-    fr.init_masks(geometric=True, reeval=True)
+    fr.init_masks(geometric=geometric, reeval=True)
     vis = oracle.visibility(boxes, cam)
     assert not vis["flags"].any()
-    om = vis["vis"]
+    # without the geometric maps every box counts as met by every ray
+    om = vis["vis"] if geometric else np.ones((K, H, W), np.uint8)
     state, budget = om.copy(), np.zeros((K, H, W))
     faded = [s.subset(np.arange(s.n)) for s in scenes]
     for s in faded:
@@ -445,7 +447,7 @@ def test_composite_reeval_three_renders_match_oracle(torch_gpu):
         torch.cuda.synchronize()
         ref = oracle.forward(scs, boxes, cam, ST, masks=state)
         rr = oracle.composite_reeval(ref.Cparts, ref.Tparts, boxes, cam, ST, state, budget,
-                                     omega=om)
+                                     omega=om if geometric else None)
         for p in ref.parts:
             bad |= p["flags"] != 0
         bad |= rr["flags"] != 0
@@ -468,13 +470,15 @@ def test_composite_reeval_three_renders_match_oracle(torch_gpu):
     assert stats[1][1] > 500 and stats[1][0] > 1000
 
 
-@pytest.mark.parametrize("cells_kind", ["grid", "kd"])
-def test_cross_boundary_filter_matches_oracle(torch_gpu, cells_kind):
+@pytest.mark.parametrize("cells_kind,tile", [("grid", (16, 16)), ("kd", (16, 16)),
+                                             ("grid", (32, 8))])
+def test_cross_boundary_filter_matches_oracle(torch_gpu, cells_kind, tile):
     """Per-ray cross-boundary filtering on K = 8 cells: the filter bits of
     every Gaussian bit-exact where the oracle's decision is not within
     rounding reach, and the filtered renders, composition, masks and
     gradients against the oracle run with its own bits."""
-    print(f"case: cross-boundary filter k8 {cells_kind}", flush=True)
+    print(f"case: cross-boundary filter k8 {cells_kind} tile {tile}", flush=True)
+    st = synth.RenderSettings(tile_w=tile[0], tile_h=tile[1])
     torch = torch_gpu
     from paper_2606_18588_amd import binding as B
     scene = synth.make_cube_scene(6, 9000, log_scale=(-3.0, 0.5))
@@ -494,13 +498,13 @@ def test_cross_boundary_filter_matches_oracle(torch_gpu, cells_kind):
     K, H, W = 8, cam.height, cam.width
     from paper_2606_18588_amd.pipeline import Frame, GaussianParams
     params = [GaussianParams.from_scene(c) for c in scenes]
-    fr = Frame(params, boxes, cam, ST, cross_filter=True)
+    fr = Frame(params, boxes, cam, st, cross_filter=True)
     fr.init_masks()
     out = fr.forward(update_masks=True).cpu().numpy()
     torch.cuda.synchronize()
     vis = oracle.visibility(boxes, cam)
     assert not vis["flags"].any()
-    xfs = oracle.cross_filters(scenes, boxes, cam, ST)
+    xfs = oracle.cross_filters(scenes, boxes, cam, st)
     nfilt = 0
     for k in range(K):
         got = fr.views[k].xf.cpu().numpy().view(np.uint32)[:scenes[k].n]
@@ -508,7 +512,7 @@ def test_cross_boundary_filter_matches_oracle(torch_gpu, cells_kind):
         assert_same(got[ok], xfs[k]["xf"][ok], f"filter bits of cell {k}")
         nfilt += int((xfs[k]["xf"] != 0).sum())
     assert nfilt > 100
-    ref = oracle.forward(scenes, boxes, cam, ST, xfilters=xfs)
+    ref = oracle.forward(scenes, boxes, cam, st, xfilters=xfs)
     fl = ref.comp["flags"].copy()
     for p in ref.parts:
         fl |= p["flags"]
@@ -533,7 +537,7 @@ def test_cross_boundary_filter_matches_oracle(torch_gpu, cells_kind):
     grads = [p.zeros_like() for p in params]
     fr.backward(torch.as_tensor(d).cuda(), grads)
     torch.cuda.synchronize()
-    gref = oracle.backward(scenes, boxes, cam, ST, ref, d[..., :3].astype(np.float64),
+    gref = oracle.backward(scenes, boxes, cam, st, ref, d[..., :3].astype(np.float64),
                            d[..., 3].astype(np.float64), xfilters=xfs)
     for k in range(K):
         v = fr.views[k].n_tiles.cpu().numpy() > 0
