@@ -29,24 +29,21 @@ namespace {
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
-constexpr uint64_t kEFlagAgg = 1ull << 62;
-constexpr uint64_t kEFlagIncl = 2ull << 62;
-constexpr uint64_t kEValMask = (1ull << 62) - 1;
 constexpr int kSpinLimit = 1 << 20;
 constexpr int kLookback = 8;  // predecessor statuses read per look-back round trip
 constexpr int kScanItems = 16;  // preprocess blocks per thread in the count scan
 constexpr int kScanTile = 256 * kScanItems;
 
-__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
+// Look-back status words: the flag and the count share one 32-bit word, so
+// a reader that sees the flag sees its count, and no other memory is
+// published through the word (the scattered keys are read by the next
+// launch).  Device-scope atomic loads and stores without ordering suffice,
+// and they avoid the cache write-back and invalidation an acquire or
+// release at device scope costs on a multi-XCD GPU.
+__device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_rel(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_acq64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel64(uint64_t* p, uint64_t v) {
+__device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -429,9 +426,9 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
   const uint32_t tot = c0 + c1 + c2 + c3;
   if (!a.offsets) {
     if (part == 0)
-      st_rel(&a.status[d], kFlagIncl | tot);
+      st_status(&a.status[d], kFlagIncl | tot);
     else
-      st_rel(&a.status[(size_t)part * kRadixBins + d], kFlagAgg | tot);
+      st_status(&a.status[(size_t)part * kRadixBins + d], kFlagAgg | tot);
   }
   __syncthreads();
   s_wh[0][d] = 0, s_wh[1][d] = c0, s_wh[2][d] = c0 + c1, s_wh[3][d] = c0 + c1 + c2;
@@ -451,7 +448,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
       uint32_t st[kLookback];
 #pragma unroll
       for (int q = 0; q < kLookback; ++q)
-        st[q] = j - q >= 0 ? ld_acq(&a.status[(size_t)(j - q) * kRadixBins + d]) : kFlagIncl;
+        st[q] = j - q >= 0 ? ld_status(&a.status[(size_t)(j - q) * kRadixBins + d]) : kFlagIncl;
       bool stop = false;
       int used = 0;
 #pragma unroll
@@ -478,7 +475,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    st_rel(&a.status[(size_t)part * kRadixBins + d], kFlagIncl | ((excl + tot) & kValMask));
+    st_status(&a.status[(size_t)part * kRadixBins + d], kFlagIncl | ((excl + tot) & kValMask));
   }
   s_dst[d] = gex + excl - loc;
   __syncthreads();
