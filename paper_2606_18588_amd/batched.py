@@ -10,7 +10,8 @@ preprocess launch for all its views, a sort per view, one render launch and
 one render-backward launch over the group's (view, tile) work items, and
 the views' parameter gradients summed in view order.  Plain form: the
 per-view calls one view after another.  Both forms give bit-identical
-images; gradients agree to 1e-5 (see the render backward's reduction).
+images, and the same screen-space and parameter gradients: the render
+backward has no atomics and the views' gradients are added in view order.
 
 Per-instance buffers (instance values, sort workspace, backward rows) are
 the bulk of the memory; groups run one after another on one stream, so all
