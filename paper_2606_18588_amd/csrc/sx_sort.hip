@@ -72,7 +72,6 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s4,
 
 SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y) {
   SortLayout L;
-  const int64_t tiles_total = tiles_x * tiles_y;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
