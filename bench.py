@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--requests", type=int, default=800,
                     help="serve: measured requests (after 200 warm-up requests)")
     ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="cells: streams for the cells' independent forward chains")
     ap.add_argument("--cross-filter", action="store_true",
                     help="cells: per-ray cross-boundary filtering of every cell's render")
     ap.add_argument("--reeval", action="store_true",
@@ -344,7 +346,8 @@ def bench_cells(args):
         cams = synth.g8_cameras(w, h)
         targets = [torch.as_tensor(synth.random_image(500 + k, w, h)).cuda()
                    for k in range(len(cams))]
-        frames = [Frame(params, cells, c, st, cross_filter=args.cross_filter) for c in cams]
+        frames = [Frame(params, cells, c, st, cross_filter=args.cross_filter,
+                        streams=args.streams) for c in cams]
         dout = torch.empty((h, w, 4), dtype=torch.float32, device="cuda")
         for f in frames:  # size every cell's instance buffers once, with headroom
             f.init_masks(geometric=True, reeval=args.reeval)
@@ -415,6 +418,7 @@ def bench_cells(args):
                                "geometric visibility and temporal saturation masks"
                                + (" re-evaluated every render" if args.reeval else "")
                                + (", cross-boundary filtering" if args.cross_filter else "")
+                               + f", cells' chains on {args.streams} stream(s)"
                                + ", one Adam update per step",
                    "gaussians": int(sum(p.n for p in params)), "cells": len(params),
                    "views": 8},

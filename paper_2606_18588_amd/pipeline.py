@@ -256,8 +256,12 @@ class Frame:
 
     def __init__(self, cells: Sequence[GaussianParams], boxes, cam, settings,
                  flags=0, capacities=None, keep_keys=False, device="cuda",
-                 cross_filter=False):
+                 cross_filter=False, streams=1):
         self.cross_filter = cross_filter
+        # asynchronous forwards spread the cells' independent preprocess,
+        # sort and render chains over this many streams (default priority)
+        self.side = ([torch.cuda.Stream(device=device) for _ in range(streams)]
+                     if streams > 1 else None)
         self.cells = list(cells)
         self.boxes = list(boxes)
         assert len(self.cells) == len(self.boxes)
@@ -324,11 +328,24 @@ class Frame:
         after init_masks(reeval=True), re-evaluates the view's state."""
         if update_masks and self.budget is not None and not use_masks:
             raise ValueError("re-evaluation needs the renders restricted to the masks")
+        side = self.side if (self.side is not None and not sync) else None
+        main = torch.cuda.current_stream()
+        if side is not None:
+            ready = torch.cuda.Event()
+            ready.record(main)
+            for s in side:
+                s.wait_event(ready)
         for k, v in enumerate(self.views):
-            v.preprocess()
-            v.sort(sync=sync)
             m = self.masks[k] if (use_masks and self.masks is not None) else None
-            v.render(m)
+            with torch.cuda.stream(side[k % len(side)] if side is not None else main):
+                v.preprocess()
+                v.sort(sync=sync)
+                v.render(m)
+        if side is not None:
+            for s in side:
+                done = torch.cuda.Event()
+                done.record(s)
+                main.wait_event(done)
         parts = [v.partial for v in self.views]
         if update_masks and self.budget is not None:
             B.sx_composite_reeval(parts, self.boxes, self.c_cam, self.c_par, self.out,
@@ -339,9 +356,31 @@ class Frame:
         return self.out
 
     def backward(self, dout, grads: Sequence[GaussianParams], accumulate=False):
-        states = [v.state(g) for v, g in zip(self.views, grads)]
-        B.sx_backward(states, self.boxes, self.c_cam, self.c_par, dout,
-                      B.SX_BWD_ACCUMULATE if accumulate else 0)
+        if self.side is None:
+            states = [v.state(g) for v, g in zip(self.views, grads)]
+            B.sx_backward(states, self.boxes, self.c_cam, self.c_par, dout,
+                          B.SX_BWD_ACCUMULATE if accumulate else 0)
+            return
+        # the same calls as sx_backward, with the cells' render and
+        # projection backwards on the side streams (cell k always on stream
+        # k mod n, so its gradient accumulations keep their order)
+        for v in self.views:
+            v.ensure_backward_buffers()
+        main = torch.cuda.current_stream()
+        B.sx_composite_backward([v.partial for v in self.views], self.boxes, self.c_cam,
+                                self.c_par, dout, [v.dpartial for v in self.views])
+        ready = torch.cuda.Event()
+        ready.record(main)
+        for s in self.side:
+            s.wait_event(ready)
+        for k, (v, g) in enumerate(zip(self.views, grads)):
+            with torch.cuda.stream(self.side[k % len(self.side)]):
+                v.render_backward(v.dpartial)
+                v.preprocess_backward(g, accumulate)
+        for s in self.side:
+            done = torch.cuda.Event()
+            done.record(s)
+            main.wait_event(done)
 
 
 class BatchedViews:

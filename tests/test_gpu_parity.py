@@ -583,6 +583,42 @@ def test_cross_boundary_filter_degenerate_cases(torch_gpu):
     torch.cuda.synchronize()
 
 
+def test_frame_forward_on_side_streams_bit_identical(torch_gpu):
+    """The cells' forward and backward chains spread over four streams give
+    the same image, masks and gradients bit for bit as one stream."""
+    print("case: frame forward on side streams", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd.pipeline import Frame, GaussianParams
+    scene = synth.make_cube_scene(3, 8000, log_scale=(-3.6, 0.5))
+    cam = synth.camera_from_rows(
+        np.array([[1, 0, 0], [0, 0.9950, -0.0998], [0, 0.0998, 0.9950]]), (0.13, 0.21, -3.0),
+        96, 80, 70.0)
+    xe, ye = [-1.0, -0.5, 0.0, 0.5, 1.0], [-1.0, 0.0, 1.0]
+    part = synth.grid_partition(scene, xe, ye)
+    boxes = grid_cells_xy(xe, ye)
+    scenes = part.cell_scenes(scene)
+    outs = []
+    dout = torch.as_tensor(np.random.default_rng(3).normal(
+        size=(cam.height, cam.width, 4)).astype(np.float32)).cuda()
+    for streams in (1, 4):
+        params = [GaussianParams.from_scene(c) for c in scenes]
+        fr = Frame(params, boxes, cam, ST, streams=streams)
+        fr.init_masks(geometric=True)
+        fr.forward(use_masks=True, sync=True)  # sizes the buffers
+        fr.init_masks(geometric=True)
+        out = fr.forward(use_masks=True, update_masks=True, sync=False)
+        grads = [p.zeros_like() for p in params]
+        fr.backward(dout, grads)
+        fr.backward(dout, grads, accumulate=True)
+        torch.cuda.synchronize()
+        outs.append((out.cpu().numpy(), fr.masks.cpu().numpy(),
+                     [t.cpu().numpy() for g in grads for t in g.tensors()]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    for a, b in zip(outs[0][2], outs[1][2]):
+        assert np.array_equal(a, b)
+
+
 def test_composite_kd_cells_matches_oracle(torch_gpu):
     """K = 8 cells from the KD-tree partitioner (boxes bounded on some axes,
     unbounded at the scene's outside): the composition by ray entry order
