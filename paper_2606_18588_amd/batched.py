@@ -29,7 +29,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import binding as B
-from .pipeline import BatchedViews, CellView, GaussianParams
+from .pipeline import BatchedViews, CellView, GaussianParams, run_on_streams
 
 _ALIGN = 256
 
@@ -93,6 +93,8 @@ class MultiViewStep:
             v.dout = torch.empty_like(v.partial)
         self.box = [_Box()]
         self.batches = [BatchedViews.from_views([self.views[i] for i in g]) for g in self.groups]
+        # the batched form overlaps the views' independent sorts and losses
+        self.side = None if plain else [torch.cuda.Stream(device=device) for _ in range(4)]
         self.adam_m = [torch.zeros_like(t) for t in params.tensors()]
         self.adam_v = [torch.zeros_like(t) for t in params.tensors()]
         self.t = 0
@@ -128,10 +130,11 @@ class MultiViewStep:
         else:
             for g, bv in zip(self.groups, self.batches):
                 bv.preprocess()
-                bv.sort(sync=False)
+                bv.sort(sync=False, streams=self.side)
                 bv.render(want_nblend=count_blends)
-                for i in g:
-                    self._loss_and_grad(self.views[i], self.targets[i])
+                run_on_streams(self.side, [lambda i=i: self._loss_and_grad(self.views[i],
+                                                                           self.targets[i])
+                                           for i in g])
                 bv.render_backward()
                 # the first group overwrites the gradients, later ones add
                 bv.preprocess_backward(self.grads, accumulate=g is not self.groups[0])

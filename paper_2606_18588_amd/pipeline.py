@@ -246,6 +246,29 @@ class CellView:
         return s
 
 
+def run_on_streams(streams, jobs):
+    """Run independent jobs (callables enqueueing device work) round-robin on
+    `streams` after the current stream's earlier work; the current stream
+    then waits for all of them (no streams: on the current stream).
+    Returns the jobs' results."""
+    if not streams:
+        return [job() for job in jobs]
+    main = torch.cuda.current_stream()
+    ready = torch.cuda.Event()
+    ready.record(main)
+    for st in streams:
+        st.wait_event(ready)
+    out = []
+    for k, job in enumerate(jobs):
+        with torch.cuda.stream(streams[k % len(streams)]):
+            out.append(job())
+    for st in streams:
+        done = torch.cuda.Event()
+        done.record(st)
+        main.wait_event(done)
+    return out
+
+
 def ctypes_pointer(obj):
     import ctypes
     return ctypes.pointer(obj)
@@ -431,8 +454,13 @@ class BatchedViews:
         B.sx_preprocess_multi(self.views[0].c_g, self.c_cams, self.c_par,
                               [v.c_proj for v in self.views])
 
-    def sort(self, sync=True):
-        return [v.sort(sync=sync) for v in self.views]
+    def sort(self, sync=True, streams=None):
+        """Per-view sorts; asynchronous ones may be spread over `streams`
+        (the views' sorts are independent; the caller's stream waits for
+        all of them)."""
+        if sync or not streams:
+            return [v.sort(sync=sync) for v in self.views]
+        return run_on_streams(streams, [lambda v=v: v.sort(sync=False) for v in self.views])
 
     def _structs(self, backward=False, want_nblend=True):
         out = []

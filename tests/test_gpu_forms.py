@@ -136,6 +136,39 @@ def test_batched_views_bit_identical_to_per_view(torch_gpu, tile):
         assert not np.any(_np(getattr(over, name))[unseen]), name
 
 
+def test_multiview_step_side_streams_and_plain_agree(torch_gpu):
+    """The batched training step with its sorts and losses on side streams
+    gives bit for bit the gradients of the same step on one stream and of
+    the plain per-view step (views of uneven size, two groups)."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.batched import MultiViewStep
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    print("case: multi-view step on side streams", flush=True)
+    scene = synth.tiny_scene(seed=13, n=4000)
+    rng = np.random.default_rng(21)
+    cams = []
+    for k in range(6):
+        a = rng.uniform(0, 2 * math.pi)
+        cams.append(synth.look_at_camera((3.5 * math.cos(a), 3.5 * math.sin(a), 1.0),
+                                         (0.0, 0.0, 0.0), int(rng.integers(40, 160)),
+                                         int(rng.integers(30, 120)), hfov_deg=55.0))
+    targets = [torch.as_tensor(rng.uniform(size=(c.height, c.width, 3)).astype(np.float32)).cuda()
+               for c in cams]
+    grads = []
+    for mode in ("streams", "one", "plain"):
+        params = GaussianParams.from_scene(scene)
+        g = params.zeros_like()
+        step = MultiViewStep(params, g, cams, targets, ST, batch=4, plain=(mode == "plain"))
+        if mode == "one":
+            step.side = None
+        step.run(lr=0.0, check=True)
+        torch.cuda.synchronize()
+        grads.append([t.cpu().numpy() for t in g.tensors()])
+    for a, b, c in zip(*grads):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+    assert any(np.abs(a).max() > 0 for a in grads[0])
+
+
 def test_batched_views_sixteen_uneven(torch_gpu):
     """The largest batch (16 views of uneven size, some empty) in one
     launch each, per-view outputs bit-identical to the per-view calls."""
