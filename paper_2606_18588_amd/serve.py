@@ -33,7 +33,7 @@ import numpy as np
 import torch
 
 from . import binding as B
-from .pipeline import GaussianParams
+from .pipeline import GaussianParams, run_on_streams
 
 _ALIGN = 256
 _MAX_CAPACITY = (1 << 31) - 1  # largest instance capacity the sort accepts
@@ -102,6 +102,7 @@ class Server:
         self.params = params
         self.settings = settings
         self.plain = plain
+        self.side = None if plain else [torch.cuda.Stream(device=device) for _ in range(4)]
         self.max_batch = 1 if plain else max_batch
         self.inflight = inflight
         self.arena_bytes = int(arena_bytes)
@@ -185,18 +186,30 @@ class Server:
         off = 0
         views = []
         pixels = []
-        for j, (it, cam, s, cap) in enumerate(zip(items, cams, slots, caps)):
+        bufs = []
+        for it, cap in zip(items, caps):
             tx, ty = _tile_grid(it.cam, self.settings)
-            tiles = tx * ty
             wsb = B.sx_sort_workspace_size(self.n, cap, tx, ty)
             vals = arena[off:off + 4 * cap].view(torch.int32)
             off += _align(4 * cap)
             ws = arena[off:off + wsb]
             off += _align(wsb)
-            ranges = s.ranges[:2 * (tiles + 1)]
-            B.sx_sort(s.c_proj, self.n, cam, self.c_par, cap, None, vals, ranges, ws,
-                      sync_counts=False)
+            bufs.append((vals, ws, tx * ty))
+
+        def sort_job(j):
+            vals, ws, tiles = bufs[j]
+            s = slots[j]
+            B.sx_sort(s.c_proj, self.n, cams[j], self.c_par, caps[j], None, vals,
+                      s.ranges[:2 * (tiles + 1)], ws, sync_counts=False)
             counts[j].copy_(ws[:32].view(torch.int64), non_blocking=True)
+
+        # the requests' sorts are independent: batched, they overlap on the
+        # side streams (joined before the render)
+        run_on_streams(None if self.plain else self.side,
+                       [lambda j=j: sort_job(j) for j in range(len(items))])
+        for j, (it, cam, s, cap) in enumerate(zip(items, cams, slots, caps)):
+            vals, ws, tiles = bufs[j]
+            ranges = s.ranges[:2 * (tiles + 1)]
             px = it.cam.width * it.cam.height
             pixels.append(px)
             if self.plain:
