@@ -167,7 +167,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "exchange is not part of this build", file=sys.stderr)
+              "exchange of partial pixels between GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
