@@ -646,6 +646,21 @@ def test_cross_filter_hand_cases(orc):
     # a culled Gaussian (behind the camera) carries no bits
     f = orc.cross_filter(_scene_of([(-0.1, 0.0, -5.0)], [0.1]), cam, st, open_cells, 0)
     assert list(f["xf"]) == [0]
+    # anisotropic support: scales (0.3, 0.01, 0.01) reach 0.9 along the long
+    # axis and 0.03 across it; along x the Gaussian at x = -0.1 spans the
+    # plane, turned 90 degrees about z (long axis along y) it does not, and
+    # turned 45 degrees its x half-extent is 3 sqrt((0.09 + 1e-4) / 2) = 0.637
+    sc = _scene_of([(-0.1, 0.0, 0.0)] * 3, [1.0] * 3)
+    sc.log_scales = np.log(np.array([[0.3, 0.01, 0.01]] * 3, np.float32))
+    c45, s45 = math.cos(math.pi / 8), math.sin(math.pi / 8)
+    sc.quats = np.array([[1, 0, 0, 0], [math.sqrt(0.5), 0, 0, math.sqrt(0.5)],
+                         [c45, 0, 0, s45]], np.float32)
+    f = orc.cross_filter(sc, cam, st, open_cells, 0)
+    assert list(f["xf"]) == [0b10, 0, 0b10]
+    sc.means = np.array([[-0.62, 0.0, 0.0], [-0.62, 0.0, 0.0], [-0.65, 0.0, 0.0]], np.float32)
+    sc.quats = np.array([[c45, 0, 0, s45]] * 3, np.float32)
+    f = orc.cross_filter(sc, cam, st, open_cells, 0)
+    assert list(f["xf"]) == [0b10, 0b10, 0]  # 0.637 > 0.62 and < 0.65
 
 
 def test_cross_filter_render_drops_exactly_the_pair(orc):
