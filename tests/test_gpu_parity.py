@@ -409,8 +409,8 @@ def test_composite_with_visibility_matches_oracle(torch_gpu):
           f"invisible pairs {(vis['vis'] == 0).sum()}", flush=True)
 
 
-@pytest.mark.parametrize("geometric", [True, False])
-def test_composite_reeval_three_renders_match_oracle(torch_gpu, geometric):
+@pytest.mark.parametrize("geometric,same_frame", [(True, False), (False, False), (True, True)])
+def test_composite_reeval_three_renders_match_oracle(torch_gpu, geometric, same_frame):
     """Saturation carried across three renders of one view with speculative
     re-evaluation: KD cells starting from their geometric maps; render 1
     prunes pairs behind saturated prefixes and keeps their budgets; the
@@ -427,7 +427,9 @@ def test_composite_reeval_three_renders_match_oracle(torch_gpu, geometric):
     boxes = [synth.Cell(lo, hi) for lo, hi in boxes_t]
     scenes = [scene.subset(np.nonzero(cell_of == k)[0]) for k in range(8)]
     K, H, W = 8, cam.height, cam.width
-    fr, params = _frame(torch, scenes, boxes, cam)
+    from paper_2606_18588_amd import binding as Bf
+    fr, params = _frame(torch, scenes, boxes, cam,
+                        flags=Bf.SX_FLAG_SAME_FRAME_CULL if same_frame else 0)
     fr.init_masks(geometric=geometric, reeval=True)
     vis = oracle.visibility(boxes, cam)
     assert not vis["flags"].any()
@@ -447,7 +449,8 @@ def test_composite_reeval_three_renders_match_oracle(torch_gpu, geometric):
         torch.cuda.synchronize()
         ref = oracle.forward(scs, boxes, cam, ST, masks=state)
         rr = oracle.composite_reeval(ref.Cparts, ref.Tparts, boxes, cam, ST, state, budget,
-                                     omega=om if geometric else None)
+                                     omega=om if geometric else None,
+                                     same_frame_cull=same_frame)
         for p in ref.parts:
             bad |= p["flags"] != 0
         bad |= rr["flags"] != 0
