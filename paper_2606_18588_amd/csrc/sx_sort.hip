@@ -31,7 +31,7 @@ constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
 constexpr int kSpinLimit = 1 << 20;
 constexpr int kLookback = 8;  // predecessor statuses read per look-back round trip
-constexpr int kScanItems = 16;  // preprocess blocks per thread in the count scan
+constexpr int kScanItems = 4;  // preprocess blocks per thread in the count scan
 constexpr int kScanTile = 256 * kScanItems;
 
 // Look-back status words: the flag and the count share one 32-bit word, so
