@@ -310,6 +310,20 @@ sx_status sx_l1_loss(const float* out, const float* target, int32_t width,
                      int32_t height, float* dout, float* loss_sum,
                      sx_stream stream);
 
+/* The composition (Eq. 5, as sx_composite with its clearing rule), the L1
+ * loss of the composed image (the RGB term of the paper's loss) and the
+ * composition backward of that loss (Eq. 6-7; as
+ * sx_l1_loss followed by sx_composite_backward) in one pass over the
+ * pixels; the results are bit-identical to the three calls.
+ *   target [H*W*3]; out [H*W*4]; masks as sx_composite (or NULL);
+ *   loss_sum (device float, may be NULL) receives += the mean absolute
+ *   error; dpartials HOST array of K device pointers to [H*W*4] buffers
+ *   receiving dL/d(C^m, T^m). */
+sx_status sx_composite_l1(int32_t K, const float* const* partials, const sx_cell* cells,
+                          const sx_camera* cam, const sx_params* p, const float* target,
+                          float* out, uint32_t* masks, float* loss_sum,
+                          float* const* dpartials, sx_stream stream);
+
 /* ------------------------------------------------------------- a7-a9 --
  * Backward through the composition and every cell's render and
  * projection (Eq. 6-7).  For cell m at pixel p with order position j:

@@ -90,7 +90,7 @@ EXPORTS = (
     "sx_adam", "sx_fill_u32", "sx_preprocess_multi", "sx_multi_workspace_size",
     "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
     "sx_render_backward_stages", "sx_visibility", "sx_kd_partition",
-    "sx_composite_reeval", "sx_cross_filter",
+    "sx_composite_reeval", "sx_cross_filter", "sx_composite_l1",
 )
 
 _lib = None
@@ -299,6 +299,14 @@ def set_cross_filter(proj: SxProjected, xf, omega, cell: int, n_cells: int) -> N
     proj.omega = None if xf is None else ptr(omega)
     proj.cell = int(cell) if xf is not None else 0
     proj.n_cells = int(n_cells) if xf is not None else 0
+
+
+def sx_composite_l1(partials: Sequence[torch.Tensor], cells, cam: SxCamera, p: SxParams,
+                    target, out, masks, loss_sum, dpartials, stream=None) -> None:
+    _check("sx_composite_l1", lib().sx_composite_l1(
+        c_i32(len(partials)), ptr_array(partials), cells_array(cells), ctypes.byref(cam),
+        ctypes.byref(p), ptr(target), ptr(out), ptr(masks), ptr(loss_sum),
+        ptr_array(dpartials), stream_handle(stream)))
 
 
 def sx_l1_loss(out, target, width: int, height: int, dout, loss_sum,

@@ -273,6 +273,22 @@ sx_status sx_composite_reeval(int32_t K, const float* const* partials,
              "sx_composite_reeval");
 }
 
+sx_status sx_composite_l1(int32_t K, const float* const* partials, const sx_cell* cells,
+                          const sx_camera* cam, const sx_params* p, const float* target,
+                          float* out, uint32_t* masks, float* loss_sum,
+                          float* const* dpartials, sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  SX_TRY(check_cells(K, partials, cells));
+  if (!target || !out || !dpartials) return fail(SX_EINVAL, "null argument");
+  for (int m = 0; m < K; ++m)
+    if (!partials[m] || !dpartials[m]) return fail(SX_EINVAL, "null buffer for cell %d", m);
+  return dev(sx::launch_composite_l1(K, partials, cells, sx::make_dcam(*cam),
+                                     sx::make_kparams(*p, *cam), target, out, masks, loss_sum,
+                                     dpartials, (hipStream_t)stream),
+             "sx_composite_l1");
+}
+
 sx_status sx_l1_loss(const float* out, const float* target, int32_t width,
                      int32_t height, float* dout, float* loss_sum, sx_stream stream) {
   if (!out || !target || !dout) return fail(SX_EINVAL, "null argument");

@@ -211,6 +211,97 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompArgs a) {
   }
 }
 
+// Composition, L1 loss and composition backward in one pass per pixel: the
+// same arithmetic as k_composite (clearing rule), k_l1 and k_composite_bwd
+// in that order, so the results are bit-identical to the three launches,
+// without writing and re-reading dL/d(rgb) or re-reading the partials.
+template <int KM>
+__global__ __launch_bounds__(256) void k_composite_l1(CompArgs a, const float* __restrict__ target,
+                                                      float inv_n, float* loss) {
+  const uint32_t HW = (uint32_t)a.W * a.H;
+  const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+  const bool inside = p < HW;
+  const uint32_t pp = inside ? p : 0u;
+  const int px = (int)(pp % a.W), py = (int)(pp / a.W);
+  int rank[KM];
+  cell_ranks<KM>(a, px, py, rank);
+  float4 cm[KM];
+#pragma unroll
+  for (int m = 0; m < KM; ++m)
+    cm[m] = (inside && m < a.K) ? a.part[m][pp] : make_float4(0.f, 0.f, 0.f, 1.f);
+  float P = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+  bool act[KM], use[KM];
+  float Pin[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+      if (m < a.K && rank[m] == j) {
+        Pin[m] = P;
+        act[m] = P >= a.t_min;
+        use[m] = act[m] || !a.same_frame;
+        if (use[m]) {
+          c0 = fmaf(P, cm[m].x, c0);
+          c1 = fmaf(P, cm[m].y, c1);
+          c2 = fmaf(P, cm[m].z, c2);
+          P = P * cm[m].w;
+        }
+      }
+    }
+  }
+  const float4 o = make_float4(c0 + P * a.bg[0], c1 + P * a.bg[1], c2 + P * a.bg[2], P);
+  if (inside) a.out[p] = o;
+  if (a.masks) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t w0 = (p - lane) >> 5;
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+      if (m >= a.K) break;
+      const uint64_t keep = __ballot(!inside || act[m]);
+      if (lane == 0 || lane == 32) {
+        const uint32_t w = w0 + (lane >> 5);
+        if (w < a.words) a.masks[(size_t)m * a.words + w] &= (uint32_t)(keep >> lane);
+      }
+    }
+  }
+  // L1: dL/d(rgb) = sign(rgb - target) / (3HW), dL/dT = 0
+  float l = 0.f;
+  float4 G = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (inside) {
+    const float d0 = o.x - target[3 * (size_t)p + 0];
+    const float d1 = o.y - target[3 * (size_t)p + 1];
+    const float d2 = o.z - target[3 * (size_t)p + 2];
+    auto sgn = [](float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); };
+    G = make_float4(sgn(d0) * inv_n, sgn(d1) * inv_n, sgn(d2) * inv_n, 0.f);
+    l = (fabsf(d0) + fabsf(d1) + fabsf(d2)) * inv_n;
+  }
+  if (loss) {
+    for (int off = 32; off >= 1; off >>= 1) l += __shfl_xor(l, off, 64);
+    if ((threadIdx.x & 63) == 0) unsafeAtomicAdd(loss, l);
+  }
+  if (!inside) return;
+  float B0 = a.bg[0], B1 = a.bg[1], B2 = a.bg[2], U = 1.f;
+#pragma unroll
+  for (int j = KM - 1; j >= 0; --j) {
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+      if (m < a.K && rank[m] == j) {
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (use[m]) {
+          const float Pj = Pin[m];
+          q.x = Pj * G.x, q.y = Pj * G.y, q.z = Pj * G.z;
+          q.w = Pj * (G.x * B0 + G.y * B1 + G.z * B2 + G.w * U);
+          B0 = fmaf(cm[m].w, B0, cm[m].x);
+          B1 = fmaf(cm[m].w, B1, cm[m].y);
+          B2 = fmaf(cm[m].w, B2, cm[m].z);
+          U = U * cm[m].w;
+        }
+        a.dpart[m][p] = q;
+      }
+    }
+  }
+}
+
 static CompArgs comp_args(int K, const float* const* partials, const sx_cell* cells,
                           const DCam& cam, const KParams& p) {
   CompArgs a{};
@@ -350,6 +441,31 @@ hipError_t launch_composite_backward(int K, const float* const* partials,
     hipLaunchKernelGGL(k_composite_bwd<8>, grid, dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(k_composite_bwd<16>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_composite_l1(int K, const float* const* partials, const sx_cell* cells,
+                               const DCam& cam, const KParams& p, const float* target,
+                               float* out, uint32_t* masks, float* loss,
+                               float* const* dpartials, hipStream_t st) {
+  CompArgs a = comp_args(K, partials, cells, cam, p);
+  a.out = reinterpret_cast<float4*>(out);
+  a.masks = masks;
+  const uint32_t HW = (uint32_t)cam.W * cam.H;
+  a.words = (HW + 31) / 32;
+  for (int m = 0; m < K; ++m) a.dpart[m] = reinterpret_cast<float4*>(dpartials[m]);
+  const float inv_n = 1.f / (3.f * (float)HW);
+  const dim3 grid((HW + 255) / 256);
+  if (K <= 1)
+    hipLaunchKernelGGL(k_composite_l1<1>, grid, dim3(256), 0, st, a, target, inv_n, loss);
+  else if (K <= 2)
+    hipLaunchKernelGGL(k_composite_l1<2>, grid, dim3(256), 0, st, a, target, inv_n, loss);
+  else if (K <= 4)
+    hipLaunchKernelGGL(k_composite_l1<4>, grid, dim3(256), 0, st, a, target, inv_n, loss);
+  else if (K <= 8)
+    hipLaunchKernelGGL(k_composite_l1<8>, grid, dim3(256), 0, st, a, target, inv_n, loss);
+  else
+    hipLaunchKernelGGL(k_composite_l1<16>, grid, dim3(256), 0, st, a, target, inv_n, loss);
   return hipGetLastError();
 }
 

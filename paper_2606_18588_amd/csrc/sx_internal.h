@@ -308,6 +308,10 @@ hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint3
 hipError_t launch_cross_filter(const sx_gaussians& g, const sx_projected& proj, int K,
                                const sx_cell* cells, int cell, const DCam& cam, uint32_t* xf,
                                hipStream_t st);
+hipError_t launch_composite_l1(int K, const float* const* partials, const sx_cell* cells,
+                               const DCam& cam, const KParams& p, const float* target,
+                               float* out, uint32_t* masks, float* loss,
+                               float* const* dpartials, hipStream_t st);
 // budget non-NULL selects the re-evaluating form (masks then required)
 hipError_t launch_composite(int K, const float* const* partials,
                             const sx_cell* cells, const DCam& cam,

@@ -622,6 +622,52 @@ def test_frame_forward_on_side_streams_bit_identical(torch_gpu):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("K", [1, 8])
+def test_composite_l1_fused_equals_three_calls(torch_gpu, K):
+    """sx_composite_l1 gives bit for bit the image, masks, loss and partial
+    gradients of sx_composite, sx_l1_loss and sx_composite_backward."""
+    print(f"case: fused composite + L1 + backward K={K}", flush=True)
+    torch = torch_gpu
+    from paper_2606_18588_amd import binding as B
+    scene = synth.make_cube_scene(3, 8000, log_scale=(-3.6, 0.5))
+    cam = synth.camera_from_rows(
+        np.array([[1, 0, 0], [0, 0.9950, -0.0998], [0, 0.0998, 0.9950]]), (0.13, 0.21, -3.0),
+        97, 81, 70.0)
+    if K == 1:
+        boxes, scenes = [big_box()], [scene]
+    else:
+        xe, ye = [-1.0, -0.5, 0.0, 0.5, 1.0], [-1.0, 0.0, 1.0]
+        boxes = grid_cells_xy(xe, ye)
+        scenes = synth.grid_partition(scene, xe, ye).cell_scenes(scene)
+    fr, _ = _frame(torch, scenes, boxes, cam)
+    fr.forward()
+    H, W = cam.height, cam.width
+    target = torch.as_tensor(np.random.default_rng(2).uniform(
+        size=(H, W, 3)).astype(np.float32)).cuda()
+    parts = [v.partial for v in fr.views]
+    words = (H * W + 31) // 32
+    res = []
+    for fused in (False, True):
+        out = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+        masks = torch.full((K, words), -1, dtype=torch.int32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        dparts = [torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for _ in range(K)]
+        if fused:
+            B.sx_composite_l1(parts, boxes, fr.c_cam, fr.c_par, target, out, masks, loss, dparts)
+        else:
+            dout = torch.empty_like(out)
+            B.sx_composite(parts, boxes, fr.c_cam, fr.c_par, out, masks)
+            B.sx_l1_loss(out, target, W, H, dout, loss)
+            B.sx_composite_backward(parts, boxes, fr.c_cam, fr.c_par, dout, dparts)
+        torch.cuda.synchronize()
+        res.append([out.cpu().numpy(), masks.cpu().numpy()] + [d.cpu().numpy() for d in dparts])
+        res[-1].append(float(loss.item()))
+    for a, b in zip(res[0][:-1], res[1][:-1]):
+        assert np.array_equal(a, b)
+    # the loss sum is an atomic sum of per-wavefront partials: order may differ
+    assert abs(res[0][-1] - res[1][-1]) <= 1e-6 * abs(res[0][-1])
+
+
 def test_composite_kd_cells_matches_oracle(torch_gpu):
     """K = 8 cells from the KD-tree partitioner (boxes bounded on some axes,
     unbounded at the scene's outside): the composition by ray entry order
