@@ -81,9 +81,9 @@ class Step:
         self.counts = self.view.sort(sync=True)
         self.view._alloc_sort(int(self.counts[1] * 1.05) + 4096)
         self.view.ensure_backward_buffers()  # sized for the new capacity
-        self.stage_names = ["preprocess", "sort", "render", "composite", "l1",
-                            "composite_bwd", "render_bwd_prep", "render_bwd_walk",
-                            "render_bwd_reduce", "preprocess_bwd"]
+        self.stage_names = ["preprocess", "sort", "render", "composite_l1",
+                            "render_bwd_prep", "render_bwd_walk", "render_bwd_reduce",
+                            "preprocess_bwd"]
 
     def run(self, events=None, count=False):
         B, v = self.B, self.view
@@ -95,22 +95,19 @@ class Step:
         if ev: ev[2].record()
         v.render(None, want_nblend=count)
         if ev: ev[3].record()
-        B.sx_composite([v.partial], self.box, self.c_cam, self.c_par, self.out, None)
+        # composition (Eq. 5), L1 and the composition backward in one pass
+        B.sx_composite_l1([v.partial], self.box, self.c_cam, self.c_par, self.target,
+                          self.out, None, None, [v.dpartial])
         if ev: ev[4].record()
-        B.sx_l1_loss(self.out, self.target, self.cam.width, self.cam.height, self.dout, None)
-        if ev: ev[5].record()
-        B.sx_composite_backward([v.partial], self.box, self.c_cam, self.c_par, self.dout,
-                                [v.dpartial])
-        if ev: ev[6].record()
         # the three stages of sx_render_backward, called one by one so that
         # events bracket the reverse walk alone
         for i, stage in enumerate((B.SX_RB_PREPARE, B.SX_RB_WALK, B.SX_RB_REDUCE)):
             B.sx_render_backward_stages(v.c_proj, v.vals, v.ranges, v.ws, v.params.n,
                                         v.capacity, v.bwd_ws, self.c_cam, self.c_par, None,
                                         v.partial, v.last, v.dpartial, None, v.g2d, stage)
-            if ev: ev[7 + i].record()
+            if ev: ev[5 + i].record()
         v.preprocess_backward(self.grads)
-        if ev: ev[10].record()
+        if ev: ev[8].record()
 
 
 def cpu_baseline(scene, cam, settings, min_s=10.0, max_steps=20):
