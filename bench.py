@@ -366,9 +366,15 @@ def bench_cells(args):
             blends = 0
             for f, tg in zip(frames, targets):
                 before = f.masks.clone() if (count and f.omega is not None) else None
-                f.forward(use_masks=True, update_masks=True, sync=False)
-                B.sx_l1_loss(f.out, tg, w, h, dout, None)
-                f.backward(dout, grads, accumulate=True)
+                if f.budget is None:
+                    # render, composition + L1 + composition backward in one
+                    # pass, every cell's backward
+                    f.train_l1(tg, grads, accumulate=True, use_masks=True, update_masks=True,
+                               sync=False)
+                else:
+                    f.forward(use_masks=True, update_masks=True, sync=False)
+                    B.sx_l1_loss(f.out, tg, w, h, dout, None)
+                    f.backward(dout, grads, accumulate=True)
                 if count:
                     blends += sum(int(v.nblend.sum().item()) for v in f.views)
                     if before is not None:

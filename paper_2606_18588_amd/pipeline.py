@@ -351,6 +351,17 @@ class Frame:
         after init_masks(reeval=True), re-evaluates the view's state."""
         if update_masks and self.budget is not None and not use_masks:
             raise ValueError("re-evaluation needs the renders restricted to the masks")
+        self._render_cells(use_masks, sync)
+        parts = [v.partial for v in self.views]
+        if update_masks and self.budget is not None:
+            B.sx_composite_reeval(parts, self.boxes, self.c_cam, self.c_par, self.out,
+                                  self.masks, self.omega, self.budget)
+        else:
+            B.sx_composite(parts, self.boxes, self.c_cam, self.c_par, self.out,
+                           self.masks if update_masks else None)
+        return self.out
+
+    def _render_cells(self, use_masks, sync):
         side = self.side if (self.side is not None and not sync) else None
         main = torch.cuda.current_stream()
         if side is not None:
@@ -369,13 +380,23 @@ class Frame:
                 done = torch.cuda.Event()
                 done.record(s)
                 main.wait_event(done)
-        parts = [v.partial for v in self.views]
-        if update_masks and self.budget is not None:
-            B.sx_composite_reeval(parts, self.boxes, self.c_cam, self.c_par, self.out,
-                                  self.masks, self.omega, self.budget)
-        else:
-            B.sx_composite(parts, self.boxes, self.c_cam, self.c_par, self.out,
-                           self.masks if update_masks else None)
+
+    def train_l1(self, target, grads: Sequence[GaussianParams], accumulate=False,
+                 use_masks=False, update_masks=False, sync=True, loss_sum=None):
+        """One training pass of the view against an L1 target: every cell
+        rendered, composed with the L1 loss and its composition backward in
+        one pass (sx_composite_l1; the saturation masks follow the clearing
+        rule), then every cell's backward.  The same results as forward,
+        sx_l1_loss and backward; re-evaluating frames use those instead."""
+        if self.budget is not None:
+            raise ValueError("re-evaluating frames compose with forward()")
+        self._render_cells(use_masks, sync)
+        for v in self.views:
+            v.ensure_backward_buffers()
+        B.sx_composite_l1([v.partial for v in self.views], self.boxes, self.c_cam, self.c_par,
+                          target, self.out, self.masks if update_masks else None, loss_sum,
+                          [v.dpartial for v in self.views])
+        self._cells_backward(grads, accumulate)
         return self.out
 
     def backward(self, dout, grads: Sequence[GaussianParams], accumulate=False):
@@ -389,9 +410,18 @@ class Frame:
         # k mod n, so its gradient accumulations keep their order)
         for v in self.views:
             v.ensure_backward_buffers()
-        main = torch.cuda.current_stream()
         B.sx_composite_backward([v.partial for v in self.views], self.boxes, self.c_cam,
                                 self.c_par, dout, [v.dpartial for v in self.views])
+        self._cells_backward(grads, accumulate)
+
+    def _cells_backward(self, grads, accumulate):
+        """Every cell's render and projection backward from its dpartial."""
+        if self.side is None:
+            for v, g in zip(self.views, grads):
+                v.render_backward(v.dpartial)
+                v.preprocess_backward(g, accumulate)
+            return
+        main = torch.cuda.current_stream()
         ready = torch.cuda.Event()
         ready.record(main)
         for s in self.side:

@@ -620,6 +620,30 @@ def test_frame_forward_on_side_streams_bit_identical(torch_gpu):
     assert np.array_equal(outs[0][1], outs[1][1])
     for a, b in zip(outs[0][2], outs[1][2]):
         assert np.array_equal(a, b)
+    # the fused training pass against forward, L1 and backward
+    from paper_2606_18588_amd import binding as Bb
+    target = torch.as_tensor(np.random.default_rng(4).uniform(
+        size=(cam.height, cam.width, 3)).astype(np.float32)).cuda()
+    res = []
+    for fused in (False, True):
+        params = [GaussianParams.from_scene(c) for c in scenes]
+        fr = Frame(params, boxes, cam, ST, streams=4)
+        fr.init_masks(geometric=True)
+        fr.forward(use_masks=True, sync=True)
+        fr.init_masks(geometric=True)
+        grads = [p.zeros_like() for p in params]
+        if fused:
+            out = fr.train_l1(target, grads, use_masks=True, update_masks=True, sync=False)
+        else:
+            out = fr.forward(use_masks=True, update_masks=True, sync=False)
+            dl = torch.empty_like(out)
+            Bb.sx_l1_loss(out, target, cam.width, cam.height, dl, None)
+            fr.backward(dl, grads)
+        torch.cuda.synchronize()
+        res.append([out.cpu().numpy(), fr.masks.cpu().numpy()] +
+                   [t.cpu().numpy() for g in grads for t in g.tensors()])
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("K", [1, 8])
