@@ -90,7 +90,6 @@ class MultiViewStep:
         for v in self.views:
             v.ensure_backward_buffers()
             v.out = torch.empty_like(v.partial)
-            v.dout = torch.empty_like(v.partial)
         self.box = [_Box()]
         self.batches = [BatchedViews.from_views([self.views[i] for i in g]) for g in self.groups]
         # the batched form overlaps the views' independent sorts and losses
@@ -105,9 +104,10 @@ class MultiViewStep:
         return len(self.views)
 
     def _loss_and_grad(self, v: CellView, target):
-        B.sx_composite([v.partial], self.box, v.c_cam, v.c_par, v.out, None)
-        B.sx_l1_loss(v.out, target, v.W, v.H, v.dout, None)
-        B.sx_composite_backward([v.partial], self.box, v.c_cam, v.c_par, v.dout, [v.dpartial])
+        # composition, L1 and composition backward in one pass (bit-identical
+        # to sx_composite, sx_l1_loss and sx_composite_backward)
+        B.sx_composite_l1([v.partial], self.box, v.c_cam, v.c_par, target, v.out, None, None,
+                          [v.dpartial])
 
     def run(self, lr: float = 1e-4, count_blends: bool = False, check: bool = False):
         """One step; with check, synchronises after each group and raises if
