@@ -823,6 +823,198 @@ def test_backward_matches_finite_differences_k2(orc):
     _fd_check(orc, sc, part, cam, 2)
 
 
+def _fd_grads(loss, scenes, grads, rng, names=("means", "log_scales", "quats",
+                                                 "opacity_logits", "sh"),
+              per_array=120, only=None):
+    """Central differences of loss() at sampled entries of each cell's
+    parameter arrays, compared with the analytic gradients per element
+    (relative, floored at 1e-3 of the largest difference quotient).
+    `only` maps a cell to the Gaussian indices whose entries are sampled."""
+    for k, cs in enumerate(scenes):
+        for name in names:
+            arr = getattr(cs, name)
+            flat = arr.reshape(-1)
+            gflat = grads[k][name].reshape(-1)
+            per = flat.size // max(cs.n, 1)
+            pool = np.arange(flat.size)
+            if only is not None and k in only:
+                pool = (np.asarray(only[k])[:, None] * per + np.arange(per)).reshape(-1)
+            idx = pool if pool.size <= per_array else np.sort(rng.choice(pool, per_array,
+                                                                          replace=False))
+            fd = np.zeros(len(idx))
+            for j, i in enumerate(idx):
+                h = 1e-6 * max(1.0, abs(flat[i]))
+                old = flat[i]
+                flat[i] = old + h
+                lp = loss()
+                flat[i] = old - h
+                lm = loss()
+                flat[i] = old
+                fd[j] = (lp - lm) / (2 * h)
+            scale = max(np.abs(fd).max(), 1e-12)
+            err = np.abs(gflat[idx] - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
+            assert err.max() <= 1e-3, (k, name, err.max())
+
+
+def _flag_free(orc, scenes_fn, cells, cam, st, seeds, accept=lambda fr: True, **kw):
+    """The first seed whose scenes render with no flagged pixel (no pair
+    within rounding or difference-step reach of a discrete threshold) and
+    that `accept` takes."""
+    for seed in seeds:
+        scenes = scenes_fn(seed)
+        fr = orc.forward(scenes, cells, cam, st, delta_q=1e-3, **kw)
+        fl = np.bitwise_or.reduce([p["flags"] for p in fr.parts]) | fr.comp["flags"]
+        if not fl.any() and accept(fr):
+            return scenes, fr
+    raise AssertionError("no flag-free scene")
+
+
+def test_depth_gradient_matches_finite_differences(orc):
+    """Eq. 6-7 with the partial depth D = sum z_i alpha_i T_i in the loss
+    (reading 1 of the garbled D^m): the depth terms of the reverse walk
+    (dalpha gets g_D (z_i - RD), the depth itself gets alpha_i T_i g_D,
+    which reaches the means through the camera z) against central
+    differences of L = sum wC.C + wT.T + wD.D on one cell."""
+    cam = synth.fd_camera()
+    cell = [synth.Cell((-math.inf,) * 3, (math.inf,) * 3)]
+    scenes, _ = _flag_free(orc, lambda s: [synth.fd_scene(s).astype(np.float64)], cell, cam,
+                           ST, range(400, 440))
+    sc = scenes[0]
+    rng = np.random.default_rng(11)
+    wc = rng.normal(size=(cam.height, cam.width, 3))
+    wt = rng.normal(size=(cam.height, cam.width))
+    wd = rng.normal(size=(cam.height, cam.width))
+    g = orc.render_backward(sc, cam, ST, wc, wt, wd)
+    g0 = orc.render_backward(sc, cam, ST, wc, wt, None)
+    # the depth term changes the mean and opacity gradients substantially
+    for name in ("means", "opacity_logits"):
+        assert np.abs(g[name] - g0[name]).max() > 0.05 * np.abs(g[name]).max(), name
+    assert np.abs(g["g2d"][:, 9]).max() > 0 and not g0["g2d"][:, 9].any()
+
+    def loss():
+        r = orc.render(sc, cam, ST)
+        return float((r["C"] * wc).sum() + (r["T"] * wt).sum() + (r["D"] * wd).sum())
+    _fd_grads(loss, [sc], [g], rng)
+
+
+def test_background_term_matches_finite_differences(orc):
+    """Eq. 6-7 with a background behind the last cell (B_{K+1} = bg): the
+    transmittance gradient of every cell gets P_j G.B_{j+1} with the
+    background in B, through two depth-separated cells."""
+    import dataclasses
+    st = dataclasses.replace(ST, bg=(0.3, 0.6, 0.9))
+    cam = synth.fd_camera()
+    part_of = lambda s: synth.axis_slab_partition(s, 2, [-10.0, 0.0, 10.0])
+    cells = part_of(synth.fd_scene(0)).cells
+
+    def scenes_of(seed):
+        s = synth.fd_scene(seed).astype(np.float64)
+        return part_of(s).cell_scenes(s)
+    scenes, _ = _flag_free(orc, scenes_of, cells, cam, st, range(500, 540))
+    rng = np.random.default_rng(12)
+    wr = rng.normal(size=(cam.height, cam.width, 3))
+    wt = rng.normal(size=(cam.height, cam.width))
+    fr = orc.forward(scenes, cells, cam, st)
+    grads = orc.backward(scenes, cells, cam, st, fr, wr, wt)
+    # against bg = 0 the gradients differ (the background term is exercised)
+    fr0 = orc.forward(scenes, cells, cam, ST)
+    g0 = orc.backward(scenes, cells, cam, ST, fr0, wr, wt)
+    assert np.abs(grads[0]["opacity_logits"] - g0[0]["opacity_logits"]).max() > \
+        0.05 * np.abs(grads[0]["opacity_logits"]).max()
+
+    def loss():
+        f = orc.forward(scenes, cells, cam, st)
+        return float((f.comp["rgb"] * wr).sum() + (f.comp["T"] * wt).sum())
+    _fd_grads(loss, scenes, grads, rng, per_array=60)
+
+
+def clamp_scene(seed):
+    """The finite-difference scene with Gaussian 0 made nearly opaque
+    (logit 8, o = 0.99966), large (log-scales about -1) and in front of the others
+    on the optical axis, so that alpha = o exp(-q/2) exceeds alpha_max = 0.99
+    at the pixel centres within about 1.4 of its 10-pixel sigma."""
+    s = synth.fd_scene(seed).astype(np.float64)
+    s.means[0] = (0.03, -0.02, -1.2)
+    s.log_scales[0] = (-0.85, -1.15, -1.0)
+    s.opacity_logits[0] = 8.0
+    return s
+
+
+def test_clamped_alpha_matches_finite_differences(orc):
+    """Eq. 1 with the clamp alpha = min(alpha_max, o G): where it is clamped
+    alpha does not depend on the opacity or the conic, so those pairs pass
+    no gradient to them (only colour and the transmittance chain see them).
+    Central differences of every parameter of the clamped Gaussian and a
+    sample of the others."""
+    cam = synth.fd_camera()
+    cell = [synth.Cell((-math.inf,) * 3, (math.inf,) * 3)]
+    scenes, _ = _flag_free(orc, lambda s: [clamp_scene(s)], cell, cam, ST, range(600, 640))
+    sc = scenes[0]
+    pr = orc.preprocess(sc, cam, ST)
+    # pixel centres where Gaussian 0 is clamped (it is first on every ray)
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width] + 0.5
+    dx, dy = xs - pr["mean2d"][0, 0], ys - pr["mean2d"][0, 1]
+    a, b, c = pr["conic"][0]
+    G = np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+    n_clamped = int((pr["opacity"][0] * G > ST.alpha_max).sum())
+    assert n_clamped >= 3, n_clamped
+    rng = np.random.default_rng(13)
+    wc = rng.normal(size=(cam.height, cam.width, 3))
+    wt = rng.normal(size=(cam.height, cam.width))
+    g = orc.render_backward(sc, cam, ST, wc, wt, None)
+
+    def loss():
+        r = orc.render(sc, cam, ST)
+        return float((r["C"] * wc).sum() + (r["T"] * wt).sum())
+    _fd_grads(loss, [sc], [g], rng, only={0: [0]})
+    _fd_grads(loss, [sc], [g], rng, names=("means", "opacity_logits"), per_array=40)
+
+
+def same_frame_scenes(seed):
+    """A 32-Gaussian finite-difference scene in two depth slabs (camera-side
+    slab z < 0) with the front slab's Gaussians made larger (log-scale + 0.4)
+    and opaque (logit + 4), so that the transmittance through it drops below
+    t_min on part of the image."""
+    s = synth.fd_scene(seed, n=32).astype(np.float64)
+    front = s.means[:, 2] < 0
+    s.log_scales[front] += 0.4
+    s.opacity_logits[front] += 4.0
+    part = synth.axis_slab_partition(s, 2, [-10.0, 0.0, 10.0])
+    return part.cell_scenes(s), part.cells
+
+
+def test_same_frame_cull_matches_finite_differences(orc):
+    """The saturation rule applied in the same frame: a cell behind a prefix
+    with P_j < t_min is treated as the identity in Eq. 5 and gets no
+    gradient (its dC, dT are zero and the cells in front of it see B and U
+    without it).  t_min = 0.05 here so that two opaque slabs saturate;
+    central differences through two cells with the culling on."""
+    import dataclasses
+    st = dataclasses.replace(ST, t_min=0.05)
+    cam = synth.fd_camera()
+    cells = same_frame_scenes(0)[1]
+
+    def culls(fr):
+        return int((fr.comp["mask"][1] == 0).sum()) >= 20
+    scenes, fr = _flag_free(orc, lambda s: same_frame_scenes(s)[0], cells, cam, st,
+                            range(700, 760), accept=culls, same_frame_cull=True)
+    rng = np.random.default_rng(14)
+    wr = rng.normal(size=(cam.height, cam.width, 3))
+    wt = rng.normal(size=(cam.height, cam.width))
+    fr = orc.forward(scenes, cells, cam, st, same_frame_cull=True)
+    grads = orc.backward(scenes, cells, cam, st, fr, wr, wt, same_frame_cull=True)
+    # culling changes the image and the back cell's gradients
+    fr0 = orc.forward(scenes, cells, cam, st)
+    assert np.abs(fr0.comp["rgb"] - fr.comp["rgb"]).max() > 1e-4
+    g0 = orc.backward(scenes, cells, cam, st, fr0, wr, wt)
+    assert np.abs(g0[1]["means"] - grads[1]["means"]).max() > 0
+
+    def loss():
+        f = orc.forward(scenes, cells, cam, st, same_frame_cull=True)
+        return float((f.comp["rgb"] * wr).sum() + (f.comp["T"] * wt).sum())
+    _fd_grads(loss, scenes, grads, rng, per_array=60)
+
+
 # ------------------------------------------------------------- harness ----
 def test_l1_and_adam_match_torch(orc):
     import torch
