@@ -396,13 +396,20 @@ def render_backward(scene, cam, settings, dC=None, dT=None, dD=None,
                     mask=None, xfilter=None) -> dict:
     """Gradients of one cell's partial render with respect to the screen
     quantities (g2d [n,10]: mean2d x/y, conic a/b/c, opacity, rgb, depth) and
-    the raw parameters (means, log_scales, quats, opacity_logits, sh)."""
+    the raw parameters (means, log_scales, quats, opacity_logits, sh).  Also
+    g2d_scale [n,10]: a first-order scale of the rounding error of an FP32
+    evaluation of each screen-space entry, in units of the FP32 unit
+    roundoff (for test tolerances; it enters no gradient): per pixel term,
+    the sizes of the quantities it is formed from before they cancel, times
+    the ulps its inputs carry (the pairs the walk spans, the rounding of
+    alpha from FP32 screen position, conic and opacity)."""
     n = scene.n
     nc = scene.sh.shape[1]
     s = _scene64(scene)
     out = dict(g2d=np.zeros((n, 10)), means=np.zeros((n, 3)),
                log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
-               opacity_logits=np.zeros(n), sh=np.zeros((n, nc, 3)))
+               opacity_logits=np.zeros(n), sh=np.zeros((n, nc, 3)),
+               g2d_scale=np.zeros((n, 10)))
 
     def arr(a):
         return None if a is None else np.ascontiguousarray(np.asarray(a, np.float64))
@@ -413,7 +420,25 @@ def render_backward(scene, cam, settings, dC=None, dT=None, dD=None,
         ctypes.byref(_params(settings, _sh_degree(scene))), _p(m),
         _p(arr(dC)), _p(arr(dT)), _p(arr(dD)), _p(out["g2d"]),
         _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]),
-        _p(out["opacity_logits"]), _p(out["sh"]), _p(xf), _p(pb))
+        _p(out["opacity_logits"]), _p(out["sh"]), _p(xf), _p(pb), _p(out["g2d_scale"]))
+    return out
+
+
+def preprocess_backward(scene, cam, settings, g2d) -> dict:
+    """The projection backward alone: screen-space gradients g2d [n,10] of
+    one view (as render_backward returns them) chained to the raw
+    parameters (means, log_scales, quats, opacity_logits, sh)."""
+    n = scene.n
+    nc = scene.sh.shape[1]
+    s = _scene64(scene)
+    out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+               opacity_logits=np.zeros(n), sh=np.zeros((n, nc, 3)))
+    g = np.ascontiguousarray(np.asarray(g2d, np.float64)[:, :10])
+    lib().or_preprocess_backward(
+        ctypes.c_int64(n), *[_p(a) for a in s], ctypes.byref(_cam(cam)),
+        ctypes.byref(_params(settings, _sh_degree(scene))), _p(g),
+        _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]),
+        _p(out["opacity_logits"]), _p(out["sh"]))
     return out
 
 

@@ -893,18 +893,41 @@ int or_composite_backward(int K, const double* Cparts, const double* Tparts,
 // Outputs (accumulated with +=, caller zeroes):
 //   g2d [n*10]: dmean2d(2), dconic(3), dopacity, drgb(3), ddepth  (screen)
 //   gmeans [n*3], glog_scales [n*3], gquats [n*4], glogits [n], gsh [n*nc*3]
+// Chain of the screen-space gradients acc [n][10] (mean2d x, y, conic a, b,
+// c, opacity, rgb, depth) through the projection to the raw parameters
+// (paper, background: the parametrisation Sigma = R S S^T R^T, the EWA
+// projection and the SH colour), added into the parameter gradients.
+static void chain_to_params(const SceneIn& s, const Cam* cam, const Params* P,
+                            const std::vector<Proj>& pr, const double* acc,
+                            double* gmeans, double* glog_scales, double* gquats,
+                            double* glogits, double* gsh);
+
 int or_render_backward(int64_t n, const double* means, const double* log_scales,
                        const double* quats, const double* logits, const double* sh,
                        const Cam* cam, const Params* P, const uint8_t* mask,
                        const double* dC, const double* dT, const double* dD,
                        double* g2d, double* gmeans, double* glog_scales,
                        double* gquats, double* glogits, double* gsh,
-                       const uint32_t* xf, const uint32_t* pixbits) {
+                       const uint32_t* xf, const uint32_t* pixbits, double* g2d_scale) {
   SceneIn s{n, means, log_scales, quats, logits, sh};
   std::vector<Proj> pr = preprocess_all(s, *cam, *P);
   Bins b = make_bins(pr, *cam, *P);
   const int W = cam->width, H = cam->height;
   std::vector<double> acc((size_t)n * 10, 0.0);
+  // Optional first-order rounding-error scale of each screen-space gradient
+  // entry of an FP32 evaluation (test tolerances only; it enters no
+  // gradient), in units of the FP32 unit roundoff.  Per pixel term:
+  //  - the magnitudes the term is formed from before they cancel (for
+  //    d alpha: T_i (|G| (|c| + |R|) + |g_D| (|z| + |RD|)) + |g_T| T_i U);
+  //  - times (N + 16 + rho): a walk that recovers T_i and carries R, RD and
+  //    U over the pixel's N blended pairs is off by a few ulps per pair, and
+  //    alpha computed from FP32 record fields is off by rho ulps relative,
+  //    rho = (dq/u)/2 + 3 with dq the error of q from rounding the screen
+  //    position (held relative to the principal point: magnitude M =
+  //    max|mean2d - c| + max(W, H)/2 pixels), the conic and q's own sum;
+  //  - plus the rounding of the offsets dx, dy (M ulps) in the factors of
+  //    the mean and conic terms.
+  std::vector<double> sacc(g2d_scale ? (size_t)n * 10 : 0, 0.0);
 #pragma omp parallel
   {
     std::vector<Blend> bl;
@@ -949,21 +972,78 @@ int or_render_backward(int64_t n, const double* means, const double* log_scales,
 #pragma omp atomic
             a[k] += loc[k];
           }
+          if (g2d_scale) {
+            double sa = 0.0;
+            for (int k = 0; k < 3; ++k) sa += std::fabs(G[k]) * (std::fabs(pj.rgb[k]) + std::fabs(R[k]));
+            sa = e.Ti * (sa + std::fabs(gD) * (std::fabs(pj.depth) + std::fabs(RD)) +
+                         std::fabs(gT) * U);
+            const double A = std::fabs(pj.conic[0]), Bc = std::fabs(pj.conic[1]),
+                         Cc = std::fabs(pj.conic[2]);
+            const double ax = std::fabs(e.dx), ay = std::fabs(e.dy);
+            const double M = std::max(std::fabs(pj.mean2d[0] - cam->cx),
+                                      std::fabs(pj.mean2d[1] - cam->cy)) +
+                             0.5 * std::max(W, H);
+            const double qabs = A * ax * ax + 2.0 * Bc * ax * ay + Cc * ay * ay;
+            const double rho =
+                0.5 * (2.0 * ((A * ax + Bc * ay) + (Bc * ax + Cc * ay)) * M + 2.0 * qabs) + 3.0;
+            const double f = (double)bl.size() + 16.0 + rho;
+            double sl[10] = {0};
+            for (int k = 0; k < 3; ++k) sl[6 + k] = f * std::fabs(w * G[k]);
+            sl[9] = f * std::fabs(w * gD);
+            if (!e.clamped) {
+              sl[5] = f * sa * e.gval;
+              const double dq = sa * 0.5 * e.alpha;
+              sl[0] = dq * 2.0 * (f * (A * ax + Bc * ay) + (A + Bc) * M);
+              sl[1] = dq * 2.0 * (f * (Bc * ax + Cc * ay) + (Bc + Cc) * M);
+              sl[2] = dq * (f * ax * ax + 2.0 * ax * M);
+              sl[3] = dq * 2.0 * (f * ax * ay + (ax + ay) * M);
+              sl[4] = dq * (f * ay * ay + 2.0 * ay * M);
+            }
+            double* sc = &sacc[(size_t)e.g * 10];
+            for (int k = 0; k < 10; ++k) {
+#pragma omp atomic
+              sc[k] += sl[k];
+            }
+          }
           for (int k = 0; k < 3; ++k) R[k] = pj.rgb[k] * e.alpha + (1.0 - e.alpha) * R[k];
           RD = pj.depth * e.alpha + (1.0 - e.alpha) * RD;
           U *= (1.0 - e.alpha);
         }
       }
   }
+  if (g2d)
+    for (size_t k = 0; k < acc.size(); ++k) g2d[k] += acc[k];
+  if (g2d_scale)
+    for (size_t k = 0; k < sacc.size(); ++k) g2d_scale[k] += sacc[k];
+  chain_to_params(s, cam, P, pr, acc.data(), gmeans, glog_scales, gquats, glogits, gsh);
+  return 0;
+}
+
+// The projection backward alone: screen-space gradients g2d_in [n][10] of a
+// view chained to the parameters (added into the outputs).
+int or_preprocess_backward(int64_t n, const double* means, const double* log_scales,
+                           const double* quats, const double* logits, const double* sh,
+                           const Cam* cam, const Params* P, const double* g2d_in,
+                           double* gmeans, double* glog_scales, double* gquats,
+                           double* glogits, double* gsh) {
+  SceneIn s{n, means, log_scales, quats, logits, sh};
+  std::vector<Proj> pr = preprocess_all(s, *cam, *P);
+  chain_to_params(s, cam, P, pr, g2d_in, gmeans, glog_scales, gquats, glogits, gsh);
+  return 0;
+}
+
+}  // extern "C"
+
+static void chain_to_params(const SceneIn& s, const Cam* cam, const Params* P,
+                            const std::vector<Proj>& pr, const double* acc,
+                            double* gmeans, double* glog_scales, double* gquats,
+                            double* glogits, double* gsh) {
+  const int64_t n = s.n;
   const int nc = (P->sh_degree + 1) * (P->sh_degree + 1);
-  double Cc[3];
-  cam_center(*cam, Cc);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     const Proj& p = pr[i];
-    double* a = &acc[(size_t)i * 10];
-    if (g2d)
-      for (int k = 0; k < 10; ++k) g2d[i * 10 + k] += a[k];
+    const double* a = &acc[(size_t)i * 10];
     if (!p.valid) continue;
     const Gauss g = gauss_at(s, i, nc);
     // colour -> SH coefficients and view direction
@@ -1094,8 +1174,9 @@ int or_render_backward(int64_t n, const double* means, const double* log_scales,
       gmeans[i * 3 + k] += v + gmu[k];
     }
   }
-  return 0;
 }
+
+extern "C" {
 
 // Visible-pixel maps of K cell boxes for one camera: vis [K][H*W] bytes
 // (1 = the pixel's centre ray meets the part of the box inside the

@@ -373,6 +373,32 @@ def fd_camera() -> Camera:
     return tiny_camera(64, 64)
 
 
+def clamp_fd_scene(seed: int) -> Scene:
+    """The finite-difference scene (FP64) with Gaussian 0 made nearly opaque
+    (logit 8, o = 0.99966), large (log-scales about -1) and in front of the
+    others on the optical axis, so that o exp(-q/2) exceeds an alpha clamp of
+    0.99 at the pixel centres within about 1.4 of its 10-pixel sigma."""
+    s = fd_scene(seed).astype(np.float64)
+    s.means[0] = (0.03, -0.02, -1.2)
+    s.log_scales[0] = (-0.85, -1.15, -1.0)
+    s.opacity_logits[0] = 8.0
+    return s
+
+
+def same_frame_fd_scenes(seed: int):
+    """A 32-Gaussian finite-difference scene (FP64) in two depth slabs
+    (camera-side slab z < 0) with the front slab's Gaussians made larger
+    (log-scale + 0.4) and opaque (logit + 4), so that the transmittance
+    through it drops below a threshold of 0.05 on part of the 64x64 view.
+    Returns (cell scenes, cells)."""
+    s = fd_scene(seed, n=32).astype(np.float64)
+    front = s.means[:, 2] < 0
+    s.log_scales[front] += 0.4
+    s.opacity_logits[front] += 4.0
+    part = axis_slab_partition(s, 2, [-10.0, 0.0, 10.0])
+    return part.cell_scenes(s), part.cells
+
+
 def g2_scene(seed: int = 1, n: int = 2_000_000) -> Scene:
     """One GPU's share: 2M Gaussians on a 1 km x 1 km ground plane, SH3."""
     return make_ground_scene(seed, n)

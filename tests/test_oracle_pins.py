@@ -928,18 +928,6 @@ def test_background_term_matches_finite_differences(orc):
     _fd_grads(loss, scenes, grads, rng, per_array=60)
 
 
-def clamp_scene(seed):
-    """The finite-difference scene with Gaussian 0 made nearly opaque
-    (logit 8, o = 0.99966), large (log-scales about -1) and in front of the others
-    on the optical axis, so that alpha = o exp(-q/2) exceeds alpha_max = 0.99
-    at the pixel centres within about 1.4 of its 10-pixel sigma."""
-    s = synth.fd_scene(seed).astype(np.float64)
-    s.means[0] = (0.03, -0.02, -1.2)
-    s.log_scales[0] = (-0.85, -1.15, -1.0)
-    s.opacity_logits[0] = 8.0
-    return s
-
-
 def test_clamped_alpha_matches_finite_differences(orc):
     """Eq. 1 with the clamp alpha = min(alpha_max, o G): where it is clamped
     alpha does not depend on the opacity or the conic, so those pairs pass
@@ -948,7 +936,7 @@ def test_clamped_alpha_matches_finite_differences(orc):
     sample of the others."""
     cam = synth.fd_camera()
     cell = [synth.Cell((-math.inf,) * 3, (math.inf,) * 3)]
-    scenes, _ = _flag_free(orc, lambda s: [clamp_scene(s)], cell, cam, ST, range(600, 640))
+    scenes, _ = _flag_free(orc, lambda s: [synth.clamp_fd_scene(s)], cell, cam, ST, range(600, 640))
     sc = scenes[0]
     pr = orc.preprocess(sc, cam, ST)
     # pixel centres where Gaussian 0 is clamped (it is first on every ray)
@@ -970,19 +958,6 @@ def test_clamped_alpha_matches_finite_differences(orc):
     _fd_grads(loss, [sc], [g], rng, names=("means", "opacity_logits"), per_array=40)
 
 
-def same_frame_scenes(seed):
-    """A 32-Gaussian finite-difference scene in two depth slabs (camera-side
-    slab z < 0) with the front slab's Gaussians made larger (log-scale + 0.4)
-    and opaque (logit + 4), so that the transmittance through it drops below
-    t_min on part of the image."""
-    s = synth.fd_scene(seed, n=32).astype(np.float64)
-    front = s.means[:, 2] < 0
-    s.log_scales[front] += 0.4
-    s.opacity_logits[front] += 4.0
-    part = synth.axis_slab_partition(s, 2, [-10.0, 0.0, 10.0])
-    return part.cell_scenes(s), part.cells
-
-
 def test_same_frame_cull_matches_finite_differences(orc):
     """The saturation rule applied in the same frame: a cell behind a prefix
     with P_j < t_min is treated as the identity in Eq. 5 and gets no
@@ -992,11 +967,11 @@ def test_same_frame_cull_matches_finite_differences(orc):
     import dataclasses
     st = dataclasses.replace(ST, t_min=0.05)
     cam = synth.fd_camera()
-    cells = same_frame_scenes(0)[1]
+    cells = synth.same_frame_fd_scenes(0)[1]
 
     def culls(fr):
         return int((fr.comp["mask"][1] == 0).sum()) >= 20
-    scenes, fr = _flag_free(orc, lambda s: same_frame_scenes(s)[0], cells, cam, st,
+    scenes, fr = _flag_free(orc, lambda s: synth.same_frame_fd_scenes(s)[0], cells, cam, st,
                             range(700, 760), accept=culls, same_frame_cull=True)
     rng = np.random.default_rng(14)
     wr = rng.normal(size=(cam.height, cam.width, 3))
@@ -1013,6 +988,39 @@ def test_same_frame_cull_matches_finite_differences(orc):
         f = orc.forward(scenes, cells, cam, st, same_frame_cull=True)
         return float((f.comp["rgb"] * wr).sum() + (f.comp["T"] * wt).sum())
     _fd_grads(loss, scenes, grads, rng, per_array=60)
+
+
+def test_projection_backward_alone_and_error_scale(orc):
+    """The projection backward on its own (the chain from screen-space to
+    parameter gradients) reproduces the parameter gradients of the full
+    render backward from its screen-space gradients (the same chain; the
+    full chain is pinned by the central differences above), and is linear
+    in them.  The rounding-error scale that tolerances use bounds each
+    entry's magnitude from above by at least its 16-fold (every term is
+    counted with its pre-cancellation magnitude, times at least the pixel's
+    blended pairs + 16) and is zero exactly where a Gaussian has no blended
+    pair."""
+    cam = synth.fd_camera()
+    sc = synth.fd_scene(3).astype(np.float64)
+    rng = np.random.default_rng(5)
+    wc = rng.normal(size=(cam.height, cam.width, 3))
+    wt = rng.normal(size=(cam.height, cam.width))
+    wd = rng.normal(size=(cam.height, cam.width))
+    rb = orc.render_backward(sc, cam, ST, wc, wt, wd)
+    pb = orc.preprocess_backward(sc, cam, ST, rb["g2d"])
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        np.testing.assert_allclose(pb[name], rb[name], rtol=1e-12, atol=1e-14 *
+                                   max(1.0, np.abs(rb[name]).max()), err_msg=name)
+    pb2 = orc.preprocess_backward(sc, cam, ST, 2.0 * rb["g2d"])
+    np.testing.assert_allclose(pb2["means"], 2.0 * pb["means"], rtol=1e-12, atol=1e-14)
+    sc_ = rb["g2d_scale"]
+    assert np.all(sc_ >= 16.0 * np.abs(rb["g2d"]) * (1.0 - 1e-12))
+    r = orc.render(sc, cam, ST)
+    blended = np.zeros(sc.n, bool)
+    pr = orc.preprocess(sc, cam, ST)
+    blended[pr["valid"] == 1] = np.abs(rb["g2d"][pr["valid"] == 1]).max(1) > 0
+    assert np.array_equal(sc_.max(1) > 0, blended)
+    assert r["nblend"].sum() > 0
 
 
 # ------------------------------------------------------------- harness ----
