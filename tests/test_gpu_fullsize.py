@@ -4,13 +4,15 @@ view, 16x16 tiles, through the same calls.
 
 - preprocess: the tile count of every Gaussian bit-exact; the records of a
   sample of visible Gaussians within FP32 rounding of the oracle's FP64;
-- sort: visible and instance counts, then every key and value of the 32M
+- sort: visible and instance counts, then every key and value of the 824k
   instances and every tile range, bit-exact;
 - render: a sample of tiles (random ones plus the corners and the ragged
   bottom row) against the oracle restricted to those tiles by its pixel mask;
 - backward: an upstream gradient that is non-zero only on unflagged pixels
   of the sampled tiles, so the oracle's screen-space and parameter gradients
-  are exact references for the kernel's full-image backward.
+  are exact references for the kernel's full-image backward (per element,
+  1e-3 relative above FULL_FLOOR of each family's largest entry);
+- the fraction of flagged pixels is reported and bounded.
 """
 import numpy as np
 import pytest
@@ -18,10 +20,15 @@ import pytest
 import oracle
 import synth
 from gpu_helpers import (assert_ranges, assert_same, compare_image, jump_bound, need_gpu,
-                         rec_fields, rel_err)
+                         rec_fields, check_grad, check_grad_scaled, FULL_FLOOR)
 
 pytestmark = pytest.mark.gpu
 ST = synth.RenderSettings()
+# bounds on the fraction of sampled pixels the oracle flags as ambiguous
+# (measured 0.37% on the 2M view; 2.0-2.4% with 8 cells, where the flags of
+# eight renders and of the composition order add up)
+FLAG_G2 = 0.01
+FLAG_K8 = 0.05
 
 
 @pytest.fixture(scope="module")
@@ -93,7 +100,7 @@ def test_fullsize_render_and_backward(g2):
     part = v.partial.cpu().numpy()
     cmax = float(rec_fields(v.rec)["rgb"][v.n_tiles.cpu().numpy() > 0].max())
     e, nf = compare_image(part[on][:, :3], ref["C"][on], ref["flags"][on], 1e-4,
-                          jump_bound(ST, cmax))
+                          jump_bound(ST, cmax), max_flagged=FLAG_G2)
     compare_image(part[on][:, 3], ref["T"][on], ref["flags"][on], 1e-4, 1.0)
     nb = v.nblend.cpu().numpy()
     ok = on & (ref["flags"] == 0)
@@ -116,11 +123,16 @@ def test_fullsize_render_and_backward(g2):
     assert hit.sum() > 100
     vis = v.n_tiles.cpu().numpy() > 0
     for c in range(9):
-        e = rel_err(g2d[vis, c], rb["g2d"][vis, c])
-        assert e <= 2e-3, (c, e)
+        check_grad_scaled(g2d[vis, c], rb["g2d"][vis, c], rb["g2d_scale"][vis, c],
+                          f"G2 g2d[{c}]")
+    # the parameter gradients: the projection backward of the kernel's own
+    # screen-space gradients, and against the oracle's end to end
+    pb = oracle.preprocess_backward(scene, cam, ST, v.g2d.cpu().numpy())
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         got = getattr(grads, name).cpu().numpy()[vis]
-        assert rel_err(got, rb[name][vis]) <= 2e-3, name
+        check_grad(got, pb[name][vis], f"G2 {name} (chain of the kernel's g2d)", tol=1e-5,
+                   floor=1e-4)
+        check_grad(got, rb[name][vis], f"G2 {name}", floor=FULL_FLOOR)
 
 
 # ------------------------------------------------------------ K = 8 cells --
@@ -163,7 +175,7 @@ def test_fullsize_k8_composite_and_backward(g8):
                for v in fr.views)  # a cell behind the camera has no visible Gaussian
     out = g8["out"]
     e, nf = compare_image(out[on][:, :3], ref.comp["rgb"][on], fl[on], 1e-4,
-                          K * jump_bound(ST, cmax))
+                          K * jump_bound(ST, cmax), max_flagged=FLAG_K8)
     compare_image(out[on][:, 3], ref.comp["T"][on], fl[on], 1e-4, 1.0)
     masks = fr.masks.cpu().numpy().view(np.uint32)
     bits = np.unpackbits(masks.view(np.uint8), bitorder="little").reshape(K, -1)[:, :cam.width * cam.height]
@@ -190,10 +202,14 @@ def test_fullsize_k8_composite_and_backward(g8):
             continue
         g2d = fr.views[k].g2d.cpu().numpy()[:, :10]
         for c in range(9):
-            assert rel_err(g2d[vis, c], gref[k]["g2d"][vis, c]) <= 2e-3, (k, c)
+            check_grad_scaled(g2d[vis, c], gref[k]["g2d"][vis, c],
+                              gref[k]["g2d_scale"][vis, c], f"K=8 cell {k} g2d[{c}]")
+        pb = oracle.preprocess_backward(scenes[k], cam, ST, fr.views[k].g2d.cpu().numpy())
         for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
             got = getattr(grads[k], name).cpu().numpy()[vis]
-            assert rel_err(got, gref[k][name][vis]) <= 2e-3, (k, name)
+            check_grad(got, pb[name][vis], f"K=8 cell {k} {name} (chain of the kernel's g2d)",
+                       tol=1e-5, floor=1e-4)
+            check_grad(got, gref[k][name][vis], f"K=8 cell {k} {name}", floor=FULL_FLOOR)
     assert hit > 100
 
 
@@ -234,7 +250,8 @@ def test_fullsize_k8_cross_filter_and_reeval(g8):
     on = m == 1
     cmax = max(float(rec_fields(v.rec)["rgb"][v.n_tiles.cpu().numpy() > 0].max(initial=0.0))
                for v in fr.views)
-    e, nf = compare_image(out[on][:, :3], rr["rgb"][on], fl[on], 1e-4, K * jump_bound(ST, cmax))
+    e, nf = compare_image(out[on][:, :3], rr["rgb"][on], fl[on], 1e-4, K * jump_bound(ST, cmax),
+                          max_flagged=FLAG_K8)
     compare_image(out[on][:, 3], rr["T"][on], fl[on], 1e-4, 1.0)
     ok = (on & (fl == 0)).reshape(-1)
     bits = np.unpackbits(fr.masks.cpu().numpy().view(np.uint8), bitorder="little").reshape(K, -1)[:, :H * W]
@@ -244,3 +261,41 @@ def test_fullsize_k8_cross_filter_and_reeval(g8):
     pruned = int(((rr["mask"] == 0) & (om == 1)).reshape(K, -1)[:, ok].sum())
     print(f"full-size K=8 filtered + re-evaluated: {nfilt} filtered Gaussians, "
           f"max-abs {e:.3g}, flagged {nf}, pruned pairs {pruned}", flush=True)
+
+
+# --------------------------------------------- sort: reduce-then-scan form --
+@pytest.mark.parametrize("view", ["aerial 45 deg", "nadir 700 m"])
+def test_sort_reduce_then_scan_bit_exact(view):
+    """Above 2,097,152 Gaussians (more than 512 partitions of 4096 depth
+    keys) every depth pass of the sort runs in its reduce-then-scan form
+    (per-partition digit counts, a scan per digit over the partitions, then
+    the ranking and scatter) instead of the decoupled look-back.  On a
+    2.2M-Gaussian ground scene, the benchmark's aerial view (about 180k
+    visible) and a nadir view from 700 m that sees about half the scene
+    (about 290 partitions in use): every key, value and tile range
+    bit-exact against the oracle's stable sort, overflow and error words
+    zero."""
+    need_gpu()
+    import torch
+    from paper_2606_18588_amd.pipeline import CellView, GaussianParams, spatial_order
+    print(f"case: sort reduce-then-scan, 2.2M Gaussians, {view}", flush=True)
+    scene = synth.g2_scene(n=2_200_000)
+    scene = scene.subset(spatial_order(scene.means))
+    cam = (synth.g2_camera() if view.startswith("aerial")
+           else synth.nadir_camera((0.0, 0.0, 700.0), 1920, 1080))
+    params = GaussianParams.from_scene(scene)
+    v = CellView(params, cam, ST, keep_keys=True)
+    assert (params.n + 4095) // 4096 > 512
+    v.preprocess()
+    counts = v.sort(sync=True)
+    v.post_counts()
+    vis, inst, over = v.poll_counts()  # raises if a bounded wait ran out
+    assert over == 0 and (vis, inst) == tuple(counts)
+    keys, vals, ranges = oracle.sort_keys(scene, cam, ST)
+    print(f"reduce-then-scan sort: {vis} visible, {inst} instances", flush=True)
+    assert inst == len(keys)
+    assert_same(v.keys[:inst].cpu().numpy().view(np.uint64), keys, "keys")
+    assert_same(v.vals[:inst].cpu().numpy().view(np.uint32), vals, "vals")
+    assert_ranges(v.ranges.cpu().numpy().view(np.uint32)[:-1], ranges)
+    del v, params
+    torch.cuda.empty_cache()

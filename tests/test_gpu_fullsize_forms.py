@@ -15,7 +15,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import compare_image, jump_bound, need_gpu, rec_fields, rel_err
+from gpu_helpers import (FULL_FLOOR, check_grad, check_grad_scaled, compare_image, jump_bound,
+                         need_gpu, rec_fields)
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +56,7 @@ def test_fullsize_batched_views(torch_gpu_fs):
         part = v.partial.cpu().numpy()
         cmax = float(rec_fields(v.rec)["rgb"][v.n_tiles.cpu().numpy() > 0].max())
         e, nf = compare_image(part[on][:, :3], ref["C"][on], ref["flags"][on], 1e-4,
-                              jump_bound(st, cmax))
+                              jump_bound(st, cmax), max_flagged=0.05)
         compare_image(part[on][:, 3], ref["T"][on], ref["flags"][on], 1e-4, 1.0)
         print(f"batched view {k} {c.width}x{c.height}: max-abs {e:.3g} flagged {nf}", flush=True)
         if k == 0:
@@ -77,10 +78,14 @@ def test_fullsize_batched_views(torch_gpu_fs):
     assert (np.abs(rb["g2d"]).max(1) > 0).sum() > 100
     g2d = bv.views[0].g2d.cpu().numpy()[:, :10]
     for c in range(9):
-        assert rel_err(g2d[vis, c], rb["g2d"][vis, c]) <= 2e-3, c
+        check_grad_scaled(g2d[vis, c], rb["g2d"][vis, c], rb["g2d_scale"][vis, c],
+                          f"15M batched g2d[{c}]")
+    pb = oracle.preprocess_backward(scene, cams[0], st, bv.views[0].g2d.cpu().numpy())
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         got = getattr(grads, name).cpu().numpy()[vis]
-        assert rel_err(got, rb[name][vis]) <= 2e-3, name
+        check_grad(got, pb[name][vis], f"15M batched {name} (chain of the kernel's g2d)",
+                   tol=1e-5, floor=1e-4)
+        check_grad(got, rb[name][vis], f"15M batched {name}", floor=FULL_FLOOR)
 
 
 def test_fullsize_served_4k_request(torch_gpu_fs):
@@ -105,6 +110,6 @@ def test_fullsize_served_4k_request(torch_gpu_fs):
     ref = oracle.render(scene, big, st, mask=m)
     on = m == 1
     e, nf = compare_image(img[on][:, :3], ref["C"][on], ref["flags"][on], 1e-4,
-                          jump_bound(st, 1.5))
+                          jump_bound(st, 1.5), max_flagged=0.05)
     compare_image(img[on][:, 3], ref["T"][on], ref["flags"][on], 1e-4, 1.0)
     print(f"served 4K: max-abs {e:.3g} flagged {nf}", flush=True)

@@ -6,8 +6,9 @@ Tolerances: integer/byte/index work bit-exact (tile counts, footprints,
 sort keys, values, ranges, masks); pixels max-abs 1e-4 on pixels the oracle
 does not flag as ambiguous (a pair within rounding reach of alpha_min, a
 transmittance within reach of t_min, an ambiguous float32 depth rounding or
-composite order), flagged pixels within the jump bound; gradients within
-1e-3 of the largest entry of their parameter family.
+composite order), flagged pixels within the jump bound; gradients per
+element within 1e-3 relative, each entry's magnitude floored at 1e-3 of
+the largest entry of its parameter family.
 """
 import math
 
@@ -17,8 +18,8 @@ import pytest
 import oracle
 import synth
 from gpu_helpers import (assert_ranges, assert_same, big_box, compare_image,
-                         expand_lists, grid_cells_xy, jump_bound, need_gpu,
-                         rec_fields, rel_err)
+                         check_grad, expand_lists, grid_cells_xy, jump_bound,
+                         need_gpu, rec_fields)
 
 pytestmark = pytest.mark.gpu
 ST = synth.RenderSettings()
@@ -548,7 +549,7 @@ def test_cross_boundary_filter_matches_oracle(torch_gpu, cells_kind, tile):
             continue
         for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
             got = getattr(grads[k], name).cpu().numpy()[v]
-            assert rel_err(got, gref[k][name][v]) <= 2e-3, (k, name)
+            check_grad(got, gref[k][name][v], f"filtered cell {k} {name}")
 
 
 def test_cross_boundary_filter_degenerate_cases(torch_gpu):
@@ -805,8 +806,7 @@ def test_backward_matches_oracle_and_fd(torch_gpu, K):
     for k in range(K):
         for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
             got = getattr(grads[k], name).cpu().numpy().astype(np.float64)
-            e = rel_err(got, gref[k][name])
-            assert e <= 1e-3, (k, name, e)
+            check_grad(got, gref[k][name], f"K={K} cell {k} {name}")
 
 
 def test_backward_screen_space_matches_oracle(torch_gpu):
@@ -838,11 +838,10 @@ def test_backward_screen_space_matches_oracle(torch_gpu):
         bad |= (pr_r[:, 0] <= x) & (x <= pr_r[:, 2]) & (pr_r[:, 1] <= y) & (y <= pr_r[:, 3])
     ok = (pr["valid"] == 1) & ~bad
     for c in range(9):
-        e = rel_err(g2d[ok, c], rb["g2d"][ok, c])
-        assert e <= 2e-3, (c, e)
+        check_grad(g2d[ok, c], rb["g2d"][ok, c], f"tiny g2d[{c}]")
     for name in ("means", "opacity_logits", "sh"):
         got = getattr(grads[0], name).cpu().numpy()[ok]
-        assert rel_err(got, rb[name][ok]) <= 2e-3, name
+        check_grad(got, rb[name][ok], f"tiny {name}")
 
 
 # ------------------------------------------------------------------- a10 --
@@ -959,5 +958,4 @@ def test_screen_list_sort_render_backward(torch_gpu, n_near):
     ok = (pr["valid"] == 1) & ~bad
     assert ok[-n_near:].any()
     for c in range(9):
-        e = rel_err(g2d[ok, c], rb["g2d"][ok, c])
-        assert e <= 2e-3, (c, e)
+        check_grad(g2d[ok, c], rb["g2d"][ok, c], f"screen list g2d[{c}]")
