@@ -20,7 +20,9 @@ from .pipeline import Frame, GaussianParams
 class _SplatFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, frame: Frame, *tensors):
-        out = frame.forward()
+        # every cell enqueued asynchronously; one host synchronisation for
+        # the view reads the cells' instance counts back together
+        out = frame.forward_checked()
         ctx.frame = frame
         ctx.n_in = len(tensors)
         rgb = out[..., :3]

@@ -64,9 +64,24 @@ class MultiViewStep:
         self.views = [CellView(params, c, settings, capacity=0, device=device) for c in cams]
         self.targets = list(targets)
         self.counts = [count_instances(v) for v in self.views]
+        self.margin = margin
         self.caps = [int(inst * margin) + 4096 for _, inst in self.counts]
         self.groups = [list(range(i, min(i + self.batch, len(cams))))
                        for i in range(0, len(cams), self.batch)]
+        self._build_arena(device)
+        self.box = [_Box()]
+        self.batches = [BatchedViews.from_views([self.views[i] for i in g]) for g in self.groups]
+        # the batched form overlaps the views' independent sorts and losses
+        self.side = None if plain else [torch.cuda.Stream(device=device) for _ in range(4)]
+        self.adam_m = [torch.zeros_like(t) for t in params.tensors()]
+        self.adam_v = [torch.zeros_like(t) for t in params.tensors()]
+        self.t = 0
+        self.blends = None
+        self.regrown = 0  # arena rebuilds after views came near their capacity
+
+    def _build_arena(self, device):
+        """One arena for the per-instance buffers of the largest group; the
+        groups run one after another and reuse it."""
         need = 0
         layout = {}
         for g in self.groups:
@@ -89,15 +104,32 @@ class MultiViewStep:
             self.views[i].bind_instance_buffers(self.caps[i], vals, ws, bw)
         for v in self.views:
             v.ensure_backward_buffers()
-            v.out = torch.empty_like(v.partial)
-        self.box = [_Box()]
-        self.batches = [BatchedViews.from_views([self.views[i] for i in g]) for g in self.groups]
-        # the batched form overlaps the views' independent sorts and losses
-        self.side = None if plain else [torch.cuda.Stream(device=device) for _ in range(4)]
-        self.adam_m = [torch.zeros_like(t) for t in params.tensors()]
-        self.adam_v = [torch.zeros_like(t) for t in params.tensors()]
-        self.t = 0
-        self.blends = None
+            if getattr(v, "out", None) is None:
+                v.out = torch.empty_like(v.partial)
+
+    def _watch_counts(self):
+        """The previous step's instance counts, posted by its asynchronous
+        sorts (their copies are normally complete by the time the host
+        enqueues the next step).  A view that overflowed raises: that step
+        rendered a truncated list.  Views that came within 5% of their
+        capacity (the Gaussians move and grow during training) get larger
+        buffers before this step."""
+        grow = []
+        for i, v in enumerate(self.views):
+            vis, inst, over = v.poll_counts()
+            self.counts[i] = (vis, inst)
+            if over:
+                raise RuntimeError(f"view {i}: {inst} instances overflowed its capacity "
+                                   "in the previous step")
+            if inst * 1.05 > self.caps[i]:
+                grow.append(i)
+        if grow:
+            torch.cuda.synchronize()  # the old arena may still be in use on side streams
+            for i in grow:
+                self.caps[i] = int(self.counts[i][1] * self.margin) + 4096
+            self.arena = None
+            self._build_arena(self.views[0].device)
+            self.regrown += 1
 
     @property
     def n_views(self):
@@ -111,7 +143,10 @@ class MultiViewStep:
 
     def run(self, lr: float = 1e-4, count_blends: bool = False, check: bool = False):
         """One step; with check, synchronises after each group and raises if
-        any view's instances overflowed its capacity."""
+        any view's instances overflowed its capacity.  Without, the counts
+        of this step are read at the start of the next one."""
+        if self.t > 0 and not check:
+            self._watch_counts()
         blends = 0
         if self.plain:
             for t in self.grads.tensors():
@@ -152,9 +187,9 @@ class MultiViewStep:
 
     def _check(self, group):
         for i in group:
-            c = B.sx_sort_counts(self.views[i].ws, self.params.n)
-            if c[2] or c[1] > self.caps[i]:
-                raise RuntimeError(f"view {i}: {c[1]} instances overflow capacity {self.caps[i]}")
+            vis, inst, over = self.views[i].poll_counts()
+            if over or inst > self.caps[i]:
+                raise RuntimeError(f"view {i}: {inst} instances overflow capacity {self.caps[i]}")
 
 
 class _Box:

@@ -114,6 +114,10 @@ class CellView:
         self.ranges = torch.empty((self.tiles + 1, 2), dtype=torch.int32, device=device)
         self.keep_keys = keep_keys
         self.counts = None
+        # pinned copy of the sort workspace's count words {visible,
+        # instances, overflow, error}, posted after every asynchronous sort
+        self._h_counts = None
+        self._counts_ev = None
         self._alloc_sort(capacity if capacity is not None else max(1024, 4 * n))
         hw = self.H * self.W
         self.partial = torch.empty((self.H, self.W, 4), dtype=torch.float32, device=device)
@@ -175,10 +179,12 @@ class CellView:
     def sort(self, sync=True):
         """With sync, reads the instance count back once and grows the
         buffers when they are too small; without, sorts asynchronously into
-        the current capacity."""
+        the current capacity and posts an asynchronous copy of the count
+        words (read them with poll_counts once the stream got that far)."""
         if not sync:
             B.sx_sort(self.c_proj, self.params.n, self.c_cam, self.c_par, self.capacity,
                       self.keys, self.vals, self.ranges, self.ws, sync_counts=False)
+            self.post_counts()
             return None
         try:
             self.counts = B.sx_sort(self.c_proj, self.params.n, self.c_cam, self.c_par,
@@ -193,6 +199,28 @@ class CellView:
                                     self.capacity, self.keys, self.vals, self.ranges, self.ws,
                                     sync_counts=True)
         return self.counts
+
+    def post_counts(self):
+        """Enqueue a copy of the last sort's count words into pinned host
+        memory on the current stream."""
+        if self._h_counts is None:
+            self._h_counts = torch.zeros((4,), dtype=torch.int64, pin_memory=True)
+            self._counts_ev = torch.cuda.Event()
+        self._h_counts.copy_(self.ws[:32].view(torch.int64), non_blocking=True)
+        self._counts_ev.record()
+
+    def poll_counts(self):
+        """(visible, instances, overflow) of the last asynchronous sort; waits
+        for its count copy.  A sort whose bounded look-back wait ran out left
+        an unsorted list: that raises."""
+        if self._counts_ev is None:
+            raise RuntimeError("no asynchronous sort posted its counts")
+        self._counts_ev.synchronize()
+        vis, inst, over, err = (int(x) for x in self._h_counts.tolist())
+        if err:
+            raise RuntimeError("sx_sort: a bounded wait of the depth passes ran out; "
+                               "the instance list of this view is not sorted")
+        return vis, inst, over
 
     def render(self, mask=None, want_depth=False, want_nblend=True):
         self.mask = mask
@@ -300,6 +328,9 @@ class Frame:
         self.c_par = B.params(settings, sh_deg, flags)
         self.out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=device)
         self.masks = None
+        # the masks a forward rendered with (the composition may clear bits
+        # of self.masks; the backward of that forward needs the old ones)
+        self._masks_fwd = None
         self.omega = None   # geometric maps (re-evaluation, cross-boundary filter)
         self.budget = None  # [K, H*W] stale consumption of pruned pairs
         if cross_filter:
@@ -351,7 +382,7 @@ class Frame:
         after init_masks(reeval=True), re-evaluates the view's state."""
         if update_masks and self.budget is not None and not use_masks:
             raise ValueError("re-evaluation needs the renders restricted to the masks")
-        self._render_cells(use_masks, sync)
+        self._render_cells(use_masks, sync, update_masks)
         parts = [v.partial for v in self.views]
         if update_masks and self.budget is not None:
             B.sx_composite_reeval(parts, self.boxes, self.c_cam, self.c_par, self.out,
@@ -359,21 +390,71 @@ class Frame:
         else:
             B.sx_composite(parts, self.boxes, self.c_cam, self.c_par, self.out,
                            self.masks if update_masks else None)
+        if sync:
+            self._raise_on_overflow(self.check_counts())
         return self.out
 
-    def _render_cells(self, use_masks, sync):
+    def check_counts(self):
+        """Reads every cell's posted sort counts (waiting for them) and
+        returns the indices of the cells whose instances overflowed their
+        capacity; raises if a sort's bounded wait ran out."""
+        bad = []
+        for k, v in enumerate(self.views):
+            vis, inst, over = v.poll_counts()
+            v.counts = (vis, inst)
+            if over or inst > v.capacity:
+                bad.append(k)
+        return bad
+
+    def _raise_on_overflow(self, bad):
+        if bad:
+            raise RuntimeError(f"cells {bad}: instances overflow the sort capacity")
+
+    def forward_checked(self, use_masks=False, update_masks=False, headroom=1.25):
+        """Asynchronous forward followed by one host synchronisation: the
+        cells' count words are read back together, and cells whose
+        instances overflowed are regrown (with `headroom`) and the view is
+        rendered again, starting from the same masks and budgets."""
+        saved = None
+        if update_masks and self.masks is not None:
+            saved = (self.masks.clone(), None if self.budget is None else self.budget.clone())
+        for attempt in range(2):
+            out = self.forward(use_masks, update_masks, sync=False)
+            bad = self.check_counts()
+            if not bad:
+                return out
+            for k in bad:
+                v = self.views[k]
+                v._alloc_sort(int(v.counts[1] * headroom) + 1024)
+            if saved is not None:
+                self.masks.copy_(saved[0])
+                if saved[1] is not None:
+                    self.budget.copy_(saved[1])
+        self._raise_on_overflow(bad)
+
+    def _render_cells(self, use_masks, sync, update_masks=False):
         side = self.side if (self.side is not None and not sync) else None
         main = torch.cuda.current_stream()
+        masks = self.masks if use_masks else None
+        if masks is not None and update_masks:
+            # render from a copy: the composition is about to clear bits of
+            # self.masks, and this forward's backward needs the bits it used
+            if self._masks_fwd is None or self._masks_fwd.shape != masks.shape:
+                self._masks_fwd = torch.empty_like(masks)
+            self._masks_fwd.copy_(masks)
+            masks = self._masks_fwd
         if side is not None:
             ready = torch.cuda.Event()
             ready.record(main)
             for s in side:
                 s.wait_event(ready)
         for k, v in enumerate(self.views):
-            m = self.masks[k] if (use_masks and self.masks is not None) else None
+            m = masks[k] if masks is not None else None
             with torch.cuda.stream(side[k % len(side)] if side is not None else main):
                 v.preprocess()
                 v.sort(sync=sync)
+                if sync:
+                    v.post_counts()
                 v.render(m)
         if side is not None:
             for s in side:
@@ -390,13 +471,15 @@ class Frame:
         sx_l1_loss and backward; re-evaluating frames use those instead."""
         if self.budget is not None:
             raise ValueError("re-evaluating frames compose with forward()")
-        self._render_cells(use_masks, sync)
+        self._render_cells(use_masks, sync, update_masks)
         for v in self.views:
             v.ensure_backward_buffers()
         B.sx_composite_l1([v.partial for v in self.views], self.boxes, self.c_cam, self.c_par,
                           target, self.out, self.masks if update_masks else None, loss_sum,
                           [v.dpartial for v in self.views])
         self._cells_backward(grads, accumulate)
+        if sync:
+            self._raise_on_overflow(self.check_counts())
         return self.out
 
     def backward(self, dout, grads: Sequence[GaussianParams], accumulate=False):

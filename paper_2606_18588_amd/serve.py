@@ -237,7 +237,10 @@ class Server:
     def _finish(self, b: _Batch, now: float, queue: collections.deque, done: List[Done]):
         requeue = []
         for j, (it, cap) in enumerate(zip(b.items, b.caps)):
-            vis, inst, over = (int(x) for x in b.counts[j, :3])
+            vis, inst, over, err = (int(x) for x in b.counts[j, :4])
+            if err:
+                raise RuntimeError(f"request {it.rid}: a bounded wait of the sort's depth "
+                                   "passes ran out; its instance list is not sorted")
             if over or inst > cap:
                 if inst > _MAX_CAPACITY:
                     raise RuntimeError(f"request {it.rid}: {inst} instances exceed the sort's "
