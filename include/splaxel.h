@@ -188,8 +188,11 @@ sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
                   const sx_params* p, int64_t capacity, uint64_t* keys,
                   uint32_t* vals, uint32_t* tile_ranges, void* ws,
                   size_t ws_bytes, uint64_t* h_counts, sx_stream stream);
-/* Reads {visible, instances, overflow} from a sort workspace (device ->
- * HOST uint64[3]); synchronises the stream. */
+/* Reads the four count words of a sort workspace into HOST uint64[4]:
+ * {visible, instances, overflow, error}; synchronises the stream.
+ * overflow != 0: the instances exceeded the capacity (only the first
+ * `capacity` were sorted); error != 0: a bounded wait of the depth passes
+ * ran out and the list is not sorted (the caller must not use it). */
 sx_status sx_sort_counts(const void* ws, int64_t n, uint64_t* h_out,
                          sx_stream stream);
 
@@ -443,10 +446,11 @@ sx_status sx_fill_u32(uint32_t* ptr, int64_t n, uint32_t value,
  * GPUs and groups views whose participant cells do not overlap (Sec. 4.4,
  * view bucketing); on one GPU the views of a batch share the device, so the
  * batched calls below run the per-view stages of up to SX_MAX_VIEWS views of
- * ONE cell in one launch each, pulling (view, tile) work items from a
- * shared queue ordered by cost.  Results are bit-identical to the per-view
- * calls (every work item owns its pixels; the per-Gaussian gradient rows of
- * each view are reduced separately). */
+ * ONE cell in one launch each: workgroup b takes the b-th (view, tile) work
+ * item, the views' tile grids laid end to end, each in raster order.
+ * Results are bit-identical to the per-view calls (every work item owns its
+ * pixels; the per-Gaussian gradient rows of each view are reduced
+ * separately). */
 #define SX_MAX_VIEWS 16
 
 /* One view of a batched call.  Every pointer refers to that view's buffers
