@@ -12,7 +12,8 @@
  * Conventions for every call:
  *   - Array arguments are DEVICE pointers owned by the caller unless a
  *     comment says "host".  The library never allocates device memory; the
- *     caller provides workspaces sized by the *_workspace_size queries.
+ *     caller provides workspaces sized by the *_workspace_size queries (one
+ *     exception: the static scratch array of sx_render_backward_noalloc).
  *   - All work is enqueued on `stream` (a hipStream_t; NULL = the default
  *     stream) and is asynchronous unless a comment says the call
  *     synchronises.
@@ -419,6 +420,27 @@ sx_status sx_render_backward_stages(const sx_projected* proj, const uint32_t* va
                                     const uint32_t* last, const float* dpartial,
                                     const float* ddepth, float* g2d, int32_t stages,
                                     sx_stream stream);
+/* sx_render_backward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments and results (the same kernels) without
+ * bwd_ws.  Its scratch, the per-tile visited counts and one 40-byte
+ * gradient row per instance (sx_backward_workspace_size(capacity, tiles)
+ * bytes), is a static device array of SX_NOALLOC_SCRATCH_BYTES that every
+ * device the library runs on holds until the process ends (64 MiB: about
+ * 1.6M instances at 1080p with 16x16 tiles).  A capacity whose scratch does
+ * not fit returns SX_EINVAL before anything is enqueued.  Calls no
+ * allocator.  All calls on one device share the array: calls that overlap
+ * in time on one device (on different streams, or from different threads)
+ * race and must be ordered by the caller.  No part of the array needs
+ * clearing between calls (each call writes every row and count it reads). */
+#define SX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+sx_status sx_render_backward_noalloc(const sx_projected* proj, const uint32_t* vals,
+                                     const uint32_t* tile_ranges, const void* sort_ws,
+                                     int64_t n, int64_t capacity, const sx_camera* cam,
+                                     const sx_params* p, const uint32_t* mask,
+                                     const float* partial, const uint32_t* last,
+                                     const float* dpartial, const float* ddepth, float* g2d,
+                                     sx_stream stream);
 /* sort_ws/capacity: the sort of this view (its list of visible Gaussians
  * drives the launch). */
 sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,

@@ -91,7 +91,9 @@ EXPORTS = (
     "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
     "sx_render_backward_stages", "sx_visibility", "sx_kd_partition",
     "sx_composite_reeval", "sx_cross_filter", "sx_composite_l1",
+    "sx_render_backward_noalloc",
 )
+SX_NOALLOC_SCRATCH_BYTES = 64 << 20  # the static scratch of sx_render_backward_noalloc
 
 _lib = None
 
@@ -340,6 +342,18 @@ def sx_render_backward(proj: SxProjected, vals, ranges, sort_ws, n: int,
         c_i64(capacity), ptr(bwd_ws), ctypes.byref(cam), ctypes.byref(p),
         ptr(mask), ptr(partial), ptr(last), ptr(dpartial), ptr(ddepth),
         ptr(g2d), stream_handle(stream)))
+
+
+def sx_render_backward_noalloc(proj: SxProjected, vals, ranges, sort_ws, n: int,
+                               capacity: int, cam: SxCamera, p: SxParams, mask, partial,
+                               last, dpartial, ddepth, g2d, stream=None) -> None:
+    """sx_render_backward with its scratch in the library's static device
+    array (for callers that cannot allocate; calls on one device must not
+    overlap)."""
+    _check("sx_render_backward_noalloc", lib().sx_render_backward_noalloc(
+        ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(sort_ws), c_i64(n),
+        c_i64(capacity), ctypes.byref(cam), ctypes.byref(p), ptr(mask), ptr(partial),
+        ptr(last), ptr(dpartial), ptr(ddepth), ptr(g2d), stream_handle(stream)))
 
 
 def sx_render_backward_stages(proj: SxProjected, vals, ranges, sort_ws, n: int,

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "sx_internal.h"
@@ -347,6 +348,38 @@ sx_status sx_render_backward_stages(const sx_projected* proj, const uint32_t* va
              "sx_render_backward");
 }
 
+// Scratch of sx_render_backward_noalloc: the per-tile visited counts and
+// the per-instance gradient rows of the render backward, in one static
+// device array instead of a caller workspace.  Each device holds its own
+// copy (allocated when the code object is loaded, held until the process
+// ends); host code only ever uses the per-device address that
+// hipGetSymbolAddress returns for it, never the array's name.
+static __device__ __align__(256) unsigned char scratch[SX_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+sx_status scratch_address(void** out) {
+  int dev_id = 0;
+  hipError_t e = hipGetDevice(&dev_id);
+  if (e != hipSuccess) return dev(e, "hipGetDevice");
+  if (dev_id < 0 || dev_id >= kMaxDevices) return fail(SX_EUNSUPPORTED, "device %d", dev_id);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev_id]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return dev(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SX_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev_id] = p;
+  }
+  *out = g_scratch_ptr[dev_id];
+  return SX_OK;
+}
+}  // namespace
+
 sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
                              const uint32_t* tile_ranges, const void* sort_ws,
                              int64_t n, int64_t capacity, void* bwd_ws,
@@ -356,6 +389,30 @@ sx_status sx_render_backward(const sx_projected* proj, const uint32_t* vals,
                              const float* ddepth, float* g2d, sx_stream stream) {
   return sx_render_backward_stages(proj, vals, tile_ranges, sort_ws, n, capacity, bwd_ws, cam, p,
                                    mask, partial, last, dpartial, ddepth, g2d, SX_RB_ALL, stream);
+}
+
+sx_status sx_render_backward_noalloc(const sx_projected* proj, const uint32_t* vals,
+                                     const uint32_t* tile_ranges, const void* sort_ws,
+                                     int64_t n, int64_t capacity, const sx_camera* cam,
+                                     const sx_params* p, const uint32_t* mask,
+                                     const float* partial, const uint32_t* last,
+                                     const float* dpartial, const float* ddepth, float* g2d,
+                                     sx_stream stream) {
+  SX_TRY(check_cam(cam));
+  SX_TRY(check_params(p));
+  if (capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "bad capacity");
+  const sx::KParams kp = sx::make_kparams(*p, *cam);
+  const size_t need = sx::bwd_layout(capacity, (int64_t)kp.tiles_x * kp.tiles_y).total;
+  if (need > (size_t)SX_NOALLOC_SCRATCH_BYTES)
+    return fail(SX_EINVAL,
+                "sx_render_backward_noalloc: capacity %lld on a %dx%d tile grid needs %zu scratch "
+                "bytes, more than the static %llu",
+                (long long)capacity, kp.tiles_x, kp.tiles_y, need,
+                (unsigned long long)SX_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  SX_TRY(scratch_address(&ws));
+  return sx_render_backward_stages(proj, vals, tile_ranges, sort_ws, n, capacity, ws, cam, p, mask,
+                                   partial, last, dpartial, ddepth, g2d, SX_RB_ALL, stream);
 }
 
 sx_status sx_preprocess_backward(const sx_gaussians* g, const sx_camera* cam,

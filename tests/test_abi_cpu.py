@@ -208,3 +208,19 @@ def test_kd_partition_matches_oracle(L):
     bad[5, 1] = np.nan
     with pytest.raises(B.SplaxelError):
         B.sx_kd_partition(bad, 4)
+
+
+def test_noalloc_backward_rejects_capacity_beyond_its_scratch(L):
+    """The allocation-free render backward refuses, on the host, a capacity
+    whose gradient rows do not fit its static scratch array."""
+    from paper_2606_18588_amd import binding as B
+    import synth
+    cam = B.camera(synth.tiny_camera(128, 128))
+    par = B.params(synth.RenderSettings(), 0, 0)
+    rows = B.SX_NOALLOC_SCRATCH_BYTES // 40
+    code = L.sx_render_backward_noalloc(None, None, None, None, ctypes.c_int64(10),
+                                        ctypes.c_int64(rows + 1), ctypes.byref(cam),
+                                        ctypes.byref(par), None, None, None, None, None, None,
+                                        None)
+    assert code == B.SX_EINVAL
+    assert b"scratch" in L.sx_last_error_string()
