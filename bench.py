@@ -17,7 +17,12 @@ blended in the forward pass (counted once by the renderer's per-pixel
 counter; the step is deterministic, so B is the same every step).
 
 Prints ONE JSON line.  Per-stage times, the roofline of the dominant kernel
-and the CPU oracle baseline are included in it.
+and the CPU oracle baseline are included in it, and (unless --no-extras)
+the metric's two other parts on their own workloads: views/s of the K = 8
+cells training step on the 8M-Gaussian scene at 1920x1080
+(views_per_s_8M_1080p, with the roofline of its reverse walk) and serving
+p50/p99 latency and frames/s on the resident 30M-Gaussian scene against
+plain per-view service (serve_p50_ms, serve_p99_ms, serve_30M).
 """
 from __future__ import annotations
 
@@ -161,6 +166,13 @@ def main():
                     help="cells: carry the saturation state with speculative re-evaluation")
     ap.add_argument("--partition", choices=("grid", "kd"), default="grid",
                     help="cells: the 4 x 2 ground grid of the configuration, or KD-tree cells")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="plain: skip the K = 8 cells step and the serving trace that the "
+                         "default line also reports")
+    ap.add_argument("--cells-steps", type=int, default=10,
+                    help="plain: timed K = 8 cells steps (8 views each) for the extra fields")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="plain: measured requests of the serving trace for the extra fields")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -232,7 +244,7 @@ def main():
         "config": {"workload": "one GPU's share: 2M Gaussians SH3 on a 1 km^2 ground plane, "
                                "1920x1080 aerial view, K=1, L1 fwd+bwd",
                    "gaussians": scene.n, "width": cam.width, "height": cam.height,
-                   "tile": args.tile, "cells": 1},
+                   "tile": args.tile, "cells": 1, "layout": "Morton order of the means"},
         "views_per_s": 1e3 / ms, "blends_per_step": blends, "visible": n_vis,
         "instances": n_inst, "stage_ms": stages, "wall_s": wall,
         "roofline": roof,
@@ -241,6 +253,32 @@ def main():
         t0 = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(scene, cam, settings)
         log(f"bench: cpu baseline {time.perf_counter() - t0:.1f}s")
+    if not args.no_extras:
+        # the metric's other two parts, on their own workloads
+        del st
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        cells, n8 = cells_measure(args, ((1920, 1080),), args.cells_steps, 2)
+        c = cells["1920x1080"]
+        line["views_per_s_8M_1080p"] = c["views_per_s"]
+        line["cells_8M_1080p"] = dict(c, workload=cells_workload(args), gaussians=n8,
+                                      layout="each cell in Morton order of its means")
+        log(f"bench: K=8 cells {c['views_per_s']:.1f} views/s at 1080p "
+            f"({time.perf_counter() - t0:.1f}s)")
+        t0 = time.perf_counter()
+        srv, n30 = serve_measure(args.serve_requests, args.serve_requests // 4)
+        b, p = srv["batched"], srv["plain"]
+        line["serve_p50_ms"] = b["open_loop"]["p50_ms"]
+        line["serve_p99_ms"] = b["open_loop"]["p99_ms"]
+        line["serve_frames_per_s"] = b["open_loop"]["frames_per_s"]
+        line["serve_30M"] = {
+            "workload": SERVE_WORKLOAD, "gaussians": n30, "requests": args.serve_requests,
+            "warmup_requests": args.serve_requests // 4,
+            "layout": "Morton order of the means", "batched": b, "plain": p,
+            "closed_loop_speedup_vs_plain": b["closed_loop_frames_per_s"] /
+            p["closed_loop_frames_per_s"]}
+        log(f"bench: serve p50 {line['serve_p50_ms']:.2f} ms p99 {line['serve_p99_ms']:.2f} ms "
+            f"({time.perf_counter() - t0:.1f}s)")
     print(json.dumps(line), flush=True)
 
 
@@ -307,6 +345,35 @@ def bench_batched(args):
 
 
 def bench_cells(args):
+    """The K = 8 composition workload (cells_measure) at 1920x1080 (the
+    metric's resolution) and 1600x1200 (the configuration's), printed as its
+    own line."""
+    out, n_gauss = cells_measure(args, ((1920, 1080), (1600, 1200)), args.steps, args.warmup)
+    m = out["1920x1080"]
+    line = {
+        "metric": "views/s @1080p 8M G", "value": m["views_per_s"], "unit": "views/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cells_workload(args), "gaussians": n_gauss, "cells": 8,
+                   "views": 8, "layout": "each cell in Morton order of its means"},
+        "resolutions": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cells_workload(args):
+    return ("8M Gaussians SH3 on a 1 km^2 ground plane in K=8 cells "
+            f"({'KD-tree' if args.partition == 'kd' else '4x2 grid'}), "
+            "8 aerial views, fwd + L1 + bwd per view with "
+            "geometric visibility and temporal saturation masks"
+            + (" re-evaluated every render" if args.reeval else "")
+            + (", cross-boundary filtering" if args.cross_filter else "")
+            + f", cells' chains on {args.streams} stream(s)"
+            + ", one Adam update per step")
+
+
+def cells_measure(args, sizes, steps, warmup, walk_roofline=True):
     """The K = 8 composition workload: 8M Gaussians split by centre into a
     4 x 2 grid of cells on the ground plane, 8 views from (10, 20, 150) m.
     One training step = for every view, each cell's preprocess, sort and
@@ -314,8 +381,9 @@ def bench_cells(args):
     geometrically visible and, from the view's previous step, not behind a
     saturated prefix), composition (Eq. 5, updating the masks), L1, the
     composition backward and every cell's backward; then one Adam update of
-    every cell.  Views/s at 1920x1080 (the metric's resolution) and at
-    1600x1200 (the configuration's)."""
+    every cell.  Returns ({"WxH": results}, Gaussians).  With walk_roofline,
+    one more step runs with every cell's chain on one stream and timing
+    events around each reverse walk, for the roofline of that kernel."""
     import torch
     import synth
     from paper_2606_18588_amd import binding as B
@@ -339,7 +407,8 @@ def bench_cells(args):
     log(f"bench: 8M scene in {len(params)} cells ready in {time.perf_counter() - t0:.1f}s")
     st = synth.RenderSettings()
     out = {}
-    for (w, h) in ((1920, 1080), (1600, 1200)):
+    n_gauss = int(sum(p.n for p in params))
+    for (w, h) in sizes:
         cams = synth.g8_cameras(w, h)
         targets = [torch.as_tensor(synth.random_image(500 + k, w, h)).cuda()
                    for k in range(len(cams))]
@@ -388,19 +457,39 @@ def bench_cells(args):
                     k += 1
             return blends
 
-        for _ in range(max(args.warmup, 2)):
+        for _ in range(max(warmup, 2)):
             step()
         blends = step(count=True)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(args.steps):
+        for _ in range(steps):
             step()
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
+        ms = e0.elapsed_time(e1) / steps
         out[f"{w}x{h}"] = {"ms_per_step": ms, "views_per_s": len(cams) / (ms / 1e3),
                            "blends_per_step": blends, "blends_per_s": blends / (ms / 1e3)}
+        if walk_roofline and not args.reeval:
+            # every cell's chain on one stream, timing events around each
+            # reverse walk (the kernel the K = 8 step spends most time in)
+            walks = []
+            for f in frames:
+                f.walk_events, f._side_saved, f.side = walks, f.side, None
+            blends_w = step(count=True)
+            torch.cuda.synchronize()
+            for f in frames:
+                f.walk_events, f.side = None, f._side_saved
+            walk_ms = sum(a.elapsed_time(b) for a, b in walks)
+            ops = 53.0 * blends_w
+            ach = ops / (walk_ms / 1e3) / 1e12
+            out[f"{w}x{h}"]["roofline"] = {
+                "bound": "alu", "kernel": "k_render_bwd<16, 16, false, false>",
+                "achieved": ach, "peak": ALU_PEAK_TOPS, "unit": "T lane-op/s",
+                "frac": ach / ALU_PEAK_TOPS, "traffic": None, "algorithmic_ops": ops,
+                "launches": len(walks), "walk_ms_per_step": walk_ms,
+                "timing": "events around each of the step's reverse walks, the cells' chains "
+                          "on one stream"}
         if args.reeval:
             out[f"{w}x{h}"].update(reactivated=flips[0], pruned_before=flips[1],
                                    flip_rate=flips[0] / max(flips[1], 1))
@@ -409,31 +498,42 @@ def bench_cells(args):
             + (f", re-activated {flips[0]} of {flips[1]} pruned pairs" if args.reeval else ""))
         del frames
         torch.cuda.empty_cache()
-    m = out["1920x1080"]
+    del params, grads, moments
+    torch.cuda.empty_cache()
+    return out, n_gauss
+
+
+def bench_serve(args):
+    """The serving workload (serve_measure), printed as its own line."""
+    res, n_gauss = serve_measure(args.requests, 200)
+    b, p = res["batched"], res["plain"]
     line = {
-        "metric": "views/s @1080p 8M G", "value": m["views_per_s"], "unit": "views/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "metric": "serve p50 latency ms", "value": b["open_loop"]["p50_ms"], "unit": "ms",
+        "n_gpus": 1, "steps": args.requests, "warmup": 200,
+        "ms_per_step": b["open_loop"]["mean_ms"], "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "8M Gaussians SH3 on a 1 km^2 ground plane in K=8 cells "
-                               f"({'KD-tree' if args.partition == 'kd' else '4x2 grid'}), "
-                               "8 aerial views, fwd + L1 + bwd per view with "
-                               "geometric visibility and temporal saturation masks"
-                               + (" re-evaluated every render" if args.reeval else "")
-                               + (", cross-boundary filtering" if args.cross_filter else "")
-                               + f", cells' chains on {args.streams} stream(s)"
-                               + ", one Adam update per step",
-                   "gaussians": int(sum(p.n for p in params)), "cells": len(params),
-                   "views": 8},
-        "resolutions": out,
+        "config": {"workload": SERVE_WORKLOAD, "gaussians": n_gauss, "requests": args.requests,
+                   "layout": "Morton order of the means"},
+        "p99_ms": b["open_loop"]["p99_ms"], "frames_per_s": b["open_loop"]["frames_per_s"],
+        "closed_loop_frames_per_s": b["closed_loop_frames_per_s"],
+        "plain": p,
+        "speedup_closed_loop_vs_plain": b["closed_loop_frames_per_s"] /
+        p["closed_loop_frames_per_s"],
+        "batched": b,
     }
     print(json.dumps(line), flush=True)
 
 
-def bench_serve(args):
+SERVE_WORKLOAD = ("resident 30M Gaussians SH3 on a 2 km x 2 km ground plane, Poisson 200 req/s, "
+                  "resolutions uniform over 640x360, 1280x720, 1920x1080, 3840x2160, forward "
+                  "render + composition")
+
+
+def serve_measure(requests, warm_n):
     """Poisson request trace (200 req/s, resolutions 640x360..3840x2160) on a
     resident 30M-Gaussian scene: continuous batching against plain per-view
-    service, open loop (latency) and closed loop (max frames/s)."""
+    service, open loop (latency) and closed loop (max frames/s).  Returns
+    ({"batched": ..., "plain": ...}, Gaussians)."""
     import torch
     import synth
     from paper_2606_18588_amd.pipeline import GaussianParams
@@ -444,8 +544,7 @@ def bench_serve(args):
     scene = scene.subset(spatial_order(scene.means))  # the resident layout
     params = GaussianParams.from_scene(scene)
     del scene
-    warm_n = 200
-    trace = synth.serve_trace(warm_n + args.requests)
+    trace = synth.serve_trace(warm_n + requests)
     log(f"bench: 30M scene + {len(trace)} requests ready in {time.perf_counter() - t0:.1f}s")
     st = synth.RenderSettings()
 
@@ -471,24 +570,10 @@ def bench_serve(args):
                      "batches": srv.n_batches, "overflows": srv.overflows}
         del srv
         torch.cuda.empty_cache()
-    b, p = res["batched"], res["plain"]
-    line = {
-        "metric": "serve p50 latency ms", "value": b["open_loop"]["p50_ms"], "unit": "ms",
-        "n_gpus": 1, "steps": args.requests, "warmup": warm_n,
-        "ms_per_step": b["open_loop"]["mean_ms"], "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "resident 30M Gaussians SH3 on a 2 km x 2 km ground plane, "
-                               "Poisson 200 req/s, resolutions uniform over 640x360, "
-                               "1280x720, 1920x1080, 3840x2160, forward render + composition",
-                   "gaussians": params.n, "requests": args.requests},
-        "p99_ms": b["open_loop"]["p99_ms"], "frames_per_s": b["open_loop"]["frames_per_s"],
-        "closed_loop_frames_per_s": b["closed_loop_frames_per_s"],
-        "plain": p,
-        "speedup_closed_loop_vs_plain": b["closed_loop_frames_per_s"] /
-        p["closed_loop_frames_per_s"],
-        "batched": b,
-    }
-    print(json.dumps(line), flush=True)
+    n_gauss = params.n
+    del params
+    torch.cuda.empty_cache()
+    return res, n_gauss
 
 
 # Single-kernel stages: (entry point's only kernel, its source file).
@@ -525,8 +610,10 @@ def roofline(st, stage_ms):
     """Roofline entry for the largest kernel that has an entry point of its
     own (so that events around the call time exactly that kernel).  The
     per-unit algorithmic work: HBM-bound stages count the bytes the method
-    must move, the rasterizers count FP32 lane operations (15 per pair
-    evaluation and 8 per blend forward, 53 per blend in the reverse walk)."""
+    must move, the rasterizers count FP32 lane-operation slots (15 per pair
+    evaluation and 8 per blend forward, 53 per blend in the reverse walk;
+    unit "T lane-op/s").  working_set_bytes is what the kernel touches: below
+    the 256 MB Infinity Cache a bandwidth figure may be served from it."""
     n = st.params.n
     n_vis, n_inst = st.counts
     sh_bytes = st.params.sh.shape[1] * 3 * 4
@@ -542,9 +629,20 @@ def roofline(st, stage_ms):
         else:
             ops = 53.0 * st.blends
         ach = ops / (ms / 1e3) / 1e12
+        hw = st.cam.width * st.cam.height
+        tiles = st.view.tiles
+        if stage == "render":
+            # records (48 B per visible Gaussian), values, ranges; partial,
+            # last and blend count written
+            ws = 48 * n_vis + 4 * n_inst + 8 * tiles + 24 * hw
+        else:
+            # records, values, ranges, per-tile counts; partial, last and
+            # dpartial read; one 40-byte gradient row per instance written
+            ws = 48 * n_vis + 44 * n_inst + 12 * tiles + 36 * hw
         return {"bound": "alu", "kernel": kernel, "achieved": ach, "peak": ALU_PEAK_TOPS,
-                "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS, "traffic": pmc_traffic(kernel, src),
-                "algorithmic_ops": ops}
+                "unit": "T lane-op/s", "frac": ach / ALU_PEAK_TOPS,
+                "traffic": pmc_traffic(kernel, src), "algorithmic_ops": ops,
+                "working_set_bytes": ws}
     if stage == "preprocess":
         # every Gaussian: mean read (12 B), tile count written (4 B); the
         # visible ones also read logit, scales, rotation and SH and write the
@@ -560,7 +658,7 @@ def roofline(st, stage_ms):
     tr = pmc_traffic(kernel, src)
     return {"bound": "hbm", "kernel": kernel, "achieved": ach, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": tr,
-            "algorithmic_bytes": byts}
+            "algorithmic_bytes": byts, "working_set_bytes": byts}
 
 
 if __name__ == "__main__":

@@ -241,11 +241,27 @@ class CellView:
             self.bwd_ws = torch.empty((self.backward_bytes(self.capacity),), dtype=torch.uint8,
                                       device=self.device)
 
-    def render_backward(self, dpartial, ddepth=None):
+    def render_backward(self, dpartial, ddepth=None, walk_events=None):
+        """With walk_events (a list), the three stages are called one by one
+        and a (start, end) pair of timing events around the reverse walk is
+        appended to it."""
         self.ensure_backward_buffers()
-        B.sx_render_backward(self.c_proj, self.vals, self.ranges, self.ws, self.params.n,
-                             self.capacity, self.bwd_ws, self.c_cam, self.c_par, self.mask,
-                             self.partial, self.last, dpartial, ddepth, self.g2d)
+        if walk_events is None:
+            B.sx_render_backward(self.c_proj, self.vals, self.ranges, self.ws, self.params.n,
+                                 self.capacity, self.bwd_ws, self.c_cam, self.c_par, self.mask,
+                                 self.partial, self.last, dpartial, ddepth, self.g2d)
+            return self.g2d
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        for stage in (B.SX_RB_PREPARE, B.SX_RB_WALK, B.SX_RB_REDUCE):
+            if stage == B.SX_RB_WALK:
+                ev[0].record()
+            B.sx_render_backward_stages(self.c_proj, self.vals, self.ranges, self.ws,
+                                        self.params.n, self.capacity, self.bwd_ws, self.c_cam,
+                                        self.c_par, self.mask, self.partial, self.last,
+                                        dpartial, ddepth, self.g2d, stage)
+            if stage == B.SX_RB_WALK:
+                ev[1].record()
+        walk_events.append(ev)
         return self.g2d
 
     def preprocess_backward(self, grads: GaussianParams, accumulate=False):
@@ -333,6 +349,8 @@ class Frame:
         self._masks_fwd = None
         self.omega = None   # geometric maps (re-evaluation, cross-boundary filter)
         self.budget = None  # [K, H*W] stale consumption of pruned pairs
+        # a list to time every cell's reverse walk in (see CellView.render_backward)
+        self.walk_events = None
         if cross_filter:
             self._set_omega(self._visibility())
 
@@ -501,7 +519,7 @@ class Frame:
         """Every cell's render and projection backward from its dpartial."""
         if self.side is None:
             for v, g in zip(self.views, grads):
-                v.render_backward(v.dpartial)
+                v.render_backward(v.dpartial, walk_events=self.walk_events)
                 v.preprocess_backward(g, accumulate)
             return
         main = torch.cuda.current_stream()
