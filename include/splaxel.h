@@ -159,9 +159,9 @@ sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
 /* ------------------------------------------------------------- a2-a4 --
  * Depth sort (paper, background: sorting step): the result of a stable
  * sort of the 64-bit keys  key = tile_id << 32 | bits(float32 depth)  with
- * ties by Gaussian index.  The depth digits are radix sorted on the visible
- * Gaussians before duplication; the depth-ordered list is then split by
- * tile through a hierarchy of 4 x 4 bins, each level keeping the order.
+ * ties by Gaussian index.  The visible Gaussians, in index order, are split
+ * by tile through a hierarchy of 4 x 4 bins, each level keeping the order;
+ * then every tile's list is sorted by (depth bits, index) in LDS.
  * Outputs: vals[i] = Gaussian index of the i-th instance, optionally
  * keys[i], and tile_ranges[t] = [start, end) per tile (tile_id = ty *
  * tiles_x + tx; an empty tile has start == end), tiles * 2 uint32.
@@ -176,12 +176,14 @@ sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
  *              instances and raises a flag read by sx_sort_counts().
  * The workspace begins with uint64 {visible, instances, overflow, error}
  * (32 bytes, valid once the call's work has completed), so a caller may
- * also copy them to pinned host memory asynchronously.
+ * also copy them to pinned host memory asynchronously (error is reserved
+ * for a failed bounded wait; the current sort has none and leaves it 0).
  * keys may be NULL. */
 /* Bytes of the sort workspace for n Gaussians, `capacity` instances and a
- * tiles_x x tiles_y grid: about 24 bytes per Gaussian plus 4 bytes per
- * instance (8 once the grid is wider or taller than 16 tiles) for the lists
- * of the tile binning. */
+ * tiles_x x tiles_y grid: about 8 bytes per Gaussian plus 16 bytes per
+ * instance (the per-tile lists and their merge buffer), and 4 more bytes per
+ * instance (8 once the grid is wider or taller than 16 tiles) for the inner
+ * lists of the tile binning. */
 sx_status sx_sort_workspace_size(int64_t n, int64_t capacity,
                                  int32_t tiles_x, int32_t tiles_y,
                                  size_t* bytes);

@@ -12,10 +12,6 @@ namespace sx {
 constexpr int kRecFloats = 12;   // per-Gaussian render record (48 B)
 constexpr int kG2dFloats = 12;   // per-Gaussian screen-space gradient row
 constexpr int kPreBlock = 256;   // Gaussians per preprocess block
-constexpr int kSortBlock = 256;  // threads per radix-sort block
-constexpr int kSortItems = 16;   // keys per thread
-constexpr int kSortTile = kSortBlock * kSortItems;  // keys per partition
-constexpr int kRadixBins = 256;
 constexpr int kMaxCells = 16;
 constexpr int kMaxViews = 16;  // views per batched launch
 constexpr int kBinSeg = 1024;   // entries per segment of a bin list (tile binning)
@@ -49,21 +45,21 @@ struct SortLayout {
   size_t inst_off;     // uint32[nb]   exclusive instance offsets per block
   size_t ioff;         // uint32[n]    first instance of each visible Gaussian
   size_t scan_part;    // uint64[tiles][2] per-tile (visible, instance) sums
-  size_t dkey[2];      // uint32[n]    depth keys (ping-pong)
-  size_t didx[2];      // uint32[n]    Gaussian indices (ping-pong)
   size_t vidx;         // uint32[n]    visible Gaussians in index order
-  size_t zero_begin;   // start of the region cleared on every call
-  size_t dhist;        // uint32[4][256] depth digit histograms
-  size_t counters;     // uint32[16] partition counters
-  size_t dstatus;      // uint32[4][dparts][256]
-  size_t zero_end;
+  size_t vrect;        // ushort4[n]   their tile rectangles (same order)
+  size_t vkey;         // uint32[n]    their depth bits (same order)
   size_t bl_list[2];   // uint32[cap] bin lists of the inner levels (ping-pong)
   size_t bl_bins[2];   // uint2[bins] (start, length) per bin (ping-pong)
   size_t bl_seg[2];    // uint32[bins + 2] first segment per bin (ping-pong)
-  size_t bl_tot;       // uint32[tiles] entries per child bin
+  size_t bl_tot;       // uint32[tiles] entries per child bin (cleared by the
+                       // first kernel of every call)
+  int64_t tot_words;
   size_t bl_cnt;       // uint32[segments][16] entries per (segment, child)
+  size_t pairs[2];     // uint64[cap] per-tile lists of depth bits << 32 | index
+                       // (the last level's output; [1] is the merge buffer of
+                       // tiles longer than one LDS chunk)
   size_t total;
-  int64_t nb, dparts;
+  int64_t nb;
   int bl_levels;       // levels of 4x4 subdivision above the tiles (>= 1)
 };
 SortLayout sort_layout(int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
@@ -84,8 +80,7 @@ BwdLayout bwd_layout(int64_t capacity, int64_t tiles_total);
 // what the backward needs from a cell's sort workspace
 struct SortView {
   const uint64_t* counts;
-  const uint32_t* didx;   // depth-sorted visible Gaussians
-  const uint32_t* vidx;   // the same Gaussians in index order
+  const uint32_t* vidx;   // the visible Gaussians in index order
   const uint32_t* ioff;   // [n] first instance of each visible Gaussian, index order
 };
 SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);

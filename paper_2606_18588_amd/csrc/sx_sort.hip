@@ -4,48 +4,39 @@
 //     key = tile_id << 32 | bits(float32 depth)
 // over instances emitted in Gaussian-index order, i.e. the order
 // (tile, depth bits, Gaussian index).  It is built in two phases:
-//   1. the depth digits are radix sorted on the compacted list of visible
-//      Gaussians before duplication (4 LSD passes over ~N_vis elements, one
-//      "onesweep" kernel each: wave64 ballot ranking, decoupled look-back
-//      with bounded waits, LDS reorder for coalesced writes);
-//   2. the depth-ordered list is split by tile through a hierarchy of bins
-//      (bins of 4^L x 4^L tiles, each bin having 4 x 4 child bins): the
-//      list of a bin is cut into segments, and for every segment each of 16
-//      wavefronts ballot-filters the entries whose tile rectangle meets its
-//      child bin.  A count pass and an exclusive scan give every (segment,
-//      child) its output offset, and a write pass stores the entries in
-//      order, so each child's list stays depth-ordered and every store is a
-//      contiguous run of a wavefront.  The last level's bins are single
-//      tiles; their lists are the instance values and the scan gives the
-//      tile ranges.
-// No step uses atomics on the output; every wait is bounded (a spin limit
-// raises an error flag instead of hanging).
+//   1. the list of visible Gaussians, in index order, is split by tile
+//      through a hierarchy of bins (bins of 4^L x 4^L tiles, each bin having
+//      4 x 4 child bins): the list of a bin is cut into segments, and for
+//      every segment each of 16 wavefronts ballot-filters the entries whose
+//      tile rectangle meets its child bin.  A count pass and an exclusive
+//      scan give every (segment, child) its output offset, and a write pass
+//      stores the entries in order, so each child's list keeps the index
+//      order and every store is a contiguous run of a wavefront.  The last
+//      level's bins are single tiles: their lists hold (depth bits, index)
+//      pairs and the scan gives the tile ranges;
+//   2. every tile's list is sorted by (depth bits, index) by one workgroup
+//      in LDS: a rank count for lists of up to 256 entries, a bitonic
+//      network up to 2048, and sorted 2048-entry chunks merged through LDS
+//      windows beyond that.
+// No step uses atomics on the output, and no step waits on another
+// workgroup.
+#include <algorithm>
+
 #include "sx_internal.h"
 
 namespace sx {
 
 namespace {
 
-constexpr uint32_t kFlagAgg = 1u << 30;
-constexpr uint32_t kFlagIncl = 2u << 30;
-constexpr uint32_t kValMask = (1u << 30) - 1;
-constexpr int kSpinLimit = 1 << 20;
-constexpr int kLookback = 8;  // predecessor statuses read per look-back round trip
 constexpr int kScanItems = 4;  // preprocess blocks per thread in the count scan
 constexpr int kScanTile = 256 * kScanItems;
-
-// Look-back status words: the flag and the count share one 32-bit word, so
-// a reader that sees the flag sees its count, and no other memory is
-// published through the word (the scattered keys are read by the next
-// launch).  Device-scope atomic loads and stores without ordering suffice,
-// and they avoid the cache write-back and invalidation an acquire or
-// release at device scope costs on a multi-XCD GPU.
-__device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+constexpr int kRootFan = 4;      // child bins per axis of the root's split
+constexpr int kTsThreads = 256;  // threads of the per-tile sort
+constexpr int kTsRank = 256;     // longest list sorted by rank counting
+constexpr int kTsChunk = 2048;   // longest list sorted in LDS at once (16 KB: the
+                                 // LDS of 10 workgroups fits a CU, more than its
+                                 // wave slots hold)
+constexpr int kTsWin = 1024;     // merge window per run
 
 // Exclusive scan of one uint32 per thread over a 256-thread block.
 __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s4,
@@ -79,18 +70,13 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
     return o;
   };
   L.nb = (n + kPreBlock - 1) / kPreBlock;
-  L.dparts = (n + kSortTile - 1) / kSortTile;
-  if (L.dparts < 1) L.dparts = 1;
-  L.zero_begin = off;
   L.counts = take(4 * sizeof(uint64_t));  // offset 0: part of the ABI
-  L.dhist = take(4 * kRadixBins * 4);
-  L.counters = take(16 * 4);
-  L.dstatus = take((size_t)4 * L.dparts * kRadixBins * 4);
   // binning: levels of 4x4 bins until one bin covers the grid; per level,
   // the children's entry totals (accumulated by the count pass)
   const int64_t big = tiles_x > tiles_y ? tiles_x : tiles_y;
+  // the root (kRootFan) over levels of fan 4 covers kRootFan * 4^(levels - 1) tiles
   int levels = 1;
-  while ((int64_t(1) << (2 * levels)) < big) ++levels;
+  while ((int64_t(kRootFan) << (2 * (levels - 1))) < big) ++levels;
   L.bl_levels = levels;
   int64_t tot_words = 0;
   for (int lev = 0; lev < levels; ++lev) {
@@ -98,14 +84,14 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
     tot_words += ((tiles_x + side - 1) / side) * ((tiles_y + side - 1) / side);
   }
   L.bl_tot = take((size_t)tot_words * 4);
-  L.zero_end = off;
+  L.tot_words = tot_words;
   L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
   L.inst_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
   L.ioff = take((size_t)(n > 0 ? n : 1) * 4);
   L.scan_part = take((size_t)((L.nb + kScanTile - 1) / kScanTile + 1) * 16);
-  for (int k = 0; k < 2; ++k) L.dkey[k] = take((size_t)(n > 0 ? n : 1) * 4);
-  for (int k = 0; k < 2; ++k) L.didx[k] = take((size_t)(n > 0 ? n : 1) * 4);
   L.vidx = take((size_t)(n > 0 ? n : 1) * 4);
+  L.vrect = take((size_t)(n > 0 ? n : 1) * 8);
+  L.vkey = take((size_t)(n > 0 ? n : 1) * 4);
   // every entry of an inner level is a (Gaussian, bin) pair with at least
   // one instance in the bin, so an inner list never exceeds the instance count
   const int64_t bins = ((tiles_x + 3) / 4) * ((tiles_y + 3) / 4);
@@ -114,7 +100,13 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
   L.bl_list[0] = levels >= 3 ? take(list_bytes) : off;
   for (int k = 0; k < 2; ++k) L.bl_bins[k] = take((size_t)(bins + 1) * 8);
   for (int k = 0; k < 2; ++k) L.bl_seg[k] = take((size_t)(bins + 2) * 4);
-  L.bl_cnt = take((size_t)(cap / kBinSeg + bins + 2) * 16 * 4);
+  {
+    // (segment, child) counts: 256 per segment of the root, 16 below
+    const size_t segs = (size_t)(cap / kBinSeg) + 2;
+    const size_t words = std::max(segs * 256, (segs + (size_t)bins) * 16);
+    L.bl_cnt = take(words * 4);
+  }
+  for (int k = 0; k < 2; ++k) L.pairs[k] = take((size_t)(cap > 0 ? cap : 1) * 8);
   L.total = off;
   return L;
 }
@@ -140,7 +132,6 @@ SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x,
   const char* b = static_cast<const char*>(ws);
   SortView v;
   v.counts = reinterpret_cast<const uint64_t*>(b + L.counts);
-  v.didx = reinterpret_cast<const uint32_t*>(b + L.didx[0]);
   v.vidx = reinterpret_cast<const uint32_t*>(b + L.vidx);
   v.ioff = reinterpret_cast<const uint32_t*>(b + L.ioff);
   return v;
@@ -160,8 +151,16 @@ __device__ __forceinline__ uint64_t block_sum256_u64(uint64_t v, unsigned long l
 }
 
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ bsum, int64_t nb,
-                                                     uint64_t* __restrict__ part) {
+                                                     uint64_t* __restrict__ part,
+                                                     uint32_t* __restrict__ tot, int64_t tot_words,
+                                                     uint64_t* counts) {
   __shared__ unsigned long long s4[4];
+  // the first kernel of the call also clears what later kernels accumulate
+  // into: the binning's child totals and the reserved error word
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < tot_words;
+       k += (int64_t)gridDim.x * 256)
+    tot[k] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[3] = 0;
   const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint64_t sv = 0, si = 0;
 #pragma unroll
@@ -231,20 +230,22 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
   }
 }
 
-// Compacted (depth bits, Gaussian index) list of visible Gaussians in index
-// order.  The index list stays untouched by the depth passes (the first one
-// reads it): the backward walks the visible Gaussians in this order, where
-// neighbouring lanes read neighbouring parameter rows.
+// Compacted list of the visible Gaussians in index order: the input of the
+// tile binning, and the order in which the backward walks the visible
+// Gaussians (neighbouring lanes read neighbouring parameter rows).
 // Also gives every visible Gaussian the offset of its first (Gaussian, tile)
 // instance in index order, ioff[i]: the backward stores the gradient row of
 // instance (i, tile) at ioff[i] + the tile's raster position in i's tile
 // rectangle, so that each Gaussian's rows are contiguous.
 __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restrict__ n_tiles,
-                                                       const float* __restrict__ rec, int64_t n,
+                                                       const float* __restrict__ rec,
+                                                       const uint16_t* __restrict__ rect,
+                                                       int64_t n,
                                                        const uint32_t* __restrict__ vis_off,
                                                        const uint32_t* __restrict__ inst_off,
-                                                       uint32_t* __restrict__ dkey,
-                                                       uint32_t* __restrict__ didx,
+                                                       uint32_t* __restrict__ vidx,
+                                                       ushort4* __restrict__ vrect,
+                                                       uint32_t* __restrict__ vkey,
                                                        uint32_t* __restrict__ ioff) {
   static_assert(kPreBlock == 256, "the instance scan is a 256-lane block scan");
   __shared__ uint32_t sw[kPreBlock / 64];
@@ -261,266 +262,41 @@ __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restric
   for (int k = 0; k < w; ++k) pre += sw[k];
   if (v) {
     const uint32_t pos = vis_off[blockIdx.x] + pre + rank;
-    dkey[pos] = __float_as_uint(rec[(size_t)i * kRecFloats + 9]);
-    didx[pos] = (uint32_t)i;
+    vidx[pos] = (uint32_t)i;
+    vrect[pos] = reinterpret_cast<const ushort4*>(rect)[i];
+    vkey[pos] = __float_as_uint(rec[(size_t)i * kRecFloats + 9]);
     ioff[i] = inst_off[blockIdx.x] + iex;
   }
 }
 
-// Global digit histograms of the depth keys for all four passes.
-__global__ __launch_bounds__(kSortBlock) void k_hist_depth(const uint32_t* __restrict__ keys,
-                                                           const uint64_t* counts,
-                                                           uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[4][kRadixBins];
-  for (int k = threadIdx.x; k < 4 * kRadixBins; k += kSortBlock) (&h[0][0])[k] = 0;
-  __syncthreads();
-  const uint64_t n = counts[0];
-  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-  for (int it = 0; it < kSortItems; ++it) {
-    const uint64_t i = base + (uint64_t)it * kSortBlock + threadIdx.x;
-    if (i < n) {
-      const uint32_t k = keys[i];
-      atomicAdd(&h[0][k & 255], 1u);
-      atomicAdd(&h[1][(k >> 8) & 255], 1u);
-      atomicAdd(&h[2][(k >> 16) & 255], 1u);
-      atomicAdd(&h[3][(k >> 24) & 255], 1u);
-    }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < 4 * kRadixBins; k += kSortBlock) {
-    const uint32_t c = (&h[0][0])[k];
-    if (c) atomicAdd(&hist[k], c);
-  }
-}
-
-
-// ------------------------------------------------------------- onesweep --
-struct SweepArgs {
-  const uint32_t* __restrict__ keys_in;
-  const uint32_t* __restrict__ vals_in;
-  uint32_t* __restrict__ keys_out;
-  uint32_t* __restrict__ vals_out;
-  const uint64_t* count;
-  uint64_t cap;
-  int shift, bits;
-  const uint32_t* __restrict__ hist;
-  uint32_t* status;
-  uint32_t* part_counter;
-  uint64_t* err;
-  // reduce-then-scan form: status holds, digit-major with row length
-  // pstride, each partition's first output position per digit (no look-back)
-  int offsets;
-  uint32_t pstride;
-};
-
-// Reduce-then-scan form of a pass, used when there are many partitions (a
-// look-back chain grows with the partition count): every partition's digit
-// counts, then per digit a scan over the partitions, then the scatter of
-// k_onesweep with those positions.
-__device__ __forceinline__ uint32_t sweep_n(const SweepArgs& a) {
-  uint64_t n64 = *a.count;
-  if (n64 > a.cap) n64 = a.cap;
-  return (uint32_t)n64;
-}
-
-__global__ __launch_bounds__(kSortBlock) void k_part_hist(SweepArgs a) {
-  __shared__ uint32_t h[kRadixBins];
-  const uint32_t n = sweep_n(a);
-  const uint32_t parts = (n + kSortTile - 1) / kSortTile;
-  const uint32_t dmask = (1u << a.bits) - 1u;
-  for (uint32_t part = blockIdx.x; part < parts; part += gridDim.x) {
-    __syncthreads();
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t base = (uint64_t)part * kSortTile;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)kSortTile; i += kSortBlock)
-      if (base + i < n) atomicAdd(&h[(a.keys_in[base + i] >> a.shift) & dmask], 1u);
-    __syncthreads();
-    a.status[(size_t)threadIdx.x * a.pstride + part] = h[threadIdx.x];
-  }
-}
-
-// One block per digit: the digit's global start (the counts of smaller
-// digits) plus an exclusive scan of its per-partition counts.
-__global__ __launch_bounds__(kSortBlock) void k_part_scan(SweepArgs a) {
-  __shared__ uint32_t s4[4];
-  __shared__ uint32_t s_tot;
-  const uint32_t n = sweep_n(a);
-  const uint32_t parts = (n + kSortTile - 1) / kSortTile;
-  const uint32_t d = blockIdx.x;
-  uint32_t gtot;
-  const uint32_t gex = block_excl_scan256(a.hist[threadIdx.x], s4, &gtot);
-  if (threadIdx.x == d) s_tot = gex;
-  __syncthreads();
-  uint32_t run = s_tot;
-  uint32_t* row = a.status + (size_t)d * a.pstride;
-  for (uint32_t p0 = 0; p0 < parts; p0 += kSortBlock) {
-    const uint32_t p = p0 + threadIdx.x;
-    const uint32_t c = p < parts ? row[p] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan256(c, s4, &tot);
-    if (p < parts) row[p] = run + ex;
-    run += tot;
-  }
-}
-
-// One stable LSD pass over `bits` digits at `shift` of the keys.  Blocks
-// take partitions from an atomic counter until none is left, so a partition
-// only waits (in the look-back) on partitions that running blocks hold.
-__global__ __launch_bounds__(kSortBlock) void k_onesweep(SweepArgs a) {
-  __shared__ uint32_t s_keys[kSortTile];
-  __shared__ uint32_t s_vals[kSortTile];
-  // per-wave digit counters, then destinations and local offsets
-  __shared__ uint32_t s_aux[6 * kRadixBins + 8];
-  uint32_t(*s_wh)[kRadixBins] = reinterpret_cast<uint32_t(*)[kRadixBins]>(s_aux);
-  uint32_t* s_dst = s_aux + 4 * kRadixBins;
-  uint32_t* s_loc = s_aux + 5 * kRadixBins;
-  __shared__ uint32_t s_scan[4];
-  __shared__ uint32_t s_part;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const uint32_t n = sweep_n(a);
-  for (;;) {
-  __syncthreads();  // the previous partition is fully written out
-  if (tid == 0) s_part = atomicAdd(a.part_counter, 1u);
-  __syncthreads();
-  const uint32_t part = s_part;
-  const uint64_t base = (uint64_t)part * kSortTile;
-  if (base >= n) return;
-  const uint32_t tile_n = (n - base) < (uint64_t)kSortTile ? (uint32_t)(n - base) : (uint32_t)kSortTile;
-  const uint32_t dmask = (1u << a.bits) - 1u;
-  for (int k = tid; k < 4 * kRadixBins; k += kSortBlock) s_aux[k] = 0;
-  __syncthreads();
-
-  uint32_t k[kSortItems], v[kSortItems], rk[kSortItems], dg[kSortItems];
-#pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
-    const uint32_t idx = (uint32_t)w * (kSortTile / 4) + it * 64 + lane;
-    const bool valid = idx < tile_n;
-    k[it] = valid ? a.keys_in[base + idx] : 0u;
-    v[it] = valid ? a.vals_in[base + idx] : 0u;
-  }
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
-#pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
-    const uint32_t idx = (uint32_t)w * (kSortTile / 4) + it * 64 + lane;
-    const bool valid = idx < tile_n;
-    const uint32_t d = (k[it] >> a.shift) & dmask;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < a.bits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
-    }
-    const uint64_t lower = peers & lt_mask;
-    uint32_t pre = 0;
-    if (valid) pre = s_wh[w][d];
-    if (valid && lower == 0) s_wh[w][d] = pre + (uint32_t)__popcll(peers);
-    rk[it] = pre + (uint32_t)__popcll(lower);
-    dg[it] = valid ? d : 0xFFFFFFFFu;
-  }
-  __syncthreads();
-  // per digit: wave offsets, block total, block-local offsets
-  const uint32_t d = tid;
-  const uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
-  const uint32_t tot = c0 + c1 + c2 + c3;
-  if (!a.offsets) {
-    if (part == 0)
-      st_status(&a.status[d], kFlagIncl | tot);
-    else
-      st_status(&a.status[(size_t)part * kRadixBins + d], kFlagAgg | tot);
-  }
-  __syncthreads();
-  s_wh[0][d] = 0, s_wh[1][d] = c0, s_wh[2][d] = c0 + c1, s_wh[3][d] = c0 + c1 + c2;
-  const uint32_t loc = block_excl_scan256(tot, s_scan, nullptr);
-  const uint32_t gex =
-      a.offsets ? a.status[(size_t)d * a.pstride + part] : block_excl_scan256(a.hist[d], s_scan, nullptr);
-  s_loc[d] = loc;
-  // decoupled look-back over earlier partitions for this digit, reading a
-  // window of kLookback predecessors per round trip: their sum is taken down
-  // to the nearest inclusive prefix; a predecessor not yet published ends
-  // the window and is waited for (bounded spin)
-  uint32_t excl = 0;
-  if (!a.offsets && part > 0) {
-    int64_t j = (int64_t)part - 1;
-    int spins = 0;
-    while (j >= 0) {
-      uint32_t st[kLookback];
-#pragma unroll
-      for (int q = 0; q < kLookback; ++q)
-        st[q] = j - q >= 0 ? ld_status(&a.status[(size_t)(j - q) * kRadixBins + d]) : kFlagIncl;
-      bool stop = false;
-      int used = 0;
-#pragma unroll
-      for (int q = 0; q < kLookback; ++q) {
-        if (stop) continue;
-        if ((st[q] & ~kValMask) == 0) {  // not published yet: wait on it
-          stop = true;
-          continue;
-        }
-        excl += st[q] & kValMask;
-        ++used;
-        if ((st[q] & kFlagIncl) != 0) {
-          stop = true;
-          j = -1;  // done
-        }
-      }
-      if (j < 0) break;
-      j -= used;
-      if (used == 0) {
-        if (++spins > kSpinLimit) {
-          atomicOr((unsigned long long*)a.err, 1ull);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    st_status(&a.status[(size_t)part * kRadixBins + d], kFlagIncl | ((excl + tot) & kValMask));
-  }
-  s_dst[d] = gex + excl - loc;
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
-    if (dg[it] != 0xFFFFFFFFu) {
-      const uint32_t pos = s_loc[dg[it]] + s_wh[w][dg[it]] + rk[it];
-      if (pos < (uint32_t)kSortTile) {
-        s_keys[pos] = k[it];
-        s_vals[pos] = v[it];
-      }
-    }
-  }
-  __syncthreads();
-  for (uint32_t i = tid; i < tile_n; i += kSortBlock) {
-    const uint32_t key = s_keys[i];
-    const uint32_t val = s_vals[i];
-    const uint32_t o = s_dst[(key >> a.shift) & dmask] + i;
-    if (o >= n) continue;  // only reachable if the counts were inconsistent
-    a.keys_out[o] = key;
-    a.vals_out[o] = val;
-  }
-  }
-}
-
 // ------------------------------------------------------------ binning --
-// One level of the tile hierarchy: parents are bins of 4*side x 4*side
+// One level of the tile hierarchy: parents are bins of fan*side x fan*side
 // tiles (grid pgx x pgy, lists in `in`), children bins of side x side
-// (grid cgx x cgy).  Child (cx, cy) belongs to parent (cx/4, cy/4) at slot
-// (cy%4)*4 + cx%4.  Parent lists are cut into segments of kBinSeg entries;
-// pseg[p] is the first segment of parent p and pseg[nparents] the total.
+// (grid cgx x cgy).  Child (cx, cy) belongs to parent (cx/fan, cy/fan) at
+// slot (cy%fan)*fan + cx%fan; a wavefront takes fan*fan/16 slots.  The
+// root level has one parent and fan kRootFan, the levels below fan 4 (a
+// root of fan 16, a row of 16 slots per wavefront, measured slower: its
+// wavefronts scan the segment once per slot).  Parent lists are cut into
+// segments of kBinSeg entries; pseg[p] is the first segment of parent p and
+// pseg[nparents] the total.
 struct BinLevel {
-  const uint32_t* __restrict__ in;
+  const uint32_t* __restrict__ in;  // positions in the compacted visible list
   const uint2* __restrict__ pbins;   // (start, length) per parent
   const uint32_t* __restrict__ pseg;
   int pgx, pgy, cgx, cgy, side, tiles_x, tiles_y;
-  const uint16_t* __restrict__ rect;
+  int fan;    // children per parent along each axis (4 or 16)
+  int cpw;    // children per wavefront: fan * fan / 16
+  const ushort4* __restrict__ vrect;  // tile rectangle per compacted position
+  const uint32_t* __restrict__ vkey;  // depth bits per compacted position
+  const uint32_t* __restrict__ vidx;  // Gaussian index per compacted position
   const uint64_t* counts;
-  uint32_t* __restrict__ cnt;   // [segments][16]
+  uint32_t* __restrict__ cnt;   // [segments][fan * fan]
   uint32_t* __restrict__ tot;   // [children], zeroed before the count pass
   uint2* __restrict__ cbins;    // (start, length) per child (inner levels)
   uint32_t* __restrict__ cseg;  // segment starts of the children (inner levels)
-  uint32_t* __restrict__ out;   // child lists; the instance values at the last level
+  uint32_t* __restrict__ out;     // child lists of the inner levels
   uint32_t* __restrict__ ranges;  // last level: [tiles][2]
-  uint64_t* __restrict__ keys;    // last level, optional
-  const float* __restrict__ rec;
+  uint64_t* __restrict__ pairs;   // last level: depth bits << 32 | index per instance
   int last;
   int inline_scan;  // few children: the write pass scans the totals itself
 };
@@ -541,10 +317,10 @@ __device__ __forceinline__ int bin_segment(const BinLevel& a, uint32_t sg, uint3
   return l;
 }
 
-// Tile region of the child bin of parent p at slot w; false if outside.
-__device__ __forceinline__ bool bin_child(const BinLevel& a, int p, int w, int* c, int* rx0,
+// Tile region of the child bin of parent p at slot `slot`; false if outside.
+__device__ __forceinline__ bool bin_child(const BinLevel& a, int p, int slot, int* c, int* rx0,
                                           int* rx1, int* ry0, int* ry1) {
-  const int cx = (p % a.pgx) * 4 + (w & 3), cy = (p / a.pgx) * 4 + (w >> 2);
+  const int cx = (p % a.pgx) * a.fan + slot % a.fan, cy = (p / a.pgx) * a.fan + slot / a.fan;
   if (cx >= a.cgx || cy >= a.cgy) return false;
   *c = cy * a.cgx + cx;
   *rx0 = cx * a.side, *ry0 = cy * a.side;
@@ -557,9 +333,9 @@ __device__ __forceinline__ void bin_stage(const BinLevel& a, uint32_t lo, uint32
                                           uint32_t* s_g, ushort4* s_rc) {
   __syncthreads();  // the previous segment is consumed
   for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
-    const uint32_t g = a.in[lo + i];
+    const uint32_t g = a.in ? a.in[lo + i] : lo + i;  // the root list is 0, 1, ...
     s_g[i] = g;
-    s_rc[i] = reinterpret_cast<const ushort4*>(a.rect)[g];
+    s_rc[i] = a.vrect[g];
   }
   __syncthreads();
 }
@@ -578,16 +354,20 @@ __global__ __launch_bounds__(1024) void k_bin_count(BinLevel a) {
     uint32_t lo, m;
     const int p = bin_segment(a, sg, &lo, &m);
     bin_stage(a, lo, m, s_g, s_rc);
-    int c = 0, rx0, rx1, ry0, ry1;
-    uint32_t n = 0;
-    if (bin_child(a, p, w, &c, &rx0, &rx1, &ry0, &ry1))
-      for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
-        const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
-        n += (uint32_t)__popcll(__ballot(hit));
+    const int nslot = a.fan * a.fan;
+    for (int k = 0; k < a.cpw; ++k) {
+      const int slot = w * a.cpw + k;
+      int c = 0, rx0, rx1, ry0, ry1;
+      uint32_t n = 0;
+      if (bin_child(a, p, slot, &c, &rx0, &rx1, &ry0, &ry1))
+        for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
+          const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
+          n += (uint32_t)__popcll(__ballot(hit));
+        }
+      if (lane == 0) {
+        a.cnt[(size_t)sg * nslot + slot] = n;
+        if (n) atomicAdd(&a.tot[c], n);  // integer sum: the order does not matter
       }
-    if (lane == 0) {
-      a.cnt[(size_t)sg * 16 + w] = n;
-      if (n) atomicAdd(&a.tot[c], n);  // integer sum: the order does not matter
     }
   }
 }
@@ -707,12 +487,15 @@ __global__ __launch_bounds__(1024) void k_bin_write(BinLevel a) {
     uint32_t lo, m;
     const int p = bin_segment(a, sg, &lo, &m);
     bin_stage(a, lo, m, s_g, s_rc);
+    const int nslot = a.fan * a.fan;
+    for (int k = 0; k < a.cpw; ++k) {
+    const int slot = w * a.cpw + k;
     int c, rx0, rx1, ry0, ry1;
-    if (!bin_child(a, p, w, &c, &rx0, &rx1, &ry0, &ry1)) continue;
+    if (!bin_child(a, p, slot, &c, &rx0, &rx1, &ry0, &ry1)) continue;
     // start of this (segment, child): the child's start plus the entries
     // the parent's earlier segments gave it
     uint32_t base = 0;
-    for (uint32_t q = a.pseg[p] + lane; q < sg; q += 64) base += a.cnt[(size_t)q * 16 + w];
+    for (uint32_t q = a.pseg[p] + lane; q < sg; q += 64) base += a.cnt[(size_t)q * nslot + slot];
     for (int o = 32; o >= 1; o >>= 1) base += __shfl_xor(base, o, 64);
     if (a.inline_scan) {
       uint32_t start = 0;
@@ -722,19 +505,148 @@ __global__ __launch_bounds__(1024) void k_bin_write(BinLevel a) {
     } else {
       base += a.last ? a.ranges[2 * (size_t)c] : a.cbins[c].x;
     }
-    const uint64_t zkey = (uint64_t)c << 32;
     for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
       const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
       const uint64_t b = __ballot(hit);
       if (hit) {
         const uint32_t pos = base + (uint32_t)__popcll(b & lt);
         const uint32_t g = s_g[j];
-        a.out[pos] = g;
-        if (a.keys) a.keys[pos] = zkey | __float_as_uint(a.rec[(size_t)g * kRecFloats + 9]);
+        if (a.last)
+          a.pairs[pos] = (uint64_t)a.vkey[g] << 32 | a.vidx[g];
+        else
+          a.out[pos] = g;
       }
       base += (uint32_t)__popcll(b);
     }
+    }
   }
+}
+
+// ------------------------------------------------------------ tile sort --
+// Every tile's list of (depth bits << 32 | Gaussian index) keys, in index
+// order after the binning, sorted ascending by one workgroup; the keys are
+// unique, so the order is (depth bits, index) whatever the method.
+
+// Bitonic network over np (a power of two <= kTsChunk) keys in LDS.
+__device__ __forceinline__ void ts_bitonic(uint64_t* s, uint32_t np) {
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t k = 2; k <= np; k <<= 1)
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < np / 2; i += kTsThreads) {
+        const uint32_t x = ((i & ~(j - 1)) << 1) | (i & (j - 1)), y = x + j;
+        const uint64_t u = s[x], v = s[y];
+        if ((u > v) == ((x & k) == 0)) s[x] = v, s[y] = u;
+      }
+      __syncthreads();
+    }
+}
+
+// Outputs of one list position: the instance value and, if asked, the
+// 64-bit key tile << 32 | depth bits.
+__device__ __forceinline__ void ts_out(uint32_t* vals, uint64_t* keys, uint32_t pos,
+                                       uint32_t tile, uint64_t k) {
+  vals[pos] = (uint32_t)k;
+  if (keys) keys[pos] = (uint64_t)tile << 32 | (k >> 32);
+}
+
+// Merge-path split of the first d outputs of merging a[0..na) and b[0..nb)
+// (ascending, unique): how many come from a.
+__device__ __forceinline__ uint32_t ts_split(const uint64_t* a, uint32_t na, const uint64_t* b,
+                                             uint32_t nb, uint32_t d) {
+  uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < b[d - 1 - mid]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kTsThreads) void k_tile_sort(const uint32_t* __restrict__ ranges,
+                                                          uint64_t* __restrict__ pa,
+                                                          uint64_t* __restrict__ pb,
+                                                          uint32_t* __restrict__ vals,
+                                                          uint64_t* __restrict__ keys) {
+  __shared__ uint64_t s_k[kTsChunk];
+  const uint32_t tile = blockIdx.x, tid = threadIdx.x;
+  const uint32_t s0 = ranges[2 * (size_t)tile], L = ranges[2 * (size_t)tile + 1] - s0;
+  if (L == 0) return;
+  if (L <= (uint32_t)kTsRank) {
+    // rank counting: each key's position is the number of smaller keys
+    uint64_t k = 0;
+    if (tid < L) k = s_k[tid] = pa[s0 + tid];
+    __syncthreads();
+    if (tid < L) {
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < L; ++j) r += s_k[j] < k ? 1u : 0u;
+      ts_out(vals, keys, s0 + r, tile, k);
+    }
+    return;
+  }
+  if (L <= (uint32_t)kTsChunk) {
+    uint32_t np = 512;
+    while (np < L) np <<= 1;
+    for (uint32_t i = tid; i < np; i += kTsThreads) s_k[i] = i < L ? pa[s0 + i] : ~0ull;
+    __syncthreads();
+    ts_bitonic(s_k, np);
+    for (uint32_t i = tid; i < L; i += kTsThreads) ts_out(vals, keys, s0 + i, tile, s_k[i]);
+    return;
+  }
+  // long list: sorted chunks of kTsChunk keys (in place in pa), then merge
+  // passes of doubling run width between pa and pb, each merge streamed
+  // through LDS windows of kTsWin keys per run
+  uint64_t* src = pa + s0;
+  uint64_t* dst = pb + s0;
+  for (uint32_t c0 = 0; c0 < L; c0 += kTsChunk) {
+    const uint32_t m = L - c0 < (uint32_t)kTsChunk ? L - c0 : (uint32_t)kTsChunk;
+    __syncthreads();
+    for (uint32_t i = tid; i < (uint32_t)kTsChunk; i += kTsThreads) s_k[i] = i < m ? src[c0 + i] : ~0ull;
+    __syncthreads();
+    ts_bitonic(s_k, kTsChunk);
+    for (uint32_t i = tid; i < m; i += kTsThreads) src[c0 + i] = s_k[i];
+  }
+  uint64_t* sa = s_k;
+  uint64_t* sb = s_k + kTsWin;
+  constexpr uint32_t kPer = kTsWin / kTsThreads;  // outputs per thread per window
+  for (uint32_t w = kTsChunk; w < L; w <<= 1) {
+    for (uint32_t lo = 0; lo < L; lo += 2 * w) {
+      const uint32_t la = L - lo < w ? L - lo : w;
+      const uint32_t lb = L - lo - la < w ? L - lo - la : w;
+      const uint64_t* A = src + lo;
+      const uint64_t* Bv = src + lo + la;
+      uint32_t ia = 0, ib = 0, o = 0;
+      while (o < la + lb) {
+        const uint32_t na = la - ia < (uint32_t)kTsWin ? la - ia : (uint32_t)kTsWin;
+        const uint32_t nb = lb - ib < (uint32_t)kTsWin ? lb - ib : (uint32_t)kTsWin;
+        __syncthreads();  // the previous window is consumed
+        for (uint32_t i = tid; i < (uint32_t)kTsWin; i += kTsThreads) {
+          sa[i] = i < na ? A[ia + i] : ~0ull;
+          sb[i] = i < nb ? Bv[ib + i] : ~0ull;
+        }
+        __syncthreads();
+        // the window's outputs are the `win` smallest remaining keys, all
+        // within the loaded prefixes of both runs
+        const uint32_t left = la + lb - o;
+        const uint32_t win = left < (uint32_t)kTsWin ? left : (uint32_t)kTsWin;
+        const uint32_t d0 = tid * kPer < win ? tid * kPer : win;
+        uint32_t i = ts_split(sa, na, sb, nb, d0), j = d0 - i;
+        for (uint32_t q = 0; q < kPer && d0 + q < win; ++q) {
+          const bool take_a = j >= nb || (i < na && sa[i] < sb[j]);
+          dst[lo + o + d0 + q] = take_a ? sa[i] : sb[j];
+          if (take_a) ++i; else ++j;
+        }
+        const uint32_t ea = ts_split(sa, na, sb, nb, win);
+        ia += ea;
+        ib += win - ea;
+        o += win;
+      }
+    }
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+    __syncthreads();  // this pass's outputs are written before the next reads them
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < L; i += kTsThreads) ts_out(vals, keys, s0 + i, tile, src[i]);
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
@@ -756,22 +668,6 @@ hipError_t launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-// One pass over at most `parts` partitions: with few partitions the
-// look-back form, otherwise reduce-then-scan (status must then hold
-// parts * kRadixBins words, which the look-back form needs as well).
-constexpr uint32_t kLookbackParts = 512;
-static void launch_pass(SweepArgs a, uint32_t parts, hipStream_t st) {
-  const unsigned grid = parts < 1024u ? parts : 1024u;
-  if (parts > kLookbackParts) {
-    a.offsets = 1;
-    a.pstride = parts;
-    hipLaunchKernelGGL(k_part_hist, dim3(parts < 2048u ? parts : 2048u), dim3(kSortBlock), 0, st, a);
-    hipLaunchKernelGGL(k_part_scan, dim3(kRadixBins), dim3(kSortBlock), 0, st, a);
-  }
-  hipLaunchKernelGGL(k_onesweep, dim3(grid > 0 ? grid : 1), dim3(kSortBlock), 0, st, a);
-}
-
-
 hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
                        int64_t capacity, int64_t tiles_total, uint64_t* keys,
                        uint32_t* vals, uint32_t* ranges, char* ws,
@@ -782,8 +678,8 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
   hipError_t e;
   auto u32 = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   uint64_t* counts = reinterpret_cast<uint64_t*>(ws + L.counts);
-  if ((e = launch_fill(u32(L.zero_begin), (int64_t)((L.zero_end - L.zero_begin) / 4), 0, st))) return e;
   if (n == 0) {
+    if ((e = launch_fill(u32(L.counts), 8, 0, st))) return e;
     if ((e = launch_fill(ranges, tiles_total * 2, 0, st))) return e;
     if (h_counts) h_counts[0] = h_counts[1] = 0;
     return hipSuccess;
@@ -792,7 +688,7 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     const unsigned tiles = (unsigned)((L.nb + kScanTile - 1) / kScanTile);
     uint64_t* part = reinterpret_cast<uint64_t*>(ws + L.scan_part);
     hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(256), 0, st, proj.block_sums,
-                       (int64_t)L.nb, part);
+                       (int64_t)L.nb, part, u32(L.bl_tot), L.tot_words, counts);
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, st, proj.block_sums,
                        (int64_t)L.nb, part, u32(L.vis_off), u32(L.inst_off), counts,
                        (int64_t)capacity,
@@ -810,31 +706,11 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
       return hipSuccess;
     }
   }
-  // phase 1: depth digits (bits 0..30; depth > 0, sign bit clear) in 8,8,8,7
   hipLaunchKernelGGL(k_compact, dim3((unsigned)L.nb), dim3(kPreBlock), 0, st, proj.n_tiles,
-                     proj.rec, n, u32(L.vis_off), u32(L.inst_off), u32(L.dkey[0]), u32(L.vidx),
-                     u32(L.ioff));
-  hipLaunchKernelGGL(k_hist_depth, dim3((unsigned)L.dparts), dim3(kSortBlock), 0, st,
-                     u32(L.dkey[0]), counts, u32(L.dhist));
-  uint32_t* counters = u32(L.counters);
-  uint64_t* err = counts + 3;
-  for (int ps = 0; ps < 4; ++ps) {
-    SweepArgs a{};
-    a.keys_in = u32(L.dkey[ps & 1]);
-    a.vals_in = ps == 0 ? u32(L.vidx) : u32(L.didx[ps & 1]);
-    a.keys_out = u32(L.dkey[(ps + 1) & 1]);
-    a.vals_out = u32(L.didx[(ps + 1) & 1]);
-    a.count = counts;
-    a.cap = (uint64_t)n;
-    a.shift = 8 * ps;
-    a.bits = ps == 3 ? 7 : 8;
-    a.hist = u32(L.dhist) + ps * kRadixBins;
-    a.status = u32(L.dstatus) + (size_t)ps * L.dparts * kRadixBins;
-    a.part_counter = counters + ps;
-    a.err = err;
-    launch_pass(a, (uint32_t)L.dparts, st);
-  }
-  // phase 2: split the depth-ordered list by tile, level by level
+                     proj.rec, proj.rect, n, u32(L.vis_off), u32(L.inst_off), u32(L.vidx),
+                     reinterpret_cast<ushort4*>(ws + L.vrect), u32(L.vkey), u32(L.ioff));
+  // phase 1: split the index-ordered list of visible Gaussians by tile,
+  // level by level
   uint2* bins[2] = {reinterpret_cast<uint2*>(ws + L.bl_bins[0]),
                     reinterpret_cast<uint2*>(ws + L.bl_bins[1])};
   uint32_t* seg[2] = {u32(L.bl_seg[0]), u32(L.bl_seg[1])};
@@ -846,7 +722,9 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     tot_off[lev] = o;
     o += ((p.tiles_x + side - 1) / side) * ((p.tiles_y + side - 1) / side);
   }
-  const uint32_t* in = u32(L.didx[0]);
+  const uint32_t* in = nullptr;  // the root bin lists compacted positions 0, 1, ...
+  uint64_t* pairs[2] = {reinterpret_cast<uint64_t*>(ws + L.pairs[0]),
+                        reinterpret_cast<uint64_t*>(ws + L.pairs[1])};
   int cur = 0;
   for (int lev = L.bl_levels - 1; lev >= 0; --lev) {
     const int side = 1 << (2 * lev);
@@ -856,21 +734,24 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     a.pseg = seg[cur];
     a.cgx = (p.tiles_x + side - 1) / side;
     a.cgy = (p.tiles_y + side - 1) / side;
-    a.pgx = (a.cgx + 3) / 4;
-    a.pgy = (a.cgy + 3) / 4;
+    a.fan = lev == L.bl_levels - 1 ? kRootFan : 4;  // the root: one parent
+    a.cpw = a.fan * a.fan / 16;
+    a.pgx = (a.cgx + a.fan - 1) / a.fan;
+    a.pgy = (a.cgy + a.fan - 1) / a.fan;
     a.side = side;
     a.tiles_x = p.tiles_x, a.tiles_y = p.tiles_y;
-    a.rect = proj.rect;
+    a.vrect = reinterpret_cast<const ushort4*>(ws + L.vrect);
+    a.vkey = u32(L.vkey);
+    a.vidx = u32(L.vidx);
     a.counts = counts;
     a.cnt = u32(L.bl_cnt);
     a.tot = u32(L.bl_tot) + tot_off[lev];
     a.cbins = bins[cur ^ 1];
     a.cseg = seg[cur ^ 1];
     a.last = lev == 0;
-    a.out = a.last ? vals : lists[lev & 1];
+    a.out = a.last ? nullptr : lists[lev & 1];
     a.ranges = ranges;
-    a.keys = a.last ? keys : nullptr;
-    a.rec = proj.rec;
+    a.pairs = a.last ? pairs[0] : nullptr;
     const int64_t nparents = (int64_t)a.pgx * a.pgy;
     const int64_t segs_max = capacity / kBinSeg + nparents + 1;
     const unsigned grid = (unsigned)(segs_max < 4096 ? segs_max : 4096);
@@ -881,6 +762,9 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     in = a.out;
     cur ^= 1;
   }
+  // phase 2: each tile's list by (depth bits, index)
+  hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)tiles_total), dim3(kTsThreads), 0, st, ranges,
+                     pairs[0], pairs[1], vals, keys);
   return hipGetLastError();
 }
 

@@ -81,6 +81,19 @@ def spatial_order(means: np.ndarray, bits: int = 10) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
+_COUNT_STREAMS = {}
+
+
+def _count_stream(device) -> torch.cuda.Stream:
+    """A side stream per device for the copies of sort count words to the
+    host, so that they overlap the render instead of following the sort on
+    the caller's stream."""
+    s = _COUNT_STREAMS.get(device)
+    if s is None:
+        s = _COUNT_STREAMS[device] = torch.cuda.Stream(device=device)
+    return s
+
+
 def tiles_of(cam, settings):
     tx = (cam.width + settings.tile_w - 1) // settings.tile_w
     ty = (cam.height + settings.tile_h - 1) // settings.tile_h
@@ -143,7 +156,13 @@ class CellView:
         self._xf_boxes, self._xf_cell, self._omega = list(boxes), int(cell), omega
         B.set_cross_filter(self.c_proj, self.xf, omega, cell, len(self._xf_boxes))
 
+    def _wait_count_copy(self):
+        # a posted copy of the count words may still read the workspace
+        if self._counts_ev is not None:
+            self._counts_ev.synchronize()
+
     def _alloc_sort(self, capacity: int):
+        self._wait_count_copy()
         self.capacity = int(capacity)
         self.vals = torch.empty((max(self.capacity, 1),), dtype=torch.int32, device=self.device)
         self.keys = (torch.empty((max(self.capacity, 1),), dtype=torch.int64, device=self.device)
@@ -165,6 +184,7 @@ class CellView:
             raise ValueError("instance buffers too small for the capacity")
         if bwd_ws is not None and bwd_ws.numel() < self.backward_bytes(capacity):
             raise ValueError("backward workspace too small for the capacity")
+        self._wait_count_copy()
         self.capacity = int(capacity)
         self.vals, self.ws, self.bwd_ws = vals, ws, bwd_ws
         self.keys = None
@@ -181,6 +201,9 @@ class CellView:
         buffers when they are too small; without, sorts asynchronously into
         the current capacity and posts an asynchronous copy of the count
         words (read them with poll_counts once the stream got that far)."""
+        if self._counts_ev is not None:
+            # the previous sort's count copy reads the words this sort clears
+            torch.cuda.current_stream().wait_event(self._counts_ev)
         if not sync:
             B.sx_sort(self.c_proj, self.params.n, self.c_cam, self.c_par, self.capacity,
                       self.keys, self.vals, self.ranges, self.ws, sync_counts=False)
@@ -202,12 +225,18 @@ class CellView:
 
     def post_counts(self):
         """Enqueue a copy of the last sort's count words into pinned host
-        memory on the current stream."""
+        memory, on a side stream after the current stream's sort."""
         if self._h_counts is None:
             self._h_counts = torch.zeros((4,), dtype=torch.int64, pin_memory=True)
             self._counts_ev = torch.cuda.Event()
-        self._h_counts.copy_(self.ws[:32].view(torch.int64), non_blocking=True)
-        self._counts_ev.record()
+        main = torch.cuda.current_stream()
+        side = _count_stream(main.device)
+        ready = torch.cuda.Event()
+        ready.record(main)
+        side.wait_event(ready)
+        with torch.cuda.stream(side):
+            self._h_counts.copy_(self.ws[:32].view(torch.int64), non_blocking=True)
+            self._counts_ev.record(side)
 
     def poll_counts(self):
         """(visible, instances, overflow) of the last asynchronous sort; waits

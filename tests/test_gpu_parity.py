@@ -140,8 +140,8 @@ def _check_lists(v, counts, keys, vals, ranges):
 
 def test_sort_ragged_and_capacity(torch_gpu):
     """Non-multiple image size (ragged tile tail), a capacity that is too
-    small (SX_ECAPACITY, then a retry with grown buffers) and a
-    multi-partition radix sort (instances > 4096 per partition)."""
+    small (SX_ECAPACITY, then a retry with grown buffers), and more than
+    12k instances."""
     print("case: sort ragged 100x70 capacity", flush=True)
     torch = torch_gpu
     from paper_2606_18588_amd import binding as B
@@ -164,8 +164,8 @@ def test_sort_ragged_and_capacity(torch_gpu):
 
 
 def test_sort_large_grid(torch_gpu):
-    """A large tile grid (2048x1152 with 8x8 tiles: 36864 tiles, five levels
-    of 4x4 bins): keys, values and ranges are still bit-exact."""
+    """A large tile grid (2048x1152 with 8x8 tiles: 36864 tiles, four
+    levels of 4x4 bins): keys, values and ranges are still bit-exact."""
     print("case: sort large grid 2048x1152 8x8", flush=True)
     torch = torch_gpu
     st = synth.RenderSettings(tile_w=8, tile_h=8)
@@ -176,6 +176,24 @@ def test_sort_large_grid(torch_gpu):
     counts = v.sort(sync=True)
     keys, vals, ranges = oracle.sort_keys(scene, cam, st)
     assert len(keys) > 4 * 4096
+    _check_lists(v, counts, keys, vals, ranges)
+
+
+def test_sort_long_tile_lists_bit_exact(torch_gpu):
+    """Tile lists of 839 to 10130 entries (30k large Gaussians in a 128x96
+    view): the per-tile sort's bitonic network (up to 2048 entries) and its
+    merge of sorted 2048-entry chunks through LDS windows (one to three
+    merge passes) give the oracle's keys, values and ranges bit for bit."""
+    print("case: sort long tile lists 128x96", flush=True)
+    torch = torch_gpu
+    scene = synth.make_cube_scene(17, 30000, log_scale=(-2.3, 0.5))
+    cam = synth.tiny_camera(128, 96)
+    _, v = _cell_view(torch, scene, cam)
+    v.preprocess()
+    counts = v.sort(sync=True)
+    keys, vals, ranges = oracle.sort_keys(scene, cam, ST)
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    assert lens.max() > 8192 and ((lens > 256) & (lens <= 2048)).any()
     _check_lists(v, counts, keys, vals, ranges)
 
 
@@ -194,7 +212,7 @@ def test_sort_async_overflow_flag(torch_gpu):
     v.sort(sync=False)
     c4 = B.sx_sort_counts(v.ws, p.n)
     assert c4[1] > 2000 and c4[2] == 1 and c4[3] == 0
-    r = v.ranges.cpu().numpy().view(np.uint32)
+    r = v.ranges.cpu().numpy().view(np.uint32)[:-1]  # the tiles' rows (the last is spare)
     assert r.max() <= 2000
 
 
