@@ -4,19 +4,23 @@ launches (the paper's view bucketing and overlapped pipeline, Sec. 4.4,
 on one GPU).
 
 Every request is one camera.  The server keeps up to `inflight` batches on
-the GPU at once; a batch takes up to `max_batch` queued requests in arrival
-order while their estimated sort buffers (instance values + sort workspace)
-fit into the batch's arena of `arena_bytes`.  A batch runs one preprocess
-launch for all its views, one asynchronous sort per view into its arena
-slice, one render launch over all (view, tile) work items and a
-composition per view (K = 1: background under the residual transmittance).
+the GPU at once, each on its own stream with its own buffers, so that a
+batch formed from requests that arrived while another ran overlaps it on
+the device (continuous batching); a batch takes up to `max_batch` queued
+requests in arrival order while their estimated sort buffers (instance
+values + sort workspace) fit into the batch's arena of `arena_bytes`.  A
+batch runs one preprocess launch for all its views, one asynchronous sort
+per view into its arena slice (the sorts of a batch on side streams of its
+own), one render launch over all (view, tile) work items and a composition
+per view (K = 1: background under the residual transmittance); a batch of
+one request takes the per-view calls, which give the same image.
 Completion is seen on the host by polling the batch's event.  The instance
 estimate is learned from completed requests; a request whose instances
 overflow its estimate is re-queued at the front with the exact count.
 
-With plain=True the same loop serves one request per batch with the
-per-view calls (sx_preprocess, sx_sort, sx_render_partial, sx_composite),
-the baseline the batched form is measured against.
+With plain=True the loop serves one request at a time on one stream with
+the per-view calls (sx_preprocess, sx_sort, sx_render_partial,
+sx_composite): the baseline the batched form is measured against.
 
 Buffers are torch tensors (device memory, pinned host memory, streams);
 every step runs in libsplaxel's kernels.
@@ -91,6 +95,7 @@ class _Batch:
     counts: torch.Tensor  # pinned [V, 4] uint64 as int64
     slots: List[_Slot]
     pixels: List[int]
+    slot: int  # the in-flight slot (stream and buffers) it runs on
 
 
 class Server:
@@ -102,7 +107,15 @@ class Server:
         self.params = params
         self.settings = settings
         self.plain = plain
-        self.side = None if plain else [torch.cuda.Stream(device=device) for _ in range(4)]
+        if plain:
+            inflight = 1
+        # every in-flight batch has its own stream, side streams for its
+        # sorts and workspaces, so batch k + 1 runs while batch k is on the
+        # GPU (all streams at the default priority)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(inflight)]
+        self.side = (None if plain else
+                     [[torch.cuda.Stream(device=device) for _ in range(4)]
+                      for _ in range(inflight)])
         self.max_batch = 1 if plain else max_batch
         self.inflight = inflight
         self.arena_bytes = int(arena_bytes)
@@ -121,10 +134,10 @@ class Server:
                        for _ in range(inflight)]
         self.counts = [torch.zeros((self.max_batch, 4), dtype=torch.int64, pin_memory=True)
                        for _ in range(inflight)]
-        self.multi_ws = torch.empty(
-            (B.sx_multi_workspace_size([B.camera(_dummy_cam(max_width, max_height))] *
-                                       self.max_batch, self.c_par),),
-            dtype=torch.uint8, device=device)
+        mw = B.sx_multi_workspace_size([B.camera(_dummy_cam(max_width, max_height))] *
+                                       self.max_batch, self.c_par)
+        self.multi_ws = [torch.empty((mw,), dtype=torch.uint8, device=device)
+                         for _ in range(inflight)]
         self.box = [_Box()]
         self.ratio = None  # instances per pixel, learned
         self.recent = collections.deque(maxlen=64)
@@ -174,12 +187,20 @@ class Server:
         return items, caps
 
     def _launch(self, k: int, index: int, items: List[_Item], caps: List[int]) -> _Batch:
+        """Enqueue a batch on in-flight slot k's stream."""
+        with torch.cuda.stream(self.streams[k]):
+            return self._launch_on(k, index, items, caps)
+
+    def _launch_on(self, k: int, index: int, items: List[_Item], caps: List[int]) -> _Batch:
+        # one request alone takes the per-view calls (the same results as
+        # the batched launches, bit for bit, with less overhead)
+        single = self.plain or len(items) == 1
         slots = self.slots[k][:len(items)]
         arena = self.arenas[k]
         counts = self.counts[k]
         cams = [B.camera(it.cam) for it in items]
         projs = [s.c_proj for s in slots]
-        if self.plain:
+        if single:
             B.sx_preprocess(self.c_g, cams[0], self.c_par, projs[0])
         else:
             B.sx_preprocess_multi(self.c_g, cams, self.c_par, projs)
@@ -205,14 +226,14 @@ class Server:
 
         # the requests' sorts are independent: batched, they overlap on the
         # side streams (joined before the render)
-        run_on_streams(None if self.plain else self.side,
+        run_on_streams(None if single else self.side[k],
                        [lambda j=j: sort_job(j) for j in range(len(items))])
         for j, (it, cam, s, cap) in enumerate(zip(items, cams, slots, caps)):
             vals, ws, tiles = bufs[j]
             ranges = s.ranges[:2 * (tiles + 1)]
             px = it.cam.width * it.cam.height
             pixels.append(px)
-            if self.plain:
+            if single:
                 B.sx_render_partial(s.c_proj, vals, ranges, cam, self.c_par, None,
                                     s.partial[:4 * px], None, s.last[:px], None)
             else:
@@ -226,13 +247,13 @@ class Server:
                 v.partial = B.ptr(s.partial)
                 v.last = B.ptr(s.last)
                 views.append(v)
-        if not self.plain:
-            B.sx_render_multi(views, self.c_par, self.multi_ws)
+        if not single:
+            B.sx_render_multi(views, self.c_par, self.multi_ws[k])
         for it, cam, s, px in zip(items, cams, slots, pixels):
             B.sx_composite([s.partial[:4 * px]], self.box, cam, self.c_par, s.out[:4 * px], None)
         ev = torch.cuda.Event()
         ev.record()
-        return _Batch(index, items, caps, ev, counts, slots, pixels)
+        return _Batch(index, items, caps, ev, counts, slots, pixels, k)
 
     def _finish(self, b: _Batch, now: float, queue: collections.deque, done: List[Done]):
         requeue = []
@@ -256,6 +277,10 @@ class Server:
                 px = b.pixels[j]
                 self.images[it.rid] = b.slots[j].out[:4 * px].view(
                     it.cam.height, it.cam.width, 4).clone()
+        if self.images is not None:
+            # the next batch on this slot's stream rewrites the images just
+            # copied on the caller's stream: it waits for the copies
+            self.streams[b.slot].wait_stream(torch.cuda.current_stream())
         for it in reversed(requeue):
             queue.appendleft(it)
 
