@@ -166,6 +166,9 @@ def main():
                     help="cells: carry the saturation state with speculative re-evaluation")
     ap.add_argument("--partition", choices=("grid", "kd"), default="grid",
                     help="cells: the 4 x 2 ground grid of the configuration, or KD-tree cells")
+    ap.add_argument("--repartition", action="store_true",
+                    help="cells: also time one repartition of the 8M scene's 4 x 2 grid cells "
+                         "into KD-tree cells (parameters and Adam moments moved on the GPU)")
     ap.add_argument("--no-extras", action="store_true",
                     help="plain: skip the K = 8 cells step and the serving trace that the "
                          "default line also reports")
@@ -405,6 +408,23 @@ def cells_measure(args, sizes, steps, warmup, walk_roofline=True):
     grads = [p.zeros_like() for p in params]
     moments = [(torch.zeros_like(t), torch.zeros_like(t)) for p in params for t in p.tensors()]
     log(f"bench: 8M scene in {len(params)} cells ready in {time.perf_counter() - t0:.1f}s")
+    rep = None
+    if getattr(args, "repartition", False):
+        from paper_2606_18588_amd.pipeline import imbalance, repartition
+        states = [[m for t in range(5) for m in moments[5 * k + t]] for k in range(len(params))]
+        before = imbalance(params)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            new, _, new_states = repartition(params, len(params), states)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            del new, new_states
+        rep = {"imbalance_before": before, "ms": 1e3 * min(times),
+               "bytes_moved": int(sum(t.numel() * 4 for p in params for t in p.tensors()) * 3)}
+        log(f"bench: repartition of {len(params)} cells ({before:.3f} imbalance): "
+            f"{rep['ms']:.1f} ms")
     st = synth.RenderSettings()
     out = {}
     n_gauss = int(sum(p.n for p in params))
@@ -500,6 +520,8 @@ def cells_measure(args, sizes, steps, warmup, walk_roofline=True):
         torch.cuda.empty_cache()
     del params, grads, moments
     torch.cuda.empty_cache()
+    if rep is not None:
+        out["repartition"] = rep
     return out, n_gauss
 
 

@@ -228,6 +228,32 @@ sx_status sx_render_partial(const sx_projected* proj, const uint32_t* vals,
 sx_status sx_kd_partition(int64_t n, const float* means, int32_t K, sx_cell* cells,
                           int32_t* cell_of);
 
+/* Load monitoring and repartitioning (the paper's appendix, implementation
+ * details: the imbalance ratio N_max / mean(N) - 1 of the cells' Gaussian
+ * counts is checked during training and the cells are repartitioned when it
+ * exceeds 20%; on one GPU the all-to-all redistribution is a move of rows
+ * between cell buffers).
+ * sx_imbalance: ratio of HOST counts[K] (K in 1..16, at least one
+ *   Gaussian) into *ratio.  Host code.
+ * sx_repartition_plan: for HOST cell_of[n] (the new cell of every Gaussian,
+ *   indexed over the old cells laid end to end, e.g. from sx_kd_partition
+ *   of all their means), writes HOST dst_index[n] (each Gaussian's row in
+ *   its new cell: its rank among that cell's Gaussians, in the old order)
+ *   and counts[K] (the new cell sizes).  Host code.
+ * sx_move_rows: moves rows of row_floats floats (one parameter array, or an
+ *   optimiser state of the same layout) from K_src source buffers (HOST
+ *   array of device pointers, src_counts[K_src] rows each, laid end to end
+ *   in that order) to K_dst destination buffers (HOST array of device
+ *   pointers, each sized for its new count): row g goes to row dst_index[g]
+ *   of buffer dst_cell[g] (DEVICE int32 [n] each, n = sum of src_counts).
+ *   Destinations must not overlap sources.  Asynchronous on `stream`. */
+sx_status sx_imbalance(int32_t K, const int64_t* counts, double* ratio);
+sx_status sx_repartition_plan(int64_t n, const int32_t* cell_of, int32_t K, int32_t* dst_index,
+                              int64_t* counts);
+sx_status sx_move_rows(int32_t row_floats, int32_t K_src, const int64_t* src_counts,
+                       const float* const* src, int32_t K_dst, float* const* dst,
+                       const int32_t* dst_cell, const int32_t* dst_index, sx_stream stream);
+
 /* Geometric visibility of K cell boxes for one view (redundancy reduction
  * section, spatial part): the part of a box inside the view frustum is
  * convex, and its projection onto the image is the set of pixels whose

@@ -299,6 +299,16 @@ def kd_partition(means, K: int):
     return boxes, cell_of
 
 
+def repartition(cell_arrays: Sequence[np.ndarray], cell_of, K: int) -> List[np.ndarray]:
+    """The redistribution of a repartition (appendix, implementation
+    details: all-to-all redistribution after new boundaries): the old
+    cells' rows laid end to end, row g belongs to new cell cell_of[g], and
+    each new cell keeps the rows in their old order."""
+    rows = np.concatenate([np.asarray(a) for a in cell_arrays])
+    cell_of = np.asarray(cell_of)
+    return [rows[cell_of == k] for k in range(K)]
+
+
 def imbalance(cell_of, K: int) -> float:
     """N_max / mean(N) - 1 over the K cells' Gaussian counts."""
     counts = np.bincount(np.asarray(cell_of), minlength=K)

@@ -91,7 +91,7 @@ EXPORTS = (
     "sx_render_multi", "sx_render_backward_multi", "sx_preprocess_backward_multi",
     "sx_render_backward_stages", "sx_visibility", "sx_kd_partition",
     "sx_composite_reeval", "sx_cross_filter", "sx_composite_l1",
-    "sx_render_backward_noalloc",
+    "sx_render_backward_noalloc", "sx_imbalance", "sx_repartition_plan", "sx_move_rows",
 )
 SX_NOALLOC_SCRATCH_BYTES = 64 << 20  # the static scratch of sx_render_backward_noalloc
 
@@ -397,6 +397,38 @@ def sx_kd_partition(means, K: int):
         cell_of.ctypes.data_as(ctypes.c_void_p)))
     boxes = [(tuple(c.lo), tuple(c.hi)) for c in cells]
     return boxes, cell_of
+
+
+def sx_imbalance(counts) -> float:
+    """N_max / mean(N) - 1 of the cells' Gaussian counts."""
+    import numpy as np
+    c = np.ascontiguousarray(np.asarray(counts, np.int64))
+    r = ctypes.c_double()
+    _check("sx_imbalance", lib().sx_imbalance(c_i32(len(c)), c.ctypes.data_as(ctypes.c_void_p),
+                                              ctypes.byref(r)))
+    return float(r.value)
+
+
+def sx_repartition_plan(cell_of, K: int):
+    """(dst_index int32 [n], counts int64 [K]) for the new cell of every
+    Gaussian (host arrays)."""
+    import numpy as np
+    co = np.ascontiguousarray(np.asarray(cell_of, np.int32))
+    dst = np.zeros(len(co), np.int32)
+    counts = np.zeros(K, np.int64)
+    _check("sx_repartition_plan", lib().sx_repartition_plan(
+        c_i64(len(co)), co.ctypes.data_as(ctypes.c_void_p), c_i32(K),
+        dst.ctypes.data_as(ctypes.c_void_p), counts.ctypes.data_as(ctypes.c_void_p)))
+    return dst, counts
+
+
+def sx_move_rows(row_floats: int, src: Sequence[torch.Tensor], src_counts,
+                 dst: Sequence[torch.Tensor], dst_cell: torch.Tensor, dst_index: torch.Tensor,
+                 stream=None) -> None:
+    sc = (ctypes.c_int64 * len(src))(*[int(c) for c in src_counts])
+    _check("sx_move_rows", lib().sx_move_rows(
+        c_i32(row_floats), c_i32(len(src)), sc, ptr_array(src), c_i32(len(dst)),
+        ptr_array(dst), ptr(dst_cell), ptr(dst_index), stream_handle(stream)))
 
 
 def sx_visibility(cells, cam: SxCamera, masks, stream=None) -> None:

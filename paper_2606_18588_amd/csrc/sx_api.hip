@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/splaxel.h: argument
 // validation, conversion of the camera/parameters to kernel form, and
 // mapping of HIP errors to sx_status.  Nothing here allocates device memory.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -212,6 +213,55 @@ sx_status sx_kd_partition(int64_t n, const float* means, int32_t K, sx_cell* cel
   for (int m = 0; m < K; ++m)
     for (int j = 0; j < 3; ++j) cells[m].lo[j] = lo[m * 3 + j], cells[m].hi[j] = hi[m * 3 + j];
   return SX_OK;
+}
+
+sx_status sx_imbalance(int32_t K, const int64_t* counts, double* ratio) {
+  if (K < 1 || K > sx::kMaxCells) return fail(SX_EINVAL, "K=%d outside 1..%d", K, sx::kMaxCells);
+  if (!counts || !ratio) return fail(SX_EINVAL, "null argument");
+  int64_t mx = 0, tot = 0;
+  for (int k = 0; k < K; ++k) {
+    if (counts[k] < 0) return fail(SX_EINVAL, "negative count in cell %d", k);
+    mx = std::max(mx, counts[k]);
+    tot += counts[k];
+  }
+  if (tot == 0) return fail(SX_EINVAL, "no Gaussians");
+  *ratio = (double)mx * K / (double)tot - 1.0;
+  return SX_OK;
+}
+
+sx_status sx_repartition_plan(int64_t n, const int32_t* cell_of, int32_t K, int32_t* dst_index,
+                              int64_t* counts) {
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "n out of range");
+  if (K < 1 || K > sx::kMaxCells) return fail(SX_EINVAL, "K=%d outside 1..%d", K, sx::kMaxCells);
+  if (!counts || (n > 0 && (!cell_of || !dst_index))) return fail(SX_EINVAL, "null argument");
+  for (int64_t g = 0; g < n; ++g)
+    if (cell_of[g] < 0 || cell_of[g] >= K)
+      return fail(SX_EINVAL, "cell_of[%lld] = %d outside 0..%d", (long long)g, cell_of[g], K - 1);
+  sx::repartition_plan(n, cell_of, K, dst_index, counts);
+  return SX_OK;
+}
+
+sx_status sx_move_rows(int32_t row_floats, int32_t K_src, const int64_t* src_counts,
+                       const float* const* src, int32_t K_dst, float* const* dst,
+                       const int32_t* dst_cell, const int32_t* dst_index, sx_stream stream) {
+  if (row_floats < 1 || row_floats > 4096) return fail(SX_EINVAL, "row_floats=%d", row_floats);
+  if (K_src < 1 || K_src > sx::kMaxCells || K_dst < 1 || K_dst > sx::kMaxCells)
+    return fail(SX_EINVAL, "cell counts %d, %d outside 1..%d", K_src, K_dst, sx::kMaxCells);
+  if (!src_counts || !src || !dst) return fail(SX_EINVAL, "null argument");
+  int64_t off[sx::kMaxCells + 1];
+  off[0] = 0;
+  for (int c = 0; c < K_src; ++c) {
+    if (src_counts[c] < 0) return fail(SX_EINVAL, "negative count in source cell %d", c);
+    if (src_counts[c] > 0 && !src[c]) return fail(SX_EINVAL, "source cell %d is NULL", c);
+    off[c + 1] = off[c] + src_counts[c];
+  }
+  if (off[K_src] >= (int64_t(1) << 31)) return fail(SX_EINVAL, "too many rows");
+  if (off[K_src] > 0 && (!dst_cell || !dst_index)) return fail(SX_EINVAL, "null mapping");
+  for (int c = 0; c < K_dst; ++c)
+    if (!dst[c]) return fail(SX_EINVAL, "destination cell %d is NULL", c);
+  return dev(sx::launch_move_rows(off[K_src], row_floats, K_src, off, src, K_dst, dst, dst_cell,
+                                  dst_index, (hipStream_t)stream),
+             "sx_move_rows");
 }
 
 sx_status sx_visibility(int32_t K, const sx_cell* cells, const sx_camera* cam, uint32_t* masks,

@@ -298,6 +298,11 @@ hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams&
                                    hipStream_t st);
 // host: KD-tree partition of n means [n*3] into K boxes lo/hi [K*3], cell_of [n]
 void kd_partition(int64_t n, const float* means, int K, float* lo, float* hi, int32_t* cell_of);
+void repartition_plan(int64_t n, const int32_t* cell_of, int K, int32_t* dst_index,
+                      int64_t* counts);
+hipError_t launch_move_rows(int64_t n, int row_floats, int k_src, const int64_t* src_off,
+                            const float* const* src, int k_dst, float* const* dst,
+                            const int32_t* dst_cell, const int32_t* dst_index, hipStream_t st);
 hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint32_t* masks,
                              hipStream_t st);
 hipError_t launch_cross_filter(const sx_gaussians& g, const sx_projected& proj, int K,

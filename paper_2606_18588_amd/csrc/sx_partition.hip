@@ -4,7 +4,8 @@
 // have the largest extent, at the quantile of the means that gives the two
 // halves their share of cells (the median when K is a power of two).  The
 // boxes are disjoint and cover space (the outermost bounds are infinite),
-// so the composition's per-ray order is exact for them.  Host code.
+// so the composition's per-ray order is exact for them.  Host code, plus
+// the device move of a repartition's rows.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -60,6 +61,60 @@ void split(const float* means, std::vector<int64_t>& idx, int64_t b, int64_t e, 
 }
 
 }  // namespace
+
+// Destination of every Gaussian of a repartition: dst_index[g] is g's rank
+// among the Gaussians of its new cell cell_of[g], in the order of g (so each
+// new cell keeps the relative order of its Gaussians); counts[k] the new
+// cell sizes.
+void repartition_plan(int64_t n, const int32_t* cell_of, int K, int32_t* dst_index,
+                      int64_t* counts) {
+  for (int k = 0; k < K; ++k) counts[k] = 0;
+  for (int64_t g = 0; g < n; ++g) dst_index[g] = (int32_t)counts[cell_of[g]]++;
+}
+
+// Row moves of a repartition: row g (global index over the source cells
+// laid end to end) of every array goes to row dst_index[g] of new cell
+// dst_cell[g].  One thread per (row, float4 or float).
+struct MoveArgs {
+  const float* src[kMaxCells];
+  float* dst[kMaxCells];
+  int64_t src_off[kMaxCells + 1];  // first global row of each source cell
+  int k_src;
+  int row_floats;
+  int64_t n;
+  const int32_t* dst_cell;
+  const int32_t* dst_index;
+};
+
+__global__ __launch_bounds__(256) void k_move_rows(MoveArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t g = t / a.row_floats;
+  const int f = (int)(t - g * a.row_floats);
+  if (g >= a.n) return;
+  int c = 0;
+  while (c + 1 < a.k_src && a.src_off[c + 1] <= g) ++c;
+  const int64_t i = g - a.src_off[c];
+  a.dst[a.dst_cell[g]][(int64_t)a.dst_index[g] * a.row_floats + f] =
+      a.src[c][i * a.row_floats + f];
+}
+
+hipError_t launch_move_rows(int64_t n, int row_floats, int k_src, const int64_t* src_off,
+                            const float* const* src, int k_dst, float* const* dst,
+                            const int32_t* dst_cell, const int32_t* dst_index, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  MoveArgs a{};
+  for (int c = 0; c < k_src; ++c) a.src[c] = src[c];
+  for (int c = 0; c <= k_src; ++c) a.src_off[c] = src_off[c];
+  for (int c = 0; c < k_dst; ++c) a.dst[c] = dst[c];
+  a.k_src = k_src;
+  a.row_floats = row_floats;
+  a.n = n;
+  a.dst_cell = dst_cell;
+  a.dst_index = dst_index;
+  const int64_t threads = n * row_floats;
+  hipLaunchKernelGGL(k_move_rows, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
 
 void kd_partition(int64_t n, const float* means, int K, float* lo, float* hi, int32_t* cell_of) {
   std::vector<int64_t> idx((size_t)n);

@@ -94,6 +94,47 @@ def _count_stream(device) -> torch.cuda.Stream:
     return s
 
 
+REPARTITION_THRESHOLD = 0.2  # the paper's trigger on N_max / mean(N) - 1
+
+
+def imbalance(cells: Sequence["GaussianParams"]) -> float:
+    """Load imbalance N_max / mean(N) - 1 of the cells' Gaussian counts."""
+    return B.sx_imbalance([c.n for c in cells])
+
+
+def repartition(cells: Sequence["GaussianParams"], K: int = None, states=None):
+    """New KD-tree cells over all Gaussians of `cells` (the partition
+    strategy of the paper's appendix), with every Gaussian's parameter rows
+    (and the rows of `states`: per cell a list of tensors laid out like its
+    parameter arrays, e.g. Adam moments) moved to its new cell on the
+    device, keeping the Gaussians' relative order.  The means go to the host
+    for the KD split (12 bytes per Gaussian); nothing else leaves the GPU.
+    Returns (new cells, boxes as synth-style (lo, hi) tuples, new states)."""
+    K = len(cells) if K is None else int(K)
+    dev = cells[0].means.device
+    means = torch.cat([c.means for c in cells]).cpu().numpy()
+    boxes, cell_of = B.sx_kd_partition(means, K)
+    dst_index, counts = B.sx_repartition_plan(cell_of, K)
+    d_cell = torch.as_tensor(cell_of).to(dev)
+    d_index = torch.as_tensor(dst_index).to(dev)
+    src_counts = [c.n for c in cells]
+
+    def move(src):  # src: one tensor per old cell, rows of equal width
+        width = int(src[0][0].numel()) if src[0].shape[0] else int(np.prod(src[0].shape[1:]))
+        out = [torch.empty((max(int(n), 1),) + tuple(src[0].shape[1:]), dtype=src[0].dtype,
+                           device=dev) for n in counts]
+        B.sx_move_rows(width, src, src_counts, out, d_cell, d_index)
+        return [o[:int(n)] for o, n in zip(out, counts)]
+    arrays = [move([getattr(c, name) for c in cells])
+              for name in ("means", "log_scales", "quats", "opacity_logits", "sh")]
+    new_cells = [GaussianParams(*[arrays[a][k] for a in range(5)]) for k in range(K)]
+    new_states = None
+    if states is not None:
+        moved = [move([st[j] for st in states]) for j in range(len(states[0]))]
+        new_states = [[moved[j][k] for j in range(len(moved))] for k in range(K)]
+    return new_cells, boxes, new_states
+
+
 def tiles_of(cam, settings):
     tx = (cam.width + settings.tile_w - 1) // settings.tile_w
     ty = (cam.height + settings.tile_h - 1) // settings.tile_h

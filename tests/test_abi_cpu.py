@@ -224,3 +224,27 @@ def test_noalloc_backward_rejects_capacity_beyond_its_scratch(L):
                                         None)
     assert code == B.SX_EINVAL
     assert b"scratch" in L.sx_last_error_string()
+
+
+def test_imbalance_and_repartition_plan_match_the_oracle(L):
+    """Host parts of a repartition: the imbalance ratio against the
+    oracle's, and the plan (each Gaussian's row in its new cell) against
+    the oracle's redistribution of the global row indices."""
+    import numpy as np
+    import oracle
+    from paper_2606_18588_amd import binding as B
+    rng = np.random.default_rng(4)
+    cell_of = rng.integers(0, 5, size=1000).astype(np.int32)
+    counts = np.bincount(cell_of, minlength=5)
+    assert abs(B.sx_imbalance(counts) - oracle.imbalance(cell_of, 5)) < 1e-12
+    dst, cnt = B.sx_repartition_plan(cell_of, 5)
+    assert np.array_equal(cnt, counts)
+    moved = oracle.repartition([np.arange(1000)], cell_of, 5)
+    for k in range(5):
+        rows = np.nonzero(cell_of == k)[0]
+        assert np.array_equal(moved[k], rows)
+        assert np.array_equal(dst[rows], np.arange(len(rows)))
+    with pytest.raises(B.SplaxelError):
+        B.sx_repartition_plan(np.array([0, 5], np.int32), 5)
+    with pytest.raises(B.SplaxelError):
+        B.sx_imbalance([0, 0])

@@ -1023,6 +1023,34 @@ def test_projection_backward_alone_and_error_scale(orc):
     assert r["nblend"].sum() > 0
 
 
+def test_repartition_redistribution_by_brute_force(orc):
+    """The oracle's redistribution equals a row-by-row placement: every old
+    row appended, in order, to the list of its new cell; rows are neither
+    lost nor duplicated."""
+    rng = np.random.default_rng(8)
+    cells = [rng.normal(size=(n, 3)) for n in (5, 0, 9, 4)]
+    cell_of = rng.integers(0, 3, size=18)
+    got = orc.repartition(cells, cell_of, 3)
+    lists = [[], [], []]
+    g = 0
+    for a in cells:
+        for row in a:
+            lists[cell_of[g]].append(row)
+            g += 1
+    for k in range(3):
+        ref = np.array(lists[k]).reshape(-1, 3)
+        assert np.array_equal(got[k], ref), k
+    assert sum(len(x) for x in got) == 18
+
+
+def test_imbalance_ratio_closed_form(orc):
+    """N_max / mean(N) - 1: zero for equal counts; 3 of 4 Gaussians in one
+    of two cells: 3 / 2 - 1 = 0.5."""
+    assert orc.imbalance([0, 1, 0, 1], 2) == 0.0
+    assert orc.imbalance([0, 0, 0, 1], 2) == 0.5
+    assert abs(orc.imbalance([0] * 6 + [1] * 2 + [2] * 2, 3) - (6 / (10 / 3) - 1)) < 1e-15
+
+
 # ------------------------------------------------------------- harness ----
 def test_l1_and_adam_match_torch(orc):
     import torch
