@@ -266,6 +266,13 @@ sx_status sx_move_rows(int32_t row_floats, int32_t K_src, const int64_t* src_cou
 sx_status sx_visibility(int32_t K, const sx_cell* cells, const sx_camera* cam,
                         uint32_t* masks, sx_stream stream);
 
+/* Pixels per cell of K mask rows of `words` uint32 words each (the layout
+ * of sx_visibility): counts[m] (device, K uint32) = set bits of row m.  The
+ * cells with a non-empty geometric map are a view's participants, the set
+ * the paper's view bucketing (Sec. 4.4, GetParticipants) schedules by. */
+sx_status sx_mask_counts(int32_t K, const uint32_t* masks, int64_t words, uint32_t* counts,
+                         sx_stream stream);
+
 /* Per-ray cross-boundary filter (appendix, implementation details:
  * cross-boundary Gaussians).  A Gaussian assigned to cell k by its mean
  * whose spatial support reaches into cell s is removed from the ray of
@@ -495,12 +502,15 @@ sx_status sx_fill_u32(uint32_t* ptr, int64_t n, uint32_t value,
  * Batched views.  The paper spreads the views of a training batch over
  * GPUs and groups views whose participant cells do not overlap (Sec. 4.4,
  * view bucketing); on one GPU the views of a batch share the device, so the
- * batched calls below run the per-view stages of up to SX_MAX_VIEWS views of
- * ONE cell in one launch each: workgroup b takes the b-th (view, tile) work
- * item, the views' tile grids laid end to end, each in raster order.
- * Results are bit-identical to the per-view calls (every work item owns its
- * pixels; the per-Gaussian gradient rows of each view are reduced
- * separately). */
+ * batched calls below run the per-view stages of up to SX_MAX_VIEWS items in
+ * one launch each: workgroup b takes the b-th (item, tile) work unit, the
+ * items' tile grids laid end to end, each in raster order.  An item is one
+ * view of one cell; the items of a render or render-backward launch may
+ * belong to different cells (each carries its cell's projection, sort and,
+ * for the backward, Gaussian count), which is how a bucket of views with
+ * disjoint participant cells runs in one launch.  Results are
+ * bit-identical to the per-view calls (every work item owns its pixels;
+ * the per-Gaussian gradient rows of each item are reduced separately). */
 #define SX_MAX_VIEWS 16
 
 /* One view of a batched call.  Every pointer refers to that view's buffers
@@ -520,6 +530,8 @@ typedef struct sx_view {
   const float* dpartial;       /* backward: [H*W*4] upstream gradient   */
   float* g2d;                  /* backward: [n*12] screen gradients     */
   void* bwd_ws;                /* backward: sx_backward_workspace_size  */
+  int64_t n;                   /* backward: Gaussians of this item's
+                                  cell, or 0 for the call's n           */
 } sx_view;
 
 /* Preprocess of one cell's Gaussians for V views in one launch (Eq. 1
@@ -543,9 +555,10 @@ sx_status sx_render_multi(int32_t V, const sx_view* views,
                           const sx_params* p, void* ws, size_t ws_bytes,
                           sx_stream stream);
 
-/* Render backward (Eq. 6-7 through each view's local render) of V views of
- * one cell of n Gaussians in one launch, then each view's
- * per-Gaussian reduction into views[v].g2d; each view needs every member.
+/* Render backward (Eq. 6-7 through each item's local render) of V items in
+ * one launch, then each item's per-Gaussian reduction into views[v].g2d;
+ * each item needs every member; an item's cell has views[v].n Gaussians,
+ * or n when that member is 0.
  * Follow with sx_preprocess_backward_multi (or sx_preprocess_backward per
  * view) to sum the views' parameter gradients. */
 sx_status sx_render_backward_multi(int32_t V, const sx_view* views, int64_t n,

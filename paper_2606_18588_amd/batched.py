@@ -250,3 +250,172 @@ def autotune(params: GaussianParams, grads: GaussianParams, cams, targets, make_
         torch.cuda.empty_cache()
     out.sort(key=lambda r: r.ms)
     return out
+
+
+# ------------------------------------------------------------------ K > 1 --
+def bucket_views(participants: Sequence[set]) -> List[List[int]]:
+    """Conflict-free view bucketing (Sec. 4.4, view consolidation): the
+    views in order, each put into the first bucket whose cells are disjoint
+    from its participant cells (that bucket then holds those cells too), or
+    into a new bucket when every existing one conflicts.  Views in a bucket
+    never touch the same cell."""
+    buckets: List[List[int]] = []
+    used: List[set] = []
+    for v, parts in enumerate(participants):
+        for b, u in zip(buckets, used):
+            if not (u & parts):
+                b.append(v)
+                u |= parts
+                break
+        else:
+            buckets.append([v])
+            used.append(set(parts))
+    return buckets
+
+
+def item_struct(v: CellView, mask, n: int, backward: bool) -> B.SxView:
+    """One (view, cell) work item of a batched launch."""
+    s = B.SxView()
+    s.cam = v.c_cam
+    s.proj = v.c_proj
+    s.vals = B.ptr(v.vals)
+    s.tile_ranges = B.ptr(v.ranges)
+    s.sort_ws = B.ptr(v.ws)
+    s.capacity = v.capacity
+    s.mask = B.ptr(mask)
+    s.partial = B.ptr(v.partial)
+    s.depth = None
+    s.last = B.ptr(v.last)
+    s.nblend = B.ptr(v.nblend)
+    s.n = n
+    if backward:
+        v.ensure_backward_buffers()
+        s.dpartial = B.ptr(v.dpartial)
+        s.g2d = B.ptr(v.g2d)
+        s.bwd_ws = B.ptr(v.bwd_ws)
+    return s
+
+
+class BucketedCells:
+    """K = 8-style training over V views of a scene split into K cells,
+    scheduled by conflict-free view bucketing (Sec. 4.4).  A view's
+    participants are the cells whose geometric visibility map is non-empty
+    (sx_mask_counts of sx_visibility); views are bucketed so that the views
+    of a bucket share no cell.  Per bucket: every (view, participant cell)
+    item is projected and sorted (the sorts on side streams), one render
+    launch covers all items' tiles, each view is composed with its L1 loss
+    and composition backward (sx_composite_l1; a cell outside the view's
+    participants holds the identity partial, rendered once with an empty
+    mask), and one render-backward launch covers all items.  Finally every
+    cell's parameter gradient sums its items over the views in view order
+    (sx_preprocess_backward_multi).  Masks start from the geometric maps and
+    are cleared by saturation, as in Frame.train_l1; the results equal the
+    per-view frames' bit for bit."""
+
+    def __init__(self, cells: Sequence[GaussianParams], boxes, cams, settings, margin=1.1,
+                 streams: int = 4, device="cuda"):
+        from .pipeline import Frame
+        self.cells = list(cells)
+        self.K = len(self.cells)
+        self.frames = [Frame(self.cells, boxes, c, settings, device=device) for c in cams]
+        self.c_par = self.frames[0].c_par
+        counts = torch.empty((self.K,), dtype=torch.int32, device=device)
+        self.participants = []
+        for f in self.frames:
+            f.init_masks(geometric=True)
+            B.sx_mask_counts(f.masks, counts)
+            self.participants.append({m for m, c in enumerate(counts.tolist()) if c > 0})
+        self.buckets = bucket_views(self.participants)
+        # size every item's buffers from one synchronous pass; cells outside a
+        # view render the identity once (their masks are empty and stay so)
+        for f in self.frames:
+            f.forward(use_masks=True, sync=True)
+            for v in f.views:
+                v._alloc_sort(int(v.counts[1] * margin) + 4096)
+                v.ensure_backward_buffers()
+        self.margin = margin
+        self.side = [torch.cuda.Stream(device=device) for _ in range(streams)] if streams else None
+        need = 1
+        for b in self.buckets:
+            cams_b = [self.frames[vi].c_cam for vi, _ in self.items(b)]
+            if cams_b:
+                need = max(need, B.sx_multi_workspace_size(cams_b, self.c_par))
+        self.ws = torch.empty((need,), dtype=torch.uint8, device=device)
+        self.t = 0
+        self.regrown = 0
+
+    def items(self, views: Sequence[int]):
+        return [(vi, m) for vi in views for m in sorted(self.participants[vi])]
+
+    def _watch_counts(self):
+        """The previous step's posted instance counts: an overflow raises;
+        items within 5% of their capacity get larger buffers."""
+        grow = []
+        for f in self.frames:
+            for m, v in enumerate(f.views):
+                if v._counts_ev is None:
+                    continue
+                vis, inst, over = v.poll_counts()
+                if over:
+                    raise RuntimeError(f"cell {m}: {inst} instances overflowed its capacity")
+                if inst * 1.05 > v.capacity:
+                    grow.append((v, inst))
+        if grow:
+            torch.cuda.synchronize()
+            for v, inst in grow:
+                v._alloc_sort(int(inst * self.margin) + 4096)
+                v.ensure_backward_buffers()
+            self.regrown += 1
+
+    def step(self, targets, grads: Sequence[GaussianParams], count_blends=False):
+        """Forward, L1 against targets[view], backward of every view; the
+        cells' gradients are overwritten with the sums.  Returns the blend
+        count when asked (one read-back per item)."""
+        if self.t > 0:
+            self._watch_counts()
+        blends = 0
+        for b in self.buckets:
+            items = self.items(b)
+            jobs = []
+            for vi, m in items:
+                v = self.frames[vi].views[m]
+                jobs.append(lambda v=v: (v.preprocess(), v.sort(sync=False)))
+            run_on_streams(self.side, jobs)
+            # the renders read a copy of the masks the compositions update
+            for vi in b:
+                f = self.frames[vi]
+                if f._masks_fwd is None:
+                    f._masks_fwd = torch.empty_like(f.masks)
+                f._masks_fwd.copy_(f.masks)
+            fwd = [item_struct(self.frames[vi].views[m], self.frames[vi]._masks_fwd[m],
+                               self.cells[m].n, False) for vi, m in items]
+            if fwd:
+                B.sx_render_multi(fwd, self.c_par, self.ws)
+            for vi in b:
+                f = self.frames[vi]
+                B.sx_composite_l1([v.partial for v in f.views], f.boxes, f.c_cam, f.c_par,
+                                  targets[vi], f.out, f.masks, None,
+                                  [v.dpartial for v in f.views])
+            bwd = [item_struct(self.frames[vi].views[m], self.frames[vi]._masks_fwd[m],
+                               self.cells[m].n, True) for vi, m in items]
+            if bwd:
+                B.sx_render_backward_multi(bwd, 0, self.c_par, self.ws)
+            if count_blends:
+                blends += sum(int(self.frames[vi].views[m].nblend.sum().item())
+                              for vi, m in items)
+        for m in range(self.K):
+            its = [(vi, m) for vi in range(len(self.frames)) if m in self.participants[vi]]
+            g = grads[m]
+            if not its:
+                for t in g.tensors():
+                    B.sx_fill_u32(t, 0)
+                continue
+            for k in range(0, len(its), B.SX_MAX_VIEWS):
+                chunk = its[k:k + B.SX_MAX_VIEWS]
+                st = [item_struct(self.frames[vi].views[mm], self.frames[vi]._masks_fwd[mm],
+                                  self.cells[mm].n, True) for vi, mm in chunk]
+                B.sx_preprocess_backward_multi(self.cells[m].struct(), st, self.c_par,
+                                               g.grad_struct(),
+                                               B.SX_BWD_ACCUMULATE if k else 0)
+        self.t += 1
+        return blends

@@ -76,7 +76,8 @@ class SxView(ctypes.Structure):
     _fields_ = [("cam", SxCamera), ("proj", SxProjected), ("vals", c_p),
                 ("tile_ranges", c_p), ("sort_ws", c_p), ("capacity", c_i64),
                 ("mask", c_p), ("partial", c_p), ("depth", c_p), ("last", c_p),
-                ("nblend", c_p), ("dpartial", c_p), ("g2d", c_p), ("bwd_ws", c_p)]
+                ("nblend", c_p), ("dpartial", c_p), ("g2d", c_p), ("bwd_ws", c_p),
+                ("n", c_i64)]
 
 
 SX_MAX_VIEWS = 16
@@ -92,6 +93,7 @@ EXPORTS = (
     "sx_render_backward_stages", "sx_visibility", "sx_kd_partition",
     "sx_composite_reeval", "sx_cross_filter", "sx_composite_l1",
     "sx_render_backward_noalloc", "sx_imbalance", "sx_repartition_plan", "sx_move_rows",
+    "sx_mask_counts",
 )
 SX_NOALLOC_SCRATCH_BYTES = 64 << 20  # the static scratch of sx_render_backward_noalloc
 
@@ -429,6 +431,13 @@ def sx_move_rows(row_floats: int, src: Sequence[torch.Tensor], src_counts,
     _check("sx_move_rows", lib().sx_move_rows(
         c_i32(row_floats), c_i32(len(src)), sc, ptr_array(src), c_i32(len(dst)),
         ptr_array(dst), ptr(dst_cell), ptr(dst_index), stream_handle(stream)))
+
+
+def sx_mask_counts(masks: torch.Tensor, counts: torch.Tensor, stream=None) -> None:
+    """counts[m] = set bits of row m of masks [K, words]."""
+    K, words = masks.shape
+    _check("sx_mask_counts", lib().sx_mask_counts(c_i32(K), ptr(masks), c_i64(words),
+                                                  ptr(counts), stream_handle(stream)))
 
 
 def sx_visibility(cells, cam: SxCamera, masks, stream=None) -> None:

@@ -264,6 +264,14 @@ sx_status sx_move_rows(int32_t row_floats, int32_t K_src, const int64_t* src_cou
              "sx_move_rows");
 }
 
+sx_status sx_mask_counts(int32_t K, const uint32_t* masks, int64_t words, uint32_t* counts,
+                         sx_stream stream) {
+  if (K < 1 || K > sx::kMaxCells) return fail(SX_EINVAL, "K=%d outside 1..%d", K, sx::kMaxCells);
+  if (words < 0) return fail(SX_EINVAL, "words < 0");
+  if (!counts || (words > 0 && !masks)) return fail(SX_EINVAL, "null argument");
+  return dev(sx::launch_mask_counts(K, masks, words, counts, (hipStream_t)stream), "sx_mask_counts");
+}
+
 sx_status sx_visibility(int32_t K, const sx_cell* cells, const sx_camera* cam, uint32_t* masks,
                         sx_stream stream) {
   SX_TRY(check_cam(cam));
@@ -547,6 +555,7 @@ static void to_multi(int32_t V, const sx_view* views, const sx_params* p, sx::Mu
     m.partial = w.partial, m.depth = w.depth, m.last = w.last, m.nblend = w.nblend;
     m.sort_ws = w.sort_ws, m.capacity = w.capacity;
     m.dpartial = w.dpartial, m.g2d = w.g2d, m.bwd_ws = w.bwd_ws;
+    m.n = w.n;
   }
 }
 
@@ -608,11 +617,15 @@ sx_status sx_render_backward_multi(int32_t V, const sx_view* views, int64_t n, c
   if (ws_bytes < need) return fail(SX_EINVAL, "workspace %zu bytes < required %zu", ws_bytes, need);
   sx::MultiView mv[sx::kMaxViews];
   to_multi(V, views, p, mv);
+  for (int v = 0; v < V; ++v) {
+    if (mv[v].n < 0 || mv[v].n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "view %d: n out of range", v);
+    if (mv[v].n == 0) mv[v].n = n;
+  }
   const sx::KParams kp = sx::make_kparams(*p, views[0].cam);
-  SX_TRY(dev(sx::launch_render_backward_multi(V, mv, n, kp, static_cast<char*>(ws), (hipStream_t)stream),
+  SX_TRY(dev(sx::launch_render_backward_multi(V, mv, kp, static_cast<char*>(ws), (hipStream_t)stream),
              "sx_render_backward_multi"));
   for (int v = 0; v < V; ++v)
-    SX_TRY(dev(sx::launch_grad_reduce_view(mv[v], n, kp, (hipStream_t)stream), "sx_render_backward_multi"));
+    SX_TRY(dev(sx::launch_grad_reduce_view(mv[v], kp, (hipStream_t)stream), "sx_render_backward_multi"));
   return SX_OK;
 }
 

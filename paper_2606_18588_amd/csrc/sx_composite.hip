@@ -389,6 +389,31 @@ hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint3
   return hipGetLastError();
 }
 
+// Set bits per row of K mask rows of `words` words (a cell's visible pixels
+// in a geometric map): one row per grid row, a wavefront sum per block and
+// one integer atomic per block (the order of the integer sums is free).
+__global__ __launch_bounds__(256) void k_mask_counts(const uint32_t* __restrict__ masks,
+                                                     int64_t words, uint32_t* counts) {
+  const int m = blockIdx.y;
+  uint32_t c = 0;
+  for (int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x; w < words;
+       w += (int64_t)gridDim.x * 256)
+    c += __popc(masks[(int64_t)m * words + w]);
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(&counts[m], c);
+}
+
+hipError_t launch_mask_counts(int K, const uint32_t* masks, int64_t words, uint32_t* counts,
+                              hipStream_t st) {
+  hipError_t e = launch_fill(counts, K, 0, st);
+  if (e != hipSuccess || words == 0) return e;
+  int64_t bx = (words + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_mask_counts, dim3((unsigned)bx, (unsigned)K), dim3(256), 0, st, masks,
+                     words, counts);
+  return hipGetLastError();
+}
+
 template <bool RE>
 static void launch_comp_k(int K, dim3 grid, const CompArgs& a, hipStream_t st) {
   if (K <= 1)

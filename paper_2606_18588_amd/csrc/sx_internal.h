@@ -288,14 +288,14 @@ struct MultiView {
   const float* dpartial;
   float* g2d;
   void* bwd_ws;
+  int64_t n;  // Gaussians of the item's cell
 };
 size_t multi_workspace_bytes(int64_t items);
 hipError_t launch_render_multi(int V, const MultiView* mv, const KParams& p, char* ws,
                                hipStream_t st);
-hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, const KParams& p,
+hipError_t launch_render_backward_multi(int V, const MultiView* mv, const KParams& p,
                                         char* ws, hipStream_t st);
-hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams& p,
-                                   hipStream_t st);
+hipError_t launch_grad_reduce_view(const MultiView& v, const KParams& p, hipStream_t st);
 // host: KD-tree partition of n means [n*3] into K boxes lo/hi [K*3], cell_of [n]
 void kd_partition(int64_t n, const float* means, int K, float* lo, float* hi, int32_t* cell_of);
 void repartition_plan(int64_t n, const int32_t* cell_of, int K, int32_t* dst_index,
@@ -303,6 +303,8 @@ void repartition_plan(int64_t n, const int32_t* cell_of, int K, int32_t* dst_ind
 hipError_t launch_move_rows(int64_t n, int row_floats, int k_src, const int64_t* src_off,
                             const float* const* src, int k_dst, float* const* dst,
                             const int32_t* dst_cell, const int32_t* dst_index, hipStream_t st);
+hipError_t launch_mask_counts(int K, const uint32_t* masks, int64_t words, uint32_t* counts,
+                              hipStream_t st);
 hipError_t launch_visibility(int K, const sx_cell* cells, const DCam& cam, uint32_t* masks,
                              hipStream_t st);
 hipError_t launch_cross_filter(const sx_gaussians& g, const sx_projected& proj, int K,

@@ -756,7 +756,7 @@ hipError_t launch_render_multi(int V, const MultiView* mv, const KParams& p, cha
   return hipGetLastError();
 }
 
-hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, const KParams& p,
+hipError_t launch_render_backward_multi(int V, const MultiView* mv, const KParams& p,
                                         char* ws, hipStream_t st) {
   (void)ws;
   RenderBwdMultiArgs m;
@@ -764,7 +764,7 @@ hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, c
   for (int v = 0; v < V; ++v) {
     KParams pv = p;
     pv.tiles_x = mv[v].tiles_x, pv.tiles_y = mv[v].tiles_y;
-    const SortView sv = sort_view(mv[v].sort_ws, n, mv[v].capacity, pv.tiles_x, pv.tiles_y);
+    const SortView sv = sort_view(mv[v].sort_ws, mv[v].n, mv[v].capacity, pv.tiles_x, pv.tiles_y);
     m.view[v] = make_bwd_args(mv[v].proj, mv[v].vals, mv[v].ranges, sv, mv[v].capacity,
                               mv[v].cam, pv, mv[v].mask, mv[v].partial, mv[v].last,
                               mv[v].dpartial, nullptr, static_cast<char*>(mv[v].bwd_ws));
@@ -775,12 +775,11 @@ hipError_t launch_render_backward_multi(int V, const MultiView* mv, int64_t n, c
   return hipGetLastError();
 }
 
-hipError_t launch_grad_reduce_view(const MultiView& v, int64_t n, const KParams& p,
-                                   hipStream_t st) {
+hipError_t launch_grad_reduce_view(const MultiView& v, const KParams& p, hipStream_t st) {
   KParams pv = p;
   pv.tiles_x = v.tiles_x, pv.tiles_y = v.tiles_y;
-  return launch_bwd_reduce(v.proj, sort_view(v.sort_ws, n, v.capacity, pv.tiles_x, pv.tiles_y),
-                           n, v.capacity, pv, v.g2d, static_cast<char*>(v.bwd_ws), st);
+  return launch_bwd_reduce(v.proj, sort_view(v.sort_ws, v.n, v.capacity, pv.tiles_x, pv.tiles_y),
+                           v.n, v.capacity, pv, v.g2d, static_cast<char*>(v.bwd_ws), st);
 }
 
 }  // namespace sx

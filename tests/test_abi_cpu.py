@@ -248,3 +248,12 @@ def test_imbalance_and_repartition_plan_match_the_oracle(L):
         B.sx_repartition_plan(np.array([0, 5], np.int32), 5)
     with pytest.raises(B.SplaxelError):
         B.sx_imbalance([0, 0])
+
+
+def test_bucket_views_greedy_first_fit():
+    """Sec. 4.4's scheduler: each view joins the first bucket with no cell in
+    common, else opens a new one."""
+    from paper_2606_18588_amd.batched import bucket_views
+    parts = [{0, 1}, {2}, {1, 3}, {0}, {3}, set(), {2, 4}]
+    assert bucket_views(parts) == [[0, 1, 4, 5], [2, 3, 6]]
+    assert bucket_views([{0}, {0}, {0}]) == [[0], [1], [2]]

@@ -12,6 +12,7 @@ in a fixed order), and the views' parameter gradients are added in view
 order.
 """
 import math
+from dataclasses import replace as dataclasses_replace
 
 import numpy as np
 import pytest
@@ -409,3 +410,68 @@ def test_server_overflow_requeue_and_admission(torch_gpu):
         assert_same(_np(small.images[r.rid]), _np(ref.images[r.rid]), f"request {r.rid}")
     lat = [d.latency_s for d in done]
     assert min(lat) >= 0.0
+
+
+# ------------------------------------------------- K > 1: view bucketing --
+def test_bucketed_cells_bit_identical_to_per_view_frames(torch_gpu):
+    """Eight nadir views over a cube scene split into a 4 x 2 grid of cells:
+    the views are bucketed by disjoint participant cells, each bucket runs
+    one render and one render-backward launch over its (view, cell) items;
+    images, saturation masks and every cell's gradients over two steps equal
+    the per-view K-cell frames bit for bit, and one view matches the
+    oracle."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.batched import BucketedCells
+    from paper_2606_18588_amd.pipeline import Frame, GaussianParams
+    print("case: bucketed K=8 cells vs per-view frames", flush=True)
+    scene = synth.make_cube_scene(23, 12000, log_scale=(-3.6, 0.5))
+    xe, ye = (-1.0, -0.5, 0.0, 0.5, 1.0), (-1.0, 0.0, 1.0)
+    part = synth.grid_partition(scene, xe, ye)
+    scenes = part.cell_scenes(scene)
+    # the prisms clipped to the scene's height: a steep ray then meets only
+    # the cells under its footprint, so views over different spots share no
+    # cell
+    boxes = [synth.Cell((c.lo[0], c.lo[1], -1.2), (c.hi[0], c.hi[1], 1.2)) for c in part.cells]
+    st = dataclasses_replace(ST, t_min=0.05)  # saturation clears bits within the test
+    spots = [(-0.75, -0.5), (0.75, 0.5), (-0.75, 0.5), (0.75, -0.5), (-0.25, -0.5),
+             (0.25, 0.5), (0.0, 0.0), (0.25, -0.5)]
+    cams = [synth.nadir_camera((x, y, 2.2), 72, 56, hfov_deg=18.0) for x, y in spots]
+    targets = [torch.as_tensor(synth.random_image(60 + k, c.width, c.height)).cuda()
+               for k, c in enumerate(cams)]
+    cells_a = [GaussianParams.from_scene(s) for s in scenes]
+    cells_b = [GaussianParams.from_scene(s) for s in scenes]
+    bc = BucketedCells(cells_a, boxes, cams, st)
+    print("participants", bc.participants, "buckets", bc.buckets, flush=True)
+    assert len(bc.buckets) < len(cams) and max(len(b) for b in bc.buckets) >= 2
+    frames = [Frame(cells_b, boxes, c, st) for c in cams]
+    for f in frames:
+        f.init_masks(geometric=True)
+    ga = [c.zeros_like() for c in cells_a]
+    gb = [c.zeros_like() for c in cells_b]
+    for step in range(2):
+        bc.step(targets, ga)
+        for g in gb:
+            for t in g.tensors():
+                t.zero_()
+        for f, tg in zip(frames, targets):
+            f.train_l1(tg, gb, accumulate=True, use_masks=True, update_masks=True, sync=True)
+        torch.cuda.synchronize()
+        for k, (fa, fb) in enumerate(zip(bc.frames, frames)):
+            assert_same(_np(fa.out), _np(fb.out), f"step {step} image {k}")
+            assert_same(_np(fa.masks), _np(fb.masks), f"step {step} masks {k}")
+        for m in range(len(scenes)):
+            for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+                assert_same(_np(getattr(ga[m], name)), _np(getattr(gb[m], name)),
+                            f"step {step} cell {m} {name}")
+    assert any(np.abs(_np(g.means)).max() > 0 for g in ga)
+    # the first step's image of view 0 against the oracle (geometric masks)
+    vis = oracle.visibility(boxes, cams[0])["vis"]
+    ref = oracle.forward(scenes, boxes, cams[0], st, masks=vis)
+    fl = ref.comp["flags"].copy()
+    for p in ref.parts:
+        fl |= p["flags"]
+    bc2 = BucketedCells([GaussianParams.from_scene(s) for s in scenes], boxes, cams[:1], st)
+    bc2.step(targets[:1], [c.zeros_like() for c in cells_a])
+    torch.cuda.synchronize()
+    compare_image(_np(bc2.frames[0].out)[..., :3], ref.comp["rgb"], fl, 1e-4,
+                  len(scenes) * jump_bound(st, 1.5))
