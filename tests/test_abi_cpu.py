@@ -61,12 +61,13 @@ def test_size_queries(L):
     a = B.sx_sort_workspace_size(1000, 5000, 8, 8)
     b = B.sx_sort_workspace_size(1000, 50000, 8, 8)
     assert 0 < a < b
-    # per instance: one bin list of 4 bytes for grids of two levels, two
-    # from three levels on (plus a little segment bookkeeping)
+    # per instance: 16 bytes of per-tile (depth, index) lists and their
+    # merge buffer, one inner bin list of 4 bytes for grids of two levels,
+    # two from three levels on (plus a little segment bookkeeping)
     c = B.sx_sort_workspace_size(1000, 50000, 241, 136)
     d = B.sx_sort_workspace_size(1000, 60000, 241, 136)
-    assert 8 * 10000 <= d - c <= 9 * 10000
-    assert 4 * 10000 <= b - a <= 5 * 45000
+    assert 24 * 10000 <= d - c <= 25 * 10000
+    assert 20 * 45000 <= b - a <= 21 * 45000
     # one 40-byte gradient row per instance and a word per tile
     c = B.sx_backward_workspace_size(5000, 64)
     assert 5000 * 40 <= c <= 5000 * 40 + 64 * 4 + 512
