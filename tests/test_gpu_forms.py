@@ -475,3 +475,44 @@ def test_bucketed_cells_bit_identical_to_per_view_frames(torch_gpu):
     torch.cuda.synchronize()
     compare_image(_np(bc2.frames[0].out)[..., :3], ref.comp["rgb"], fl, 1e-4,
                   len(scenes) * jump_bound(st, 1.5))
+
+
+def test_autotuner_times_the_grid_and_leaves_the_model_unchanged(torch_gpu):
+    """The batched step's autotuner times every (tile shape, views per
+    launch) pair that fits the memory budget, returns them fastest first,
+    and restores the parameters after each trial; a budget below some
+    arenas drops those pairs.  The fastest pair's batched step gives the
+    same gradients, bit for bit, as the plain per-view step with its tile
+    shape."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.batched import MultiViewStep, autotune
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    print("case: autotuner", flush=True)
+    scene = synth.tiny_scene(seed=13, n=3000)
+    cams = _orbit_cams()
+    targets = [torch.as_tensor(synth.random_image(80 + k, c.width, c.height)).cuda()
+               for k, c in enumerate(cams)]
+    params = GaussianParams.from_scene(scene)
+    grads = params.zeros_like()
+    before = [t.clone() for t in params.tensors()]
+    mk = lambda tw, th: synth.RenderSettings(tile_w=tw, tile_h=th)
+    res = autotune(params, grads, cams, targets, mk, tiles=("16x16", "32x8"), batches=(1, 3),
+                   reps=1)
+    assert sorted((r.tile, r.batch) for r in res) == [("16x16", 1), ("16x16", 3), ("32x8", 1),
+                                                    ("32x8", 3)]
+    assert [r.ms for r in res] == sorted(r.ms for r in res) and all(r.ms > 0 for r in res)
+    for a, b in zip(params.tensors(), before):
+        assert_same(_np(a), _np(b), "parameters after tuning")
+    small = MultiViewStep(params, grads, cams, targets, mk(16, 16), batch=1).arena_bytes
+    res2 = autotune(params, grads, cams, targets, mk, tiles=("16x16",), batches=(1, 3),
+                    mem_budget=small, reps=1)
+    assert [(r.tile, r.batch) for r in res2] == [("16x16", 1)]
+    # the tuned configuration trains like the plain per-view step
+    best = res[0]
+    tw, th = (int(x) for x in best.tile.split("x"))
+    ga, gb = params.zeros_like(), params.zeros_like()
+    MultiViewStep(params, ga, cams, targets, mk(tw, th), batch=best.batch).run(0.0, check=True)
+    MultiViewStep(params, gb, cams, targets, mk(tw, th), plain=True).run(0.0, check=True)
+    torch.cuda.synchronize()
+    for a, b in zip(ga.tensors(), gb.tensors()):
+        assert_same(_np(a), _np(b), "tuned vs plain gradients")
