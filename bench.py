@@ -27,8 +27,10 @@ plain per-view service (serve_p50_ms, serve_p99_ms, serve_30M).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
+import platform
 import sys
 import time
 
@@ -135,9 +137,39 @@ def cpu_baseline(scene, cam, settings, min_s=10.0, max_steps=20):
         blends += int(fr.parts[0]["nblend"].sum())
         steps += 1
     dt = time.perf_counter() - t0
+    # one thread on the 960x540 centre crop of the same view (the whole
+    # projection, a quarter of the pixels): a few seconds of work
+    w, h = cam.width // 2, cam.height // 2
+    x0, y0 = (cam.width - w) // 2, (cam.height - h) // 2
+    crop = dataclasses.replace(cam, cx=cam.cx - x0, cy=cam.cy - y0, width=w, height=h)
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        fr = oracle.forward([scene], [box], crop, settings)
+        _, g = oracle.l1_loss(fr.comp["rgb"], target[y0:y0 + h, x0:x0 + w])
+        oracle.backward([scene], [box], crop, settings, fr, g)
+        dt1 = time.perf_counter() - t1
+        b1 = int(fr.parts[0]["nblend"].sum())
+    finally:
+        oracle.set_threads(cores)
     return {"value": blends / dt, "unit": "blends/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} full steps: the 1920x1080 view of the 2M-Gaussian scene, "
-                      f"FP64 forward + L1 + backward, {blends} blends in {dt:.2f} s"}
+                      f"FP64 forward + L1 + backward, {blends} blends in {dt:.2f} s",
+            "single_thread": {"value": b1 / dt1, "unit": "blends/s", "cores": 1,
+                              "sample": f"one step on the {w}x{h} centre crop of the same "
+                                        f"view, {b1} blends in {dt1:.2f} s"},
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def main():
