@@ -68,6 +68,71 @@ __device__ __forceinline__ bool box_meets(float bxw, float byw, int x0, int x1, 
   const int bx0 = (int)(bx & 0xFFFFu), by0 = (int)(by & 0xFFFFu);
   return bx0 <= x1 && bx0 + (int)(bx >> 16) >= x0 && by0 <= y1 && by0 + (int)(by >> 16) >= y0;
 }
+// Rows of one tile column that a Gaussian's footprint can reach.  With
+// coordinates relative to the mean, the pixel centres of the column have
+// x in [X0, X1]; the result [y0, y1] (empty when y0 > y1) holds the y of
+// every such centre whose FP32 alpha test could pass.  The footprint
+// {q <= Q}, Q = 2 ln(o / alpha_min), meets the column in a convex set whose
+// highest point is the ellipse's own (where a x + b y = 0) if that lies in
+// the column and otherwise lies on an edge line x = X0 or x = X1, where
+// c y^2 + 2 b x y + a x^2 - Q = 0 gives it; likewise the lowest.  The
+// interval is the hull of those candidates.  Every approximation widens
+// it: Q is raised by 1e-3 (|Q| + 1) and by 1e-5 (|a| + 2|b| + |c|) r2 (r2 the
+// squared distance to the farthest tile corner; the pixel test's q has an
+// FP32 error below 1e-6 of that), the determinant a c - b^2 is lowered by
+// 1e-5 (|a c| + b^2) (a needle whose determinant rounding swamps gets the
+// whole column), and the ends are padded.  So the test never drops a pixel
+// the per-pixel alpha test would blend, and forward and backward, which
+// both apply it to the same rows, evaluate the same pairs.
+__device__ __forceinline__ float2 column_rows(float a, float b, float c, float o, float log_amin,
+                                              float X0, float X1, float r2) {
+  constexpr float kFar = 3e38f;
+  const float Q0 = 2.f * (__logf(o) - log_amin);  // v_log_f32: absolute error ~1e-7
+  const float Q = Q0 + 1e-3f * (fabsf(Q0) + 1.f) + 1e-5f * (fabsf(a) + 2.f * fabsf(b) + fabsf(c)) * r2;
+  if (!(Q >= 0.f)) return make_float2(kFar, -kFar);
+  const float det = a * c - b * b;
+  const float dlo = det - 1e-5f * (fabsf(a * c) + b * b);
+  if (!(dlo > 0.f) || !(a > 0.f) || !(c > 0.f)) return make_float2(-kFar, kFar);
+  // hardware square root and reciprocal (within 1 ulp), inside the margins
+  const float yf = __builtin_amdgcn_sqrtf(Q * a * __builtin_amdgcn_rcpf(dlo));
+  const float xt = -b * yf * __builtin_amdgcn_rcpf(a);  // highest point (xt, yf); lowest (-xt, -yf)
+  const float tol = 1e-3f * (1.f + fabsf(xt));
+  float ymax = (xt >= X0 - tol && xt <= X1 + tol) ? yf : -kFar;
+  float ymin = (-xt >= X0 - tol && -xt <= X1 + tol) ? -yf : kFar;
+  const float rc = __builtin_amdgcn_rcpf(c);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float xe = e ? X1 : X0;
+    const float disc = Q * c - dlo * xe * xe;
+    if (disc >= 0.f) {
+      const float sq = __builtin_amdgcn_sqrtf(disc);
+      ymax = fmaxf(ymax, (sq - b * xe) * rc);
+      ymin = fminf(ymin, (-sq - b * xe) * rc);
+    }
+  }
+  ymax += 1e-3f * (1.f + fabsf(ymax));
+  ymin -= 1e-3f * (1.f + fabsf(ymin));
+  return make_float2(ymin, ymax);
+}
+
+// column_rows for the column of tile (tx, ty) and the record's Gaussian.
+template <int TW, int TH>
+__device__ __forceinline__ float2 tile_column_rows(const float4& r0, const float4& r1, float cx,
+                                                   float cy, float log_amin, int tx, int ty) {
+  const float X0 = ((float)(tx * TW) + 0.5f - cx) - r0.x;
+  const float X1 = ((float)(tx * TW + TW - 1) + 0.5f - cx) - r0.x;
+  const float Y0 = ((float)(ty * TH) + 0.5f - cy) - r0.y;
+  const float Y1 = ((float)(ty * TH + TH - 1) + 0.5f - cy) - r0.y;
+  const float r2 = fmaxf(X0 * X0, X1 * X1) + fmaxf(Y0 * Y0, Y1 * Y1);
+  return column_rows(r0.z, r0.w, r1.x, r1.y, log_amin, X0, X1, r2);
+}
+
+// Pixel rows [py0, py1] (pixel centres) meet the interval.
+__device__ __forceinline__ bool rows_meet(float2 yr, int py0, int py1, float cy, float my) {
+  const float Y0 = ((float)py0 + 0.5f - cy) - my, Y1 = ((float)py1 + 0.5f - cy) - my;
+  return yr.x <= Y1 && yr.y >= Y0;
+}
+
 template <int TW, int TH, bool FILT = false>
 __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
                                             float4 (*s_rec)[3][64], uint32_t* s_xf = nullptr) {
@@ -86,6 +151,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
   const int wx0 = tx * TW, wx1 = wx0 + TW - 1;
   const int wy0 = ty * TH + w * WR, wy1 = wy0 + WR - 1;
   const uint2 rg = a.ranges[tile];
+  const float log_amin = __logf(a.alpha_min);
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   uint32_t lst = 0, nb = 0;
   bool done = !active;
@@ -101,7 +167,9 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
       s_rec[w][1][lane] = q1;
       s_rec[w][2][lane] = q2;
       if (FILT) s_xf[w * 64 + lane] = a.xf[gl];
-      meets = box_meets(q2.z, q2.w, wx0, wx1, wy0, wy1);
+      meets = box_meets(q2.z, q2.w, wx0, wx1, wy0, wy1) &&
+              rows_meet(tile_column_rows<TW, TH>(q0, q1, a.cx, a.cy, log_amin, tx, ty), wy0,
+                        wy1, a.cy, q0.y);
     }
     uint64_t todo = __ballot(meets);
     __builtin_amdgcn_wave_barrier();
@@ -219,6 +287,24 @@ __device__ __forceinline__ void wave_sum10_store(const float (&v)[10], float* ds
   }
 }
 
+// A gradient row holds, for one (Gaussian, tile) instance, the sums over its
+// blended pixels of h = -2 dL/dq times 1 (implicitly), dx, dy, dx^2, dx dy,
+// dy^2 in slots 0-4 (dx, dy = pixel centre - mean2d), then dL/do, dL/dc and
+// dL/dz.  Since q = a dx^2 + 2 b dx dy + c dy^2 with one conic per
+// Gaussian, the mean2d and conic gradients are linear in those moments:
+//   dL/dmean2d = (a Sx + b Sy, b Sx + c Sy),
+//   dL/d(a, b, c) = (-Sxx / 2, -Sxy, -Syy / 2),
+// so the walk accumulates five products per pair and the reduction applies
+// the conic once per Gaussian.
+__device__ __forceinline__ void row_to_g2d(float (&v)[10], float a, float b, float c) {
+  const float sx = v[0], sy = v[1];
+  v[0] = fmaf(a, sx, b * sy);
+  v[1] = fmaf(b, sx, c * sy);
+  v[2] *= -0.5f;
+  v[3] = -v[3];
+  v[4] *= -0.5f;
+}
+
 // Reverse walk of each pixel's blended pairs.  With R the colour behind pair
 // i (normalised by T_{i+1}), T_final the partial transmittance and
 // (G, g_T, g_D) the gradients of (C^m, T^m, D^m):
@@ -264,6 +350,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     }
   }
   if (wave_last == 0) return;  // nothing blended here: no pixel reads
+  const float log_amin = __logf(a.alpha_min);
   uint32_t pxy[PPT];  // pixel x | y << 16
   float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
   float gx[PPT], gy[PPT], gz[PPT], gd[PPT], gtf[PPT];
@@ -320,11 +407,13 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       s_rec[1][lane] = q1;
       s_rec[2][lane] = q2;
       if (FILT) s_xf[lane] = a.xf[gl];
+      const float2 yr = tile_column_rows<TW, TH>(q0, q1, a.cx, a.cy, log_amin, tx, ty);
 #pragma unroll
       for (int k = 0; k < PPT; ++k)
         mk[k] = (uint32_t)(j0 + lane) < gmax[k] &&
                 box_meets(q2.z, q2.w, tx * TW, tx * TW + TW - 1, ty * TH + k * WR,
-                          ty * TH + k * WR + WR - 1);
+                          ty * TH + k * WR + WR - 1) &&
+                rows_meet(yr, ty * TH + k * WR, ty * TH + k * WR + WR - 1, a.cy, q0.y);
       s_e[lane] = instance_row(a, gl, tx, ty);
     }
     uint64_t gm[PPT];
@@ -379,14 +468,14 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       T[k] = Ti;
       const float dae = use && !ae.clamped ? da : 0.f;  // alpha clamped: no o, q terms
       v[5] = fmaf(dae, ae.G, v[5]);
-      const float dq = -0.5f * al * dae;
-      const float m2 = -2.f * dq;
-      v[0] = fmaf(m2, fmaf(r0.z, dx, r0.w * dy), v[0]);
-      v[1] = fmaf(m2, fmaf(r0.w, dx, r1.x * dy), v[1]);
-      const float qx = dq * dx, qy = dq * dy;
-      v[2] = fmaf(qx, dx, v[2]);
-      v[3] = fmaf(qx + qx, dy, v[3]);
-      v[4] = fmaf(qy, dy, v[4]);
+      // h = -2 dL/dq; the row keeps the moments of h (see row_to_g2d)
+      const float h = al * dae;
+      const float hx = h * dx, hy = h * dy;
+      v[0] += hx;
+      v[1] += hy;
+      v[2] = fmaf(hx, dx, v[2]);
+      v[3] = fmaf(hx, dy, v[3]);
+      v[4] = fmaf(hy, dy, v[4]);
     }
     if (!any) {
       if (lane == 63 && in_cap) {
@@ -459,6 +548,7 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ ioff,
                                                      const uint32_t* __restrict__ n_tiles,
                                                      const float* __restrict__ rows, uint64_t cap,
+                                                     const float* __restrict__ rec,
                                                      float* __restrict__ g2d) {
   const int lane = threadIdx.x & 63;
   const uint64_t nvis = counts[0];
@@ -487,6 +577,8 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t* __restrict_
           acc[2 * q] += v.x, acc[2 * q + 1] += v.y;
         }
       }
+      const float* cg = rec + (size_t)g * kRecFloats;
+      row_to_g2d(acc, cg[2], cg[3], cg[4]);
       float4* d = reinterpret_cast<float4*>(g2d + (size_t)g * kG2dFloats);
       d[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       d[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
@@ -506,6 +598,10 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t* __restrict_
           v[2 * q] += x.x, v[2 * q + 1] += x.y;
         }
       }
+      // linear in the row sums, so applied to each lane's part before the
+      // cross-lane sum
+      const float* cg = rec + (size_t)gw * kRecFloats;
+      row_to_g2d(v, cg[2], cg[3], cg[4]);
       float* d = g2d + (size_t)gw * kG2dFloats;
       wave_sum10_store(v, d, lane, true);
       if (lane == 0) d[10] = 0.f, d[11] = 0.f;
@@ -682,7 +778,8 @@ static hipError_t launch_bwd_reduce(const sx_projected& proj, const SortView& sv
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_slot_reduce, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(256),
                        0, st, sv.vidx, sv.counts, sv.ioff, proj.n_tiles,
-                       reinterpret_cast<const float*>(bws + BL.rows), (uint64_t)capacity, g2d);
+                       reinterpret_cast<const float*>(bws + BL.rows), (uint64_t)capacity,
+                       proj.rec, g2d);
   }
   return hipGetLastError();
 }
