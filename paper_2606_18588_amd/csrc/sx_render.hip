@@ -115,17 +115,30 @@ __device__ __forceinline__ float2 column_rows(float a, float b, float c, float o
   return make_float2(ymin, ymax);
 }
 
-// column_rows for the column of tile (tx, ty) and the record's Gaussian.
-template <int TW, int TH>
-__device__ __forceinline__ float2 tile_column_rows(const float4& r0, const float4& r1, float cx,
-                                                   float cy, float log_amin, int tx, int ty) {
-  const float X0 = ((float)(tx * TW) + 0.5f - cx) - r0.x;
-  const float X1 = ((float)(tx * TW + TW - 1) + 0.5f - cx) - r0.x;
-  const float Y0 = ((float)(ty * TH) + 0.5f - cy) - r0.y;
-  const float Y1 = ((float)(ty * TH + TH - 1) + 0.5f - cy) - r0.y;
+// column_rows for the pixel columns [px0, px1] over rows [py0, py1] and the
+// record's Gaussian.
+__device__ __forceinline__ float2 strip_rows(const float4& r0, const float4& r1, float cx,
+                                             float cy, float log_amin, int px0, int px1, int py0,
+                                             int py1) {
+  const float X0 = ((float)px0 + 0.5f - cx) - r0.x;
+  const float X1 = ((float)px1 + 0.5f - cx) - r0.x;
+  const float Y0 = ((float)py0 + 0.5f - cy) - r0.y;
+  const float Y1 = ((float)py1 + 0.5f - cy) - r0.y;
   const float r2 = fmaxf(X0 * X0, X1 * X1) + fmaxf(Y0 * Y0, Y1 * Y1);
   return column_rows(r0.z, r0.w, r1.x, r1.y, log_amin, X0, X1, r2);
 }
+
+// Pixel groups: forward and reverse walk split a tile into 8x8 blocks of
+// 64 pixels (block k at column k % (TW/8), row k / (TW/8)); lane l holds
+// pixel (l % 8, l / 8) of its block.  A block is more compact than a strip
+// of 64 pixels, so fewer blocks than strips meet a footprint.
+template <int TW, int TH>
+struct Blocks {
+  static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 blocks");
+  static constexpr int BX = TW / 8;
+  __device__ static int x0(int tx, int k) { return tx * TW + (k % BX) * 8; }
+  __device__ static int y0(int ty, int k) { return ty * TH + (k / BX) * 8; }
+};
 
 // Pixel rows [py0, py1] (pixel centres) meet the interval.
 __device__ __forceinline__ bool rows_meet(float2 yr, int py0, int py1, float cy, float my) {
@@ -137,19 +150,17 @@ template <int TW, int TH, bool FILT = false>
 __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
                                             float4 (*s_rec)[3][64], uint32_t* s_xf = nullptr) {
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int px = tx * TW + lx, py = ty * TH + ly;
+  // pixel rectangle of this wavefront: 8x8 block w of the tile
+  const int wx0 = Blocks<TW, TH>::x0(tx, w), wx1 = wx0 + 7;
+  const int wy0 = Blocks<TW, TH>::y0(ty, w), wy1 = wy0 + 7;
+  const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
   const bool inside = px < a.W && py < a.H;
   const uint32_t pix = (uint32_t)py * a.W + px;
   bool active = inside;
   if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
   const uint32_t pbits = (FILT && active) ? filter_bits(a.omega, a.words, a.ncells, a.cell, pix) : 0u;
   const float fx = (float)px + 0.5f - a.cx, fy = (float)py + 0.5f - a.cy;
-  // pixel rectangle of this wavefront (64 consecutive pixels of the tile)
-  constexpr int WR = 64 / TW;  // rows per wavefront
-  const int wx0 = tx * TW, wx1 = wx0 + TW - 1;
-  const int wy0 = ty * TH + w * WR, wy1 = wy0 + WR - 1;
   const uint2 rg = a.ranges[tile];
   const float log_amin = __logf(a.alpha_min);
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
@@ -168,8 +179,9 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
       s_rec[w][2][lane] = q2;
       if (FILT) s_xf[w * 64 + lane] = a.xf[gl];
       meets = box_meets(q2.z, q2.w, wx0, wx1, wy0, wy1) &&
-              rows_meet(tile_column_rows<TW, TH>(q0, q1, a.cx, a.cy, log_amin, tx, ty), wy0,
-                        wy1, a.cy, q0.y);
+              rows_meet(strip_rows(q0, q1, a.cx, a.cy, log_amin, wx0, wx1, ty * TH,
+                                   ty * TH + TH - 1),
+                        wy0, wy1, a.cy, q0.y);
     }
     uint64_t todo = __ballot(meets);
     __builtin_amdgcn_wave_barrier();
@@ -335,7 +347,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
                                                 float4 (*s_rec)[64], uint32_t* s_e,
                                                 uint32_t* s_xf = nullptr) {
   constexpr int PPT = TW * TH / 64;
-  constexpr int WR = 64 / TW;  // rows per group of 64 pixels
+  using BL = Blocks<TW, TH>;
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int lane = threadIdx.x;
   const uint32_t wave_last = a.nv[tile];  // max of the pixels' `last` over the tile
@@ -351,20 +363,17 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
   }
   if (wave_last == 0) return;  // nothing blended here: no pixel reads
   const float log_amin = __logf(a.alpha_min);
-  uint32_t pxy[PPT];  // pixel x | y << 16
   float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
   float gx[PPT], gy[PPT], gz[PPT], gd[PPT], gtf[PPT];
   uint32_t lst[PPT], pbits[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int li = lane + 64 * k;
-    const int px = tx * TW + li % TW, py = ty * TH + li / TW;
+    const int px = BL::x0(tx, k) + (lane & 7), py = BL::y0(ty, k) + (lane >> 3);
     const bool inside = px < a.W && py < a.H;
     const uint32_t pix = inside ? (uint32_t)py * a.W + px : 0u;
     bool active = inside;
     if (active && a.mask) active = (a.mask[pix >> 5] >> (pix & 31)) & 1u;
     pbits[k] = (FILT && active) ? filter_bits(a.omega, a.words, a.ncells, a.cell, pix) : 0u;
-    pxy[k] = (uint32_t)px | ((uint32_t)py << 16);
     fx[k] = (float)px + 0.5f - a.cx;
     fy[k] = (float)py + 0.5f - a.cy;
     float Tf = 1.f, gt = 0.f;
@@ -407,13 +416,20 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       s_rec[1][lane] = q1;
       s_rec[2][lane] = q2;
       if (FILT) s_xf[lane] = a.xf[gl];
-      const float2 yr = tile_column_rows<TW, TH>(q0, q1, a.cx, a.cy, log_amin, tx, ty);
+      // the rows of each block column the footprint reaches (the same
+      // interval the forward computes for its blocks of that column)
+      float2 yr[BL::BX];
 #pragma unroll
-      for (int k = 0; k < PPT; ++k)
-        mk[k] = (uint32_t)(j0 + lane) < gmax[k] &&
-                box_meets(q2.z, q2.w, tx * TW, tx * TW + TW - 1, ty * TH + k * WR,
-                          ty * TH + k * WR + WR - 1) &&
-                rows_meet(yr, ty * TH + k * WR, ty * TH + k * WR + WR - 1, a.cy, q0.y);
+      for (int c = 0; c < BL::BX; ++c) {
+        const int x0 = BL::x0(tx, c);
+        yr[c] = strip_rows(q0, q1, a.cx, a.cy, log_amin, x0, x0 + 7, ty * TH, ty * TH + TH - 1);
+      }
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        const int x0 = BL::x0(tx, k), y0 = BL::y0(ty, k);
+        mk[k] = (uint32_t)(j0 + lane) < gmax[k] && box_meets(q2.z, q2.w, x0, x0 + 7, y0, y0 + 7) &&
+                rows_meet(yr[k % BL::BX], y0, y0 + 7, a.cy, q0.y);
+      }
       s_e[lane] = instance_row(a, gl, tx, ty);
     }
     uint64_t gm[PPT];
