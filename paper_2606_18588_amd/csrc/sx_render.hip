@@ -174,8 +174,8 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
       const uint32_t gl = a.vals[jb + lane];
       const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)gl * kRecFloats);
       const float4 q0 = r[0], q1 = r[1], q2 = r[2];
-      s_rec[w][0][lane] = q0;
-      s_rec[w][1][lane] = q1;
+      s_rec[w][0][lane] = make_float4(q0.x, q0.y, q0.z * kConicToExp2, q0.w * kConicToExp2);
+      s_rec[w][1][lane] = make_float4(q1.x * kConicToExp2, q1.y, q1.z, q1.w);
       s_rec[w][2][lane] = q2;
       if (FILT) s_xf[w * 64 + lane] = a.xf[gl];
       meets = box_meets(q2.z, q2.w, wx0, wx1, wy0, wy1) &&
@@ -317,6 +317,30 @@ __device__ __forceinline__ void row_to_g2d(float (&v)[10], float a, float b, flo
   v[4] *= -0.5f;
 }
 
+// Sums two entries' ten per-lane values over the wavefront and stores them,
+// entry A's to da and B's to db (null: not stored).  The 32-lane swap of
+// value i pairs A (kept in lanes 0-31) with B (lanes 32-63), the 16-lane
+// swap pairs values 2p and 2p+1, so that row r of register p carries value
+// 2p + (r & 1) of entry A (r < 2) or B; four DPP steps finish every row and
+// lane 0 of each row stores.  Without a depth gradient value 9 is zero.
+template <bool TEN>
+__device__ __forceinline__ void wave_sum_pair_store(const float (&va)[10], const float (&vb)[10],
+                                                    float* da, float* db, int lane) {
+  float u[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) u[i] = (TEN || i < 9) ? swap_add32(va[i], vb[i]) : 0.f;
+  float w[5];
+#pragma unroll
+  for (int p = 0; p < 5; ++p) w[p] = row_sum16(swap_add16(u[2 * p], u[2 * p + 1]));
+  const int r = lane >> 4;
+  float* d = (r & 2) ? db : da;
+  if ((lane & 15) == 0 && d) {
+    const int q = r & 1;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) d[2 * p + q] = w[p];
+  }
+}
+
 // Reverse walk of each pixel's blended pairs.  With R the colour behind pair
 // i (normalised by T_{i+1}), T_final the partial transmittance and
 // (G, g_T, g_D) the gradients of (C^m, T^m, D^m):
@@ -324,6 +348,9 @@ __device__ __forceinline__ void row_to_g2d(float (&v)[10], float a, float b, flo
 //   dalpha_i = T_i [G.(c_i - R) + g_D (z_i - RD)] - g_T T_final / (1 - alpha_i)
 // then alpha = o exp(-q/2) gives do = dalpha exp(-q/2), dq = -alpha/2 dalpha
 // (zero when alpha was clamped), and q gives the mean2d and conic terms.
+// R and RD enter only through S = G.R + g_D RD, which obeys the same
+// recursion (S <- alpha (G.c_i + g_D z_i) + (1 - alpha) S), so each pixel
+// carries that one scalar instead of the four.
 //
 // One wavefront per tile; each lane owns TW*TH/64 pixels and sums their
 // contributions in registers, then one cross-lane reduction (DPP) per
@@ -363,7 +390,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
   }
   if (wave_last == 0) return;  // nothing blended here: no pixel reads
   const float log_amin = __logf(a.alpha_min);
-  float fx[PPT], fy[PPT], T[PPT], R0[PPT], R1[PPT], R2[PPT], RD[PPT];
+  float fx[PPT], fy[PPT], T[PPT], S[PPT];
   float gx[PPT], gy[PPT], gz[PPT], gd[PPT], gtf[PPT];
   uint32_t lst[PPT], pbits[PPT];
 #pragma unroll
@@ -388,7 +415,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
     }
     T[k] = Tf;
     gtf[k] = gt * Tf;
-    R0[k] = R1[k] = R2[k] = RD[k] = 0.f;
+    S[k] = 0.f;
   }
   // per pixel group, the entries any of its pixels reached
   uint32_t gmax[PPT];
@@ -412,8 +439,8 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       const uint32_t gl = a.vals[rg.x + (uint32_t)(j0 + lane)];
       const float4* rr = reinterpret_cast<const float4*>(a.rec + (size_t)gl * kRecFloats);
       const float4 q0 = rr[0], q1 = rr[1], q2 = rr[2];
-      s_rec[0][lane] = q0;
-      s_rec[1][lane] = q1;
+      s_rec[0][lane] = make_float4(q0.x, q0.y, q0.z * kConicToExp2, q0.w * kConicToExp2);
+      s_rec[1][lane] = make_float4(q1.x * kConicToExp2, q1.y, q1.z, q1.w);
       s_rec[2][lane] = q2;
       if (FILT) s_xf[lane] = a.xf[gl];
       // the rows of each block column the footprint reaches (the same
@@ -436,12 +463,11 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
 #pragma unroll
     for (int k = 0; k < PPT; ++k) gm[k] = __ballot(mk[k]);
     __builtin_amdgcn_wave_barrier();
+    // one entry's contributions, summed per lane into v; false when no
+    // pixel of the tile blends it
     auto entry = [&](const float4& r0, const float4& r1, const float4& r2, int kk, uint32_t xe,
-                     uint32_t e) {
+                     float (&v)[10]) -> bool {
     const int j = j0 + kk;
-    float2* dst = reinterpret_cast<float2*>(a.rows + (size_t)e * kRowFloats);
-    const bool in_cap = (uint64_t)e < a.cap;
-    float v[10];
 #pragma unroll
     for (int m = 0; m < 10; ++m) v[m] = 0.f;
     bool any = false;
@@ -466,21 +492,14 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       v[6] = fmaf(w, gx[k], v[6]);
       v[7] = fmaf(w, gy[k], v[7]);
       v[8] = fmaf(w, gz[k], v[8]);
-      const float d0 = r1.z - R0[k], d1 = r1.w - R1[k], d2 = r2.x - R2[k];
-      float da = gx[k] * d0;
-      da = fmaf(gy[k], d1, da);
-      da = fmaf(gz[k], d2, da);
+      float gc = fmaf(gz[k], r2.x, fmaf(gy[k], r1.w, gx[k] * r1.z));  // G.c_i (+ g_D z_i)
       if constexpr (DG) {
-        const float dd = r2.y - RD[k];
         v[9] = fmaf(w, gd[k], v[9]);
-        da = fmaf(gd[k], dd, da);
-        RD[k] = fmaf(al, dd, RD[k]);
+        gc = fmaf(gd[k], r2.y, gc);
       }
-      da = fmaf(Ti, da, -(gtf[k] * rom));
-      // R <- alpha c + (1 - alpha) R
-      R0[k] = fmaf(al, d0, R0[k]);
-      R1[k] = fmaf(al, d1, R1[k]);
-      R2[k] = fmaf(al, d2, R2[k]);
+      const float dS = gc - S[k];
+      const float da = fmaf(Ti, dS, -(gtf[k] * rom));
+      S[k] = fmaf(al, dS, S[k]);
       T[k] = Ti;
       const float dae = use && !ae.clamped ? da : 0.f;  // alpha clamped: no o, q terms
       v[5] = fmaf(dae, ae.G, v[5]);
@@ -493,16 +512,10 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       v[3] = fmaf(hx, dy, v[3]);
       v[4] = fmaf(hy, dy, v[4]);
     }
-    if (!any) {
-      if (lane == 63 && in_cap) {
-        const float2 z = make_float2(0.f, 0.f);
-        dst[0] = z, dst[1] = z, dst[2] = z, dst[3] = z, dst[4] = z;
-      }
-      return;
-    }
-    wave_sum10_store(v, reinterpret_cast<float*>(dst), lane, in_cap);
+    return any;
     };
-    // two entries per LDS round trip, back to front
+    // two entries per LDS round trip, back to front; their rows are summed
+    // over the wavefront together
     for (int kk = cnt - 1; kk >= 0; kk -= 2) {
       const bool two = kk >= 1;
       const int k2 = two ? kk - 1 : kk;
@@ -510,8 +523,28 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       const float4 q0 = s_rec[0][k2], q1 = s_rec[1][k2], q2 = s_rec[2][k2];
       const uint32_t x1 = FILT ? s_xf[kk] : 0u, x2 = FILT ? s_xf[k2] : 0u;
       const uint32_t e1 = s_e[kk], e2 = s_e[k2];
-      entry(p0, p1, p2, kk, x1, e1);
-      if (two) entry(q0, q1, q2, k2, x2, e2);
+      float va[10], vb[10];
+      bool any = entry(p0, p1, p2, kk, x1, va);
+      if (two) {
+        const bool anyb = entry(q0, q1, q2, k2, x2, vb);
+        any = any || anyb;
+      } else {
+#pragma unroll
+        for (int m = 0; m < 10; ++m) vb[m] = 0.f;
+      }
+      float* da = (uint64_t)e1 < a.cap ? a.rows + (size_t)e1 * kRowFloats : nullptr;
+      float* db = two && (uint64_t)e2 < a.cap ? a.rows + (size_t)e2 * kRowFloats : nullptr;
+      if (any) {
+        wave_sum_pair_store<DG>(va, vb, da, db, lane);
+      } else {
+        // nothing blended either entry: zero rows
+        float* d = lane == 63 ? da : lane == 62 ? db : nullptr;
+        if (d) {
+          float2* d2 = reinterpret_cast<float2*>(d);
+          const float2 z = make_float2(0.f, 0.f);
+          d2[0] = z, d2[1] = z, d2[2] = z, d2[3] = z, d2[4] = z;
+        }
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }

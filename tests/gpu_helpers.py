@@ -143,14 +143,28 @@ def check_grad_scaled(got, ref, scale, what, tol=1e-3, kappa=1.0):
     return need
 
 
-# Floor of the per-element gradient check at the full workloads.  There a
-# screen-space gradient is an FP32 sum over up to thousands of pixels whose
-# terms cancel (the mean gradient of a footprint gets terms of both signs on
-# either side of its centre); the kernel's sums then differ from the FP64
-# ones by a few 1e-6 of the family's largest entry (measured: at most 4.7e-6
-# over 2.5M Gaussians), so entries below 1e-2 of the largest are held to
-# 1e-5 of the largest in absolute terms, and all others to 1e-3 relative.
-FULL_FLOOR = 1e-2
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def param_scales(scene, cam, settings, g2d_scale, vis):
+    """FP32 error scale of each raw-parameter gradient of the visible
+    Gaussians (rows of `vis`), propagated from the screen-space scale.  The
+    projection backward is linear in g2d: column c moves the parameter
+    gradients by J_c g2d[c], so an error within u g2d_scale[c] in every
+    column moves them by at most u sum_c |J_c| g2d_scale[c].  Each column's
+    chain |J_c| g2d_scale[c] is the oracle's projection backward of that
+    column alone (one Gaussian's chain does not involve another's)."""
+    import oracle
+    idx = np.nonzero(vis)[0]
+    sub = scene.subset(idx)
+    out = {}
+    for c in range(10):
+        g = np.zeros((idx.size, 10))
+        g[:, c] = np.asarray(g2d_scale, np.float64)[idx, c]
+        pb = oracle.preprocess_backward(sub, cam, settings, g)
+        for name in PARAM_NAMES:
+            out[name] = out.get(name, 0.0) + np.abs(pb[name])
+    return out
 
 
 def check_grad(got, ref, what, tol=1e-3, floor=1e-3):

@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import (FULL_FLOOR, check_grad, check_grad_scaled, compare_image, jump_bound,
+from gpu_helpers import (check_grad, check_grad_scaled, compare_image, jump_bound, param_scales,
                          need_gpu, rec_fields)
 
 pytestmark = pytest.mark.gpu
@@ -81,11 +81,12 @@ def test_fullsize_batched_views(torch_gpu_fs):
         check_grad_scaled(g2d[vis, c], rb["g2d"][vis, c], rb["g2d_scale"][vis, c],
                           f"15M batched g2d[{c}]")
     pb = oracle.preprocess_backward(scene, cams[0], st, bv.views[0].g2d.cpu().numpy())
+    ps = param_scales(scene, cams[0], st, rb["g2d_scale"], vis)
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         got = getattr(grads, name).cpu().numpy()[vis]
         check_grad(got, pb[name][vis], f"15M batched {name} (chain of the kernel's g2d)",
                    tol=1e-5, floor=1e-4)
-        check_grad(got, rb[name][vis], f"15M batched {name}", floor=FULL_FLOOR)
+        check_grad_scaled(got, rb[name][vis], ps[name], f"15M batched {name}")
 
 
 def test_fullsize_served_4k_request(torch_gpu_fs):
