@@ -159,9 +159,9 @@ sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
 /* ------------------------------------------------------------- a2-a4 --
  * Depth sort (paper, background: sorting step): the result of a stable
  * sort of the 64-bit keys  key = tile_id << 32 | bits(float32 depth)  with
- * ties by Gaussian index.  The visible Gaussians, in index order, are split
- * by tile through a hierarchy of 4 x 4 bins, each level keeping the order;
- * then every tile's list is sorted by (depth bits, index) in LDS.
+ * ties by Gaussian index.  The visible Gaussians' instances are binned by
+ * tile (a count pass, a scan and a write pass), then every tile's list is
+ * sorted by (depth bits, index) in LDS.
  * Outputs: vals[i] = Gaussian index of the i-th instance, optionally
  * keys[i], and tile_ranges[t] = [start, end) per tile (tile_id = ty *
  * tiles_x + tx; an empty tile has start == end), tiles * 2 uint32.
@@ -172,18 +172,17 @@ sx_status sx_preprocess(const sx_gaussians* g, const sx_camera* cam,
  *              the stream once after counting, writes {visible,
  *              instances} and returns SX_ECAPACITY (with nothing sorted)
  *              when instances > capacity.  If NULL the call is fully
- *              asynchronous; an overflow sorts only the first `capacity`
- *              instances and raises a flag read by sx_sort_counts().
+ *              asynchronous; an overflow writes no instance (every tile
+ *              range is empty) and raises a flag read by sx_sort_counts().
  * The workspace begins with uint64 {visible, instances, overflow, error}
  * (32 bytes, valid once the call's work has completed), so a caller may
  * also copy them to pinned host memory asynchronously (error is reserved
- * for a failed bounded wait; the current sort has none and leaves it 0).
+ * and left 0: no step of the sort waits on another workgroup).
  * keys may be NULL. */
 /* Bytes of the sort workspace for n Gaussians, `capacity` instances and a
- * tiles_x x tiles_y grid: about 8 bytes per Gaussian plus 16 bytes per
- * instance (the per-tile lists and their merge buffer), and 4 more bytes per
- * instance (8 once the grid is wider or taller than 16 tiles) for the inner
- * lists of the tile binning. */
+ * tiles_x x tiles_y grid: about 20 bytes per Gaussian (the compacted
+ * visible list), 16 bytes per instance (the per-tile lists and their merge
+ * buffer) and 8 bytes per tile. */
 sx_status sx_sort_workspace_size(int64_t n, int64_t capacity,
                                  int32_t tiles_x, int32_t tiles_y,
                                  size_t* bytes);
@@ -193,9 +192,9 @@ sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
                   size_t ws_bytes, uint64_t* h_counts, sx_stream stream);
 /* Reads the four count words of a sort workspace into HOST uint64[4]:
  * {visible, instances, overflow, error}; synchronises the stream.
- * overflow != 0: the instances exceeded the capacity (only the first
- * `capacity` were sorted); error != 0: a bounded wait of the depth passes
- * ran out and the list is not sorted (the caller must not use it). */
+ * overflow != 0: the instances exceeded the capacity (nothing was binned:
+ * every tile range is empty); error != 0 means the list must not be used
+ * (reserved: the current sort always leaves it 0). */
 sx_status sx_sort_counts(const void* ws, int64_t n, uint64_t* h_out,
                          sx_stream stream);
 

@@ -14,7 +14,6 @@ constexpr int kG2dFloats = 12;   // per-Gaussian screen-space gradient row
 constexpr int kPreBlock = 256;   // Gaussians per preprocess block
 constexpr int kMaxCells = 16;
 constexpr int kMaxViews = 16;  // views per batched launch
-constexpr int kBinSeg = 1024;   // entries per segment of a bin list (tile binning)
 constexpr float kLog2e = 1.4426950408889634f;
 
 // Camera in double (exact widening of the caller's float values) plus the
@@ -48,19 +47,14 @@ struct SortLayout {
   size_t vidx;         // uint32[n]    visible Gaussians in index order
   size_t vrect;        // ushort4[n]   their tile rectangles (same order)
   size_t vkey;         // uint32[n]    their depth bits (same order)
-  size_t bl_list[2];   // uint32[cap] bin lists of the inner levels (ping-pong)
-  size_t bl_bins[2];   // uint2[bins] (start, length) per bin (ping-pong)
-  size_t bl_seg[2];    // uint32[bins + 2] first segment per bin (ping-pong)
-  size_t bl_tot;       // uint32[tiles] entries per child bin (cleared by the
+  size_t tcount;       // uint32[tiles] instances per tile (cleared by the
                        // first kernel of every call)
-  int64_t tot_words;
-  size_t bl_cnt;       // uint32[segments][16] entries per (segment, child)
+  size_t cursor;       // uint32[tiles] next free slot of each tile's list
   size_t pairs[2];     // uint64[cap] per-tile lists of depth bits << 32 | index
-                       // (the last level's output; [1] is the merge buffer of
+                       // (the binning's output; [1] is the merge buffer of
                        // tiles longer than one LDS chunk)
   size_t total;
   int64_t nb;
-  int bl_levels;       // levels of 4x4 subdivision above the tiles (>= 1)
 };
 SortLayout sort_layout(int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
 

@@ -4,22 +4,16 @@
 //     key = tile_id << 32 | bits(float32 depth)
 // over instances emitted in Gaussian-index order, i.e. the order
 // (tile, depth bits, Gaussian index).  It is built in two phases:
-//   1. the list of visible Gaussians, in index order, is split by tile
-//      through a hierarchy of bins (bins of 4^L x 4^L tiles, each bin having
-//      4 x 4 child bins): the list of a bin is cut into segments, and for
-//      every segment each of 16 wavefronts ballot-filters the entries whose
-//      tile rectangle meets its child bin.  A count pass and an exclusive
-//      scan give every (segment, child) its output offset, and a write pass
-//      stores the entries in order, so each child's list keeps the index
-//      order and every store is a contiguous run of a wavefront.  The last
-//      level's bins are single tiles: their lists hold (depth bits, index)
-//      pairs and the scan gives the tile ranges;
+//   1. the compacted visible Gaussians are binned by tile: a count pass,
+//      one scan (the tile ranges) and a write pass that stores each
+//      instance's (depth bits, index) pair at a free slot of its tile's
+//      list, in no particular order;
 //   2. every tile's list is sorted by (depth bits, index) by one workgroup
 //      in LDS: a rank count for lists of up to 256 entries, a bitonic
 //      network up to 2048, and sorted 2048-entry chunks merged through LDS
-//      windows beyond that.
-// No step uses atomics on the output, and no step waits on another
-// workgroup.
+//      windows beyond that.  The pairs are unique, so the result does not
+//      depend on the order phase 1 left.
+// No step waits on another workgroup.
 #include <algorithm>
 
 #include "sx_internal.h"
@@ -30,7 +24,6 @@ namespace {
 
 constexpr int kScanItems = 4;  // preprocess blocks per thread in the count scan
 constexpr int kScanTile = 256 * kScanItems;
-constexpr int kRootFan = 4;      // child bins per axis of the root's split
 constexpr int kTsThreads = 256;  // threads of the per-tile sort
 constexpr int kTsRank = 256;     // longest list sorted by rank counting
 constexpr int kTsChunk = 2048;   // longest list sorted in LDS at once (16 KB: the
@@ -71,20 +64,9 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
   };
   L.nb = (n + kPreBlock - 1) / kPreBlock;
   L.counts = take(4 * sizeof(uint64_t));  // offset 0: part of the ABI
-  // binning: levels of 4x4 bins until one bin covers the grid; per level,
-  // the children's entry totals (accumulated by the count pass)
-  const int64_t big = tiles_x > tiles_y ? tiles_x : tiles_y;
-  // the root (kRootFan) over levels of fan 4 covers kRootFan * 4^(levels - 1) tiles
-  int levels = 1;
-  while ((int64_t(kRootFan) << (2 * (levels - 1))) < big) ++levels;
-  L.bl_levels = levels;
-  int64_t tot_words = 0;
-  for (int lev = 0; lev < levels; ++lev) {
-    const int64_t side = int64_t(1) << (2 * lev);
-    tot_words += ((tiles_x + side - 1) / side) * ((tiles_y + side - 1) / side);
-  }
-  L.bl_tot = take((size_t)tot_words * 4);
-  L.tot_words = tot_words;
+  const size_t tiles = (size_t)(tiles_x * tiles_y > 0 ? tiles_x * tiles_y : 1);
+  L.tcount = take(tiles * 4);
+  L.cursor = take(tiles * 4);
   L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
   L.inst_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
   L.ioff = take((size_t)(n > 0 ? n : 1) * 4);
@@ -92,20 +74,6 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
   L.vidx = take((size_t)(n > 0 ? n : 1) * 4);
   L.vrect = take((size_t)(n > 0 ? n : 1) * 8);
   L.vkey = take((size_t)(n > 0 ? n : 1) * 4);
-  // every entry of an inner level is a (Gaussian, bin) pair with at least
-  // one instance in the bin, so an inner list never exceeds the instance count
-  const int64_t bins = ((tiles_x + 3) / 4) * ((tiles_y + 3) / 4);
-  const size_t list_bytes = (size_t)(cap > 0 ? cap : 1) * 4;
-  L.bl_list[1] = levels >= 2 ? take(list_bytes) : off;  // level 1 writes list[1]
-  L.bl_list[0] = levels >= 3 ? take(list_bytes) : off;
-  for (int k = 0; k < 2; ++k) L.bl_bins[k] = take((size_t)(bins + 1) * 8);
-  for (int k = 0; k < 2; ++k) L.bl_seg[k] = take((size_t)(bins + 2) * 4);
-  {
-    // (segment, child) counts: 256 per segment of the root, 16 below
-    const size_t segs = (size_t)(cap / kBinSeg) + 2;
-    const size_t words = std::max(segs * 256, (segs + (size_t)bins) * 16);
-    L.bl_cnt = take(words * 4);
-  }
   for (int k = 0; k < 2; ++k) L.pairs[k] = take((size_t)(cap > 0 ? cap : 1) * 8);
   L.total = off;
   return L;
@@ -156,7 +124,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
                                                      uint64_t* counts) {
   __shared__ unsigned long long s4[4];
   // the first kernel of the call also clears what later kernels accumulate
-  // into: the binning's child totals and the reserved error word
+  // into: the binning's tile counts and the reserved error word
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < tot_words;
        k += (int64_t)gridDim.x * 256)
     tot[k] = 0;
@@ -178,9 +146,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
                                                     const uint64_t* __restrict__ part,
                                                     uint32_t* __restrict__ vis_off,
                                                     uint32_t* __restrict__ inst_off,
-                                                    uint64_t* counts, int64_t cap,
-                                                    uint2* __restrict__ root_bin,
-                                                    uint32_t* __restrict__ root_seg) {
+                                                    uint64_t* counts, int64_t cap) {
   __shared__ unsigned long long s4[4];
   __shared__ uint32_t s_scan[4];
   const bool last = blockIdx.x == gridDim.x - 1;
@@ -220,13 +186,60 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
     const bool over = pi > (uint64_t)cap;
     counts[0] = pv + total;
     counts[1] = pi;
-    counts[2] = over ? 1ull : 0ull;
-    // the root of the binning: one bin holding every visible Gaussian in
-    // depth order (none when the instances overflow the buffer)
-    const uint32_t nvis = over ? 0u : (uint32_t)(pv + total);
-    root_bin[0] = make_uint2(0u, nvis);
-    root_seg[0] = 0;
-    root_seg[1] = (nvis + kBinSeg - 1) / kBinSeg;
+    counts[2] = over ? 1ull : 0ull;  // the binning then writes nothing
+  }
+}
+
+// The same scan in one workgroup (one launch instead of two) for scenes of
+// at most kOneScan preprocess blocks: each of 1024 threads takes
+// kOneScan / 1024 consecutive blocks.  It also clears the tile counts and
+// the reserved error word.
+constexpr int kOneScan = 16384;
+
+__global__ __launch_bounds__(1024) void k_scan_one(const uint32_t* __restrict__ bsum, int64_t nb,
+                                                   uint32_t* __restrict__ vis_off,
+                                                   uint32_t* __restrict__ inst_off,
+                                                   uint64_t* counts, int64_t cap,
+                                                   uint32_t* __restrict__ tcount, int64_t tiles) {
+  __shared__ unsigned long long s_v[16], s_i[16];
+  constexpr int per = kOneScan / 1024;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int64_t k = tid; k < tiles; k += 1024) tcount[k] = 0;
+  const int64_t b0 = (int64_t)tid * per;
+  uint32_t v[per], iv[per];
+  unsigned long long sv = 0, si = 0;
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    const bool in = b0 + j < nb;
+    v[j] = in ? bsum[2 * (b0 + j)] : 0u;
+    iv[j] = in ? bsum[2 * (b0 + j) + 1] : 0u;
+    sv += v[j], si += iv[j];
+  }
+  unsigned long long xv = sv, xi = si;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long yv = __shfl_up(xv, o, 64), yi = __shfl_up(xi, o, 64);
+    if (lane >= o) xv += yv, xi += yi;
+  }
+  if (lane == 63) s_v[w] = xv, s_i[w] = xi;
+  __syncthreads();
+  unsigned long long pv = xv - sv, pi = xi - si, tv = 0, ti = 0;
+  for (int k = 0; k < 16; ++k) {
+    if (k < w) pv += s_v[k], pi += s_i[k];
+    tv += s_v[k], ti += s_i[k];
+  }
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    if (b0 + j < nb) {
+      vis_off[b0 + j] = (uint32_t)pv;
+      inst_off[b0 + j] = (uint32_t)pi;  // exact within the 2^31 capacity bound
+    }
+    pv += v[j], pi += iv[j];
+  }
+  if (tid == 0) {
+    counts[0] = tv;
+    counts[1] = ti;
+    counts[2] = ti > (unsigned long long)cap ? 1ull : 0ull;  // the binning then writes nothing
+    counts[3] = 0;
   }
 }
 
@@ -270,255 +283,204 @@ __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restric
 }
 
 // ------------------------------------------------------------ binning --
-// One level of the tile hierarchy: parents are bins of fan*side x fan*side
-// tiles (grid pgx x pgy, lists in `in`), children bins of side x side
-// (grid cgx x cgy).  Child (cx, cy) belongs to parent (cx/fan, cy/fan) at
-// slot (cy%fan)*fan + cx%fan; a wavefront takes fan*fan/16 slots.  The
-// root level has one parent and fan kRootFan, the levels below fan 4 (a
-// root of fan 16, a row of 16 slots per wavefront, measured slower: its
-// wavefronts scan the segment once per slot).  Parent lists are cut into
-// segments of kBinSeg entries; pseg[p] is the first segment of parent p and
-// pseg[nparents] the total.
-struct BinLevel {
-  const uint32_t* __restrict__ in;  // positions in the compacted visible list
-  const uint2* __restrict__ pbins;   // (start, length) per parent
-  const uint32_t* __restrict__ pseg;
-  int pgx, pgy, cgx, cgy, side, tiles_x, tiles_y;
-  int fan;    // children per parent along each axis (4 or 16)
-  int cpw;    // children per wavefront: fan * fan / 16
+// Every visible Gaussian's instances go to the lists of the tiles its
+// rectangle covers: a count pass gives each tile's length, one scan its
+// range, and a write pass stores (depth bits << 32 | index) at the tile's
+// next free slot.  The order inside a tile's list is whatever the slots
+// were taken in; the tile sort below makes it (depth bits, index).
+//
+// Each workgroup takes a contiguous run of the compacted visible list (the
+// Gaussians are stored in Morton order, so a run covers few tiles), in
+// chunks of kBinChunk Gaussians.  A chunk's instances are numbered through
+// a block scan of the rectangle areas and dealt to the threads in turn
+// (thread q takes instances q, q + kBinThreads, ...; a binary search over
+// the chunk's instance starts in LDS names the Gaussian), so a Gaussian
+// covering hundreds of tiles does not serialise one thread.  Counts and
+// slots are aggregated in an LDS counter per tile of the grid, so that a
+// tile sees one device atomic per workgroup that reaches it; grids of more
+// than kLdsTiles tiles use a device atomic per instance instead.
+constexpr int kBinThreads = 512;
+constexpr int kBinChunk = 2048;
+constexpr int kBinPer = kBinChunk / kBinThreads;
+constexpr int kLdsTiles = 8192;  // 32 KB of LDS counters
+
+struct TileBin {
   const ushort4* __restrict__ vrect;  // tile rectangle per compacted position
   const uint32_t* __restrict__ vkey;  // depth bits per compacted position
   const uint32_t* __restrict__ vidx;  // Gaussian index per compacted position
-  const uint64_t* counts;
-  uint32_t* __restrict__ cnt;   // [segments][fan * fan]
-  uint32_t* __restrict__ tot;   // [children], zeroed before the count pass
-  uint2* __restrict__ cbins;    // (start, length) per child (inner levels)
-  uint32_t* __restrict__ cseg;  // segment starts of the children (inner levels)
-  uint32_t* __restrict__ out;     // child lists of the inner levels
-  uint32_t* __restrict__ ranges;  // last level: [tiles][2]
-  uint64_t* __restrict__ pairs;   // last level: depth bits << 32 | index per instance
-  int last;
-  int inline_scan;  // few children: the write pass scans the totals itself
+  const uint64_t* counts;             // [0] visible, [2] overflow
+  int tiles_x, tiles;
+  uint32_t* __restrict__ tcount;  // [tiles] instances per tile (cleared by the
+                                  // first kernel of the call)
+  uint32_t* __restrict__ cursor;  // [tiles] next free slot (set by the scan)
+  uint64_t* __restrict__ pairs;   // per-tile lists
+  uint64_t cap;                   // entries of pairs
 };
 
-// Segment `sg`: its parent, first entry and entry count.
-__device__ __forceinline__ int bin_segment(const BinLevel& a, uint32_t sg, uint32_t* lo,
-                                           uint32_t* m) {
-  int l = 0, h = a.pgx * a.pgy - 1;  // largest p with pseg[p] <= sg
-  while (l < h) {
-    const int mid = (l + h + 1) >> 1;
-    if (a.pseg[mid] <= sg) l = mid; else h = mid - 1;
-  }
-  const uint2 pb = a.pbins[l];
-  const uint32_t off = (sg - a.pseg[l]) * (uint32_t)kBinSeg;
-  *lo = pb.x + off;
-  const uint32_t rest = pb.y - off;
-  *m = rest < (uint32_t)kBinSeg ? rest : (uint32_t)kBinSeg;
-  return l;
+struct BinLds {
+  uint32_t start[kBinChunk + 1];  // exclusive scan of the chunk's areas
+  ushort4 rc[kBinChunk];
+  uint32_t scan[kBinThreads / 64];
+};
+
+// The run of compacted positions [*b0, *b1) of this workgroup (empty when
+// the instances overflowed the buffer: nothing is binned).
+__device__ __forceinline__ void bin_run(const TileBin& a, uint64_t* b0, uint64_t* b1) {
+  const uint64_t nvis = a.counts[2] ? 0ull : a.counts[0];
+  const uint64_t per = (nvis + gridDim.x - 1) / gridDim.x;
+  *b0 = (uint64_t)blockIdx.x * per;
+  *b1 = *b0 + per < nvis ? *b0 + per : nvis;
 }
 
-// Tile region of the child bin of parent p at slot `slot`; false if outside.
-__device__ __forceinline__ bool bin_child(const BinLevel& a, int p, int slot, int* c, int* rx0,
-                                          int* rx1, int* ry0, int* ry1) {
-  const int cx = (p % a.pgx) * a.fan + slot % a.fan, cy = (p / a.pgx) * a.fan + slot / a.fan;
-  if (cx >= a.cgx || cy >= a.cgy) return false;
-  *c = cy * a.cgx + cx;
-  *rx0 = cx * a.side, *ry0 = cy * a.side;
-  *rx1 = min(*rx0 + a.side, a.tiles_x), *ry1 = min(*ry0 + a.side, a.tiles_y);
-  return true;
-}
-
-// Stage one segment (Gaussian ids and tile rectangles) in LDS.
-__device__ __forceinline__ void bin_stage(const BinLevel& a, uint32_t lo, uint32_t m,
-                                          uint32_t* s_g, ushort4* s_rc) {
-  __syncthreads();  // the previous segment is consumed
-  for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
-    const uint32_t g = a.in ? a.in[lo + i] : lo + i;  // the root list is 0, 1, ...
-    s_g[i] = g;
-    s_rc[i] = a.vrect[g];
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ bool meets(ushort4 rc, int rx0, int rx1, int ry0, int ry1) {
-  return (int)rc.x < rx1 && rx0 < (int)rc.z && (int)rc.y < ry1 && ry0 < (int)rc.w;
-}
-
-// Count pass: entries of each (segment, child).
-__global__ __launch_bounds__(1024) void k_bin_count(BinLevel a) {
-  __shared__ uint32_t s_g[kBinSeg];
-  __shared__ ushort4 s_rc[kBinSeg];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t nseg = a.pseg[a.pgx * a.pgy];
-  for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-    uint32_t lo, m;
-    const int p = bin_segment(a, sg, &lo, &m);
-    bin_stage(a, lo, m, s_g, s_rc);
-    const int nslot = a.fan * a.fan;
-    for (int k = 0; k < a.cpw; ++k) {
-      const int slot = w * a.cpw + k;
-      int c = 0, rx0, rx1, ry0, ry1;
-      uint32_t n = 0;
-      if (bin_child(a, p, slot, &c, &rx0, &rx1, &ry0, &ry1))
-        for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
-          const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
-          n += (uint32_t)__popcll(__ballot(hit));
-        }
-      if (lane == 0) {
-        a.cnt[(size_t)sg * nslot + slot] = n;
-        if (n) atomicAdd(&a.tot[c], n);  // integer sum: the order does not matter
-      }
-    }
-  }
-}
-
-// One block: exclusive scan of the children's totals (their list starts;
-// tile ranges at the last level) and, for inner levels, of their segment
-// counts.
-__device__ __forceinline__ void bin_scan(const BinLevel& a, uint32_t* s_a, uint32_t* s_b) {
-  const int tid = threadIdx.x;
-  const int C = a.cgx * a.cgy;
-  const int chunk = (C + 1023) / 1024;
-  const int beg = tid * chunk, end = beg + chunk < C ? beg + chunk : C;
-  uint32_t sa = 0, sb = 0;
-  for (int c = beg; c < end; ++c) {
-    const uint32_t t = a.tot[c];
-    sa += t;
-    sb += (t + kBinSeg - 1) / kBinSeg;
-  }
-  s_a[tid] = sa, s_b[tid] = sb;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint32_t va = tid >= o ? s_a[tid - o] : 0u, vb = tid >= o ? s_b[tid - o] : 0u;
-    __syncthreads();
-    s_a[tid] += va, s_b[tid] += vb;
-    __syncthreads();
-  }
-  uint32_t ra = s_a[tid] - sa, rb = s_b[tid] - sb;
-  for (int c = beg; c < end; ++c) {
-    const uint32_t t = a.tot[c];
-    if (a.last) {
-      a.ranges[2 * (size_t)c] = ra;
-      a.ranges[2 * (size_t)c + 1] = ra + t;
-    } else {
-      a.cbins[c] = make_uint2(ra, t);
-      a.cseg[c] = rb;
-    }
-    ra += t;
-    rb += (t + kBinSeg - 1) / kBinSeg;
-  }
-  if (!a.last && tid == 1023) a.cseg[C] = s_b[1023];
-}
-
-// The same scan for up to kScanLds children: the totals are read once,
-// coalesced, into LDS, and scanned with wavefront shuffles and one
-// cross-wavefront step instead of a barrier per Hillis-Steele round.
-constexpr int kScanLds = 8192;
-
-__device__ __forceinline__ void bin_scan_lds(const BinLevel& a, uint32_t* s_t) {
-  __shared__ uint32_t s_wa[16], s_wb[16];
+// Calls f(compacted position, tile) for every instance of the run.
+template <typename F>
+__device__ __forceinline__ void bin_each(const TileBin& a, uint64_t b0, uint64_t b1, BinLds& L,
+                                         F f) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int C = a.cgx * a.cgy;
-  for (int c = tid; c < C; c += 1024) s_t[c] = a.tot[c];
-  __syncthreads();
-  constexpr int chunk = kScanLds / 1024;
-  const int beg = tid * chunk, end = beg + chunk < C ? beg + chunk : C;
-  uint32_t sa = 0, sb = 0;
-  for (int c = beg; c < end; ++c) {
-    const uint32_t t = s_t[c];
-    sa += t;
-    sb += (t + kBinSeg - 1) / kBinSeg;
-  }
-  uint32_t xa = sa, xb = sb;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t ya = __shfl_up(xa, o, 64), yb = __shfl_up(xb, o, 64);
-    if (lane >= o) xa += ya, xb += yb;
-  }
-  if (lane == 63) s_wa[w] = xa, s_wb[w] = xb;
-  __syncthreads();
-  uint32_t pa = 0, pb = 0, tb = 0;
-  for (int k = 0; k < 16; ++k) {
-    if (k < w) pa += s_wa[k], pb += s_wb[k];
-    tb += s_wb[k];
-  }
-  uint32_t ra = pa + xa - sa, rb = pb + xb - sb;
-  for (int c = beg; c < end; ++c) {
-    const uint32_t t = s_t[c];
-    if (a.last) {
-      a.ranges[2 * (size_t)c] = ra;
-      a.ranges[2 * (size_t)c + 1] = ra + t;
-    } else {
-      a.cbins[c] = make_uint2(ra, t);
-      a.cseg[c] = rb;
+  for (uint64_t c0 = b0; c0 < b1; c0 += kBinChunk) {
+    const int m = b1 - c0 < (uint64_t)kBinChunk ? (int)(b1 - c0) : kBinChunk;
+    // areas of the thread's kBinPer consecutive Gaussians, block scan
+    ushort4 rc[kBinPer];
+    uint32_t ar[kBinPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+      const int j = tid * kBinPer + k;
+      rc[k] = j < m ? a.vrect[c0 + j] : make_ushort4(0, 0, 0, 0);
+      ar[k] = (uint32_t)(rc[k].z - rc[k].x) * (uint32_t)(rc[k].w - rc[k].y);
+      sum += ar[k];
     }
-    ra += t;
-    rb += (t + kBinSeg - 1) / kBinSeg;
-  }
-  if (!a.last && tid == 0) a.cseg[C] = tb;
-}
-
-__global__ __launch_bounds__(1024) void k_bin_scan(BinLevel a) {
-  if (a.cgx * a.cgy <= kScanLds) {
-    __shared__ uint32_t s_t[kScanLds];
-    bin_scan_lds(a, s_t);
-    return;
-  }
-  __shared__ uint32_t s_a[1024], s_b[1024];
-  bin_scan(a, s_a, s_b);
-}
-
-// Write pass: every wavefront appends the entries of its child in order.
-// With inline_scan (at most kInlineChildren children) there is no scan
-// launch: each wavefront sums the totals of the children before its own,
-// and workgroup 0 also writes the scan's outputs for the next level.
-constexpr int kInlineChildren = 1024;
-
-__global__ __launch_bounds__(1024) void k_bin_write(BinLevel a) {
-  __shared__ uint32_t s_g[kBinSeg];
-  __shared__ ushort4 s_rc[kBinSeg];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (a.inline_scan && blockIdx.x == 0) {
-    __shared__ uint32_t s_a[1024], s_b[1024];
-    bin_scan(a, s_a, s_b);
-  }
-  const uint32_t nseg = a.pseg[a.pgx * a.pgy];
-  const uint64_t lt = (1ull << lane) - 1ull;
-  for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-    uint32_t lo, m;
-    const int p = bin_segment(a, sg, &lo, &m);
-    bin_stage(a, lo, m, s_g, s_rc);
-    const int nslot = a.fan * a.fan;
-    for (int k = 0; k < a.cpw; ++k) {
-    const int slot = w * a.cpw + k;
-    int c, rx0, rx1, ry0, ry1;
-    if (!bin_child(a, p, slot, &c, &rx0, &rx1, &ry0, &ry1)) continue;
-    // start of this (segment, child): the child's start plus the entries
-    // the parent's earlier segments gave it
-    uint32_t base = 0;
-    for (uint32_t q = a.pseg[p] + lane; q < sg; q += 64) base += a.cnt[(size_t)q * nslot + slot];
-    for (int o = 32; o >= 1; o >>= 1) base += __shfl_xor(base, o, 64);
-    if (a.inline_scan) {
-      uint32_t start = 0;
-      for (int q = lane; q < c; q += 64) start += a.tot[q];
-      for (int o = 32; o >= 1; o >>= 1) start += __shfl_xor(start, o, 64);
-      base += start;
-    } else {
-      base += a.last ? a.ranges[2 * (size_t)c] : a.cbins[c].x;
+    uint32_t x = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
     }
-    for (uint32_t j = lane; j < (m + 63) / 64 * 64; j += 64) {
-      const bool hit = j < m && meets(s_rc[j < m ? j : 0], rx0, rx1, ry0, ry1);
-      const uint64_t b = __ballot(hit);
-      if (hit) {
-        const uint32_t pos = base + (uint32_t)__popcll(b & lt);
-        const uint32_t g = s_g[j];
-        if (a.last)
-          a.pairs[pos] = (uint64_t)a.vkey[g] << 32 | a.vidx[g];
-        else
-          a.out[pos] = g;
+    __syncthreads();  // every thread is done with the previous chunk's arrays
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k)
+      if (tid * kBinPer + k < m) L.rc[tid * kBinPer + k] = rc[k];
+    if (lane == 63) L.scan[w] = x;
+    __syncthreads();
+    uint32_t run = x - sum, total = 0;
+    for (int k = 0; k < kBinThreads / 64; ++k) {
+      if (k < w) run += L.scan[k];
+      total += L.scan[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+      L.start[tid * kBinPer + k] = run;
+      run += ar[k];
+    }
+    if (tid == 0) L.start[kBinChunk] = total;
+    __syncthreads();
+    for (uint32_t q = tid; q < total; q += kBinThreads) {
+      int lo = 0, hi = m - 1;  // last Gaussian whose start <= q
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.start[mid] <= q) lo = mid; else hi = mid - 1;
       }
-      base += (uint32_t)__popcll(b);
+      const ushort4 g = L.rc[lo];
+      const uint32_t r = q - L.start[lo], wd = (uint32_t)(g.z - g.x);
+      const uint32_t ry = r / wd;
+      const int t = (int)(g.y + ry) * a.tiles_x + (int)(g.x + (r - ry * wd));
+      if ((unsigned)t < (unsigned)a.tiles) f(c0 + (uint64_t)lo, t);  // always, by construction
     }
+  }
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(kBinThreads) void k_tile_count(TileBin a) {
+  __shared__ BinLds L;
+  __shared__ uint32_t s_h[LDS ? kLdsTiles : 1];
+  uint64_t b0, b1;
+  bin_run(a, &b0, &b1);
+  if (b0 >= b1) return;  // the same for the whole workgroup
+  if (LDS) {
+    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) s_h[t] = 0;
+    bin_each(a, b0, b1, L, [&](uint64_t, int t) { atomicAdd(&s_h[t], 1u); });
+    __syncthreads();
+    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) {
+      const uint32_t c = s_h[t];
+      if (c) atomicAdd(&a.tcount[t], c);  // integer sums: any order
     }
+  } else {
+    bin_each(a, b0, b1, L, [&](uint64_t, int t) { atomicAdd(&a.tcount[t], 1u); });
+  }
+}
+
+// One workgroup: exclusive scan of the tile counts into the tile ranges
+// [start, end) and the write pass's cursors (= start), through LDS in
+// chunks of kScanChunk tiles with a running carry.
+constexpr int kScanChunk = 8192;
+
+__global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t* __restrict__ tcount,
+                                                    int tiles, uint32_t* __restrict__ ranges,
+                                                    uint32_t* __restrict__ cursor) {
+  __shared__ uint32_t s_t[kScanChunk];
+  __shared__ uint32_t s_w[16];
+  constexpr int per = kScanChunk / 1024;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < tiles; c0 += kScanChunk) {
+    const int m = tiles - c0 < kScanChunk ? tiles - c0 : kScanChunk;
+    for (int t = tid; t < kScanChunk; t += 1024) s_t[t] = t < m ? tcount[c0 + t] : 0u;
+    __syncthreads();
+    uint32_t v[per], sum = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) v[k] = s_t[tid * per + k], sum += v[k];
+    uint32_t x = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint32_t run = carry + x - sum, total = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < w) run += s_w[k];
+      total += s_w[k];
+    }
+#pragma unroll
+    for (int k = 0; k < per; ++k) s_t[tid * per + k] = run, run += v[k];
+    __syncthreads();
+    for (int t = tid; t < m; t += 1024) {
+      const uint32_t st = s_t[t];
+      ranges[2 * (size_t)(c0 + t)] = st;
+      ranges[2 * (size_t)(c0 + t) + 1] = st + tcount[c0 + t];
+      cursor[c0 + t] = st;
+    }
+    carry += total;
+    __syncthreads();
+  }
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(kBinThreads) void k_tile_write(TileBin a) {
+  __shared__ BinLds L;
+  __shared__ uint32_t s_h[LDS ? kLdsTiles : 1];
+  uint64_t b0, b1;
+  bin_run(a, &b0, &b1);
+  if (b0 >= b1) return;
+  auto key = [&](uint64_t i) { return (uint64_t)a.vkey[i] << 32 | a.vidx[i]; };
+  if (LDS) {
+    // count again, reserve each tile's slots with one device atomic, then
+    // hand them out from LDS
+    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) s_h[t] = 0;
+    bin_each(a, b0, b1, L, [&](uint64_t, int t) { atomicAdd(&s_h[t], 1u); });
+    __syncthreads();
+    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) {
+      const uint32_t c = s_h[t];
+      if (c) s_h[t] = atomicAdd(&a.cursor[t], c);
+    }
+    __syncthreads();
+    bin_each(a, b0, b1, L, [&](uint64_t i, int t) {
+      const uint32_t pos = atomicAdd(&s_h[t], 1u);
+      if (pos < a.cap) a.pairs[pos] = key(i);  // always, the slots being reserved
+    });
+  } else {
+    bin_each(a, b0, b1, L, [&](uint64_t i, int t) {
+      const uint32_t pos = atomicAdd(&a.cursor[t], 1u);
+      if (pos < a.cap) a.pairs[pos] = key(i);
+    });
   }
 }
 
@@ -684,15 +646,18 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     if (h_counts) h_counts[0] = h_counts[1] = 0;
     return hipSuccess;
   }
-  {
+  if (L.nb <= kOneScan) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, proj.block_sums, (int64_t)L.nb,
+                       u32(L.vis_off), u32(L.inst_off), counts, (int64_t)capacity,
+                       u32(L.tcount), tiles_total);
+  } else {
     const unsigned tiles = (unsigned)((L.nb + kScanTile - 1) / kScanTile);
     uint64_t* part = reinterpret_cast<uint64_t*>(ws + L.scan_part);
     hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(256), 0, st, proj.block_sums,
-                       (int64_t)L.nb, part, u32(L.bl_tot), L.tot_words, counts);
+                       (int64_t)L.nb, part, u32(L.tcount), tiles_total, counts);
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, st, proj.block_sums,
                        (int64_t)L.nb, part, u32(L.vis_off), u32(L.inst_off), counts,
-                       (int64_t)capacity,
-                       reinterpret_cast<uint2*>(ws + L.bl_bins[0]), u32(L.bl_seg[0]));
+                       (int64_t)capacity);
   }
   if ((e = hipGetLastError())) return e;
   if (h_counts) {
@@ -709,59 +674,35 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
   hipLaunchKernelGGL(k_compact, dim3((unsigned)L.nb), dim3(kPreBlock), 0, st, proj.n_tiles,
                      proj.rec, proj.rect, n, u32(L.vis_off), u32(L.inst_off), u32(L.vidx),
                      reinterpret_cast<ushort4*>(ws + L.vrect), u32(L.vkey), u32(L.ioff));
-  // phase 1: split the index-ordered list of visible Gaussians by tile,
-  // level by level
-  uint2* bins[2] = {reinterpret_cast<uint2*>(ws + L.bl_bins[0]),
-                    reinterpret_cast<uint2*>(ws + L.bl_bins[1])};
-  uint32_t* seg[2] = {u32(L.bl_seg[0]), u32(L.bl_seg[1])};
-  uint32_t* lists[2] = {u32(L.bl_list[0]), u32(L.bl_list[1])};
-  // (the root bin, bins[0] and seg[0], was written with the visible count)
-  int64_t tot_off[32];
-  for (int lev = 0, o = 0; lev < L.bl_levels; ++lev) {
-    const int side = 1 << (2 * lev);
-    tot_off[lev] = o;
-    o += ((p.tiles_x + side - 1) / side) * ((p.tiles_y + side - 1) / side);
-  }
-  const uint32_t* in = nullptr;  // the root bin lists compacted positions 0, 1, ...
-  uint64_t* pairs[2] = {reinterpret_cast<uint64_t*>(ws + L.pairs[0]),
-                        reinterpret_cast<uint64_t*>(ws + L.pairs[1])};
-  int cur = 0;
-  for (int lev = L.bl_levels - 1; lev >= 0; --lev) {
-    const int side = 1 << (2 * lev);
-    BinLevel a{};
-    a.in = in;
-    a.pbins = bins[cur];
-    a.pseg = seg[cur];
-    a.cgx = (p.tiles_x + side - 1) / side;
-    a.cgy = (p.tiles_y + side - 1) / side;
-    a.fan = lev == L.bl_levels - 1 ? kRootFan : 4;  // the root: one parent
-    a.cpw = a.fan * a.fan / 16;
-    a.pgx = (a.cgx + a.fan - 1) / a.fan;
-    a.pgy = (a.cgy + a.fan - 1) / a.fan;
-    a.side = side;
-    a.tiles_x = p.tiles_x, a.tiles_y = p.tiles_y;
+  // phase 1: the instances into their tiles' lists
+  {
+    TileBin a{};
     a.vrect = reinterpret_cast<const ushort4*>(ws + L.vrect);
     a.vkey = u32(L.vkey);
     a.vidx = u32(L.vidx);
     a.counts = counts;
-    a.cnt = u32(L.bl_cnt);
-    a.tot = u32(L.bl_tot) + tot_off[lev];
-    a.cbins = bins[cur ^ 1];
-    a.cseg = seg[cur ^ 1];
-    a.last = lev == 0;
-    a.out = a.last ? nullptr : lists[lev & 1];
-    a.ranges = ranges;
-    a.pairs = a.last ? pairs[0] : nullptr;
-    const int64_t nparents = (int64_t)a.pgx * a.pgy;
-    const int64_t segs_max = capacity / kBinSeg + nparents + 1;
-    const unsigned grid = (unsigned)(segs_max < 4096 ? segs_max : 4096);
-    a.inline_scan = a.cgx * a.cgy <= kInlineChildren;
-    hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(1024), 0, st, a);
-    if (!a.inline_scan) hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, a);
-    hipLaunchKernelGGL(k_bin_write, dim3(grid), dim3(1024), 0, st, a);
-    in = a.out;
-    cur ^= 1;
+    a.tiles_x = p.tiles_x;
+    a.tiles = (int)tiles_total;
+    a.tcount = u32(L.tcount);
+    a.cursor = u32(L.cursor);
+    a.pairs = reinterpret_cast<uint64_t*>(ws + L.pairs[0]);
+    a.cap = (uint64_t)(capacity > 0 ? capacity : 1);
+    int64_t blocks = n / 4096;
+    blocks = blocks < 1 ? 1 : blocks > 512 ? 512 : blocks;
+    if (tiles_total <= kLdsTiles) {
+      hipLaunchKernelGGL(k_tile_count<true>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
+      hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, a.tcount, a.tiles, ranges,
+                         a.cursor);
+      hipLaunchKernelGGL(k_tile_write<true>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
+    } else {
+      hipLaunchKernelGGL(k_tile_count<false>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
+      hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, a.tcount, a.tiles, ranges,
+                         a.cursor);
+      hipLaunchKernelGGL(k_tile_write<false>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
+    }
   }
+  uint64_t* pairs[2] = {reinterpret_cast<uint64_t*>(ws + L.pairs[0]),
+                        reinterpret_cast<uint64_t*>(ws + L.pairs[1])};
   // phase 2: each tile's list by (depth bits, index)
   hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)tiles_total), dim3(kTsThreads), 0, st, ranges,
                      pairs[0], pairs[1], vals, keys);
