@@ -24,6 +24,8 @@
  *     the calling thread.
  *   - Layouts are row-major; pixel (x, y) has index y*W + x and its centre
  *     at (x + 0.5, y + 0.5).  FP32 throughout unless stated.
+ *   - Device arrays start on 16-byte boundaries (the kernels use vector
+ *     loads; hipMalloc and torch allocations qualify).
  *   - Calls on distinct streams with distinct buffers are independent; the
  *     library holds no mutable global state.
  */

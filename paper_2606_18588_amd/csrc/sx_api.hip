@@ -136,6 +136,8 @@ sx_status sx_sort(const sx_projected* proj, int64_t n, const sx_camera* cam,
   SX_TRY(check_params(p));
   if (!proj || (n > 0 && (!proj->rec || !proj->rect || !proj->n_tiles || !proj->block_sums)))
     return fail(SX_EINVAL, "null projected array");
+  if (n > 0 && (reinterpret_cast<uintptr_t>(proj->block_sums) & 7))
+    return fail(SX_EINVAL, "block_sums is not 8-byte aligned");
   if (n < 0 || n >= (int64_t(1) << 31)) return fail(SX_EINVAL, "n out of range");
   if (capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(SX_EINVAL, "capacity must be in [0, 2^31)");
   if (!vals && capacity > 0) return fail(SX_EINVAL, "vals is NULL");

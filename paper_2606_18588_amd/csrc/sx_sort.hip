@@ -191,33 +191,39 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 }
 
 // The same scan in one workgroup (one launch instead of two) for scenes of
-// at most kOneScan preprocess blocks: each of 1024 threads takes
-// kOneScan / 1024 consecutive blocks.  It also clears the tile counts and
-// the reserved error word.
-constexpr int kOneScan = 16384;
+// at most kOneScan preprocess blocks: the block sums are loaded coalesced
+// into LDS, each of 1024 threads adds up kOneScan / 1024 consecutive
+// blocks, and one block-wide scan of those sums gives every offset.  It
+// also clears the tile counts and the reserved error word.
+constexpr int kOneScan = 8192;
 
-__global__ __launch_bounds__(1024) void k_scan_one(const uint32_t* __restrict__ bsum, int64_t nb,
+__global__ __launch_bounds__(1024) void k_scan_one(const uint2* __restrict__ bsum, int64_t nb,
                                                    uint32_t* __restrict__ vis_off,
                                                    uint32_t* __restrict__ inst_off,
                                                    uint64_t* counts, int64_t cap,
                                                    uint32_t* __restrict__ tcount, int64_t tiles) {
+  __shared__ uint16_t s_vis[kOneScan];  // a block has at most kPreBlock visible
+  __shared__ uint32_t s_ins[kOneScan];
   __shared__ unsigned long long s_v[16], s_i[16];
   constexpr int per = kOneScan / 1024;
+  static_assert(kPreBlock <= 65535, "visible counts fit 16 bits");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int64_t k = tid; k < tiles; k += 1024) tcount[k] = 0;
-  const int64_t b0 = (int64_t)tid * per;
-  uint32_t v[per], iv[per];
-  unsigned long long sv = 0, si = 0;
-#pragma unroll
-  for (int j = 0; j < per; ++j) {
-    const bool in = b0 + j < nb;
-    v[j] = in ? bsum[2 * (b0 + j)] : 0u;
-    iv[j] = in ? bsum[2 * (b0 + j) + 1] : 0u;
-    sv += v[j], si += iv[j];
+  for (int j = tid; j < kOneScan; j += 1024) {
+    const uint2 b = j < nb ? bsum[j] : make_uint2(0u, 0u);  // (visible, instances)
+    s_vis[j] = (uint16_t)b.x;
+    s_ins[j] = b.y;
   }
-  unsigned long long xv = sv, xi = si;
+  __syncthreads();
+  uint32_t sv = 0;
+  unsigned long long si = 0;
+#pragma unroll
+  for (int k = 0; k < per; ++k) sv += s_vis[tid * per + k], si += s_ins[tid * per + k];
+  uint32_t xv = sv;
+  unsigned long long xi = si;
   for (int o = 1; o < 64; o <<= 1) {
-    const unsigned long long yv = __shfl_up(xv, o, 64), yi = __shfl_up(xi, o, 64);
+    const uint32_t yv = __shfl_up(xv, o, 64);
+    const unsigned long long yi = __shfl_up(xi, o, 64);
     if (lane >= o) xv += yv, xi += yi;
   }
   if (lane == 63) s_v[w] = xv, s_i[w] = xi;
@@ -228,12 +234,13 @@ __global__ __launch_bounds__(1024) void k_scan_one(const uint32_t* __restrict__ 
     tv += s_v[k], ti += s_i[k];
   }
 #pragma unroll
-  for (int j = 0; j < per; ++j) {
-    if (b0 + j < nb) {
-      vis_off[b0 + j] = (uint32_t)pv;
-      inst_off[b0 + j] = (uint32_t)pi;  // exact within the 2^31 capacity bound
+  for (int k = 0; k < per; ++k) {
+    const int64_t j = (int64_t)tid * per + k;
+    if (j < nb) {
+      vis_off[j] = (uint32_t)pv;
+      inst_off[j] = (uint32_t)pi;  // exact within the 2^31 capacity bound
     }
-    pv += v[j], pi += iv[j];
+    pv += s_vis[j], pi += s_ins[j];
   }
   if (tid == 0) {
     counts[0] = tv;
@@ -647,7 +654,8 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     return hipSuccess;
   }
   if (L.nb <= kOneScan) {
-    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, proj.block_sums, (int64_t)L.nb,
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st,
+                       reinterpret_cast<const uint2*>(proj.block_sums), (int64_t)L.nb,
                        u32(L.vis_off), u32(L.inst_off), counts, (int64_t)capacity,
                        u32(L.tcount), tiles_total);
   } else {

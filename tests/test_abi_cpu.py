@@ -117,14 +117,20 @@ def test_invalid_arguments_are_rejected_on_host(L):
     cells[0].lo[0], cells[0].hi[0] = 1.0, 0.0
     assert L.sx_composite(ctypes.c_int32(1), parts, cells, ctypes.byref(cam),
                           ctypes.byref(good), ctypes.c_void_p(1), None, None) == B.SX_EINVAL
-    # sort: undersized workspace
+    # sort: undersized workspace, misaligned block sums
     proj = B.SxProjected()
-    proj.rec = proj.rect = proj.n_tiles = proj.block_sums = ctypes.c_void_p(1)
+    proj.rec = proj.rect = proj.n_tiles = proj.block_sums = ctypes.c_void_p(256)
     assert L.sx_sort(ctypes.byref(proj), ctypes.c_int64(10), ctypes.byref(cam),
-                     ctypes.byref(good), ctypes.c_int64(100), None, ctypes.c_void_p(1),
-                     ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_size_t(16), None,
+                     ctypes.byref(good), ctypes.c_int64(100), None, ctypes.c_void_p(256),
+                     ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_size_t(16), None,
                      None) == B.SX_EINVAL
     assert b"workspace" in L.sx_last_error_string()
+    proj.block_sums = ctypes.c_void_p(260)
+    assert L.sx_sort(ctypes.byref(proj), ctypes.c_int64(10), ctypes.byref(cam),
+                     ctypes.byref(good), ctypes.c_int64(100), None, ctypes.c_void_p(256),
+                     ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_size_t(1 << 30), None,
+                     None) == B.SX_EINVAL
+    assert b"aligned" in L.sx_last_error_string()
     # adam: step must be >= 1
     assert L.sx_adam(ctypes.c_int64(4), ctypes.c_void_p(1), ctypes.c_void_p(1),
                      ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_int32(0),
