@@ -288,7 +288,7 @@ def main():
                    "tile": args.tile, "cells": 1, "layout": "Morton order of the means"},
         "views_per_s": 1e3 / ms, "blends_per_step": blends, "visible": n_vis,
         "instances": n_inst, "stage_ms": stages, "wall_s": wall,
-        "roofline": roof,
+        "roofline": roof, "stage_roofline": stage_rooflines(st, stages),
     }
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
@@ -757,6 +757,50 @@ def pmc_traffic(kernel, src):
             if d.get("kernel") == kernel and d.get("source_sha") == source_sha(src):
                 return d["hbm_bytes_per_launch"]
     return None
+
+
+def stage_rooflines(st, stage_ms):
+    """Every stage's algorithmic work (the per-unit figures of the design
+    notes times this step's counts) over its event-timed duration, as a
+    fraction of the bound that limits it: HBM bytes for the data-movement
+    stages (the sort also against its one-pass floor of 24 B per
+    instance), FP32 lane-operation slots for the two rasterizer walks."""
+    n = st.params.n
+    n_vis, n_inst = st.counts
+    hw = st.cam.width * st.cam.height
+    tiles = st.view.tiles
+    sh_bytes = st.params.sh.shape[1] * 3 * 4
+    pbytes = 12 + 12 + 16 + 4 + sh_bytes
+    # significant key bits at this grid: tile id bits + 32 depth bits, in
+    # 8-bit LSD passes (the radix-sort reference the per-unit figure uses)
+    passes = -(-(max(tiles - 1, 1).bit_length() + 32) // 8)
+    hbm = {
+        "preprocess": 16 * n + (4 + 12 + 16 + sh_bytes + 56) * n_vis,
+        "sort": n_inst * (24 * passes + 8),
+        "composite_l1": (16 + 16 + 32 + 12) * hw,
+        "render_bwd_prep": 4 * hw + 4 * tiles,
+        "render_bwd_reduce": 40 * n_inst + (12 + 48) * n_vis,
+        "preprocess_bwd": (8 + pbytes + 40 + pbytes) * n_vis,
+    }
+    alu = {"render": 15.0 * n_inst * 256 + 8.0 * st.blends,
+           "render_bwd_walk": 53.0 * st.blends}
+    out = {}
+    for k, ms in stage_ms.items():
+        if ms <= 0:
+            continue
+        if k in hbm:
+            ach = hbm[k] / (ms / 1e3) / 1e9
+            out[k] = {"bound": "hbm", "algorithmic_bytes": hbm[k], "achieved": round(ach, 1),
+                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}
+            if k == "sort":
+                out[k]["passes"] = passes
+                out[k]["frac_one_pass_floor"] = round(24 * n_inst / (ms / 1e3) / 1e9 /
+                                                      HBM_PEAK_GBS, 4)
+        elif k in alu:
+            ach = alu[k] / (ms / 1e3) / 1e12
+            out[k] = {"bound": "alu", "algorithmic_ops": alu[k], "achieved": round(ach, 3),
+                      "unit": "T lane-op/s", "frac": round(ach / ALU_PEAK_TOPS, 4)}
+    return out
 
 
 def roofline(st, stage_ms):

@@ -50,6 +50,7 @@ struct SortLayout {
   size_t tcount;       // uint32[tiles] instances per tile (cleared by the
                        // first kernel of every call)
   size_t cursor;       // uint32[tiles] next free slot of each tile's list
+  size_t order;        // uint32[tiles] tiles by descending list length
   size_t pairs[2];     // uint64[cap] per-tile lists of depth bits << 32 | index
                        // (the binning's output; [1] is the merge buffer of
                        // tiles longer than one LDS chunk)
@@ -76,6 +77,7 @@ struct SortView {
   const uint64_t* counts;
   const uint32_t* vidx;   // the visible Gaussians in index order
   const uint32_t* ioff;   // [n] first instance of each visible Gaussian, index order
+  const uint32_t* order;  // [tiles] tiles by descending list length (the walk's order)
 };
 SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x, int64_t tiles_y);
 

@@ -250,6 +250,7 @@ struct RenderBwdArgs {
   const float4* __restrict__ dpartial;
   const float* __restrict__ ddepth;
   const uint32_t* __restrict__ nv;    // entries visited per tile
+  const uint32_t* __restrict__ order; // the walk's tile order (a permutation of the tiles)
   const uint32_t* __restrict__ ioff;  // first instance row of each visible Gaussian
   const ushort4* __restrict__ rect;   // tile rectangles [x0, y0, x1, y1)
   uint64_t cap;
@@ -556,9 +557,12 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   __shared__ uint32_t s_e[64];
   __shared__ uint32_t s_xf[FILT ? 64 : 1];
   const int ntile = a.tiles_x * a.tiles_y;
-  const int tile = blockIdx.x;
-  if (tile >= ntile) return;
-  render_tile_bwd<TW, TH, DG, FILT>(a, tile, s_rec, s_e, s_xf);
+  if ((int)blockIdx.x >= ntile) return;
+  // the sort's order (a permutation of the tiles; its n = 0 call writes
+  // none, and then no tile has an entry)
+  const uint32_t tile = a.order[blockIdx.x];
+  if (tile >= (uint32_t)ntile) return;
+  render_tile_bwd<TW, TH, DG, FILT>(a, (int)tile, s_rec, s_e, s_xf);
 }
 
 // Entries each tile's reverse walk visits: the largest `last` over its
@@ -793,6 +797,7 @@ static RenderBwdArgs make_bwd_args(const sx_projected& proj, const uint32_t* val
   a.dpartial = reinterpret_cast<const float4*>(dpartial);
   a.ddepth = ddepth;
   a.nv = reinterpret_cast<const uint32_t*>(bws + BL.nv);
+  a.order = sv.order;
   a.ioff = sv.ioff;
   a.rect = reinterpret_cast<const ushort4*>(proj.rect);
   a.cap = (uint64_t)capacity;

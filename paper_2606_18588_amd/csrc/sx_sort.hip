@@ -67,6 +67,7 @@ SortLayout sort_layout(int64_t n, int64_t cap, int64_t tiles_x, int64_t tiles_y)
   const size_t tiles = (size_t)(tiles_x * tiles_y > 0 ? tiles_x * tiles_y : 1);
   L.tcount = take(tiles * 4);
   L.cursor = take(tiles * 4);
+  L.order = take(tiles * 4);
   L.vis_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
   L.inst_off = take((size_t)(L.nb > 0 ? L.nb : 1) * 4);
   L.ioff = take((size_t)(n > 0 ? n : 1) * 4);
@@ -102,6 +103,7 @@ SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x,
   v.counts = reinterpret_cast<const uint64_t*>(b + L.counts);
   v.vidx = reinterpret_cast<const uint32_t*>(b + L.vidx);
   v.ioff = reinterpret_cast<const uint32_t*>(b + L.ioff);
+  v.order = reinterpret_cast<const uint32_t*>(b + L.order);
   return v;
 }
 
@@ -416,14 +418,21 @@ __global__ __launch_bounds__(kBinThreads) void k_tile_count(TileBin a) {
 
 // One workgroup: exclusive scan of the tile counts into the tile ranges
 // [start, end) and the write pass's cursors (= start), through LDS in
-// chunks of kScanChunk tiles with a running carry.
+// chunks of kScanChunk tiles with a running carry; then the tiles in
+// descending order of list length (buckets of 4 entries, any order within
+// a bucket), the order in which the reverse walk takes them: the long
+// tiles start early and the wave slots drain evenly at the end (the order
+// changes no result: each tile's rows depend on that tile alone).
 constexpr int kScanChunk = 8192;
+constexpr int kOrderBuckets = 256;
 
 __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t* __restrict__ tcount,
                                                     int tiles, uint32_t* __restrict__ ranges,
-                                                    uint32_t* __restrict__ cursor) {
+                                                    uint32_t* __restrict__ cursor,
+                                                    uint32_t* __restrict__ order) {
   __shared__ uint32_t s_t[kScanChunk];
   __shared__ uint32_t s_w[16];
+  __shared__ uint32_t s_c[kOrderBuckets];
   constexpr int per = kScanChunk / 1024;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   uint32_t carry = 0;
@@ -458,6 +467,30 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t* __restrict__
     carry += total;
     __syncthreads();
   }
+  auto bucket = [&](int t) {
+    const uint32_t b = tcount[t] >> 2;
+    return kOrderBuckets - 1 - (int)(b < (uint32_t)kOrderBuckets - 1 ? b : kOrderBuckets - 1);
+  };
+  if (tid < kOrderBuckets) s_c[tid] = 0;
+  __syncthreads();
+  for (int t = tid; t < tiles; t += 1024) atomicAdd(&s_c[bucket(t)], 1u);
+  __syncthreads();
+  if (tid < 64) {  // exclusive scan of the bucket sizes, 4 per lane
+    constexpr int bp = kOrderBuckets / 64;
+    uint32_t v[bp], sum = 0;
+#pragma unroll
+    for (int k = 0; k < bp; ++k) v[k] = s_c[tid * bp + k], sum += v[k];
+    uint32_t x = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (tid >= o) x += y;
+    }
+    uint32_t run = x - sum;
+#pragma unroll
+    for (int k = 0; k < bp; ++k) s_c[tid * bp + k] = run, run += v[k];
+  }
+  __syncthreads();
+  for (int t = tid; t < tiles; t += 1024) order[atomicAdd(&s_c[bucket(t)], 1u)] = (uint32_t)t;
 }
 
 template <bool LDS>
@@ -648,10 +681,13 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
   auto u32 = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   uint64_t* counts = reinterpret_cast<uint64_t*>(ws + L.counts);
   if (n == 0) {
+    // no instance: zero counts, empty ranges and the tile order
     if ((e = launch_fill(u32(L.counts), 8, 0, st))) return e;
-    if ((e = launch_fill(ranges, tiles_total * 2, 0, st))) return e;
+    if ((e = launch_fill(u32(L.tcount), tiles_total, 0, st))) return e;
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, u32(L.tcount), (int)tiles_total,
+                       ranges, u32(L.cursor), u32(L.order));
     if (h_counts) h_counts[0] = h_counts[1] = 0;
-    return hipSuccess;
+    return hipGetLastError();
   }
   if (L.nb <= kOneScan) {
     hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st,
@@ -700,12 +736,12 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     if (tiles_total <= kLdsTiles) {
       hipLaunchKernelGGL(k_tile_count<true>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
       hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, a.tcount, a.tiles, ranges,
-                         a.cursor);
+                         a.cursor, u32(L.order));
       hipLaunchKernelGGL(k_tile_write<true>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
     } else {
       hipLaunchKernelGGL(k_tile_count<false>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
       hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, a.tcount, a.tiles, ranges,
-                         a.cursor);
+                         a.cursor, u32(L.order));
       hipLaunchKernelGGL(k_tile_write<false>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
     }
   }
