@@ -777,7 +777,9 @@ def stage_rooflines(st, stage_ms):
     hbm = {
         "preprocess": 16 * n + (4 + 12 + 16 + sh_bytes + 56) * n_vis,
         "sort": n_inst * (24 * passes + 8),
-        "composite_l1": (16 + 16 + 32 + 12) * hw,
+        # the fused pass: partials read (16 B per cell), target read (12),
+        # composed image (16) and partial gradients (16 per cell) written
+        "composite_l1": (32 * 1 + 28) * hw,
         "render_bwd_prep": 4 * hw + 4 * tiles,
         "render_bwd_reduce": 40 * n_inst + (12 + 48) * n_vis,
         "preprocess_bwd": (8 + pbytes + 40 + pbytes) * n_vis,
