@@ -281,15 +281,16 @@ class CellView:
 
     def poll_counts(self):
         """(visible, instances, overflow) of the last asynchronous sort; waits
-        for its count copy.  A sort whose bounded look-back wait ran out left
-        an unsorted list: that raises."""
+        for its count copy.  The fourth count word (reserved for a sort that
+        could not complete; the current sort always leaves it 0) raises when
+        set."""
         if self._counts_ev is None:
             raise RuntimeError("no asynchronous sort posted its counts")
         self._counts_ev.synchronize()
         vis, inst, over, err = (int(x) for x in self._h_counts.tolist())
         if err:
-            raise RuntimeError("sx_sort: a bounded wait of the depth passes ran out; "
-                               "the instance list of this view is not sorted")
+            raise RuntimeError("sx_sort: the error count word is set; the instance list of "
+                               "this view must not be used")
         return vis, inst, over
 
     def render(self, mask=None, want_depth=False, want_nblend=True):
@@ -485,7 +486,7 @@ class Frame:
     def check_counts(self):
         """Reads every cell's posted sort counts (waiting for them) and
         returns the indices of the cells whose instances overflowed their
-        capacity; raises if a sort's bounded wait ran out."""
+        capacity; raises if a sort's error word is set."""
         bad = []
         for k, v in enumerate(self.views):
             vis, inst, over = v.poll_counts()

@@ -260,8 +260,8 @@ class Server:
         for j, (it, cap) in enumerate(zip(b.items, b.caps)):
             vis, inst, over, err = (int(x) for x in b.counts[j, :4])
             if err:
-                raise RuntimeError(f"request {it.rid}: a bounded wait of the sort's depth "
-                                   "passes ran out; its instance list is not sorted")
+                raise RuntimeError(f"request {it.rid}: the sort's error word is set; its "
+                                   "instance list must not be used")
             if over or inst > cap:
                 if inst > _MAX_CAPACITY:
                     raise RuntimeError(f"request {it.rid}: {inst} instances exceed the sort's "

@@ -289,7 +289,7 @@ def test_sort_large_scene_bit_exact(view):
     v.preprocess()
     counts = v.sort(sync=True)
     v.post_counts()
-    vis, inst, over = v.poll_counts()  # raises if a bounded wait ran out
+    vis, inst, over = v.poll_counts()  # raises if the error word is set
     assert over == 0 and (vis, inst) == tuple(counts)
     keys, vals, ranges = oracle.sort_keys(scene, cam, ST)
     print(f"large-scene sort: {vis} visible, {inst} instances", flush=True)
