@@ -98,10 +98,31 @@ class _Batch:
     slot: int  # the in-flight slot (stream and buffers) it runs on
 
 
+def slot_bytes(n: int, max_px: int, max_tiles: int) -> int:
+    """Device bytes of one view slot (_Slot): the projection's per-Gaussian
+    record, tile rectangle and tile count (60 B per Gaussian, indexed by
+    Gaussian), its block sums, the tile ranges and three per-pixel buffers
+    of the largest view."""
+    return (60 * max(n, 1) + 8 * B.sx_preprocess_blocks(n) + 8 * (max_tiles + 1)
+            + 36 * max_px)
+
+
+def batch_width(max_batch: int, inflight: int, per_slot: int, budget: int) -> int:
+    """Views per batch such that inflight x width slots fit `budget` bytes
+    (at least 1, at most max_batch)."""
+    fit = budget // max(per_slot * inflight, 1)
+    return int(max(1, min(max_batch, fit)))
+
+
 class Server:
     def __init__(self, params: GaussianParams, settings, max_width=3840, max_height=2160,
                  max_batch=16, inflight=2, arena_bytes=24 << 30, plain=False,
-                 safety=1.15, device="cuda"):
+                 safety=1.15, slot_budget=None, device="cuda"):
+        """slot_budget: device bytes the view slots of all in-flight batches
+        may take (default: half the memory free once the arenas are set
+        aside).  A slot holds the projection of the whole scene for one view,
+        so on a large scene the budget, not max_batch, bounds the views per
+        batch."""
         if not 1 <= max_batch <= B.SX_MAX_VIEWS:
             raise ValueError(f"max_batch must be in 1..{B.SX_MAX_VIEWS}")
         self.params = params
@@ -128,6 +149,12 @@ class Server:
         tx = (max_width + settings.tile_w - 1) // settings.tile_w
         ty = (max_height + settings.tile_h - 1) // settings.tile_h
         self.max_tiles = tx * ty
+        per_slot = slot_bytes(self.n, max_width * max_height, self.max_tiles)
+        if slot_budget is None:
+            free, _ = torch.cuda.mem_get_info(device)
+            slot_budget = max(0, free - inflight * self.arena_bytes) // 2
+        self.slot_budget = int(slot_budget)
+        self.max_batch = batch_width(self.max_batch, inflight, per_slot, self.slot_budget)
         self.slots = [[_Slot(self.n, max_width * max_height, self.max_tiles, device)
                        for _ in range(self.max_batch)] for _ in range(inflight)]
         self.arenas = [torch.empty((self.arena_bytes,), dtype=torch.uint8, device=device)

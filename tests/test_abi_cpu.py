@@ -263,3 +263,21 @@ def test_bucket_views_greedy_first_fit():
     parts = [{0, 1}, {2}, {1, 3}, {0}, {3}, set(), {2, 4}]
     assert bucket_views(parts) == [[0, 1, 4, 5], [2, 3, 6]]
     assert bucket_views([{0}, {0}, {0}]) == [[0], [1], [2]]
+
+
+def test_server_batch_width_from_memory_budget():
+    """The serving loop's view slots hold a whole-scene projection each, so
+    the batch width comes from the slot memory budget: 60 bytes per Gaussian
+    plus the largest view's pixel buffers per slot, inflight x width slots
+    within the budget, never below one view or above max_batch."""
+    from paper_2606_18588_amd import binding as B
+    from paper_2606_18588_amd.serve import batch_width, slot_bytes
+    n, px, tiles = 30_000_000, 3840 * 2160, 240 * 135
+    per = slot_bytes(n, px, tiles)
+    assert per == 60 * n + 8 * B.sx_preprocess_blocks(n) + 8 * (tiles + 1) + 36 * px
+    assert batch_width(16, 2, per, 32 * per) == 16          # fits: unchanged
+    assert batch_width(16, 2, per, 14 * per + per // 2) == 7  # 2 x 7 slots fit, 2 x 8 do not
+    assert batch_width(16, 2, per, per) == 1                  # at least one view
+    # a 120M-Gaussian scene: 7.5 GB per slot, 106 GB of budget -> 7 views per batch
+    big = slot_bytes(120_000_000, px, tiles)
+    assert batch_width(16, 2, big, 106 << 30) == (106 << 30) // (2 * big)

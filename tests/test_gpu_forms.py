@@ -382,6 +382,31 @@ def test_server_alone_vs_mix_bit_identical(torch_gpu):
                   bound=jump_bound(ST, 1.5))
 
 
+def test_server_slot_budget_bounds_batch_width(torch_gpu):
+    """A slot budget of five view slots with two batches in flight gives
+    batches of at most two views, and the images stay bit-identical to the
+    default server's."""
+    torch = torch_gpu
+    from paper_2606_18588_amd.pipeline import GaussianParams
+    from paper_2606_18588_amd.serve import slot_bytes
+    print("case: server slot budget", flush=True)
+    scene = synth.tiny_scene(seed=17, n=5000)
+    params = GaussianParams.from_scene(scene)
+    reqs = _requests(12, seed=9)
+    ref = _server(torch, params, arena_bytes=256 << 20)
+    ref.calibrate(reqs[0].camera)
+    ref.serve(reqs, open_loop=False, keep_images=True)
+    tx, ty = (200 + ST.tile_w - 1) // ST.tile_w, (160 + ST.tile_h - 1) // ST.tile_h
+    per = slot_bytes(params.n, 200 * 160, tx * ty)
+    srv = _server(torch, params, arena_bytes=256 << 20, slot_budget=5 * per)
+    assert srv.max_batch == 2
+    srv.calibrate(reqs[0].camera)
+    srv.serve(reqs, open_loop=False, keep_images=True)
+    assert srv.n_batches >= len(reqs) // 2
+    for r in reqs:
+        assert_same(_np(srv.images[r.rid]), _np(ref.images[r.rid]), f"request {r.rid}")
+
+
 def test_server_overflow_requeue_and_admission(torch_gpu):
     """Under-estimated instance counts overflow the sort buffers: those
     requests are re-queued with the exact count and their images still
