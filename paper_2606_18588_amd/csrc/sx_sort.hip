@@ -305,9 +305,9 @@ __global__ __launch_bounds__(kPreBlock) void k_compact(const uint32_t* __restric
 // (thread q takes instances q, q + kBinThreads, ...; a binary search over
 // the chunk's instance starts in LDS names the Gaussian), so a Gaussian
 // covering hundreds of tiles does not serialise one thread.  Counts and
-// slots are aggregated in an LDS counter per tile of the grid, so that a
-// tile sees one device atomic per workgroup that reaches it; grids of more
-// than kLdsTiles tiles use a device atomic per instance instead.
+// slots are aggregated in an LDS counter per tile, so that a tile sees one
+// device atomic per workgroup that reaches it (grids of more than
+// kLdsTiles tiles in windows of that many).
 constexpr int kBinThreads = 512;
 constexpr int kBinChunk = 2048;
 constexpr int kBinPer = kBinChunk / kBinThreads;
@@ -396,23 +396,27 @@ __device__ __forceinline__ void bin_each(const TileBin& a, uint64_t b0, uint64_t
   }
 }
 
-template <bool LDS>
+// Both passes aggregate in LDS over windows of kLdsTiles tiles: a grid
+// wider than one window is taken window by window, each enumerating the
+// run's instances again and keeping those of its window.
 __global__ __launch_bounds__(kBinThreads) void k_tile_count(TileBin a) {
   __shared__ BinLds L;
-  __shared__ uint32_t s_h[LDS ? kLdsTiles : 1];
+  __shared__ uint32_t s_h[kLdsTiles];
   uint64_t b0, b1;
   bin_run(a, &b0, &b1);
   if (b0 >= b1) return;  // the same for the whole workgroup
-  if (LDS) {
-    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) s_h[t] = 0;
-    bin_each(a, b0, b1, L, [&](uint64_t, int t) { atomicAdd(&s_h[t], 1u); });
+  for (int w0 = 0; w0 < a.tiles; w0 += kLdsTiles) {
+    const int wn = a.tiles - w0 < kLdsTiles ? a.tiles - w0 : kLdsTiles;
+    __syncthreads();  // the previous window's counters are flushed
+    for (int t = threadIdx.x; t < wn; t += kBinThreads) s_h[t] = 0;
+    bin_each(a, b0, b1, L, [&](uint64_t, int t) {
+      if ((unsigned)(t - w0) < (unsigned)wn) atomicAdd(&s_h[t - w0], 1u);
+    });
     __syncthreads();
-    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) {
+    for (int t = threadIdx.x; t < wn; t += kBinThreads) {
       const uint32_t c = s_h[t];
-      if (c) atomicAdd(&a.tcount[t], c);  // integer sums: any order
+      if (c) atomicAdd(&a.tcount[w0 + t], c);  // integer sums: any order
     }
-  } else {
-    bin_each(a, b0, b1, L, [&](uint64_t, int t) { atomicAdd(&a.tcount[t], 1u); });
   }
 }
 
@@ -493,33 +497,33 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t* __restrict__
   for (int t = tid; t < tiles; t += 1024) order[atomicAdd(&s_c[bucket(t)], 1u)] = (uint32_t)t;
 }
 
-template <bool LDS>
 __global__ __launch_bounds__(kBinThreads) void k_tile_write(TileBin a) {
   __shared__ BinLds L;
-  __shared__ uint32_t s_h[LDS ? kLdsTiles : 1];
+  __shared__ uint32_t s_h[kLdsTiles];
   uint64_t b0, b1;
   bin_run(a, &b0, &b1);
   if (b0 >= b1) return;
   auto key = [&](uint64_t i) { return (uint64_t)a.vkey[i] << 32 | a.vidx[i]; };
-  if (LDS) {
+  for (int w0 = 0; w0 < a.tiles; w0 += kLdsTiles) {
+    const int wn = a.tiles - w0 < kLdsTiles ? a.tiles - w0 : kLdsTiles;
+    auto in_window = [&](int t) { return (unsigned)(t - w0) < (unsigned)wn; };
     // count again, reserve each tile's slots with one device atomic, then
     // hand them out from LDS
-    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) s_h[t] = 0;
-    bin_each(a, b0, b1, L, [&](uint64_t, int t) { atomicAdd(&s_h[t], 1u); });
+    __syncthreads();  // the previous window's slots are handed out
+    for (int t = threadIdx.x; t < wn; t += kBinThreads) s_h[t] = 0;
+    bin_each(a, b0, b1, L, [&](uint64_t, int t) {
+      if (in_window(t)) atomicAdd(&s_h[t - w0], 1u);
+    });
     __syncthreads();
-    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) {
+    for (int t = threadIdx.x; t < wn; t += kBinThreads) {
       const uint32_t c = s_h[t];
-      if (c) s_h[t] = atomicAdd(&a.cursor[t], c);
+      if (c) s_h[t] = atomicAdd(&a.cursor[w0 + t], c);
     }
     __syncthreads();
     bin_each(a, b0, b1, L, [&](uint64_t i, int t) {
-      const uint32_t pos = atomicAdd(&s_h[t], 1u);
+      if (!in_window(t)) return;
+      const uint32_t pos = atomicAdd(&s_h[t - w0], 1u);
       if (pos < a.cap) a.pairs[pos] = key(i);  // always, the slots being reserved
-    });
-  } else {
-    bin_each(a, b0, b1, L, [&](uint64_t i, int t) {
-      const uint32_t pos = atomicAdd(&a.cursor[t], 1u);
-      if (pos < a.cap) a.pairs[pos] = key(i);
     });
   }
 }
@@ -733,17 +737,10 @@ hipError_t launch_sort(const sx_projected& proj, int64_t n, const KParams& p,
     a.cap = (uint64_t)(capacity > 0 ? capacity : 1);
     int64_t blocks = n / 4096;
     blocks = blocks < 1 ? 1 : blocks > 512 ? 512 : blocks;
-    if (tiles_total <= kLdsTiles) {
-      hipLaunchKernelGGL(k_tile_count<true>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
-      hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, a.tcount, a.tiles, ranges,
-                         a.cursor, u32(L.order));
-      hipLaunchKernelGGL(k_tile_write<true>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
-    } else {
-      hipLaunchKernelGGL(k_tile_count<false>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
-      hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, a.tcount, a.tiles, ranges,
-                         a.cursor, u32(L.order));
-      hipLaunchKernelGGL(k_tile_write<false>, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
-    }
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, a.tcount, a.tiles, ranges,
+                       a.cursor, u32(L.order));
+    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)blocks), dim3(kBinThreads), 0, st, a);
   }
   uint64_t* pairs[2] = {reinterpret_cast<uint64_t*>(ws + L.pairs[0]),
                         reinterpret_cast<uint64_t*>(ws + L.pairs[1])};
