@@ -266,6 +266,16 @@ __device__ __forceinline__ void preprocess_block(const PreArgs& a, int64_t blk) 
     if (k < w) pre += s_w[k];
     ncand += s_w[k];
   }
+  // most blocks of a large scene lie wholly outside the view: no FP64 work
+  // and zero sums (ncand is the same in every thread, so the whole block
+  // leaves here and no barrier below is left waiting)
+  if (ncand == 0) {
+    if (threadIdx.x == 0) {
+      a.block_sums[2 * (size_t)blk + 0] = 0;
+      a.block_sums[2 * (size_t)blk + 1] = 0;
+    }
+    return;
+  }
   if (cand) s_cand[pre + __popcll(bal & ((1ull << lane) - 1))] = threadIdx.x;
   __syncthreads();
   uint32_t cnt = 0;
@@ -274,11 +284,8 @@ __device__ __forceinline__ void preprocess_block(const PreArgs& a, int64_t blk) 
     cnt = project_one<D>(a, ii);
     a.n_tiles[ii] = cnt;
   }
-  uint32_t vis = cnt > 0 ? 1u : 0u;
-  for (int o = 32; o >= 1; o >>= 1) {
-    vis += __shfl_xor(vis, o, 64);
-    cnt += __shfl_xor(cnt, o, 64);
-  }
+  const uint32_t vis = (uint32_t)__popcll(__ballot(cnt > 0));
+  cnt = __builtin_amdgcn_readlane(wave_sum_u32_to_lane63(cnt), 63);
   if (lane == 0) sv[w] = vis, sc[w] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
