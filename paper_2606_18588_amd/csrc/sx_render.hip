@@ -342,6 +342,45 @@ __device__ __forceinline__ void wave_sum_pair_store(const float (&va)[10], const
   }
 }
 
+// The same sums through LDS, for the nine values of the walk without a
+// depth gradient.  Values 0-7 of both entries are 16 outputs of 64 partials
+// each: every lane writes its 16 partials as one column of a 16-row table,
+// then lane L sums chunk L & 3 (16 partials) of row L >> 2 and two DPP
+// steps add the four chunks of a row.  Per pair that is 17 VALU
+// instructions for the 16 sums (the LDS traffic runs beside the VALU, the
+// walk's bound) instead of the 44 of the transposition in registers.  Value
+// 8 takes the register path alone: a 32-lane swap, a row sum, a row
+// broadcast; lanes 31 and 63 hold its two totals and store them with the
+// zero of value 9.
+// Table layout: row o (output) holds four chunks of 16 partials padded to
+// 17 floats, rows 68 floats apart, so that neither the column writes nor
+// the chunk reads put two lanes on one bank.
+constexpr int kRedChunk = 17, kRedRow = 4 * kRedChunk, kRedFloats = 16 * kRedRow;
+__device__ __forceinline__ void wave_sum_pair_store_lds(const float (&va)[10],
+                                                        const float (&vb)[10], float* da,
+                                                        float* db, int lane, float* s_red) {
+  float* wr = s_red + (lane >> 4) * kRedChunk + (lane & 15);
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    wr[o * kRedRow] = va[o];
+    wr[(8 + o) * kRedRow] = vb[o];
+  }
+  float u8 = row_sum16(swap_add32(va[8], vb[8]));
+  u8 += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(u8), 0x142, 0xA, 0xF, false));
+  const float* rd = s_red + (lane >> 2) * kRedRow + (lane & 3) * kRedChunk;
+  float t[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t[i] = rd[2 * i] + rd[2 * i + 1];
+  float sum = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+  sum += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sum), 0xB1, 0xF, 0xF, true));
+  sum += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sum), 0x4E, 0xF, 0xF, true));
+  float* d = (lane & 32) ? db : da;
+  if ((lane & 3) == 0 && d) d[(lane >> 2) & 7] = sum;
+  // value 9 (the depth gradient's, zero here) is stored too: the row is
+  // read whole
+  if ((lane & 31) == 31 && d) *reinterpret_cast<float2*>(d + 8) = make_float2(u8, 0.f);
+}
+
 // Reverse walk of each pixel's blended pairs.  With R the colour behind pair
 // i (normalised by T_{i+1}), T_final the partial transmittance and
 // (G, g_T, g_D) the gradients of (C^m, T^m, D^m):
@@ -373,7 +412,7 @@ __device__ __forceinline__ uint32_t instance_row(const RenderBwdArgs& a, uint32_
 template <int TW, int TH, bool DG, bool FILT = false>
 __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile,
                                                 float4 (*s_rec)[64], uint32_t* s_e,
-                                                uint32_t* s_xf = nullptr) {
+                                                float* s_red, uint32_t* s_xf = nullptr) {
   constexpr int PPT = TW * TH / 64;
   using BL = Blocks<TW, TH>;
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -536,7 +575,10 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       float* da = (uint64_t)e1 < a.cap ? a.rows + (size_t)e1 * kRowFloats : nullptr;
       float* db = two && (uint64_t)e2 < a.cap ? a.rows + (size_t)e2 * kRowFloats : nullptr;
       if (any) {
-        wave_sum_pair_store<DG>(va, vb, da, db, lane);
+        if constexpr (DG)
+          wave_sum_pair_store<true>(va, vb, da, db, lane);
+        else
+          wave_sum_pair_store_lds(va, vb, da, db, lane, s_red);
       } else {
         // nothing blended either entry: zero rows
         float* d = lane == 63 ? da : lane == 62 ? db : nullptr;
@@ -555,6 +597,7 @@ template <int TW, int TH, bool DG, bool FILT>
 __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   __shared__ float4 s_rec[3][64];
   __shared__ uint32_t s_e[64];
+  __shared__ float s_red[DG ? 1 : kRedFloats];
   __shared__ uint32_t s_xf[FILT ? 64 : 1];
   const int ntile = a.tiles_x * a.tiles_y;
   if ((int)blockIdx.x >= ntile) return;
@@ -562,7 +605,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderBwdArgs a) {
   // none, and then no tile has an entry)
   const uint32_t tile = a.order[blockIdx.x];
   if (tile >= (uint32_t)ntile) return;
-  render_tile_bwd<TW, TH, DG, FILT>(a, (int)tile, s_rec, s_e, s_xf);
+  render_tile_bwd<TW, TH, DG, FILT>(a, (int)tile, s_rec, s_e, s_red, s_xf);
 }
 
 // Entries each tile's reverse walk visits: the largest `last` over its
@@ -700,11 +743,12 @@ template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_render_bwd_multi(RenderBwdMultiArgs m) {
   __shared__ float4 s_rec[3][64];
   __shared__ uint32_t s_e[64];
+  __shared__ float s_red[kRedFloats];
   const uint32_t b = blockIdx.x;
   if (b >= m.base[m.V]) return;
   const int v = item_view(m.base, m.V, b);
   // batched views carry no depth gradient
-  render_tile_bwd<TW, TH, false>(m.view[v], (int)(b - m.base[v]), s_rec, s_e);
+  render_tile_bwd<TW, TH, false>(m.view[v], (int)(b - m.base[v]), s_rec, s_e, s_red);
 }
 
 static_assert(sizeof(RenderBwdMultiArgs) <= 4096, "kernel argument block too large");
