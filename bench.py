@@ -739,7 +739,7 @@ def serve_measure(requests, warm_n):
 KERNEL_OF_STAGE = {
     "preprocess": ("k_preprocess<3>", "sx_preprocess.hip"),
     "preprocess_bwd": ("k_preprocess_backward<3, false>", "sx_preprocess.hip"),
-    "render": ("k_render<16, 16, false>", "sx_render.hip"),
+    "render": ("k_render<16, 16, false, false>", "sx_render.hip"),
     "render_bwd_walk": ("k_render_bwd<16, 16, false, false>", "sx_render.hip"),
 }
 PMC_FILE = os.path.join(ROOT, "profiles", "g2_pmc_traffic.txt")

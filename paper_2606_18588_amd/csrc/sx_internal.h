@@ -228,13 +228,14 @@ struct AlphaEval {
   float alpha;  // min(alpha_max, o G)
   bool clamped;
 };
-// (a, b, c): the conic times kConicToExp2, so that the form below is
-// -q/2 in base 2
+// (a, b2, c): the conic times kConicToExp2, so that the form below is
+// -q/2 in base 2, with b doubled (b2 = b + b, exact) when the record is
+// staged rather than at every evaluation
 constexpr float kConicToExp2 = -0.5f * kLog2e;
 __device__ __forceinline__ AlphaEval eval_alpha(float dx, float dy, float a,
-                                                float b, float c, float o,
+                                                float b2, float c, float o,
                                                 float alpha_max) {
-  const float t = fmaf(b + b, dy, a * dx);     // a dx + 2 b dy
+  const float t = fmaf(b2, dy, a * dx);        // a dx + 2 b dy
   const float e = fmaf(t, dx, (c * dy) * dy);  // a dx^2 + 2 b dx dy + c dy^2
   AlphaEval r;
   r.G = __builtin_amdgcn_exp2f(e);

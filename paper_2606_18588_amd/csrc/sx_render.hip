@@ -146,7 +146,9 @@ __device__ __forceinline__ bool rows_meet(float2 yr, int py0, int py1, float cy,
   return yr.x <= Y1 && yr.y >= Y0;
 }
 
-template <int TW, int TH, bool FILT = false>
+// CNT: the per-pixel blend count may be asked for (a.nblend); without it
+// the count is compiled out of the blend loop.
+template <int TW, int TH, bool FILT = false, bool CNT = true>
 __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
                                             float4 (*s_rec)[3][64], uint32_t* s_xf = nullptr) {
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -165,16 +167,22 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
   const float log_amin = __logf(a.alpha_min);
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   uint32_t lst = 0, nb = 0;
-  bool done = !active;
+  // the alpha an entry needs to blend: alpha_min while the pixel is live,
+  // kDone (above any alpha) once it is saturated or inactive, which folds
+  // the pixel's state into the one comparison
+  constexpr float kDone = 2.f;
+  float athr = active ? a.alpha_min : kDone;
+  const bool count = CNT && a.nblend != nullptr;
   for (uint32_t jb = rg.x; jb < rg.y; jb += 64) {
-    if (__ballot(!done) == 0) break;
+    if (__ballot(athr < kDone) == 0) break;
     const uint32_t cnt = rg.y - jb < 64u ? rg.y - jb : 64u;
     bool meets = false;
     if ((uint32_t)lane < cnt) {
       const uint32_t gl = a.vals[jb + lane];
       const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)gl * kRecFloats);
       const float4 q0 = r[0], q1 = r[1], q2 = r[2];
-      s_rec[w][0][lane] = make_float4(q0.x, q0.y, q0.z * kConicToExp2, q0.w * kConicToExp2);
+      const float bk = q0.w * kConicToExp2;
+      s_rec[w][0][lane] = make_float4(q0.x, q0.y, q0.z * kConicToExp2, bk + bk);
       s_rec[w][1][lane] = make_float4(q1.x * kConicToExp2, q1.y, q1.z, q1.w);
       s_rec[w][2][lane] = q2;
       if (FILT) s_xf[w * 64 + lane] = a.xf[gl];
@@ -190,7 +198,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
     auto blend = [&](const float4& r0, const float4& r1, const float4& r2, uint32_t kc,
                      uint32_t xe) {
       const AlphaEval ae = eval_alpha(fx - r0.x, fy - r0.y, r0.z, r0.w, r1.x, r1.y, a.alpha_max);
-      const bool use = !done && ae.alpha >= a.alpha_min && (!FILT || (xe & pbits) == 0u);
+      const bool use = ae.alpha >= athr && (!FILT || (xe & pbits) == 0u);
       if (__ballot(use) == 0) return;  // nothing to blend in this rectangle
       const float al = use ? ae.alpha : 0.f;
       const float wt = al * T;
@@ -199,13 +207,13 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
       C2 = fmaf(r2.x, wt, C2);
       D = fmaf(r2.y, wt, D);
       T = T * (1.f - al);
-      nb += use ? 1u : 0u;
+      if (count) nb += use ? 1u : 0u;
       lst = use ? jb + kc - rg.x + 1 : lst;
-      done = done || (use && T < a.t_min);
+      athr = (use && T < a.t_min) ? kDone : athr;
     };
     // two entries per LDS round trip
     while (todo) {
-      if (__ballot(!done) == 0) break;
+      if (__ballot(athr < kDone) == 0) break;
       const uint32_t k1 = (uint32_t)__builtin_ctzll(todo);
       todo &= todo - 1;
       const bool two = todo != 0;
@@ -223,18 +231,18 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int tile,
     a.partial[pix] = make_float4(C0, C1, C2, T);
     a.last[pix] = lst;
     if (a.depth) a.depth[pix] = D;
-    if (a.nblend) a.nblend[pix] = nb;
+    if (count) a.nblend[pix] = nb;
   }
 }
 
-template <int TW, int TH, bool FILT>
+template <int TW, int TH, bool FILT, bool CNT>
 __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
   __shared__ float4 s_rec[TW * TH / 64][3][64];
   __shared__ uint32_t s_xf[FILT ? TW * TH : 1];
   const int ntile = a.tiles_x * a.tiles_y;
   const int tile = blockIdx.x;
   if (tile >= ntile) return;
-  render_tile<TW, TH, FILT>(a, tile, s_rec, s_xf);
+  render_tile<TW, TH, FILT, CNT>(a, tile, s_rec, s_xf);
 }
 
 struct RenderBwdArgs {
@@ -479,7 +487,8 @@ __device__ __forceinline__ void render_tile_bwd(const RenderBwdArgs& a, int tile
       const uint32_t gl = a.vals[rg.x + (uint32_t)(j0 + lane)];
       const float4* rr = reinterpret_cast<const float4*>(a.rec + (size_t)gl * kRecFloats);
       const float4 q0 = rr[0], q1 = rr[1], q2 = rr[2];
-      s_rec[0][lane] = make_float4(q0.x, q0.y, q0.z * kConicToExp2, q0.w * kConicToExp2);
+      const float bk = q0.w * kConicToExp2;
+      s_rec[0][lane] = make_float4(q0.x, q0.y, q0.z * kConicToExp2, bk + bk);
       s_rec[1][lane] = make_float4(q1.x * kConicToExp2, q1.y, q1.z, q1.w);
       s_rec[2][lane] = q2;
       if (FILT) s_xf[lane] = a.xf[gl];
@@ -761,10 +770,14 @@ bool tile_shape_supported(int tw, int th) {
 template <int TW, int TH>
 static void launch_fwd_t(const RenderArgs& a, hipStream_t st) {
   const int grid = a.tiles_x * a.tiles_y;
-  if (a.xf)
-    hipLaunchKernelGGL((k_render<TW, TH, true>), dim3(grid), dim3(TW * TH), 0, st, a);
+  if (a.xf && a.nblend)
+    hipLaunchKernelGGL((k_render<TW, TH, true, true>), dim3(grid), dim3(TW * TH), 0, st, a);
+  else if (a.xf)
+    hipLaunchKernelGGL((k_render<TW, TH, true, false>), dim3(grid), dim3(TW * TH), 0, st, a);
+  else if (a.nblend)
+    hipLaunchKernelGGL((k_render<TW, TH, false, true>), dim3(grid), dim3(TW * TH), 0, st, a);
   else
-    hipLaunchKernelGGL((k_render<TW, TH, false>), dim3(grid), dim3(TW * TH), 0, st, a);
+    hipLaunchKernelGGL((k_render<TW, TH, false, false>), dim3(grid), dim3(TW * TH), 0, st, a);
 }
 template <int TW, int TH>
 static void launch_bwd_t(const RenderBwdArgs& a, hipStream_t st) {
