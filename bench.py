@@ -790,7 +790,7 @@ def stage_rooflines(st, stage_ms):
         "render_bwd_reduce": 40 * n_inst + (12 + 48) * n_vis,
         "preprocess_bwd": (8 + pbytes + 40 + pbytes) * n_vis,
     }
-    alu = {"render": 15.0 * n_inst * 256 + 8.0 * st.blends,
+    alu = {"render": 24.0 * st.blends,
            "render_bwd_walk": 53.0 * st.blends}
     out = {}
     for k, ms in stage_ms.items():
@@ -815,9 +815,10 @@ def roofline(st, stage_ms):
     """Roofline entry for the largest kernel that has an entry point of its
     own (so that events around the call time exactly that kernel).  The
     per-unit algorithmic work: HBM-bound stages count the bytes the method
-    must move, the rasterizers count FP32 lane-operation slots (15 per pair
-    evaluation and 8 per blend forward, 53 per blend in the reverse walk;
-    unit "T lane-op/s").  working_set_bytes is what the kernel touches: below
+    must move, the rasterizers count FP32 lane-operation slots per blended
+    (pixel, Gaussian) pair (24 forward: 14 for alpha and its test, 10 for
+    the blend; 53 in the reverse walk; unit "T lane-op/s"), so that the
+    evaluations of pairs that do not blend count as overhead in both.  working_set_bytes is what the kernel touches: below
     the 256 MB Infinity Cache a bandwidth figure may be served from it."""
     n = st.params.n
     n_vis, n_inst = st.counts
@@ -826,11 +827,10 @@ def roofline(st, stage_ms):
     ms = stage_ms[stage]
     kernel, src = KERNEL_OF_STAGE[stage]
     if stage in ("render", "render_bwd_walk"):
-        # FP32 lane-operation slots (a transcendental or reciprocal takes 4):
-        # forward 15 per pair evaluation (every instance x tile pixels) and 8
-        # more per blend; reverse walk 53 per blend
+        # FP32 lane-operation slots per blend (a transcendental or
+        # reciprocal takes 4): forward 24, reverse walk 53
         if stage == "render":
-            ops = 15.0 * n_inst * 256 + 8.0 * st.blends
+            ops = 24.0 * st.blends
         else:
             ops = 53.0 * st.blends
         ach = ops / (ms / 1e3) / 1e12
