@@ -865,6 +865,48 @@ def test_backward_screen_space_matches_oracle(torch_gpu):
         check_grad(got, rb[name][ok], f"tiny {name}")
 
 
+def test_backward_walks_every_tile_poisoned_rows(torch_gpu):
+    """Every tile is walked and every instance row written: the backward
+    workspace is filled with NaN bytes first, on a view where the cube
+    covers the centre of a wide image, so that 2,000 of its 2,048
+    tiles are empty and the walk's tile order places them in runs (the
+    order's shortest-list bucket, filled a wavefront at a time).  The
+    screen-space gradients must be finite and match the oracle."""
+    print("case: backward with poisoned rows, 1024x512, mostly empty tiles", flush=True)
+    torch = torch_gpu
+    scene = synth.tiny_scene()
+    f = (128 / 2.0) / math.tan(math.radians(30.0))
+    cam = synth.camera_from_rows(np.eye(3), (0.0, 0.0, -3.0), 1024, 512, f)
+    fr, params = _frame(torch, [scene], [big_box()], cam)
+    out = fr.forward()
+    target = torch.as_tensor(synth.random_image(103, cam.width, cam.height)).cuda()
+    from paper_2606_18588_amd import binding as B
+    dout = torch.empty_like(out)
+    B.sx_l1_loss(out, target, cam.width, cam.height, dout, None)
+    v = fr.views[0]
+    v.ensure_backward_buffers()
+    v.bwd_ws.fill_(255)
+    grads = [params[0].zeros_like()]
+    fr.backward(dout, grads)
+    torch.cuda.synchronize()
+    pr = oracle.preprocess(scene, cam, ST)
+    vis = pr["valid"] == 1
+    g2d = v.g2d.cpu().numpy()[:, :10]
+    assert np.isfinite(g2d[vis]).all()
+    d = dout.cpu().numpy()
+    ref = oracle.forward([scene], [big_box()], cam, ST)
+    rb = oracle.render_backward(scene, cam, ST, d[..., :3].astype(np.float64), None, None)
+    fl = ref.parts[0]["flags"] != 0
+    bad = np.zeros(scene.n, bool)
+    for y, x in zip(*np.nonzero(fl)):
+        pr_r = pr["pix_rect"]
+        bad |= (pr_r[:, 0] <= x) & (x <= pr_r[:, 2]) & (pr_r[:, 1] <= y) & (y <= pr_r[:, 3])
+    ok = vis & ~bad
+    print(f"visible {int(vis.sum())}, compared {int(ok.sum())}", flush=True)
+    for c in range(9):
+        check_grad(g2d[ok, c], rb["g2d"][ok, c], f"wide g2d[{c}]")
+
+
 # ------------------------------------------------------------------- a10 --
 def test_adam_matches_oracle(torch_gpu):
     print("case: adam", flush=True)
