@@ -616,14 +616,21 @@ __device__ __forceinline__ void backward_one(const PreBwdArgs& a, int64_t i, boo
 
 // One lane per visible Gaussian, taken from the sort's compacted list in
 // index order, so the FP64 chain runs in full wavefronts and neighbouring
-// lanes read and write neighbouring parameter rows.
+// lanes read and write neighbouring parameter rows.  The grid is capped
+// (kPreBwdGrid workgroups, each striding over the list): the visible count
+// is known on the device only, and a grid sized for every Gaussian would
+// send thousands of workgroups that find nothing to do through the few
+// slots this kernel's register footprint leaves per CU (two workgroups),
+// each holding its slot for a memory round trip.
+constexpr unsigned kPreBwdGrid = 1024;
 template <int D, bool ACC>
 __global__ __launch_bounds__(kPreBlock) void k_preprocess_backward(PreBwdArgs a) {
-  const uint64_t i = (uint64_t)blockIdx.x * kPreBlock + threadIdx.x;
-  if (i >= a.vis_count[0]) return;
-  const uint32_t g = a.vis[i];
-  if (a.n_tiles[g] == 0) return;
-  backward_one<D>(a, (int64_t)g, ACC);
+  const uint64_t nv = a.vis_count[0];
+  for (uint64_t i = (uint64_t)blockIdx.x * kPreBlock + threadIdx.x; i < nv;
+       i += (uint64_t)gridDim.x * kPreBlock) {
+    const uint32_t g = a.vis[i];
+    if (a.n_tiles[g] != 0) backward_one<D>(a, (int64_t)g, ACC);
+  }
 }
 
 hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
@@ -644,7 +651,8 @@ hipError_t launch_preprocess_backward(const sx_gaussians& g, const DCam& cam,
   a.gmeans = gr.means, a.glog_scales = gr.log_scales, a.gquats = gr.quats;
   a.glogits = gr.opacity_logits, a.gsh = gr.sh;
   a.accumulate = accumulate ? 1 : 0;
-  const dim3 grid((unsigned)((g.n + kPreBlock - 1) / kPreBlock));
+  const int64_t blocks = (g.n + kPreBlock - 1) / kPreBlock;
+  const dim3 grid((unsigned)(blocks < kPreBwdGrid ? blocks : kPreBwdGrid));
 #define SX_PB(D)                                                                               \
   do {                                                                                         \
     if (accumulate)                                                                            \
