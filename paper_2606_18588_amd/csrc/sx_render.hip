@@ -654,10 +654,13 @@ __global__ __launch_bounds__(64) void k_tile_extent(const uint32_t* __restrict__
 
 // Per-Gaussian sum of its instance rows, which are contiguous (rows
 // ioff[g] .. ioff[g] + n_tiles[g]), into g2d[g]; every visible Gaussian's
-// row is written, so nothing is cleared first.  A lane sums the rows of a
-// Gaussian with few tiles in order; the wavefront shares the rows of each
-// Gaussian with more (strided, then one cross-lane sum).
-constexpr uint32_t kLaneRows = 16;
+// row is written, so nothing is cleared first.  Four lanes share a
+// Gaussian with up to kQuadRows rows: lane q of the quad sums rows q, q + 4,
+// ... (the quad reads consecutive rows together) and two DPP steps add the
+// quad's four sums, so a lane's chain of dependent loads is a quarter as
+// long; the wavefront shares the rows of each Gaussian with more (strided,
+// then one cross-lane sum).
+constexpr uint32_t kQuadRows = 64;
 
 __global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t* __restrict__ vidx,
                                                      const uint64_t* counts,
@@ -666,11 +669,14 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t* __restrict_
                                                      const float* __restrict__ rows, uint64_t cap,
                                                      const float* __restrict__ rec,
                                                      float* __restrict__ g2d) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, q = lane & 3;
   const uint64_t nvis = counts[0];
-  for (uint64_t i0 = (uint64_t)blockIdx.x * 256 + (threadIdx.x & ~63u); i0 < nvis;
-       i0 += (uint64_t)gridDim.x * 256) {
-    const uint64_t i = i0 + (uint64_t)lane;
+  // t0: the wavefront's first thread; its 16 quads take visible Gaussians
+  // t0 / 4 .. t0 / 4 + 15 (a uniform loop, so every lane of a quad runs
+  // the DPP steps)
+  for (uint64_t t0 = (uint64_t)blockIdx.x * 256 + (threadIdx.x & ~63u); t0 / 4 < nvis;
+       t0 += (uint64_t)gridDim.x * 256) {
+    const uint64_t i = (t0 + (uint64_t)lane) >> 2;
     uint32_t g = 0, base = 0, cnt = 0;
     if (i < nvis) {
       g = vidx[i];
@@ -680,19 +686,28 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t* __restrict_
       const uint64_t end = (uint64_t)base + cnt;
       cnt = end <= cap ? cnt : (uint32_t)(base < cap ? cap - base : 0);
     }
-    const bool wide = i < nvis && cnt > kLaneRows;
-    if (i < nvis && !wide) {
-      float acc[kRowFloats];
+    const bool wide = cnt > kQuadRows;
+    float acc[kRowFloats];
 #pragma unroll
-      for (int q = 0; q < kRowFloats; ++q) acc[q] = 0.f;
-      for (uint32_t r = 0; r < cnt; ++r) {
+    for (int m = 0; m < kRowFloats; ++m) acc[m] = 0.f;
+    if (!wide) {
+      for (uint32_t r = (uint32_t)q; r < cnt; r += 4) {
         const float2* src = reinterpret_cast<const float2*>(rows + (size_t)(base + r) * kRowFloats);
 #pragma unroll
-        for (int q = 0; q < kRowFloats / 2; ++q) {
-          const float2 v = src[q];
-          acc[2 * q] += v.x, acc[2 * q + 1] += v.y;
+        for (int m = 0; m < kRowFloats / 2; ++m) {
+          const float2 v = src[m];
+          acc[2 * m] += v.x, acc[2 * m + 1] += v.y;
         }
       }
+    }
+#pragma unroll
+    for (int m = 0; m < kRowFloats; ++m) {
+      float x = acc[m];
+      x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));
+      x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, true));
+      acc[m] = x;
+    }
+    if (i < nvis && q == 0 && !wide) {
       const float* cg = rec + (size_t)g * kRecFloats;
       row_to_g2d(acc, cg[2], cg[3], cg[4]);
       float4* d = reinterpret_cast<float4*>(g2d + (size_t)g * kG2dFloats);
@@ -700,18 +715,20 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t* __restrict_
       d[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
       d[2] = make_float4(acc[8], acc[9], 0.f, 0.f);
     }
-    for (uint64_t wm = __ballot(wide); wm; wm &= wm - 1) {
+    // the wide Gaussians, one at a time over the whole wavefront (the four
+    // lanes of its quad agree on it; its first lane is taken)
+    for (uint64_t wm = __ballot(i < nvis && q == 0 && wide); wm; wm &= wm - 1) {
       const int l = __builtin_ctzll(wm);
       const uint32_t gw = __shfl(g, l, 64), bw = __shfl(base, l, 64), cw = __shfl(cnt, l, 64);
       float v[kRowFloats];
 #pragma unroll
-      for (int q = 0; q < kRowFloats; ++q) v[q] = 0.f;
+      for (int m = 0; m < kRowFloats; ++m) v[m] = 0.f;
       for (uint32_t r = (uint32_t)lane; r < cw; r += 64) {
         const float2* src = reinterpret_cast<const float2*>(rows + (size_t)(bw + r) * kRowFloats);
 #pragma unroll
-        for (int q = 0; q < kRowFloats / 2; ++q) {
-          const float2 x = src[q];
-          v[2 * q] += x.x, v[2 * q + 1] += x.y;
+        for (int m = 0; m < kRowFloats / 2; ++m) {
+          const float2 x = src[m];
+          v[2 * m] += x.x, v[2 * m + 1] += x.y;
         }
       }
       // linear in the row sums, so applied to each lane's part before the
@@ -897,8 +914,8 @@ static hipError_t launch_bwd_reduce(const sx_projected& proj, const SortView& sv
   const int64_t tiles = (int64_t)p.tiles_x * p.tiles_y;
   const BwdLayout BL = bwd_layout(capacity, tiles);
   if (n > 0) {
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_slot_reduce, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(256),
+    const int64_t blocks = (4 * n + 255) / 256;  // four lanes per Gaussian
+    hipLaunchKernelGGL(k_slot_reduce, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256),
                        0, st, sv.vidx, sv.counts, sv.ioff, proj.n_tiles,
                        reinterpret_cast<const float*>(bws + BL.rows), (uint64_t)capacity,
                        proj.rec, g2d);
