@@ -746,9 +746,16 @@ PMC_FILE = os.path.join(ROOT, "profiles", "g2_pmc_traffic.txt")
 
 
 def source_sha(name):
+    """Hash of a kernel's source file and the headers every kernel file
+    includes (the device helpers and constants of sx_internal.h, the ABI's
+    structs), so that a change to either voids the committed counters."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2606_18588_amd", "csrc", name)
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in (os.path.join(ROOT, "paper_2606_18588_amd", "csrc", name),
+                 os.path.join(ROOT, "paper_2606_18588_amd", "csrc", "sx_internal.h"),
+                 os.path.join(ROOT, "include", "splaxel.h")):
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def pmc_traffic(kernel, src):

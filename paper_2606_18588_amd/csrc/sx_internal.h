@@ -86,28 +86,10 @@ SortView sort_view(const void* ws, int64_t n, int64_t capacity, int64_t tiles_x,
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Sum over a 64-lane wavefront with DPP row rotations and row broadcasts;
-// the total ends up in lane 63.
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-  int x = __float_as_int(v);
-  // quad_perm [1,0,3,2] and [2,3,0,1]
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false));
-  x = __float_as_int(v);
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false));
-  x = __float_as_int(v);
-  // row_ror:4, row_ror:8 -> every lane holds its 16-lane row sum
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x124, 0xF, 0xF, false));
-  x = __float_as_int(v);
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false));
-  x = __float_as_int(v);
-  // row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false));
-  x = __float_as_int(v);
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false));
-  return v;
-}
-
-// The same sum for unsigned integers (exact; the total in lane 63).
+// Sum of unsigned integers over a 64-lane wavefront with DPP: quad
+// permutations and row rotations give every lane its 16-lane row's sum,
+// then row broadcasts carry rows 0-2 into row 3; the total ends up in lane
+// 63 (exact).
 __device__ __forceinline__ uint32_t wave_sum_u32_to_lane63(uint32_t v) {
   v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
   v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
